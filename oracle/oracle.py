@@ -1,0 +1,300 @@
+"""ctypes binding of the CPU oracle (lsb_oracle.cpp).
+
+TEST INFRASTRUCTURE ONLY.  The parameter block below mirrors orc::Params of
+the oracle's own source; it is not shared with the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "lsb_oracle.cpp")
+LIB_PATH = os.path.join(HERE, "liblsb_oracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with the host compiler (plain C++17, OpenMP)."""
+    cmd = ["g++", "-std=c++17", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", LIB_PATH, SRC]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return LIB_PATH
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("lattice", C.c_int), ("storage", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("bc", C.c_int * 6), ("wall_u", (C.c_double * 3) * 6),
+        ("rho_phys", C.c_double * 2), ("tau", C.c_double * 2), ("accel", (C.c_double * 3) * 2),
+        ("sigma", C.c_double), ("band", C.c_double), ("n_ext", C.c_int), ("ext_dtau", C.c_double),
+        ("reinit_every", C.c_int), ("n_reinit", C.c_int), ("reinit_dtau", C.c_double),
+        ("heaviside_eps", C.c_double), ("use_pb", C.c_int), ("pb0", C.c_double),
+        ("init_hydrostatic", C.c_int), ("fp16_scale_log2", C.c_int),
+    ]
+
+
+def _params(p: dict) -> _Params:
+    s = _Params()
+    for k, _ in _Params._fields_:
+        v = p[k]
+        if k == "bc":
+            for i in range(6):
+                s.bc[i] = int(v[i])
+        elif k == "wall_u":
+            for i in range(6):
+                for a in range(3):
+                    s.wall_u[i][a] = float(v[i][a])
+        elif k in ("rho_phys", "tau"):
+            for i in range(2):
+                getattr(s, k)[i] = float(v[i])
+        elif k == "accel":
+            for i in range(2):
+                for a in range(3):
+                    s.accel[i][a] = float(v[i][a])
+        else:
+            setattr(s, k, v)
+    return s
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
+        build()
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER(_Params)
+    dp = C.POINTER(C.c_double)
+    ub = C.POINTER(C.c_ubyte)
+    lib.orc_create.restype = C.c_void_p
+    lib.orc_create.argtypes = [P]
+    lib.orc_destroy.argtypes = [C.c_void_p]
+    lib.orc_init.argtypes = [C.c_void_p, dp, dp, dp]
+    lib.orc_step.argtypes = [C.c_void_p, C.c_int]
+    lib.orc_nstep.restype = C.c_long
+    lib.orc_nstep.argtypes = [C.c_void_p]
+    lib.orc_get_pop.argtypes = [C.c_void_p, dp]
+    lib.orc_get_fields.argtypes = [C.c_void_p, dp, dp, dp, ub]
+    lib.orc_get_interface.argtypes = [C.c_void_p, dp, dp, dp, ub]
+    lib.orc_get_moments.argtypes = [C.c_void_p, dp]
+    lib.orc_get_integrals.argtypes = [C.c_void_p, dp]
+    lib.orc_lattice.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), dp,
+                                C.POINTER(C.c_int)]
+    lib.orc_feq.argtypes = [C.c_int, C.c_double, dp, dp]
+    lib.orc_refill_weights.argtypes = [C.c_double, dp]
+    lib.orc_heaviside.restype = C.c_double
+    lib.orc_heaviside.argtypes = [C.c_double, C.c_double]
+    lib.orc_geometry.argtypes = [P, dp, dp, dp]
+    lib.orc_advect_rate.argtypes = [P, dp, dp, dp]
+    lib.orc_advect.argtypes = [P, dp, dp, C.c_int]
+    lib.orc_reinit.argtypes = [P, dp, C.c_int]
+    lib.orc_extend.argtypes = [P, dp, ub, dp]
+    lib.orc_tan_create.restype = C.c_void_p
+    lib.orc_tan_create.argtypes = [P]
+    lib.orc_tan_destroy.argtypes = [C.c_void_p]
+    lib.orc_tan_init.argtypes = [C.c_void_p, dp, dp, C.c_double, dp, dp]
+    lib.orc_tan_step.argtypes = [C.c_void_p, C.c_int]
+    lib.orc_tan_centroid.argtypes = [C.c_void_p, C.c_int, dp, dp]
+    lib.orc_tan_get_pop.argtypes = [C.c_void_p, dp, dp]
+    _lib = lib
+    return lib
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a, n=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None:
+        assert a.size == n, (a.size, n)
+    return a
+
+
+def lattice(lat: int):
+    lib = _load()
+    D, Q = C.c_int(), C.c_int()
+    c = (C.c_int * 81)()
+    w = np.zeros(27)
+    opp = (C.c_int * 27)()
+    assert lib.orc_lattice(lat, C.byref(D), C.byref(Q), c, _dp(w), opp) == 0
+    q = Q.value
+    cc = np.array(c[:3 * q], dtype=np.int64).reshape(q, 3)
+    return D.value, q, cc, w[:q].copy(), np.array(opp[:q])
+
+
+def feq(lat: int, rho: float, u) -> np.ndarray:
+    lib = _load()
+    u = _f64(np.asarray(u, dtype=np.float64).reshape(3))
+    out = np.zeros(27)
+    assert lib.orc_feq(lat, float(rho), _dp(u), _dp(out)) == 0
+    return out[: lattice(lat)[1]]
+
+
+def refill_weights(q: float) -> np.ndarray:
+    out = np.zeros(3)
+    _load().orc_refill_weights(float(q), _dp(out))
+    return out
+
+
+def heaviside(phi: float, eps: float) -> float:
+    return _load().orc_heaviside(float(phi), float(eps))
+
+
+def _ncell(p):
+    return p["nx"] * p["ny"] * p["nz"]
+
+
+def _dim(p):
+    return 2 if p["lattice"] == 0 else 3
+
+
+def geometry(p: dict, phi):
+    lib = _load()
+    N = _ncell(p)
+    phi = _f64(phi, N)
+    n = np.zeros(N * _dim(p))
+    k = np.zeros(N)
+    assert lib.orc_geometry(C.byref(_params(p)), _dp(phi), _dp(n), _dp(k)) == 0
+    shp = (p["nz"], p["ny"], p["nx"])
+    return n.reshape(shp + (_dim(p),)), k.reshape(shp)
+
+
+def advect_rate(p: dict, phi, u):
+    lib = _load()
+    N = _ncell(p)
+    phi = _f64(phi, N)
+    u = _f64(u, 3 * N)
+    out = np.zeros(N)
+    assert lib.orc_advect_rate(C.byref(_params(p)), _dp(phi), _dp(u), _dp(out)) == 0
+    return out.reshape(p["nz"], p["ny"], p["nx"])
+
+
+def advect(p: dict, phi, u, nsteps: int):
+    lib = _load()
+    N = _ncell(p)
+    phi = _f64(phi, N).copy()
+    u = _f64(u, 3 * N)
+    assert lib.orc_advect(C.byref(_params(p)), _dp(phi), _dp(u), int(nsteps)) == 0
+    return phi.reshape(p["nz"], p["ny"], p["nx"])
+
+
+def reinit(p: dict, phi, calls: int = 1):
+    lib = _load()
+    N = _ncell(p)
+    phi = _f64(phi, N).copy()
+    assert lib.orc_reinit(C.byref(_params(p)), _dp(phi), int(calls)) == 0
+    return phi.reshape(p["nz"], p["ny"], p["nx"])
+
+
+def extend(p: dict, phi, fixed, u):
+    lib = _load()
+    N = _ncell(p)
+    phi = _f64(phi, N)
+    fx = np.ascontiguousarray(fixed, dtype=np.uint8).reshape(N)
+    u = _f64(u, 3 * N).copy()
+    assert lib.orc_extend(C.byref(_params(p)), _dp(phi), fx.ctypes.data_as(C.POINTER(C.c_ubyte)), _dp(u)) == 0
+    return u.reshape(p["nz"], p["ny"], p["nx"], 3)
+
+
+class Oracle:
+    """One oracle simulation (FP64)."""
+
+    def __init__(self, params: dict, phi0, rho0=None, u0=None):
+        self.lib = _load()
+        self.p = dict(params)
+        self._cp = _params(self.p)
+        self.h = self.lib.orc_create(C.byref(self._cp))
+        if not self.h:
+            raise ValueError("oracle rejected the parameters")
+        self.N = _ncell(self.p)
+        self.shape = (self.p["nz"], self.p["ny"], self.p["nx"])
+        self.D, self.Q = lattice(self.p["lattice"])[:2]
+        phi0 = _f64(phi0, self.N)
+        rho0 = _f64(rho0, self.N)
+        u0 = _f64(u0, 3 * self.N)
+        assert self.lib.orc_init(self.h, _dp(phi0), _dp(rho0), _dp(u0)) == 0
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.orc_destroy(self.h)
+            self.h = None
+
+    def step(self, n: int = 1):
+        assert self.lib.orc_step(self.h, int(n)) == 0
+
+    @property
+    def nstep(self):
+        return self.lib.orc_nstep(self.h)
+
+    def populations(self):
+        out = np.zeros(self.Q * self.N)
+        self.lib.orc_get_pop(self.h, _dp(out))
+        return out.reshape((self.Q,) + self.shape)
+
+    def fields(self):
+        rho = np.zeros(self.N)
+        u = np.zeros(self.N * self.D)
+        p = np.zeros(self.N)
+        ph = np.zeros(self.N, dtype=np.uint8)
+        self.lib.orc_get_fields(self.h, _dp(rho), _dp(u), _dp(p), ph.ctypes.data_as(C.POINTER(C.c_ubyte)))
+        return dict(rho=rho.reshape(self.shape), u=u.reshape(self.shape + (self.D,)), p=p.reshape(self.shape),
+                    phase=ph.reshape(self.shape))
+
+    def interface(self):
+        phi = np.zeros(self.N)
+        n = np.zeros(self.N * self.D)
+        k = np.zeros(self.N)
+        t = np.zeros(self.N, dtype=np.uint8)
+        self.lib.orc_get_interface(self.h, _dp(phi), _dp(n), _dp(k), t.ctypes.data_as(C.POINTER(C.c_ubyte)))
+        return dict(phi=phi.reshape(self.shape), normal=n.reshape(self.shape + (self.D,)),
+                    kappa=k.reshape(self.shape), tags=t.reshape(self.shape))
+
+    def moments(self):
+        out = np.zeros(10 * self.N)
+        self.lib.orc_get_moments(self.h, _dp(out))
+        return out.reshape(self.shape + (10,))
+
+    def integrals(self):
+        out = np.zeros(16)
+        self.lib.orc_get_integrals(self.h, _dp(out))
+        return dict(mass=out[0:2].copy(), volume_gas=out[2], centroid=out[3:6].copy(), vel_b=out[6:9].copy(),
+                    pb=out[9], umax=out[10], step=int(out[11]))
+
+
+class TangentOracle:
+    """Forward-mode tangent of the oracle (dual numbers, frozen decisions)."""
+
+    def __init__(self, params: dict, phi0, dphi0=None, dsigma=0.0, rho0=None, u0=None):
+        self.lib = _load()
+        self.p = dict(params)
+        self._cp = _params(self.p)
+        self.h = self.lib.orc_tan_create(C.byref(self._cp))
+        if not self.h:
+            raise ValueError("oracle rejected the parameters")
+        N = _ncell(self.p)
+        self.N = N
+        assert self.lib.orc_tan_init(self.h, _dp(_f64(phi0, N)), _dp(_f64(dphi0, N)), float(dsigma),
+                                     _dp(_f64(rho0, N)), _dp(_f64(u0, 3 * N))) == 0
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.orc_tan_destroy(self.h)
+            self.h = None
+
+    def step(self, n: int = 1):
+        assert self.lib.orc_tan_step(self.h, int(n)) == 0
+
+    def centroid(self, axis: int):
+        v, t = C.c_double(), C.c_double()
+        self.lib.orc_tan_centroid(self.h, int(axis), C.byref(v), C.byref(t))
+        return v.value, t.value
