@@ -1,0 +1,165 @@
+/*
+ * lsb.h -- C ABI of the coupled level-set lattice Boltzmann hot path on
+ * AMD MI355X (gfx950).
+ *
+ * Method: Vorspohl, Peng, Meinke, Krug, Schroeder, "Coupled Level-Set Lattice
+ * Boltzmann Method on Adaptive Cartesian Grids".  Each fluid phase runs its
+ * own lattice Boltzmann solver (Sec. 2.1); the phases are coupled at the
+ * sharp interface phi = 0 by interpolated bounce-back carrying the stress
+ * jump (Sec. 2.3); the level set is advected, extended and reinitialised on
+ * a narrow band (Sec. 2.2); cells swept by the interface are refilled
+ * (Sec. 2.4).
+ *
+ * Conventions
+ *   - Grids are dense, uniform, cell centred (x = i + 1/2), row-major
+ *     [nz][ny][nx]; nz = 1 with D2Q9 is two-dimensional.
+ *   - Phase 0 is the liquid (phi < 0), phase 1 the gas (phi >= 0).
+ *   - Faces are ordered -x, +x, -y, +y, -z, +z.  Paired faces are either both
+ *     periodic or both walls.
+ *   - Lattice units: dx = dt = 1, cs^2 = 1/3.
+ *   - Every function returns LSB_OK (0) or a negative error code;
+ *     lsb_last_error() gives a thread-local message.
+ *   - Device memory belongs to the caller: the library computes the size of
+ *     one workspace (lsb_workspace_bytes), the caller allocates it and binds
+ *     it (lsb_bind).  The library never allocates or frees device memory.
+ *   - `stream` is a hipStream_t (may be NULL for the default stream).  Calls
+ *     enqueue work on it; calls that take host pointers (on_device = 0)
+ *     synchronise the stream before returning.
+ */
+#ifndef LSB_H
+#define LSB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { LSB_OK = 0, LSB_EINVAL = -1, LSB_ENOMEM = -2, LSB_EDEVICE = -3, LSB_ESTATE = -4, LSB_EUNSTABLE = -5 };
+
+/* Velocity sets (Sec. 2.1 velocity-set figure; D3Q19 is the textbook subset
+ * made of the D3Q27 directions 0..17 plus rest). */
+enum { LSB_D2Q9 = 0, LSB_D3Q19 = 1, LSB_D3Q27 = 2 };
+
+/* Population storage.  F64: FP64 deviations f - w, FP64 arithmetic.
+ * F32: FP32 deviations, FP32 arithmetic.  F16DEV / BF16DEV: scaled deviations
+ * s (f - w) / w stored in FP16 (s = 2^fp16_scale_log2) or BF16 (s = 1), FP32
+ * arithmetic.  Level set, geometry and moments are FP64 on the F64 path and
+ * FP32 otherwise; reductions accumulate in FP64. */
+enum { LSB_F64 = 0, LSB_F32 = 1, LSB_F16DEV = 2, LSB_BF16DEV = 3 };
+
+/* Face conditions: periodic; no-slip wall on the face (halfway bounce-back,
+ * moving with wall_u, Sec. 2.1 eq:bb); free-slip wall (specular reflection). */
+enum { LSB_PERIODIC = 0, LSB_NOSLIP = 1, LSB_FREESLIP = 2 };
+
+/* Problem statement (Sec. 2 and the setups of Sec. 3). */
+typedef struct lsb_params {
+  int lattice, storage, nx, ny, nz;
+  int bc[6];
+  double wall_u[6][3];      /* velocity of each no-slip face */
+  double rho_phys[2];       /* physical densities [liquid, gas] */
+  double tau[2];            /* BGK relaxation times, tau = 1/2 + nu / cs^2 (eq:omega) */
+  double accel[2][3];       /* body acceleration of each phase (gravity, or force density / rho_phys) */
+  double sigma;             /* surface tension */
+  double band;              /* narrow-band half width B in cells (level set clamped to +-B) */
+  int n_ext;                /* velocity-extension sweeps per step (eq:hyperbolicExtension) */
+  double ext_dtau;          /* pseudo time step of the extension */
+  int reinit_every;         /* reinitialise every k steps (0 = never) */
+  int n_reinit;             /* pseudo steps per reinitialisation */
+  double reinit_dtau;       /* pseudo time step of the reinitialisation */
+  double heaviside_eps;     /* half width of the smoothed Heaviside (Sec. 3.2 integrals) */
+  int use_pb;               /* gas pressure baseline follows the centroid under gravity */
+  double pb0;               /* initial gas pressure baseline */
+  int init_hydrostatic;     /* default initial LB density is hydrostatic about the gas centroid */
+  int fp16_scale_log2;      /* s = 2^k for LSB_F16DEV (typically 12) */
+} lsb_params;
+
+typedef struct lsb_plan lsb_plan; /* opaque; owned by the library */
+
+/* Integral quantities (Sec. 3.2): per-phase mass, Heaviside-weighted gas
+ * volume, centroid and bubble velocity, gas pressure baseline, max |u|. */
+typedef struct lsb_integrals {
+  double mass[2];
+  double volume_gas;
+  double centroid[3];
+  double vel_b[3];
+  double pb;
+  double umax;
+  long step;
+} lsb_integrals;
+
+/* Validate a parameter block and create a plan (host memory only).
+ * Errors: LSB_EINVAL for an unknown lattice/storage, a grid smaller than
+ * 4 cells per used axis, nz != 1 with D2Q9, unpaired periodic faces,
+ * tau <= 1/2, band < 2, negative counts. */
+int lsb_create(const lsb_params* params, lsb_plan** out);
+void lsb_destroy(lsb_plan* plan);
+
+/* Bytes of device workspace the plan needs (256-byte aligned regions). */
+int lsb_workspace_bytes(const lsb_plan* plan, size_t* bytes);
+
+/* Bind a caller-owned device buffer of at least lsb_workspace_bytes bytes.
+ * LSB_ENOMEM if it is too small; LSB_EINVAL for a NULL pointer. */
+int lsb_bind(lsb_plan* plan, void* device_workspace, size_t bytes);
+
+/* Initial state (Sec. 2.1 equilibrium; Sec. 2.2 signed distance):
+ * phi0 [N] signed distance (clamped to +-band); rho0 [N] LB density or NULL
+ * (1, or hydrostatic when init_hydrostatic); u0 [N*3] velocity (x,y,z
+ * interleaved per cell) or NULL (rest).  Populations start at the
+ * equilibrium.  Arrays are device pointers when on_device != 0, otherwise
+ * host pointers staged through the workspace.  LSB_ESTATE before lsb_bind. */
+int lsb_init(lsb_plan* plan, const double* phi0, const double* rho0, const double* u0, int on_device,
+             void* stream);
+
+/* Advance nsteps time steps (collide-stream with wall and interface
+ * bounce-back, extension, advection, periodic reinitialisation,
+ * classification, geometry, refill, centroid and pressure baseline).
+ * If check_every > 0, every check_every steps the stream is synchronised and
+ * LSB_EUNSTABLE returned on a non-finite or non-positive density or
+ * |u| > 0.3.  LSB_ESTATE before lsb_init. */
+int lsb_step(lsb_plan* plan, int nsteps, int check_every, void* stream);
+
+/* Macroscopic fields: rho [N] (sum of populations), u [N*d] (d = 2 or 3,
+ * interleaved per cell; time-centred velocity sum(c f)/rho - a/2), p [N]
+ * (phase pressure rho_phys cs^2 (rho - 1), plus the baseline in the gas),
+ * phase [N] (0 liquid, 1 gas).  Any pointer may be NULL. */
+int lsb_get_fields(lsb_plan* plan, double* rho, double* u, double* p, uint8_t* phase, int on_device,
+                   void* stream);
+
+/* Interface description: phi [N], normal [N*d], kappa [N] (valid on
+ * LS-active cells), tags [N] (bit0 gas, bit1 LS-active, bit2 has a lattice
+ * link to the other phase).  Any pointer may be NULL. */
+int lsb_get_interface(lsb_plan* plan, double* phi, double* normal, double* kappa, uint8_t* tags,
+                      int on_device, void* stream);
+
+/* Decoded populations A[i*N + cell] (post-collision, FP64). */
+int lsb_get_populations(lsb_plan* plan, double* out, int on_device, void* stream);
+
+/* Moments of the last collision per cell, [N][10] = (rho, u[3], S[6] with
+ * S = xx, yy, zz, xy, xz, yz); valid on LS-active cells. */
+int lsb_get_moments(lsb_plan* plan, double* out, int on_device, void* stream);
+
+/* Integral quantities, FP64, synchronises the stream. */
+int lsb_get_integrals(lsb_plan* plan, lsb_integrals* out, void* stream);
+
+/* Checkpoint / resume: device-to-device copy of the full state into or out
+ * of a caller buffer of lsb_state_bytes bytes. */
+int lsb_state_bytes(const lsb_plan* plan, size_t* bytes);
+int lsb_save_state(lsb_plan* plan, void* device_dst, void* stream);
+int lsb_load_state(lsb_plan* plan, const void* device_src, void* stream);
+
+/* Steps taken since lsb_init. */
+long lsb_step_count(const lsb_plan* plan);
+
+/* Number of cells on the interface / in the band after the last step
+ * (synchronises the stream). counts[0] interface-adjacent cells, counts[1]
+ * active tiles, counts[2] cells refilled in the last step. */
+int lsb_get_counts(lsb_plan* plan, int* counts, void* stream);
+
+const char* lsb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSB_H */

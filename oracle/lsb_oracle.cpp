@@ -316,7 +316,15 @@ struct Sim {
     // zero because the velocity is continuous.
     const double eta_bar = 0.5 * (eta[0] + eta[1]);
     const double jeta = eta[1] - eta[0];
-    T E = ((p_g - p_l) + sig * kG) / (2.0 * eta_bar);
+    // The pressure part of the normal jump acts as an explicit feedback: one
+    // step changes an interface cell's pressure by about
+    // rho cs^2 q(1-q) sum_i 6 w_i (c_i.n)^2 E <= rho cs^2 E / 4, which
+    // overshoots when eta_bar < rho / 48 (every workload with tau near 1/2).
+    // Reading: the divisor of this part is floored at rho_max cs^2 / 8, which
+    // bounds the one-step gain of a flat interface by one (deadbeat) and is
+    // inactive whenever the explicit feedback is already stable.
+    const double eta_p = std::max(eta_bar, std::max(P.rho_phys[0], P.rho_phys[1]) * CS2 / 8.0);
+    T E = ((p_g - p_l) + sig * kG) / (2.0 * eta_p);
     T Sb[6];
     for (int m = 0; m < 6; ++m) Sb[m] = 0.5 * (MS[6 * c + m] + MS[6 * s + m]);
     const double acoef = -jeta / eta_bar;

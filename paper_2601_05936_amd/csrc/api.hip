@@ -1,0 +1,435 @@
+// api.hip -- implementation of the C ABI declared in include/lsb.h: parameter
+// validation, workspace layout, host-pointer staging, dispatch to the
+// (velocity set, storage) launch table.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "plan.h"
+
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define LSB_HIP(x)                                                                                    \
+  do {                                                                                                \
+    hipError_t e_ = (x);                                                                              \
+    if (e_ != hipSuccess) return fail(LSB_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Staging area for host-pointer calls: the non-current population buffer,
+// which the next step overwrites completely.
+size_t staging_bytes(const lsb_plan* p) { return (size_t)p->Q * p->N * p->bytes_pop; }
+char* staging(lsb_plan* p) { return p->ws + p->off_A[p->cur ^ 1]; }
+
+int check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LSB_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  return LSB_OK;
+}
+}  // namespace
+
+namespace lsb {
+void set_error(const std::string& msg) { g_err = msg; }
+}  // namespace lsb
+
+extern "C" {
+
+const char* lsb_last_error(void) { return g_err.c_str(); }
+
+int lsb_create(const lsb_params* P, lsb_plan** out) {
+  if (!P || !out) return fail(LSB_EINVAL, "null argument");
+  *out = nullptr;
+  if (P->lattice < LSB_D2Q9 || P->lattice > LSB_D3Q27) return fail(LSB_EINVAL, "unknown lattice");
+  if (P->storage < LSB_F64 || P->storage > LSB_BF16DEV) return fail(LSB_EINVAL, "unknown storage");
+  if (P->lattice == LSB_D2Q9 && P->nz != 1) return fail(LSB_EINVAL, "D2Q9 needs nz == 1");
+  if (P->nx < 4 || P->ny < 4 || (P->lattice != LSB_D2Q9 && P->nz < 4) || P->nz < 1)
+    return fail(LSB_EINVAL, "grid must have at least 4 cells per used axis");
+  if ((double)P->nx * P->ny * P->nz > 2147483647.0 / 2) return fail(LSB_EINVAL, "grid too large for 32-bit cell indices");
+  for (int a = 0; a < 3; ++a) {
+    for (int s = 0; s < 2; ++s)
+      if (P->bc[2 * a + s] < LSB_PERIODIC || P->bc[2 * a + s] > LSB_FREESLIP) return fail(LSB_EINVAL, "unknown face condition");
+    if ((P->bc[2 * a] == LSB_PERIODIC) != (P->bc[2 * a + 1] == LSB_PERIODIC))
+      return fail(LSB_EINVAL, "paired faces must both be periodic or both walls");
+  }
+  if (P->lattice == LSB_D2Q9 && P->bc[4] != LSB_PERIODIC) return fail(LSB_EINVAL, "2D grids need periodic z faces");
+  if (!(P->tau[0] > 0.5) || !(P->tau[1] > 0.5)) return fail(LSB_EINVAL, "tau must exceed 1/2");
+  if (!(P->rho_phys[0] > 0) || !(P->rho_phys[1] > 0)) return fail(LSB_EINVAL, "physical densities must be positive");
+  if (!(P->band >= 2.0)) return fail(LSB_EINVAL, "band must be at least 2 cells");
+  if (P->n_ext < 0 || P->n_reinit < 0 || P->reinit_every < 0) return fail(LSB_EINVAL, "negative iteration count");
+  if (!(P->heaviside_eps > 0)) return fail(LSB_EINVAL, "heaviside_eps must be positive");
+  if (P->storage == LSB_F16DEV && (P->fp16_scale_log2 < 0 || P->fp16_scale_log2 > 20))
+    return fail(LSB_EINVAL, "fp16_scale_log2 out of range");
+
+  lsb_plan* p = new lsb_plan();
+  p->P = *P;
+  p->D = P->lattice == LSB_D2Q9 ? 2 : 3;
+  p->Q = P->lattice == LSB_D2Q9 ? 9 : (P->lattice == LSB_D3Q19 ? 19 : 27);
+  p->N = P->nx * P->ny * P->nz;
+  p->bytes_pop = P->storage == LSB_F64 ? 8 : (P->storage == LSB_F32 ? 4 : 2);
+  p->bytes_real = P->storage == LSB_F64 ? 8 : 4;
+  if (p->D == 2) { p->tdim[0] = 16; p->tdim[1] = 16; p->tdim[2] = 1; }
+  else { p->tdim[0] = 8; p->tdim[1] = 8; p->tdim[2] = 8; }
+  const int n[3] = {P->nx, P->ny, P->nz};
+  p->ntiles = 1;
+  for (int a = 0; a < 3; ++a) {
+    p->ntile[a] = (n[a] + p->tdim[a] - 1) / p->tdim[a];
+    p->ntiles *= p->ntile[a];
+  }
+  p->grid_tiles = std::min(p->ntiles, 2048);
+  p->grid_cells = (int)std::min<long>(((long)p->N + 255) / 256, 4096);
+  p->red_blocks = 512;
+  switch (P->lattice) {
+    case LSB_D2Q9: p->ops = lsb::ops_d2q9(P->storage); break;
+    case LSB_D3Q19: p->ops = lsb::ops_d3q19(P->storage); break;
+    default: p->ops = lsb::ops_d3q27(P->storage); break;
+  }
+  // workspace layout
+  const size_t N = (size_t)p->N;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  for (int b = 0; b < 2; ++b) p->off_A[b] = take((size_t)p->Q * N * p->bytes_pop);
+  p->off_phi = take(N * p->bytes_real);
+  p->off_s1 = take(N * p->bytes_real);
+  p->off_s2 = take(N * p->bytes_real);
+  p->off_p0 = take(N * p->bytes_real);
+  p->off_tag = take(N);
+  p->off_aux = take(N);
+  for (int b = 0; b < 2; ++b) p->off_M[b] = take(10 * N * p->bytes_real);
+  p->off_G = take(4 * N * p->bytes_real);
+  for (int b = 0; b < 2; ++b) p->off_ut[b] = take(3 * N * p->bytes_real);
+  p->off_scal = take(lsb::SC_COUNT * sizeof(double));
+  p->off_cnt = take(lsb::CNT_NUM * sizeof(int));
+  p->off_tile_act = take((size_t)p->ntiles);
+  p->off_tile_list = take((size_t)p->ntiles * sizeof(int));
+  p->off_cand_list = take((size_t)p->ntiles * sizeof(int));
+  p->off_spec_list = take(N * sizeof(int));
+  p->off_flip_list = take(N * sizeof(int));
+  p->off_partial = take((size_t)p->red_blocks * 16 * sizeof(double));
+  p->total = o;
+  *out = p;
+  return LSB_OK;
+}
+
+void lsb_destroy(lsb_plan* p) { delete p; }
+
+int lsb_workspace_bytes(const lsb_plan* p, size_t* bytes) {
+  if (!p || !bytes) return fail(LSB_EINVAL, "null argument");
+  *bytes = p->total;
+  return LSB_OK;
+}
+
+int lsb_bind(lsb_plan* p, void* ws, size_t bytes) {
+  if (!p || !ws) return fail(LSB_EINVAL, "null argument");
+  if (bytes < p->total) return fail(LSB_ENOMEM, "workspace too small: need " + std::to_string(p->total) + " bytes");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(LSB_EINVAL, "workspace must be 256-byte aligned");
+  p->ws = static_cast<char*>(ws);
+  p->bound = true;
+  p->inited = false;
+  return LSB_OK;
+}
+
+int lsb_init(lsb_plan* p, const double* phi0, const double* rho0, const double* u0, int on_device, void* stream) {
+  if (!p) return fail(LSB_EINVAL, "null plan");
+  if (!p->bound) return fail(LSB_ESTATE, "lsb_init before lsb_bind");
+  if (!phi0) return fail(LSB_EINVAL, "phi0 is required");
+  hipStream_t st = as_stream(stream);
+  const int N = p->N;
+  p->cur = 0;
+  p->nstep = 0;
+  if (on_device) {
+    p->ops->init_phi(p, phi0, 0, N, st);
+    LSB_HIP(hipGetLastError());
+    p->ops->init_band(p, st);
+    LSB_HIP(hipGetLastError());
+    p->ops->init_pop(p, rho0, u0, 0, N, st);
+  } else {
+    // stage host arrays through the (not yet used) second population buffer
+    char* stg = p->ws + p->off_A[1];
+    const size_t cap = staging_bytes(p);
+    const int chunk_phi = (int)std::min<size_t>(N, cap / sizeof(double));
+    for (int c0 = 0; c0 < N; c0 += chunk_phi) {
+      const int c1 = std::min(N, c0 + chunk_phi);
+      LSB_HIP(hipMemcpyAsync(stg, phi0 + c0, (size_t)(c1 - c0) * sizeof(double), hipMemcpyHostToDevice, st));
+      p->ops->init_phi(p, reinterpret_cast<double*>(stg), c0, c1, st);
+      LSB_HIP(hipStreamSynchronize(st));
+    }
+    p->ops->init_band(p, st);
+    LSB_HIP(hipGetLastError());
+    const int chunk = (int)std::min<size_t>(N, cap / (4 * sizeof(double)));
+    for (int c0 = 0; c0 < N; c0 += chunk) {
+      const int c1 = std::min(N, c0 + chunk);
+      double* r = reinterpret_cast<double*>(stg);
+      double* u = r + (c1 - c0);
+      if (rho0) LSB_HIP(hipMemcpyAsync(r, rho0 + c0, (size_t)(c1 - c0) * sizeof(double), hipMemcpyHostToDevice, st));
+      if (u0) LSB_HIP(hipMemcpyAsync(u, u0 + 3 * (size_t)c0, 3 * (size_t)(c1 - c0) * sizeof(double), hipMemcpyHostToDevice, st));
+      p->ops->init_pop(p, rho0 ? r : nullptr, u0 ? u : nullptr, c0, c1, st);
+      LSB_HIP(hipStreamSynchronize(st));
+    }
+  }
+  LSB_HIP(hipGetLastError());
+  LSB_HIP(hipStreamSynchronize(st));
+  p->inited = true;
+  return LSB_OK;
+}
+
+int lsb_get_integrals(lsb_plan* p, lsb_integrals* out, void* stream);
+
+int lsb_step(lsb_plan* p, int nsteps, int check_every, void* stream) {
+  if (!p) return fail(LSB_EINVAL, "null plan");
+  if (!p->inited) return fail(LSB_ESTATE, "lsb_step before lsb_init");
+  if (nsteps < 0) return fail(LSB_EINVAL, "negative step count");
+  hipStream_t st = as_stream(stream);
+  for (int s = 0; s < nsteps; ++s) {
+    p->ops->step(p, st);
+    if (int r = check_launch()) return r;
+    if (check_every > 0 && (p->nstep % check_every) == 0) {
+      lsb_integrals I;
+      if (int r = lsb_get_integrals(p, &I, stream)) return r;
+      double bad = 0;
+      std::vector<double> part((size_t)p->red_blocks * 16);
+      LSB_HIP(hipMemcpy(part.data(), p->ws + p->off_partial, part.size() * sizeof(double), hipMemcpyDeviceToHost));
+      for (int b = 0; b < p->red_blocks; ++b) bad += part[16 * (size_t)b + 10];
+      if (bad > 0 || !std::isfinite(I.mass[0]) || !std::isfinite(I.mass[1]))
+        return fail(LSB_EUNSTABLE, "unstable state at step " + std::to_string(p->nstep));
+    }
+  }
+  return LSB_OK;
+}
+
+int lsb_get_fields(lsb_plan* p, double* rho, double* u, double* pr, uint8_t* phase, int on_device, void* stream) {
+  if (!p) return fail(LSB_EINVAL, "null plan");
+  if (!p->inited) return fail(LSB_ESTATE, "no state");
+  hipStream_t st = as_stream(stream);
+  const int N = p->N;
+  if (on_device) {
+    p->ops->fields(p, rho, u, pr, phase, 0, N, st);
+    return check_launch();
+  }
+  char* stg = staging(p);
+  const size_t cap = staging_bytes(p);
+  const int D = p->D;
+  struct Part { int kind; void* host; size_t per_cell; };
+  const Part parts[4] = {{0, rho, sizeof(double)}, {1, u, D * sizeof(double)}, {2, pr, sizeof(double)}, {3, phase, 1}};
+  for (const Part& pt : parts) {
+    if (!pt.host) continue;
+    const int chunk = (int)std::min<size_t>(N, cap / pt.per_cell);
+    for (int c0 = 0; c0 < N; c0 += chunk) {
+      const int c1 = std::min(N, c0 + chunk);
+      double* d = reinterpret_cast<double*>(stg);
+      p->ops->fields(p, pt.kind == 0 ? d : nullptr, pt.kind == 1 ? d : nullptr, pt.kind == 2 ? d : nullptr,
+                     pt.kind == 3 ? reinterpret_cast<uint8_t*>(stg) : nullptr, c0, c1, st);
+      LSB_HIP(hipGetLastError());
+      LSB_HIP(hipMemcpyAsync(static_cast<char*>(pt.host) + (size_t)c0 * pt.per_cell, stg, (size_t)(c1 - c0) * pt.per_cell,
+                             hipMemcpyDeviceToHost, st));
+      LSB_HIP(hipStreamSynchronize(st));
+    }
+  }
+  return LSB_OK;
+}
+
+int lsb_get_interface(lsb_plan* p, double* phi, double* nrm, double* kap, uint8_t* tags, int on_device, void* stream) {
+  if (!p) return fail(LSB_EINVAL, "null plan");
+  if (!p->inited) return fail(LSB_ESTATE, "no state");
+  hipStream_t st = as_stream(stream);
+  const int N = p->N;
+  if (on_device) {
+    p->ops->interface(p, phi, nrm, kap, tags, 0, N, st);
+    return check_launch();
+  }
+  char* stg = staging(p);
+  const size_t cap = staging_bytes(p);
+  const int D = p->D;
+  struct Part { int kind; void* host; size_t per_cell; };
+  const Part parts[4] = {{0, phi, sizeof(double)}, {1, nrm, D * sizeof(double)}, {2, kap, sizeof(double)}, {3, tags, 1}};
+  for (const Part& pt : parts) {
+    if (!pt.host) continue;
+    const int chunk = (int)std::min<size_t>(N, cap / pt.per_cell);
+    for (int c0 = 0; c0 < N; c0 += chunk) {
+      const int c1 = std::min(N, c0 + chunk);
+      double* d = reinterpret_cast<double*>(stg);
+      p->ops->interface(p, pt.kind == 0 ? d : nullptr, pt.kind == 1 ? d : nullptr, pt.kind == 2 ? d : nullptr,
+                        pt.kind == 3 ? reinterpret_cast<uint8_t*>(stg) : nullptr, c0, c1, st);
+      LSB_HIP(hipGetLastError());
+      LSB_HIP(hipMemcpyAsync(static_cast<char*>(pt.host) + (size_t)c0 * pt.per_cell, stg, (size_t)(c1 - c0) * pt.per_cell,
+                             hipMemcpyDeviceToHost, st));
+      LSB_HIP(hipStreamSynchronize(st));
+    }
+  }
+  return LSB_OK;
+}
+
+int lsb_get_populations(lsb_plan* p, double* out, int on_device, void* stream) {
+  if (!p || !out) return fail(LSB_EINVAL, "null argument");
+  if (!p->inited) return fail(LSB_ESTATE, "no state");
+  hipStream_t st = as_stream(stream);
+  const int N = p->N;
+  if (on_device) {
+    p->ops->populations(p, out, 0, p->Q, 0, N, st);
+    return check_launch();
+  }
+  char* stg = staging(p);
+  const int chunk = (int)std::min<size_t>(N, staging_bytes(p) / sizeof(double));
+  for (int i = 0; i < p->Q; ++i)
+    for (int c0 = 0; c0 < N; c0 += chunk) {
+      const int c1 = std::min(N, c0 + chunk);
+      p->ops->populations(p, reinterpret_cast<double*>(stg), i, i + 1, c0, c1, st);
+      LSB_HIP(hipGetLastError());
+      LSB_HIP(hipMemcpyAsync(out + (size_t)i * N + c0, stg, (size_t)(c1 - c0) * sizeof(double), hipMemcpyDeviceToHost, st));
+      LSB_HIP(hipStreamSynchronize(st));
+    }
+  return LSB_OK;
+}
+
+int lsb_get_moments(lsb_plan* p, double* out, int on_device, void* stream) {
+  if (!p || !out) return fail(LSB_EINVAL, "null argument");
+  if (!p->inited) return fail(LSB_ESTATE, "no state");
+  hipStream_t st = as_stream(stream);
+  const int N = p->N;
+  if (on_device) {
+    p->ops->moments(p, out, 0, N, st);
+    return check_launch();
+  }
+  char* stg = staging(p);
+  const int chunk = (int)std::min<size_t>(N, staging_bytes(p) / (10 * sizeof(double)));
+  for (int c0 = 0; c0 < N; c0 += chunk) {
+    const int c1 = std::min(N, c0 + chunk);
+    p->ops->moments(p, reinterpret_cast<double*>(stg), c0, c1, st);
+    LSB_HIP(hipGetLastError());
+    LSB_HIP(hipMemcpyAsync(out + 10 * (size_t)c0, stg, 10 * (size_t)(c1 - c0) * sizeof(double), hipMemcpyDeviceToHost, st));
+    LSB_HIP(hipStreamSynchronize(st));
+  }
+  return LSB_OK;
+}
+
+int lsb_get_integrals(lsb_plan* p, lsb_integrals* out, void* stream) {
+  if (!p || !out) return fail(LSB_EINVAL, "null argument");
+  if (!p->inited) return fail(LSB_ESTATE, "no state");
+  hipStream_t st = as_stream(stream);
+  p->ops->integrals_partial(p, st);
+  LSB_HIP(hipGetLastError());
+  std::vector<double> part((size_t)p->red_blocks * 16);
+  LSB_HIP(hipMemcpyAsync(part.data(), p->ws + p->off_partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  double pb = 0;
+  LSB_HIP(hipMemcpyAsync(&pb, p->ws + p->off_scal + lsb::SC_PB * sizeof(double), sizeof(double), hipMemcpyDeviceToHost, st));
+  LSB_HIP(hipStreamSynchronize(st));
+  double v[11] = {0};
+  double umax = 0;
+  for (int b = 0; b < p->red_blocks; ++b) {
+    for (int m = 0; m < 11; ++m)
+      if (m != 9) v[m] += part[16 * (size_t)b + m];
+    umax = std::max(umax, part[16 * (size_t)b + 9]);
+  }
+  out->mass[0] = v[0];
+  out->mass[1] = v[1];
+  out->volume_gas = v[2];
+  for (int a = 0; a < 3; ++a) {
+    out->centroid[a] = v[2] > 0 ? v[3 + a] / v[2] : 0.0;
+    out->vel_b[a] = v[2] > 0 ? v[6 + a] / v[2] : 0.0;
+  }
+  out->pb = pb;
+  out->umax = umax;
+  out->step = p->nstep;
+  return LSB_OK;
+}
+
+// State image: populations, phi, moments, scalars (device) plus a small
+// host header with the step count.
+static size_t state_layout(const lsb_plan* p, size_t* o_pop, size_t* o_phi, size_t* o_M, size_t* o_scal, size_t* o_hdr) {
+  const size_t N = (size_t)p->N;
+  size_t o = 0;
+  *o_hdr = o; o = align256(o + 64);
+  *o_pop = o; o = align256(o + (size_t)p->Q * N * p->bytes_pop);
+  *o_phi = o; o = align256(o + N * p->bytes_real);
+  *o_M = o; o = align256(o + 10 * N * p->bytes_real);
+  *o_scal = o; o = align256(o + lsb::SC_COUNT * sizeof(double));
+  return o;
+}
+
+int lsb_state_bytes(const lsb_plan* p, size_t* bytes) {
+  if (!p || !bytes) return fail(LSB_EINVAL, "null argument");
+  size_t a, b, c, d, e;
+  *bytes = state_layout(p, &a, &b, &c, &d, &e);
+  return LSB_OK;
+}
+
+int lsb_save_state(lsb_plan* p, void* dst, void* stream) {
+  if (!p || !dst) return fail(LSB_EINVAL, "null argument");
+  if (!p->inited) return fail(LSB_ESTATE, "no state");
+  hipStream_t st = as_stream(stream);
+  size_t o_pop, o_phi, o_M, o_scal, o_hdr;
+  state_layout(p, &o_pop, &o_phi, &o_M, &o_scal, &o_hdr);
+  char* d = static_cast<char*>(dst);
+  const size_t N = (size_t)p->N;
+  long hdr[8] = {0x4c5342, p->nstep, p->N, p->Q, (long)p->bytes_pop, 0, 0, 0};
+  LSB_HIP(hipMemcpyAsync(d + o_hdr, hdr, sizeof(hdr), hipMemcpyHostToDevice, st));
+  LSB_HIP(hipMemcpyAsync(d + o_pop, p->ws + p->off_A[p->cur], (size_t)p->Q * N * p->bytes_pop, hipMemcpyDeviceToDevice, st));
+  LSB_HIP(hipMemcpyAsync(d + o_phi, p->ws + p->off_phi, N * p->bytes_real, hipMemcpyDeviceToDevice, st));
+  LSB_HIP(hipMemcpyAsync(d + o_M, p->ws + p->off_M[p->cur], 10 * N * p->bytes_real, hipMemcpyDeviceToDevice, st));
+  LSB_HIP(hipMemcpyAsync(d + o_scal, p->ws + p->off_scal, lsb::SC_COUNT * sizeof(double), hipMemcpyDeviceToDevice, st));
+  LSB_HIP(hipStreamSynchronize(st));
+  return LSB_OK;
+}
+
+int lsb_load_state(lsb_plan* p, const void* src, void* stream) {
+  if (!p || !src) return fail(LSB_EINVAL, "null argument");
+  if (!p->bound) return fail(LSB_ESTATE, "lsb_load_state before lsb_bind");
+  hipStream_t st = as_stream(stream);
+  size_t o_pop, o_phi, o_M, o_scal, o_hdr;
+  state_layout(p, &o_pop, &o_phi, &o_M, &o_scal, &o_hdr);
+  const char* s = static_cast<const char*>(src);
+  long hdr[8];
+  LSB_HIP(hipMemcpyAsync(hdr, s + o_hdr, sizeof(hdr), hipMemcpyDeviceToHost, st));
+  LSB_HIP(hipStreamSynchronize(st));
+  if (hdr[0] != 0x4c5342 || hdr[2] != p->N || hdr[3] != p->Q || hdr[4] != (long)p->bytes_pop)
+    return fail(LSB_EINVAL, "state image does not match this plan");
+  const size_t N = (size_t)p->N;
+  p->cur = 0;
+  LSB_HIP(hipMemcpyAsync(p->ws + p->off_A[0], s + o_pop, (size_t)p->Q * N * p->bytes_pop, hipMemcpyDeviceToDevice, st));
+  LSB_HIP(hipMemcpyAsync(p->ws + p->off_phi, s + o_phi, N * p->bytes_real, hipMemcpyDeviceToDevice, st));
+  LSB_HIP(hipMemcpyAsync(p->ws + p->off_s1, s + o_phi, N * p->bytes_real, hipMemcpyDeviceToDevice, st));
+  LSB_HIP(hipMemcpyAsync(p->ws + p->off_s2, s + o_phi, N * p->bytes_real, hipMemcpyDeviceToDevice, st));
+  LSB_HIP(hipMemcpyAsync(p->ws + p->off_p0, s + o_phi, N * p->bytes_real, hipMemcpyDeviceToDevice, st));
+  LSB_HIP(hipMemcpyAsync(p->ws + p->off_M[0], s + o_M, 10 * N * p->bytes_real, hipMemcpyDeviceToDevice, st));
+  LSB_HIP(hipMemcpyAsync(p->ws + p->off_scal, s + o_scal, lsb::SC_COUNT * sizeof(double), hipMemcpyDeviceToDevice, st));
+  p->ops->rebuild(p, st);
+  LSB_HIP(hipGetLastError());
+  LSB_HIP(hipStreamSynchronize(st));
+  p->nstep = hdr[1];
+  p->inited = true;
+  return LSB_OK;
+}
+
+long lsb_step_count(const lsb_plan* p) { return p ? p->nstep : -1; }
+
+int lsb_get_counts(lsb_plan* p, int* counts, void* stream) {
+  if (!p || !counts) return fail(LSB_EINVAL, "null argument");
+  if (!p->inited) return fail(LSB_ESTATE, "no state");
+  hipStream_t st = as_stream(stream);
+  int c[lsb::CNT_NUM];
+  LSB_HIP(hipMemcpyAsync(c, p->ws + p->off_cnt, sizeof(c), hipMemcpyDeviceToHost, st));
+  LSB_HIP(hipStreamSynchronize(st));
+  counts[0] = c[lsb::CNT_SPEC];
+  counts[1] = c[lsb::CNT_TILES];
+  counts[2] = c[lsb::CNT_FLIP];
+  return LSB_OK;
+}
+
+}  // extern "C"

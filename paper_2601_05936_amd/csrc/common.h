@@ -1,0 +1,212 @@
+// common.h -- device-side building blocks shared by the HIP kernels:
+// velocity sets, storage codecs, the kernel argument block, index helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+
+#include "../../include/lsb.h"
+
+namespace lsb {
+
+// Tag bits of one cell (one byte per cell).
+enum : uint8_t {
+  T_GAS = 1,      // phase: gas (phi >= 0)
+  T_ACT = 2,      // LS-active: in the narrow band or next to it
+  T_SPEC = 4,     // has a lattice link to a cell of the other phase
+  T_OLDGAS = 16,  // phase before the last classification (refill)
+};
+
+// ---------------------------------------------------------------------------
+// Velocity sets.  Direction order of the paper's velocity-set figure, rest
+// last.  D3Q19 = D3Q27 directions 0..17 + rest.
+// ---------------------------------------------------------------------------
+template <int LAT>
+struct Lat;
+
+template <>
+struct Lat<LSB_D2Q9> {
+  static constexpr int D = 2, Q = 9;
+  __host__ __device__ static constexpr int cx(int i) { return (i == 0 || i == 4 || i == 5) ? -1 : ((i == 1 || i == 6 || i == 7) ? 1 : 0); }
+  __host__ __device__ static constexpr int cy(int i) { return (i == 2 || i == 4 || i == 7) ? -1 : ((i == 3 || i == 5 || i == 6) ? 1 : 0); }
+  __host__ __device__ static constexpr int cz(int) { return 0; }
+};
+
+namespace detail {
+// D3Q27 directions of the paper's figure, packed as (cx+1) + 3(cy+1) + 9(cz+1).
+__host__ __device__ constexpr int d3q27_code(int i) {
+  constexpr int code[27] = {12, 14, 10, 16, 4, 22, 9, 15, 11, 17, 3, 21, 5, 23, 1, 19, 7, 25,
+                            0, 18, 6, 24, 2, 20, 8, 26, 13};
+  return code[i];
+}
+}  // namespace detail
+
+template <>
+struct Lat<LSB_D3Q27> {
+  static constexpr int D = 3, Q = 27;
+  __host__ __device__ static constexpr int cx(int i) { return detail::d3q27_code(i) % 3 - 1; }
+  __host__ __device__ static constexpr int cy(int i) { return (detail::d3q27_code(i) / 3) % 3 - 1; }
+  __host__ __device__ static constexpr int cz(int i) { return detail::d3q27_code(i) / 9 - 1; }
+};
+
+template <>
+struct Lat<LSB_D3Q19> {
+  static constexpr int D = 3, Q = 19;
+  __host__ __device__ static constexpr int cx(int i) { return i == 18 ? 0 : Lat<LSB_D3Q27>::cx(i); }
+  __host__ __device__ static constexpr int cy(int i) { return i == 18 ? 0 : Lat<LSB_D3Q27>::cy(i); }
+  __host__ __device__ static constexpr int cz(int i) { return i == 18 ? 0 : Lat<LSB_D3Q27>::cz(i); }
+};
+
+template <int LAT>
+__host__ __device__ constexpr int c2(int i) {
+  return Lat<LAT>::cx(i) * Lat<LAT>::cx(i) + Lat<LAT>::cy(i) * Lat<LAT>::cy(i) + Lat<LAT>::cz(i) * Lat<LAT>::cz(i);
+}
+
+// Lattice weights (Sec. 2.1; D3Q19 textbook).
+template <int LAT>
+__host__ __device__ constexpr double wgt(int i) {
+  return LAT == LSB_D2Q9 ? (c2<LAT>(i) == 0 ? 4.0 / 9 : c2<LAT>(i) == 1 ? 1.0 / 9 : 1.0 / 36)
+       : LAT == LSB_D3Q19 ? (c2<LAT>(i) == 0 ? 1.0 / 3 : c2<LAT>(i) == 1 ? 1.0 / 18 : 1.0 / 36)
+       : (c2<LAT>(i) == 0 ? 8.0 / 27 : c2<LAT>(i) == 1 ? 2.0 / 27 : c2<LAT>(i) == 2 ? 1.0 / 54 : 1.0 / 216);
+}
+
+template <int LAT>
+__host__ __device__ constexpr int opp(int i) {
+  int j = 0;
+  for (int k = 0; k < Lat<LAT>::Q; ++k)
+    if (Lat<LAT>::cx(k) == -Lat<LAT>::cx(i) && Lat<LAT>::cy(k) == -Lat<LAT>::cy(i) && Lat<LAT>::cz(k) == -Lat<LAT>::cz(i)) j = k;
+  return j;
+}
+
+template <int LAT>
+__host__ __device__ constexpr int dir_of(int x, int y, int z) {
+  int j = -1;
+  for (int k = 0; k < Lat<LAT>::Q; ++k)
+    if (Lat<LAT>::cx(k) == x && Lat<LAT>::cy(k) == y && Lat<LAT>::cz(k) == z) j = k;
+  return j;
+}
+
+// ---------------------------------------------------------------------------
+// Storage codecs.  Populations are kept as deviations d_i = f_i - w_i from
+// the rest state; the FP16/BF16 paths store s d_i / w_i.
+// ---------------------------------------------------------------------------
+template <int ST>
+struct Codec;
+
+template <>
+struct Codec<LSB_F64> {
+  using T = double;
+  using R = double;
+  __device__ static R dec(T v, R, R) { return v; }
+  __device__ static T enc(R d, R, R) { return d; }
+};
+
+template <>
+struct Codec<LSB_F32> {
+  using T = float;
+  using R = float;
+  __device__ static R dec(T v, R, R) { return v; }
+  __device__ static T enc(R d, R, R) { return d; }
+};
+
+template <>
+struct Codec<LSB_F16DEV> {
+  using T = uint16_t;
+  using R = float;
+  // w_over_s = w / s, s_over_w = s / w
+  __device__ static R dec(T v, R w_over_s, R) { return __half2float(__ushort_as_half(v)) * w_over_s; }
+  __device__ static T enc(R d, R, R s_over_w) { return __half_as_ushort(__float2half_rn(d * s_over_w)); }
+};
+
+template <>
+struct Codec<LSB_BF16DEV> {
+  using T = uint16_t;
+  using R = float;
+  __device__ static R dec(T v, R w_over_s, R) {
+    return __uint_as_float(((unsigned)v) << 16) * w_over_s;
+  }
+  __device__ static T enc(R d, R, R s_over_w) {
+    __hip_bfloat16 b = __float2bfloat16(d * s_over_w);  // round to nearest even
+    return *reinterpret_cast<uint16_t*>(&b);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Kernel argument block (everything a kernel may need, by value).
+// ---------------------------------------------------------------------------
+template <class T, class R>
+struct KArgs {
+  int nx, ny, nz, N;
+  int per[3];         // axis periodic?
+  int bcf[6];         // face conditions
+  R wall_u[6][3];
+  R omega[2];
+  R acc[2][3];
+  R rho_phys[2];
+  R eta[2];
+  R sigma;
+  R band;
+  R ext_dtau, reinit_dtau;
+  R heps;
+  R scale;            // storage scale s
+  int use_pb;
+  // tiles
+  int tdim[3];        // tile extents
+  int ntile[3];       // tiles per axis
+  int ntiles;
+  // state
+  const T* __restrict__ A;  // populations read this step
+  T* __restrict__ An;       // populations written this step
+  R* phi;
+  R* s1;
+  R* s2;
+  R* p0;
+  uint8_t* tag;
+  uint8_t* aux;
+  const R* M;               // moments of the previous collision [10][N]
+  R* Mn;                    // moments written this step
+  R* G;                     // normal[3], kappa  [4][N]
+  R* ut_a;
+  R* ut_b;
+  double* scal;             // device scalars (see SC_*)
+  // lists
+  int* counters;            // see CNT_*
+  uint8_t* tile_act;        // per tile: has LS-active cells
+  int* tile_list;           // active tiles
+  int* cand_list;           // candidate tiles for classification
+  int* spec_list;           // interface-adjacent cells
+  int* flip_list;           // cells whose phase changed
+  double* partial;          // reduction partials
+};
+
+// device scalar slots
+enum { SC_PB = 0, SC_XC0 = 1, SC_XC = 4, SC_V = 7, SC_COUNT = 16 };
+// counters
+enum { CNT_TILES = 0, CNT_CAND = 1, CNT_SPEC = 2, CNT_FLIP = 3, CNT_NUM = 8 };
+
+// Level-set stencil coordinate: periodic wrap, or even mirror about a wall face.
+__device__ __forceinline__ int ls_coord(int s, int n, int periodic) {
+  if (s >= 0 && s < n) return s;
+  if (periodic) return s < 0 ? s + n * ((-s + n - 1) / n) : s % n;
+  return s < 0 ? -1 - s : 2 * n - 1 - s;
+}
+
+// Lattice neighbour coordinate: periodic wrap, -1 when leaving through a wall.
+__device__ __forceinline__ int lb_coord(int s, int n, int periodic) {
+  if (s >= 0 && s < n) return s;
+  if (!periodic) return -1;
+  return s < 0 ? s + n : s - n;
+}
+
+__device__ __forceinline__ unsigned remap_xcd(unsigned b, unsigned nb) {
+  // MI355X dispatches consecutive workgroups round-robin over 8 XCDs; give
+  // each XCD a contiguous range of logical blocks so that neighbouring blocks
+  // share one L2.
+  if ((nb & 7u) != 0u) return b;
+  return (b & 7u) * (nb >> 3) + (b >> 3);
+}
+
+}  // namespace lsb

@@ -1,0 +1,194 @@
+// driver.h -- host launch sequence of one time step and of the queries,
+// templated on the velocity set and the storage.  Included by one
+// translation unit per velocity set.
+#pragma once
+
+#include "kernels.h"
+#include "plan.h"
+
+namespace lsb {
+
+template <int LAT, int ST>
+struct Driver {
+  using S = Step<LAT, ST>;
+  using T = typename S::T;
+  using R = typename S::R;
+  using Args = typename S::Args;
+
+  static Args args(lsb_plan* p, int cur) {
+    Args a{};
+    const lsb_params& P = p->P;
+    a.nx = P.nx; a.ny = P.ny; a.nz = P.nz; a.N = p->N;
+    for (int ax = 0; ax < 3; ++ax) a.per[ax] = P.bc[2 * ax] == LSB_PERIODIC;
+    for (int f = 0; f < 6; ++f) {
+      a.bcf[f] = P.bc[f];
+      for (int m = 0; m < 3; ++m) a.wall_u[f][m] = (R)P.wall_u[f][m];
+    }
+    for (int k = 0; k < 2; ++k) {
+      const double nu = (P.tau[k] - 0.5) / 3.0;
+      a.omega[k] = (R)((1.0 / 3.0) / (nu + 0.5 / 3.0));
+      for (int m = 0; m < 3; ++m) a.acc[k][m] = (R)P.accel[k][m];
+      a.rho_phys[k] = (R)P.rho_phys[k];
+      a.eta[k] = (R)(P.rho_phys[k] * nu);
+    }
+    a.sigma = (R)P.sigma;
+    a.band = (R)P.band;
+    a.ext_dtau = (R)P.ext_dtau;
+    a.reinit_dtau = (R)P.reinit_dtau;
+    a.heps = (R)P.heaviside_eps;
+    a.scale = ST == LSB_F16DEV ? (R)ldexp(1.0, P.fp16_scale_log2) : (R)1;
+    a.use_pb = P.use_pb;
+    for (int ax = 0; ax < 3; ++ax) { a.tdim[ax] = p->tdim[ax]; a.ntile[ax] = p->ntile[ax]; }
+    a.ntiles = p->ntiles;
+    char* w = p->ws;
+    a.A = reinterpret_cast<const T*>(w + p->off_A[cur]);
+    a.An = reinterpret_cast<T*>(w + p->off_A[cur ^ 1]);
+    a.phi = reinterpret_cast<R*>(w + p->off_phi);
+    a.s1 = reinterpret_cast<R*>(w + p->off_s1);
+    a.s2 = reinterpret_cast<R*>(w + p->off_s2);
+    a.p0 = reinterpret_cast<R*>(w + p->off_p0);
+    a.tag = reinterpret_cast<uint8_t*>(w + p->off_tag);
+    a.aux = reinterpret_cast<uint8_t*>(w + p->off_aux);
+    a.M = reinterpret_cast<const R*>(w + p->off_M[cur]);
+    a.Mn = reinterpret_cast<R*>(w + p->off_M[cur ^ 1]);
+    a.G = reinterpret_cast<R*>(w + p->off_G);
+    a.ut_a = reinterpret_cast<R*>(w + p->off_ut[0]);
+    a.ut_b = reinterpret_cast<R*>(w + p->off_ut[1]);
+    a.scal = reinterpret_cast<double*>(w + p->off_scal);
+    a.counters = reinterpret_cast<int*>(w + p->off_cnt);
+    a.tile_act = reinterpret_cast<uint8_t*>(w + p->off_tile_act);
+    a.tile_list = reinterpret_cast<int*>(w + p->off_tile_list);
+    a.cand_list = reinterpret_cast<int*>(w + p->off_cand_list);
+    a.spec_list = reinterpret_cast<int*>(w + p->off_spec_list);
+    a.flip_list = reinterpret_cast<int*>(w + p->off_flip_list);
+    a.partial = reinterpret_cast<double*>(w + p->off_partial);
+    return a;
+  }
+
+  static int cell_grid(const lsb_plan* p) {
+    long g = ((long)p->N + 255) / 256;
+    return (int)(g < 8192 ? g : 8192);
+  }
+
+  // Classification of all tiles (initialisation and state reload).
+  static void classify_all(lsb_plan* p, hipStream_t st) {
+    Args a = args(p, p->cur);
+    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a);
+    k_dilate<LAT, ST><<<(p->ntiles + 255) / 256, 256, 0, st>>>(a, 1);
+    k_classify<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a, 0);
+    k_geometry<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
+  }
+
+  static void centroid(lsb_plan* p, int mode, hipStream_t st) {
+    Args a = args(p, p->cur);
+    k_centroid_partial<LAT, ST><<<p->red_blocks, 256, 0, st>>>(a);
+    const lsb_params& P = p->P;
+    k_centroid_final<LAT, ST><<<1, 256, 0, st>>>(a, p->red_blocks, mode, P.pb0, P.rho_phys[0], P.accel[0][0],
+                                                 P.accel[0][1], P.accel[0][2]);
+  }
+
+  static void init_phi(lsb_plan* p, const double* phi0, int c0, int c1, hipStream_t st) {
+    p->cur = 0;
+    Args a = args(p, 0);
+    const int g = (int)(((long)(c1 - c0) + 255) / 256 < 8192 ? ((long)(c1 - c0) + 255) / 256 : 8192);
+    k_init_phi<LAT, ST><<<g > 0 ? g : 1, 256, 0, st>>>(a, phi0, c0, c1);
+  }
+
+  static void init_band(lsb_plan* p, hipStream_t st) {
+    Args a = args(p, p->cur);
+    k_clear_tiles<LAT, ST><<<(p->ntiles + 255) / 256, 256, 0, st>>>(a);
+    classify_all(p, st);
+    centroid(p, 0, st);
+    k_set_scalar<LAT, ST><<<1, 1, 0, st>>>(a, SC_PB, p->P.pb0);
+  }
+
+  // populations and both moment buffers of the current state (buffer 0)
+  static void init_pop(lsb_plan* p, const double* rho0, const double* u0, int c0, int c1, hipStream_t st) {
+    Args b = args(p, 1);  // b.An == buffer 0, b.M == buffer 1, b.Mn == buffer 0
+    const int g = (int)(((long)(c1 - c0) + 255) / 256 < 8192 ? ((long)(c1 - c0) + 255) / 256 : 8192);
+    k_init_pop<LAT, ST><<<g > 0 ? g : 1, 256, 0, st>>>(b, rho0, u0, p->P.init_hydrostatic, c0, c1);
+  }
+
+  static void step(lsb_plan* p, hipStream_t st) {
+    const lsb_params& P = p->P;
+    Args a = args(p, p->cur);
+    const int xchunks = (P.nx + 255) / 256;
+    const int rows = P.ny * P.nz;
+    // a2-a4: collide and stream
+    k_lb_bulk<LAT, ST><<<xchunks * rows, 256, 0, st>>>(a, xchunks);
+    k_lb_iface<LAT, ST><<<p->grid_cells, 256, 0, st>>>(a);
+    // a6: extension (ut ping-pong), advection
+    k_ext_seed<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
+    R* ua = a.ut_a;
+    R* ub = a.ut_b;
+    for (int it = 0; it < P.n_ext; ++it) {
+      Args e = a;
+      e.ut_a = ua;
+      e.ut_b = ub;
+      k_ext_iter<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(e);
+      R* t = ua; ua = ub; ub = t;
+    }
+    for (int stage = 1; stage <= 3; ++stage) k_rk3_stage<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a, stage, ua);
+    // a7: reinitialisation
+    if (P.reinit_every > 0 && P.n_reinit > 0 && ((p->nstep + 1) % P.reinit_every) == 0) {
+      k_reinit_prep<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
+      for (int it = 0; it < P.n_reinit; ++it)
+        for (int stage = 1; stage <= 3; ++stage)
+          k_reinit_stage<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a, stage, it == P.n_reinit - 1 ? 1 : 0);
+    }
+    k_ls_sync<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
+    // a8: classification on the dilated band, geometry, refill
+    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a);
+    k_dilate<LAT, ST><<<(p->ntiles + 255) / 256, 256, 0, st>>>(a, 0);
+    k_classify<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a, 1);
+    k_geometry<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
+    k_refill<LAT, ST><<<p->grid_cells, 256, 0, st>>>(a);
+    p->cur ^= 1;
+    // a9: centroid and gas pressure baseline
+    if (P.use_pb) centroid(p, 1, st);
+    ++p->nstep;
+  }
+
+  static void fields(lsb_plan* p, double* rho, double* u, double* pr, uint8_t* ph, int c0, int c1, hipStream_t st) {
+    k_fields<LAT, ST><<<cell_grid(p), 256, 0, st>>>(args(p, p->cur), rho, u, pr, ph, c0, c1);
+  }
+  static void populations(lsb_plan* p, double* out, int i0, int i1, int c0, int c1, hipStream_t st) {
+    k_populations<LAT, ST><<<cell_grid(p), 256, 0, st>>>(args(p, p->cur), out, i0, i1, c0, c1);
+  }
+  static void interface(lsb_plan* p, double* phi, double* nrm, double* kap, uint8_t* tags, int c0, int c1,
+                        hipStream_t st) {
+    k_export_interface<LAT, ST><<<cell_grid(p), 256, 0, st>>>(args(p, p->cur), phi, nrm, kap, tags, c0, c1);
+  }
+  static void moments(lsb_plan* p, double* out, int c0, int c1, hipStream_t st) {
+    k_export_moments<LAT, ST><<<cell_grid(p), 256, 0, st>>>(args(p, p->cur), out, c0, c1);
+  }
+  static void integrals_partial(lsb_plan* p, hipStream_t st) {
+    k_integrals_partial<LAT, ST><<<p->red_blocks, 256, 0, st>>>(args(p, p->cur));
+  }
+  static void rebuild(lsb_plan* p, hipStream_t st) {
+    Args a = args(p, p->cur);
+    k_clear_tiles<LAT, ST><<<(p->ntiles + 255) / 256, 256, 0, st>>>(a);
+    classify_all(p, st);
+  }
+
+  static const Ops* table() {
+    static const Ops ops = {init_phi, init_band, init_pop, step, fields, populations, interface, moments,
+                            integrals_partial, rebuild};
+    return &ops;
+  }
+};
+
+}  // namespace lsb
+
+#define LSB_DEFINE_OPS(NAME, LAT)                                   \
+  namespace lsb {                                                   \
+  const Ops* NAME(int storage) {                                    \
+    switch (storage) {                                              \
+      case LSB_F64: return Driver<LAT, LSB_F64>::table();           \
+      case LSB_F32: return Driver<LAT, LSB_F32>::table();           \
+      case LSB_F16DEV: return Driver<LAT, LSB_F16DEV>::table();     \
+      case LSB_BF16DEV: return Driver<LAT, LSB_BF16DEV>::table();   \
+      default: return nullptr;                                      \
+    }                                                               \
+  }                                                                 \
+  }

@@ -1,0 +1,1100 @@
+// kernels.h -- HIP kernels of one time step, templated on the velocity set
+// (LAT) and the population storage (ST).  Included by one translation unit
+// per velocity set.
+//
+// Data layout in HBM (structure of arrays, cell index c = (z*ny + y)*nx + x):
+//   A[i][c]     populations as deviations from the rest state (codec ST)
+//   phi[c]      level set; s1/s2 Runge-Kutta stages; p0 reinit reference
+//   tag[c]      bit field (T_* in common.h)
+//   M[m][c]     rho, u[3], S[6] of the last collision (LS-active cells)
+//   G[m][c]     normal[3], curvature (LS-active cells)
+//   ut[a][c]    extension velocity
+// The level-set kernels run over a compact list of 8x8x8 (3D) or 16x16 (2D)
+// tiles that hold LS-active cells, with a fixed grid that strides over the
+// device-resident tile count.
+#pragma once
+
+#include "common.h"
+
+namespace lsb {
+
+template <int LAT, int ST>
+struct Step {
+  using L = Lat<LAT>;
+  using C = Codec<ST>;
+  using T = typename C::T;
+  using R = typename C::R;
+  using Args = KArgs<T, R>;
+  static constexpr int Q = L::Q;
+  static constexpr int D = L::D;
+};
+
+// ---------------------------------------------------------------------------
+// a2: moments, BGK collision with body force, store; moments to M on active
+// cells.  d[] holds the incoming deviations f_i - w_i after streaming and
+// bounce-back.
+// ---------------------------------------------------------------------------
+template <int LAT, int ST>
+__device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args& a, int c, int k, bool active,
+                                              typename Step<LAT, ST>::R* d) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  using L = typename S::L;
+  using C = typename S::C;
+  constexpr int Q = S::Q;
+  R rp = 0, m0 = 0, m1 = 0, m2 = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    rp += d[i];
+    if (L::cx(i)) m0 += (R)L::cx(i) * d[i];
+    if (L::cy(i)) m1 += (R)L::cy(i) * d[i];
+    if (L::cz(i)) m2 += (R)L::cz(i) * d[i];
+  }
+  const R rho = (R)1 + rp;
+  const R inv = (R)1 / rho;
+  const R ux = m0 * inv, uy = m1 * inv, uz = m2 * inv;
+  const R uu = ux * ux + uy * uy + uz * uz;
+  const R om = a.omega[k];
+  const R fx = (R)3 * a.acc[k][0], fy = (R)3 * a.acc[k][1], fz = (R)3 * a.acc[k][2];
+  R P0 = 0, P1 = 0, P2 = 0, P3 = 0, P4 = 0, P5 = 0;
+  const R s = a.scale;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R w = (R)wgt<LAT>(i);
+    const R cu = (R)L::cx(i) * ux + (R)L::cy(i) * uy + (R)L::cz(i) * uz;
+    const R deq = w * (rp + rho * ((R)3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu));
+    const R fn = d[i] - deq;
+    if (active) {
+      if (L::cx(i)) P0 += fn;
+      if (L::cy(i)) P1 += fn;
+      if (L::cz(i)) P2 += fn;
+      if (L::cx(i) * L::cy(i)) P3 += (R)(L::cx(i) * L::cy(i)) * fn;
+      if (L::cx(i) * L::cz(i)) P4 += (R)(L::cx(i) * L::cz(i)) * fn;
+      if (L::cy(i) * L::cz(i)) P5 += (R)(L::cy(i) * L::cz(i)) * fn;
+    }
+    const R ca = (R)L::cx(i) * fx + (R)L::cy(i) * fy + (R)L::cz(i) * fz;
+    const R out = d[i] - om * fn + w * rho * ca;
+    a.An[(size_t)i * a.N + c] = C::enc(out, w / s, s / w);
+  }
+  if (active) {
+    const size_t N = a.N;
+    const R fac = -(R)1.5 * om * inv;  // -omega / (2 rho cs^2)
+    a.Mn[c] = rho;
+    a.Mn[N + c] = ux;
+    a.Mn[2 * N + c] = uy;
+    a.Mn[3 * N + c] = uz;
+    a.Mn[4 * N + c] = fac * P0;
+    a.Mn[5 * N + c] = fac * P1;
+    a.Mn[6 * N + c] = fac * P2;
+    a.Mn[7 * N + c] = fac * P3;
+    a.Mn[8 * N + c] = fac * P4;
+    a.Mn[9 * N + c] = fac * P5;
+  }
+}
+
+// Reflection of direction i across the crossed axes (mask bit a = axis a).
+template <int LAT>
+__host__ __device__ constexpr int reflect_dir(int i, int mask) {
+  return dir_of<LAT>((mask & 1) ? -Lat<LAT>::cx(i) : Lat<LAT>::cx(i), (mask & 2) ? -Lat<LAT>::cy(i) : Lat<LAT>::cy(i),
+                     (mask & 4) ? -Lat<LAT>::cz(i) : Lat<LAT>::cz(i));
+}
+
+// a3: incoming deviation for a link whose source lies beyond a wall face.
+// Halfway bounce-back with the moving-wall term if any crossed face is
+// no-slip; specular reflection otherwise.  check_phase: a reflected source
+// in the other phase falls back to plain bounce-back.
+template <int LAT, int ST, bool check_phase>
+__device__ __noinline__ typename Step<LAT, ST>::R wall_pull(const typename Step<LAT, ST>::Args& a, int c, int x, int y,
+                                                              int z, int i, int k) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  using L = typename S::L;
+  using C = typename S::C;
+  const int cc[3] = {L::cx(i), L::cy(i), L::cz(i)};
+  const int pos[3] = {x, y, z};
+  const int n[3] = {a.nx, a.ny, a.nz};
+  int mask = 0;
+  int src[3];
+  for (int ax = 0; ax < 3; ++ax) {
+    int sv = pos[ax] - cc[ax];
+    if (sv >= 0 && sv < n[ax]) { src[ax] = sv; continue; }
+    if (a.per[ax]) { src[ax] = sv < 0 ? sv + n[ax] : sv - n[ax]; continue; }
+    mask |= 1 << ax;
+    src[ax] = pos[ax];
+  }
+  const R s = a.scale;
+  const int j = opp<LAT>(i);
+  const R wj = (R)wgt<LAT>(j);
+  for (int ax = 0; ax < 3; ++ax) {
+    if (!(mask & (1 << ax))) continue;
+    const int face = 2 * ax + (pos[ax] - cc[ax] < 0 ? 0 : 1);
+    if (a.bcf[face] == LSB_NOSLIP) {
+      const R cu = (R)cc[0] * a.wall_u[face][0] + (R)cc[1] * a.wall_u[face][1] + (R)cc[2] * a.wall_u[face][2];
+      return C::dec(a.A[(size_t)j * a.N + c], wj / s, s / wj) + (R)6 * (R)wgt<LAT>(i) * cu;
+    }
+  }
+  const int ir = reflect_dir<LAT>(i, mask);
+  const int sc = (src[2] * a.ny + src[1]) * a.nx + src[0];
+  if (check_phase && ((a.tag[sc] & T_GAS) != k)) return C::dec(a.A[(size_t)j * a.N + c], wj / s, s / wj);
+  const R wr = (R)wgt<LAT>(ir);
+  return C::dec(a.A[(size_t)ir * a.N + sc], wr / s, s / wr);
+}
+
+// ---------------------------------------------------------------------------
+// a2/a3 bulk: cells with no lattice link to the other phase.  One thread per
+// cell, 256-cell blocks along x, XCD-aware block order.
+// ---------------------------------------------------------------------------
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_lb_bulk(const typename Step<LAT, ST>::Args a, int xchunks) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  using L = typename S::L;
+  using C = typename S::C;
+  constexpr int Q = S::Q;
+  const unsigned b = remap_xcd(blockIdx.x, gridDim.x);
+  const int row = (int)(b / (unsigned)xchunks);
+  const int x = (int)(b - (unsigned)row * xchunks) * 256 + (int)threadIdx.x;
+  if (x >= a.nx) return;
+  const int y = row % a.ny;
+  const int z = row / a.ny;
+  const int c = row * a.nx + x;
+  const uint8_t t = a.tag[c];
+  if (t & T_SPEC) return;
+  const int k = t & T_GAS;
+  // source coordinate x - c for c = -1, 0, +1
+  const int xs[3] = {lb_coord(x + 1, a.nx, a.per[0]), x, lb_coord(x - 1, a.nx, a.per[0])};
+  const int ys[3] = {lb_coord(y + 1, a.ny, a.per[1]), y, lb_coord(y - 1, a.ny, a.per[1])};
+  const int zs[3] = {lb_coord(z + 1, a.nz, a.per[2]), z, lb_coord(z - 1, a.nz, a.per[2])};
+  const R s = a.scale;
+  R d[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int sx = xs[L::cx(i) + 1], sy = ys[L::cy(i) + 1], sz = zs[L::cz(i) + 1];
+    const R w = (R)wgt<LAT>(i);
+    if ((sx | sy | sz) >= 0) {
+      d[i] = C::dec(a.A[(size_t)i * a.N + (sz * a.ny + sy) * a.nx + sx], w / s, s / w);
+    } else {
+      d[i] = wall_pull<LAT, ST, false>(a, c, x, y, z, i, k);
+    }
+  }
+  collide_store<LAT, ST>(a, c, k, (t & T_ACT) != 0, d);
+}
+
+// ---------------------------------------------------------------------------
+// a4: interface bounce-back (eq:bb with the momentum term eq:bb_cc and the
+// stress jump eq:Sdecomp).  Own cell c (phase k) pulls direction i from the
+// other-phase cell sc = c - c_i.  Deviation form: all weights of the
+// interpolation sum to one, so the rest state cancels.
+// ---------------------------------------------------------------------------
+template <int LAT, int ST>
+__device__ __noinline__ typename Step<LAT, ST>::R iface_pull(const typename Step<LAT, ST>::Args& a, int c, int x, int y,
+                                                               int z, int sc, int i, int k) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  using L = typename S::L;
+  using C = typename S::C;
+  const size_t N = a.N;
+  const int cc[3] = {L::cx(i), L::cy(i), L::cz(i)};
+  const int j = opp<LAT>(i);
+  const R s = a.scale;
+  const R w = (R)wgt<LAT>(i);
+  const R px = a.phi[c], py = a.phi[sc];
+  const R q = px / (px - py);
+  // interface velocity (linear interpolation of the previous moments)
+  R uG[3], nG[3];
+  for (int m = 0; m < 3; ++m) uG[m] = ((R)1 - q) * a.M[(1 + m) * N + c] + q * a.M[(1 + m) * N + sc];
+  R nn = 0;
+  for (int m = 0; m < 3; ++m) {
+    nG[m] = ((R)1 - q) * a.G[m * N + c] + q * a.G[m * N + sc];
+    nn += nG[m] * nG[m];
+  }
+  const R nl = sqrt(nn);
+  if (nl > (R)1e-30) for (int m = 0; m < 3; ++m) nG[m] = nG[m] / nl;
+  const R kG = ((R)1 - q) * a.G[3 * N + c] + q * a.G[3 * N + sc];
+  const int o = 1 - k;
+  const R pb = (R)a.scal[SC_PB];
+  R p_own = a.rho_phys[k] / (R)3 * (a.M[c] - (R)1) + (k == 1 ? pb : (R)0);
+  R p_oth = a.rho_phys[o] / (R)3 * (a.M[sc] - (R)1) + (o == 1 ? pb : (R)0);
+  for (int m = 0; m < 3; ++m) {
+    p_own = p_own + a.rho_phys[k] * a.acc[k][m] * (R)(-cc[m]) * q;
+    p_oth = p_oth + a.rho_phys[o] * a.acc[o][m] * (R)cc[m] * ((R)1 - q);
+  }
+  const R p_l = (k == 0) ? p_own : p_oth;
+  const R p_g = (k == 0) ? p_oth : p_own;
+  const R eta_bar = (R)0.5 * (a.eta[0] + a.eta[1]);
+  const R jeta = a.eta[1] - a.eta[0];
+  // pressure part of the normal jump: divisor floored at rho_max cs^2 / 8 so
+  // that the explicit pressure feedback cannot overshoot
+  const R rmax = a.rho_phys[0] > a.rho_phys[1] ? a.rho_phys[0] : a.rho_phys[1];
+  const R eta_p = eta_bar > rmax / (R)24 ? eta_bar : rmax / (R)24;
+  const R E = ((p_g - p_l) + a.sigma * kG) / ((R)2 * eta_p);
+  R Sb[6];
+  for (int m = 0; m < 6; ++m) Sb[m] = (R)0.5 * (a.M[(4 + m) * N + c] + a.M[(4 + m) * N + sc]);
+  const R acoef = -jeta / eta_bar;
+  const R Sm[3][3] = {{Sb[0], Sb[3], Sb[4]}, {Sb[3], Sb[1], Sb[5]}, {Sb[4], Sb[5], Sb[2]}};
+  const R cn = (R)cc[0] * nG[0] + (R)cc[1] * nG[1] + (R)cc[2] * nG[2];
+  R nAn = 0, nAc = 0;
+  for (int p = 0; p < 3; ++p)
+    for (int r = 0; r < 3; ++r) {
+      nAn = nAn + acoef * nG[p] * Sm[p][r] * nG[r];
+      nAc = nAc + acoef * nG[p] * Sm[p][r] * (R)cc[r];
+    }
+  const R cSc = cn * cn * E + (R)2 * cn * nAc - cn * cn * nAn;
+  const R s_own = (k == 0) ? (R)1 : (R)-1;
+  const R cu = (R)cc[0] * uG[0] + (R)cc[1] * uG[1] + (R)cc[2] * uG[2];
+  const R W = (R)6 * w * (cu + q * ((R)1 - q) * s_own * cSc);
+  const R dj = C::dec(a.A[(size_t)j * N + c], w / s, s / w);
+  if (q < (R)0.5) {
+    const int fx = lb_coord(x + cc[0], a.nx, a.per[0]);
+    const int fy = lb_coord(y + cc[1], a.ny, a.per[1]);
+    const int fz = lb_coord(z + cc[2], a.nz, a.per[2]);
+    if ((fx | fy | fz) >= 0) {
+      const int fc = (fz * a.ny + fy) * a.nx + fx;
+      if ((a.tag[fc] & T_GAS) == k) {
+        const R djf = C::dec(a.A[(size_t)j * N + fc], w / s, s / w);
+        return (R)2 * q * dj + ((R)1 - (R)2 * q) * djf + W;
+      }
+    }
+    return dj + W;
+  }
+  const R di = C::dec(a.A[(size_t)i * N + c], w / s, s / w);
+  return dj / ((R)2 * q) + ((R)2 * q - (R)1) / ((R)2 * q) * di + W / ((R)2 * q);
+}
+
+// a2-a4 for the listed interface-adjacent cells.
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::Args a) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  using L = typename S::L;
+  using C = typename S::C;
+  constexpr int Q = S::Q;
+  const int n = a.counters[CNT_SPEC];
+  const R s = a.scale;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+    const int c = a.spec_list[e];
+    const int x = c % a.nx;
+    const int y = (c / a.nx) % a.ny;
+    const int z = c / (a.nx * a.ny);
+    const uint8_t t = a.tag[c];
+    const int k = t & T_GAS;
+    R d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int sx = lb_coord(x - L::cx(i), a.nx, a.per[0]);
+      const int sy = lb_coord(y - L::cy(i), a.ny, a.per[1]);
+      const int sz = lb_coord(z - L::cz(i), a.nz, a.per[2]);
+      if ((sx | sy | sz) < 0) {
+        d[i] = wall_pull<LAT, ST, true>(a, c, x, y, z, i, k);
+        continue;
+      }
+      const int sc = (sz * a.ny + sy) * a.nx + sx;
+      if ((a.tag[sc] & T_GAS) == k) {
+        const R w = (R)wgt<LAT>(i);
+        d[i] = C::dec(a.A[(size_t)i * a.N + sc], w / s, s / w);
+      } else {
+        d[i] = iface_pull<LAT, ST>(a, c, x, y, z, sc, i, k);
+      }
+    }
+    collide_store<LAT, ST>(a, c, k, (t & T_ACT) != 0, d);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tile helpers for the level-set kernels.
+// ---------------------------------------------------------------------------
+template <class Args>
+__device__ __forceinline__ void tile_origin(const Args& a, int t, int& x0, int& y0, int& z0) {
+  const int tx = t % a.ntile[0];
+  const int ty = (t / a.ntile[0]) % a.ntile[1];
+  const int tz = t / (a.ntile[0] * a.ntile[1]);
+  x0 = tx * a.tdim[0];
+  y0 = ty * a.tdim[1];
+  z0 = tz * a.tdim[2];
+}
+
+// Loop body over the cells of the listed tiles:  F(c, x, y, z).
+template <class Args, class F>
+__device__ __forceinline__ void for_tile_cells(const Args& a, const int* list, int count, F&& f) {
+  const int tcells = a.tdim[0] * a.tdim[1] * a.tdim[2];
+  for (int e = blockIdx.x; e < count; e += gridDim.x) {
+    int x0, y0, z0;
+    tile_origin(a, list[e], x0, y0, z0);
+    for (int l = threadIdx.x; l < tcells; l += blockDim.x) {
+      const int x = x0 + l % a.tdim[0];
+      const int y = y0 + (l / a.tdim[0]) % a.tdim[1];
+      const int z = z0 + l / (a.tdim[0] * a.tdim[1]);
+      if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
+      f((z * a.ny + y) * a.nx + x, x, y, z);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a6: velocity extension.  Seed from the new moments Mn.
+// ---------------------------------------------------------------------------
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_ext_seed(const typename Step<LAT, ST>::Args a) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  using L = typename S::L;
+  const size_t N = a.N;
+  for_tile_cells(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
+    const uint8_t t = a.tag[c];
+    if (!(t & T_ACT)) return;
+    if (!(t & T_SPEC)) {
+      for (int m = 0; m < 3; ++m) a.ut_a[m * N + c] = a.Mn[(1 + m) * N + c];
+      return;
+    }
+    const int k = t & T_GAS;
+    R acc[3] = {0, 0, 0};
+    int cnt = 0;
+    for (int i = 0; i < S::Q; ++i) {
+      if (c2<LAT>(i) == 0) continue;
+      const int sx = lb_coord(x - L::cx(i), a.nx, a.per[0]);
+      const int sy = lb_coord(y - L::cy(i), a.ny, a.per[1]);
+      const int sz = lb_coord(z - L::cz(i), a.nz, a.per[2]);
+      if ((sx | sy | sz) < 0) continue;
+      const int sc = (sz * a.ny + sy) * a.nx + sx;
+      if ((a.tag[sc] & T_GAS) == k) continue;
+      const R q = a.phi[c] / (a.phi[c] - a.phi[sc]);
+      for (int m = 0; m < 3; ++m) acc[m] += ((R)1 - q) * a.Mn[(1 + m) * N + c] + q * a.Mn[(1 + m) * N + sc];
+      ++cnt;
+    }
+    for (int m = 0; m < 3; ++m) a.ut_a[m * N + c] = acc[m] / (R)cnt;
+  });
+}
+
+// One forward-Euler sweep of the first-order upwind extension; interface
+// cells are held.  Reads ut_a, writes ut_b.
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_ext_iter(const typename Step<LAT, ST>::Args a) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  const size_t N = a.N;
+  for_tile_cells(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
+    const uint8_t t = a.tag[c];
+    if (!(t & T_ACT)) return;
+    R u[3] = {a.ut_a[c], a.ut_a[N + c], a.ut_a[2 * N + c]};
+    if (!(t & T_SPEC)) {
+      const R ph = a.phi[c];
+      const R sg = ph / sqrt(ph * ph + (R)1);
+      const int pos[3] = {x, y, z};
+      const int n[3] = {a.nx, a.ny, a.nz};
+      R out[3] = {u[0], u[1], u[2]};
+      for (int ax = 0; ax < S::D; ++ax) {
+        const R v = sg * a.G[ax * N + c];
+        if (v == (R)0) continue;
+        const int dir = v > (R)0 ? -1 : 1;
+        const int sv = lb_coord(pos[ax] + dir, n[ax], a.per[ax]);
+        if (sv < 0) continue;
+        int p2[3] = {x, y, z};
+        p2[ax] = sv;
+        const int nc = (p2[2] * a.ny + p2[1]) * a.nx + p2[0];
+        if (!(a.tag[nc] & T_ACT)) continue;
+        for (int m = 0; m < 3; ++m) {
+          const R un = a.ut_a[m * N + nc];
+          const R diff = v > (R)0 ? (u[m] - un) : (un - u[m]);
+          out[m] -= a.ext_dtau * v * diff;
+        }
+      }
+      u[0] = out[0]; u[1] = out[1]; u[2] = out[2];
+    }
+    a.ut_b[c] = u[0];
+    a.ut_b[N + c] = u[1];
+    a.ut_b[2 * N + c] = u[2];
+  });
+}
+
+// ---------------------------------------------------------------------------
+// a6: TVD-RK3 stage of the transport equation with the fifth-order upwind
+// stencil.  stage 1: s1 = phi + L(phi); stage 2: s2 = 3/4 phi + 1/4 (s1 +
+// L(s1)); stage 3: phi = 1/3 phi + 2/3 (s2 + L(s2)), clamped to the band.
+// Non-active cells keep phi = s1 = s2 (maintained by k_ls_sync).
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ R upwind5(const R* f, int c, int stride_m3, int stride_m2, int stride_m1, int stride_p1,
+                                     int stride_p2, int stride_p3, bool positive) {
+  if (positive)
+    return ((R)-2 * f[stride_m3] + (R)15 * f[stride_m2] - (R)60 * f[stride_m1] + (R)20 * f[c] + (R)30 * f[stride_p1] -
+            (R)3 * f[stride_p2]) / (R)60;
+  return ((R)3 * f[stride_m2] - (R)30 * f[stride_m1] - (R)20 * f[c] + (R)60 * f[stride_p1] - (R)15 * f[stride_p2] +
+          (R)2 * f[stride_p3]) / (R)60;
+}
+
+template <class Args>
+__device__ __forceinline__ int ls_index(const Args& a, int x, int y, int z, int ax, int o) {
+  int p[3] = {x, y, z};
+  const int n[3] = {a.nx, a.ny, a.nz};
+  p[ax] = ls_coord(p[ax] + o, n[ax], a.per[ax]);
+  return (p[2] * a.ny + p[1]) * a.nx + p[0];
+}
+
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_rk3_stage(const typename Step<LAT, ST>::Args a, int stage, const typename Step<LAT, ST>::R* ut) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  const size_t N = a.N;
+  const R* in = stage == 1 ? a.phi : (stage == 2 ? a.s1 : a.s2);
+  R* out = stage == 1 ? a.s1 : (stage == 2 ? a.s2 : a.phi);
+  for_tile_cells(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
+    if (!(a.tag[c] & T_ACT)) return;
+    R r = 0;
+    for (int ax = 0; ax < S::D; ++ax) {
+      const R u = ut[ax * N + c];
+      const R dd = upwind5<R>(in, c, ls_index(a, x, y, z, ax, -3), ls_index(a, x, y, z, ax, -2),
+                              ls_index(a, x, y, z, ax, -1), ls_index(a, x, y, z, ax, 1), ls_index(a, x, y, z, ax, 2),
+                              ls_index(a, x, y, z, ax, 3), u >= (R)0);
+      r = r - u * dd;
+    }
+    const R v = in[c] + r;
+    R o;
+    if (stage == 1) o = v;
+    else if (stage == 2) o = (R)0.75 * a.phi[c] + (R)0.25 * v;
+    else {
+      o = ((R)1 / (R)3) * a.phi[c] + ((R)2 / (R)3) * v;
+      if (o > a.band) o = a.band;
+      if (o < -a.band) o = -a.band;
+    }
+    out[c] = o;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// a7: constrained reinitialisation (see the oracle's reading): prep stores
+// phi0 and the zero-set cells; each stage integrates
+// -S(phi0)(|grad phi|_Godunov-WENO5 - 1) plus the crossing-ratio forcing.
+// ---------------------------------------------------------------------------
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_reinit_prep(const typename Step<LAT, ST>::Args a) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  for_tile_cells(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
+    if (!(a.tag[c] & T_ACT)) return;
+    const R ph = a.phi[c];
+    a.p0[c] = ph;
+    const bool g0 = ph >= (R)0;
+    uint8_t fix = 0;
+    for (int ax = 0; ax < S::D; ++ax)
+      for (int sg = -1; sg <= 1; sg += 2)
+        if ((a.phi[ls_index(a, x, y, z, ax, sg)] >= (R)0) != g0) fix = 1;
+    a.aux[c] = fix;
+  });
+}
+
+template <class R>
+__device__ __forceinline__ R weno5(R v1, R v2, R v3, R v4, R v5) {
+  const R eps = (R)1e-6;
+  const R p0 = v1 / (R)3 - (R)7 * v2 / (R)6 + (R)11 * v3 / (R)6;
+  const R p1 = -v2 / (R)6 + (R)5 * v3 / (R)6 + v4 / (R)3;
+  const R p2 = v3 / (R)3 + (R)5 * v4 / (R)6 - v5 / (R)6;
+  const R a0 = v1 - (R)2 * v2 + v3, b0 = v1 - (R)4 * v2 + (R)3 * v3;
+  const R a1 = v2 - (R)2 * v3 + v4, b1 = v2 - v4;
+  const R a2 = v3 - (R)2 * v4 + v5, b2 = (R)3 * v3 - (R)4 * v4 + v5;
+  const R s0 = (R)13 / (R)12 * a0 * a0 + (R)0.25 * b0 * b0;
+  const R s1 = (R)13 / (R)12 * a1 * a1 + (R)0.25 * b1 * b1;
+  const R s2 = (R)13 / (R)12 * a2 * a2 + (R)0.25 * b2 * b2;
+  const R w0 = (R)0.1 / ((eps + s0) * (eps + s0));
+  const R w1 = (R)0.6 / ((eps + s1) * (eps + s1));
+  const R w2 = (R)0.3 / ((eps + s2) * (eps + s2));
+  return (w0 * p0 + w1 * p1 + w2 * p2) / (w0 + w1 + w2);
+}
+
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_reinit_stage(const typename Step<LAT, ST>::Args a, int stage, int last) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  const R* in = stage == 1 ? a.phi : (stage == 2 ? a.s1 : a.s2);
+  R* out = stage == 1 ? a.s1 : (stage == 2 ? a.s2 : a.phi);
+  const R beta = (R)0.5;
+  const R dt = a.reinit_dtau;
+  for_tile_cells(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
+    if (!(a.tag[c] & T_ACT)) return;
+    const R ph0 = a.p0[c];
+    const R S0 = ph0 / sqrt(ph0 * ph0 + (R)1);
+    R h2 = 0;
+    for (int ax = 0; ax < S::D; ++ax) {
+      const R m3 = in[ls_index(a, x, y, z, ax, -3)], m2 = in[ls_index(a, x, y, z, ax, -2)];
+      const R m1 = in[ls_index(a, x, y, z, ax, -1)], c0 = in[c];
+      const R q1 = in[ls_index(a, x, y, z, ax, 1)], q2 = in[ls_index(a, x, y, z, ax, 2)];
+      const R q3 = in[ls_index(a, x, y, z, ax, 3)];
+      const R dm = weno5<R>(m2 - m3, m1 - m2, c0 - m1, q1 - c0, q2 - q1);
+      const R dp = weno5<R>(q3 - q2, q2 - q1, q1 - c0, c0 - m1, m1 - m2);
+      R t;
+      if (S0 > (R)0) {
+        const R aa = dm > (R)0 ? dm : (R)0;
+        const R bb = dp < (R)0 ? dp : (R)0;
+        t = aa * aa > bb * bb ? aa * aa : bb * bb;
+      } else {
+        const R aa = dm < (R)0 ? dm : (R)0;
+        const R bb = dp > (R)0 ? dp : (R)0;
+        t = aa * aa > bb * bb ? aa * aa : bb * bb;
+      }
+      h2 = h2 + t;
+    }
+    R rt = -S0 * (sqrt(h2) - (R)1);
+    if (a.aux[c]) {
+      const bool g0 = ph0 >= (R)0;
+      R acc = 0;
+      int cnt = 0;
+      for (int ax = 0; ax < S::D; ++ax)
+        for (int sg = -1; sg <= 1; sg += 2) {
+          const int j = ls_index(a, x, y, z, ax, sg);
+          if ((a.p0[j] >= (R)0) == g0) continue;
+          acc = acc + ph0 * (in[c] - in[j]) / (ph0 - a.p0[j]);
+          ++cnt;
+        }
+      rt = rt + beta * (acc / (R)cnt - in[c]);
+    }
+    const R v = in[c] + dt * rt;
+    R o;
+    if (stage == 1) o = v;
+    else if (stage == 2) o = (R)0.75 * a.phi[c] + (R)0.25 * v;
+    else {
+      o = ((R)1 / (R)3) * a.phi[c] + ((R)2 / (R)3) * v;
+      if (last) {
+        if (o > a.band) o = a.band;
+        if (o < -a.band) o = -a.band;
+      }
+    }
+    out[c] = o;
+  });
+}
+
+// Restore phi = s1 = s2 = p0 on the band after the level-set update.
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_ls_sync(const typename Step<LAT, ST>::Args a) {
+  for_tile_cells(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int, int, int) {
+    if (!(a.tag[c] & T_ACT)) return;
+    const auto v = a.phi[c];
+    a.s1[c] = v;
+    a.s2[c] = v;
+    a.p0[c] = v;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// a8: classification.  Candidate tiles = active tiles dilated by one tile.
+// ---------------------------------------------------------------------------
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_reset_counters(const typename Step<LAT, ST>::Args a) {
+  if (threadIdx.x < CNT_NUM) a.counters[threadIdx.x] = 0;
+}
+
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_clear_tiles(const typename Step<LAT, ST>::Args a) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t < a.ntiles) a.tile_act[t] = 0;
+}
+
+template <int LAT, int ST>
+__global__ void k_set_scalar(const typename Step<LAT, ST>::Args a, int slot, double v) {
+  a.scal[slot] = v;
+}
+
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_dilate(const typename Step<LAT, ST>::Args a, int all) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.ntiles) return;
+  bool cand = all != 0;
+  if (!cand) {
+    const int tx = t % a.ntile[0], ty = (t / a.ntile[0]) % a.ntile[1], tz = t / (a.ntile[0] * a.ntile[1]);
+    const int zr = Step<LAT, ST>::D == 3 ? 1 : 0;
+    for (int dz = -zr; dz <= zr && !cand; ++dz)
+      for (int dy = -1; dy <= 1 && !cand; ++dy)
+        for (int dx = -1; dx <= 1 && !cand; ++dx) {
+          const int ux = lb_coord(tx + dx, a.ntile[0], a.per[0]);
+          const int uy = lb_coord(ty + dy, a.ntile[1], a.per[1]);
+          const int uz = lb_coord(tz + dz, a.ntile[2], a.per[2]);
+          if ((ux | uy | uz) < 0) continue;
+          if (a.tile_act[(uz * a.ntile[1] + uy) * a.ntile[0] + ux]) cand = true;
+        }
+  }
+  if (cand) {
+    const int slot = atomicAdd(&a.counters[CNT_CAND], 1);
+    a.cand_list[slot] = t;
+  }
+}
+
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_classify(const typename Step<LAT, ST>::Args a, int record_flips) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  using L = typename S::L;
+  __shared__ int any_act;
+  const int count = a.counters[CNT_CAND];
+  const int tcells = a.tdim[0] * a.tdim[1] * a.tdim[2];
+  const R B = a.band;
+  for (int e = blockIdx.x; e < count; e += gridDim.x) {
+    const int t = a.cand_list[e];
+    int x0, y0, z0;
+    tile_origin(a, t, x0, y0, z0);
+    if (threadIdx.x == 0) any_act = 0;
+    __syncthreads();
+    int mine = 0;
+    for (int l = threadIdx.x; l < tcells; l += blockDim.x) {
+      const int x = x0 + l % a.tdim[0];
+      const int y = y0 + (l / a.tdim[0]) % a.tdim[1];
+      const int z = z0 + l / (a.tdim[0] * a.tdim[1]);
+      if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
+      const int c = (z * a.ny + y) * a.nx + x;
+      const int ph = a.phi[c] >= (R)0 ? 1 : 0;
+      bool act = false;
+      const int zr = S::D == 3 ? 1 : 0;
+      for (int dz = -zr; dz <= zr && !act; ++dz)
+        for (int dy = -1; dy <= 1 && !act; ++dy)
+          for (int dx = -1; dx <= 1 && !act; ++dx) {
+            const int sx = lb_coord(x + dx, a.nx, a.per[0]);
+            const int sy = lb_coord(y + dy, a.ny, a.per[1]);
+            const int sz = lb_coord(z + dz, a.nz, a.per[2]);
+            if ((sx | sy | sz) < 0) continue;
+            const R v = a.phi[(sz * a.ny + sy) * a.nx + sx];
+            if (v < B && v > -B) act = true;
+          }
+      bool spec = false;
+      for (int i = 0; i < S::Q && !spec; ++i) {
+        if (c2<LAT>(i) == 0) continue;
+        const int sx = lb_coord(x - L::cx(i), a.nx, a.per[0]);
+        const int sy = lb_coord(y - L::cy(i), a.ny, a.per[1]);
+        const int sz = lb_coord(z - L::cz(i), a.nz, a.per[2]);
+        if ((sx | sy | sz) < 0) continue;
+        if ((a.phi[(sz * a.ny + sy) * a.nx + sx] >= (R)0 ? 1 : 0) != ph) spec = true;
+      }
+      const int old = a.tag[c] & T_GAS;
+      a.tag[c] = (uint8_t)(ph | (act ? T_ACT : 0) | (spec ? T_SPEC : 0) | (old ? T_OLDGAS : 0));
+      if (act) mine = 1;
+      if (spec) a.spec_list[atomicAdd(&a.counters[CNT_SPEC], 1)] = c;
+      if (record_flips && ph != old) a.flip_list[atomicAdd(&a.counters[CNT_FLIP], 1)] = c;
+    }
+    if (mine) any_act = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      a.tile_act[t] = any_act ? 1 : 0;
+      if (any_act) a.tile_list[atomicAdd(&a.counters[CNT_TILES], 1)] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a5: normal and curvature by central differences on the active cells.
+// ---------------------------------------------------------------------------
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_geometry(const typename Step<LAT, ST>::Args a) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  const size_t N = a.N;
+  for_tile_cells(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
+    if (!(a.tag[c] & T_ACT)) return;
+    auto at = [&](int dx, int dy, int dz) {
+      const int sx = ls_coord(x + dx, a.nx, a.per[0]);
+      const int sy = ls_coord(y + dy, a.ny, a.per[1]);
+      const int sz = ls_coord(z + dz, a.nz, a.per[2]);
+      return a.phi[(sz * a.ny + sy) * a.nx + sx];
+    };
+    const R p = a.phi[c];
+    const R gx = (R)0.5 * (at(1, 0, 0) - at(-1, 0, 0));
+    const R gy = (R)0.5 * (at(0, 1, 0) - at(0, -1, 0));
+    R gz = 0, zz = 0, xz = 0, yz = 0;
+    const R xx = at(1, 0, 0) - (R)2 * p + at(-1, 0, 0);
+    const R yy = at(0, 1, 0) - (R)2 * p + at(0, -1, 0);
+    const R xy = (R)0.25 * (at(1, 1, 0) - at(1, -1, 0) - at(-1, 1, 0) + at(-1, -1, 0));
+    if (S::D == 3) {
+      gz = (R)0.5 * (at(0, 0, 1) - at(0, 0, -1));
+      zz = at(0, 0, 1) - (R)2 * p + at(0, 0, -1);
+      xz = (R)0.25 * (at(1, 0, 1) - at(1, 0, -1) - at(-1, 0, 1) + at(-1, 0, -1));
+      yz = (R)0.25 * (at(0, 1, 1) - at(0, 1, -1) - at(0, -1, 1) + at(0, -1, -1));
+    }
+    const R g2 = gx * gx + gy * gy + gz * gz;
+    const R g = sqrt(g2);
+    if (g < (R)1e-12) {
+      a.G[c] = 0; a.G[N + c] = 0; a.G[2 * N + c] = 0; a.G[3 * N + c] = 0;
+      return;
+    }
+    a.G[c] = gx / g;
+    a.G[N + c] = gy / g;
+    a.G[2 * N + c] = gz / g;
+    const R num = xx * (gy * gy + gz * gz) + yy * (gx * gx + gz * gz) + zz * (gx * gx + gy * gy) - (R)2 * gx * gy * xy -
+                  (R)2 * gx * gz * xz - (R)2 * gy * gz * yz;
+    a.G[3 * N + c] = num / (g2 * g);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// a8: refill of cells whose phase changed (Sec. 2.4).  Reads only
+// established cells, writes only flipped cells.
+// ---------------------------------------------------------------------------
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_refill(const typename Step<LAT, ST>::Args a) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  using L = typename S::L;
+  using C = typename S::C;
+  constexpr int Q = S::Q;
+  const size_t N = a.N;
+  const int n = a.counters[CNT_FLIP];
+  const R s = a.scale;
+  const R pb = (R)a.scal[SC_PB];
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+    const int c = a.flip_list[e];
+    const int x = c % a.nx, y = (c / a.nx) % a.ny, z = c / (a.nx * a.ny);
+    const uint8_t t = a.tag[c];
+    const int knew = t & T_GAS;
+    const int kold = (t & T_OLDGAS) ? 1 : 0;
+    const R sgn = knew == 1 ? (R)1 : (R)-1;
+    const R m0 = sgn * a.G[c], m1 = sgn * a.G[N + c], m2 = sgn * a.G[2 * N + c];
+    // candidate directions by alignment with the normal into the new phase
+    int order[Q];
+    R score[Q];
+    int nc = 0;
+    for (int i = 0; i < Q; ++i) {
+      const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
+      const int l2 = cx * cx + cy * cy + cz * cz;
+      if (l2 == 0) continue;
+      const R sc = ((R)cx * m0 + (R)cy * m1 + (R)cz * m2) / sqrt((R)l2);
+      if (!(sc > (R)0)) continue;
+      int p = nc++;
+      order[p] = i;
+      score[p] = sc;
+      while (p > 0 && score[p - 1] < sc) {
+        order[p] = order[p - 1]; score[p] = score[p - 1];
+        order[p - 1] = i; score[p - 1] = sc;
+        --p;
+      }
+    }
+    const R rhoO = a.Mn[c];
+    const R uG0 = a.Mn[N + c], uG1 = a.Mn[2 * N + c], uG2 = a.Mn[3 * N + c];
+    const R pold = a.rho_phys[kold] / (R)3 * (rhoO - (R)1) + (kold == 1 ? pb : (R)0);
+    const R kap = a.G[3 * N + c];
+    const R pnew = knew == 0 ? pold + a.sigma * kap : pold - a.sigma * kap;
+    const R rhoG = (R)1 + (pnew - (knew == 1 ? pb : (R)0)) / (a.rho_phys[knew] / (R)3);
+    auto established = [&](int sc) {
+      const uint8_t ts = a.tag[sc];
+      return (ts & T_GAS) == knew && ((ts & T_OLDGAS) ? 1 : 0) == knew;
+    };
+    bool done = false;
+    for (int tt = 0; tt < nc && !done; ++tt) {
+      const int i = order[tt];
+      const int ex = L::cx(i), ey = L::cy(i), ez = L::cz(i);
+      const int x1 = lb_coord(x + ex, a.nx, a.per[0]), y1 = lb_coord(y + ey, a.ny, a.per[1]),
+                z1 = lb_coord(z + ez, a.nz, a.per[2]);
+      if ((x1 | y1 | z1) < 0) continue;
+      const int c1 = (z1 * a.ny + y1) * a.nx + x1;
+      if (!established(c1)) continue;
+      const int x2 = lb_coord(x + 2 * ex, a.nx, a.per[0]), y2 = lb_coord(y + 2 * ey, a.ny, a.per[1]),
+                z2 = lb_coord(z + 2 * ez, a.nz, a.per[2]);
+      int c2c = -1;
+      if ((x2 | y2 | z2) >= 0) {
+        const int cc2 = (z2 * a.ny + y2) * a.nx + x2;
+        if (established(cc2)) c2c = cc2;
+      }
+      const bool two = c2c >= 0;
+      R q;
+      const int xm = lb_coord(x - ex, a.nx, a.per[0]), ym = lb_coord(y - ey, a.ny, a.per[1]),
+                zm = lb_coord(z - ez, a.nz, a.per[2]);
+      const R phc = a.phi[c];
+      bool crossed = false;
+      if ((xm | ym | zm) >= 0) {
+        const R phm = a.phi[(zm * a.ny + ym) * a.nx + xm];
+        if ((phm >= (R)0) != (phc >= (R)0)) { crossed = true; q = phc / (phc - phm); }
+      }
+      if (!crossed) {
+        const R len = sqrt((R)(ex * ex + ey * ey + ez * ez));
+        const R en = ((R)ex * a.G[c] + (R)ey * a.G[N + c] + (R)ez * a.G[2 * N + c]) / len;
+        const R aen = fabs(en);
+        if (aen < (R)1e-12) q = (R)1;
+        else {
+          q = fabs(phc) / (aen * len);
+          if (q > (R)1) q = (R)1;
+        }
+      }
+      R w0, w1, w2 = 0;
+      if (two) {
+        w0 = (R)2 / ((q + (R)1) * (q + (R)2));
+        w1 = (R)2 * q / (q + (R)1);
+        w2 = -q / (q + (R)2);
+      } else {
+        w0 = (R)1 / ((R)1 + q);
+        w1 = q / ((R)1 + q);
+      }
+      const R rr = w0 * rhoG + w1 * a.Mn[c1] + (two ? w2 * a.Mn[c2c] : (R)0);
+      R ur[3];
+      const R uGv[3] = {uG0, uG1, uG2};
+      for (int m = 0; m < 3; ++m)
+        ur[m] = w0 * uGv[m] + w1 * a.Mn[(1 + m) * N + c1] + (two ? w2 * a.Mn[(1 + m) * N + c2c] : (R)0);
+      const R r1 = a.Mn[c1];
+      const R u1[3] = {a.Mn[N + c1], a.Mn[2 * N + c1], a.Mn[3 * N + c1]};
+      const R uur = ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2];
+      const R uu1 = u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const R w = (R)wgt<LAT>(k);
+        const R cur = (R)L::cx(k) * ur[0] + (R)L::cy(k) * ur[1] + (R)L::cz(k) * ur[2];
+        const R cu1 = (R)L::cx(k) * u1[0] + (R)L::cy(k) * u1[1] + (R)L::cz(k) * u1[2];
+        // equilibria as deviations from the rest state
+        const R de = w * ((rr - (R)1) + rr * ((R)3 * cur + (R)4.5 * cur * cur - (R)1.5 * uur));
+        const R de1 = w * ((r1 - (R)1) + r1 * ((R)3 * cu1 + (R)4.5 * cu1 * cu1 - (R)1.5 * uu1));
+        const R d1 = C::dec(a.An[(size_t)k * N + c1], w / s, s / w);
+        // f(x_r) = feq(rho_r, u_r) + (f(x1) - feq(x1))
+        a.An[(size_t)k * N + c] = C::enc(de + (d1 - de1), w / s, s / w);
+      }
+      a.Mn[c] = rr;
+      for (int m = 0; m < 3; ++m) a.Mn[(1 + m) * N + c] = ur[m];
+      for (int m = 0; m < 6; ++m) a.Mn[(4 + m) * N + c] = a.Mn[(4 + m) * N + c1];
+      done = true;
+    }
+    if (!done) {
+      const R uu = uG0 * uG0 + uG1 * uG1 + uG2 * uG2;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const R w = (R)wgt<LAT>(k);
+        const R cu = (R)L::cx(k) * uG0 + (R)L::cy(k) * uG1 + (R)L::cz(k) * uG2;
+        const R de = w * ((rhoG - (R)1) + rhoG * ((R)3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu));
+        a.An[(size_t)k * N + c] = C::enc(de, w / s, s / w);
+      }
+      a.Mn[c] = rhoG;
+      for (int m = 0; m < 6; ++m) a.Mn[(4 + m) * N + c] = 0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a9: Heaviside-weighted gas volume and centroid, deterministic two-pass
+// reduction in FP64 over a fixed grid.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double heaviside_d(double phi, double eps) {
+  if (phi < -eps) return 0.0;
+  if (phi > eps) return 1.0;
+  const double pi = 3.14159265358979323846;
+  return 0.5 * (1.0 + phi / eps + sin(pi * phi / eps) / pi);
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* part) {
+  __shared__ double sh[256];
+  for (int m = 0; m < NV; ++m) {
+    sh[threadIdx.x] = v[m];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[m] = sh[0];
+    __syncthreads();
+  }
+}
+
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_centroid_partial(const typename Step<LAT, ST>::Args a) {
+  double v[4] = {0, 0, 0, 0};
+  const double eps = (double)a.heps;
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < a.N; c += gridDim.x * 256) {
+    const double h = heaviside_d((double)a.phi[c], eps);
+    if (h == 0.0) continue;
+    const int x = c % a.nx, y = (c / a.nx) % a.ny, z = c / (a.nx * a.ny);
+    v[0] += h;
+    v[1] += h * (x + 0.5);
+    v[2] += h * (y + 0.5);
+    v[3] += h * (z + 0.5);
+  }
+  block_sum<4>(v, a.partial + 4 * blockIdx.x);
+}
+
+// mode 0: initial centroid -> SC_XC0; mode 1: centroid -> SC_XC and the
+// pressure baseline Pb = pb0 + rho_l a_l . (x_c - x_c0).
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_centroid_final(const typename Step<LAT, ST>::Args a, int nparts, int mode,
+                                                         double pb0, double rho_l, double al0, double al1, double al2) {
+  double v[4] = {0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nparts; b += 256)
+    for (int m = 0; m < 4; ++m) v[m] += a.partial[4 * b + m];
+  __shared__ double out[4];
+  block_sum<4>(v, out);
+  if (threadIdx.x == 0) {
+    const double V = out[0];
+    double xc[3];
+    for (int m = 0; m < 3; ++m) xc[m] = V > 0 ? out[1 + m] / V : 0.0;
+    a.scal[SC_V] = V;
+    if (mode == 0) {
+      for (int m = 0; m < 3; ++m) a.scal[SC_XC0 + m] = xc[m];
+    } else {
+      for (int m = 0; m < 3; ++m) a.scal[SC_XC + m] = xc[m];
+      double pb = pb0;
+      const double al[3] = {al0, al1, al2};
+      for (int m = 0; m < 3; ++m) pb = pb + rho_l * al[m] * (xc[m] - a.scal[SC_XC0 + m]);
+      a.scal[SC_PB] = pb;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation and output kernels.
+// ---------------------------------------------------------------------------
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_init_phi(const typename Step<LAT, ST>::Args a, const double* phi0, int c0,
+                                                  int c1) {
+  using R = typename Step<LAT, ST>::R;
+  for (int c = c0 + blockIdx.x * 256 + threadIdx.x; c < c1; c += gridDim.x * 256) {
+    double p = phi0[c - c0];
+    const double B = (double)a.band;
+    if (p > B) p = B;
+    if (p < -B) p = -B;
+    const R v = (R)p;
+    a.phi[c] = v; a.s1[c] = v; a.s2[c] = v; a.p0[c] = v;
+    a.tag[c] = 0;
+  }
+}
+
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_init_pop(const typename Step<LAT, ST>::Args a, const double* rho0,
+                                                  const double* u0, int hydro, int c0, int c1) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  using L = typename S::L;
+  using C = typename S::C;
+  const size_t N = a.N;
+  const R s = a.scale;
+  for (int c = c0 + blockIdx.x * 256 + threadIdx.x; c < c1; c += gridDim.x * 256) {
+    const int x = c % a.nx, y = (c / a.nx) % a.ny, z = c / (a.nx * a.ny);
+    const int k = a.tag[c] & T_GAS;
+    double rho;
+    if (rho0) rho = rho0[c - c0];
+    else {
+      rho = 1.0;
+      if (hydro) {
+        const double pos[3] = {x + 0.5, y + 0.5, z + 0.5};
+        for (int m = 0; m < 3; ++m) rho = rho + (double)a.acc[k][m] * (pos[m] - a.scal[SC_XC0 + m]) / (1.0 / 3.0);
+      }
+    }
+    double u[3] = {0, 0, 0};
+    if (u0) for (int m = 0; m < 3; ++m) u[m] = u0[3 * (size_t)(c - c0) + m];
+    if (S::D == 2) u[2] = 0;
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+#pragma unroll
+    for (int i = 0; i < S::Q; ++i) {
+      const double w = wgt<LAT>(i);
+      const double cu = L::cx(i) * u[0] + L::cy(i) * u[1] + L::cz(i) * u[2];
+      const double fe = w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+      a.An[(size_t)i * N + c] = C::enc((R)(fe - w), (R)w / s, s / (R)w);
+    }
+    R* Ms[2] = {const_cast<R*>(a.M), a.Mn};
+    for (int b = 0; b < 2; ++b) {
+      Ms[b][c] = (R)rho;
+      for (int m = 0; m < 3; ++m) Ms[b][(1 + m) * N + c] = (R)u[m];
+      for (int m = 0; m < 6; ++m) Ms[b][(4 + m) * N + c] = 0;
+    }
+  }
+}
+
+// Macroscopic output from the current populations (a.A).
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_fields(const typename Step<LAT, ST>::Args a, double* rho_out, double* u_out,
+                                                double* p_out, uint8_t* ph_out, int c0, int c1) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  using L = typename S::L;
+  using C = typename S::C;
+  const R s = a.scale;
+  for (int c = c0 + blockIdx.x * 256 + threadIdx.x; c < c1; c += gridDim.x * 256) {
+    double rho = 0, m[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < S::Q; ++i) {
+      const R w = (R)wgt<LAT>(i);
+      const double f = wgt<LAT>(i) + (double)C::dec(a.A[(size_t)i * a.N + c], w / s, s / w);
+      rho += f;
+      m[0] += L::cx(i) * f; m[1] += L::cy(i) * f; m[2] += L::cz(i) * f;
+    }
+    const int k = a.tag[c] & T_GAS;
+    const size_t o = (size_t)(c - c0);
+    if (rho_out) rho_out[o] = rho;
+    if (u_out)
+      for (int d = 0; d < S::D; ++d) u_out[(size_t)S::D * o + d] = m[d] / rho - 0.5 * (double)a.acc[k][d];
+    if (p_out) p_out[o] = (double)a.rho_phys[k] / 3.0 * (rho - 1.0) + (k == 1 ? a.scal[SC_PB] : 0.0);
+    if (ph_out) ph_out[o] = (uint8_t)k;
+  }
+}
+
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_populations(const typename Step<LAT, ST>::Args a, double* out, int i0, int i1,
+                                                     int c0, int c1) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  using C = typename S::C;
+  const R s = a.scale;
+  const size_t n = (size_t)(c1 - c0);
+  for (int c = c0 + blockIdx.x * 256 + threadIdx.x; c < c1; c += gridDim.x * 256)
+    for (int i = i0; i < i1; ++i) {
+      double w = 0;
+      for (int k = 0; k < S::Q; ++k) if (k == i) w = wgt<LAT>(k);
+      out[(size_t)(i - i0) * n + (c - c0)] = w + (double)C::dec(a.A[(size_t)i * a.N + c], (R)w / s, s / (R)w);
+    }
+}
+
+// Integral quantities: per-block partials of mass[2], V, sum x H[3],
+// sum u H[3], max |u|, bad-cell count.
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_integrals_partial(const typename Step<LAT, ST>::Args a) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  using L = typename S::L;
+  using C = typename S::C;
+  const R s = a.scale;
+  double v[11] = {0};
+  double umax = 0;
+  const double eps = (double)a.heps;
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < a.N; c += gridDim.x * 256) {
+    double rho = 0, m[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < S::Q; ++i) {
+      const R w = (R)wgt<LAT>(i);
+      const double f = wgt<LAT>(i) + (double)C::dec(a.A[(size_t)i * a.N + c], w / s, s / w);
+      rho += f;
+      m[0] += L::cx(i) * f; m[1] += L::cy(i) * f; m[2] += L::cz(i) * f;
+    }
+    const int k = a.tag[c] & T_GAS;
+    double u[3];
+    for (int d = 0; d < 3; ++d) u[d] = m[d] / rho - 0.5 * (double)a.acc[k][d];
+    v[k] += rho;
+    const double h = heaviside_d((double)a.phi[c], eps);
+    const int x = c % a.nx, y = (c / a.nx) % a.ny, z = c / (a.nx * a.ny);
+    v[2] += h;
+    v[3] += h * (x + 0.5); v[4] += h * (y + 0.5); v[5] += h * (z + 0.5);
+    v[6] += h * u[0]; v[7] += h * u[1]; v[8] += h * u[2];
+    const double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    if (!(rho > 0.0) || !(un <= 0.3) || !isfinite(rho)) v[10] += 1.0;
+    if (un > umax) umax = un;
+  }
+  block_sum<11>(v, a.partial + 16 * blockIdx.x);
+  // max of |u|
+  __shared__ double sh[256];
+  sh[threadIdx.x] = umax;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w && sh[threadIdx.x + w] > sh[threadIdx.x]) sh[threadIdx.x] = sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.partial[16 * blockIdx.x + 9] = sh[0];
+}
+
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_export_interface(const typename Step<LAT, ST>::Args a, double* phi, double* nrm,
+                                                          double* kap, uint8_t* tags, int c0, int c1) {
+  using S = Step<LAT, ST>;
+  const size_t N = a.N;
+  for (int c = c0 + blockIdx.x * 256 + threadIdx.x; c < c1; c += gridDim.x * 256) {
+    const size_t o = (size_t)(c - c0);
+    if (phi) phi[o] = (double)a.phi[c];
+    if (nrm) for (int d = 0; d < S::D; ++d) nrm[(size_t)S::D * o + d] = (double)a.G[d * N + c];
+    if (kap) kap[o] = (double)a.G[3 * N + c];
+    if (tags) tags[o] = a.tag[c] & (T_GAS | T_ACT | T_SPEC);
+  }
+}
+
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_export_moments(const typename Step<LAT, ST>::Args a, double* out, int c0, int c1) {
+  const size_t N = a.N;
+  for (int c = c0 + blockIdx.x * 256 + threadIdx.x; c < c1; c += gridDim.x * 256)
+    for (int m = 0; m < 10; ++m) out[10 * (size_t)(c - c0) + m] = (double)a.M[m * N + c];
+}
+
+}  // namespace lsb

@@ -1,0 +1,63 @@
+// plan.h -- host-side plan: validated parameters, workspace layout and the
+// per-(velocity set, storage) launch table.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/lsb.h"
+
+struct lsb_plan;
+
+namespace lsb {
+
+// Cell-range launchers [c0, c1) write their outputs at offset c - c0, so
+// host-pointer calls can stage chunks through the workspace.
+struct Ops {
+  void (*init_phi)(lsb_plan*, const double* phi0, int c0, int c1, hipStream_t);
+  void (*init_band)(lsb_plan*, hipStream_t);
+  void (*init_pop)(lsb_plan*, const double* rho0, const double* u0, int c0, int c1, hipStream_t);
+  void (*step)(lsb_plan*, hipStream_t);
+  void (*fields)(lsb_plan*, double* rho, double* u, double* p, uint8_t* phase, int c0, int c1, hipStream_t);
+  void (*populations)(lsb_plan*, double* out, int i0, int i1, int c0, int c1, hipStream_t);
+  void (*interface)(lsb_plan*, double* phi, double* nrm, double* kap, uint8_t* tags, int c0, int c1, hipStream_t);
+  void (*moments)(lsb_plan*, double* out, int c0, int c1, hipStream_t);
+  void (*integrals_partial)(lsb_plan*, hipStream_t);
+  void (*rebuild)(lsb_plan*, hipStream_t);
+};
+
+const Ops* ops_d2q9(int storage);
+const Ops* ops_d3q19(int storage);
+const Ops* ops_d3q27(int storage);
+
+void set_error(const std::string& msg);
+
+}  // namespace lsb
+
+struct lsb_plan {
+  lsb_params P;
+  int D = 0, Q = 0;
+  int N = 0;
+  size_t bytes_pop = 0;  // bytes per stored population value
+  size_t bytes_real = 0; // bytes per level-set / moment value
+  int tdim[3] = {1, 1, 1};
+  int ntile[3] = {1, 1, 1};
+  int ntiles = 0;
+  int red_blocks = 512;  // fixed reduction grid (deterministic sums)
+  // workspace regions (byte offsets)
+  size_t off_A[2], off_phi, off_s1, off_s2, off_p0, off_tag, off_aux, off_M[2], off_G, off_ut[2];
+  size_t off_scal, off_cnt, off_tile_act, off_tile_list, off_cand_list, off_spec_list, off_flip_list, off_partial;
+  size_t total = 0;
+  char* ws = nullptr;
+  int cur = 0;           // index of the current population / moment buffer
+  bool bound = false;
+  bool inited = false;
+  long nstep = 0;
+  const lsb::Ops* ops = nullptr;
+  // grid sizes of list-driven kernels
+  int grid_tiles = 1024;
+  int grid_cells = 1024;
+};

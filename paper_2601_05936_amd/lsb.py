@@ -1,0 +1,231 @@
+"""Thin Python binding of liblsb.so (argument marshalling only).
+
+Every step of the method runs in the HIP kernels behind the C ABI of
+include/lsb.h; this module only converts parameters, hands over torch device
+memory (the caller-owned workspace) and stream handles, and wraps results.
+It fails loudly when the built library is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblsb.so")
+
+LSB_OK, LSB_EINVAL, LSB_ENOMEM, LSB_EDEVICE, LSB_ESTATE, LSB_EUNSTABLE = 0, -1, -2, -3, -4, -5
+D2Q9, D3Q19, D3Q27 = 0, 1, 2
+F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
+
+
+class LsbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lsb error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    """Mirror of lsb_params (include/lsb.h)."""
+    _fields_ = [
+        ("lattice", C.c_int), ("storage", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("bc", C.c_int * 6), ("wall_u", (C.c_double * 3) * 6),
+        ("rho_phys", C.c_double * 2), ("tau", C.c_double * 2), ("accel", (C.c_double * 3) * 2),
+        ("sigma", C.c_double), ("band", C.c_double), ("n_ext", C.c_int), ("ext_dtau", C.c_double),
+        ("reinit_every", C.c_int), ("n_reinit", C.c_int), ("reinit_dtau", C.c_double),
+        ("heaviside_eps", C.c_double), ("use_pb", C.c_int), ("pb0", C.c_double),
+        ("init_hydrostatic", C.c_int), ("fp16_scale_log2", C.c_int),
+    ]
+
+
+class Integrals(C.Structure):
+    _fields_ = [("mass", C.c_double * 2), ("volume_gas", C.c_double), ("centroid", C.c_double * 3),
+                ("vel_b", C.c_double * 3), ("pb", C.c_double), ("umax", C.c_double), ("step", C.c_long)]
+
+
+EXPORTS = [
+    "lsb_create", "lsb_destroy", "lsb_workspace_bytes", "lsb_bind", "lsb_init", "lsb_step", "lsb_get_fields",
+    "lsb_get_interface", "lsb_get_populations", "lsb_get_moments", "lsb_get_integrals", "lsb_state_bytes",
+    "lsb_save_state", "lsb_load_state", "lsb_step_count", "lsb_get_counts", "lsb_last_error",
+]
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load the built library (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(or python paper_2601_05936_amd/build.py)")
+    lib = C.CDLL(LIB_PATH)
+    vp, dp, sz = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_size_t)
+    P = C.POINTER(Params)
+    lib.lsb_create.argtypes = [P, C.POINTER(vp)]
+    lib.lsb_destroy.argtypes = [vp]
+    lib.lsb_destroy.restype = None
+    lib.lsb_workspace_bytes.argtypes = [vp, sz]
+    lib.lsb_bind.argtypes = [vp, vp, C.c_size_t]
+    lib.lsb_init.argtypes = [vp, vp, vp, vp, C.c_int, vp]
+    lib.lsb_step.argtypes = [vp, C.c_int, C.c_int, vp]
+    lib.lsb_get_fields.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp]
+    lib.lsb_get_interface.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp]
+    lib.lsb_get_populations.argtypes = [vp, vp, C.c_int, vp]
+    lib.lsb_get_moments.argtypes = [vp, vp, C.c_int, vp]
+    lib.lsb_get_integrals.argtypes = [vp, C.POINTER(Integrals), vp]
+    lib.lsb_state_bytes.argtypes = [vp, sz]
+    lib.lsb_save_state.argtypes = [vp, vp, vp]
+    lib.lsb_load_state.argtypes = [vp, vp, vp]
+    lib.lsb_step_count.argtypes = [vp]
+    lib.lsb_step_count.restype = C.c_long
+    lib.lsb_get_counts.argtypes = [vp, C.POINTER(C.c_int), vp]
+    lib.lsb_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def to_params(p: dict) -> Params:
+    s = Params()
+    for k, _ in Params._fields_:
+        v = p[k]
+        if k == "bc":
+            for i in range(6):
+                s.bc[i] = int(v[i])
+        elif k == "wall_u":
+            for i in range(6):
+                for a in range(3):
+                    s.wall_u[i][a] = float(v[i][a])
+        elif k in ("rho_phys", "tau"):
+            for i in range(2):
+                getattr(s, k)[i] = float(v[i])
+        elif k == "accel":
+            for i in range(2):
+                for a in range(3):
+                    s.accel[i][a] = float(v[i][a])
+        else:
+            setattr(s, k, v)
+    return s
+
+
+def _check(rc: int):
+    if rc != LSB_OK:
+        raise LsbError(rc, load().lsb_last_error().decode())
+
+
+class Sim:
+    """One simulation on one GPU.  Device memory is a torch uint8 tensor
+    (the caller-owned workspace); calls run on torch's current stream."""
+
+    def __init__(self, params: dict, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.p = dict(params)
+        self.device = torch.device(device)
+        self._cp = to_params(self.p)
+        h = C.c_void_p()
+        _check(self.lib.lsb_create(C.byref(self._cp), C.byref(h)))
+        self.h = h
+        nb = C.c_size_t()
+        _check(self.lib.lsb_workspace_bytes(self.h, C.byref(nb)))
+        self.workspace_bytes = nb.value
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        _check(self.lib.lsb_bind(self.h, C.c_void_p(self.ws.data_ptr()), nb.value))
+        self.N = self.p["nx"] * self.p["ny"] * self.p["nz"]
+        self.D = 2 if self.p["lattice"] == D2Q9 else 3
+        self.Q = {D2Q9: 9, D3Q19: 19, D3Q27: 27}[self.p["lattice"]]
+        self.shape = (self.p["nz"], self.p["ny"], self.p["nx"])
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.lsb_destroy(self.h)
+            self.h = None
+
+    def stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _dev(self, a, n):
+        if a is None:
+            return None
+        t = self.torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)) if isinstance(a, np.ndarray) \
+            else a.reshape(-1).to(self.torch.float64)
+        assert t.numel() == n, (t.numel(), n)
+        return t.to(self.device).contiguous()
+
+    def init(self, phi0, rho0=None, u0=None):
+        """phi0 [N] signed distance; rho0 [N] or None; u0 [N,3] or None (numpy or torch)."""
+        t_phi = self._dev(phi0, self.N)
+        t_rho = self._dev(rho0, self.N)
+        t_u = self._dev(u0, 3 * self.N)
+        ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+        _check(self.lib.lsb_init(self.h, ptr(t_phi), ptr(t_rho), ptr(t_u), 1, self.stream()))
+        return self
+
+    def step(self, n: int = 1, check_every: int = 0):
+        _check(self.lib.lsb_step(self.h, int(n), int(check_every), self.stream()))
+
+    @property
+    def nstep(self) -> int:
+        return self.lib.lsb_step_count(self.h)
+
+    def _out(self, n, dtype):
+        return self.torch.empty(n, dtype=dtype, device=self.device)
+
+    def fields(self, as_numpy=True):
+        t = self.torch
+        rho, u, p = self._out(self.N, t.float64), self._out(self.N * self.D, t.float64), self._out(self.N, t.float64)
+        ph = self._out(self.N, t.uint8)
+        _check(self.lib.lsb_get_fields(self.h, C.c_void_p(rho.data_ptr()), C.c_void_p(u.data_ptr()),
+                                       C.c_void_p(p.data_ptr()), C.c_void_p(ph.data_ptr()), 1, self.stream()))
+        out = dict(rho=rho.view(self.shape), u=u.view(self.shape + (self.D,)), p=p.view(self.shape),
+                   phase=ph.view(self.shape))
+        return {k: v.cpu().numpy() for k, v in out.items()} if as_numpy else out
+
+    def interface(self, as_numpy=True):
+        t = self.torch
+        phi, n, k = self._out(self.N, t.float64), self._out(self.N * self.D, t.float64), self._out(self.N, t.float64)
+        tags = self._out(self.N, t.uint8)
+        _check(self.lib.lsb_get_interface(self.h, C.c_void_p(phi.data_ptr()), C.c_void_p(n.data_ptr()),
+                                          C.c_void_p(k.data_ptr()), C.c_void_p(tags.data_ptr()), 1, self.stream()))
+        out = dict(phi=phi.view(self.shape), normal=n.view(self.shape + (self.D,)), kappa=k.view(self.shape),
+                   tags=tags.view(self.shape))
+        return {kk: v.cpu().numpy() for kk, v in out.items()} if as_numpy else out
+
+    def populations(self, as_numpy=True):
+        out = self._out(self.Q * self.N, self.torch.float64)
+        _check(self.lib.lsb_get_populations(self.h, C.c_void_p(out.data_ptr()), 1, self.stream()))
+        out = out.view((self.Q,) + self.shape)
+        return out.cpu().numpy() if as_numpy else out
+
+    def moments(self, as_numpy=True):
+        out = self._out(10 * self.N, self.torch.float64)
+        _check(self.lib.lsb_get_moments(self.h, C.c_void_p(out.data_ptr()), 1, self.stream()))
+        out = out.view(self.shape + (10,))
+        return out.cpu().numpy() if as_numpy else out
+
+    def integrals(self) -> dict:
+        I = Integrals()
+        _check(self.lib.lsb_get_integrals(self.h, C.byref(I), self.stream()))
+        return dict(mass=np.array(I.mass[:]), volume_gas=I.volume_gas, centroid=np.array(I.centroid[:]),
+                    vel_b=np.array(I.vel_b[:]), pb=I.pb, umax=I.umax, step=I.step)
+
+    def counts(self) -> dict:
+        c = (C.c_int * 3)()
+        _check(self.lib.lsb_get_counts(self.h, c, self.stream()))
+        return dict(iface_cells=c[0], active_tiles=c[1], refilled=c[2])
+
+    def state_bytes(self) -> int:
+        nb = C.c_size_t()
+        _check(self.lib.lsb_state_bytes(self.h, C.byref(nb)))
+        return nb.value
+
+    def save_state(self):
+        buf = self.torch.empty(self.state_bytes(), dtype=self.torch.uint8, device=self.device)
+        _check(self.lib.lsb_save_state(self.h, C.c_void_p(buf.data_ptr()), self.stream()))
+        return buf
+
+    def load_state(self, buf):
+        _check(self.lib.lsb_load_state(self.h, C.c_void_p(buf.data_ptr()), self.stream()))

@@ -1,0 +1,78 @@
+"""The C-ABI library loads and exports every entry point include/lsb.h
+declares; parameter validation and the workspace layout need no GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2601_05936_amd import lsb, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lsb.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(lsb_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lsb.load()
+    syms = declared_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(lsb.EXPORTS)
+
+
+def test_params_struct_matches_header_field_order():
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct lsb_params"):text.index("} lsb_params;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"\b([a-z_0-9]+)(?:\[[0-9]+\])*\s*[;,]", body)
+    assert [n for n in names if n != "int"] == [f for f, _ in lsb.Params._fields_]
+
+
+def _create(p):
+    lib = lsb.load()
+    h = C.c_void_p()
+    rc = lib.lsb_create(C.byref(lsb.to_params(p)), C.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("bad", [
+    dict(lattice=7), dict(storage=9), dict(nz=3),  # D2Q9 with nz != 1
+    dict(tau=[0.5, 0.8]), dict(band=1.0), dict(bc=[0, 1, 0, 0, 0, 0]), dict(nx=2),
+])
+def test_create_rejects_invalid_parameters(bad):
+    p = W.default_params(lattice=W.D2Q9, nx=16, ny=16, nz=1,
+                         bc=[W.PERIODIC] * 6)
+    p.update(bad)
+    rc, h = _create(p)
+    assert rc == lsb.LSB_EINVAL
+    assert lsb.load().lsb_last_error().decode()
+
+
+@pytest.mark.parametrize("lat,storage,shape,pop_bytes", [
+    (W.D2Q9, W.F64, (64, 32, 1), 8), (W.D3Q19, W.F32, (20, 18, 22), 4), (W.D3Q27, W.F16DEV, (16, 16, 16), 2),
+])
+def test_workspace_layout_and_state_image(lat, storage, shape, pop_bytes):
+    nx, ny, nz = shape
+    p = W.default_params(lattice=lat, storage=storage, nx=nx, ny=ny, nz=nz)
+    rc, h = _create(p)
+    assert rc == 0
+    lib = lsb.load()
+    nb = C.c_size_t()
+    assert lib.lsb_workspace_bytes(h, C.byref(nb)) == 0
+    N = nx * ny * nz
+    Q = {W.D2Q9: 9, W.D3Q19: 19, W.D3Q27: 27}[lat]
+    assert nb.value >= 2 * Q * N * pop_bytes
+    sb = C.c_size_t()
+    assert lib.lsb_state_bytes(h, C.byref(sb)) == 0
+    assert sb.value >= Q * N * pop_bytes
+    # binding a too small buffer is refused before any device access
+    assert lib.lsb_bind(h, C.c_void_p(256), 16) == lsb.LSB_ENOMEM
+    # stepping before init is a state error
+    assert lib.lsb_step(h, 1, 0, None) == lsb.LSB_ESTATE
+    lib.lsb_destroy(h)
