@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the coupled level-set lattice Boltzmann step on
+one MI355X.
+
+Workload: D3Q27 512^3 stratified liquid/gas layer with the wavy interface
+z = 256 + 8 sin(2 pi x/512) cos(2 pi y/512), periodic x/y, no-slip z,
+density ratio 1000, viscosity ratio 50, sigma 1e-3 (synthetic, built from
+the problem statement; no dataset).  One "step" is the whole hot path:
+collide-stream with wall and interface bounce-back, velocity extension,
+RK3 advection, reinitialisation every 10 steps, classification, geometry,
+refill.  Each storage mode (FP16-deviation, FP32, FP64) runs W untimed
+warm-up steps and K timed steps bracketed by device synchronisation.
+
+Prints one JSON line: the headline value is whole-step MLUPS of the
+FP16-deviation storage path (FP32 arithmetic); the FP32/FP64 paths are in
+"modes".  "roofline" refers to the dominant kernel (the bulk
+collide-stream kernel) timed with HIP events on its own stream.
+"cpu_baseline" times the CPU oracle on a bounded sample of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_mode(size, storage, steps, warmup):
+    import torch
+
+    from paper_2601_05936_amd import workloads as W
+    from paper_2601_05936_amd.lsb import Sim
+
+    w = W.wavy_stratified_3d(n=size, storage=storage)
+    p = w["params"]
+    t0 = time.time()
+    phi0 = torch.from_numpy(W.wavy_phi(p, 8.0 * size / 512.0)).to("cuda:0")
+    s = Sim(p).init(phi0)
+    del phi0
+    torch.cuda.synchronize()
+    log(f"[{storage}] init {time.time() - t0:.1f}s workspace {s.workspace_bytes / 2**30:.1f} GiB")
+    s.step(warmup)
+    torch.cuda.synchronize()
+    s.set_kernel_timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    s.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    k_ms, k_n = s.kernel_timing()
+    s.set_kernel_timing(False)
+    counts = s.counts()
+    I = s.integrals()
+    N = s.N
+    Q = s.Q
+    b = {0: 8, 1: 4, 2: 2, 3: 2}[storage]
+    k_avg_ms = k_ms / max(k_n, 1)
+    bulk_cells = N - counts["iface_cells"]
+    # algorithmic bytes of one bulk launch: read Q and write Q populations of
+    # every bulk cell, read one tag byte per cell
+    alg_bytes = bulk_cells * 2 * Q * b + N
+    achieved = alg_bytes / (k_avg_ms * 1e-3) / 1e9
+    res = dict(
+        mlups=N * steps / (ms * 1e-3) / 1e6,
+        ms_per_step=ms / steps,
+        k1_ms=k_avg_ms,
+        k1_mlups=N / (k_avg_ms * 1e-3) / 1e6,
+        k1_gbs=achieved,
+        k1_frac=achieved / HBM_PEAK_GBS,
+        k1_launches=k_n,
+        alg_bytes_per_launch=alg_bytes,
+        bytes_per_cell=2 * Q * b + 1,
+        iface_cells=counts["iface_cells"],
+        active_tiles=counts["active_tiles"],
+        mass=[float(m) for m in I["mass"]],
+        umax=float(I["umax"]),
+    )
+    log(f"[{storage}] {res}")
+    del s
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(seconds: float):
+    """The CPU oracle (as it stands) on a bounded sample of the workload:
+    the same problem at 128^3 (interface amplitude scaled to 2)."""
+    import oracle as O
+    from paper_2601_05936_amd import workloads as W
+
+    n = 128
+    w = W.wavy_stratified_3d(n=n, storage=W.F64)
+    p = w["params"]
+    phi = W.wavy_phi(p, 8.0 * n / 512.0)
+    threads = os.environ.get("OMP_NUM_THREADS")
+    o = O.Oracle(p, phi)
+    t0 = time.time()
+    o.step(1)
+    t1 = time.time() - t0
+    extra = max(0, int(seconds / max(t1, 1e-3)) - 1)
+    t0 = time.time()
+    if extra:
+        o.step(extra)
+    t = time.time() - t0
+    steps = extra if extra else 1
+    if not extra:
+        t = t1
+    return dict(value=n ** 3 * steps / t / 1e6, unit="MLUPS", cores=int(threads) if threads else os.cpu_count(),
+                kind="oracle", sample=f"D3Q27 wavy stratified 128^3 (amplitude 2), {steps} FP64 steps after 1 warm-up step")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--modes", default="f16dev,f32,f64")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=float, default=0.0,
+                    help="also run a plain device copy of this many GiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    from paper_2601_05936_amd.workloads import F16DEV, F32, F64
+    names = {"f16dev": F16DEV, "f32": F32, "f64": F64}
+    modes = [m.strip() for m in args.modes.split(",") if m.strip()]
+    results = {}
+    for m in modes:
+        results[m] = run_mode(args.size, names[m], args.steps, args.warmup)
+    if args.copy_calibration > 0:
+        nbytes = int(args.copy_calibration * 2**30)
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nbytes} bytes read and written")
+        del a, b
+    head = modes[0]
+    r = results[head]
+    out = {
+        "metric": "MLUPS + HBM GB/s (% peak), FP16-storage vs FP32 vs FP64 on 1 GPU; adjoint MLUPS",
+        "value": r["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if head == "f64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"D3Q27 wavy stratified {args.size}^3, periodic x/y, no-slip z, density ratio 1000, "
+                               f"viscosity ratio 50, sigma 1e-3 (throughput configuration)",
+                   "storage": head, "cells": args.size ** 3},
+        "modes": results,
+        "roofline": {"bound": "hbm", "achieved": r["k1_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": r["k1_frac"], "traffic": None,
+                     "kernel": "k_lb_bulk (collide-stream, bulk cells)",
+                     "bytes_per_cell": r["bytes_per_cell"], "alg_bytes_per_launch": r["alg_bytes_per_launch"],
+                     "avg_ms": r["k1_ms"]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -157,6 +157,14 @@ long lsb_step_count(const lsb_plan* plan);
  * active tiles, counts[2] cells refilled in the last step. */
 int lsb_get_counts(lsb_plan* plan, int* counts, void* stream);
 
+/* Kernel timing: while enabled, every step records a pair of HIP events on
+ * its stream around the bulk collide-stream kernel (the dominant kernel;
+ * one launch per step).  Enabling clears the accumulator.
+ * lsb_get_kernel_timing waits for the recorded events and returns the summed
+ * kernel duration in milliseconds and the number of launches timed. */
+int lsb_set_kernel_timing(lsb_plan* plan, int enable);
+int lsb_get_kernel_timing(lsb_plan* plan, double* total_ms, long* launches);
+
 const char* lsb_last_error(void);
 
 #ifdef __cplusplus

@@ -316,14 +316,15 @@ struct Sim {
     // zero because the velocity is continuous.
     const double eta_bar = 0.5 * (eta[0] + eta[1]);
     const double jeta = eta[1] - eta[0];
-    // The pressure part of the normal jump acts as an explicit feedback: one
-    // step changes an interface cell's pressure by about
-    // rho cs^2 q(1-q) sum_i 6 w_i (c_i.n)^2 E <= rho cs^2 E / 4, which
-    // overshoots when eta_bar < rho / 48 (every workload with tau near 1/2).
-    // Reading: the divisor of this part is floored at rho_max cs^2 / 8, which
-    // bounds the one-step gain of a flat interface by one (deadbeat) and is
-    // inactive whenever the explicit feedback is already stable.
-    const double eta_p = std::max(eta_bar, std::max(P.rho_phys[0], P.rho_phys[1]) * CS2 / 8.0);
+    // The pressure part of the normal jump acts as an explicit feedback with
+    // a one-step lag (E uses the moments of the previous collision): one step
+    // changes an interface cell's pressure by k Delta with
+    // k = rho cs^2 q(1-q) sum_i 6 w_i (c_i.n)^2 / (2 eta) <= rho / (24 eta),
+    // and the lagged iteration x' = x - k x_prev has roots of modulus sqrt(k),
+    // so it diverges for k > 1 (eta_bar < rho / 24: every workload with tau
+    // near 1/2).  Reading: the divisor of this part is floored at
+    // rho_max cs^2 / 4, which bounds k by 1/2 (roots of modulus 0.71).
+    const double eta_p = std::max(eta_bar, std::max(P.rho_phys[0], P.rho_phys[1]) * CS2 / 4.0);
     T E = ((p_g - p_l) + sig * kG) / (2.0 * eta_p);
     T Sb[6];
     for (int m = 0; m < 6; ++m) Sb[m] = 0.5 * (MS[6 * c + m] + MS[6 * s + m]);
@@ -821,7 +822,13 @@ struct Sim {
           w0 = 1.0 / (1.0 + q);
           w1 = q / (1.0 + q);
         }
-        T rr = w0 * rhoG + w1 * Mr1[x1] + (two ? w2 * Mr1[x2] : T(0.0));
+        // Converting the old phase's pressure into the density of a lighter
+        // new phase multiplies the old phase's pressure fluctuations by
+        // rho_old / rho_new in LB density (1000 for liquid -> gas); reading:
+        // into the lighter phase the boundary density is that of the nearest
+        // established cell of the new phase.
+        T rhoB = (P.rho_phys[knew] >= P.rho_phys[kold]) ? rhoG : Mr1[x1];
+        T rr = w0 * rhoB + w1 * Mr1[x1] + (two ? w2 * Mr1[x2] : T(0.0));
         T ur[3];
         for (int a = 0; a < 3; ++a)
           ur[a] = w0 * uG[a] + w1 * Mu1[3 * x1 + a] + (two ? w2 * Mu1[3 * x2 + a] : T(0.0));

@@ -44,6 +44,33 @@ int check_launch() {
 
 namespace lsb {
 void set_error(const std::string& msg) { g_err = msg; }
+
+static const int kEventPairs = 512;
+
+static void timing_flush(lsb_plan* p) {
+  if (p->ev_used == 0) return;
+  (void)hipEventSynchronize(p->ev[2 * (p->ev_used - 1) + 1]);
+  for (int k = 0; k < p->ev_used; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p->ev[2 * k], p->ev[2 * k + 1]) == hipSuccess) {
+      p->timing_ms += ms;
+      ++p->timing_launches;
+    }
+  }
+  p->ev_used = 0;
+}
+
+void timing_begin(lsb_plan* p, hipStream_t st) {
+  if (!p->timing) return;
+  if (p->ev_used == kEventPairs) timing_flush(p);
+  (void)hipEventRecord(p->ev[2 * p->ev_used], st);
+}
+
+void timing_end(lsb_plan* p, hipStream_t st) {
+  if (!p->timing) return;
+  (void)hipEventRecord(p->ev[2 * p->ev_used + 1], st);
+  ++p->ev_used;
+}
 }  // namespace lsb
 
 extern "C" {
@@ -128,7 +155,11 @@ int lsb_create(const lsb_params* P, lsb_plan** out) {
   return LSB_OK;
 }
 
-void lsb_destroy(lsb_plan* p) { delete p; }
+void lsb_destroy(lsb_plan* p) {
+  if (!p) return;
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  delete p;
+}
 
 int lsb_workspace_bytes(const lsb_plan* p, size_t* bytes) {
   if (!p || !bytes) return fail(LSB_EINVAL, "null argument");
@@ -418,6 +449,30 @@ int lsb_load_state(lsb_plan* p, const void* src, void* stream) {
 }
 
 long lsb_step_count(const lsb_plan* p) { return p ? p->nstep : -1; }
+
+int lsb_set_kernel_timing(lsb_plan* p, int enable) {
+  if (!p) return fail(LSB_EINVAL, "null plan");
+  if (enable && p->ev.empty()) {
+    p->ev.resize(2 * lsb::kEventPairs);
+    for (auto& e : p->ev) LSB_HIP(hipEventCreate(&e));
+  }
+  if (p->timing) lsb::timing_flush(p);
+  p->timing = enable != 0;
+  p->ev_used = 0;
+  if (enable) {
+    p->timing_ms = 0.0;
+    p->timing_launches = 0;
+  }
+  return LSB_OK;
+}
+
+int lsb_get_kernel_timing(lsb_plan* p, double* total_ms, long* launches) {
+  if (!p || !total_ms || !launches) return fail(LSB_EINVAL, "null argument");
+  lsb::timing_flush(p);
+  *total_ms = p->timing_ms;
+  *launches = p->timing_launches;
+  return LSB_OK;
+}
 
 int lsb_get_counts(lsb_plan* p, int* counts, void* stream) {
   if (!p || !counts) return fail(LSB_EINVAL, "null argument");

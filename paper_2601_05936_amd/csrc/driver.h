@@ -115,7 +115,9 @@ struct Driver {
     const int xchunks = (P.nx + 255) / 256;
     const int rows = P.ny * P.nz;
     // a2-a4: collide and stream
+    timing_begin(p, st);
     k_lb_bulk<LAT, ST><<<xchunks * rows, 256, 0, st>>>(a, xchunks);
+    timing_end(p, st);
     k_lb_iface<LAT, ST><<<p->grid_cells, 256, 0, st>>>(a);
     // a6: extension (ut ping-pong), advection
     k_ext_seed<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);

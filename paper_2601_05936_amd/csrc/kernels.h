@@ -223,10 +223,10 @@ __device__ __noinline__ typename Step<LAT, ST>::R iface_pull(const typename Step
   const R p_g = (k == 0) ? p_oth : p_own;
   const R eta_bar = (R)0.5 * (a.eta[0] + a.eta[1]);
   const R jeta = a.eta[1] - a.eta[0];
-  // pressure part of the normal jump: divisor floored at rho_max cs^2 / 8 so
-  // that the explicit pressure feedback cannot overshoot
+  // pressure part of the normal jump: divisor floored at rho_max cs^2 / 4 so
+  // that the lagged explicit pressure feedback has gain k <= 1/2
   const R rmax = a.rho_phys[0] > a.rho_phys[1] ? a.rho_phys[0] : a.rho_phys[1];
-  const R eta_p = eta_bar > rmax / (R)24 ? eta_bar : rmax / (R)24;
+  const R eta_p = eta_bar > rmax / (R)12 ? eta_bar : rmax / (R)12;
   const R E = ((p_g - p_l) + a.sigma * kG) / ((R)2 * eta_p);
   R Sb[6];
   for (int m = 0; m < 6; ++m) Sb[m] = (R)0.5 * (a.M[(4 + m) * N + c] + a.M[(4 + m) * N + sc]);
@@ -817,7 +817,9 @@ __global__ __launch_bounds__(256) void k_refill(const typename Step<LAT, ST>::Ar
         w0 = (R)1 / ((R)1 + q);
         w1 = q / ((R)1 + q);
       }
-      const R rr = w0 * rhoG + w1 * a.Mn[c1] + (two ? w2 * a.Mn[c2c] : (R)0);
+      // into a lighter phase the boundary density is the nearest new-phase cell's
+      const R rhoB = a.rho_phys[knew] >= a.rho_phys[kold] ? rhoG : a.Mn[c1];
+      const R rr = w0 * rhoB + w1 * a.Mn[c1] + (two ? w2 * a.Mn[c2c] : (R)0);
       R ur[3];
       const R uGv[3] = {uG0, uG1, uG2};
       for (int m = 0; m < 3; ++m)

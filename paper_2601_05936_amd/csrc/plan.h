@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/lsb.h"
 
@@ -34,6 +35,9 @@ const Ops* ops_d3q19(int storage);
 const Ops* ops_d3q27(int storage);
 
 void set_error(const std::string& msg);
+// events around the dominant kernel (no-ops unless timing is enabled)
+void timing_begin(lsb_plan* p, hipStream_t st);
+void timing_end(lsb_plan* p, hipStream_t st);
 
 }  // namespace lsb
 
@@ -57,6 +61,12 @@ struct lsb_plan {
   bool inited = false;
   long nstep = 0;
   const lsb::Ops* ops = nullptr;
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;  // start/stop pairs
+  int ev_used = 0;
+  double timing_ms = 0.0;
+  long timing_launches = 0;
   // grid sizes of list-driven kernels
   int grid_tiles = 1024;
   int grid_cells = 1024;

@@ -47,7 +47,8 @@ class Integrals(C.Structure):
 EXPORTS = [
     "lsb_create", "lsb_destroy", "lsb_workspace_bytes", "lsb_bind", "lsb_init", "lsb_step", "lsb_get_fields",
     "lsb_get_interface", "lsb_get_populations", "lsb_get_moments", "lsb_get_integrals", "lsb_state_bytes",
-    "lsb_save_state", "lsb_load_state", "lsb_step_count", "lsb_get_counts", "lsb_last_error",
+    "lsb_save_state", "lsb_load_state", "lsb_step_count", "lsb_get_counts", "lsb_set_kernel_timing",
+    "lsb_get_kernel_timing", "lsb_last_error",
 ]
 
 _lib = None
@@ -82,6 +83,8 @@ def load() -> C.CDLL:
     lib.lsb_step_count.argtypes = [vp]
     lib.lsb_step_count.restype = C.c_long
     lib.lsb_get_counts.argtypes = [vp, C.POINTER(C.c_int), vp]
+    lib.lsb_set_kernel_timing.argtypes = [vp, C.c_int]
+    lib.lsb_get_kernel_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_long)]
     lib.lsb_last_error.restype = C.c_char_p
     _lib = lib
     return lib
@@ -216,6 +219,15 @@ class Sim:
         c = (C.c_int * 3)()
         _check(self.lib.lsb_get_counts(self.h, c, self.stream()))
         return dict(iface_cells=c[0], active_tiles=c[1], refilled=c[2])
+
+    def set_kernel_timing(self, enable: bool = True):
+        _check(self.lib.lsb_set_kernel_timing(self.h, 1 if enable else 0))
+
+    def kernel_timing(self):
+        """(total ms, launches) of the bulk collide-stream kernel since enabling."""
+        ms, n = C.c_double(), C.c_long()
+        _check(self.lib.lsb_get_kernel_timing(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def state_bytes(self) -> int:
         nb = C.c_size_t()
