@@ -110,6 +110,11 @@ int lsb_create(const lsb_params* P, lsb_plan** out) {
   p->bytes_real = P->storage == LSB_F64 ? 8 : 4;
   if (p->D == 2) { p->tdim[0] = 16; p->tdim[1] = 16; p->tdim[2] = 1; }
   else { p->tdim[0] = 8; p->tdim[1] = 8; p->tdim[2] = 8; }
+  // the classification kernel stages a tile plus a one-cell halo in 1024 LDS slots
+  if ((p->tdim[0] + 2) * (p->tdim[1] + 2) * (p->tdim[2] + (p->D == 3 ? 2 : 0)) > 1024) {
+    delete p;
+    return fail(LSB_EINVAL, "internal: tile too large for the classification kernel");
+  }
   const int n[3] = {P->nx, P->ny, P->nz};
   p->ntiles = 1;
   for (int a = 0; a < 3; ++a) {

@@ -89,6 +89,45 @@ __host__ __device__ constexpr int dir_of(int x, int y, int z) {
   return j;
 }
 
+// Lattice tables for runtime direction indices (constant memory).
+template <int LAT>
+struct Tables {
+  int cx[27], cy[27], cz[27], opp[27];
+  float wf[27], wif[27];
+  double wd[27], wid[27];
+};
+
+template <int LAT>
+__host__ __device__ constexpr Tables<LAT> make_tables() {
+  Tables<LAT> t{};
+  for (int i = 0; i < Lat<LAT>::Q; ++i) {
+    t.cx[i] = Lat<LAT>::cx(i);
+    t.cy[i] = Lat<LAT>::cy(i);
+    t.cz[i] = Lat<LAT>::cz(i);
+    t.opp[i] = opp<LAT>(i);
+    t.wd[i] = wgt<LAT>(i);
+    t.wf[i] = (float)wgt<LAT>(i);
+    t.wid[i] = 1.0 / wgt<LAT>(i);
+    t.wif[i] = (float)(1.0 / wgt<LAT>(i));
+  }
+  return t;
+}
+
+template <int LAT>
+__constant__ Tables<LAT> tab = make_tables<LAT>();
+
+template <int LAT, class R>
+__device__ __forceinline__ R tw(int i) {
+  if constexpr (sizeof(R) == 8) return tab<LAT>.wd[i];
+  else return tab<LAT>.wf[i];
+}
+
+template <int LAT, class R>
+__device__ __forceinline__ R twinv(int i) {
+  if constexpr (sizeof(R) == 8) return tab<LAT>.wid[i];
+  else return tab<LAT>.wif[i];
+}
+
 // ---------------------------------------------------------------------------
 // Storage codecs.  Populations are kept as deviations d_i = f_i - w_i from
 // the rest state; the FP16/BF16 paths store s d_i / w_i.
@@ -96,6 +135,7 @@ __host__ __device__ constexpr int dir_of(int x, int y, int z) {
 template <int ST>
 struct Codec;
 
+// dec(v, w, 1/s) -> deviation; enc(d, 1/w, s) -> stored value (multiplies only).
 template <>
 struct Codec<LSB_F64> {
   using T = double;
@@ -116,20 +156,17 @@ template <>
 struct Codec<LSB_F16DEV> {
   using T = uint16_t;
   using R = float;
-  // w_over_s = w / s, s_over_w = s / w
-  __device__ static R dec(T v, R w_over_s, R) { return __half2float(__ushort_as_half(v)) * w_over_s; }
-  __device__ static T enc(R d, R, R s_over_w) { return __half_as_ushort(__float2half_rn(d * s_over_w)); }
+  __device__ static R dec(T v, R w, R inv_s) { return __half2float(__ushort_as_half(v)) * (w * inv_s); }
+  __device__ static T enc(R d, R inv_w, R s) { return __half_as_ushort(__float2half_rn(d * (s * inv_w))); }
 };
 
 template <>
 struct Codec<LSB_BF16DEV> {
   using T = uint16_t;
   using R = float;
-  __device__ static R dec(T v, R w_over_s, R) {
-    return __uint_as_float(((unsigned)v) << 16) * w_over_s;
-  }
-  __device__ static T enc(R d, R, R s_over_w) {
-    __hip_bfloat16 b = __float2bfloat16(d * s_over_w);  // round to nearest even
+  __device__ static R dec(T v, R w, R inv_s) { return __uint_as_float(((unsigned)v) << 16) * (w * inv_s); }
+  __device__ static T enc(R d, R inv_w, R s) {
+    __hip_bfloat16 b = __float2bfloat16(d * (s * inv_w));  // round to nearest even
     return *reinterpret_cast<uint16_t*>(&b);
   }
 };
@@ -152,6 +189,7 @@ struct KArgs {
   R ext_dtau, reinit_dtau;
   R heps;
   R scale;            // storage scale s
+  R inv_scale;        // 1 / s
   int use_pb;
   // tiles
   int tdim[3];        // tile extents

@@ -37,6 +37,7 @@ struct Driver {
     a.reinit_dtau = (R)P.reinit_dtau;
     a.heps = (R)P.heaviside_eps;
     a.scale = ST == LSB_F16DEV ? (R)ldexp(1.0, P.fp16_scale_log2) : (R)1;
+    a.inv_scale = ST == LSB_F16DEV ? (R)ldexp(1.0, -P.fp16_scale_log2) : (R)1;
     a.use_pb = P.use_pb;
     for (int ax = 0; ax < 3; ++ax) { a.tdim[ax] = p->tdim[ax]; a.ntile[ax] = p->ntile[ax]; }
     a.ntiles = p->ntiles;

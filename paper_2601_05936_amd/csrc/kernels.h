@@ -32,13 +32,16 @@ struct Step {
 // ---------------------------------------------------------------------------
 // a2: moments, BGK collision with body force, store; moments to M on active
 // cells.  d[] holds the incoming deviations f_i - w_i after streaming and
-// bounce-back.
+// bounce-back.  Opposite directions (i, opp(i)) share the even part of the
+// equilibrium, w (rho - 1 + rho (9/2 (c.u)^2 - 3/2 u.u)), and flip the sign of
+// the odd parts (3 w rho c.u and the force 3 w rho c.a).
 // ---------------------------------------------------------------------------
 template <int LAT, int ST>
 __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args& a, int c, int k, bool active,
                                               typename Step<LAT, ST>::R* d) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
+  using T = typename S::T;
   using L = typename S::L;
   using C = typename S::C;
   constexpr int Q = S::Q;
@@ -46,38 +49,65 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     rp += d[i];
-    if (L::cx(i)) m0 += (R)L::cx(i) * d[i];
-    if (L::cy(i)) m1 += (R)L::cy(i) * d[i];
-    if (L::cz(i)) m2 += (R)L::cz(i) * d[i];
+    if (L::cx(i) > 0) m0 += d[i]; else if (L::cx(i) < 0) m0 -= d[i];
+    if (L::cy(i) > 0) m1 += d[i]; else if (L::cy(i) < 0) m1 -= d[i];
+    if (L::cz(i) > 0) m2 += d[i]; else if (L::cz(i) < 0) m2 -= d[i];
   }
   const R rho = (R)1 + rp;
   const R inv = (R)1 / rho;
   const R ux = m0 * inv, uy = m1 * inv, uz = m2 * inv;
-  const R uu = ux * ux + uy * uy + uz * uz;
+  const R uu15 = (R)1.5 * (ux * ux + uy * uy + uz * uz);
   const R om = a.omega[k];
-  const R fx = (R)3 * a.acc[k][0], fy = (R)3 * a.acc[k][1], fz = (R)3 * a.acc[k][2];
-  R P0 = 0, P1 = 0, P2 = 0, P3 = 0, P4 = 0, P5 = 0;
+  const R omc = (R)1 - om;
+  const R fx = (R)3 * a.acc[k][0] * rho, fy = (R)3 * a.acc[k][1] * rho, fz = (R)3 * a.acc[k][2] * rho;
+  const R ux3 = (R)3 * rho * ux, uy3 = (R)3 * rho * uy, uz3 = (R)3 * rho * uz;
   const R s = a.scale;
+  const size_t N = a.N;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
+    const int j = opp<LAT>(i);
+    if (j < i) continue;
     const R w = (R)wgt<LAT>(i);
-    const R cu = (R)L::cx(i) * ux + (R)L::cy(i) * uy + (R)L::cz(i) * uz;
-    const R deq = w * (rp + rho * ((R)3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu));
-    const R fn = d[i] - deq;
-    if (active) {
-      if (L::cx(i)) P0 += fn;
-      if (L::cy(i)) P1 += fn;
-      if (L::cz(i)) P2 += fn;
-      if (L::cx(i) * L::cy(i)) P3 += (R)(L::cx(i) * L::cy(i)) * fn;
-      if (L::cx(i) * L::cz(i)) P4 += (R)(L::cx(i) * L::cz(i)) * fn;
-      if (L::cy(i) * L::cz(i)) P5 += (R)(L::cy(i) * L::cz(i)) * fn;
+    const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
+    R cu = 0, cu3 = 0, ca = 0;
+    if (cx) { cu += (R)cx * ux; cu3 += (R)cx * ux3; ca += (R)cx * fx; }
+    if (cy) { cu += (R)cy * uy; cu3 += (R)cy * uy3; ca += (R)cy * fy; }
+    if (cz) { cu += (R)cz * uz; cu3 += (R)cz * uz3; ca += (R)cz * fz; }
+    const R even = w * (rp + rho * ((R)4.5 * cu * cu - uu15));
+    if (j == i) {
+      const R out = omc * d[i] + om * even;
+      a.An[(size_t)i * N + c] = C::enc(out, (R)(1.0 / wgt<LAT>(i)), s);
+      continue;
     }
-    const R ca = (R)L::cx(i) * fx + (R)L::cy(i) * fy + (R)L::cz(i) * fz;
-    const R out = d[i] - om * fn + w * rho * ca;
-    a.An[(size_t)i * a.N + c] = C::enc(out, w / s, s / w);
+    const R odd = w * cu3;
+    const R fo = w * ca;
+    const R out_i = omc * d[i] + om * (even + odd) + fo;
+    const R out_j = omc * d[j] + om * (even - odd) - fo;
+    a.An[(size_t)i * N + c] = C::enc(out_i, (R)(1.0 / wgt<LAT>(i)), s);
+    a.An[(size_t)j * N + c] = C::enc(out_j, (R)(1.0 / wgt<LAT>(j)), s);
   }
   if (active) {
-    const size_t N = a.N;
+    // strain rate from the second moment of f - f^eq (pairs: 2 x even part)
+    R P0 = 0, P1 = 0, P2 = 0, P3 = 0, P4 = 0, P5 = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int j = opp<LAT>(i);
+      if (j <= i) continue;
+      const R w = (R)wgt<LAT>(i);
+      const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
+      R cu = 0;
+      if (cx) cu += (R)cx * ux;
+      if (cy) cu += (R)cy * uy;
+      if (cz) cu += (R)cz * uz;
+      const R even = w * (rp + rho * ((R)4.5 * cu * cu - uu15));
+      const R fn2 = (d[i] + d[j]) - (R)2 * even;
+      if (cx) P0 += fn2;
+      if (cy) P1 += fn2;
+      if (cz) P2 += fn2;
+      if (cx * cy) P3 += (R)(cx * cy) * fn2;
+      if (cx * cz) P4 += (R)(cx * cz) * fn2;
+      if (cy * cz) P5 += (R)(cy * cz) * fn2;
+    }
     const R fac = -(R)1.5 * om * inv;  // -omega / (2 rho cs^2)
     a.Mn[c] = rho;
     a.Mn[N + c] = ux;
@@ -104,7 +134,7 @@ __host__ __device__ constexpr int reflect_dir(int i, int mask) {
 // no-slip; specular reflection otherwise.  check_phase: a reflected source
 // in the other phase falls back to plain bounce-back.
 template <int LAT, int ST, bool check_phase>
-__device__ __noinline__ typename Step<LAT, ST>::R wall_pull(const typename Step<LAT, ST>::Args& a, int c, int x, int y,
+__device__ __forceinline__ typename Step<LAT, ST>::R wall_pull(const typename Step<LAT, ST>::Args& a, int c, int x, int y,
                                                               int z, int i, int k) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
@@ -130,24 +160,27 @@ __device__ __noinline__ typename Step<LAT, ST>::R wall_pull(const typename Step<
     const int face = 2 * ax + (pos[ax] - cc[ax] < 0 ? 0 : 1);
     if (a.bcf[face] == LSB_NOSLIP) {
       const R cu = (R)cc[0] * a.wall_u[face][0] + (R)cc[1] * a.wall_u[face][1] + (R)cc[2] * a.wall_u[face][2];
-      return C::dec(a.A[(size_t)j * a.N + c], wj / s, s / wj) + (R)6 * (R)wgt<LAT>(i) * cu;
+      return C::dec(a.A[(size_t)j * a.N + c], wj, a.inv_scale) + (R)6 * (R)wgt<LAT>(i) * cu;
     }
   }
   const int ir = reflect_dir<LAT>(i, mask);
   const int sc = (src[2] * a.ny + src[1]) * a.nx + src[0];
-  if (check_phase && ((a.tag[sc] & T_GAS) != k)) return C::dec(a.A[(size_t)j * a.N + c], wj / s, s / wj);
+  if (check_phase && ((a.tag[sc] & T_GAS) != k)) return C::dec(a.A[(size_t)j * a.N + c], wj, a.inv_scale);
   const R wr = (R)wgt<LAT>(ir);
-  return C::dec(a.A[(size_t)ir * a.N + sc], wr / s, s / wr);
+  return C::dec(a.A[(size_t)ir * a.N + sc], wr, a.inv_scale);
 }
 
 // ---------------------------------------------------------------------------
 // a2/a3 bulk: cells with no lattice link to the other phase.  One thread per
-// cell, 256-cell blocks along x, XCD-aware block order.
+// cell, 256-cell blocks along x, XCD-aware block order.  Cells away from wall
+// faces take a branch-free gather (per-direction base pointer plus a 32-bit
+// cell offset); wall-adjacent cells apply the wall rule per direction.
 // ---------------------------------------------------------------------------
 template <int LAT, int ST>
 __global__ __launch_bounds__(256) void k_lb_bulk(const typename Step<LAT, ST>::Args a, int xchunks) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
+  using T = typename S::T;
   using L = typename S::L;
   using C = typename S::C;
   constexpr int Q = S::Q;
@@ -165,16 +198,30 @@ __global__ __launch_bounds__(256) void k_lb_bulk(const typename Step<LAT, ST>::A
   const int xs[3] = {lb_coord(x + 1, a.nx, a.per[0]), x, lb_coord(x - 1, a.nx, a.per[0])};
   const int ys[3] = {lb_coord(y + 1, a.ny, a.per[1]), y, lb_coord(y - 1, a.ny, a.per[1])};
   const int zs[3] = {lb_coord(z + 1, a.nz, a.per[2]), z, lb_coord(z - 1, a.nz, a.per[2])};
-  const R s = a.scale;
+  const R is = a.inv_scale;
   R d[Q];
+  const bool wall = (xs[0] | xs[2] | ys[0] | ys[2] | zs[0] | zs[2]) < 0;
+  if (!wall) {
+    int rowoff[3][3];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const int sx = xs[L::cx(i) + 1], sy = ys[L::cy(i) + 1], sz = zs[L::cz(i) + 1];
-    const R w = (R)wgt<LAT>(i);
-    if ((sx | sy | sz) >= 0) {
-      d[i] = C::dec(a.A[(size_t)i * a.N + (sz * a.ny + sy) * a.nx + sx], w / s, s / w);
-    } else {
-      d[i] = wall_pull<LAT, ST, false>(a, c, x, y, z, i, k);
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) rowoff[dz][dy] = (zs[dz] * a.ny + ys[dy]) * a.nx;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const T* __restrict__ Ai = a.A + (size_t)i * a.N;
+      const unsigned off = (unsigned)(rowoff[L::cz(i) + 1][L::cy(i) + 1] + xs[L::cx(i) + 1]);
+      d[i] = C::dec(Ai[off], (R)wgt<LAT>(i), is);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int sx = xs[L::cx(i) + 1], sy = ys[L::cy(i) + 1], sz = zs[L::cz(i) + 1];
+      if ((sx | sy | sz) >= 0) {
+        d[i] = C::dec(a.A[(size_t)i * a.N + (sz * a.ny + sy) * a.nx + sx], (R)wgt<LAT>(i), is);
+      } else {
+        d[i] = wall_pull<LAT, ST, false>(a, c, x, y, z, i, k);
+      }
     }
   }
   collide_store<LAT, ST>(a, c, k, (t & T_ACT) != 0, d);
@@ -184,20 +231,20 @@ __global__ __launch_bounds__(256) void k_lb_bulk(const typename Step<LAT, ST>::A
 // a4: interface bounce-back (eq:bb with the momentum term eq:bb_cc and the
 // stress jump eq:Sdecomp).  Own cell c (phase k) pulls direction i from the
 // other-phase cell sc = c - c_i.  Deviation form: all weights of the
-// interpolation sum to one, so the rest state cancels.
+// interpolation sum to one, so the rest state cancels.  Runtime direction
+// index (constant-memory tables).
 // ---------------------------------------------------------------------------
 template <int LAT, int ST>
-__device__ __noinline__ typename Step<LAT, ST>::R iface_pull(const typename Step<LAT, ST>::Args& a, int c, int x, int y,
-                                                               int z, int sc, int i, int k) {
+__device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename Step<LAT, ST>::Args& a, int c, int x, int y,
+                                                                  int z, int sc, int i, int k) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
-  using L = typename S::L;
   using C = typename S::C;
   const size_t N = a.N;
-  const int cc[3] = {L::cx(i), L::cy(i), L::cz(i)};
-  const int j = opp<LAT>(i);
+  const int cc[3] = {tab<LAT>.cx[i], tab<LAT>.cy[i], tab<LAT>.cz[i]};
+  const int j = tab<LAT>.opp[i];
   const R s = a.scale;
-  const R w = (R)wgt<LAT>(i);
+  const R w = tw<LAT, R>(i);
   const R px = a.phi[c], py = a.phi[sc];
   const R q = px / (px - py);
   // interface velocity (linear interpolation of the previous moments)
@@ -243,7 +290,7 @@ __device__ __noinline__ typename Step<LAT, ST>::R iface_pull(const typename Step
   const R s_own = (k == 0) ? (R)1 : (R)-1;
   const R cu = (R)cc[0] * uG[0] + (R)cc[1] * uG[1] + (R)cc[2] * uG[2];
   const R W = (R)6 * w * (cu + q * ((R)1 - q) * s_own * cSc);
-  const R dj = C::dec(a.A[(size_t)j * N + c], w / s, s / w);
+  const R dj = C::dec(a.A[(size_t)j * N + c], w, a.inv_scale);
   if (q < (R)0.5) {
     const int fx = lb_coord(x + cc[0], a.nx, a.per[0]);
     const int fy = lb_coord(y + cc[1], a.ny, a.per[1]);
@@ -251,26 +298,78 @@ __device__ __noinline__ typename Step<LAT, ST>::R iface_pull(const typename Step
     if ((fx | fy | fz) >= 0) {
       const int fc = (fz * a.ny + fy) * a.nx + fx;
       if ((a.tag[fc] & T_GAS) == k) {
-        const R djf = C::dec(a.A[(size_t)j * N + fc], w / s, s / w);
+        const R djf = C::dec(a.A[(size_t)j * N + fc], w, a.inv_scale);
         return (R)2 * q * dj + ((R)1 - (R)2 * q) * djf + W;
       }
     }
     return dj + W;
   }
-  const R di = C::dec(a.A[(size_t)i * N + c], w / s, s / w);
+  const R di = C::dec(a.A[(size_t)i * N + c], w, a.inv_scale);
   return dj / ((R)2 * q) + ((R)2 * q - (R)1) / ((R)2 * q) * di + W / ((R)2 * q);
 }
 
-// a2-a4 for the listed interface-adjacent cells.
+// Incoming deviation of direction i (runtime index) for an interface-adjacent
+// cell: plain streaming, wall rule or interface bounce-back.
+template <int LAT, int ST>
+__device__ __forceinline__ typename Step<LAT, ST>::R pull_general(const typename Step<LAT, ST>::Args& a, int c, int x,
+                                                                    int y, int z, int i, int k) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  using C = typename S::C;
+  const R s = a.scale;
+  const int cx = tab<LAT>.cx[i], cy = tab<LAT>.cy[i], cz = tab<LAT>.cz[i];
+  const int sx = lb_coord(x - cx, a.nx, a.per[0]);
+  const int sy = lb_coord(y - cy, a.ny, a.per[1]);
+  const int sz = lb_coord(z - cz, a.nz, a.per[2]);
+  const R w = tw<LAT, R>(i);
+  if ((sx | sy | sz) < 0) {
+    // a3 at an interface-adjacent cell: halfway bounce-back for any crossed
+    // no-slip face, else specular reflection (bounce-back if the reflected
+    // source lies in the other phase)
+    const int pos[3] = {x, y, z};
+    const int cc[3] = {cx, cy, cz};
+    const int n[3] = {a.nx, a.ny, a.nz};
+    const int sv3[3] = {sx, sy, sz};
+    int src[3];
+    int rc[3];
+    const int j = tab<LAT>.opp[i];
+    for (int ax = 0; ax < 3; ++ax) {
+      src[ax] = sv3[ax] < 0 ? pos[ax] : sv3[ax];
+      rc[ax] = sv3[ax] < 0 ? -cc[ax] : cc[ax];
+    }
+    for (int ax = 0; ax < 3; ++ax) {
+      if (sv3[ax] >= 0) continue;
+      const int face = 2 * ax + (pos[ax] - cc[ax] < 0 ? 0 : 1);
+      if (a.bcf[face] == LSB_NOSLIP) {
+        const R cu = (R)cc[0] * a.wall_u[face][0] + (R)cc[1] * a.wall_u[face][1] + (R)cc[2] * a.wall_u[face][2];
+        return C::dec(a.A[(size_t)j * a.N + c], w, a.inv_scale) + (R)6 * w * cu;
+      }
+    }
+    const int sc = (src[2] * a.ny + src[1]) * a.nx + src[0];
+    if ((a.tag[sc] & T_GAS) != k) return C::dec(a.A[(size_t)j * a.N + c], w, a.inv_scale);
+    int ir = 0;
+    for (int m = 0; m < S::Q; ++m)
+      if (tab<LAT>.cx[m] == rc[0] && tab<LAT>.cy[m] == rc[1] && tab<LAT>.cz[m] == rc[2]) ir = m;
+    return C::dec(a.A[(size_t)ir * a.N + sc], w, a.inv_scale);
+  }
+  const int sc = (sz * a.ny + sy) * a.nx + sx;
+  if ((a.tag[sc] & T_GAS) == k) return C::dec(a.A[(size_t)i * a.N + sc], w, a.inv_scale);
+  return iface_pull<LAT, ST>(a, c, x, y, z, sc, i, k);
+}
+
+// a2-a4 for the listed interface-adjacent cells: a runtime loop over the
+// directions gathers the incoming populations into LDS and the moments, a
+// second loop collides and stores.
 template <int LAT, int ST>
 __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::Args a) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
-  using L = typename S::L;
   using C = typename S::C;
   constexpr int Q = S::Q;
   const int n = a.counters[CNT_SPEC];
   const R s = a.scale;
+  const size_t N = a.N;
+  __shared__ R fl[Q * 256];
   for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
     const int c = a.spec_list[e];
     const int x = c % a.nx;
@@ -278,25 +377,50 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
     const int z = c / (a.nx * a.ny);
     const uint8_t t = a.tag[c];
     const int k = t & T_GAS;
-    R d[Q];
-#pragma unroll
+    const bool active = (t & T_ACT) != 0;
+    R rp = 0, m0 = 0, m1 = 0, m2 = 0;
+#pragma unroll 1
     for (int i = 0; i < Q; ++i) {
-      const int sx = lb_coord(x - L::cx(i), a.nx, a.per[0]);
-      const int sy = lb_coord(y - L::cy(i), a.ny, a.per[1]);
-      const int sz = lb_coord(z - L::cz(i), a.nz, a.per[2]);
-      if ((sx | sy | sz) < 0) {
-        d[i] = wall_pull<LAT, ST, true>(a, c, x, y, z, i, k);
-        continue;
-      }
-      const int sc = (sz * a.ny + sy) * a.nx + sx;
-      if ((a.tag[sc] & T_GAS) == k) {
-        const R w = (R)wgt<LAT>(i);
-        d[i] = C::dec(a.A[(size_t)i * a.N + sc], w / s, s / w);
-      } else {
-        d[i] = iface_pull<LAT, ST>(a, c, x, y, z, sc, i, k);
-      }
+      const R f = pull_general<LAT, ST>(a, c, x, y, z, i, k);
+      fl[i * 256 + threadIdx.x] = f;
+      rp += f;
+      m0 += (R)tab<LAT>.cx[i] * f;
+      m1 += (R)tab<LAT>.cy[i] * f;
+      m2 += (R)tab<LAT>.cz[i] * f;
     }
-    collide_store<LAT, ST>(a, c, k, (t & T_ACT) != 0, d);
+    const R rho = (R)1 + rp;
+    const R inv = (R)1 / rho;
+    const R ux = m0 * inv, uy = m1 * inv, uz = m2 * inv;
+    const R uu = ux * ux + uy * uy + uz * uz;
+    const R om = a.omega[k];
+    const R fx = (R)3 * a.acc[k][0], fy = (R)3 * a.acc[k][1], fz = (R)3 * a.acc[k][2];
+    R P0 = 0, P1 = 0, P2 = 0, P3 = 0, P4 = 0, P5 = 0;
+#pragma unroll 1
+    for (int i = 0; i < Q; ++i) {
+      const R f = fl[i * 256 + threadIdx.x];
+      const R w = tw<LAT, R>(i);
+      const R cx = (R)tab<LAT>.cx[i], cy = (R)tab<LAT>.cy[i], cz = (R)tab<LAT>.cz[i];
+      const R cu = cx * ux + cy * uy + cz * uz;
+      const R deq = w * (rp + rho * ((R)3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu));
+      const R fn = f - deq;
+      P0 += cx * cx * fn; P1 += cy * cy * fn; P2 += cz * cz * fn;
+      P3 += cx * cy * fn; P4 += cx * cz * fn; P5 += cy * cz * fn;
+      const R ca = cx * fx + cy * fy + cz * fz;
+      a.An[(size_t)i * N + c] = C::enc(f - om * fn + w * rho * ca, twinv<LAT, R>(i), s);
+    }
+    if (active) {
+      const R fac = -(R)1.5 * om * inv;
+      a.Mn[c] = rho;
+      a.Mn[N + c] = ux;
+      a.Mn[2 * N + c] = uy;
+      a.Mn[3 * N + c] = uz;
+      a.Mn[4 * N + c] = fac * P0;
+      a.Mn[5 * N + c] = fac * P1;
+      a.Mn[6 * N + c] = fac * P2;
+      a.Mn[7 * N + c] = fac * P3;
+      a.Mn[8 * N + c] = fac * P4;
+      a.Mn[9 * N + c] = fac * P5;
+    }
   }
 }
 
@@ -621,44 +745,52 @@ __global__ __launch_bounds__(256) void k_classify(const typename Step<LAT, ST>::
   using S = Step<LAT, ST>;
   using R = typename S::R;
   using L = typename S::L;
+  // tile plus a one-cell halo staged in LDS; cells beyond a wall face are
+  // marked invalid (lattice-neighbour semantics: they are skipped)
+  constexpr int MAXH = 1024;
+  __shared__ R sphi[MAXH];
   __shared__ int any_act;
   const int count = a.counters[CNT_CAND];
   const int tcells = a.tdim[0] * a.tdim[1] * a.tdim[2];
+  const int hz = S::D == 3 ? 1 : 0;
+  const int LX = a.tdim[0] + 2, LY = a.tdim[1] + 2, LZ = a.tdim[2] + 2 * hz;
   const R B = a.band;
+  const R INVALID = (R)1e30;
   for (int e = blockIdx.x; e < count; e += gridDim.x) {
     const int t = a.cand_list[e];
     int x0, y0, z0;
     tile_origin(a, t, x0, y0, z0);
     if (threadIdx.x == 0) any_act = 0;
+    for (int l = threadIdx.x; l < LX * LY * LZ; l += blockDim.x) {
+      const int lx = l % LX, ly = (l / LX) % LY, lz = l / (LX * LY);
+      const int gx = lb_coord(x0 - 1 + lx, a.nx, a.per[0]);
+      const int gy = lb_coord(y0 - 1 + ly, a.ny, a.per[1]);
+      const int gz = lb_coord(z0 - hz + lz, a.nz, a.per[2]);
+      sphi[l] = ((gx | gy | gz) < 0) ? INVALID : a.phi[(gz * a.ny + gy) * a.nx + gx];
+    }
     __syncthreads();
     int mine = 0;
     for (int l = threadIdx.x; l < tcells; l += blockDim.x) {
-      const int x = x0 + l % a.tdim[0];
-      const int y = y0 + (l / a.tdim[0]) % a.tdim[1];
-      const int z = z0 + l / (a.tdim[0] * a.tdim[1]);
+      const int ix = l % a.tdim[0], iy = (l / a.tdim[0]) % a.tdim[1], iz = l / (a.tdim[0] * a.tdim[1]);
+      const int x = x0 + ix, y = y0 + iy, z = z0 + iz;
       if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
       const int c = (z * a.ny + y) * a.nx + x;
-      const int ph = a.phi[c] >= (R)0 ? 1 : 0;
+      const int lc = ((iz + hz) * LY + iy + 1) * LX + ix + 1;
+      const R pc = sphi[lc];
+      const int ph = pc >= (R)0 ? 1 : 0;
       bool act = false;
-      const int zr = S::D == 3 ? 1 : 0;
-      for (int dz = -zr; dz <= zr && !act; ++dz)
-        for (int dy = -1; dy <= 1 && !act; ++dy)
-          for (int dx = -1; dx <= 1 && !act; ++dx) {
-            const int sx = lb_coord(x + dx, a.nx, a.per[0]);
-            const int sy = lb_coord(y + dy, a.ny, a.per[1]);
-            const int sz = lb_coord(z + dz, a.nz, a.per[2]);
-            if ((sx | sy | sz) < 0) continue;
-            const R v = a.phi[(sz * a.ny + sy) * a.nx + sx];
-            if (v < B && v > -B) act = true;
+      for (int dz = -hz; dz <= hz; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            const R v = sphi[lc + (dz * LY + dy) * LX + dx];
+            act = act || (v < B && v > -B);
           }
       bool spec = false;
-      for (int i = 0; i < S::Q && !spec; ++i) {
+#pragma unroll
+      for (int i = 0; i < S::Q; ++i) {
         if (c2<LAT>(i) == 0) continue;
-        const int sx = lb_coord(x - L::cx(i), a.nx, a.per[0]);
-        const int sy = lb_coord(y - L::cy(i), a.ny, a.per[1]);
-        const int sz = lb_coord(z - L::cz(i), a.nz, a.per[2]);
-        if ((sx | sy | sz) < 0) continue;
-        if ((a.phi[(sz * a.ny + sy) * a.nx + sx] >= (R)0 ? 1 : 0) != ph) spec = true;
+        const R v = sphi[lc - (L::cz(i) * LY + L::cy(i)) * LX - L::cx(i)];
+        if (v != INVALID && ((v >= (R)0 ? 1 : 0) != ph)) spec = true;
       }
       const int old = a.tag[c] & T_GAS;
       a.tag[c] = (uint8_t)(ph | (act ? T_ACT : 0) | (spec ? T_SPEC : 0) | (old ? T_OLDGAS : 0));
@@ -836,9 +968,9 @@ __global__ __launch_bounds__(256) void k_refill(const typename Step<LAT, ST>::Ar
         // equilibria as deviations from the rest state
         const R de = w * ((rr - (R)1) + rr * ((R)3 * cur + (R)4.5 * cur * cur - (R)1.5 * uur));
         const R de1 = w * ((r1 - (R)1) + r1 * ((R)3 * cu1 + (R)4.5 * cu1 * cu1 - (R)1.5 * uu1));
-        const R d1 = C::dec(a.An[(size_t)k * N + c1], w / s, s / w);
+        const R d1 = C::dec(a.An[(size_t)k * N + c1], w, a.inv_scale);
         // f(x_r) = feq(rho_r, u_r) + (f(x1) - feq(x1))
-        a.An[(size_t)k * N + c] = C::enc(de + (d1 - de1), w / s, s / w);
+        a.An[(size_t)k * N + c] = C::enc(de + (d1 - de1), (R)(1.0 / wgt<LAT>(k)), s);
       }
       a.Mn[c] = rr;
       for (int m = 0; m < 3; ++m) a.Mn[(1 + m) * N + c] = ur[m];
@@ -852,7 +984,7 @@ __global__ __launch_bounds__(256) void k_refill(const typename Step<LAT, ST>::Ar
         const R w = (R)wgt<LAT>(k);
         const R cu = (R)L::cx(k) * uG0 + (R)L::cy(k) * uG1 + (R)L::cz(k) * uG2;
         const R de = w * ((rhoG - (R)1) + rhoG * ((R)3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu));
-        a.An[(size_t)k * N + c] = C::enc(de, w / s, s / w);
+        a.An[(size_t)k * N + c] = C::enc(de, (R)(1.0 / wgt<LAT>(k)), s);
       }
       a.Mn[c] = rhoG;
       for (int m = 0; m < 6; ++m) a.Mn[(4 + m) * N + c] = 0;
@@ -977,7 +1109,7 @@ __global__ __launch_bounds__(256) void k_init_pop(const typename Step<LAT, ST>::
       const double w = wgt<LAT>(i);
       const double cu = L::cx(i) * u[0] + L::cy(i) * u[1] + L::cz(i) * u[2];
       const double fe = w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-      a.An[(size_t)i * N + c] = C::enc((R)(fe - w), (R)w / s, s / (R)w);
+      a.An[(size_t)i * N + c] = C::enc((R)(fe - w), (R)(1.0 / w), s);
     }
     R* Ms[2] = {const_cast<R*>(a.M), a.Mn};
     for (int b = 0; b < 2; ++b) {
@@ -1002,7 +1134,7 @@ __global__ __launch_bounds__(256) void k_fields(const typename Step<LAT, ST>::Ar
 #pragma unroll
     for (int i = 0; i < S::Q; ++i) {
       const R w = (R)wgt<LAT>(i);
-      const double f = wgt<LAT>(i) + (double)C::dec(a.A[(size_t)i * a.N + c], w / s, s / w);
+      const double f = wgt<LAT>(i) + (double)C::dec(a.A[(size_t)i * a.N + c], w, a.inv_scale);
       rho += f;
       m[0] += L::cx(i) * f; m[1] += L::cy(i) * f; m[2] += L::cz(i) * f;
     }
@@ -1028,7 +1160,7 @@ __global__ __launch_bounds__(256) void k_populations(const typename Step<LAT, ST
     for (int i = i0; i < i1; ++i) {
       double w = 0;
       for (int k = 0; k < S::Q; ++k) if (k == i) w = wgt<LAT>(k);
-      out[(size_t)(i - i0) * n + (c - c0)] = w + (double)C::dec(a.A[(size_t)i * a.N + c], (R)w / s, s / (R)w);
+      out[(size_t)(i - i0) * n + (c - c0)] = w + (double)C::dec(a.A[(size_t)i * a.N + c], (R)w, a.inv_scale);
     }
 }
 
@@ -1049,7 +1181,7 @@ __global__ __launch_bounds__(256) void k_integrals_partial(const typename Step<L
 #pragma unroll
     for (int i = 0; i < S::Q; ++i) {
       const R w = (R)wgt<LAT>(i);
-      const double f = wgt<LAT>(i) + (double)C::dec(a.A[(size_t)i * a.N + c], w / s, s / w);
+      const double f = wgt<LAT>(i) + (double)C::dec(a.A[(size_t)i * a.N + c], w, a.inv_scale);
       rho += f;
       m[0] += L::cx(i) * f; m[1] += L::cy(i) * f; m[2] += L::cz(i) * f;
     }
