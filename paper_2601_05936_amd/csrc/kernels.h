@@ -109,7 +109,7 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
       if (cy * cz) P5 += (R)(cy * cz) * fn2;
     }
     const R fac = -(R)1.5 * om * inv;  // -omega / (2 rho cs^2)
-    a.Mn[c] = rho;
+    a.Mn[c] = rp;
     a.Mn[N + c] = ux;
     a.Mn[2 * N + c] = uy;
     a.Mn[3 * N + c] = uz;
@@ -260,8 +260,8 @@ __device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename S
   const R kG = ((R)1 - q) * a.G[3 * N + c] + q * a.G[3 * N + sc];
   const int o = 1 - k;
   const R pb = (R)a.scal[SC_PB];
-  R p_own = a.rho_phys[k] / (R)3 * (a.M[c] - (R)1) + (k == 1 ? pb : (R)0);
-  R p_oth = a.rho_phys[o] / (R)3 * (a.M[sc] - (R)1) + (o == 1 ? pb : (R)0);
+  R p_own = a.rho_phys[k] / (R)3 * a.M[c] + (k == 1 ? pb : (R)0);
+  R p_oth = a.rho_phys[o] / (R)3 * a.M[sc] + (o == 1 ? pb : (R)0);
   for (int m = 0; m < 3; ++m) {
     p_own = p_own + a.rho_phys[k] * a.acc[k][m] * (R)(-cc[m]) * q;
     p_oth = p_oth + a.rho_phys[o] * a.acc[o][m] * (R)cc[m] * ((R)1 - q);
@@ -410,7 +410,7 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
     }
     if (active) {
       const R fac = -(R)1.5 * om * inv;
-      a.Mn[c] = rho;
+      a.Mn[c] = rp;
       a.Mn[N + c] = ux;
       a.Mn[2 * N + c] = uy;
       a.Mn[3 * N + c] = uz;
@@ -894,12 +894,13 @@ __global__ __launch_bounds__(256) void k_refill(const typename Step<LAT, ST>::Ar
         --p;
       }
     }
+    // LB densities are handled as deviations rho - 1 (as stored in M)
     const R rhoO = a.Mn[c];
     const R uG0 = a.Mn[N + c], uG1 = a.Mn[2 * N + c], uG2 = a.Mn[3 * N + c];
-    const R pold = a.rho_phys[kold] / (R)3 * (rhoO - (R)1) + (kold == 1 ? pb : (R)0);
+    const R pold = a.rho_phys[kold] / (R)3 * rhoO + (kold == 1 ? pb : (R)0);
     const R kap = a.G[3 * N + c];
     const R pnew = knew == 0 ? pold + a.sigma * kap : pold - a.sigma * kap;
-    const R rhoG = (R)1 + (pnew - (knew == 1 ? pb : (R)0)) / (a.rho_phys[knew] / (R)3);
+    const R rhoG = (pnew - (knew == 1 ? pb : (R)0)) / (a.rho_phys[knew] / (R)3);
     auto established = [&](int sc) {
       const uint8_t ts = a.tag[sc];
       return (ts & T_GAS) == knew && ((ts & T_OLDGAS) ? 1 : 0) == knew;
@@ -966,8 +967,8 @@ __global__ __launch_bounds__(256) void k_refill(const typename Step<LAT, ST>::Ar
         const R cur = (R)L::cx(k) * ur[0] + (R)L::cy(k) * ur[1] + (R)L::cz(k) * ur[2];
         const R cu1 = (R)L::cx(k) * u1[0] + (R)L::cy(k) * u1[1] + (R)L::cz(k) * u1[2];
         // equilibria as deviations from the rest state
-        const R de = w * ((rr - (R)1) + rr * ((R)3 * cur + (R)4.5 * cur * cur - (R)1.5 * uur));
-        const R de1 = w * ((r1 - (R)1) + r1 * ((R)3 * cu1 + (R)4.5 * cu1 * cu1 - (R)1.5 * uu1));
+        const R de = w * (rr + ((R)1 + rr) * ((R)3 * cur + (R)4.5 * cur * cur - (R)1.5 * uur));
+        const R de1 = w * (r1 + ((R)1 + r1) * ((R)3 * cu1 + (R)4.5 * cu1 * cu1 - (R)1.5 * uu1));
         const R d1 = C::dec(a.An[(size_t)k * N + c1], w, a.inv_scale);
         // f(x_r) = feq(rho_r, u_r) + (f(x1) - feq(x1))
         a.An[(size_t)k * N + c] = C::enc(de + (d1 - de1), (R)(1.0 / wgt<LAT>(k)), s);
@@ -983,7 +984,7 @@ __global__ __launch_bounds__(256) void k_refill(const typename Step<LAT, ST>::Ar
       for (int k = 0; k < Q; ++k) {
         const R w = (R)wgt<LAT>(k);
         const R cu = (R)L::cx(k) * uG0 + (R)L::cy(k) * uG1 + (R)L::cz(k) * uG2;
-        const R de = w * ((rhoG - (R)1) + rhoG * ((R)3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu));
+        const R de = w * (rhoG + ((R)1 + rhoG) * ((R)3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu));
         a.An[(size_t)k * N + c] = C::enc(de, (R)(1.0 / wgt<LAT>(k)), s);
       }
       a.Mn[c] = rhoG;
@@ -1113,7 +1114,7 @@ __global__ __launch_bounds__(256) void k_init_pop(const typename Step<LAT, ST>::
     }
     R* Ms[2] = {const_cast<R*>(a.M), a.Mn};
     for (int b = 0; b < 2; ++b) {
-      Ms[b][c] = (R)rho;
+      Ms[b][c] = (R)(rho - 1.0);
       for (int m = 0; m < 3; ++m) Ms[b][(1 + m) * N + c] = (R)u[m];
       for (int m = 0; m < 6; ++m) Ms[b][(4 + m) * N + c] = 0;
     }
@@ -1228,7 +1229,7 @@ template <int LAT, int ST>
 __global__ __launch_bounds__(256) void k_export_moments(const typename Step<LAT, ST>::Args a, double* out, int c0, int c1) {
   const size_t N = a.N;
   for (int c = c0 + blockIdx.x * 256 + threadIdx.x; c < c1; c += gridDim.x * 256)
-    for (int m = 0; m < 10; ++m) out[10 * (size_t)(c - c0) + m] = (double)a.M[m * N + c];
+    for (int m = 0; m < 10; ++m) out[10 * (size_t)(c - c0) + m] = (double)a.M[m * N + c] + (m == 0 ? 1.0 : 0.0);
 }
 
 }  // namespace lsb
