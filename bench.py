@@ -36,7 +36,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_mode(size, storage, steps, warmup):
+def run_mode(size, storage, steps, warmup, schedule):
     import torch
 
     from paper_2601_05936_amd import workloads as W
@@ -46,7 +46,7 @@ def run_mode(size, storage, steps, warmup):
     p = w["params"]
     t0 = time.time()
     phi0 = torch.from_numpy(W.wavy_phi(p, 8.0 * size / 512.0)).to("cuda:0")
-    s = Sim(p).init(phi0)
+    s = Sim(p).set_schedule(schedule).init(phi0)
     del phi0
     torch.cuda.synchronize()
     log(f"[{storage}] init {time.time() - t0:.1f}s workspace {s.workspace_bytes / 2**30:.1f} GiB")
@@ -69,7 +69,11 @@ def run_mode(size, storage, steps, warmup):
     Q = s.Q
     b = {0: 8, 1: 4, 2: 2, 3: 2}[storage]
     k_avg_ms = k_ms / max(k_n, 1)
-    bulk_cells = N - counts["iface_cells"]
+    # cells updated by the bulk collide-stream kernel: all but the interface
+    # and wall cells (serial) and also all but the LS-active tiles (overlap);
+    # in this workload the band (mid-height) and the z walls are disjoint
+    tile_cells = 512 * counts["active_tiles"] if schedule else 0
+    bulk_cells = N - counts["wall_cells"] - (tile_cells if schedule else counts["iface_cells"])
     # algorithmic bytes of one bulk launch: read Q and write Q populations of
     # every bulk cell, read one tag byte per cell
     alg_bytes = bulk_cells * 2 * Q * b + N
@@ -85,6 +89,7 @@ def run_mode(size, storage, steps, warmup):
         alg_bytes_per_launch=alg_bytes,
         bytes_per_cell=2 * Q * b + 1,
         iface_cells=counts["iface_cells"],
+        wall_cells=counts["wall_cells"],
         active_tiles=counts["active_tiles"],
         mass=[float(m) for m in I["mass"]],
         umax=float(I["umax"]),
@@ -129,6 +134,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--modes", default="f16dev,f32,f64")
+    ap.add_argument("--schedule", default="serial", choices=["serial", "overlap"],
+                    help="step schedule: one stream, or bulk collide-stream overlapped on a second stream")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
@@ -141,12 +148,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    from paper_2601_05936_amd.lsb import SCHED_OVERLAP, SCHED_SERIAL
     from paper_2601_05936_amd.workloads import F16DEV, F32, F64
+    sched = SCHED_OVERLAP if args.schedule == "overlap" else SCHED_SERIAL
     names = {"f16dev": F16DEV, "f32": F32, "f64": F64}
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
     results = {}
     for m in modes:
-        results[m] = run_mode(args.size, names[m], args.steps, args.warmup)
+        results[m] = run_mode(args.size, names[m], args.steps, args.warmup, sched)
     if args.copy_calibration > 0:
         nbytes = int(args.copy_calibration * 2**30)
         a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
@@ -173,7 +182,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"D3Q27 wavy stratified {args.size}^3, periodic x/y, no-slip z, density ratio 1000, "
                                f"viscosity ratio 50, sigma 1e-3 (throughput configuration)",
-                   "storage": head, "cells": args.size ** 3},
+                   "storage": head, "cells": args.size ** 3, "schedule": args.schedule},
         "modes": results,
         "roofline": {"bound": "hbm", "achieved": r["k1_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r["k1_frac"], "traffic": None,

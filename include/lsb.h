@@ -152,18 +152,30 @@ int lsb_load_state(lsb_plan* plan, const void* device_src, void* stream);
 /* Steps taken since lsb_init. */
 long lsb_step_count(const lsb_plan* plan);
 
-/* Number of cells on the interface / in the band after the last step
- * (synchronises the stream). counts[0] interface-adjacent cells, counts[1]
- * active tiles, counts[2] cells refilled in the last step. */
+/* Cell and tile counts after the last step (synchronises the stream);
+ * counts has 4 entries: counts[0] interface-adjacent cells, counts[1]
+ * LS-active tiles, counts[2] cells refilled in the last step, counts[3]
+ * wall-adjacent cells (cells with a lattice link through a wall face). */
 int lsb_get_counts(lsb_plan* plan, int* counts, void* stream);
 
-/* Kernel timing: while enabled, every step records a pair of HIP events on
- * its stream around the bulk collide-stream kernel (the dominant kernel;
- * one launch per step).  Enabling clears the accumulator.
+/* Kernel timing: while enabled, every step records a pair of HIP events
+ * around the bulk collide-stream kernel (the dominant kernel; one launch
+ * per step), on the stream that kernel runs on.  Enabling clears the accumulator.
  * lsb_get_kernel_timing waits for the recorded events and returns the summed
  * kernel duration in milliseconds and the number of launches timed. */
 int lsb_set_kernel_timing(lsb_plan* plan, int enable);
 int lsb_get_kernel_timing(lsb_plan* plan, double* total_ms, long* launches);
+
+/* Step schedule.  SERIAL: every kernel of a step runs on the caller's
+ * stream.  OVERLAP: the collide-stream of the cells outside the LS-active
+ * tiles runs on a library-owned stream (default priority), concurrently
+ * with the collide-stream of the band, interface and wall cells and the
+ * level-set chain on the caller's stream; each lsb_step call returns with
+ * the caller's stream ordered after all of its work.  Both give bit-identical
+ * results.  Call between steps (the default is SERIAL); LSB_EINVAL for an
+ * unknown schedule. */
+enum { LSB_SCHED_SERIAL = 0, LSB_SCHED_OVERLAP = 1 };
+int lsb_set_schedule(lsb_plan* plan, int schedule);
 
 const char* lsb_last_error(void);
 

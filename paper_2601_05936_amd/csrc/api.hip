@@ -150,11 +150,21 @@ int lsb_create(const lsb_params* P, lsb_plan** out) {
   p->off_scal = take(lsb::SC_COUNT * sizeof(double));
   p->off_cnt = take(lsb::CNT_NUM * sizeof(int));
   p->off_tile_act = take((size_t)p->ntiles);
+  p->off_tile_act2 = take((size_t)p->ntiles);
   p->off_tile_list = take((size_t)p->ntiles * sizeof(int));
   p->off_cand_list = take((size_t)p->ntiles * sizeof(int));
   p->off_spec_list = take(N * sizeof(int));
   p->off_flip_list = take(N * sizeof(int));
   p->off_partial = take((size_t)p->red_blocks * 16 * sizeof(double));
+  {
+    long nw = 0;
+    const long ax[3] = {P->nx, P->ny, P->nz};
+    for (int d = 0; d < 3; ++d)
+      if (P->bc[2 * d] != LSB_PERIODIC) nw += 2 * (ax[(d + 1) % 3] * ax[(d + 2) % 3]);
+    p->n_wall_cells = nw;
+    p->grid_walls = (int)std::max<long>(1, std::min<long>((nw + 255) / 256, 4096));
+    p->off_wall_list = take((size_t)(nw + 1) * sizeof(int));
+  }
   p->total = o;
   *out = p;
   return LSB_OK;
@@ -163,6 +173,12 @@ int lsb_create(const lsb_params* P, lsb_plan** out) {
 void lsb_destroy(lsb_plan* p) {
   if (!p) return;
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  if (p->side) {
+    (void)hipStreamSynchronize(p->side);
+    (void)hipStreamDestroy(p->side);
+  }
+  if (p->ev_ls_done) (void)hipEventDestroy(p->ev_ls_done);
+  if (p->ev_bulk_done) (void)hipEventDestroy(p->ev_bulk_done);
   delete p;
 }
 
@@ -179,6 +195,13 @@ int lsb_bind(lsb_plan* p, void* ws, size_t bytes) {
   p->ws = static_cast<char*>(ws);
   p->bound = true;
   p->inited = false;
+  if (!p->side) {
+    // side stream of the bulk collide-stream (default priority) and the two
+    // events that order it against the caller's stream
+    LSB_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+    LSB_HIP(hipEventCreateWithFlags(&p->ev_ls_done, hipEventDisableTiming));
+    LSB_HIP(hipEventCreateWithFlags(&p->ev_bulk_done, hipEventDisableTiming));
+  }
   return LSB_OK;
 }
 
@@ -189,7 +212,9 @@ int lsb_init(lsb_plan* p, const double* phi0, const double* rho0, const double* 
   hipStream_t st = as_stream(stream);
   const int N = p->N;
   p->cur = 0;
+  p->tcur = 0;
   p->nstep = 0;
+  LSB_HIP(hipStreamSynchronize(p->side));
   if (on_device) {
     p->ops->init_phi(p, phi0, 0, N, st);
     LSB_HIP(hipGetLastError());
@@ -222,6 +247,8 @@ int lsb_init(lsb_plan* p, const double* phi0, const double* rho0, const double* 
   }
   LSB_HIP(hipGetLastError());
   LSB_HIP(hipStreamSynchronize(st));
+  LSB_HIP(hipEventRecord(p->ev_ls_done, st));
+  LSB_HIP(hipEventRecord(p->ev_bulk_done, st));
   p->inited = true;
   return LSB_OK;
 }
@@ -235,6 +262,8 @@ int lsb_step(lsb_plan* p, int nsteps, int check_every, void* stream) {
   hipStream_t st = as_stream(stream);
   for (int s = 0; s < nsteps; ++s) {
     p->ops->step(p, st);
+    // the caller's stream sees the whole step (bulk part included)
+    if (p->schedule == LSB_SCHED_OVERLAP) LSB_HIP(hipStreamWaitEvent(st, p->ev_bulk_done, 0));
     if (int r = check_launch()) return r;
     if (check_every > 0 && (p->nstep % check_every) == 0) {
       lsb_integrals I;
@@ -437,7 +466,9 @@ int lsb_load_state(lsb_plan* p, const void* src, void* stream) {
   if (hdr[0] != 0x4c5342 || hdr[2] != p->N || hdr[3] != p->Q || hdr[4] != (long)p->bytes_pop)
     return fail(LSB_EINVAL, "state image does not match this plan");
   const size_t N = (size_t)p->N;
+  LSB_HIP(hipStreamSynchronize(p->side));
   p->cur = 0;
+  p->tcur = 0;
   LSB_HIP(hipMemcpyAsync(p->ws + p->off_A[0], s + o_pop, (size_t)p->Q * N * p->bytes_pop, hipMemcpyDeviceToDevice, st));
   LSB_HIP(hipMemcpyAsync(p->ws + p->off_phi, s + o_phi, N * p->bytes_real, hipMemcpyDeviceToDevice, st));
   LSB_HIP(hipMemcpyAsync(p->ws + p->off_s1, s + o_phi, N * p->bytes_real, hipMemcpyDeviceToDevice, st));
@@ -448,12 +479,21 @@ int lsb_load_state(lsb_plan* p, const void* src, void* stream) {
   p->ops->rebuild(p, st);
   LSB_HIP(hipGetLastError());
   LSB_HIP(hipStreamSynchronize(st));
+  LSB_HIP(hipEventRecord(p->ev_ls_done, st));
+  LSB_HIP(hipEventRecord(p->ev_bulk_done, st));
   p->nstep = hdr[1];
   p->inited = true;
   return LSB_OK;
 }
 
 long lsb_step_count(const lsb_plan* p) { return p ? p->nstep : -1; }
+
+int lsb_set_schedule(lsb_plan* p, int schedule) {
+  if (!p) return fail(LSB_EINVAL, "null plan");
+  if (schedule != LSB_SCHED_SERIAL && schedule != LSB_SCHED_OVERLAP) return fail(LSB_EINVAL, "unknown schedule");
+  p->schedule = schedule;
+  return LSB_OK;
+}
 
 int lsb_set_kernel_timing(lsb_plan* p, int enable) {
   if (!p) return fail(LSB_EINVAL, "null plan");
@@ -489,6 +529,7 @@ int lsb_get_counts(lsb_plan* p, int* counts, void* stream) {
   counts[0] = c[lsb::CNT_SPEC];
   counts[1] = c[lsb::CNT_TILES];
   counts[2] = c[lsb::CNT_FLIP];
+  counts[3] = c[lsb::CNT_WALL];
   return LSB_OK;
 }
 

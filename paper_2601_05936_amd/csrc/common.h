@@ -17,6 +17,7 @@ enum : uint8_t {
   T_GAS = 1,      // phase: gas (phi >= 0)
   T_ACT = 2,      // LS-active: in the narrow band or next to it
   T_SPEC = 4,     // has a lattice link to a cell of the other phase
+  T_WALL = 8,     // has a lattice link through a wall face (static)
   T_OLDGAS = 16,  // phase before the last classification (refill)
 };
 
@@ -212,18 +213,37 @@ struct KArgs {
   double* scal;             // device scalars (see SC_*)
   // lists
   int* counters;            // see CNT_*
-  uint8_t* tile_act;        // per tile: has LS-active cells
+  uint8_t* tile_act;        // per tile: has LS-active cells (this step)
+  uint8_t* tile_act_next;   // the same after this step's classification
   int* tile_list;           // active tiles
   int* cand_list;           // candidate tiles for classification
   int* spec_list;           // interface-adjacent cells
   int* flip_list;           // cells whose phase changed
+  int* wall_list;           // cells with a link through a wall face
   double* partial;          // reduction partials
 };
 
 // device scalar slots
 enum { SC_PB = 0, SC_XC0 = 1, SC_XC = 4, SC_V = 7, SC_COUNT = 16 };
 // counters
-enum { CNT_TILES = 0, CNT_CAND = 1, CNT_SPEC = 2, CNT_FLIP = 3, CNT_NUM = 8 };
+// (counters below CNT_STEP_RESET are cleared every step; CNT_WALL is static)
+enum { CNT_TILES = 0, CNT_CAND = 1, CNT_SPEC = 2, CNT_FLIP = 3, CNT_STEP_RESET = 4, CNT_WALL = 4, CNT_NUM = 8 };
+
+// Runtime selection from small arrays of the kernel argument block without
+// indexing it dynamically (which would copy the block to scratch memory).
+template <class V>
+__device__ __forceinline__ V sel2(const V (&v)[2], int i) { return i ? v[1] : v[0]; }
+template <class V>
+__device__ __forceinline__ V sel3(const V (&v)[3], int i) { return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]); }
+template <class V>
+__device__ __forceinline__ V sel6(const V (&v)[6], int i) {
+  return i < 3 ? (i == 0 ? v[0] : (i == 1 ? v[1] : v[2])) : (i == 3 ? v[3] : (i == 4 ? v[4] : v[5]));
+}
+// acceleration component m of phase k, wall velocity component m of face f
+#define ACC(a, k, m) ((k) ? (a).acc[1][m] : (a).acc[0][m])
+#define WALLU(a, f, m)                                                                                  \
+  ((f) < 3 ? ((f) == 0 ? (a).wall_u[0][m] : ((f) == 1 ? (a).wall_u[1][m] : (a).wall_u[2][m]))           \
+           : ((f) == 3 ? (a).wall_u[3][m] : ((f) == 4 ? (a).wall_u[4][m] : (a).wall_u[5][m])))
 
 // Level-set stencil coordinate: periodic wrap, or even mirror about a wall face.
 __device__ __forceinline__ int ls_coord(int s, int n, int periodic) {

@@ -57,11 +57,13 @@ struct Driver {
     a.ut_b = reinterpret_cast<R*>(w + p->off_ut[1]);
     a.scal = reinterpret_cast<double*>(w + p->off_scal);
     a.counters = reinterpret_cast<int*>(w + p->off_cnt);
-    a.tile_act = reinterpret_cast<uint8_t*>(w + p->off_tile_act);
+    a.tile_act = reinterpret_cast<uint8_t*>(w + (p->tcur ? p->off_tile_act2 : p->off_tile_act));
+    a.tile_act_next = reinterpret_cast<uint8_t*>(w + (p->tcur ? p->off_tile_act : p->off_tile_act2));
     a.tile_list = reinterpret_cast<int*>(w + p->off_tile_list);
     a.cand_list = reinterpret_cast<int*>(w + p->off_cand_list);
     a.spec_list = reinterpret_cast<int*>(w + p->off_spec_list);
     a.flip_list = reinterpret_cast<int*>(w + p->off_flip_list);
+    a.wall_list = reinterpret_cast<int*>(w + p->off_wall_list);
     a.partial = reinterpret_cast<double*>(w + p->off_partial);
     return a;
   }
@@ -74,10 +76,11 @@ struct Driver {
   // Classification of all tiles (initialisation and state reload).
   static void classify_all(lsb_plan* p, hipStream_t st) {
     Args a = args(p, p->cur);
-    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a);
+    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a, CNT_STEP_RESET);
     k_dilate<LAT, ST><<<(p->ntiles + 255) / 256, 256, 0, st>>>(a, 1);
     k_classify<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a, 0);
     k_geometry<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
+    p->tcur ^= 1;
   }
 
   static void centroid(lsb_plan* p, int mode, hipStream_t st) {
@@ -98,7 +101,9 @@ struct Driver {
   static void init_band(lsb_plan* p, hipStream_t st) {
     Args a = args(p, p->cur);
     k_clear_tiles<LAT, ST><<<(p->ntiles + 255) / 256, 256, 0, st>>>(a);
+    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a, CNT_NUM);
     classify_all(p, st);
+    k_mark_walls<LAT, ST><<<cell_grid(p), 256, 0, st>>>(a);
     centroid(p, 0, st);
     k_set_scalar<LAT, ST><<<1, 1, 0, st>>>(a, SC_PB, p->P.pb0);
   }
@@ -110,16 +115,34 @@ struct Driver {
     k_init_pop<LAT, ST><<<g > 0 ? g : 1, 256, 0, st>>>(b, rho0, u0, p->P.init_hydrostatic, c0, c1);
   }
 
+  // One step.  Serial schedule: the collide-stream (bulk, interface, walls)
+  // and then the level-set chain, all on the caller's stream st.  Overlap
+  // schedule: the caller's stream runs the collide-stream of the LS-active
+  // tiles (k_lb_band) and the interface and wall cells, then the level-set
+  // chain; the library's side stream runs the bulk collide-stream of all
+  // other cells concurrently.  Events order the two streams across steps.
   static void step(lsb_plan* p, hipStream_t st) {
     const lsb_params& P = p->P;
     Args a = args(p, p->cur);
     const int xchunks = (P.nx + 255) / 256;
     const int rows = P.ny * P.nz;
-    // a2-a4: collide and stream
-    timing_begin(p, st);
-    k_lb_bulk<LAT, ST><<<xchunks * rows, 256, 0, st>>>(a, xchunks);
-    timing_end(p, st);
+    if (p->schedule == LSB_SCHED_OVERLAP) {
+      // bulk part (side stream): after the previous step's level-set chain
+      (void)hipStreamWaitEvent(p->side, p->ev_ls_done, 0);
+      timing_begin(p, p->side);
+      k_lb_bulk<LAT, ST, true><<<xchunks * rows, 256, 0, p->side>>>(a, xchunks);
+      timing_end(p, p->side);
+      // band part (caller's stream): after the previous step's bulk part
+      (void)hipStreamWaitEvent(st, p->ev_bulk_done, 0);
+      (void)hipEventRecord(p->ev_bulk_done, p->side);
+      k_lb_band<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
+    } else {
+      timing_begin(p, st);
+      k_lb_bulk<LAT, ST, false><<<xchunks * rows, 256, 0, st>>>(a, xchunks);
+      timing_end(p, st);
+    }
     k_lb_iface<LAT, ST><<<p->grid_cells, 256, 0, st>>>(a);
+    if (p->n_wall_cells > 0) k_lb_wall<LAT, ST><<<p->grid_walls, 256, 0, st>>>(a);
     // a6: extension (ut ping-pong), advection
     k_ext_seed<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
     R* ua = a.ut_a;
@@ -141,14 +164,16 @@ struct Driver {
     }
     k_ls_sync<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
     // a8: classification on the dilated band, geometry, refill
-    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a);
+    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a, CNT_STEP_RESET);
     k_dilate<LAT, ST><<<(p->ntiles + 255) / 256, 256, 0, st>>>(a, 0);
     k_classify<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a, 1);
     k_geometry<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
     k_refill<LAT, ST><<<p->grid_cells, 256, 0, st>>>(a);
     p->cur ^= 1;
+    p->tcur ^= 1;
     // a9: centroid and gas pressure baseline
     if (P.use_pb) centroid(p, 1, st);
+    (void)hipEventRecord(p->ev_ls_done, st);
     ++p->nstep;
   }
 
@@ -171,7 +196,9 @@ struct Driver {
   static void rebuild(lsb_plan* p, hipStream_t st) {
     Args a = args(p, p->cur);
     k_clear_tiles<LAT, ST><<<(p->ntiles + 255) / 256, 256, 0, st>>>(a);
+    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a, CNT_NUM);
     classify_all(p, st);
+    k_mark_walls<LAT, ST><<<cell_grid(p), 256, 0, st>>>(a);
   }
 
   static const Ops* table() {

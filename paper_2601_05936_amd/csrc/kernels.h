@@ -57,9 +57,9 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
   const R inv = (R)1 / rho;
   const R ux = m0 * inv, uy = m1 * inv, uz = m2 * inv;
   const R uu15 = (R)1.5 * (ux * ux + uy * uy + uz * uz);
-  const R om = a.omega[k];
+  const R om = sel2(a.omega, k);
   const R omc = (R)1 - om;
-  const R fx = (R)3 * a.acc[k][0] * rho, fy = (R)3 * a.acc[k][1] * rho, fz = (R)3 * a.acc[k][2] * rho;
+  const R fx = (R)3 * ACC(a, k, 0) * rho, fy = (R)3 * ACC(a, k, 1) * rho, fz = (R)3 * ACC(a, k, 2) * rho;
   const R ux3 = (R)3 * rho * ux, uy3 = (R)3 * rho * uy, uz3 = (R)3 * rho * uz;
   const R s = a.scale;
   const size_t N = a.N;
@@ -148,7 +148,7 @@ __device__ __forceinline__ typename Step<LAT, ST>::R wall_pull(const typename St
   for (int ax = 0; ax < 3; ++ax) {
     int sv = pos[ax] - cc[ax];
     if (sv >= 0 && sv < n[ax]) { src[ax] = sv; continue; }
-    if (a.per[ax]) { src[ax] = sv < 0 ? sv + n[ax] : sv - n[ax]; continue; }
+    if (sel3(a.per, ax)) { src[ax] = sv < 0 ? sv + n[ax] : sv - n[ax]; continue; }
     mask |= 1 << ax;
     src[ax] = pos[ax];
   }
@@ -158,8 +158,8 @@ __device__ __forceinline__ typename Step<LAT, ST>::R wall_pull(const typename St
   for (int ax = 0; ax < 3; ++ax) {
     if (!(mask & (1 << ax))) continue;
     const int face = 2 * ax + (pos[ax] - cc[ax] < 0 ? 0 : 1);
-    if (a.bcf[face] == LSB_NOSLIP) {
-      const R cu = (R)cc[0] * a.wall_u[face][0] + (R)cc[1] * a.wall_u[face][1] + (R)cc[2] * a.wall_u[face][2];
+    if (sel6(a.bcf, face) == LSB_NOSLIP) {
+      const R cu = (R)cc[0] * WALLU(a, face, 0) + (R)cc[1] * WALLU(a, face, 1) + (R)cc[2] * WALLU(a, face, 2);
       return C::dec(a.A[(size_t)j * a.N + c], wj, a.inv_scale) + (R)6 * (R)wgt<LAT>(i) * cu;
     }
   }
@@ -171,19 +171,109 @@ __device__ __forceinline__ typename Step<LAT, ST>::R wall_pull(const typename St
 }
 
 // ---------------------------------------------------------------------------
-// a2/a3 bulk: cells with no lattice link to the other phase.  One thread per
-// cell, 256-cell blocks along x, XCD-aware block order.  Cells away from wall
-// faces take a branch-free gather (per-direction base pointer plus a 32-bit
-// cell offset); wall-adjacent cells apply the wall rule per direction.
+// Tile helpers for the level-set kernels.
+// ---------------------------------------------------------------------------
+template <class Args>
+__device__ __forceinline__ void tile_origin(const Args& a, int t, int& x0, int& y0, int& z0) {
+  const int tx = t % a.ntile[0];
+  const int ty = (t / a.ntile[0]) % a.ntile[1];
+  const int tz = t / (a.ntile[0] * a.ntile[1]);
+  x0 = tx * a.tdim[0];
+  y0 = ty * a.tdim[1];
+  z0 = tz * a.tdim[2];
+}
+
+// Loop body over the cells of the listed tiles:  F(c, x, y, z).
+template <class Args, class F>
+__device__ __forceinline__ void for_tile_cells(const Args& a, const int* list, int count, F&& f) {
+  const int tcells = a.tdim[0] * a.tdim[1] * a.tdim[2];
+  for (int e = blockIdx.x; e < count; e += gridDim.x) {
+    int x0, y0, z0;
+    tile_origin(a, list[e], x0, y0, z0);
+    for (int l = threadIdx.x; l < tcells; l += blockDim.x) {
+      const int x = x0 + l % a.tdim[0];
+      const int y = y0 + (l / a.tdim[0]) % a.tdim[1];
+      const int z = z0 + l / (a.tdim[0] * a.tdim[1]);
+      if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
+      f((z * a.ny + y) * a.nx + x, x, y, z);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a2 for one cell with no lattice link to the other phase or through a wall:
+// branch-free gather (per-direction base pointer plus a 32-bit cell offset).
 // ---------------------------------------------------------------------------
 template <int LAT, int ST>
-__global__ __launch_bounds__(256) void k_lb_bulk(const typename Step<LAT, ST>::Args a, int xchunks) {
+__device__ __forceinline__ void fast_cell(const typename Step<LAT, ST>::Args& a, int c, int x, int y, int z, uint8_t t) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
   using T = typename S::T;
   using L = typename S::L;
   using C = typename S::C;
   constexpr int Q = S::Q;
+  // source coordinate x - c for c = -1, 0, +1 (periodic wrap; no wall is crossed)
+  const int xs[3] = {x + 1 == a.nx ? 0 : x + 1, x, x == 0 ? a.nx - 1 : x - 1};
+  const int ys[3] = {y + 1 == a.ny ? 0 : y + 1, y, y == 0 ? a.ny - 1 : y - 1};
+  const int zs[3] = {z + 1 == a.nz ? 0 : z + 1, z, z == 0 ? a.nz - 1 : z - 1};
+  const R is = a.inv_scale;
+  R d[Q];
+  int rowoff[3][3];
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) rowoff[dz][dy] = (zs[dz] * a.ny + ys[dy]) * a.nx;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const T* __restrict__ Ai = a.A + (size_t)i * a.N;
+    const unsigned off = (unsigned)(rowoff[L::cz(i) + 1][L::cy(i) + 1] + xs[L::cx(i) + 1]);
+    d[i] = C::dec(Ai[off], (R)wgt<LAT>(i), is);
+  }
+  collide_store<LAT, ST>(a, c, t & T_GAS, (t & T_ACT) != 0, d);
+}
+
+// a2/a3 for a wall-adjacent cell with no lattice link to the other phase.
+template <int LAT, int ST>
+__device__ __forceinline__ void wall_cell(const typename Step<LAT, ST>::Args& a, int c, int x, int y, int z, uint8_t t) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  using L = typename S::L;
+  using C = typename S::C;
+  constexpr int Q = S::Q;
+  const int k = t & T_GAS;
+  const int xs[3] = {lb_coord(x + 1, a.nx, a.per[0]), x, lb_coord(x - 1, a.nx, a.per[0])};
+  const int ys[3] = {lb_coord(y + 1, a.ny, a.per[1]), y, lb_coord(y - 1, a.ny, a.per[1])};
+  const int zs[3] = {lb_coord(z + 1, a.nz, a.per[2]), z, lb_coord(z - 1, a.nz, a.per[2])};
+  const R is = a.inv_scale;
+  R d[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int sx = xs[L::cx(i) + 1], sy = ys[L::cy(i) + 1], sz = zs[L::cz(i) + 1];
+    if ((sx | sy | sz) >= 0) {
+      d[i] = C::dec(a.A[(size_t)i * a.N + (sz * a.ny + sy) * a.nx + sx], (R)wgt<LAT>(i), is);
+    } else {
+      d[i] = wall_pull<LAT, ST, false>(a, c, x, y, z, i, k);
+    }
+  }
+  collide_store<LAT, ST>(a, c, k, (t & T_ACT) != 0, d);
+}
+
+// Tile of a cell (8x8x8 tiles in 3D, 16x16 in 2D).
+template <int D, class Args>
+__device__ __forceinline__ int tile_of(const Args& a, int x, int y, int z) {
+  constexpr int sh = D == 3 ? 3 : 4;
+  const int tz = D == 3 ? (z >> 3) : 0;
+  return (tz * a.ntile[1] + (y >> sh)) * a.ntile[0] + (x >> sh);
+}
+
+// Bulk part of the collide-stream: one thread per cell, 256-cell blocks along
+// x, XCD-aware block order.  Skips interface-adjacent cells (k_lb_iface) and
+// wall-adjacent cells (k_lb_wall).  With SPLIT it also skips the cells of
+// LS-active tiles (k_lb_band): none of its cells is then LS-active, it
+// writes no moments and may run concurrently with the level-set kernels of
+// the same step.
+template <int LAT, int ST, bool SPLIT>
+__global__ __launch_bounds__(256) void k_lb_bulk(const typename Step<LAT, ST>::Args a, int xchunks) {
   const unsigned b = remap_xcd(blockIdx.x, gridDim.x);
   const int row = (int)(b / (unsigned)xchunks);
   const int x = (int)(b - (unsigned)row * xchunks) * 256 + (int)threadIdx.x;
@@ -191,40 +281,48 @@ __global__ __launch_bounds__(256) void k_lb_bulk(const typename Step<LAT, ST>::A
   const int y = row % a.ny;
   const int z = row / a.ny;
   const int c = row * a.nx + x;
+  if (SPLIT && a.tile_act[tile_of<Step<LAT, ST>::D>(a, x, y, z)]) return;
   const uint8_t t = a.tag[c];
-  if (t & T_SPEC) return;
-  const int k = t & T_GAS;
-  // source coordinate x - c for c = -1, 0, +1
-  const int xs[3] = {lb_coord(x + 1, a.nx, a.per[0]), x, lb_coord(x - 1, a.nx, a.per[0])};
-  const int ys[3] = {lb_coord(y + 1, a.ny, a.per[1]), y, lb_coord(y - 1, a.ny, a.per[1])};
-  const int zs[3] = {lb_coord(z + 1, a.nz, a.per[2]), z, lb_coord(z - 1, a.nz, a.per[2])};
-  const R is = a.inv_scale;
-  R d[Q];
-  const bool wall = (xs[0] | xs[2] | ys[0] | ys[2] | zs[0] | zs[2]) < 0;
-  if (!wall) {
-    int rowoff[3][3];
-#pragma unroll
-    for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy) rowoff[dz][dy] = (zs[dz] * a.ny + ys[dy]) * a.nx;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const T* __restrict__ Ai = a.A + (size_t)i * a.N;
-      const unsigned off = (unsigned)(rowoff[L::cz(i) + 1][L::cy(i) + 1] + xs[L::cx(i) + 1]);
-      d[i] = C::dec(Ai[off], (R)wgt<LAT>(i), is);
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const int sx = xs[L::cx(i) + 1], sy = ys[L::cy(i) + 1], sz = zs[L::cz(i) + 1];
-      if ((sx | sy | sz) >= 0) {
-        d[i] = C::dec(a.A[(size_t)i * a.N + (sz * a.ny + sy) * a.nx + sx], (R)wgt<LAT>(i), is);
-      } else {
-        d[i] = wall_pull<LAT, ST, false>(a, c, x, y, z, i, k);
-      }
-    }
+  if (t & (T_SPEC | T_WALL)) return;
+  fast_cell<LAT, ST>(a, c, x, y, z, SPLIT ? (uint8_t)(t & ~T_ACT) : t);
+}
+
+// Band part of the collide-stream: the non-interface cells of the LS-active
+// tiles (their moments feed the level-set kernels of the same step).
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_lb_band(const typename Step<LAT, ST>::Args a) {
+  for_tile_cells(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
+    const uint8_t t = a.tag[c];
+    if (t & (T_SPEC | T_WALL)) return;
+    fast_cell<LAT, ST>(a, c, x, y, z, t);
+  });
+}
+
+// Wall-adjacent cells (static list), except interface-adjacent ones.
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_lb_wall(const typename Step<LAT, ST>::Args a) {
+  const int n = a.counters[CNT_WALL];
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+    const int c = a.wall_list[e];
+    const uint8_t t = a.tag[c];
+    if (t & T_SPEC) continue;
+    const int x = c % a.nx, y = (c / a.nx) % a.ny, z = c / (a.nx * a.ny);
+    wall_cell<LAT, ST>(a, c, x, y, z, t);
   }
-  collide_store<LAT, ST>(a, c, k, (t & T_ACT) != 0, d);
+}
+
+// Marks wall-adjacent cells (a link leaves through a wall face) and lists them.
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_mark_walls(const typename Step<LAT, ST>::Args a) {
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < a.N; c += gridDim.x * 256) {
+    const int x = c % a.nx, y = (c / a.nx) % a.ny, z = c / (a.nx * a.ny);
+    const bool wx = !a.per[0] && (x == 0 || x == a.nx - 1);
+    const bool wy = !a.per[1] && (y == 0 || y == a.ny - 1);
+    const bool wz = !a.per[2] && (z == 0 || z == a.nz - 1);
+    const bool wall = wx || wy || wz;
+    a.tag[c] = (uint8_t)((a.tag[c] & ~T_WALL) | (wall ? T_WALL : 0));
+    if (wall) a.wall_list[atomicAdd(&a.counters[CNT_WALL], 1)] = c;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -260,11 +358,11 @@ __device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename S
   const R kG = ((R)1 - q) * a.G[3 * N + c] + q * a.G[3 * N + sc];
   const int o = 1 - k;
   const R pb = (R)a.scal[SC_PB];
-  R p_own = a.rho_phys[k] / (R)3 * a.M[c] + (k == 1 ? pb : (R)0);
-  R p_oth = a.rho_phys[o] / (R)3 * a.M[sc] + (o == 1 ? pb : (R)0);
+  R p_own = sel2(a.rho_phys, k) / (R)3 * a.M[c] + (k == 1 ? pb : (R)0);
+  R p_oth = sel2(a.rho_phys, o) / (R)3 * a.M[sc] + (o == 1 ? pb : (R)0);
   for (int m = 0; m < 3; ++m) {
-    p_own = p_own + a.rho_phys[k] * a.acc[k][m] * (R)(-cc[m]) * q;
-    p_oth = p_oth + a.rho_phys[o] * a.acc[o][m] * (R)cc[m] * ((R)1 - q);
+    p_own = p_own + sel2(a.rho_phys, k) * ACC(a, k, m) * (R)(-cc[m]) * q;
+    p_oth = p_oth + sel2(a.rho_phys, o) * ACC(a, o, m) * (R)cc[m] * ((R)1 - q);
   }
   const R p_l = (k == 0) ? p_own : p_oth;
   const R p_g = (k == 0) ? p_oth : p_own;
@@ -340,8 +438,8 @@ __device__ __forceinline__ typename Step<LAT, ST>::R pull_general(const typename
     for (int ax = 0; ax < 3; ++ax) {
       if (sv3[ax] >= 0) continue;
       const int face = 2 * ax + (pos[ax] - cc[ax] < 0 ? 0 : 1);
-      if (a.bcf[face] == LSB_NOSLIP) {
-        const R cu = (R)cc[0] * a.wall_u[face][0] + (R)cc[1] * a.wall_u[face][1] + (R)cc[2] * a.wall_u[face][2];
+      if (sel6(a.bcf, face) == LSB_NOSLIP) {
+        const R cu = (R)cc[0] * WALLU(a, face, 0) + (R)cc[1] * WALLU(a, face, 1) + (R)cc[2] * WALLU(a, face, 2);
         return C::dec(a.A[(size_t)j * a.N + c], w, a.inv_scale) + (R)6 * w * cu;
       }
     }
@@ -392,8 +490,8 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
     const R inv = (R)1 / rho;
     const R ux = m0 * inv, uy = m1 * inv, uz = m2 * inv;
     const R uu = ux * ux + uy * uy + uz * uz;
-    const R om = a.omega[k];
-    const R fx = (R)3 * a.acc[k][0], fy = (R)3 * a.acc[k][1], fz = (R)3 * a.acc[k][2];
+    const R om = sel2(a.omega, k);
+    const R fx = (R)3 * ACC(a, k, 0), fy = (R)3 * ACC(a, k, 1), fz = (R)3 * ACC(a, k, 2);
     R P0 = 0, P1 = 0, P2 = 0, P3 = 0, P4 = 0, P5 = 0;
 #pragma unroll 1
     for (int i = 0; i < Q; ++i) {
@@ -420,36 +518,6 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
       a.Mn[7 * N + c] = fac * P3;
       a.Mn[8 * N + c] = fac * P4;
       a.Mn[9 * N + c] = fac * P5;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Tile helpers for the level-set kernels.
-// ---------------------------------------------------------------------------
-template <class Args>
-__device__ __forceinline__ void tile_origin(const Args& a, int t, int& x0, int& y0, int& z0) {
-  const int tx = t % a.ntile[0];
-  const int ty = (t / a.ntile[0]) % a.ntile[1];
-  const int tz = t / (a.ntile[0] * a.ntile[1]);
-  x0 = tx * a.tdim[0];
-  y0 = ty * a.tdim[1];
-  z0 = tz * a.tdim[2];
-}
-
-// Loop body over the cells of the listed tiles:  F(c, x, y, z).
-template <class Args, class F>
-__device__ __forceinline__ void for_tile_cells(const Args& a, const int* list, int count, F&& f) {
-  const int tcells = a.tdim[0] * a.tdim[1] * a.tdim[2];
-  for (int e = blockIdx.x; e < count; e += gridDim.x) {
-    int x0, y0, z0;
-    tile_origin(a, list[e], x0, y0, z0);
-    for (int l = threadIdx.x; l < tcells; l += blockDim.x) {
-      const int x = x0 + l % a.tdim[0];
-      const int y = y0 + (l / a.tdim[0]) % a.tdim[1];
-      const int z = z0 + l / (a.tdim[0] * a.tdim[1]);
-      if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
-      f((z * a.ny + y) * a.nx + x, x, y, z);
     }
   }
 }
@@ -510,7 +578,7 @@ __global__ __launch_bounds__(256) void k_ext_iter(const typename Step<LAT, ST>::
         const R v = sg * a.G[ax * N + c];
         if (v == (R)0) continue;
         const int dir = v > (R)0 ? -1 : 1;
-        const int sv = lb_coord(pos[ax] + dir, n[ax], a.per[ax]);
+        const int sv = lb_coord(pos[ax] + dir, n[ax], sel3(a.per, ax));
         if (sv < 0) continue;
         int p2[3] = {x, y, z};
         p2[ax] = sv;
@@ -550,7 +618,7 @@ template <class Args>
 __device__ __forceinline__ int ls_index(const Args& a, int x, int y, int z, int ax, int o) {
   int p[3] = {x, y, z};
   const int n[3] = {a.nx, a.ny, a.nz};
-  p[ax] = ls_coord(p[ax] + o, n[ax], a.per[ax]);
+  p[ax] = ls_coord(p[ax] + o, n[ax], sel3(a.per, ax));
   return (p[2] * a.ny + p[1]) * a.nx + p[0];
 }
 
@@ -701,14 +769,17 @@ __global__ __launch_bounds__(256) void k_ls_sync(const typename Step<LAT, ST>::A
 // a8: classification.  Candidate tiles = active tiles dilated by one tile.
 // ---------------------------------------------------------------------------
 template <int LAT, int ST>
-__global__ __launch_bounds__(256) void k_reset_counters(const typename Step<LAT, ST>::Args a) {
-  if (threadIdx.x < CNT_NUM) a.counters[threadIdx.x] = 0;
+__global__ __launch_bounds__(256) void k_reset_counters(const typename Step<LAT, ST>::Args a, int n) {
+  if ((int)threadIdx.x < n) a.counters[threadIdx.x] = 0;
 }
 
 template <int LAT, int ST>
 __global__ __launch_bounds__(256) void k_clear_tiles(const typename Step<LAT, ST>::Args a) {
   const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t < a.ntiles) a.tile_act[t] = 0;
+  if (t < a.ntiles) {
+    a.tile_act[t] = 0;
+    a.tile_act_next[t] = 0;
+  }
 }
 
 template <int LAT, int ST>
@@ -737,6 +808,8 @@ __global__ __launch_bounds__(256) void k_dilate(const typename Step<LAT, ST>::Ar
   if (cand) {
     const int slot = atomicAdd(&a.counters[CNT_CAND], 1);
     a.cand_list[slot] = t;
+  } else {
+    a.tile_act_next[t] = 0;  // candidates get their flag from k_classify
   }
 }
 
@@ -792,8 +865,12 @@ __global__ __launch_bounds__(256) void k_classify(const typename Step<LAT, ST>::
         const R v = sphi[lc - (L::cz(i) * LY + L::cy(i)) * LX - L::cx(i)];
         if (v != INVALID && ((v >= (R)0 ? 1 : 0) != ph)) spec = true;
       }
-      const int old = a.tag[c] & T_GAS;
-      a.tag[c] = (uint8_t)(ph | (act ? T_ACT : 0) | (spec ? T_SPEC : 0) | (old ? T_OLDGAS : 0));
+      // a full classification (record_flips == 0) starts from no previous
+      // tag: the tag memory may be uninitialised (state reload); the wall
+      // bit is set afterwards by k_mark_walls
+      const uint8_t told = record_flips ? a.tag[c] : (uint8_t)ph;
+      const int old = told & T_GAS;
+      a.tag[c] = (uint8_t)(ph | (act ? T_ACT : 0) | (spec ? T_SPEC : 0) | (told & T_WALL) | (old ? T_OLDGAS : 0));
       if (act) mine = 1;
       if (spec) a.spec_list[atomicAdd(&a.counters[CNT_SPEC], 1)] = c;
       if (record_flips && ph != old) a.flip_list[atomicAdd(&a.counters[CNT_FLIP], 1)] = c;
@@ -801,7 +878,7 @@ __global__ __launch_bounds__(256) void k_classify(const typename Step<LAT, ST>::
     if (mine) any_act = 1;
     __syncthreads();
     if (threadIdx.x == 0) {
-      a.tile_act[t] = any_act ? 1 : 0;
+      a.tile_act_next[t] = any_act ? 1 : 0;
       if (any_act) a.tile_list[atomicAdd(&a.counters[CNT_TILES], 1)] = t;
     }
     __syncthreads();
@@ -897,10 +974,10 @@ __global__ __launch_bounds__(256) void k_refill(const typename Step<LAT, ST>::Ar
     // LB densities are handled as deviations rho - 1 (as stored in M)
     const R rhoO = a.Mn[c];
     const R uG0 = a.Mn[N + c], uG1 = a.Mn[2 * N + c], uG2 = a.Mn[3 * N + c];
-    const R pold = a.rho_phys[kold] / (R)3 * rhoO + (kold == 1 ? pb : (R)0);
+    const R pold = sel2(a.rho_phys, kold) / (R)3 * rhoO + (kold == 1 ? pb : (R)0);
     const R kap = a.G[3 * N + c];
     const R pnew = knew == 0 ? pold + a.sigma * kap : pold - a.sigma * kap;
-    const R rhoG = (pnew - (knew == 1 ? pb : (R)0)) / (a.rho_phys[knew] / (R)3);
+    const R rhoG = (pnew - (knew == 1 ? pb : (R)0)) / (sel2(a.rho_phys, knew) / (R)3);
     auto established = [&](int sc) {
       const uint8_t ts = a.tag[sc];
       return (ts & T_GAS) == knew && ((ts & T_OLDGAS) ? 1 : 0) == knew;
@@ -951,7 +1028,7 @@ __global__ __launch_bounds__(256) void k_refill(const typename Step<LAT, ST>::Ar
         w1 = q / ((R)1 + q);
       }
       // into a lighter phase the boundary density is the nearest new-phase cell's
-      const R rhoB = a.rho_phys[knew] >= a.rho_phys[kold] ? rhoG : a.Mn[c1];
+      const R rhoB = sel2(a.rho_phys, knew) >= sel2(a.rho_phys, kold) ? rhoG : a.Mn[c1];
       const R rr = w0 * rhoB + w1 * a.Mn[c1] + (two ? w2 * a.Mn[c2c] : (R)0);
       R ur[3];
       const R uGv[3] = {uG0, uG1, uG2};
@@ -1098,7 +1175,7 @@ __global__ __launch_bounds__(256) void k_init_pop(const typename Step<LAT, ST>::
       rho = 1.0;
       if (hydro) {
         const double pos[3] = {x + 0.5, y + 0.5, z + 0.5};
-        for (int m = 0; m < 3; ++m) rho = rho + (double)a.acc[k][m] * (pos[m] - a.scal[SC_XC0 + m]) / (1.0 / 3.0);
+        for (int m = 0; m < 3; ++m) rho = rho + (double)ACC(a, k, m) * (pos[m] - a.scal[SC_XC0 + m]) / (1.0 / 3.0);
       }
     }
     double u[3] = {0, 0, 0};
@@ -1143,8 +1220,8 @@ __global__ __launch_bounds__(256) void k_fields(const typename Step<LAT, ST>::Ar
     const size_t o = (size_t)(c - c0);
     if (rho_out) rho_out[o] = rho;
     if (u_out)
-      for (int d = 0; d < S::D; ++d) u_out[(size_t)S::D * o + d] = m[d] / rho - 0.5 * (double)a.acc[k][d];
-    if (p_out) p_out[o] = (double)a.rho_phys[k] / 3.0 * (rho - 1.0) + (k == 1 ? a.scal[SC_PB] : 0.0);
+      for (int d = 0; d < S::D; ++d) u_out[(size_t)S::D * o + d] = m[d] / rho - 0.5 * (double)ACC(a, k, d);
+    if (p_out) p_out[o] = (double)sel2(a.rho_phys, k) / 3.0 * (rho - 1.0) + (k == 1 ? a.scal[SC_PB] : 0.0);
     if (ph_out) ph_out[o] = (uint8_t)k;
   }
 }
@@ -1188,7 +1265,7 @@ __global__ __launch_bounds__(256) void k_integrals_partial(const typename Step<L
     }
     const int k = a.tag[c] & T_GAS;
     double u[3];
-    for (int d = 0; d < 3; ++d) u[d] = m[d] / rho - 0.5 * (double)a.acc[k][d];
+    for (int d = 0; d < 3; ++d) u[d] = m[d] / rho - 0.5 * (double)ACC(a, k, d);
     v[k] += rho;
     const double h = heaviside_d((double)a.phi[c], eps);
     const int x = c % a.nx, y = (c / a.nx) % a.ny, z = c / (a.nx * a.ny);

@@ -48,8 +48,9 @@ EXPORTS = [
     "lsb_create", "lsb_destroy", "lsb_workspace_bytes", "lsb_bind", "lsb_init", "lsb_step", "lsb_get_fields",
     "lsb_get_interface", "lsb_get_populations", "lsb_get_moments", "lsb_get_integrals", "lsb_state_bytes",
     "lsb_save_state", "lsb_load_state", "lsb_step_count", "lsb_get_counts", "lsb_set_kernel_timing",
-    "lsb_get_kernel_timing", "lsb_last_error",
+    "lsb_get_kernel_timing", "lsb_set_schedule", "lsb_last_error",
 ]
+SCHED_SERIAL, SCHED_OVERLAP = 0, 1
 
 _lib = None
 
@@ -85,6 +86,7 @@ def load() -> C.CDLL:
     lib.lsb_get_counts.argtypes = [vp, C.POINTER(C.c_int), vp]
     lib.lsb_set_kernel_timing.argtypes = [vp, C.c_int]
     lib.lsb_get_kernel_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_long)]
+    lib.lsb_set_schedule.argtypes = [vp, C.c_int]
     lib.lsb_last_error.restype = C.c_char_p
     _lib = lib
     return lib
@@ -216,9 +218,14 @@ class Sim:
                     vel_b=np.array(I.vel_b[:]), pb=I.pb, umax=I.umax, step=I.step)
 
     def counts(self) -> dict:
-        c = (C.c_int * 3)()
+        c = (C.c_int * 4)()
         _check(self.lib.lsb_get_counts(self.h, c, self.stream()))
-        return dict(iface_cells=c[0], active_tiles=c[1], refilled=c[2])
+        return dict(iface_cells=c[0], active_tiles=c[1], refilled=c[2], wall_cells=c[3])
+
+    def set_schedule(self, schedule: int):
+        """SCHED_SERIAL or SCHED_OVERLAP (bit-identical results)."""
+        _check(self.lib.lsb_set_schedule(self.h, int(schedule)))
+        return self
 
     def set_kernel_timing(self, enable: bool = True):
         _check(self.lib.lsb_set_kernel_timing(self.h, 1 if enable else 0))

@@ -76,3 +76,15 @@ def test_workspace_layout_and_state_image(lat, storage, shape, pop_bytes):
     # stepping before init is a state error
     assert lib.lsb_step(h, 1, 0, None) == lsb.LSB_ESTATE
     lib.lsb_destroy(h)
+
+
+def test_schedule_selection_is_validated():
+    p = W.default_params(lattice=W.D3Q19, nx=16, ny=16, nz=16)
+    rc, h = _create(p)
+    assert rc == 0
+    lib = lsb.load()
+    assert lib.lsb_set_schedule(h, lsb.SCHED_OVERLAP) == lsb.LSB_OK
+    assert lib.lsb_set_schedule(h, lsb.SCHED_SERIAL) == lsb.LSB_OK
+    assert lib.lsb_set_schedule(h, 7) == lsb.LSB_EINVAL
+    assert lib.lsb_set_schedule(None, 0) == lsb.LSB_EINVAL
+    lib.lsb_destroy(h)
