@@ -108,10 +108,13 @@ int lsb_create(const lsb_params* P, lsb_plan** out) {
   p->N = P->nx * P->ny * P->nz;
   p->bytes_pop = P->storage == LSB_F64 ? 8 : (P->storage == LSB_F32 ? 4 : 2);
   p->bytes_real = P->storage == LSB_F64 ? 8 : 4;
-  if (p->D == 2) { p->tdim[0] = 16; p->tdim[1] = 16; p->tdim[2] = 1; }
-  else { p->tdim[0] = 8; p->tdim[1] = 8; p->tdim[2] = 8; }
-  // the classification kernel stages a tile plus a one-cell halo in 1024 LDS slots
-  if ((p->tdim[0] + 2) * (p->tdim[1] + 2) * (p->tdim[2] + (p->D == 3 ? 2 : 0)) > 1024) {
+  if (p->D == 2) {
+    p->tdim[0] = lsb::TileShape<2>::X; p->tdim[1] = lsb::TileShape<2>::Y; p->tdim[2] = 1;
+  } else {
+    p->tdim[0] = lsb::TileShape<3>::X; p->tdim[1] = lsb::TileShape<3>::Y; p->tdim[2] = lsb::TileShape<3>::Z;
+  }
+  // the classification kernel stages a tile plus a one-cell halo in LDS
+  if ((p->tdim[0] + 2) * (p->tdim[1] + 2) * (p->tdim[2] + (p->D == 3 ? 2 : 0)) > lsb::kClassifyLds) {
     delete p;
     return fail(LSB_EINVAL, "internal: tile too large for the classification kernel");
   }

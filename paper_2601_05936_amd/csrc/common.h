@@ -172,6 +172,13 @@ struct Codec<LSB_BF16DEV> {
   }
 };
 
+// Population store of the collide-stream kernels: nontemporal, the written
+// lattice is read again only in the next step (it does not fit any cache).
+template <class T>
+__device__ __forceinline__ void store_pop(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
 // ---------------------------------------------------------------------------
 // Kernel argument block (everything a kernel may need, by value).
 // ---------------------------------------------------------------------------
@@ -227,7 +234,9 @@ struct KArgs {
 enum { SC_PB = 0, SC_XC0 = 1, SC_XC = 4, SC_V = 7, SC_COUNT = 16 };
 // counters
 // (counters below CNT_STEP_RESET are cleared every step; CNT_WALL is static)
-enum { CNT_TILES = 0, CNT_CAND = 1, CNT_SPEC = 2, CNT_FLIP = 3, CNT_STEP_RESET = 4, CNT_WALL = 4, CNT_NUM = 8 };
+// (CNT_SPEC and CNT_TILES form one aligned 64-bit word: one atomic reserves
+// slots in both lists)
+enum { CNT_SPEC = 0, CNT_TILES = 1, CNT_CAND = 2, CNT_FLIP = 3, CNT_STEP_RESET = 4, CNT_WALL = 4, CNT_NUM = 8 };
 
 // Runtime selection from small arrays of the kernel argument block without
 // indexing it dynamically (which would copy the block to scratch memory).
@@ -257,6 +266,31 @@ __device__ __forceinline__ int lb_coord(int s, int n, int periodic) {
   if (s >= 0 && s < n) return s;
   if (!periodic) return -1;
   return s < 0 ? s + n : s - n;
+}
+
+// Tiles of the narrow band: 32x4x4 cells in 3D (a 64-wide wavefront covers
+// two full x-rows), 16x16 in 2D; log2 of the extents.
+template <int D>
+struct TileShape {
+  static constexpr int SX = D == 3 ? 5 : 4, SY = D == 3 ? 2 : 4, SZ = D == 3 ? 2 : 0;
+  static constexpr int X = 1 << SX, Y = 1 << SY, Z = 1 << SZ;
+};
+// LDS slots of the classification kernel (a tile plus a one-cell halo)
+constexpr int kClassifyLds = 1280;
+
+// Append for the lanes of a wavefront with pred set: one atomic per
+// wavefront on the counter; lanes keep their order.  Returns the slot of
+// the calling lane (meaningful where pred is set).  All active lanes of the
+// wavefront must call it together.
+__device__ __forceinline__ int wave_append(int* counter, bool pred) {
+  const unsigned long long mask = __ballot(pred ? 1 : 0);
+  if (mask == 0ull) return -1;
+  const int lane = (int)__lane_id();
+  const int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+  base = __shfl(base, leader);
+  return base + __popcll(mask & ((1ull << lane) - 1ull));
 }
 
 __device__ __forceinline__ unsigned remap_xcd(unsigned b, unsigned nb) {

@@ -145,6 +145,7 @@ struct Driver {
     if (p->n_wall_cells > 0) k_lb_wall<LAT, ST><<<p->grid_walls, 256, 0, st>>>(a);
     // a6: extension (ut ping-pong), advection
     k_ext_seed<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
+    k_ext_seed_iface<LAT, ST><<<p->grid_cells, 256, 0, st>>>(a);
     R* ua = a.ut_a;
     R* ub = a.ut_b;
     for (int it = 0; it < P.n_ext; ++it) {

@@ -76,15 +76,15 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
     const R even = w * (rp + rho * ((R)4.5 * cu * cu - uu15));
     if (j == i) {
       const R out = omc * d[i] + om * even;
-      a.An[(size_t)i * N + c] = C::enc(out, (R)(1.0 / wgt<LAT>(i)), s);
+      store_pop(&a.An[(size_t)i * N + c], C::enc(out, (R)(1.0 / wgt<LAT>(i)), s));
       continue;
     }
     const R odd = w * cu3;
     const R fo = w * ca;
     const R out_i = omc * d[i] + om * (even + odd) + fo;
     const R out_j = omc * d[j] + om * (even - odd) - fo;
-    a.An[(size_t)i * N + c] = C::enc(out_i, (R)(1.0 / wgt<LAT>(i)), s);
-    a.An[(size_t)j * N + c] = C::enc(out_j, (R)(1.0 / wgt<LAT>(j)), s);
+    store_pop(&a.An[(size_t)i * N + c], C::enc(out_i, (R)(1.0 / wgt<LAT>(i)), s));
+    store_pop(&a.An[(size_t)j * N + c], C::enc(out_j, (R)(1.0 / wgt<LAT>(j)), s));
   }
   if (active) {
     // strain rate from the second moment of f - f^eq (pairs: 2 x even part)
@@ -173,27 +173,31 @@ __device__ __forceinline__ typename Step<LAT, ST>::R wall_pull(const typename St
 // ---------------------------------------------------------------------------
 // Tile helpers for the level-set kernels.
 // ---------------------------------------------------------------------------
-template <class Args>
+template <int D, class Args>
 __device__ __forceinline__ void tile_origin(const Args& a, int t, int& x0, int& y0, int& z0) {
+  using TS = TileShape<D>;
   const int tx = t % a.ntile[0];
   const int ty = (t / a.ntile[0]) % a.ntile[1];
   const int tz = t / (a.ntile[0] * a.ntile[1]);
-  x0 = tx * a.tdim[0];
-  y0 = ty * a.tdim[1];
-  z0 = tz * a.tdim[2];
+  x0 = tx << TS::SX;
+  y0 = ty << TS::SY;
+  z0 = tz << TS::SZ;
 }
 
-// Loop body over the cells of the listed tiles:  F(c, x, y, z).
-template <class Args, class F>
+// Loop body over the cells of the listed tiles:  F(c, x, y, z).  Every lane
+// of a block runs the same number of iterations (tile sizes are multiples
+// of the block size).
+template <int D, class Args, class F>
 __device__ __forceinline__ void for_tile_cells(const Args& a, const int* list, int count, F&& f) {
-  const int tcells = a.tdim[0] * a.tdim[1] * a.tdim[2];
+  using TS = TileShape<D>;
+  constexpr int tcells = TS::X * TS::Y * TS::Z;
   for (int e = blockIdx.x; e < count; e += gridDim.x) {
     int x0, y0, z0;
-    tile_origin(a, list[e], x0, y0, z0);
+    tile_origin<D>(a, list[e], x0, y0, z0);
     for (int l = threadIdx.x; l < tcells; l += blockDim.x) {
-      const int x = x0 + l % a.tdim[0];
-      const int y = y0 + (l / a.tdim[0]) % a.tdim[1];
-      const int z = z0 + l / (a.tdim[0] * a.tdim[1]);
+      const int x = x0 + (l & (TS::X - 1));
+      const int y = y0 + ((l >> TS::SX) & (TS::Y - 1));
+      const int z = z0 + (l >> (TS::SX + TS::SY));
       if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
       f((z * a.ny + y) * a.nx + x, x, y, z);
     }
@@ -258,12 +262,12 @@ __device__ __forceinline__ void wall_cell(const typename Step<LAT, ST>::Args& a,
   collide_store<LAT, ST>(a, c, k, (t & T_ACT) != 0, d);
 }
 
-// Tile of a cell (8x8x8 tiles in 3D, 16x16 in 2D).
+// Tile of a cell.
 template <int D, class Args>
 __device__ __forceinline__ int tile_of(const Args& a, int x, int y, int z) {
-  constexpr int sh = D == 3 ? 3 : 4;
-  const int tz = D == 3 ? (z >> 3) : 0;
-  return (tz * a.ntile[1] + (y >> sh)) * a.ntile[0] + (x >> sh);
+  using TS = TileShape<D>;
+  const int tz = D == 3 ? (z >> TS::SZ) : 0;
+  return (tz * a.ntile[1] + (y >> TS::SY)) * a.ntile[0] + (x >> TS::SX);
 }
 
 // Bulk part of the collide-stream: one thread per cell, 256-cell blocks along
@@ -291,7 +295,7 @@ __global__ __launch_bounds__(256) void k_lb_bulk(const typename Step<LAT, ST>::A
 // tiles (their moments feed the level-set kernels of the same step).
 template <int LAT, int ST>
 __global__ __launch_bounds__(256) void k_lb_band(const typename Step<LAT, ST>::Args a) {
-  for_tile_cells(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
+  for_tile_cells<Step<LAT, ST>::D>(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
     const uint8_t t = a.tag[c];
     if (t & (T_SPEC | T_WALL)) return;
     fast_cell<LAT, ST>(a, c, x, y, z, t);
@@ -332,9 +336,15 @@ __global__ __launch_bounds__(256) void k_mark_walls(const typename Step<LAT, ST>
 // interpolation sum to one, so the rest state cancels.  Runtime direction
 // index (constant-memory tables).
 // ---------------------------------------------------------------------------
+template <class R>
+struct OwnCell {   // level set, previous moments and geometry of the own cell
+  R phi, M[10], G[4];
+};
+
 template <int LAT, int ST>
-__device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename Step<LAT, ST>::Args& a, int c, int x, int y,
-                                                                  int z, int sc, int i, int k) {
+__device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename Step<LAT, ST>::Args& a,
+                                                                  const OwnCell<typename Step<LAT, ST>::R>& own, int c,
+                                                                  int x, int y, int z, int sc, int i, int k) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
   using C = typename S::C;
@@ -343,22 +353,22 @@ __device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename S
   const int j = tab<LAT>.opp[i];
   const R s = a.scale;
   const R w = tw<LAT, R>(i);
-  const R px = a.phi[c], py = a.phi[sc];
+  const R px = own.phi, py = a.phi[sc];
   const R q = px / (px - py);
   // interface velocity (linear interpolation of the previous moments)
   R uG[3], nG[3];
-  for (int m = 0; m < 3; ++m) uG[m] = ((R)1 - q) * a.M[(1 + m) * N + c] + q * a.M[(1 + m) * N + sc];
+  for (int m = 0; m < 3; ++m) uG[m] = ((R)1 - q) * own.M[1 + m] + q * a.M[(1 + m) * N + sc];
   R nn = 0;
   for (int m = 0; m < 3; ++m) {
-    nG[m] = ((R)1 - q) * a.G[m * N + c] + q * a.G[m * N + sc];
+    nG[m] = ((R)1 - q) * own.G[m] + q * a.G[m * N + sc];
     nn += nG[m] * nG[m];
   }
   const R nl = sqrt(nn);
   if (nl > (R)1e-30) for (int m = 0; m < 3; ++m) nG[m] = nG[m] / nl;
-  const R kG = ((R)1 - q) * a.G[3 * N + c] + q * a.G[3 * N + sc];
+  const R kG = ((R)1 - q) * own.G[3] + q * a.G[3 * N + sc];
   const int o = 1 - k;
   const R pb = (R)a.scal[SC_PB];
-  R p_own = sel2(a.rho_phys, k) / (R)3 * a.M[c] + (k == 1 ? pb : (R)0);
+  R p_own = sel2(a.rho_phys, k) / (R)3 * own.M[0] + (k == 1 ? pb : (R)0);
   R p_oth = sel2(a.rho_phys, o) / (R)3 * a.M[sc] + (o == 1 ? pb : (R)0);
   for (int m = 0; m < 3; ++m) {
     p_own = p_own + sel2(a.rho_phys, k) * ACC(a, k, m) * (R)(-cc[m]) * q;
@@ -374,7 +384,7 @@ __device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename S
   const R eta_p = eta_bar > rmax / (R)12 ? eta_bar : rmax / (R)12;
   const R E = ((p_g - p_l) + a.sigma * kG) / ((R)2 * eta_p);
   R Sb[6];
-  for (int m = 0; m < 6; ++m) Sb[m] = (R)0.5 * (a.M[(4 + m) * N + c] + a.M[(4 + m) * N + sc]);
+  for (int m = 0; m < 6; ++m) Sb[m] = (R)0.5 * (own.M[4 + m] + a.M[(4 + m) * N + sc]);
   const R acoef = -jeta / eta_bar;
   const R Sm[3][3] = {{Sb[0], Sb[3], Sb[4]}, {Sb[3], Sb[1], Sb[5]}, {Sb[4], Sb[5], Sb[2]}};
   const R cn = (R)cc[0] * nG[0] + (R)cc[1] * nG[1] + (R)cc[2] * nG[2];
@@ -409,8 +419,9 @@ __device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename S
 // Incoming deviation of direction i (runtime index) for an interface-adjacent
 // cell: plain streaming, wall rule or interface bounce-back.
 template <int LAT, int ST>
-__device__ __forceinline__ typename Step<LAT, ST>::R pull_general(const typename Step<LAT, ST>::Args& a, int c, int x,
-                                                                    int y, int z, int i, int k) {
+__device__ __forceinline__ typename Step<LAT, ST>::R pull_general(const typename Step<LAT, ST>::Args& a,
+                                                                    const OwnCell<typename Step<LAT, ST>::R>& own, int c,
+                                                                    int x, int y, int z, int i, int k) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
   using C = typename S::C;
@@ -452,7 +463,7 @@ __device__ __forceinline__ typename Step<LAT, ST>::R pull_general(const typename
   }
   const int sc = (sz * a.ny + sy) * a.nx + sx;
   if ((a.tag[sc] & T_GAS) == k) return C::dec(a.A[(size_t)i * a.N + sc], w, a.inv_scale);
-  return iface_pull<LAT, ST>(a, c, x, y, z, sc, i, k);
+  return iface_pull<LAT, ST>(a, own, c, x, y, z, sc, i, k);
 }
 
 // a2-a4 for the listed interface-adjacent cells: a runtime loop over the
@@ -476,10 +487,16 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
     const uint8_t t = a.tag[c];
     const int k = t & T_GAS;
     const bool active = (t & T_ACT) != 0;
+    OwnCell<R> own;
+    own.phi = a.phi[c];
+#pragma unroll
+    for (int m = 0; m < 10; ++m) own.M[m] = a.M[(size_t)m * N + c];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) own.G[m] = a.G[(size_t)m * N + c];
     R rp = 0, m0 = 0, m1 = 0, m2 = 0;
 #pragma unroll 1
     for (int i = 0; i < Q; ++i) {
-      const R f = pull_general<LAT, ST>(a, c, x, y, z, i, k);
+      const R f = pull_general<LAT, ST>(a, own, c, x, y, z, i, k);
       fl[i * 256 + threadIdx.x] = f;
       rp += f;
       m0 += (R)tab<LAT>.cx[i] * f;
@@ -504,7 +521,7 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
       P0 += cx * cx * fn; P1 += cy * cy * fn; P2 += cz * cz * fn;
       P3 += cx * cy * fn; P4 += cx * cz * fn; P5 += cy * cz * fn;
       const R ca = cx * fx + cy * fy + cz * fz;
-      a.An[(size_t)i * N + c] = C::enc(f - om * fn + w * rho * ca, twinv<LAT, R>(i), s);
+      store_pop(&a.An[(size_t)i * N + c], C::enc(f - om * fn + w * rho * ca, twinv<LAT, R>(i), s));
     }
     if (active) {
       const R fac = -(R)1.5 * om * inv;
@@ -527,18 +544,31 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
 // ---------------------------------------------------------------------------
 template <int LAT, int ST>
 __global__ __launch_bounds__(256) void k_ext_seed(const typename Step<LAT, ST>::Args a) {
+  const size_t N = a.N;
+  for_tile_cells<Step<LAT, ST>::D>(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int, int, int) {
+    const uint8_t t = a.tag[c];
+    if ((t & (T_ACT | T_SPEC)) != T_ACT) return;
+    for (int m = 0; m < 3; ++m) a.ut_a[m * N + c] = a.Mn[(1 + m) * N + c];
+  });
+}
+
+// Seed at the interface-adjacent cells: the mean over the cut links of the
+// velocity interpolated to the interface.
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_ext_seed_iface(const typename Step<LAT, ST>::Args a) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
   using L = typename S::L;
   const size_t N = a.N;
-  for_tile_cells(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
-    const uint8_t t = a.tag[c];
-    if (!(t & T_ACT)) return;
-    if (!(t & T_SPEC)) {
-      for (int m = 0; m < 3; ++m) a.ut_a[m * N + c] = a.Mn[(1 + m) * N + c];
-      return;
-    }
-    const int k = t & T_GAS;
+  const int n = a.counters[CNT_SPEC];
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+    const int c = a.spec_list[e];
+    const int x = c % a.nx;
+    const int y = (c / a.nx) % a.ny;
+    const int z = c / (a.nx * a.ny);
+    const int k = a.tag[c] & T_GAS;
+    const R pc = a.phi[c];
+    const R uc[3] = {a.Mn[N + c], a.Mn[2 * N + c], a.Mn[3 * N + c]};
     R acc[3] = {0, 0, 0};
     int cnt = 0;
     for (int i = 0; i < S::Q; ++i) {
@@ -549,12 +579,12 @@ __global__ __launch_bounds__(256) void k_ext_seed(const typename Step<LAT, ST>::
       if ((sx | sy | sz) < 0) continue;
       const int sc = (sz * a.ny + sy) * a.nx + sx;
       if ((a.tag[sc] & T_GAS) == k) continue;
-      const R q = a.phi[c] / (a.phi[c] - a.phi[sc]);
-      for (int m = 0; m < 3; ++m) acc[m] += ((R)1 - q) * a.Mn[(1 + m) * N + c] + q * a.Mn[(1 + m) * N + sc];
+      const R q = pc / (pc - a.phi[sc]);
+      for (int m = 0; m < 3; ++m) acc[m] += ((R)1 - q) * uc[m] + q * a.Mn[(1 + m) * N + sc];
       ++cnt;
     }
     for (int m = 0; m < 3; ++m) a.ut_a[m * N + c] = acc[m] / (R)cnt;
-  });
+  }
 }
 
 // One forward-Euler sweep of the first-order upwind extension; interface
@@ -564,7 +594,7 @@ __global__ __launch_bounds__(256) void k_ext_iter(const typename Step<LAT, ST>::
   using S = Step<LAT, ST>;
   using R = typename S::R;
   const size_t N = a.N;
-  for_tile_cells(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
+  for_tile_cells<S::D>(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
     const uint8_t t = a.tag[c];
     if (!(t & T_ACT)) return;
     R u[3] = {a.ut_a[c], a.ut_a[N + c], a.ut_a[2 * N + c]};
@@ -629,7 +659,7 @@ __global__ __launch_bounds__(256) void k_rk3_stage(const typename Step<LAT, ST>:
   const size_t N = a.N;
   const R* in = stage == 1 ? a.phi : (stage == 2 ? a.s1 : a.s2);
   R* out = stage == 1 ? a.s1 : (stage == 2 ? a.s2 : a.phi);
-  for_tile_cells(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
+  for_tile_cells<S::D>(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
     if (!(a.tag[c] & T_ACT)) return;
     R r = 0;
     for (int ax = 0; ax < S::D; ++ax) {
@@ -661,7 +691,7 @@ template <int LAT, int ST>
 __global__ __launch_bounds__(256) void k_reinit_prep(const typename Step<LAT, ST>::Args a) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
-  for_tile_cells(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
+  for_tile_cells<S::D>(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
     if (!(a.tag[c] & T_ACT)) return;
     const R ph = a.phi[c];
     a.p0[c] = ph;
@@ -700,7 +730,7 @@ __global__ __launch_bounds__(256) void k_reinit_stage(const typename Step<LAT, S
   R* out = stage == 1 ? a.s1 : (stage == 2 ? a.s2 : a.phi);
   const R beta = (R)0.5;
   const R dt = a.reinit_dtau;
-  for_tile_cells(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
+  for_tile_cells<S::D>(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
     if (!(a.tag[c] & T_ACT)) return;
     const R ph0 = a.p0[c];
     const R S0 = ph0 / sqrt(ph0 * ph0 + (R)1);
@@ -756,7 +786,7 @@ __global__ __launch_bounds__(256) void k_reinit_stage(const typename Step<LAT, S
 // Restore phi = s1 = s2 = p0 on the band after the level-set update.
 template <int LAT, int ST>
 __global__ __launch_bounds__(256) void k_ls_sync(const typename Step<LAT, ST>::Args a) {
-  for_tile_cells(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int, int, int) {
+  for_tile_cells<Step<LAT, ST>::D>(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int, int, int) {
     if (!(a.tag[c] & T_ACT)) return;
     const auto v = a.phi[c];
     a.s1[c] = v;
@@ -790,9 +820,8 @@ __global__ void k_set_scalar(const typename Step<LAT, ST>::Args a, int slot, dou
 template <int LAT, int ST>
 __global__ __launch_bounds__(256) void k_dilate(const typename Step<LAT, ST>::Args a, int all) {
   const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= a.ntiles) return;
-  bool cand = all != 0;
-  if (!cand) {
+  bool cand = all != 0 && t < a.ntiles;
+  if (!cand && t < a.ntiles) {
     const int tx = t % a.ntile[0], ty = (t / a.ntile[0]) % a.ntile[1], tz = t / (a.ntile[0] * a.ntile[1]);
     const int zr = Step<LAT, ST>::D == 3 ? 1 : 0;
     for (int dz = -zr; dz <= zr && !cand; ++dz)
@@ -805,12 +834,9 @@ __global__ __launch_bounds__(256) void k_dilate(const typename Step<LAT, ST>::Ar
           if (a.tile_act[(uz * a.ntile[1] + uy) * a.ntile[0] + ux]) cand = true;
         }
   }
-  if (cand) {
-    const int slot = atomicAdd(&a.counters[CNT_CAND], 1);
-    a.cand_list[slot] = t;
-  } else {
-    a.tile_act_next[t] = 0;  // candidates get their flag from k_classify
-  }
+  const int slot = wave_append(&a.counters[CNT_CAND], cand);
+  if (cand) a.cand_list[slot] = t;
+  else if (t < a.ntiles) a.tile_act_next[t] = 0;  // candidates get their flag from k_classify
 }
 
 template <int LAT, int ST>
@@ -818,22 +844,29 @@ __global__ __launch_bounds__(256) void k_classify(const typename Step<LAT, ST>::
   using S = Step<LAT, ST>;
   using R = typename S::R;
   using L = typename S::L;
+  using TS = TileShape<S::D>;
+  constexpr int tcells = TS::X * TS::Y * TS::Z;
+  constexpr int ITER = tcells / 256;  // cells per thread
+  constexpr int NW = 256 / 64;        // wavefronts per block
+  constexpr int hz = S::D == 3 ? 1 : 0;
+  constexpr int LX = TS::X + 2, LY = TS::Y + 2, LZ = TS::Z + 2 * hz;
+  static_assert(LX * LY * LZ <= kClassifyLds, "classification tile does not fit the LDS buffer");
+  static_assert(ITER * 256 == tcells, "tile size must be a multiple of the block size");
   // tile plus a one-cell halo staged in LDS; cells beyond a wall face are
   // marked invalid (lattice-neighbour semantics: they are skipped)
-  constexpr int MAXH = 1024;
-  __shared__ R sphi[MAXH];
-  __shared__ int any_act;
+  __shared__ R sphi[kClassifyLds];
+  __shared__ int wcnt[2][ITER][NW];  // spec / flip cells per wavefront and pass
+  __shared__ int wact[NW];
+  __shared__ int base[2];
   const int count = a.counters[CNT_CAND];
-  const int tcells = a.tdim[0] * a.tdim[1] * a.tdim[2];
-  const int hz = S::D == 3 ? 1 : 0;
-  const int LX = a.tdim[0] + 2, LY = a.tdim[1] + 2, LZ = a.tdim[2] + 2 * hz;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const R B = a.band;
   const R INVALID = (R)1e30;
   for (int e = blockIdx.x; e < count; e += gridDim.x) {
     const int t = a.cand_list[e];
     int x0, y0, z0;
-    tile_origin(a, t, x0, y0, z0);
-    if (threadIdx.x == 0) any_act = 0;
+    tile_origin<S::D>(a, t, x0, y0, z0);
     for (int l = threadIdx.x; l < LX * LY * LZ; l += blockDim.x) {
       const int lx = l % LX, ly = (l / LX) % LY, lz = l / (LX * LY);
       const int gx = lb_coord(x0 - 1 + lx, a.nx, a.per[0]);
@@ -842,44 +875,90 @@ __global__ __launch_bounds__(256) void k_classify(const typename Step<LAT, ST>::
       sphi[l] = ((gx | gy | gz) < 0) ? INVALID : a.phi[(gz * a.ny + gy) * a.nx + gx];
     }
     __syncthreads();
-    int mine = 0;
-    for (int l = threadIdx.x; l < tcells; l += blockDim.x) {
-      const int ix = l % a.tdim[0], iy = (l / a.tdim[0]) % a.tdim[1], iz = l / (a.tdim[0] * a.tdim[1]);
-      const int x = x0 + ix, y = y0 + iy, z = z0 + iz;
-      if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
-      const int c = (z * a.ny + y) * a.nx + x;
-      const int lc = ((iz + hz) * LY + iy + 1) * LX + ix + 1;
-      const R pc = sphi[lc];
-      const int ph = pc >= (R)0 ? 1 : 0;
-      bool act = false;
-      for (int dz = -hz; dz <= hz; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-          for (int dx = -1; dx <= 1; ++dx) {
-            const R v = sphi[lc + (dz * LY + dy) * LX + dx];
-            act = act || (v < B && v > -B);
-          }
-      bool spec = false;
+    bool spec[ITER], flip[ITER];
+    int cell[ITER];
+    bool act_any = false;
 #pragma unroll
-      for (int i = 0; i < S::Q; ++i) {
-        if (c2<LAT>(i) == 0) continue;
-        const R v = sphi[lc - (L::cz(i) * LY + L::cy(i)) * LX - L::cx(i)];
-        if (v != INVALID && ((v >= (R)0 ? 1 : 0) != ph)) spec = true;
+    for (int it = 0; it < ITER; ++it) {
+      const int l = threadIdx.x + it * 256;
+      const int ix = l & (TS::X - 1), iy = (l >> TS::SX) & (TS::Y - 1), iz = l >> (TS::SX + TS::SY);
+      const int x = x0 + ix, y = y0 + iy, z = z0 + iz;
+      const int c = (z * a.ny + y) * a.nx + x;
+      cell[it] = c;
+      spec[it] = false;
+      flip[it] = false;
+      if (x < a.nx && y < a.ny && z < a.nz) {
+        const int lc = ((iz + hz) * LY + iy + 1) * LX + ix + 1;
+        const R pc = sphi[lc];
+        const int ph = pc >= (R)0 ? 1 : 0;
+        bool act = false;
+        for (int dz = -hz; dz <= hz; ++dz)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              const R v = sphi[lc + (dz * LY + dy) * LX + dx];
+              act = act || (v < B && v > -B);
+            }
+        bool sp = false;
+#pragma unroll
+        for (int i = 0; i < S::Q; ++i) {
+          if (c2<LAT>(i) == 0) continue;
+          const R v = sphi[lc - (L::cz(i) * LY + L::cy(i)) * LX - L::cx(i)];
+          if (v != INVALID && ((v >= (R)0 ? 1 : 0) != ph)) sp = true;
+        }
+        // a full classification (record_flips == 0) starts from no previous
+        // tag: the tag memory may be uninitialised (state reload); the wall
+        // bit is set afterwards by k_mark_walls
+        const uint8_t told = record_flips ? a.tag[c] : (uint8_t)ph;
+        const int old = told & T_GAS;
+        a.tag[c] = (uint8_t)(ph | (act ? T_ACT : 0) | (sp ? T_SPEC : 0) | (told & T_WALL) | (old ? T_OLDGAS : 0));
+        act_any = act_any || act;
+        spec[it] = sp;
+        flip[it] = record_flips && ph != old;
       }
-      // a full classification (record_flips == 0) starts from no previous
-      // tag: the tag memory may be uninitialised (state reload); the wall
-      // bit is set afterwards by k_mark_walls
-      const uint8_t told = record_flips ? a.tag[c] : (uint8_t)ph;
-      const int old = told & T_GAS;
-      a.tag[c] = (uint8_t)(ph | (act ? T_ACT : 0) | (spec ? T_SPEC : 0) | (told & T_WALL) | (old ? T_OLDGAS : 0));
-      if (act) mine = 1;
-      if (spec) a.spec_list[atomicAdd(&a.counters[CNT_SPEC], 1)] = c;
-      if (record_flips && ph != old) a.flip_list[atomicAdd(&a.counters[CNT_FLIP], 1)] = c;
     }
-    if (mine) any_act = 1;
+    // list appends: per-wavefront counts, then one atomic per tile reserves
+    // the tile's slots in the interface-cell and tile lists together
+    unsigned long long smask[ITER], fmask[ITER];
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      smask[it] = __ballot(spec[it] ? 1 : 0);
+      fmask[it] = __ballot(flip[it] ? 1 : 0);
+      if (lane == 0) {
+        wcnt[0][it][wave] = __popcll(smask[it]);
+        wcnt[1][it][wave] = __popcll(fmask[it]);
+      }
+    }
+    const unsigned long long amask = __ballot(act_any ? 1 : 0);
+    if (lane == 0) wact[wave] = amask != 0ull;
     __syncthreads();
     if (threadIdx.x == 0) {
-      a.tile_act_next[t] = any_act ? 1 : 0;
-      if (any_act) a.tile_list[atomicAdd(&a.counters[CNT_TILES], 1)] = t;
+      int ns = 0, nf = 0, na = 0;
+      for (int it = 0; it < ITER; ++it)
+        for (int w = 0; w < NW; ++w) { ns += wcnt[0][it][w]; nf += wcnt[1][it][w]; }
+      for (int w = 0; w < NW; ++w) na |= wact[w];
+      a.tile_act_next[t] = na ? 1 : 0;
+      int sb = 0;
+      if (na || ns) {
+        // counters[CNT_SPEC] (low word) and counters[CNT_TILES] (high word)
+        const unsigned long long inc = ((unsigned long long)(na ? 1 : 0) << 32) | (unsigned long long)ns;
+        const unsigned long long old =
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[CNT_SPEC]), inc);
+        sb = (int)(old & 0xffffffffull);
+        if (na) a.tile_list[(int)(old >> 32)] = t;
+      }
+      base[0] = sb;
+      base[1] = nf ? atomicAdd(&a.counters[CNT_FLIP], nf) : 0;
+    }
+    __syncthreads();
+    int off[2] = {base[0], base[1]};
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      int ps = off[0], pf = off[1];
+      for (int w = 0; w < wave; ++w) { ps += wcnt[0][it][w]; pf += wcnt[1][it][w]; }
+      const unsigned long long below = (1ull << lane) - 1ull;
+      if (spec[it]) a.spec_list[ps + __popcll(smask[it] & below)] = cell[it];
+      if (flip[it]) a.flip_list[pf + __popcll(fmask[it] & below)] = cell[it];
+      for (int w = 0; w < NW; ++w) { off[0] += wcnt[0][it][w]; off[1] += wcnt[1][it][w]; }
     }
     __syncthreads();
   }
@@ -893,7 +972,7 @@ __global__ __launch_bounds__(256) void k_geometry(const typename Step<LAT, ST>::
   using S = Step<LAT, ST>;
   using R = typename S::R;
   const size_t N = a.N;
-  for_tile_cells(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
+  for_tile_cells<S::D>(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
     if (!(a.tag[c] & T_ACT)) return;
     auto at = [&](int dx, int dy, int dz) {
       const int sx = ls_coord(x + dx, a.nx, a.per[0]);
