@@ -124,7 +124,8 @@ int lsb_create(const lsb_params* P, lsb_plan** out) {
     p->ntile[a] = (n[a] + p->tdim[a] - 1) / p->tdim[a];
     p->ntiles *= p->ntile[a];
   }
-  p->grid_tiles = std::min(p->ntiles, 2048);
+  // one block per listed tile (blocks beyond the list length exit at once)
+  p->grid_tiles = std::min(p->ntiles, 32768);
   p->grid_cells = (int)std::min<long>(((long)p->N + 255) / 256, 4096);
   p->red_blocks = 512;
   switch (P->lattice) {
@@ -154,6 +155,8 @@ int lsb_create(const lsb_params* P, lsb_plan** out) {
   p->off_cnt = take(lsb::CNT_NUM * sizeof(int));
   p->off_tile_act = take((size_t)p->ntiles);
   p->off_tile_act2 = take((size_t)p->ntiles);
+  p->off_cflag[0] = take((size_t)p->ntiles);
+  p->off_cflag[1] = take((size_t)p->ntiles);
   p->off_tile_list = take((size_t)p->ntiles * sizeof(int));
   p->off_cand_list = take((size_t)p->ntiles * sizeof(int));
   p->off_spec_list = take(N * sizeof(int));
@@ -180,7 +183,7 @@ void lsb_destroy(lsb_plan* p) {
     (void)hipStreamSynchronize(p->side);
     (void)hipStreamDestroy(p->side);
   }
-  if (p->ev_ls_done) (void)hipEventDestroy(p->ev_ls_done);
+  if (p->ev_pop_done) (void)hipEventDestroy(p->ev_pop_done);
   if (p->ev_bulk_done) (void)hipEventDestroy(p->ev_bulk_done);
   delete p;
 }
@@ -202,7 +205,7 @@ int lsb_bind(lsb_plan* p, void* ws, size_t bytes) {
     // side stream of the bulk collide-stream (default priority) and the two
     // events that order it against the caller's stream
     LSB_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
-    LSB_HIP(hipEventCreateWithFlags(&p->ev_ls_done, hipEventDisableTiming));
+    LSB_HIP(hipEventCreateWithFlags(&p->ev_pop_done, hipEventDisableTiming));
     LSB_HIP(hipEventCreateWithFlags(&p->ev_bulk_done, hipEventDisableTiming));
   }
   return LSB_OK;
@@ -250,7 +253,7 @@ int lsb_init(lsb_plan* p, const double* phi0, const double* rho0, const double* 
   }
   LSB_HIP(hipGetLastError());
   LSB_HIP(hipStreamSynchronize(st));
-  LSB_HIP(hipEventRecord(p->ev_ls_done, st));
+  LSB_HIP(hipEventRecord(p->ev_pop_done, st));
   LSB_HIP(hipEventRecord(p->ev_bulk_done, st));
   p->inited = true;
   return LSB_OK;
@@ -479,12 +482,12 @@ int lsb_load_state(lsb_plan* p, const void* src, void* stream) {
   LSB_HIP(hipMemcpyAsync(p->ws + p->off_p0, s + o_phi, N * p->bytes_real, hipMemcpyDeviceToDevice, st));
   LSB_HIP(hipMemcpyAsync(p->ws + p->off_M[0], s + o_M, 10 * N * p->bytes_real, hipMemcpyDeviceToDevice, st));
   LSB_HIP(hipMemcpyAsync(p->ws + p->off_scal, s + o_scal, lsb::SC_COUNT * sizeof(double), hipMemcpyDeviceToDevice, st));
+  p->nstep = hdr[1];  // before the rebuild: the candidate flags are kept by step parity
   p->ops->rebuild(p, st);
   LSB_HIP(hipGetLastError());
   LSB_HIP(hipStreamSynchronize(st));
-  LSB_HIP(hipEventRecord(p->ev_ls_done, st));
+  LSB_HIP(hipEventRecord(p->ev_pop_done, st));
   LSB_HIP(hipEventRecord(p->ev_bulk_done, st));
-  p->nstep = hdr[1];
   p->inited = true;
   return LSB_OK;
 }

@@ -222,6 +222,8 @@ struct KArgs {
   int* counters;            // see CNT_*
   uint8_t* tile_act;        // per tile: has LS-active cells (this step)
   uint8_t* tile_act_next;   // the same after this step's classification
+  uint8_t* cand_prev;       // per tile: candidate of the previous step's classification
+  uint8_t* cand_next;       // per tile: candidate of this step's classification
   int* tile_list;           // active tiles
   int* cand_list;           // candidate tiles for classification
   int* spec_list;           // interface-adjacent cells
@@ -232,11 +234,11 @@ struct KArgs {
 
 // device scalar slots
 enum { SC_PB = 0, SC_XC0 = 1, SC_XC = 4, SC_V = 7, SC_COUNT = 16 };
-// counters
-// (counters below CNT_STEP_RESET are cleared every step; CNT_WALL is static)
-// (CNT_SPEC and CNT_TILES form one aligned 64-bit word: one atomic reserves
-// slots in both lists)
-enum { CNT_SPEC = 0, CNT_TILES = 1, CNT_CAND = 2, CNT_FLIP = 3, CNT_STEP_RESET = 4, CNT_WALL = 4, CNT_NUM = 8 };
+// counters: CNT_SPEC, CNT_TILES and CNT_FLIP are cleared before each
+// classification, CNT_CAND before each dilation, CNT_WALL is static.
+// CNT_SPEC and CNT_TILES form one aligned 64-bit word (one atomic reserves
+// slots in both lists).
+enum { CNT_SPEC = 0, CNT_TILES = 1, CNT_FLIP = 2, CNT_CAND = 3, CNT_WALL = 4, CNT_NUM = 8 };
 
 // Runtime selection from small arrays of the kernel argument block without
 // indexing it dynamically (which would copy the block to scratch memory).

@@ -59,6 +59,8 @@ struct Driver {
     a.counters = reinterpret_cast<int*>(w + p->off_cnt);
     a.tile_act = reinterpret_cast<uint8_t*>(w + (p->tcur ? p->off_tile_act2 : p->off_tile_act));
     a.tile_act_next = reinterpret_cast<uint8_t*>(w + (p->tcur ? p->off_tile_act : p->off_tile_act2));
+    a.cand_next = reinterpret_cast<uint8_t*>(w + p->off_cflag[p->nstep & 1]);
+    a.cand_prev = reinterpret_cast<uint8_t*>(w + p->off_cflag[(p->nstep + 1) & 1]);
     a.tile_list = reinterpret_cast<int*>(w + p->off_tile_list);
     a.cand_list = reinterpret_cast<int*>(w + p->off_cand_list);
     a.spec_list = reinterpret_cast<int*>(w + p->off_spec_list);
@@ -73,14 +75,20 @@ struct Driver {
     return (int)(g < 8192 ? g : 8192);
   }
 
-  // Classification of all tiles (initialisation and state reload).
+  // Classification of all tiles (initialisation and state reload), then the
+  // candidate tiles around the resulting band, recorded as those of the
+  // previous step (the next step's band collide-stream takes them).
   static void classify_all(lsb_plan* p, hipStream_t st) {
     Args a = args(p, p->cur);
-    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a, CNT_STEP_RESET);
+    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a, 0, CNT_WALL);
     k_dilate<LAT, ST><<<(p->ntiles + 255) / 256, 256, 0, st>>>(a, 1);
     k_classify<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a, 0);
     k_geometry<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
     p->tcur ^= 1;
+    Args b = args(p, p->cur);
+    b.cand_next = b.cand_prev;
+    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(b, CNT_CAND, 1);
+    k_dilate<LAT, ST><<<(p->ntiles + 255) / 256, 256, 0, st>>>(b, 0);
   }
 
   static void centroid(lsb_plan* p, int mode, hipStream_t st) {
@@ -101,7 +109,7 @@ struct Driver {
   static void init_band(lsb_plan* p, hipStream_t st) {
     Args a = args(p, p->cur);
     k_clear_tiles<LAT, ST><<<(p->ntiles + 255) / 256, 256, 0, st>>>(a);
-    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a, CNT_NUM);
+    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a, 0, CNT_NUM);
     classify_all(p, st);
     k_mark_walls<LAT, ST><<<cell_grid(p), 256, 0, st>>>(a);
     centroid(p, 0, st);
@@ -117,23 +125,25 @@ struct Driver {
 
   // One step.  Serial schedule: the collide-stream (bulk, interface, walls)
   // and then the level-set chain, all on the caller's stream st.  Overlap
-  // schedule: the caller's stream runs the collide-stream of the LS-active
-  // tiles (k_lb_band) and the interface and wall cells, then the level-set
-  // chain; the library's side stream runs the bulk collide-stream of all
-  // other cells concurrently.  Events order the two streams across steps.
+  // schedule: the library's side stream runs the bulk collide-stream of the
+  // cells outside the previous step's candidate tiles; it needs only the
+  // populations of the previous step's band, interface and wall parts and
+  // its own previous launch, so it runs concurrently with the previous
+  // step's level-set chain and with this step's band part.  The caller's
+  // stream runs the band collide-stream (candidate tiles), the interface and
+  // wall cells and the level-set chain.  Events order the two streams.
   static void step(lsb_plan* p, hipStream_t st) {
     const lsb_params& P = p->P;
     Args a = args(p, p->cur);
     const int xchunks = (P.nx + 255) / 256;
     const int rows = P.ny * P.nz;
+    // the populations of the previous step are complete (bulk part included)
+    (void)hipStreamWaitEvent(st, p->ev_bulk_done, 0);
     if (p->schedule == LSB_SCHED_OVERLAP) {
-      // bulk part (side stream): after the previous step's level-set chain
-      (void)hipStreamWaitEvent(p->side, p->ev_ls_done, 0);
+      (void)hipStreamWaitEvent(p->side, p->ev_pop_done, 0);
       timing_begin(p, p->side);
       k_lb_bulk<LAT, ST, true><<<xchunks * rows, 256, 0, p->side>>>(a, xchunks);
       timing_end(p, p->side);
-      // band part (caller's stream): after the previous step's bulk part
-      (void)hipStreamWaitEvent(st, p->ev_bulk_done, 0);
       (void)hipEventRecord(p->ev_bulk_done, p->side);
       k_lb_band<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
     } else {
@@ -141,8 +151,13 @@ struct Driver {
       k_lb_bulk<LAT, ST, false><<<xchunks * rows, 256, 0, st>>>(a, xchunks);
       timing_end(p, st);
     }
+    // candidate tiles of this step's classification (dilation of the
+    // current LS-active tiles); their flags bound the next bulk part
+    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a, CNT_CAND, 1);
+    k_dilate<LAT, ST><<<(p->ntiles + 255) / 256, 256, 0, st>>>(a, 0);
     k_lb_iface<LAT, ST><<<p->grid_cells, 256, 0, st>>>(a);
     if (p->n_wall_cells > 0) k_lb_wall<LAT, ST><<<p->grid_walls, 256, 0, st>>>(a);
+    (void)hipEventRecord(p->ev_pop_done, st);
     // a6: extension (ut ping-pong), advection
     k_ext_seed<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
     k_ext_seed_iface<LAT, ST><<<p->grid_cells, 256, 0, st>>>(a);
@@ -164,9 +179,8 @@ struct Driver {
           k_reinit_stage<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a, stage, it == P.n_reinit - 1 ? 1 : 0);
     }
     k_ls_sync<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
-    // a8: classification on the dilated band, geometry, refill
-    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a, CNT_STEP_RESET);
-    k_dilate<LAT, ST><<<(p->ntiles + 255) / 256, 256, 0, st>>>(a, 0);
+    // a8: classification on the candidate tiles, geometry, refill
+    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a, 0, CNT_CAND);
     k_classify<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a, 1);
     k_geometry<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
     k_refill<LAT, ST><<<p->grid_cells, 256, 0, st>>>(a);
@@ -174,7 +188,6 @@ struct Driver {
     p->tcur ^= 1;
     // a9: centroid and gas pressure baseline
     if (P.use_pb) centroid(p, 1, st);
-    (void)hipEventRecord(p->ev_ls_done, st);
     ++p->nstep;
   }
 
@@ -197,7 +210,7 @@ struct Driver {
   static void rebuild(lsb_plan* p, hipStream_t st) {
     Args a = args(p, p->cur);
     k_clear_tiles<LAT, ST><<<(p->ntiles + 255) / 256, 256, 0, st>>>(a);
-    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a, CNT_NUM);
+    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a, 0, CNT_NUM);
     classify_all(p, st);
     k_mark_walls<LAT, ST><<<cell_grid(p), 256, 0, st>>>(a);
   }

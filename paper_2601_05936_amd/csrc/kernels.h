@@ -272,10 +272,12 @@ __device__ __forceinline__ int tile_of(const Args& a, int x, int y, int z) {
 
 // Bulk part of the collide-stream: one thread per cell, 256-cell blocks along
 // x, XCD-aware block order.  Skips interface-adjacent cells (k_lb_iface) and
-// wall-adjacent cells (k_lb_wall).  With SPLIT it also skips the cells of
-// LS-active tiles (k_lb_band): none of its cells is then LS-active, it
-// writes no moments and may run concurrently with the level-set kernels of
-// the same step.
+// wall-adjacent cells (k_lb_wall).  With SPLIT it also skips the candidate
+// tiles of the previous step's classification (k_lb_band takes them): they
+// hold every LS-active cell and, by more than one lattice link, every cell
+// the interface or refill kernels update, so this part writes no moments and
+// reads nothing the level-set chain writes except the LS-active bit of tags
+// (masked).  It may run concurrently with the level-set chain.
 template <int LAT, int ST, bool SPLIT>
 __global__ __launch_bounds__(256) void k_lb_bulk(const typename Step<LAT, ST>::Args a, int xchunks) {
   const unsigned b = remap_xcd(blockIdx.x, gridDim.x);
@@ -285,17 +287,19 @@ __global__ __launch_bounds__(256) void k_lb_bulk(const typename Step<LAT, ST>::A
   const int y = row % a.ny;
   const int z = row / a.ny;
   const int c = row * a.nx + x;
-  if (SPLIT && a.tile_act[tile_of<Step<LAT, ST>::D>(a, x, y, z)]) return;
+  if (SPLIT && a.cand_prev[tile_of<Step<LAT, ST>::D>(a, x, y, z)]) return;
   const uint8_t t = a.tag[c];
   if (t & (T_SPEC | T_WALL)) return;
   fast_cell<LAT, ST>(a, c, x, y, z, SPLIT ? (uint8_t)(t & ~T_ACT) : t);
 }
 
-// Band part of the collide-stream: the non-interface cells of the LS-active
-// tiles (their moments feed the level-set kernels of the same step).
+// Band part of the collide-stream: the non-interface, non-wall cells of the
+// candidate tiles of the previous step's classification (a superset of the
+// LS-active tiles; the moments of LS-active cells feed the level-set kernels
+// of the same step).
 template <int LAT, int ST>
 __global__ __launch_bounds__(256) void k_lb_band(const typename Step<LAT, ST>::Args a) {
-  for_tile_cells<Step<LAT, ST>::D>(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
+  for_tile_cells<Step<LAT, ST>::D>(a, a.cand_list, a.counters[CNT_CAND], [&](int c, int x, int y, int z) {
     const uint8_t t = a.tag[c];
     if (t & (T_SPEC | T_WALL)) return;
     fast_cell<LAT, ST>(a, c, x, y, z, t);
@@ -493,11 +497,53 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
     for (int m = 0; m < 10; ++m) own.M[m] = a.M[(size_t)m * N + c];
 #pragma unroll
     for (int m = 0; m < 4; ++m) own.G[m] = a.G[(size_t)m * N + c];
+    // pass 1 (directions unrolled, all loads issued together): plain
+    // streaming from own-phase sources; cut links and links through a wall
+    // face are marked
+    unsigned cut = 0u, wall = 0u;
+    {
+      using L = typename S::L;
+      using T = typename S::T;
+      const R is = a.inv_scale;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const int sx = lb_coord(x - L::cx(i), a.nx, a.per[0]);
+        const int sy = lb_coord(y - L::cy(i), a.ny, a.per[1]);
+        const int sz = lb_coord(z - L::cz(i), a.nz, a.per[2]);
+        if ((sx | sy | sz) < 0) {
+          wall |= 1u << i;
+          continue;
+        }
+        const int sc = (sz * a.ny + sy) * a.nx + sx;
+        const uint8_t ts = a.tag[sc];
+        const T v = a.A[(size_t)i * N + sc];
+        if ((ts & T_GAS) != k) {
+          cut |= 1u << i;
+          continue;
+        }
+        fl[i * 256 + threadIdx.x] = C::dec(v, (R)wgt<LAT>(i), is);
+      }
+    }
+    // pass 2: interface bounce-back on the cut links
+    while (cut) {
+      const int i = __ffs(cut) - 1;
+      cut &= cut - 1u;
+      const int sx = lb_coord(x - tab<LAT>.cx[i], a.nx, a.per[0]);
+      const int sy = lb_coord(y - tab<LAT>.cy[i], a.ny, a.per[1]);
+      const int sz = lb_coord(z - tab<LAT>.cz[i], a.nz, a.per[2]);
+      const int sc = (sz * a.ny + sy) * a.nx + sx;  // in the domain (not a wall link)
+      fl[i * 256 + threadIdx.x] = iface_pull<LAT, ST>(a, own, c, x, y, z, sc, i, k);
+    }
+    // pass 3: links through a wall face
+    while (wall) {
+      const int i = __ffs(wall) - 1;
+      wall &= wall - 1u;
+      fl[i * 256 + threadIdx.x] = pull_general<LAT, ST>(a, own, c, x, y, z, i, k);
+    }
     R rp = 0, m0 = 0, m1 = 0, m2 = 0;
 #pragma unroll 1
     for (int i = 0; i < Q; ++i) {
-      const R f = pull_general<LAT, ST>(a, own, c, x, y, z, i, k);
-      fl[i * 256 + threadIdx.x] = f;
+      const R f = fl[i * 256 + threadIdx.x];
       rp += f;
       m0 += (R)tab<LAT>.cx[i] * f;
       m1 += (R)tab<LAT>.cy[i] * f;
@@ -799,8 +845,8 @@ __global__ __launch_bounds__(256) void k_ls_sync(const typename Step<LAT, ST>::A
 // a8: classification.  Candidate tiles = active tiles dilated by one tile.
 // ---------------------------------------------------------------------------
 template <int LAT, int ST>
-__global__ __launch_bounds__(256) void k_reset_counters(const typename Step<LAT, ST>::Args a, int n) {
-  if ((int)threadIdx.x < n) a.counters[threadIdx.x] = 0;
+__global__ __launch_bounds__(256) void k_reset_counters(const typename Step<LAT, ST>::Args a, int first, int n) {
+  if ((int)threadIdx.x < n) a.counters[first + threadIdx.x] = 0;
 }
 
 template <int LAT, int ST>
@@ -836,7 +882,10 @@ __global__ __launch_bounds__(256) void k_dilate(const typename Step<LAT, ST>::Ar
   }
   const int slot = wave_append(&a.counters[CNT_CAND], cand);
   if (cand) a.cand_list[slot] = t;
-  else if (t < a.ntiles) a.tile_act_next[t] = 0;  // candidates get their flag from k_classify
+  if (t < a.ntiles) {
+    a.cand_next[t] = cand ? 1 : 0;
+    if (!cand) a.tile_act_next[t] = 0;  // candidates get their flag from k_classify
+  }
 }
 
 template <int LAT, int ST>

@@ -56,10 +56,11 @@ struct lsb_plan {
   size_t off_scal, off_cnt, off_tile_act, off_tile_list, off_cand_list, off_spec_list, off_flip_list, off_partial;
   size_t off_wall_list;
   size_t off_tile_act2;    // second tile-activity buffer
+  size_t off_cflag[2];     // candidate-tile flags, by step parity
   int tcur = 0;            // which tile-activity buffer holds this step's flags
   int schedule = 0;        // LSB_SCHED_*
   hipStream_t side = nullptr;        // library-owned stream of the bulk collide-stream
-  hipEvent_t ev_ls_done = nullptr;   // level-set chain of the last step finished
+  hipEvent_t ev_pop_done = nullptr;  // band, interface and wall collide-stream of the last step finished
   hipEvent_t ev_bulk_done = nullptr; // bulk collide-stream of the last step finished
   long n_wall_cells = 0;   // bound on wall-adjacent cells (static)
   int grid_walls = 1;
