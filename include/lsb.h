@@ -166,6 +166,48 @@ int lsb_get_counts(lsb_plan* plan, int* counts, void* stream);
 int lsb_set_kernel_timing(lsb_plan* plan, int enable);
 int lsb_get_kernel_timing(lsb_plan* plan, double* total_ms, long* launches);
 
+/* ---------------------------------------------------------------------------
+ * Reverse mode (differentiation pattern; not in the paper).  Gradient of the
+ * gas centroid after n steps with respect to the surface tension sigma and
+ * the initial level set phi0, under the decisions the forward steps took
+ * (phase and band tags, cut and wall links, Bouzidi branch, upwind
+ * directions, the clamp at +-B, refill events).  D2Q9 with LSB_F64 or
+ * LSB_F32 storage only; the reinitialisation is not differentiated
+ * (n_reinit must be 0).  Adjoints are FP64.
+ *
+ * Use with time checkpoints (lsb_save_state every K steps of the forward
+ * run).  Then, for each segment from the last to the first:
+ * lsb_load_state(checkpoint), lsb_adjoint_record(K), for the last segment
+ * lsb_adjoint_seed_centroid, then lsb_adjoint_reverse.  Finally
+ * lsb_adjoint_initial.  Recording re-runs the forward kernels, which are
+ * deterministic, so the recomputed decisions are the forward run's.
+ *
+ * lsb_adjoint_workspace_bytes: device bytes for segments of up to
+ *   max_segment_steps steps (snapshots of every step's state and
+ *   intermediates, and the adjoint arrays); the caller allocates them.
+ * lsb_adjoint_bind: hands over that workspace (LSB_ENOMEM if too small).
+ * lsb_adjoint_record: runs nsteps forward steps from the current state
+ *   (serial schedule), recording them; the plan's state advances.
+ * lsb_adjoint_seed_centroid: loss L = gas centroid coordinate `axis` (0 = x,
+ *   1 = y) of the last recorded state, with the smoothed Heaviside of the
+ *   integrals; clears all adjoints and seeds dL/dphi.
+ * lsb_adjoint_reverse: reverses the recorded segment (synchronises the
+ *   stream); the adjoint of its first state is kept for the previous segment.
+ * lsb_adjoint_initial: after the segment that starts at step 0, reverses the
+ *   initialisation (clamp of phi0 to +-B, initial geometry, hydrostatic
+ *   initial density about the initial centroid unless rho0 was given) and
+ *   writes dL/dphi0 (device array of N doubles; phi0 and u0 are the device
+ *   arrays passed to lsb_init, u0 may be NULL) and dL/dsigma (host double).
+ * LSB_EINVAL for an unsupported lattice, storage or parameter, LSB_ESTATE
+ * for a wrong call order. */
+int lsb_adjoint_workspace_bytes(const lsb_plan* plan, int max_segment_steps, size_t* bytes);
+int lsb_adjoint_bind(lsb_plan* plan, void* device_workspace, size_t bytes, int max_segment_steps);
+int lsb_adjoint_record(lsb_plan* plan, int nsteps, void* stream);
+int lsb_adjoint_seed_centroid(lsb_plan* plan, int axis, void* stream);
+int lsb_adjoint_reverse(lsb_plan* plan, void* stream);
+int lsb_adjoint_initial(lsb_plan* plan, const double* phi0, const double* u0, int rho0_given, double* dL_dphi0,
+                        double* dL_dsigma, void* stream);
+
 /* Step schedule.  SERIAL: every kernel of a step runs on the caller's
  * stream.  OVERLAP: the collide-stream of the cells outside the LS-active
  * tiles runs on a library-owned stream (default priority), concurrently

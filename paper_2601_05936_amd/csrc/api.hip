@@ -129,7 +129,10 @@ int lsb_create(const lsb_params* P, lsb_plan** out) {
   p->grid_cells = (int)std::min<long>(((long)p->N + 255) / 256, 4096);
   p->red_blocks = 512;
   switch (P->lattice) {
-    case LSB_D2Q9: p->ops = lsb::ops_d2q9(P->storage); break;
+    case LSB_D2Q9:
+      p->ops = lsb::ops_d2q9(P->storage);
+      p->adj_ops = lsb::adj_ops_d2q9(P->storage);
+      break;
     case LSB_D3Q19: p->ops = lsb::ops_d3q19(P->storage); break;
     default: p->ops = lsb::ops_d3q27(P->storage); break;
   }
@@ -536,6 +539,127 @@ int lsb_get_counts(lsb_plan* p, int* counts, void* stream) {
   counts[1] = c[lsb::CNT_TILES];
   counts[2] = c[lsb::CNT_FLIP];
   counts[3] = c[lsb::CNT_WALL];
+  return LSB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Reverse mode
+// ---------------------------------------------------------------------------
+static void adj_layout(const lsb_plan* p, int max_steps, lsb::AdjState& s, size_t* total) {
+  const size_t N = (size_t)p->N, rb = p->bytes_real;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  s.s_A = take((size_t)p->Q * N * p->bytes_pop);
+  s.s_M = take(10 * N * rb);
+  s.s_phi = take(N * rb);
+  s.s_G = take(4 * N * rb);
+  s.s_tag = take(N);
+  s.s_scal = take(lsb::SC_COUNT * sizeof(double));
+  s.s_Mn = take(10 * N * rb);
+  s.s_ut = take((size_t)(p->P.n_ext + 1) * 3 * N * rb);
+  s.s_s1 = take(N * rb);
+  s.s_s2 = take(N * rb);
+  s.stride = o;
+  o = 0;
+  s.o_snap = take((size_t)(max_steps + 1) * s.stride);
+  for (int r = 0; r < 2; ++r) {
+    s.o_Abar[r] = take(9 * N * sizeof(double));
+    s.o_Mbar[r] = take(10 * N * sizeof(double));
+    s.o_phibar[r] = take(N * sizeof(double));
+    s.o_Gbar[r] = take(4 * N * sizeof(double));
+    s.o_utbar[r] = take(3 * N * sizeof(double));
+  }
+  s.o_s1bar = take(N * sizeof(double));
+  s.o_s2bar = take(N * sizeof(double));
+  s.o_ytmp = take(19 * N * sizeof(double));
+  s.o_scal = take(lsb::AdjState::SC_NUM * sizeof(double));
+  s.o_partial = take(2 * lsb::AdjState::kInitBlocks * sizeof(double));
+  *total = o;
+}
+
+static int adj_check(const lsb_plan* p) {
+  if (!p) return fail(LSB_EINVAL, "null plan");
+  if (!p->adj_ops)
+    return fail(LSB_EINVAL, "the reverse mode needs the D2Q9 lattice with LSB_F64 or LSB_F32 storage");
+  if (p->P.reinit_every > 0 && p->P.n_reinit > 0)
+    return fail(LSB_EINVAL, "the reverse mode does not differentiate the reinitialisation (set n_reinit = 0)");
+  return LSB_OK;
+}
+
+int lsb_adjoint_workspace_bytes(const lsb_plan* p, int max_segment_steps, size_t* bytes) {
+  if (int r = adj_check(p)) return r;
+  if (!bytes || max_segment_steps < 1) return fail(LSB_EINVAL, "bad argument");
+  lsb::AdjState s;
+  adj_layout(p, max_segment_steps, s, bytes);
+  return LSB_OK;
+}
+
+int lsb_adjoint_bind(lsb_plan* p, void* ws, size_t bytes, int max_segment_steps) {
+  if (int r = adj_check(p)) return r;
+  if (!ws || max_segment_steps < 1) return fail(LSB_EINVAL, "bad argument");
+  size_t need = 0;
+  lsb::AdjState s;
+  adj_layout(p, max_segment_steps, s, &need);
+  if (bytes < need) return fail(LSB_ENOMEM, "adjoint workspace too small: need " + std::to_string(need) + " bytes");
+  s.ws = static_cast<char*>(ws);
+  s.bytes = bytes;
+  s.max_steps = max_segment_steps;
+  p->adj = s;
+  return LSB_OK;
+}
+
+int lsb_adjoint_record(lsb_plan* p, int nsteps, void* stream) {
+  if (int r = adj_check(p)) return r;
+  if (!p->adj.ws) return fail(LSB_ESTATE, "lsb_adjoint_record before lsb_adjoint_bind");
+  if (!p->inited) return fail(LSB_ESTATE, "lsb_adjoint_record before lsb_init");
+  if (nsteps < 1 || nsteps > p->adj.max_steps) return fail(LSB_EINVAL, "segment length out of range");
+  hipStream_t st = as_stream(stream);
+  LSB_HIP(hipStreamWaitEvent(st, p->ev_bulk_done, 0));
+  p->adj_ops->record(p, nsteps, st);
+  if (int r = check_launch()) return r;
+  return LSB_OK;
+}
+
+int lsb_adjoint_seed_centroid(lsb_plan* p, int axis, void* stream) {
+  if (int r = adj_check(p)) return r;
+  if (!p->adj.ws || p->adj.nrec < 1) return fail(LSB_ESTATE, "no recorded segment");
+  if (axis < 0 || axis > 1) return fail(LSB_EINVAL, "axis must be 0 or 1");
+  p->adj_ops->seed_centroid(p, axis, as_stream(stream));
+  if (int r = check_launch()) return r;
+  p->adj.seeded = true;
+  return LSB_OK;
+}
+
+int lsb_adjoint_reverse(lsb_plan* p, void* stream) {
+  if (int r = adj_check(p)) return r;
+  if (!p->adj.seeded || p->adj.nrec < 1) return fail(LSB_ESTATE, "lsb_adjoint_reverse before a seed and a record");
+  hipStream_t st = as_stream(stream);
+  p->adj_ops->reverse(p, st);
+  if (int r = check_launch()) return r;
+  int flag = 0;
+  LSB_HIP(hipMemcpyAsync(&flag, p->adj.ws + p->adj.o_scal + lsb::AdjState::SC_FLAG * sizeof(double), sizeof(int),
+                         hipMemcpyDeviceToHost, st));
+  LSB_HIP(hipStreamSynchronize(st));
+  if (flag) return fail(LSB_EDEVICE, "internal: reverse-mode input list overflow");
+  return LSB_OK;
+}
+
+int lsb_adjoint_initial(lsb_plan* p, const double* phi0, const double* u0, int rho0_given, double* dL_dphi0,
+                        double* dL_dsigma, void* stream) {
+  if (int r = adj_check(p)) return r;
+  if (!p->adj.seeded || p->adj.nrec < 1) return fail(LSB_ESTATE, "no reversed segment");
+  if (!phi0 || !dL_dphi0 || !dL_dsigma) return fail(LSB_EINVAL, "null argument");
+  hipStream_t st = as_stream(stream);
+  const int hydro = (p->P.init_hydrostatic && !rho0_given) ? 1 : 0;
+  p->adj_ops->initial(p, phi0, u0, hydro, dL_dphi0, st);
+  if (int r = check_launch()) return r;
+  LSB_HIP(hipMemcpyAsync(dL_dsigma, p->adj.ws + p->adj.o_scal + lsb::AdjState::SC_SIGBAR * sizeof(double),
+                         sizeof(double), hipMemcpyDeviceToHost, st));
+  LSB_HIP(hipStreamSynchronize(st));
   return LSB_OK;
 }
 

@@ -123,6 +123,12 @@ struct Driver {
     k_init_pop<LAT, ST><<<g > 0 ? g : 1, 256, 0, st>>>(b, rho0, u0, p->P.init_hydrostatic, c0, c1);
   }
 
+  // copy of a step intermediate into the snapshot slot being recorded
+  static void rec(lsb_plan* p, size_t off, const void* src, size_t bytes, hipStream_t st) {
+    char* d = p->adj.ws + p->adj.o_snap + (size_t)p->adj.rec_slot * p->adj.stride + off;
+    (void)hipMemcpyAsync(d, src, bytes, hipMemcpyDeviceToDevice, st);
+  }
+
   // One step.  Serial schedule: the collide-stream (bulk, interface, walls)
   // and then the level-set chain, all on the caller's stream st.  Overlap
   // schedule: the library's side stream runs the bulk collide-stream of the
@@ -158,19 +164,28 @@ struct Driver {
     k_lb_iface<LAT, ST><<<p->grid_cells, 256, 0, st>>>(a);
     if (p->n_wall_cells > 0) k_lb_wall<LAT, ST><<<p->grid_walls, 256, 0, st>>>(a);
     (void)hipEventRecord(p->ev_pop_done, st);
+    const bool recording = p->adj.rec_slot >= 0;
+    const size_t rb = sizeof(R), N = (size_t)p->N;
+    if (recording) rec(p, p->adj.s_Mn, a.Mn, 10 * N * rb, st);
     // a6: extension (ut ping-pong), advection
     k_ext_seed<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
     k_ext_seed_iface<LAT, ST><<<p->grid_cells, 256, 0, st>>>(a);
     R* ua = a.ut_a;
     R* ub = a.ut_b;
+    if (recording) rec(p, p->adj.s_ut, ua, 3 * N * rb, st);
     for (int it = 0; it < P.n_ext; ++it) {
       Args e = a;
       e.ut_a = ua;
       e.ut_b = ub;
       k_ext_iter<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(e);
       R* t = ua; ua = ub; ub = t;
+      if (recording) rec(p, p->adj.s_ut + (size_t)(it + 1) * 3 * N * rb, ua, 3 * N * rb, st);
     }
     for (int stage = 1; stage <= 3; ++stage) k_rk3_stage<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a, stage, ua);
+    if (recording) {
+      rec(p, p->adj.s_s1, a.s1, N * rb, st);
+      rec(p, p->adj.s_s2, a.s2, N * rb, st);
+    }
     // a7: reinitialisation
     if (P.reinit_every > 0 && P.n_reinit > 0 && ((p->nstep + 1) % P.reinit_every) == 0) {
       k_reinit_prep<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);

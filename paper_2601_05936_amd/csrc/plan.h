@@ -30,6 +30,35 @@ struct Ops {
   void (*rebuild)(lsb_plan*, hipStream_t);
 };
 
+// reverse mode (D2Q9, FP64 / FP32 state)
+struct AdjOps {
+  void (*record)(lsb_plan*, int nsteps, hipStream_t);
+  void (*seed_centroid)(lsb_plan*, int axis, hipStream_t);
+  void (*reverse)(lsb_plan*, hipStream_t);
+  void (*initial)(lsb_plan*, const double* phi0, const double* u0, int hydro, double* dphi0, hipStream_t);
+};
+const AdjOps* adj_ops_d2q9(int storage);
+
+// Reverse-mode workspace: snapshots of a recorded checkpoint segment (state
+// before each step plus the step's intermediates) and the FP64 adjoints.
+struct AdjState {
+  // slots of the FP64 scalar block
+  enum { SC_PBBAR = 0, SC_SIGBAR = 2, SC_XC0BAR = 3, SC_W = 6, SC_XC = 8, SC_V = 10, SC_SIGMA = 11, SC_FLAG = 12,
+         SC_NUM = 16 };
+  static constexpr int kInitBlocks = 256;
+  char* ws = nullptr;
+  size_t bytes = 0;
+  int max_steps = 0;
+  size_t stride = 0, o_snap = 0;  // snapshot slot size and offset of slot 0
+  size_t s_A = 0, s_M = 0, s_phi = 0, s_G = 0, s_tag = 0, s_scal = 0, s_Mn = 0, s_ut = 0, s_s1 = 0, s_s2 = 0;
+  size_t o_Abar[2] = {0, 0}, o_Mbar[2] = {0, 0}, o_phibar[2] = {0, 0}, o_Gbar[2] = {0, 0}, o_utbar[2] = {0, 0};
+  size_t o_s1bar = 0, o_s2bar = 0, o_ytmp = 0, o_scal = 0, o_partial = 0;
+  int role = 0;       // adjoint buffers holding the adjoint of the latest state
+  int nrec = 0;       // steps of the recorded segment
+  int rec_slot = -1;  // slot written by the step being recorded
+  bool seeded = false;
+};
+
 const Ops* ops_d2q9(int storage);
 const Ops* ops_d3q19(int storage);
 const Ops* ops_d3q27(int storage);
@@ -71,6 +100,8 @@ struct lsb_plan {
   bool inited = false;
   long nstep = 0;
   const lsb::Ops* ops = nullptr;
+  const lsb::AdjOps* adj_ops = nullptr;  // null where the reverse mode is not available
+  lsb::AdjState adj;
   // kernel timing
   bool timing = false;
   std::vector<hipEvent_t> ev;  // start/stop pairs

@@ -48,7 +48,9 @@ EXPORTS = [
     "lsb_create", "lsb_destroy", "lsb_workspace_bytes", "lsb_bind", "lsb_init", "lsb_step", "lsb_get_fields",
     "lsb_get_interface", "lsb_get_populations", "lsb_get_moments", "lsb_get_integrals", "lsb_state_bytes",
     "lsb_save_state", "lsb_load_state", "lsb_step_count", "lsb_get_counts", "lsb_set_kernel_timing",
-    "lsb_get_kernel_timing", "lsb_set_schedule", "lsb_last_error",
+    "lsb_get_kernel_timing", "lsb_set_schedule", "lsb_adjoint_workspace_bytes", "lsb_adjoint_bind",
+    "lsb_adjoint_record", "lsb_adjoint_seed_centroid", "lsb_adjoint_reverse", "lsb_adjoint_initial",
+    "lsb_last_error",
 ]
 SCHED_SERIAL, SCHED_OVERLAP = 0, 1
 
@@ -87,6 +89,12 @@ def load() -> C.CDLL:
     lib.lsb_set_kernel_timing.argtypes = [vp, C.c_int]
     lib.lsb_get_kernel_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_long)]
     lib.lsb_set_schedule.argtypes = [vp, C.c_int]
+    lib.lsb_adjoint_workspace_bytes.argtypes = [vp, C.c_int, sz]
+    lib.lsb_adjoint_bind.argtypes = [vp, vp, C.c_size_t, C.c_int]
+    lib.lsb_adjoint_record.argtypes = [vp, C.c_int, vp]
+    lib.lsb_adjoint_seed_centroid.argtypes = [vp, C.c_int, vp]
+    lib.lsb_adjoint_reverse.argtypes = [vp, vp]
+    lib.lsb_adjoint_initial.argtypes = [vp, vp, vp, C.c_int, vp, dp, vp]
     lib.lsb_last_error.restype = C.c_char_p
     _lib = lib
     return lib
@@ -235,6 +243,35 @@ class Sim:
         ms, n = C.c_double(), C.c_long()
         _check(self.lib.lsb_get_kernel_timing(self.h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    # -- reverse mode (D2Q9, F64/F32 storage, no reinitialisation) ---------
+    def adjoint_bind(self, max_segment_steps: int):
+        nb = C.c_size_t()
+        _check(self.lib.lsb_adjoint_workspace_bytes(self.h, int(max_segment_steps), C.byref(nb)))
+        self.adj_ws = self.torch.empty(nb.value, dtype=self.torch.uint8, device=self.device)
+        _check(self.lib.lsb_adjoint_bind(self.h, C.c_void_p(self.adj_ws.data_ptr()), nb.value, int(max_segment_steps)))
+        return self
+
+    def adjoint_record(self, nsteps: int):
+        _check(self.lib.lsb_adjoint_record(self.h, int(nsteps), self.stream()))
+
+    def adjoint_seed_centroid(self, axis: int):
+        _check(self.lib.lsb_adjoint_seed_centroid(self.h, int(axis), self.stream()))
+
+    def adjoint_reverse(self):
+        _check(self.lib.lsb_adjoint_reverse(self.h, self.stream()))
+
+    def adjoint_initial(self, phi0, u0=None, rho0_given=False):
+        """(dL/dphi0 as a float64 device tensor of N values, dL/dsigma)."""
+        t_phi = self._dev(phi0, self.N)
+        t_u = self._dev(u0, 3 * self.N)
+        out = self._out(self.N, self.torch.float64)
+        ds = C.c_double()
+        _check(self.lib.lsb_adjoint_initial(self.h, C.c_void_p(t_phi.data_ptr()),
+                                            None if t_u is None else C.c_void_p(t_u.data_ptr()),
+                                            1 if rho0_given else 0, C.c_void_p(out.data_ptr()), C.byref(ds),
+                                            self.stream()))
+        return out.view(self.shape), ds.value
 
     def state_bytes(self) -> int:
         nb = C.c_size_t()
