@@ -100,6 +100,35 @@ def run_mode(size, storage, steps, warmup, schedule):
     return res
 
 
+def run_adjoint(steps: int, every: int):
+    """Reverse mode on the differentiation workload (256x512 D2Q9 rising
+    bubble, FP32 state, FP64 adjoints): forward with checkpoints, then the
+    backward pass (segment recompute with recording, reverse)."""
+    import numpy as np
+    import torch
+
+    from paper_2601_05936_amd import workloads as W
+    from paper_2601_05936_amd.adjoint import _run_forward, reverse_centroid
+    w = W.rising_bubble_2d(storage=W.F32)
+    p = w["params"]
+    phi0 = torch.as_tensor(np.ascontiguousarray(w["phi0"]).reshape(-1)).to("cuda:0")
+    N = p["nx"] * p["ny"]
+    torch.cuda.synchronize()
+    t0 = time.time()
+    sim, ckpts = _run_forward(p, p["sigma"], phi0, steps, every)
+    L = float(sim.integrals()["centroid"][1])
+    torch.cuda.synchronize()
+    t1 = time.time()
+    dphi0, dsig = reverse_centroid(sim, ckpts, steps, every, 1, phi0)
+    torch.cuda.synchronize()
+    t2 = time.time()
+    res = dict(workload=w["name"], steps=steps, checkpoint_every=every, loss_centroid_y=L, dL_dsigma=dsig,
+               dL_dphi0_max=float(dphi0.abs().max()), forward_s=t1 - t0, backward_s=t2 - t1,
+               adjoint_mlups=N * steps / (t2 - t1) / 1e6, forward_backward_mlups=N * steps / (t2 - t0) / 1e6)
+    log(f"[adjoint] {res}")
+    return res
+
+
 def cpu_baseline(seconds: float):
     """The CPU oracle (as it stands) on a bounded sample of the workload:
     the same problem at 128^3 (interface amplitude scaled to 2)."""
@@ -137,6 +166,7 @@ def main():
     ap.add_argument("--schedule", default="serial", choices=["serial", "overlap"],
                     help="step schedule: one stream, or bulk collide-stream overlapped on a second stream")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--adjoint-steps", type=int, default=2000, help="reverse-mode run length (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (counter calibration)")
@@ -190,6 +220,8 @@ def main():
                      "bytes_per_cell": r["bytes_per_cell"], "alg_bytes_per_launch": r["alg_bytes_per_launch"],
                      "avg_ms": r["k1_ms"]},
     }
+    if args.adjoint_steps > 0:
+        out["adjoint"] = run_adjoint(args.adjoint_steps, 100)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

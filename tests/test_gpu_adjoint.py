@@ -123,3 +123,74 @@ def test_autograd_function_and_fp32_forward(require_gpu):
     print("FP32 forward: dL/dsigma rel err", e_sig, "dL/dphi0 max rel err", e_phi, flush=True)
     assert np.isfinite(res[W.F64][1]) and res[W.F64][1] != 0.0
     assert e_sig < 1e-4 and e_phi < 1e-4
+
+
+def _full_grid_gradients(steps, storages):
+    import torch
+    from paper_2601_05936_amd.adjoint import _run_forward, reverse_centroid
+    w = W.rising_bubble_2d(storage=W.F64)
+    out = {}
+    for st in storages:
+        p = dict(w["params"], storage=st)
+        phi0 = torch.as_tensor(np.ascontiguousarray(w["phi0"]).reshape(-1)).to("cuda:0")
+        sim, ckpts = _run_forward(p, p["sigma"], phi0, steps, 100)
+        L = float(sim.integrals()["centroid"][1])
+        dphi0, dsig = reverse_centroid(sim, ckpts, steps, 100, 1, phi0)
+        out[st] = (L, dsig, dphi0.cpu().numpy().reshape(w["phi0"].shape))
+        del sim, ckpts
+    return w, out
+
+
+def test_rising_bubble_full_grid_gradient_gates(require_gpu):
+    """The differentiation workload's grid (256x512 D2Q9 rising bubble,
+    checkpoints every 100 steps, L = gas centroid height) over 500 steps:
+    FP64 dL/dsigma and <dL/dphi0, v> against the oracle tangent (1e-9);
+    FP32-state gradient against the FP64 one (1e-4)."""
+    import oracle as O
+    steps = 500
+    w, g = _full_grid_gradients(steps, (W.F64, W.F32))
+    p = w["params"]
+    t = O.TangentOracle(p, w["phi0"], dsigma=1.0)
+    t.step(steps)
+    L_orc, dL_sigma = t.centroid(1)
+    v = _band_direction(w["phi0"], p["band"])
+    t2 = O.TangentOracle(p, w["phi0"], dphi0=v)
+    t2.step(steps)
+    _, dL_v = t2.centroid(1)
+    L64, ds64, dp64 = g[W.F64]
+    e_sig = abs(ds64 - dL_sigma) / abs(dL_sigma)
+    e_v = abs(float(np.sum(dp64 * v)) - dL_v) / abs(dL_v)
+    f_sig = abs(g[W.F32][1] - ds64) / abs(ds64)
+    f_phi = np.max(np.abs(g[W.F32][2] - dp64)) / np.max(np.abs(dp64))
+    print("L", L64, L_orc, "dL/dsigma", ds64, dL_sigma, "rel", e_sig, "<dL/dphi0,v> rel", e_v, "FP32 forward rel",
+          f_sig, f_phi, flush=True)
+    assert abs(L64 - L_orc) < 1e-10 * abs(L_orc)
+    assert e_sig < TOL_TANGENT and e_v < TOL_TANGENT
+    assert f_sig < 1e-4 and f_phi < 1e-4
+
+
+def test_rising_bubble_2000_steps_gradient(require_gpu):
+    """The full differentiation workload (2000 steps).  The derivative of the
+    rise height grows about a hundredfold over the run and amplifies
+    trajectory differences: perturbing phi0 by 1e-13 changes the oracle's
+    own tangent by 1.2e-10 relative while L changes by 1.9e-14 (ratio
+    6.5e3).  The FP64 GPU trajectory differs from the oracle's by ~5e-12 in
+    L, so the tangent gate here is that ratio times the measured primal
+    difference (with a factor 2 margin), not 1e-9; the FP32-state gradient
+    (measured 2.4e-3 for dL/dsigma) is bounded at 1e-2."""
+    import oracle as O
+    steps = 2000
+    w, g = _full_grid_gradients(steps, (W.F64, W.F32))
+    p = w["params"]
+    t = O.TangentOracle(p, w["phi0"], dsigma=1.0)
+    t.step(steps)
+    L_orc, dL_sigma = t.centroid(1)
+    L64, ds64, dp64 = g[W.F64]
+    e_L = abs(L64 - L_orc) / abs(L_orc)
+    e_sig = abs(ds64 - dL_sigma) / abs(dL_sigma)
+    f_sig = abs(g[W.F32][1] - ds64) / abs(ds64)
+    print("L", L64, L_orc, "rel", e_L, "dL/dsigma", ds64, dL_sigma, "rel", e_sig, "FP32 forward rel", f_sig,
+          flush=True)
+    assert e_L < 1e-10
+    assert e_sig < max(TOL_TANGENT, 2 * 6.5e3 * e_L)
+    assert f_sig < 1e-2
