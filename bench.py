@@ -31,6 +31,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
+# HBM bytes per launch of the bulk collide-stream kernel from rocprofv3
+# FETCH_SIZE / WRITE_SIZE runs, scaled by a plain 4 GiB copy (fetch x2.000,
+# write x1.000); recorded in profiles/k_lb_bulk_wavy512_d3q27_f16dev_hbm_traffic.md.
+# Valid only for that kernel build, storage, schedule and size: null otherwise.
+MEASURED_TRAFFIC = {("f16dev", "serial", 512): 14676987046}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -215,7 +221,7 @@ def main():
                    "storage": head, "cells": args.size ** 3, "schedule": args.schedule},
         "modes": results,
         "roofline": {"bound": "hbm", "achieved": r["k1_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r["k1_frac"], "traffic": None,
+                     "frac": r["k1_frac"], "traffic": MEASURED_TRAFFIC.get((head, args.schedule, args.size)),
                      "kernel": "k_lb_bulk (collide-stream, bulk cells)",
                      "bytes_per_cell": r["bytes_per_cell"], "alg_bytes_per_launch": r["alg_bytes_per_launch"],
                      "avg_ms": r["k1_ms"]},
