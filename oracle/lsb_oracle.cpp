@@ -1039,6 +1039,28 @@ int orc_get_pop(void* h, double* out) {
   return 0;
 }
 
+// Populations (deviations f - w, as stored) and level set of a list of cells
+// (sampled comparisons on grids too large to copy out whole):
+// pop[i * n + k] = A_i(cells[k]), phi[k], tags[k] as in orc_get_interface.
+int orc_get_sample(void* h, const long* cells, int n, double* pop, double* phi, unsigned char* tags) {
+  Sim<double>* s = static_cast<Sim<double>*>(h);
+  for (int k = 0; k < n; ++k) {
+    const long c = cells[k];
+    if (c < 0 || c >= s->N) return -1;
+    if (pop) for (int i = 0; i < s->Q; ++i) pop[(size_t)i * n + k] = s->A[(size_t)i * s->N + c];
+    if (phi) phi[k] = s->phi[c];
+    if (tags) {
+      int x, y, z;
+      s->coords(c, x, y, z);
+      unsigned char t = s->gas[c] ? orc::TAG_GAS : 0;
+      if (s->act[c]) t |= orc::TAG_ACTIVE;
+      if (s->is_iface(c, x, y, z, s->gas)) t |= orc::TAG_IFACE;
+      tags[k] = t;
+    }
+  }
+  return 0;
+}
+
 int orc_get_fields(void* h, double* rho, double* u, double* p, unsigned char* phase) {
   Sim<double>* s = static_cast<Sim<double>*>(h);
   for (long c = 0; c < s->N; ++c) {

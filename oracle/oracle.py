@@ -81,6 +81,8 @@ def _load():
     lib.orc_nstep.restype = C.c_long
     lib.orc_nstep.argtypes = [C.c_void_p]
     lib.orc_get_pop.argtypes = [C.c_void_p, dp]
+    lib.orc_get_sample.argtypes = [C.c_void_p, C.POINTER(C.c_long), C.c_int, dp, dp, C.POINTER(C.c_ubyte)]
+    lib.orc_get_sample.restype = C.c_int
     lib.orc_get_fields.argtypes = [C.c_void_p, dp, dp, dp, ub]
     lib.orc_get_interface.argtypes = [C.c_void_p, dp, dp, dp, ub]
     lib.orc_get_moments.argtypes = [C.c_void_p, dp]
@@ -240,6 +242,17 @@ class Oracle:
         out = np.zeros(self.Q * self.N)
         self.lib.orc_get_pop(self.h, _dp(out))
         return out.reshape((self.Q,) + self.shape)
+
+    def sample(self, cells):
+        """Populations [Q, n], phi [n] and tags [n] at flat cell indices."""
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        n = len(cells)
+        pop = np.zeros(self.Q * n)
+        phi = np.zeros(n)
+        t = np.zeros(n, dtype=np.uint8)
+        assert self.lib.orc_get_sample(self.h, cells.ctypes.data_as(C.POINTER(C.c_long)), n, _dp(pop), _dp(phi),
+                                       t.ctypes.data_as(C.POINTER(C.c_ubyte))) == 0
+        return pop.reshape(self.Q, n), phi, t
 
     def fields(self):
         rho = np.zeros(self.N)
