@@ -683,11 +683,12 @@ __global__ __launch_bounds__(256) void k_ext_iter(const typename Step<LAT, ST>::
 template <class R>
 __device__ __forceinline__ R upwind5(const R* f, int c, int stride_m3, int stride_m2, int stride_m1, int stride_p1,
                                      int stride_p2, int stride_p3, bool positive) {
+  const R r60 = (R)(1.0 / 60.0);
   if (positive)
     return ((R)-2 * f[stride_m3] + (R)15 * f[stride_m2] - (R)60 * f[stride_m1] + (R)20 * f[c] + (R)30 * f[stride_p1] -
-            (R)3 * f[stride_p2]) / (R)60;
+            (R)3 * f[stride_p2]) * r60;
   return ((R)3 * f[stride_m2] - (R)30 * f[stride_m1] - (R)20 * f[c] + (R)60 * f[stride_p1] - (R)15 * f[stride_p2] +
-          (R)2 * f[stride_p3]) / (R)60;
+          (R)2 * f[stride_p3]) * r60;
 }
 
 template <class Args>
@@ -752,16 +753,20 @@ __global__ __launch_bounds__(256) void k_reinit_prep(const typename Step<LAT, ST
 
 template <class R>
 __device__ __forceinline__ R weno5(R v1, R v2, R v3, R v4, R v5) {
+  // constant divisors as multiplications (an IEEE division by a constant
+  // is a long instruction sequence)
   const R eps = (R)1e-6;
-  const R p0 = v1 / (R)3 - (R)7 * v2 / (R)6 + (R)11 * v3 / (R)6;
-  const R p1 = -v2 / (R)6 + (R)5 * v3 / (R)6 + v4 / (R)3;
-  const R p2 = v3 / (R)3 + (R)5 * v4 / (R)6 - v5 / (R)6;
+  const R r3 = (R)(1.0 / 3.0), r6 = (R)(1.0 / 6.0), c76 = (R)(7.0 / 6.0), c116 = (R)(11.0 / 6.0), c56 = (R)(5.0 / 6.0);
+  const R p0 = v1 * r3 - v2 * c76 + v3 * c116;
+  const R p1 = -v2 * r6 + v3 * c56 + v4 * r3;
+  const R p2 = v3 * r3 + v4 * c56 - v5 * r6;
   const R a0 = v1 - (R)2 * v2 + v3, b0 = v1 - (R)4 * v2 + (R)3 * v3;
   const R a1 = v2 - (R)2 * v3 + v4, b1 = v2 - v4;
   const R a2 = v3 - (R)2 * v4 + v5, b2 = (R)3 * v3 - (R)4 * v4 + v5;
-  const R s0 = (R)13 / (R)12 * a0 * a0 + (R)0.25 * b0 * b0;
-  const R s1 = (R)13 / (R)12 * a1 * a1 + (R)0.25 * b1 * b1;
-  const R s2 = (R)13 / (R)12 * a2 * a2 + (R)0.25 * b2 * b2;
+  const R c1312 = (R)(13.0 / 12.0);
+  const R s0 = c1312 * a0 * a0 + (R)0.25 * b0 * b0;
+  const R s1 = c1312 * a1 * a1 + (R)0.25 * b1 * b1;
+  const R s2 = c1312 * a2 * a2 + (R)0.25 * b2 * b2;
   const R w0 = (R)0.1 / ((eps + s0) * (eps + s0));
   const R w1 = (R)0.6 / ((eps + s1) * (eps + s1));
   const R w2 = (R)0.3 / ((eps + s2) * (eps + s2));
