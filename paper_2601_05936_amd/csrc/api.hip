@@ -154,6 +154,7 @@ int lsb_create(const lsb_params* P, lsb_plan** out) {
   for (int b = 0; b < 2; ++b) p->off_M[b] = take(10 * N * p->bytes_real);
   p->off_G = take(4 * N * p->bytes_real);
   for (int b = 0; b < 2; ++b) p->off_ut[b] = take(3 * N * p->bytes_real);
+  p->off_ext_k = take((size_t)3 * N * p->bytes_real);
   p->off_scal = take(lsb::SC_COUNT * sizeof(double));
   p->off_cnt = take(lsb::CNT_NUM * sizeof(int));
   p->off_tile_act = take((size_t)p->ntiles);

@@ -193,6 +193,9 @@ struct KArgs {
   R rho_phys[2];
   R eta[2];
   R sigma;
+  R iface_pc[2];      // rho_phys_k / 3 (pressure per LB density deviation)
+  R iface_inv2etap;   // 1 / (2 eta_p), eta_p the floored divisor of the pressure jump
+  R iface_acoef;      // -[eta] / eta_bar
   R band;
   R ext_dtau, reinit_dtau;
   R heps;
@@ -217,6 +220,7 @@ struct KArgs {
   R* G;                     // normal[3], kappa  [4][N]
   R* ut_a;
   R* ut_b;
+  R* ext_k;                 // per LS-active cell and axis: dtau v_ax towards the upwind neighbour, 0 if none
   double* scal;             // device scalars (see SC_*)
   // lists
   int* counters;            // see CNT_*

@@ -32,6 +32,16 @@ struct Driver {
       a.eta[k] = (R)(P.rho_phys[k] * nu);
     }
     a.sigma = (R)P.sigma;
+    {
+      // interface-coupling constants (pressure jump divisor floored at
+      // rho_max cs^2 / 4 = rho_max / 12, see iface_pull)
+      const double eta_bar = 0.5 * ((double)a.eta[0] + (double)a.eta[1]);
+      const double rmax = P.rho_phys[0] > P.rho_phys[1] ? P.rho_phys[0] : P.rho_phys[1];
+      const double eta_p = eta_bar > rmax / 12.0 ? eta_bar : rmax / 12.0;
+      for (int k = 0; k < 2; ++k) a.iface_pc[k] = (R)(P.rho_phys[k] / 3.0);
+      a.iface_inv2etap = (R)(1.0 / (2.0 * eta_p));
+      a.iface_acoef = (R)(-((double)a.eta[1] - (double)a.eta[0]) / eta_bar);
+    }
     a.band = (R)P.band;
     a.ext_dtau = (R)P.ext_dtau;
     a.reinit_dtau = (R)P.reinit_dtau;
@@ -55,6 +65,7 @@ struct Driver {
     a.G = reinterpret_cast<R*>(w + p->off_G);
     a.ut_a = reinterpret_cast<R*>(w + p->off_ut[0]);
     a.ut_b = reinterpret_cast<R*>(w + p->off_ut[1]);
+    a.ext_k = reinterpret_cast<R*>(w + p->off_ext_k);
     a.scal = reinterpret_cast<double*>(w + p->off_scal);
     a.counters = reinterpret_cast<int*>(w + p->off_cnt);
     a.tile_act = reinterpret_cast<uint8_t*>(w + (p->tcur ? p->off_tile_act2 : p->off_tile_act));

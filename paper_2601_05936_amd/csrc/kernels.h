@@ -368,28 +368,28 @@ __device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename S
     nn += nG[m] * nG[m];
   }
   const R nl = sqrt(nn);
-  if (nl > (R)1e-30) for (int m = 0; m < 3; ++m) nG[m] = nG[m] / nl;
+  if (nl > (R)1e-30) {
+    const R inl = (R)1 / nl;
+    for (int m = 0; m < 3; ++m) nG[m] = nG[m] * inl;
+  }
   const R kG = ((R)1 - q) * own.G[3] + q * a.G[3 * N + sc];
   const int o = 1 - k;
   const R pb = (R)a.scal[SC_PB];
-  R p_own = sel2(a.rho_phys, k) / (R)3 * own.M[0] + (k == 1 ? pb : (R)0);
-  R p_oth = sel2(a.rho_phys, o) / (R)3 * a.M[sc] + (o == 1 ? pb : (R)0);
+  R p_own = sel2(a.iface_pc, k) * own.M[0] + (k == 1 ? pb : (R)0);
+  R p_oth = sel2(a.iface_pc, o) * a.M[sc] + (o == 1 ? pb : (R)0);
   for (int m = 0; m < 3; ++m) {
     p_own = p_own + sel2(a.rho_phys, k) * ACC(a, k, m) * (R)(-cc[m]) * q;
     p_oth = p_oth + sel2(a.rho_phys, o) * ACC(a, o, m) * (R)cc[m] * ((R)1 - q);
   }
   const R p_l = (k == 0) ? p_own : p_oth;
   const R p_g = (k == 0) ? p_oth : p_own;
-  const R eta_bar = (R)0.5 * (a.eta[0] + a.eta[1]);
-  const R jeta = a.eta[1] - a.eta[0];
-  // pressure part of the normal jump: divisor floored at rho_max cs^2 / 4 so
-  // that the lagged explicit pressure feedback has gain k <= 1/2
-  const R rmax = a.rho_phys[0] > a.rho_phys[1] ? a.rho_phys[0] : a.rho_phys[1];
-  const R eta_p = eta_bar > rmax / (R)12 ? eta_bar : rmax / (R)12;
-  const R E = ((p_g - p_l) + a.sigma * kG) / ((R)2 * eta_p);
+  // pressure part of the normal jump: divisor 2 eta_p with eta_p the mean
+  // viscosity floored at rho_max cs^2 / 4, so that the lagged explicit
+  // pressure feedback has gain k <= 1/2 (constants of the argument block)
+  const R E = ((p_g - p_l) + a.sigma * kG) * a.iface_inv2etap;
   R Sb[6];
   for (int m = 0; m < 6; ++m) Sb[m] = (R)0.5 * (own.M[4 + m] + a.M[(4 + m) * N + sc]);
-  const R acoef = -jeta / eta_bar;
+  const R acoef = a.iface_acoef;
   const R Sm[3][3] = {{Sb[0], Sb[3], Sb[4]}, {Sb[3], Sb[1], Sb[5]}, {Sb[4], Sb[5], Sb[2]}};
   const R cn = (R)cc[0] * nG[0] + (R)cc[1] * nG[1] + (R)cc[2] * nG[2];
   R nAn = 0, nAc = 0;
@@ -417,7 +417,8 @@ __device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename S
     return dj + W;
   }
   const R di = C::dec(a.A[(size_t)i * N + c], w, a.inv_scale);
-  return dj / ((R)2 * q) + ((R)2 * q - (R)1) / ((R)2 * q) * di + W / ((R)2 * q);
+  const R i2q = (R)1 / ((R)2 * q);
+  return dj * i2q + ((R)2 * q - (R)1) * i2q * di + W * i2q;
 }
 
 // Incoming deviation of direction i (runtime index) for an interface-adjacent
@@ -590,11 +591,34 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
 // ---------------------------------------------------------------------------
 template <int LAT, int ST>
 __global__ __launch_bounds__(256) void k_ext_seed(const typename Step<LAT, ST>::Args a) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
   const size_t N = a.N;
-  for_tile_cells<Step<LAT, ST>::D>(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int, int, int) {
+  for_tile_cells<S::D>(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
     const uint8_t t = a.tag[c];
     if ((t & (T_ACT | T_SPEC)) != T_ACT) return;
     for (int m = 0; m < 3; ++m) a.ut_a[m * N + c] = a.Mn[(1 + m) * N + c];
+    // coefficients of the sweeps (phi and n are fixed over them): dtau v_ax
+    // with v = S(phi) n; 0 where v_ax is 0 or the upwind neighbour is beyond
+    // a wall or not LS-active
+    const R ph = a.phi[c];
+    const R sg = ph / sqrt(ph * ph + (R)1);
+    const int pos[3] = {x, y, z};
+    const int n[3] = {a.nx, a.ny, a.nz};
+    for (int ax = 0; ax < S::D; ++ax) {
+      const R v = sg * a.G[ax * N + c];
+      R kk = 0;
+      if (v != (R)0) {
+        const int sv = lb_coord(pos[ax] + (v > (R)0 ? -1 : 1), sel3(n, ax), sel3(a.per, ax));
+        if (sv >= 0) {
+          int p2[3] = {x, y, z};
+          p2[ax] = sv;
+          const int nc = (p2[2] * a.ny + p2[1]) * a.nx + p2[0];
+          if (a.tag[nc] & T_ACT) kk = a.ext_dtau * v;
+        }
+      }
+      a.ext_k[ax * N + c] = kk;
+    }
   });
 }
 
@@ -645,25 +669,20 @@ __global__ __launch_bounds__(256) void k_ext_iter(const typename Step<LAT, ST>::
     if (!(t & T_ACT)) return;
     R u[3] = {a.ut_a[c], a.ut_a[N + c], a.ut_a[2 * N + c]};
     if (!(t & T_SPEC)) {
-      const R ph = a.phi[c];
-      const R sg = ph / sqrt(ph * ph + (R)1);
       const int pos[3] = {x, y, z};
       const int n[3] = {a.nx, a.ny, a.nz};
       R out[3] = {u[0], u[1], u[2]};
       for (int ax = 0; ax < S::D; ++ax) {
-        const R v = sg * a.G[ax * N + c];
-        if (v == (R)0) continue;
-        const int dir = v > (R)0 ? -1 : 1;
-        const int sv = lb_coord(pos[ax] + dir, n[ax], sel3(a.per, ax));
-        if (sv < 0) continue;
+        const R kk = a.ext_k[ax * N + c];
+        if (kk == (R)0) continue;
+        const int sv = lb_coord(pos[ax] + (kk > (R)0 ? -1 : 1), sel3(n, ax), sel3(a.per, ax));
         int p2[3] = {x, y, z};
         p2[ax] = sv;
         const int nc = (p2[2] * a.ny + p2[1]) * a.nx + p2[0];
-        if (!(a.tag[nc] & T_ACT)) continue;
         for (int m = 0; m < 3; ++m) {
           const R un = a.ut_a[m * N + nc];
-          const R diff = v > (R)0 ? (u[m] - un) : (un - u[m]);
-          out[m] -= a.ext_dtau * v * diff;
+          const R diff = kk > (R)0 ? (u[m] - un) : (un - u[m]);
+          out[m] -= kk * diff;
         }
       }
       u[0] = out[0]; u[1] = out[1]; u[2] = out[2];

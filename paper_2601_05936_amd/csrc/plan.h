@@ -84,6 +84,7 @@ struct lsb_plan {
   size_t off_A[2], off_phi, off_s1, off_s2, off_p0, off_tag, off_aux, off_M[2], off_G, off_ut[2];
   size_t off_scal, off_cnt, off_tile_act, off_tile_list, off_cand_list, off_spec_list, off_flip_list, off_partial;
   size_t off_wall_list;
+  size_t off_ext_k;        // extension coefficients of the current step
   size_t off_tile_act2;    // second tile-activity buffer
   size_t off_cflag[2];     // candidate-tile flags, by step parity
   int tcur = 0;            // which tile-activity buffer holds this step's flags
