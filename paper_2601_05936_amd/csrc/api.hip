@@ -155,6 +155,7 @@ int lsb_create(const lsb_params* P, lsb_plan** out) {
   p->off_G = take(4 * N * p->bytes_real);
   for (int b = 0; b < 2; ++b) p->off_ut[b] = take(3 * N * p->bytes_real);
   p->off_ext_k = take((size_t)3 * N * p->bytes_real);
+  p->off_irec = take((size_t)16 * N * p->bytes_real);
   p->off_scal = take(lsb::SC_COUNT * sizeof(double));
   p->off_cnt = take(lsb::CNT_NUM * sizeof(int));
   p->off_tile_act = take((size_t)p->ntiles);
@@ -255,6 +256,7 @@ int lsb_init(lsb_plan* p, const double* phi0, const double* rho0, const double* 
       LSB_HIP(hipStreamSynchronize(st));
     }
   }
+  p->ops->pack(p, st);
   LSB_HIP(hipGetLastError());
   LSB_HIP(hipStreamSynchronize(st));
   LSB_HIP(hipEventRecord(p->ev_pop_done, st));
@@ -488,6 +490,7 @@ int lsb_load_state(lsb_plan* p, const void* src, void* stream) {
   LSB_HIP(hipMemcpyAsync(p->ws + p->off_scal, s + o_scal, lsb::SC_COUNT * sizeof(double), hipMemcpyDeviceToDevice, st));
   p->nstep = hdr[1];  // before the rebuild: the candidate flags are kept by step parity
   p->ops->rebuild(p, st);
+  p->ops->pack(p, st);
   LSB_HIP(hipGetLastError());
   LSB_HIP(hipStreamSynchronize(st));
   LSB_HIP(hipEventRecord(p->ev_pop_done, st));

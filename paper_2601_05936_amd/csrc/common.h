@@ -221,6 +221,7 @@ struct KArgs {
   R* ut_a;
   R* ut_b;
   R* ext_k;                 // per LS-active cell and axis: dtau v_ax towards the upwind neighbour, 0 if none
+  R* irec;                  // per interface-adjacent cell: phi, M[10], G[4] of the current state (16 values)
   double* scal;             // device scalars (see SC_*)
   // lists
   int* counters;            // see CNT_*

@@ -66,6 +66,7 @@ struct Driver {
     a.ut_a = reinterpret_cast<R*>(w + p->off_ut[0]);
     a.ut_b = reinterpret_cast<R*>(w + p->off_ut[1]);
     a.ext_k = reinterpret_cast<R*>(w + p->off_ext_k);
+    a.irec = reinterpret_cast<R*>(w + p->off_irec);
     a.scal = reinterpret_cast<double*>(w + p->off_scal);
     a.counters = reinterpret_cast<int*>(w + p->off_cnt);
     a.tile_act = reinterpret_cast<uint8_t*>(w + (p->tcur ? p->off_tile_act2 : p->off_tile_act));
@@ -214,6 +215,7 @@ struct Driver {
     p->tcur ^= 1;
     // a9: centroid and gas pressure baseline
     if (P.use_pb) centroid(p, 1, st);
+    pack(p, st);
     ++p->nstep;
   }
 
@@ -233,6 +235,11 @@ struct Driver {
   static void integrals_partial(lsb_plan* p, hipStream_t st) {
     k_integrals_partial<LAT, ST><<<p->red_blocks, 256, 0, st>>>(args(p, p->cur));
   }
+  // interface records of the current state (read by the next collide-stream)
+  static void pack(lsb_plan* p, hipStream_t st) {
+    k_pack_iface<LAT, ST><<<p->grid_cells, 256, 0, st>>>(args(p, p->cur));
+  }
+
   static void rebuild(lsb_plan* p, hipStream_t st) {
     Args a = args(p, p->cur);
     k_clear_tiles<LAT, ST><<<(p->ntiles + 255) / 256, 256, 0, st>>>(a);
@@ -243,7 +250,7 @@ struct Driver {
 
   static const Ops* table() {
     static const Ops ops = {init_phi, init_band, init_pop, step, fields, populations, interface, moments,
-                            integrals_partial, rebuild};
+                            integrals_partial, rebuild, pack};
     return &ops;
   }
 };

@@ -14,6 +14,8 @@
 // device-resident tile count.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace lsb {
@@ -345,6 +347,19 @@ struct OwnCell {   // level set, previous moments and geometry of the own cell
   R phi, M[10], G[4];
 };
 
+// Interface record of a cell: phi, M[0..9], G[0..3] and a pad, one aligned
+// 16-value slot per cell (written for the interface-adjacent cells only).
+template <class R>
+struct alignas(16 * sizeof(R) > 64 ? 64 : 16 * sizeof(R)) IfaceRec {
+  R v[16];
+};
+
+template <class Args>
+__device__ __forceinline__ auto load_rec(const Args& a, int c) {
+  using R = typename std::remove_pointer<decltype(a.irec)>::type;
+  return *reinterpret_cast<const IfaceRec<R>*>(a.irec + (size_t)16 * c);
+}
+
 template <int LAT, int ST>
 __device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename Step<LAT, ST>::Args& a,
                                                                   const OwnCell<typename Step<LAT, ST>::R>& own, int c,
@@ -357,14 +372,15 @@ __device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename S
   const int j = tab<LAT>.opp[i];
   const R s = a.scale;
   const R w = tw<LAT, R>(i);
-  const R px = own.phi, py = a.phi[sc];
+  const IfaceRec<R> rs = load_rec(a, sc);  // phi, M, G of the other-phase cell
+  const R px = own.phi, py = rs.v[0];
   const R q = px / (px - py);
   // interface velocity (linear interpolation of the previous moments)
   R uG[3], nG[3];
-  for (int m = 0; m < 3; ++m) uG[m] = ((R)1 - q) * own.M[1 + m] + q * a.M[(1 + m) * N + sc];
+  for (int m = 0; m < 3; ++m) uG[m] = ((R)1 - q) * own.M[1 + m] + q * rs.v[2 + m];
   R nn = 0;
   for (int m = 0; m < 3; ++m) {
-    nG[m] = ((R)1 - q) * own.G[m] + q * a.G[m * N + sc];
+    nG[m] = ((R)1 - q) * own.G[m] + q * rs.v[11 + m];
     nn += nG[m] * nG[m];
   }
   const R nl = sqrt(nn);
@@ -372,11 +388,11 @@ __device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename S
     const R inl = (R)1 / nl;
     for (int m = 0; m < 3; ++m) nG[m] = nG[m] * inl;
   }
-  const R kG = ((R)1 - q) * own.G[3] + q * a.G[3 * N + sc];
+  const R kG = ((R)1 - q) * own.G[3] + q * rs.v[14];
   const int o = 1 - k;
   const R pb = (R)a.scal[SC_PB];
   R p_own = sel2(a.iface_pc, k) * own.M[0] + (k == 1 ? pb : (R)0);
-  R p_oth = sel2(a.iface_pc, o) * a.M[sc] + (o == 1 ? pb : (R)0);
+  R p_oth = sel2(a.iface_pc, o) * rs.v[1] + (o == 1 ? pb : (R)0);
   for (int m = 0; m < 3; ++m) {
     p_own = p_own + sel2(a.rho_phys, k) * ACC(a, k, m) * (R)(-cc[m]) * q;
     p_oth = p_oth + sel2(a.rho_phys, o) * ACC(a, o, m) * (R)cc[m] * ((R)1 - q);
@@ -388,7 +404,7 @@ __device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename S
   // pressure feedback has gain k <= 1/2 (constants of the argument block)
   const R E = ((p_g - p_l) + a.sigma * kG) * a.iface_inv2etap;
   R Sb[6];
-  for (int m = 0; m < 6; ++m) Sb[m] = (R)0.5 * (own.M[4 + m] + a.M[(4 + m) * N + sc]);
+  for (int m = 0; m < 6; ++m) Sb[m] = (R)0.5 * (own.M[4 + m] + rs.v[5 + m]);
   const R acoef = a.iface_acoef;
   const R Sm[3][3] = {{Sb[0], Sb[3], Sb[4]}, {Sb[3], Sb[1], Sb[5]}, {Sb[4], Sb[5], Sb[2]}};
   const R cn = (R)cc[0] * nG[0] + (R)cc[1] * nG[1] + (R)cc[2] * nG[2];
@@ -493,11 +509,14 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
     const int k = t & T_GAS;
     const bool active = (t & T_ACT) != 0;
     OwnCell<R> own;
-    own.phi = a.phi[c];
+    {
+      const IfaceRec<R> ro = load_rec(a, c);
+      own.phi = ro.v[0];
 #pragma unroll
-    for (int m = 0; m < 10; ++m) own.M[m] = a.M[(size_t)m * N + c];
+      for (int m = 0; m < 10; ++m) own.M[m] = ro.v[1 + m];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) own.G[m] = a.G[(size_t)m * N + c];
+      for (int m = 0; m < 4; ++m) own.G[m] = ro.v[11 + m];
+    }
     // pass 1 (directions unrolled, all loads issued together): plain
     // streaming from own-phase sources; cut links and links through a wall
     // face are marked
@@ -583,6 +602,26 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
       a.Mn[8 * N + c] = fac * P4;
       a.Mn[9 * N + c] = fac * P5;
     }
+  }
+}
+
+// Interface records of the current state (phi, moments, geometry) of every
+// interface-adjacent cell, for the next step's interface coupling.
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_pack_iface(const typename Step<LAT, ST>::Args a) {
+  using R = typename Step<LAT, ST>::R;
+  const int n = a.counters[CNT_SPEC];
+  const size_t N = a.N;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+    const int c = a.spec_list[e];
+    IfaceRec<R> r;
+    r.v[0] = a.phi[c];
+#pragma unroll
+    for (int m = 0; m < 10; ++m) r.v[1 + m] = a.M[(size_t)m * N + c];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) r.v[11 + m] = a.G[(size_t)m * N + c];
+    r.v[15] = (R)0;
+    *reinterpret_cast<IfaceRec<R>*>(a.irec + (size_t)16 * c) = r;
   }
 }
 

@@ -28,6 +28,7 @@ struct Ops {
   void (*moments)(lsb_plan*, double* out, int c0, int c1, hipStream_t);
   void (*integrals_partial)(lsb_plan*, hipStream_t);
   void (*rebuild)(lsb_plan*, hipStream_t);
+  void (*pack)(lsb_plan*, hipStream_t);  // interface records of the current state
 };
 
 // reverse mode (D2Q9, FP64 / FP32 state)
@@ -85,6 +86,7 @@ struct lsb_plan {
   size_t off_scal, off_cnt, off_tile_act, off_tile_list, off_cand_list, off_spec_list, off_flip_list, off_partial;
   size_t off_wall_list;
   size_t off_ext_k;        // extension coefficients of the current step
+  size_t off_irec;         // packed interface records [N][16]
   size_t off_tile_act2;    // second tile-activity buffer
   size_t off_cflag[2];     // candidate-tile flags, by step parity
   int tcur = 0;            // which tile-activity buffer holds this step's flags
