@@ -38,6 +38,14 @@ struct Step {
 // equilibrium, w (rho - 1 + rho (9/2 (c.u)^2 - 3/2 u.u)), and flip the sign of
 // the odd parts (3 w rho c.u and the force 3 w rho c.a).
 // ---------------------------------------------------------------------------
+// Element of direction array `dir_base` (in elements from the population
+// base) at a 32-bit byte offset: the direction base is uniform, so the
+// address is a scalar base plus one 32-bit vector offset.
+template <class T>
+__device__ __forceinline__ T* pop_at(T* base, size_t dir_base, unsigned byte_off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base + dir_base) + byte_off);
+}
+
 template <int LAT, int ST>
 __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args& a, int c, int k, bool active,
                                               typename Step<LAT, ST>::R* d) {
@@ -65,6 +73,7 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
   const R ux3 = (R)3 * rho * ux, uy3 = (R)3 * rho * uy, uz3 = (R)3 * rho * uz;
   const R s = a.scale;
   const size_t N = a.N;
+  const unsigned cb = (unsigned)c * (unsigned)sizeof(T);  // byte offset of the cell in a direction array
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int j = opp<LAT>(i);
@@ -78,15 +87,15 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
     const R even = w * (rp + rho * ((R)4.5 * cu * cu - uu15));
     if (j == i) {
       const R out = omc * d[i] + om * even;
-      store_pop(&a.An[(size_t)i * N + c], C::enc(out, (R)(1.0 / wgt<LAT>(i)), s));
+      store_pop(pop_at(a.An, (size_t)i * N, cb), C::enc(out, (R)(1.0 / wgt<LAT>(i)), s));
       continue;
     }
     const R odd = w * cu3;
     const R fo = w * ca;
     const R out_i = omc * d[i] + om * (even + odd) + fo;
     const R out_j = omc * d[j] + om * (even - odd) - fo;
-    store_pop(&a.An[(size_t)i * N + c], C::enc(out_i, (R)(1.0 / wgt<LAT>(i)), s));
-    store_pop(&a.An[(size_t)j * N + c], C::enc(out_j, (R)(1.0 / wgt<LAT>(j)), s));
+    store_pop(pop_at(a.An, (size_t)i * N, cb), C::enc(out_i, (R)(1.0 / wgt<LAT>(i)), s));
+    store_pop(pop_at(a.An, (size_t)j * N, cb), C::enc(out_j, (R)(1.0 / wgt<LAT>(j)), s));
   }
   if (active) {
     // strain rate from the second moment of f - f^eq (pairs: 2 x even part)
@@ -229,11 +238,13 @@ __device__ __forceinline__ void fast_cell(const typename Step<LAT, ST>::Args& a,
   for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy) rowoff[dz][dy] = (zs[dz] * a.ny + ys[dy]) * a.nx;
+  // uniform per-direction base plus a 32-bit byte offset per lane (no 64-bit
+  // address arithmetic per load)
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const T* __restrict__ Ai = a.A + (size_t)i * a.N;
-    const unsigned off = (unsigned)(rowoff[L::cz(i) + 1][L::cy(i) + 1] + xs[L::cx(i) + 1]);
-    d[i] = C::dec(Ai[off], (R)wgt<LAT>(i), is);
+    const char* __restrict__ Ai = reinterpret_cast<const char*>(a.A + (size_t)i * a.N);
+    const unsigned off = (unsigned)(rowoff[L::cz(i) + 1][L::cy(i) + 1] + xs[L::cx(i) + 1]) * (unsigned)sizeof(T);
+    d[i] = C::dec(*reinterpret_cast<const T*>(Ai + off), (R)wgt<LAT>(i), is);
   }
   collide_store<LAT, ST>(a, c, t & T_GAS, (t & T_ACT) != 0, d);
 }
