@@ -135,6 +135,19 @@ struct Driver {
     k_init_pop<LAT, ST><<<g > 0 ? g : 1, 256, 0, st>>>(b, rho0, u0, p->P.init_hydrostatic, c0, c1);
   }
 
+  // bulk collide-stream launch (with or without the body-force terms).  The
+  // FP32-storage kernel reserves 32 KB of LDS per block it does not use: that
+  // holds it at five blocks per CU, where its 54 streams run at 5.4 TB/s
+  // against 4.7 TB/s at the full eight (measured); FP16 is fastest at eight,
+  // FP64 is held at four by its registers.
+  template <bool SPLIT>
+  static void bulk(const Args& a, bool force, int xchunks, int rows, hipStream_t st) {
+    const unsigned g = (unsigned)(xchunks * rows);
+    const size_t dyn = ST == LSB_F32 ? 32768 : 0;
+    if (force) k_lb_bulk<LAT, ST, SPLIT, true><<<g, 256, dyn, st>>>(a, xchunks);
+    else k_lb_bulk<LAT, ST, SPLIT, false><<<g, 256, dyn, st>>>(a, xchunks);
+  }
+
   // copy of a step intermediate into the snapshot slot being recorded
   static void rec(lsb_plan* p, size_t off, const void* src, size_t bytes, hipStream_t st) {
     char* d = p->adj.ws + p->adj.o_snap + (size_t)p->adj.rec_slot * p->adj.stride + off;
@@ -155,18 +168,21 @@ struct Driver {
     Args a = args(p, p->cur);
     const int xchunks = (P.nx + 255) / 256;
     const int rows = P.ny * P.nz;
+    bool force = false;  // any body acceleration: the bulk launch with force terms
+    for (int k = 0; k < 2; ++k)
+      for (int m = 0; m < 3; ++m) force = force || P.accel[k][m] != 0.0;
     // the populations of the previous step are complete (bulk part included)
     (void)hipStreamWaitEvent(st, p->ev_bulk_done, 0);
     if (p->schedule == LSB_SCHED_OVERLAP) {
       (void)hipStreamWaitEvent(p->side, p->ev_pop_done, 0);
       timing_begin(p, p->side);
-      k_lb_bulk<LAT, ST, true><<<xchunks * rows, 256, 0, p->side>>>(a, xchunks);
+      bulk<true>(a, force, xchunks, rows, p->side);
       timing_end(p, p->side);
       (void)hipEventRecord(p->ev_bulk_done, p->side);
       k_lb_band<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
     } else {
       timing_begin(p, st);
-      k_lb_bulk<LAT, ST, false><<<xchunks * rows, 256, 0, st>>>(a, xchunks);
+      bulk<false>(a, force, xchunks, rows, st);
       timing_end(p, st);
     }
     // candidate tiles of this step's classification (dilation of the

@@ -46,7 +46,8 @@ __device__ __forceinline__ T* pop_at(T* base, size_t dir_base, unsigned byte_off
   return reinterpret_cast<T*>(reinterpret_cast<char*>(base + dir_base) + byte_off);
 }
 
-template <int LAT, int ST>
+// FORCE = false drops the body-force terms (a launch for zero acceleration).
+template <int LAT, int ST, bool FORCE = true>
 __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args& a, int c, int k, bool active,
                                               typename Step<LAT, ST>::R* d) {
   using S = Step<LAT, ST>;
@@ -55,13 +56,21 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
   using L = typename S::L;
   using C = typename S::C;
   constexpr int Q = S::Q;
+  // moments from the pair sums and differences of opposite directions
   R rp = 0, m0 = 0, m1 = 0, m2 = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    rp += d[i];
-    if (L::cx(i) > 0) m0 += d[i]; else if (L::cx(i) < 0) m0 -= d[i];
-    if (L::cy(i) > 0) m1 += d[i]; else if (L::cy(i) < 0) m1 -= d[i];
-    if (L::cz(i) > 0) m2 += d[i]; else if (L::cz(i) < 0) m2 -= d[i];
+    const int j = opp<LAT>(i);
+    if (j < i) continue;
+    if (j == i) {
+      rp += d[i];
+      continue;
+    }
+    rp += d[i] + d[j];
+    const R df = d[i] - d[j];
+    if (L::cx(i) > 0) m0 += df; else if (L::cx(i) < 0) m0 -= df;
+    if (L::cy(i) > 0) m1 += df; else if (L::cy(i) < 0) m1 -= df;
+    if (L::cz(i) > 0) m2 += df; else if (L::cz(i) < 0) m2 -= df;
   }
   const R rho = (R)1 + rp;
   const R inv = (R)1 / rho;
@@ -81,9 +90,9 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
     const R w = (R)wgt<LAT>(i);
     const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
     R cu = 0, cu3 = 0, ca = 0;
-    if (cx) { cu += (R)cx * ux; cu3 += (R)cx * ux3; ca += (R)cx * fx; }
-    if (cy) { cu += (R)cy * uy; cu3 += (R)cy * uy3; ca += (R)cy * fy; }
-    if (cz) { cu += (R)cz * uz; cu3 += (R)cz * uz3; ca += (R)cz * fz; }
+    if (cx) { cu += (R)cx * ux; cu3 += (R)cx * ux3; if (FORCE) ca += (R)cx * fx; }
+    if (cy) { cu += (R)cy * uy; cu3 += (R)cy * uy3; if (FORCE) ca += (R)cy * fy; }
+    if (cz) { cu += (R)cz * uz; cu3 += (R)cz * uz3; if (FORCE) ca += (R)cz * fz; }
     const R even = w * (rp + rho * ((R)4.5 * cu * cu - uu15));
     if (j == i) {
       const R out = omc * d[i] + om * even;
@@ -91,9 +100,13 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
       continue;
     }
     const R odd = w * cu3;
-    const R fo = w * ca;
-    const R out_i = omc * d[i] + om * (even + odd) + fo;
-    const R out_j = omc * d[j] + om * (even - odd) - fo;
+    R out_i = omc * d[i] + om * (even + odd);
+    R out_j = omc * d[j] + om * (even - odd);
+    if (FORCE) {
+      const R fo = w * ca;
+      out_i = out_i + fo;
+      out_j = out_j - fo;
+    }
     store_pop(pop_at(a.An, (size_t)i * N, cb), C::enc(out_i, (R)(1.0 / wgt<LAT>(i)), s));
     store_pop(pop_at(a.An, (size_t)j * N, cb), C::enc(out_j, (R)(1.0 / wgt<LAT>(j)), s));
   }
@@ -219,7 +232,7 @@ __device__ __forceinline__ void for_tile_cells(const Args& a, const int* list, i
 // a2 for one cell with no lattice link to the other phase or through a wall:
 // branch-free gather (per-direction base pointer plus a 32-bit cell offset).
 // ---------------------------------------------------------------------------
-template <int LAT, int ST>
+template <int LAT, int ST, bool FORCE = true>
 __device__ __forceinline__ void fast_cell(const typename Step<LAT, ST>::Args& a, int c, int x, int y, int z, uint8_t t) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
@@ -246,7 +259,7 @@ __device__ __forceinline__ void fast_cell(const typename Step<LAT, ST>::Args& a,
     const unsigned off = (unsigned)(rowoff[L::cz(i) + 1][L::cy(i) + 1] + xs[L::cx(i) + 1]) * (unsigned)sizeof(T);
     d[i] = C::dec(*reinterpret_cast<const T*>(Ai + off), (R)wgt<LAT>(i), is);
   }
-  collide_store<LAT, ST>(a, c, t & T_GAS, (t & T_ACT) != 0, d);
+  collide_store<LAT, ST, FORCE>(a, c, t & T_GAS, (t & T_ACT) != 0, d);
 }
 
 // a2/a3 for a wall-adjacent cell with no lattice link to the other phase.
@@ -291,7 +304,7 @@ __device__ __forceinline__ int tile_of(const Args& a, int x, int y, int z) {
 // the interface or refill kernels update, so this part writes no moments and
 // reads nothing the level-set chain writes except the LS-active bit of tags
 // (masked).  It may run concurrently with the level-set chain.
-template <int LAT, int ST, bool SPLIT>
+template <int LAT, int ST, bool SPLIT, bool FORCE>
 __global__ __launch_bounds__(256) void k_lb_bulk(const typename Step<LAT, ST>::Args a, int xchunks) {
   const unsigned b = remap_xcd(blockIdx.x, gridDim.x);
   const int row = (int)(b / (unsigned)xchunks);
@@ -303,7 +316,7 @@ __global__ __launch_bounds__(256) void k_lb_bulk(const typename Step<LAT, ST>::A
   if (SPLIT && a.cand_prev[tile_of<Step<LAT, ST>::D>(a, x, y, z)]) return;
   const uint8_t t = a.tag[c];
   if (t & (T_SPEC | T_WALL)) return;
-  fast_cell<LAT, ST>(a, c, x, y, z, SPLIT ? (uint8_t)(t & ~T_ACT) : t);
+  fast_cell<LAT, ST, FORCE>(a, c, x, y, z, SPLIT ? (uint8_t)(t & ~T_ACT) : t);
 }
 
 // Band part of the collide-stream: the non-interface, non-wall cells of the

@@ -191,3 +191,36 @@ def test_overlap_schedule_is_bitwise_serial(require_gpu, lat, shape, g):
         np.testing.assert_array_equal(Is["phi"], Io["phi"])
         np.testing.assert_array_equal(Is["tags"], Io["tags"])
         assert ser.integrals()["pb"] == other.integrals()["pb"]
+
+
+@pytest.mark.parametrize("lat,shape", [(W.D3Q27, (264, 12, 10)), (W.D3Q19, (136, 16, 14)), (W.D2Q9, (264, 40, 1))])
+@pytest.mark.parametrize("walls", ["x", "y", "z"])
+@pytest.mark.parametrize("storage", [W.F32, W.F16DEV])
+def test_reduced_storage_wide_rows_against_oracle(require_gpu, lat, shape, walls, storage):
+    """FP32 / FP16-deviation storage on wide rows (several 256-cell chunks
+    of the bulk kernel, a ragged last one) with no-slip faces on one axis,
+    against the FP64 oracle at the precision pattern's level (FP32 1e-4,
+    FP16 5e-3 of the deviation scale); phase and interface tags exact."""
+    if lat == W.D2Q9 and walls == "z":
+        pytest.skip("two-dimensional grid")
+    w = W.seeded_bubble(7, lattice=lat, shape=shape)
+    p = dict(w["params"], storage=storage)
+    bc = [W.PERIODIC] * 6
+    ax = "xyz".index(walls)
+    bc[2 * ax] = bc[2 * ax + 1] = W.NOSLIP
+    p["bc"] = bc
+    p["wall_u"] = [[0.0] * 3 for _ in range(6)]
+    pf = dict(p, storage=W.F64)
+    O = _oracle()
+    o = O.Oracle(pf, w["phi0"], rho0=w["rho0"], u0=w["u0"])
+    s = _sim()(p).init(w["phi0"], w["rho0"], w["u0"])
+    o.step(20)
+    s.step(20)
+    Dd, Q, c, wq, _ = O.lattice(lat)
+    Ao, Ag = o.populations(), s.populations()
+    e = err(Ag, Ao, wq.reshape((Q, 1, 1, 1)))
+    To, Tg = o.interface()["tags"], s.interface()["tags"]
+    bad = int(np.sum(((To ^ Tg) & 5) != 0))
+    print(lat, shape, walls, storage, "pop", e, "tag mismatches", bad, flush=True)
+    assert bad == 0
+    assert e < (1e-4 if storage == W.F32 else 5e-3)
