@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # FETCH_SIZE / WRITE_SIZE runs, scaled by a plain 4 GiB copy (fetch x2.000,
 # write x1.000); recorded in profiles/k_lb_bulk_wavy512_d3q27_f16dev_hbm_traffic.md.
 # Valid only for that kernel build, storage, schedule and size: null otherwise.
-MEASURED_TRAFFIC = {("f16dev", "serial", 512): 14676987046}
+MEASURED_TRAFFIC = {("f16dev", "serial", 512): 14677568511}
 
 
 def log(*a):
@@ -169,8 +169,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--modes", default="f16dev,f32,f64")
-    ap.add_argument("--schedule", default="serial", choices=["serial", "overlap"],
-                    help="step schedule: one stream, or bulk collide-stream overlapped on a second stream")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "serial", "overlap"],
+                    help="step schedule: one stream, the bulk collide-stream overlapped on a second stream, or "
+                         "auto (the faster on this workload: serial for FP16-deviation, overlap for FP32 and FP64)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="reverse-mode run length (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -186,12 +187,18 @@ def main():
         sys.exit(2)
     from paper_2601_05936_amd.lsb import SCHED_OVERLAP, SCHED_SERIAL
     from paper_2601_05936_amd.workloads import F16DEV, F32, F64
-    sched = SCHED_OVERLAP if args.schedule == "overlap" else SCHED_SERIAL
+    def sched_of(mode):
+        if args.schedule == "auto":
+            return "serial" if mode == "f16dev" else "overlap"
+        return args.schedule
     names = {"f16dev": F16DEV, "f32": F32, "f64": F64}
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
     results = {}
     for m in modes:
-        results[m] = run_mode(args.size, names[m], args.steps, args.warmup, sched)
+        sm = sched_of(m)
+        results[m] = run_mode(args.size, names[m], args.steps, args.warmup,
+                              SCHED_OVERLAP if sm == "overlap" else SCHED_SERIAL)
+        results[m]["schedule"] = sm
     if args.copy_calibration > 0:
         nbytes = int(args.copy_calibration * 2**30)
         a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
@@ -218,10 +225,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"D3Q27 wavy stratified {args.size}^3, periodic x/y, no-slip z, density ratio 1000, "
                                f"viscosity ratio 50, sigma 1e-3 (throughput configuration)",
-                   "storage": head, "cells": args.size ** 3, "schedule": args.schedule},
+                   "storage": head, "cells": args.size ** 3, "schedule": sched_of(head)},
         "modes": results,
         "roofline": {"bound": "hbm", "achieved": r["k1_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r["k1_frac"], "traffic": MEASURED_TRAFFIC.get((head, args.schedule, args.size)),
+                     "frac": r["k1_frac"], "traffic": MEASURED_TRAFFIC.get((head, sched_of(head), args.size)),
                      "kernel": "k_lb_bulk (collide-stream, bulk cells)",
                      "bytes_per_cell": r["bytes_per_cell"], "alg_bytes_per_launch": r["alg_bytes_per_launch"],
                      "avg_ms": r["k1_ms"]},
