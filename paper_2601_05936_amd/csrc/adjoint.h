@@ -70,20 +70,27 @@ struct View {
   double band, ext_dtau, heps;
 };
 
-constexpr int KMAX = 192;  // inputs of one unit
+constexpr int KSLOT = 3;           // list entries per lane
+constexpr int KMAX = 64 * KSLOT;   // inputs of one unit
+static_assert(KSLOT == 3, "reverse_unit selects among three slots");
 
 // Accessor: enumeration (records the distinct inputs read) or seeded
-// evaluation (derivative 1 on the target input).
+// evaluation (derivative 1 on the target input).  All 64 lanes of a
+// wavefront evaluate the same unit, so the list of inputs is held across
+// the wave's registers: entry e sits on lane e % 64 in slot e / 64, a lookup
+// is one comparison per slot and a ballot, and in the seeded pass each lane
+// takes its own entries as targets.
 template <class R>
 struct Acc {
   const View<R>* v;
   int mode;  // 0 enumerate, 1 seeded
   int tarr;
   long tidx;
-  int n;
+  int n;     // entries recorded (uniform over the wave)
+  int lane;
   bool overflow;
-  unsigned char larr[KMAX];
-  int lidx[KMAX];
+  int sarr[KSLOT];
+  int sidx[KSLOT];
 
   __device__ double load(int arr, long idx) const {
     if (arr == AR_PB || arr == AR_SIG || arr == AR_XC0) return v->sval[arr][idx];
@@ -94,12 +101,20 @@ struct Acc {
     if ((arr == AR_S1 || arr == AR_S2) && !(v->tag0[idx] & T_ACT)) arr = AR_PHI0;
     const double x = load(arr, idx);
     if (mode == 0) {
-      bool found = false;
-      for (int e = 0; e < n; ++e)
-        if (larr[e] == arr && lidx[e] == idx) { found = true; break; }
-      if (!found) {
-        if (n < KMAX) { larr[n] = (unsigned char)arr; lidx[n] = (int)idx; ++n; }
-        else overflow = true;
+      bool hit = false;
+#pragma unroll
+      for (int k = 0; k < KSLOT; ++k) hit = hit || (lane + 64 * k < n && sarr[k] == arr && sidx[k] == (int)idx);
+      if (__ballot(hit) == 0) {
+        if (n < KMAX) {
+          if (lane == (n & 63)) {
+#pragma unroll
+            for (int k = 0; k < KSLOT; ++k)
+              if (k == (n >> 6)) { sarr[k] = arr; sidx[k] = (int)idx; }
+          }
+          ++n;
+        } else {
+          overflow = true;
+        }
       }
       return Dual(x);
     }
@@ -107,8 +122,11 @@ struct Acc {
   }
 };
 
-// Reverse of one unit: F(acc, out) evaluates the unit's forward arithmetic
-// and writes nout outputs; ybar are their adjoints.
+// Reverse of one unit by the 64 lanes of a wavefront (all lanes call it for
+// the same unit, converged): F(acc, out) evaluates the unit's forward
+// arithmetic and writes NOUT outputs; ybar are their adjoints.  One
+// enumeration pass lists the inputs, then each lane evaluates with the
+// derivative seeded on its own entries (lane l: inputs l, l + 64, ...).
 template <class R, int NOUT, class F>
 __device__ void reverse_unit(const View<R>& v, const double* ybar, F&& f, int* overflow_flag) {
   bool any = false;
@@ -118,24 +136,28 @@ __device__ void reverse_unit(const View<R>& v, const double* ybar, F&& f, int* o
   acc.v = &v;
   acc.mode = 0;
   acc.n = 0;
+  acc.lane = (int)(threadIdx.x & 63u);
   acc.overflow = false;
   acc.tarr = -1;
   acc.tidx = -1;
+  for (int k = 0; k < KSLOT; ++k) acc.sarr[k] = acc.sidx[k] = -1;
   Dual out[NOUT];
   f(acc, out);
-  if (acc.overflow) atomicOr(overflow_flag, 1);
+  if (acc.overflow && acc.lane == 0) atomicOr(overflow_flag, 1);
   const int nin = acc.n;
   acc.mode = 1;
-  for (int e = 0; e < nin; ++e) {
-    acc.tarr = acc.larr[e];
-    acc.tidx = acc.lidx[e];
+  for (int k = 0; k * 64 < nin; ++k) {
+    const bool mine = acc.lane + 64 * k < nin;
+    const int a = k == 0 ? acc.sarr[0] : (k == 1 ? acc.sarr[1] : acc.sarr[KSLOT - 1]);
+    const int i = k == 0 ? acc.sidx[0] : (k == 1 ? acc.sidx[1] : acc.sidx[KSLOT - 1]);
+    acc.tarr = mine ? a : -1;
+    acc.tidx = mine ? i : -1;
     f(acc, out);
     double g = 0.0;
     for (int j = 0; j < NOUT; ++j) g += ybar[j] * out[j].d;
-    if (g != 0.0) {
-      const int arr = acc.tarr;
-      const long idx = (arr == AR_PB || arr == AR_SIG) ? 0 : acc.tidx;
-      atomicAdd(&v.bar[arr][idx], g);
+    if (mine && g != 0.0) {
+      const long idx = (a == AR_PB || a == AR_SIG) ? 0 : i;
+      atomicAdd(&v.bar[a][idx], g);
     }
   }
 }
@@ -270,17 +292,11 @@ __device__ Dual pull(Acc<R>& A, int c, int x, int y, int i, int k, bool spec) {
   return A.get(AR_AIN, i * N + sc);
 }
 
-// collide-stream of cell c: out[0..8] populations (deviations) of step
-// n + 1, out[9..18] the moments (rho - 1, u, S) written on LS-active cells
-template <class R>
-__device__ void cell_collide(Acc<R>& A, int c, Dual* out) {
-  const View<R>& v = *A.v;
-  const int x = c % v.nx, y = c / v.nx;
-  const uint8_t t = v.tag0[c];
-  const int k = t & T_GAS;
-  const bool spec = (t & T_SPEC) != 0;
-  Dual f[Q9];
-  for (int i = 0; i < Q9; ++i) f[i] = pull(A, c, x, y, i, k, spec);
+// BGK collision with body force of the incoming deviations f of a cell of
+// phase k: out[0..8] populations of step n + 1, out[9..18] the moments
+// (rho - 1, u, S) written on LS-active cells
+template <class View_>
+__device__ void collision(const View_& v, int k, const Dual* f, Dual* out) {
   Dual rp(0.0), m0(0.0), m1(0.0);
   for (int i = 0; i < Q9; ++i) {
     rp += f[i];
@@ -316,6 +332,20 @@ __device__ void cell_collide(Acc<R>& A, int c, Dual* out) {
   out[16] = fac * P3;
   out[17] = Dual(0.0);
   out[18] = Dual(0.0);
+}
+
+// collide-stream of cell c (incoming populations by streaming, wall or
+// interface bounce-back, then the collision)
+template <class R>
+__device__ void cell_collide(Acc<R>& A, int c, Dual* out) {
+  const View<R>& v = *A.v;
+  const int x = c % v.nx, y = c / v.nx;
+  const uint8_t t = v.tag0[c];
+  const int k = t & T_GAS;
+  const bool spec = (t & T_SPEC) != 0;
+  Dual f[Q9];
+  for (int i = 0; i < Q9; ++i) f[i] = pull(A, c, x, y, i, k, spec);
+  collision(v, k, f, out);
 }
 
 // extension seed at an interface-adjacent cell: mean over the cut links of
@@ -583,6 +613,32 @@ __device__ inline double heaviside_prime(double phi, double eps) {
 // ---------------------------------------------------------------------------
 #define ADJ_FOR_CELLS(v) for (int c = blockIdx.x * 256 + threadIdx.x; c < (v).N; c += gridDim.x * 256)
 
+// Cells whose reverse is spread over a wavefront.  Wave w tests the 64 cells
+// w, w + nchunks, w + 2 nchunks, ... (interleaved, so the band's cells spread
+// evenly over the waves): `want(c)` runs once per cell on its own lane (it
+// may also do a cell's cheap pass-through work), then `body(c)` runs with all
+// 64 lanes for every wanted cell.  Launch with a grid of unit_blocks(N).
+template <class P, class B>
+__device__ void for_units(long N, P&& want, B&& body) {
+  const long nchunks = (N + 63) >> 6;
+  const long lane = threadIdx.x & 63u;
+  const long nw = (long)gridDim.x * 4;
+  for (long w = ((long)blockIdx.x * 256 + threadIdx.x) >> 6; w < nchunks; w += nw) {
+    const long c = w + lane * nchunks;
+    const bool on = c < N && want((int)c);
+    unsigned long long m = __ballot(on);
+    while (m) {
+      const int b = __builtin_ctzll(m);
+      m &= m - 1;
+      body((int)(w + (long)b * nchunks));
+    }
+  }
+}
+__host__ __device__ inline int unit_blocks(long N) {
+  const long g = (((N + 63) >> 6) + 3) >> 2;
+  return (int)(g < 65536 ? g : 65536);
+}
+
 // d(centroid_axis)/d phi, times a weight: bar[c] += s * H'(phi_c) (x_c - xc) / V
 template <class R>
 __global__ __launch_bounds__(256) void k_centroid_adj(const R* phi, double* bar, int nx, int N, double eps,
@@ -620,90 +676,142 @@ __global__ __launch_bounds__(256) void k_refill_take(View<R> v, double* ytmp) {
 template <class R>
 __global__ __launch_bounds__(256) void k_refill_adj(View<R> v, const double* ytmp, int* overflow) {
   const long N = v.N;
-  ADJ_FOR_CELLS(v) {
-    const uint8_t t1 = v.tag1[c];
-    if (((t1 & T_GAS) != 0) == ((t1 & T_OLDGAS) != 0)) continue;
-    double yb[19];
-    for (int m = 0; m < 19; ++m) yb[m] = ytmp[m * N + c];
-    reverse_unit<R, 19>(v, yb, [&](Acc<R>& A, Dual* out) { refill(A, c, out); }, overflow);
-  }
+  for_units(
+      N,
+      [&](int c) {
+        const uint8_t t1 = v.tag1[c];
+        return ((t1 & T_GAS) != 0) != ((t1 & T_OLDGAS) != 0);
+      },
+      [&](int c) {
+        double yb[19];
+        for (int m = 0; m < 19; ++m) yb[m] = ytmp[m * N + c];
+        reverse_unit<R, 19>(v, yb, [&](Acc<R>& A, Dual* out) { refill(A, c, out); }, overflow);
+      });
 }
 
 // geometry of the LS-active cells of `tags` from the level set `arr`
 template <class R>
 __global__ __launch_bounds__(256) void k_geometry_adj(View<R> v, int use_tag1, int arr, const double* gbar, int* overflow) {
   const long N = v.N;
-  ADJ_FOR_CELLS(v) {
-    const uint8_t t = use_tag1 ? v.tag1[c] : v.tag0[c];
-    if (!(t & T_ACT)) continue;
-    double yb[4];
-    for (int m = 0; m < 4; ++m) yb[m] = gbar[m * N + c];
-    reverse_unit<R, 4>(v, yb, [&](Acc<R>& A, Dual* out) { geometry(A, c, arr, out); }, overflow);
-  }
+  for_units(
+      N, [&](int c) { return ((use_tag1 ? v.tag1[c] : v.tag0[c]) & T_ACT) != 0; },
+      [&](int c) {
+        double yb[4];
+        for (int m = 0; m < 4; ++m) yb[m] = gbar[m * N + c];
+        reverse_unit<R, 4>(v, yb, [&](Acc<R>& A, Dual* out) { geometry(A, c, arr, out); }, overflow);
+      });
 }
 
 // TVD-RK3 stage (3, 2 or 1): output adjoint obar; cells outside the band
-// of step n pass phi through (stage 3 only)
+// of step n pass phi through (stage 3 only; atomic, since band cells whose
+// stencils reach such a cell add into the same entry)
 template <class R>
 __global__ __launch_bounds__(256) void k_rk_adj(View<R> v, int stage, const double* obar, int* overflow) {
-  ADJ_FOR_CELLS(v) {
-    if (!(v.tag0[c] & T_ACT)) {
-      if (stage == 3) v.bar[AR_PHI0][c] += obar[c];
-      continue;
-    }
-    double yb[1] = {obar[c]};
-    reverse_unit<R, 1>(v, yb, [&](Acc<R>& A, Dual* out) { rk_stage(A, c, stage, out); }, overflow);
-  }
+  for_units(
+      v.N,
+      [&](int c) {
+        const bool act = (v.tag0[c] & T_ACT) != 0;
+        if (!act && stage == 3) atomicAdd(&v.bar[AR_PHI0][c], obar[c]);
+        return act;
+      },
+      [&](int c) {
+        double yb[1] = {obar[c]};
+        reverse_unit<R, 1>(v, yb, [&](Acc<R>& A, Dual* out) { rk_stage(A, c, stage, out); }, overflow);
+      });
 }
 
 // extension sweep: adjoint of the sweep's output (AR_UTOUT) into the
-// previous sweep's velocity (AR_UT), phi_n and G_n
+// previous sweep's velocity (AR_UT), phi_n and G_n; seeded cells hold
+// their velocity
 template <class R>
 __global__ __launch_bounds__(256) void k_sweep_adj(View<R> v, int* overflow) {
   const long N = v.N;
-  ADJ_FOR_CELLS(v) {
-    const uint8_t t = v.tag0[c];
-    if (!(t & T_ACT)) continue;
-    double yb[3];
-    for (int m = 0; m < 3; ++m) yb[m] = v.bar[AR_UTOUT][m * N + c];
-    if (t & T_SPEC) {
-      for (int m = 0; m < 3; ++m) atomicAdd(&v.bar[AR_UT][m * N + c], yb[m]);
-      continue;
-    }
-    reverse_unit<R, 3>(v, yb, [&](Acc<R>& A, Dual* out) { ext_sweep(A, c, out); }, overflow);
-  }
+  for_units(
+      N,
+      [&](int c) {
+        const uint8_t t = v.tag0[c];
+        if ((t & T_ACT) && (t & T_SPEC))
+          for (int m = 0; m < 3; ++m) atomicAdd(&v.bar[AR_UT][m * N + c], v.bar[AR_UTOUT][m * N + c]);
+        return (t & T_ACT) && !(t & T_SPEC);
+      },
+      [&](int c) {
+        double yb[3];
+        for (int m = 0; m < 3; ++m) yb[m] = v.bar[AR_UTOUT][m * N + c];
+        reverse_unit<R, 3>(v, yb, [&](Acc<R>& A, Dual* out) { ext_sweep(A, c, out); }, overflow);
+      });
 }
 
 // extension seed: adjoint of the seeded velocity (AR_UTOUT) into the
-// collide-stream moments and phi_n
+// collide-stream moments and phi_n; away from the interface the seed is the
+// cell's own velocity moment
 template <class R>
 __global__ __launch_bounds__(256) void k_seed_adj(View<R> v, int* overflow) {
   const long N = v.N;
+  for_units(
+      N,
+      [&](int c) {
+        const uint8_t t = v.tag0[c];
+        if ((t & T_ACT) && !(t & T_SPEC))
+          for (int m = 0; m < 3; ++m) atomicAdd(&v.bar[AR_MNEW][(1 + m) * N + c], v.bar[AR_UTOUT][m * N + c]);
+        return (t & T_ACT) && (t & T_SPEC);
+      },
+      [&](int c) {
+        double yb[3];
+        for (int m = 0; m < 3; ++m) yb[m] = v.bar[AR_UTOUT][m * N + c];
+        reverse_unit<R, 3>(v, yb, [&](Acc<R>& A, Dual* out) { seed_iface(A, c, out); }, overflow);
+      });
+}
+
+// collide-stream, plain streaming cells (one thread per cell): the inputs
+// are the nine pulled populations
+template <class R>
+__global__ __launch_bounds__(256) void k_collide_adj_plain(View<R> v) {
+  const long N = v.N;
   ADJ_FOR_CELLS(v) {
     const uint8_t t = v.tag0[c];
-    if (!(t & T_ACT)) continue;
-    double yb[3];
-    for (int m = 0; m < 3; ++m) yb[m] = v.bar[AR_UTOUT][m * N + c];
-    if (!(t & T_SPEC)) {
-      for (int m = 0; m < 3; ++m) atomicAdd(&v.bar[AR_MNEW][(1 + m) * N + c], yb[m]);
-      continue;
+    if (t & (T_SPEC | T_WALL)) continue;
+    double yb[19];
+    for (int i = 0; i < Q9; ++i) yb[i] = v.bar[AR_ANEW][i * N + c];
+    const bool active = (t & T_ACT) != 0;
+    for (int m = 0; m < 10; ++m) yb[9 + m] = active ? v.bar[AR_MNEW][m * N + c] : 0.0;
+    bool any = false;
+    for (int j = 0; j < 19; ++j) any = any || yb[j] != 0.0;
+    if (!any) continue;
+    const int x = c % v.nx, y = c / v.nx, k = t & T_GAS;
+    long src[Q9];
+    double f0[Q9];
+    for (int i = 0; i < Q9; ++i) {
+      const int sx = coord_lb(x - L9::cx(i), v.nx, v.per[0]);
+      const int sy = coord_lb(y - L9::cy(i), v.ny, v.per[1]);
+      src[i] = (long)i * N + (long)sy * v.nx + sx;
+      f0[i] = (double)v.val[AR_AIN][src[i]];
     }
-    reverse_unit<R, 3>(v, yb, [&](Acc<R>& A, Dual* out) { seed_iface(A, c, out); }, overflow);
+    for (int e = 0; e < Q9; ++e) {
+      Dual f[Q9], out[19];
+      for (int i = 0; i < Q9; ++i) f[i] = Dual(f0[i], i == e ? 1.0 : 0.0);
+      collision(v, k, f, out);
+      double g = 0.0;
+      for (int j = 0; j < 19; ++j) g += yb[j] * out[j].d;
+      if (g != 0.0) atomicAdd(&v.bar[AR_AIN][src[e]], g);
+    }
   }
 }
 
-// collide-stream: adjoint of the populations of step n + 1 and (on LS-active
+// collide-stream, interface- and wall-adjacent cells (one cell per
+// wavefront): adjoint of the populations of step n + 1 and (on LS-active
 // cells) of the moments into the inputs of step n
 template <class R>
 __global__ __launch_bounds__(256) void k_collide_adj(View<R> v, int* overflow) {
   const long N = v.N;
-  ADJ_FOR_CELLS(v) {
-    double yb[19];
-    for (int i = 0; i < Q9; ++i) yb[i] = v.bar[AR_ANEW][i * N + c];
-    const bool active = (v.tag0[c] & T_ACT) != 0;
-    for (int m = 0; m < 10; ++m) yb[9 + m] = active ? v.bar[AR_MNEW][m * N + c] : 0.0;
-    reverse_unit<R, 19>(v, yb, [&](Acc<R>& A, Dual* out) { cell_collide(A, c, out); }, overflow);
-  }
+  for_units(
+      N, [&](int c) { return (v.tag0[c] & (T_SPEC | T_WALL)) != 0; },
+      [&](int c) {
+        const bool active = (v.tag0[c] & T_ACT) != 0;
+        double yb[19];
+        for (int i = 0; i < Q9; ++i) yb[i] = v.bar[AR_ANEW][i * N + c];
+        for (int m = 0; m < 10; ++m) yb[9 + m] = active ? v.bar[AR_MNEW][m * N + c] : 0.0;
+        reverse_unit<R, 19>(v, yb, [&](Acc<R>& A, Dual* out) { cell_collide(A, c, out); }, overflow);
+      });
 }
 
 // initial populations and moments (hydrostatic density about the initial

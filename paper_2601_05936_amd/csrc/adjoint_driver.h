@@ -24,6 +24,7 @@ struct AdjDriver {
     const int g = (p->N + 255) / 256;
     return g < 4096 ? g : 4096;
   }
+  static int grid_units(const lsb_plan* p) { return adj::unit_blocks(p->N); }
 
   // state of the current step (before it runs) into snapshot slot k
   static void snapshot_state(lsb_plan* p, int k, hipStream_t st) {
@@ -144,7 +145,7 @@ struct AdjDriver {
     AdjState& s = p->adj;
     const long N = p->N;
     const int r = s.role;
-    const int g = grid(p);
+    const int g = grid(p), gu = grid_units(p);
     int* flag = reinterpret_cast<int*>(sc(p) + AdjState::SC_FLAG);
     V v = view(p, n);
     char* s0 = slot(p, n);
@@ -161,34 +162,35 @@ struct AdjDriver {
     adj::k_zero<<<1, 1, 0, st>>>(sc(p) + AdjState::SC_PBBAR + r, 1);
     // refill (cells whose phase changed), geometry of the new band
     adj::k_refill_take<R><<<g, 256, 0, st>>>(v, dbl(p, s.o_ytmp));
-    adj::k_refill_adj<R><<<g, 256, 0, st>>>(v, dbl(p, s.o_ytmp), flag);
-    adj::k_geometry_adj<R><<<g, 256, 0, st>>>(v, 1, adj::AR_PHI1, dbl(p, s.o_Gbar[r]), flag);
+    adj::k_refill_adj<R><<<gu, 256, 0, st>>>(v, dbl(p, s.o_ytmp), flag);
+    adj::k_geometry_adj<R><<<gu, 256, 0, st>>>(v, 1, adj::AR_PHI1, dbl(p, s.o_Gbar[r]), flag);
     // TVD-RK3 stages, velocity of the last extension sweep
     const size_t lvl = 3 * N * p->bytes_real;
     const int ne = p->P.n_ext;
     int u = 0;
     v.val[adj::AR_UTOUT] = reinterpret_cast<const R*>(s0 + s.s_ut + (size_t)ne * lvl);
     v.bar[adj::AR_UTOUT] = dbl(p, s.o_utbar[u]);
-    adj::k_rk_adj<R><<<g, 256, 0, st>>>(v, 3, dbl(p, s.o_phibar[r]), flag);
-    adj::k_rk_adj<R><<<g, 256, 0, st>>>(v, 2, dbl(p, s.o_s2bar), flag);
-    adj::k_rk_adj<R><<<g, 256, 0, st>>>(v, 1, dbl(p, s.o_s1bar), flag);
+    adj::k_rk_adj<R><<<gu, 256, 0, st>>>(v, 3, dbl(p, s.o_phibar[r]), flag);
+    adj::k_rk_adj<R><<<gu, 256, 0, st>>>(v, 2, dbl(p, s.o_s2bar), flag);
+    adj::k_rk_adj<R><<<gu, 256, 0, st>>>(v, 1, dbl(p, s.o_s1bar), flag);
     // extension sweeps, last to first
     for (int k = ne; k >= 1; --k) {
       v.val[adj::AR_UTOUT] = reinterpret_cast<const R*>(s0 + s.s_ut + (size_t)k * lvl);
       v.bar[adj::AR_UTOUT] = dbl(p, s.o_utbar[u]);
       v.val[adj::AR_UT] = reinterpret_cast<const R*>(s0 + s.s_ut + (size_t)(k - 1) * lvl);
       v.bar[adj::AR_UT] = dbl(p, s.o_utbar[u ^ 1]);
-      adj::k_sweep_adj<R><<<g, 256, 0, st>>>(v, flag);
+      adj::k_sweep_adj<R><<<gu, 256, 0, st>>>(v, flag);
       zero(p, s.o_utbar[u], 3 * N, st);
       u ^= 1;
     }
     // extension seed
     v.val[adj::AR_UTOUT] = reinterpret_cast<const R*>(s0 + s.s_ut);
     v.bar[adj::AR_UTOUT] = dbl(p, s.o_utbar[u]);
-    adj::k_seed_adj<R><<<g, 256, 0, st>>>(v, flag);
+    adj::k_seed_adj<R><<<gu, 256, 0, st>>>(v, flag);
     zero(p, s.o_utbar[u], 3 * N, st);
     // collide-stream with wall and interface bounce-back
-    adj::k_collide_adj<R><<<g, 256, 0, st>>>(v, flag);
+    adj::k_collide_adj_plain<R><<<g, 256, 0, st>>>(v);
+    adj::k_collide_adj<R><<<gu, 256, 0, st>>>(v, flag);
     // the adjoint of step n + 1's state is consumed
     zero(p, s.o_Abar[r], 9 * N, st);
     zero(p, s.o_Mbar[r], 10 * N, st);
@@ -215,7 +217,7 @@ struct AdjDriver {
     v.bar[adj::AR_AIN] = dbl(p, s.o_Abar[r]);
     v.bar[adj::AR_MIN] = dbl(p, s.o_Mbar[r]);
     // geometry of the initial band
-    adj::k_geometry_adj<R><<<g, 256, 0, st>>>(v, 0, adj::AR_PHI0, dbl(p, s.o_Gbar[r]), flag);
+    adj::k_geometry_adj<R><<<grid_units(p), 256, 0, st>>>(v, 0, adj::AR_PHI0, dbl(p, s.o_Gbar[r]), flag);
     // hydrostatic initial density about the initial centroid
     if (hydro) {
       adj::k_init_pop_adj<R><<<AdjState::kInitBlocks, 256, 0, st>>>(v, u0, dbl(p, s.o_partial));
