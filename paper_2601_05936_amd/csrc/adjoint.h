@@ -249,47 +249,65 @@ __device__ Dual iface_pull(Acc<R>& A, int c, int x, int y, int sc, int i, int k)
   return dj / (Dual(2.0) * q) + (Dual(2.0) * q - Dual(1.0)) / (Dual(2.0) * q) * di + W / (Dual(2.0) * q);
 }
 
-// incoming deviation of direction i at cell c (phase k) of step n
-template <class R>
-__device__ Dual pull(Acc<R>& A, int c, int x, int y, int i, int k, bool spec) {
-  const View<R>& v = *A.v;
+// Source of the pull of direction i at cell c when no interface is
+// crossed: streaming from the upstream cell, halfway bounce-back at a
+// no-slip face (own cell, opposite direction, plus the moving-wall term cst)
+// or specular reflection at a free-slip face (reflected direction at the
+// mirrored cell).  sc is the cell whose phase decides whether the pull
+// crosses the interface (-1 for no-slip faces), refl marks reflections.
+struct Src {
+  long idx;
+  double cst;
+  int sc;
+  bool refl;
+};
+
+template <class V>
+__device__ Src plain_source(const V& v, int c, int x, int y, int i) {
   const long N = v.N;
   const int cx = L9::cx(i), cy = L9::cy(i);
   const int sx = coord_lb(x - cx, v.nx, v.per[0]);
   const int sy = coord_lb(y - cy, v.ny, v.per[1]);
-  const double w = wgt<LSB_D2Q9>(i);
-  const int j = opp<LSB_D2Q9>(i);
-  if ((sx | sy) < 0) {
-    // wall faces: halfway bounce-back for a crossed no-slip face, else
-    // specular reflection (bounce-back if the reflected source is in the
-    // other phase, checked at interface-adjacent cells)
-    const int pos[2] = {x, y};
-    const int cc[2] = {cx, cy};
-    const int n[2] = {v.nx, v.ny};
-    const int sv[2] = {sx, sy};
-    int src[2], rc[2];
-    for (int ax = 0; ax < 2; ++ax) {
-      src[ax] = sv[ax] < 0 ? pos[ax] : sv[ax];
-      rc[ax] = sv[ax] < 0 ? -cc[ax] : cc[ax];
-    }
-    for (int ax = 0; ax < 2; ++ax) {
-      if (sv[ax] >= 0) continue;
-      const int face = 2 * ax + (pos[ax] - cc[ax] < 0 ? 0 : 1);
-      if (v.bcf[face] == LSB_NOSLIP) {
-        const double cu = cc[0] * v.wall_u[face][0] + cc[1] * v.wall_u[face][1];
-        return A.get(AR_AIN, j * N + c) + Dual(6.0 * w * cu);
-      }
-    }
-    const int sc = src[1] * v.nx + src[0];
-    if (spec && (v.tag0[sc] & T_GAS) != k) return A.get(AR_AIN, j * N + c);
-    int ir = 0;
-    for (int m = 0; m < Q9; ++m)
-      if (L9::cx(m) == rc[0] && L9::cy(m) == rc[1]) ir = m;
-    return A.get(AR_AIN, ir * N + sc);
+  if ((sx | sy) >= 0) {
+    const int sc = sy * v.nx + sx;
+    return Src{(long)i * N + sc, 0.0, sc, false};
   }
-  const int sc = sy * v.nx + sx;
-  if (spec && (v.tag0[sc] & T_GAS) != k) return iface_pull(A, c, x, y, sc, i, k);
-  return A.get(AR_AIN, i * N + sc);
+  const int pos[2] = {x, y};
+  const int cc[2] = {cx, cy};
+  const int sv[2] = {sx, sy};
+  int src[2], rc[2];
+  for (int ax = 0; ax < 2; ++ax) {
+    src[ax] = sv[ax] < 0 ? pos[ax] : sv[ax];
+    rc[ax] = sv[ax] < 0 ? -cc[ax] : cc[ax];
+  }
+  for (int ax = 0; ax < 2; ++ax) {
+    if (sv[ax] >= 0) continue;
+    const int face = 2 * ax + (pos[ax] - cc[ax] < 0 ? 0 : 1);
+    if (v.bcf[face] == LSB_NOSLIP) {
+      const double cu = cc[0] * v.wall_u[face][0] + cc[1] * v.wall_u[face][1];
+      return Src{(long)opp<LSB_D2Q9>(i) * N + c, 6.0 * wgt<LSB_D2Q9>(i) * cu, -1, false};
+    }
+  }
+  const int sc = src[1] * v.nx + src[0];
+  int ir = 0;
+  for (int m = 0; m < Q9; ++m)
+    if (L9::cx(m) == rc[0] && L9::cy(m) == rc[1]) ir = m;
+  return Src{(long)ir * N + sc, 0.0, sc, true};
+}
+
+// incoming deviation of direction i at cell c (phase k) of step n; at
+// interface-adjacent cells a pull whose source lies in the other phase is
+// the interface bounce-back (a reflected source: bounce-back at the cell)
+template <class R>
+__device__ Dual pull(Acc<R>& A, int c, int x, int y, int i, int k, bool spec) {
+  const View<R>& v = *A.v;
+  const Src s = plain_source(v, c, x, y, i);
+  if (spec && s.sc >= 0 && (v.tag0[s.sc] & T_GAS) != k) {
+    if (s.refl) return A.get(AR_AIN, (long)opp<LSB_D2Q9>(i) * v.N + c);
+    return iface_pull(A, c, x, y, s.sc, i, k);
+  }
+  const Dual d = A.get(AR_AIN, s.idx);
+  return s.cst != 0.0 ? d + Dual(s.cst) : d;
 }
 
 // BGK collision with body force of the incoming deviations f of a cell of
@@ -332,20 +350,6 @@ __device__ void collision(const View_& v, int k, const Dual* f, Dual* out) {
   out[16] = fac * P3;
   out[17] = Dual(0.0);
   out[18] = Dual(0.0);
-}
-
-// collide-stream of cell c (incoming populations by streaming, wall or
-// interface bounce-back, then the collision)
-template <class R>
-__device__ void cell_collide(Acc<R>& A, int c, Dual* out) {
-  const View<R>& v = *A.v;
-  const int x = c % v.nx, y = c / v.nx;
-  const uint8_t t = v.tag0[c];
-  const int k = t & T_GAS;
-  const bool spec = (t & T_SPEC) != 0;
-  Dual f[Q9];
-  for (int i = 0; i < Q9; ++i) f[i] = pull(A, c, x, y, i, k, spec);
-  collision(v, k, f, out);
 }
 
 // extension seed at an interface-adjacent cell: mean over the cut links of
@@ -762,14 +766,17 @@ __global__ __launch_bounds__(256) void k_seed_adj(View<R> v, int* overflow) {
       });
 }
 
-// collide-stream, plain streaming cells (one thread per cell): the inputs
-// are the nine pulled populations
+// Collide-stream: adjoint of the populations of step n + 1 and (on LS-active
+// cells) of the moments into the inputs of step n.  Cells that are not
+// interface-adjacent (one thread per cell): each incoming population is a
+// single input plus a constant, so the adjoint is the collision's transposed
+// Jacobian, column by column.
 template <class R>
 __global__ __launch_bounds__(256) void k_collide_adj_plain(View<R> v) {
   const long N = v.N;
   ADJ_FOR_CELLS(v) {
     const uint8_t t = v.tag0[c];
-    if (t & (T_SPEC | T_WALL)) continue;
+    if (t & T_SPEC) continue;
     double yb[19];
     for (int i = 0; i < Q9; ++i) yb[i] = v.bar[AR_ANEW][i * N + c];
     const bool active = (t & T_ACT) != 0;
@@ -781,10 +788,10 @@ __global__ __launch_bounds__(256) void k_collide_adj_plain(View<R> v) {
     long src[Q9];
     double f0[Q9];
     for (int i = 0; i < Q9; ++i) {
-      const int sx = coord_lb(x - L9::cx(i), v.nx, v.per[0]);
-      const int sy = coord_lb(y - L9::cy(i), v.ny, v.per[1]);
-      src[i] = (long)i * N + (long)sy * v.nx + sx;
-      f0[i] = (double)v.val[AR_AIN][src[i]];
+      const Src sr = plain_source(v, c, x, y, i);
+      src[i] = sr.idx;
+      const double d = (double)v.val[AR_AIN][sr.idx];
+      f0[i] = sr.cst != 0.0 ? d + sr.cst : d;
     }
     for (int e = 0; e < Q9; ++e) {
       Dual f[Q9], out[19];
@@ -797,20 +804,41 @@ __global__ __launch_bounds__(256) void k_collide_adj_plain(View<R> v) {
   }
 }
 
-// collide-stream, interface- and wall-adjacent cells (one cell per
-// wavefront): adjoint of the populations of step n + 1 and (on LS-active
-// cells) of the moments into the inputs of step n
+// Interface-adjacent cells (one cell per wavefront): lane i < 9 takes the
+// collision's derivative with respect to incoming population i, then each
+// pull is reversed as a unit of its own with that adjoint.
 template <class R>
 __global__ __launch_bounds__(256) void k_collide_adj(View<R> v, int* overflow) {
   const long N = v.N;
   for_units(
-      N, [&](int c) { return (v.tag0[c] & (T_SPEC | T_WALL)) != 0; },
+      N, [&](int c) { return (v.tag0[c] & T_SPEC) != 0; },
       [&](int c) {
-        const bool active = (v.tag0[c] & T_ACT) != 0;
+        const uint8_t t = v.tag0[c];
+        const bool active = (t & T_ACT) != 0;
+        const int x = c % v.nx, y = c / v.nx, k = t & T_GAS;
         double yb[19];
         for (int i = 0; i < Q9; ++i) yb[i] = v.bar[AR_ANEW][i * N + c];
         for (int m = 0; m < 10; ++m) yb[9 + m] = active ? v.bar[AR_MNEW][m * N + c] : 0.0;
-        reverse_unit<R, 19>(v, yb, [&](Acc<R>& A, Dual* out) { cell_collide(A, c, out); }, overflow);
+        bool any = false;
+        for (int j = 0; j < 19; ++j) any = any || yb[j] != 0.0;
+        if (!any) return;
+        const int lane = (int)(threadIdx.x & 63u);
+        double fb = 0.0;
+        if (lane < Q9) {
+          Acc<R> A;  // values only: no seed
+          A.v = &v;
+          A.mode = 1;
+          A.tarr = -1;
+          A.tidx = -1;
+          Dual f[Q9], out[19];
+          for (int i = 0; i < Q9; ++i) f[i] = Dual(pull(A, c, x, y, i, k, true).v, i == lane ? 1.0 : 0.0);
+          collision(v, k, f, out);
+          for (int j = 0; j < 19; ++j) fb += yb[j] * out[j].d;
+        }
+        for (int i = 0; i < Q9; ++i) {
+          const double fbi = __shfl(fb, i);
+          reverse_unit<R, 1>(v, &fbi, [&](Acc<R>& A, Dual* out) { out[0] = pull(A, c, x, y, i, k, true); }, overflow);
+        }
       });
 }
 
