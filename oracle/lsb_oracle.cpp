@@ -39,6 +39,8 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <functional>
+#include <map>
 #include <vector>
 
 namespace orc {
@@ -145,6 +147,196 @@ static void equilibrium(const Lattice& L, const T& rho, const T u[3], T* feq) {
 }
 
 // --------------------------------------------------------------------------
+// Cumulant collision (Sec. 2.1, D3Q27): the populations are transformed into
+// cumulants, every cumulant relaxes towards its value for the Maxwell
+// distribution, c' = c + omega_alpha (c_eq - c), with the shear rate
+// omega_1 = omega_BGK and every other rate one, and the result is
+// transformed back.  The paper takes the operator from Geier et al. (2015);
+// here it is written from the definitions:
+//   * the 27 moments m_abc = sum_i c_ix^a c_iy^b c_iz^c f_i, a, b, c in
+//     {0, 1, 2}, determine the 27 populations (a 27 x 27 linear system);
+//   * the cumulant of index (a, b, c) is the joint cumulant of the variable
+//     list (x a times, y b times, z c times) under the normalised
+//     distribution f / rho, by the moment-cumulant formula over the set
+//     partitions pi of the list,
+//       kappa = sum_pi (-1)^(|pi| - 1) (|pi| - 1)! prod_{B in pi} E[prod_{j in B} X_j],
+//     inverted by E[X_1 ... X_n] = sum_pi prod_{B in pi} kappa(B);
+//   * the Maxwell distribution has first cumulants u, second cumulants
+//     cs^2 delta_ab and no others.
+// Relaxation groups: rho and u are conserved; the deviatoric part of the
+// second-order cumulants relaxes with omega_1 (shear), their trace with
+// omega_2 (bulk) and every cumulant of order three or more with its own
+// rate; the paper sets every rate except omega_1 to one.  Reading: the body
+// force enters as in the BGK operator (only the collision operator is
+// exchanged, the discrete Boltzmann equation is kept).
+// --------------------------------------------------------------------------
+inline int midx(int a, int b, int c) { return 9 * a + 3 * b + c; }
+
+// For every cumulant index (a, b, c), the moment-cumulant formula collected
+// into terms coef * prod_j moment[idx_j] (partitions with the same multiset of
+// block moments merged), and the inverse formula likewise.
+struct CumulantTables {
+  struct Term {
+    double coef;
+    std::vector<int> idx;
+  };
+  std::vector<Term> to_cum[27], to_mom[27];
+  double Minv[27][27];  // populations from moments (D3Q27 directions)
+};
+
+static void set_partitions(int n, std::vector<std::vector<int>>& out) {
+  // restricted growth strings: label[0] = 0, label[j] <= 1 + max(label[0..j-1])
+  std::vector<int> lab(n, 0);
+  std::function<void(int, int)> rec = [&](int j, int mx) {
+    if (j == n) { out.push_back(lab); return; }
+    for (int v = 0; v <= mx + 1; ++v) { lab[j] = v; rec(j + 1, std::max(mx, v)); }
+  };
+  if (n == 0) { out.push_back(lab); return; }
+  lab[0] = 0;
+  rec(1, 0);
+}
+
+static const CumulantTables& cumulant_tables() {
+  static const CumulantTables T = [] {
+    CumulantTables t;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        for (int c = 0; c < 3; ++c) {
+          std::vector<int> var;
+          for (int k = 0; k < a; ++k) var.push_back(0);
+          for (int k = 0; k < b; ++k) var.push_back(1);
+          for (int k = 0; k < c; ++k) var.push_back(2);
+          const int n = (int)var.size();
+          std::vector<std::vector<int>> parts;
+          set_partitions(n, parts);
+          std::map<std::vector<int>, double> cum, mom;
+          for (const auto& lab : parts) {
+            const int nb = n == 0 ? 0 : 1 + *std::max_element(lab.begin(), lab.end());
+            std::vector<int> blocks;
+            for (int B = 0; B < nb; ++B) {
+              int cnt[3] = {0, 0, 0};
+              for (int j = 0; j < n; ++j)
+                if (lab[j] == B) ++cnt[var[j]];
+              blocks.push_back(midx(cnt[0], cnt[1], cnt[2]));
+            }
+            std::sort(blocks.begin(), blocks.end());
+            double fact = 1.0;
+            for (int k = 2; k < nb; ++k) fact *= k;
+            cum[blocks] += ((nb - 1) % 2 ? -1.0 : 1.0) * fact;
+            mom[blocks] += 1.0;
+          }
+          const int m = midx(a, b, c);
+          for (const auto& kv : cum)
+            if (kv.second != 0.0) t.to_cum[m].push_back({kv.second, kv.first});
+          for (const auto& kv : mom) t.to_mom[m].push_back({kv.second, kv.first});
+        }
+    // moment matrix of D3Q27 and its inverse (Gauss-Jordan, partial pivoting)
+    const Lattice L = make_lattice(2);
+    double M[27][54];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        for (int c = 0; c < 3; ++c)
+          for (int i = 0; i < 27; ++i) {
+            const int r = midx(a, b, c);
+            M[r][i] = std::pow(L.c[i][0], a) * std::pow(L.c[i][1], b) * std::pow(L.c[i][2], c);
+            M[r][27 + i] = (r == i) ? 1.0 : 0.0;
+          }
+    for (int col = 0; col < 27; ++col) {
+      int piv = col;
+      for (int r = col + 1; r < 27; ++r)
+        if (std::fabs(M[r][col]) > std::fabs(M[piv][col])) piv = r;
+      for (int k = 0; k < 54; ++k) std::swap(M[col][k], M[piv][k]);
+      const double d = M[col][col];
+      for (int k = 0; k < 54; ++k) M[col][k] /= d;
+      for (int r = 0; r < 27; ++r) {
+        if (r == col || M[r][col] == 0.0) continue;
+        const double e = M[r][col];
+        for (int k = 0; k < 54; ++k) M[r][k] -= e * M[col][k];
+      }
+    }
+    for (int i = 0; i < 27; ++i)
+      for (int r = 0; r < 27; ++r) t.Minv[i][r] = M[i][27 + r];
+    return t;
+  }();
+  return T;
+}
+
+// Joint cumulants (index midx) of a normalised moment set m (m[0] = 1).
+template <class T>
+static void cumulants_from_moments(const T* m, T* kap) {
+  const CumulantTables& t = cumulant_tables();
+  kap[0] = m[0];
+  for (int r = 1; r < 27; ++r) {
+    T s = T(0.0);
+    for (const auto& term : t.to_cum[r]) {
+      T p = T(term.coef);
+      for (int j : term.idx) p = p * m[j];
+      s += p;
+    }
+    kap[r] = s;
+  }
+}
+
+// Normalised moments from joint cumulants (kap[0] is ignored; m[0] = 1).
+template <class T>
+static void moments_from_cumulants(const T* kap, T* m) {
+  const CumulantTables& t = cumulant_tables();
+  for (int r = 0; r < 27; ++r) {
+    T s = T(0.0);
+    for (const auto& term : t.to_mom[r]) {
+      T p = T(term.coef);
+      for (int j : term.idx) p = p * kap[j];
+      s += p;
+    }
+    m[r] = r == 0 ? T(1.0) : s;
+  }
+}
+
+// Cumulant collision of one D3Q27 cell (rates: omega1 shear, omega2 bulk,
+// omega3 every higher order; the paper's operator is omega2 = omega3 = 1)
+// plus the first-order body force w_i rho (c_i . a) / cs^2.
+template <class T>
+static void cumulant_collide(const Lattice& L, const T* f, double omega1, double omega2, double omega3,
+                             const double* acc, T* out) {
+  const CumulantTables& t = cumulant_tables();
+  T rho = T(0.0);
+  for (int i = 0; i < 27; ++i) rho += f[i];
+  T m[27], kap[27];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int c = 0; c < 3; ++c) {
+        T s = T(0.0);
+        for (int i = 0; i < 27; ++i) {
+          const double w = std::pow(L.c[i][0], a) * std::pow(L.c[i][1], b) * std::pow(L.c[i][2], c);
+          if (w != 0.0) s += w * f[i];
+        }
+        m[midx(a, b, c)] = s / rho;
+      }
+  cumulants_from_moments(m, kap);
+  // second order: trace (bulk) and deviatoric (shear) parts
+  const int dg[3] = {midx(2, 0, 0), midx(0, 2, 0), midx(0, 0, 2)};
+  const int od[3] = {midx(1, 1, 0), midx(1, 0, 1), midx(0, 1, 1)};
+  const T tr = (kap[dg[0]] + kap[dg[1]] + kap[dg[2]]) / 3.0;
+  T post[27];
+  for (int r = 0; r < 27; ++r) post[r] = kap[r];
+  const T tr_post = tr + omega2 * (CS2 - tr);
+  for (int k = 0; k < 3; ++k) post[dg[k]] = tr_post + (1.0 - omega1) * (kap[dg[k]] - tr);
+  for (int k = 0; k < 3; ++k) post[od[k]] = (1.0 - omega1) * kap[od[k]];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int c = 0; c < 3; ++c)
+        if (a + b + c >= 3) post[midx(a, b, c)] = (1.0 - omega3) * kap[midx(a, b, c)];
+  T mp[27];
+  moments_from_cumulants(post, mp);
+  for (int i = 0; i < 27; ++i) {
+    T s = T(0.0);
+    for (int r = 0; r < 27; ++r) s += t.Minv[i][r] * mp[r];
+    const double ca = L.c[i][0] * acc[0] + L.c[i][1] * acc[1] + L.c[i][2] * acc[2];
+    out[i] = rho * s + L.w[i] * rho * ca / CS2;
+  }
+}
+
+// --------------------------------------------------------------------------
 // Parameters (layout mirrored by the Python ctypes binding of the oracle).
 // Faces are ordered -x,+x,-y,+y,-z,+z.  Phase 0 is the liquid (phi < 0),
 // phase 1 the gas (phi >= 0).
@@ -168,6 +360,7 @@ struct Params {
   double pb0;
   int init_hydrostatic;
   int fp16_scale_log2;
+  int collision[2];  // per phase: 0 BGK, 1 cumulant (D3Q27 only)
 };
 
 // Tag bits used when exporting the classification.
@@ -434,8 +627,15 @@ struct Sim {
         for (int mm = 0; mm < 6; ++mm) MS1[6 * c + mm] = fac * Pi[mm];
       }
       // BGK collision plus the first-order body force of Sec. 2.1 written for
-      // a general acceleration a_k: F_i = w_i rho (c_i . a_k) / cs^2.
+      // a general acceleration a_k: F_i = w_i rho (c_i . a_k) / cs^2; or the
+      // cumulant collision with the same force.
       const double* acc = P.accel[k];
+      if (P.collision[k] == 1) {
+        T post[27];
+        cumulant_collide(L, f, om, 1.0, 1.0, acc, post);
+        for (int i = 0; i < Q; ++i) An[(size_t)i * N + c] = post[i];
+        continue;
+      }
       for (int i = 0; i < Q; ++i) {
         double ca = L.c[i][0] * acc[0] + L.c[i][1] * acc[1] + L.c[i][2] * acc[2];
         An[(size_t)i * N + c] = f[i] - om * (f[i] - feq[i]) + L.w[i] * rho * ca / CS2;
@@ -999,6 +1199,38 @@ int orc_feq(int lattice, double rho, const double* u, double* out) {
   return 0;
 }
 
+// Joint cumulants kappa[9a + 3b + c] (a, b, c in {0, 1, 2}) of the
+// normalised weighted point set (pts [n][3], weights w); kappa[0] = sum w.
+int orc_cumulants_points(int n, const double* pts, const double* w, double* kappa) {
+  if (n < 1) return -1;
+  double W = 0.0, m[27] = {};
+  for (int j = 0; j < n; ++j) W += w[j];
+  if (!(W > 0.0)) return -1;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int c = 0; c < 3; ++c) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j)
+          s += w[j] * std::pow(pts[3 * j], a) * std::pow(pts[3 * j + 1], b) * std::pow(pts[3 * j + 2], c);
+        m[orc::midx(a, b, c)] = s / W;
+      }
+  orc::cumulants_from_moments(m, kappa);
+  kappa[0] = W;
+  return 0;
+}
+
+// Normalised moments m[9a + 3b + c] from joint cumulants (kappa[0] ignored).
+void orc_moments_from_cumulants(const double* kappa, double* m) { orc::moments_from_cumulants(kappa, m); }
+
+// One D3Q27 cell through the cumulant collision (rates omega1, omega2,
+// omega3; the paper's operator is omega2 = omega3 = 1) with acceleration acc.
+int orc_cumulant_collide(const double* f, double omega1, double omega2, double omega3, const double* acc,
+                         double* out) {
+  const orc::Lattice L = orc::make_lattice(2);
+  orc::cumulant_collide(L, f, omega1, omega2, omega3, acc, out);
+  return 0;
+}
+
 void orc_refill_weights(double q, double* Lw) { Sim<double>::refill_weights(q, Lw); }
 
 double orc_heaviside(double phi, double eps) { return orc::heaviside(phi, eps); }
@@ -1010,6 +1242,8 @@ static int check_params(const orc::Params* p) {
   for (int a = 0; a < 3; ++a)
     if ((p->bc[2 * a] == orc::BC_PERIODIC) != (p->bc[2 * a + 1] == orc::BC_PERIODIC)) return -1;
   if (p->tau[0] <= 0.5 || p->tau[1] <= 0.5) return -1;
+  for (int k = 0; k < 2; ++k)
+    if (p->collision[k] != 0 && (p->collision[k] != 1 || p->lattice != 2)) return -1;
   return 0;
 }
 

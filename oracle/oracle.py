@@ -33,7 +33,7 @@ class _Params(C.Structure):
         ("sigma", C.c_double), ("band", C.c_double), ("n_ext", C.c_int), ("ext_dtau", C.c_double),
         ("reinit_every", C.c_int), ("n_reinit", C.c_int), ("reinit_dtau", C.c_double),
         ("heaviside_eps", C.c_double), ("use_pb", C.c_int), ("pb0", C.c_double),
-        ("init_hydrostatic", C.c_int), ("fp16_scale_log2", C.c_int),
+        ("init_hydrostatic", C.c_int), ("fp16_scale_log2", C.c_int), ("collision", C.c_int * 2),
     ]
 
 
@@ -55,6 +55,9 @@ def _params(p: dict) -> _Params:
             for i in range(2):
                 for a in range(3):
                     s.accel[i][a] = float(v[i][a])
+        elif k == "collision":
+            for i in range(2):
+                s.collision[i] = int(v[i])
         else:
             setattr(s, k, v)
     return s
@@ -91,6 +94,9 @@ def _load():
                                 C.POINTER(C.c_int)]
     lib.orc_feq.argtypes = [C.c_int, C.c_double, dp, dp]
     lib.orc_refill_weights.argtypes = [C.c_double, dp]
+    lib.orc_cumulants_points.argtypes = [C.c_int, dp, dp, dp]
+    lib.orc_moments_from_cumulants.argtypes = [dp, dp]
+    lib.orc_cumulant_collide.argtypes = [dp, C.c_double, C.c_double, C.c_double, dp, dp]
     lib.orc_heaviside.restype = C.c_double
     lib.orc_heaviside.argtypes = [C.c_double, C.c_double]
     lib.orc_geometry.argtypes = [P, dp, dp, dp]
@@ -140,6 +146,33 @@ def feq(lat: int, rho: float, u) -> np.ndarray:
     out = np.zeros(27)
     assert lib.orc_feq(lat, float(rho), _dp(u), _dp(out)) == 0
     return out[: lattice(lat)[1]]
+
+
+def cumulants_points(pts, w) -> np.ndarray:
+    """Joint cumulants kappa[a, b, c] (a, b, c in 0..2) of a weighted point set
+    in R^3 (normalised by the total weight; kappa[0, 0, 0] = total weight)."""
+    pts = _f64(np.asarray(pts, dtype=np.float64).reshape(-1, 3))
+    w = _f64(w, pts.shape[0])
+    out = np.zeros(27)
+    assert _load().orc_cumulants_points(pts.shape[0], _dp(pts), _dp(w), _dp(out)) == 0
+    return out.reshape(3, 3, 3)
+
+
+def moments_from_cumulants(kappa) -> np.ndarray:
+    """Normalised moments m[a, b, c] from joint cumulants (kappa[0, 0, 0] ignored)."""
+    k = _f64(np.asarray(kappa, dtype=np.float64).reshape(27))
+    out = np.zeros(27)
+    _load().orc_moments_from_cumulants(_dp(k), _dp(out))
+    return out.reshape(3, 3, 3)
+
+
+def cumulant_collide(f, omega1: float, omega2: float = 1.0, omega3: float = 1.0, acc=(0.0, 0.0, 0.0)):
+    """One D3Q27 cell (oracle direction order) through the cumulant collision."""
+    f = _f64(f, 27)
+    a = _f64(np.asarray(acc, dtype=np.float64), 3)
+    out = np.zeros(27)
+    assert _load().orc_cumulant_collide(_dp(f), float(omega1), float(omega2), float(omega3), _dp(a), _dp(out)) == 0
+    return out
 
 
 def refill_weights(q: float) -> np.ndarray:

@@ -22,6 +22,7 @@ D2Q9, D3Q19, D3Q27 = 0, 1, 2
 F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
 PERIODIC, NOSLIP, FREESLIP = 0, 1, 2
 LIQUID, GAS = 0, 1
+BGK, CUMULANT = 0, 1
 
 
 def default_params(**kw) -> dict:
@@ -32,7 +33,7 @@ def default_params(**kw) -> dict:
         rho_phys=[1.0, 1.0], tau=[0.8, 0.8], accel=[[0.0] * 3, [0.0] * 3],
         sigma=0.0, band=6.0, n_ext=8, ext_dtau=0.5,
         reinit_every=10, n_reinit=5, reinit_dtau=0.3, heaviside_eps=1.5,
-        use_pb=0, pb0=0.0, init_hydrostatic=0, fp16_scale_log2=12,
+        use_pb=0, pb0=0.0, init_hydrostatic=0, fp16_scale_log2=12, collision=[BGK, BGK],
     )
     p.update(kw)
     return p
