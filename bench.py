@@ -42,7 +42,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_mode(size, storage, steps, warmup, schedule):
+def run_mode(size, storage, steps, warmup, schedule, cumulant_gas=False):
     import torch
 
     from paper_2601_05936_amd import workloads as W
@@ -50,6 +50,8 @@ def run_mode(size, storage, steps, warmup, schedule):
 
     w = W.wavy_stratified_3d(n=size, storage=storage)
     p = w["params"]
+    if cumulant_gas:
+        p["collision"] = [W.BGK, W.CUMULANT]
     t0 = time.time()
     phi0 = torch.from_numpy(W.wavy_phi(p, 8.0 * size / 512.0)).to("cuda:0")
     s = Sim(p).set_schedule(schedule).init(phi0)
@@ -168,7 +170,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=512)
-    ap.add_argument("--modes", default="f16dev,f32,f64")
+    ap.add_argument("--modes", default="f16dev,f32,f64,f16dev-cum",
+                    help="storage modes; a '-cum' suffix runs the gas phase with the cumulant collision "
+                         "(the paper's 3D pairing: BGK liquid, cumulant gas)")
     ap.add_argument("--schedule", default="auto", choices=["auto", "serial", "overlap"],
                     help="step schedule: one stream, the bulk collide-stream overlapped on a second stream, or "
                          "auto (the faster on this workload: serial for FP16-deviation, overlap for FP32 and FP64)")
@@ -189,16 +193,18 @@ def main():
     from paper_2601_05936_amd.workloads import F16DEV, F32, F64
     def sched_of(mode):
         if args.schedule == "auto":
-            return "serial" if mode == "f16dev" else "overlap"
+            return "serial" if mode.startswith("f16dev") else "overlap"
         return args.schedule
     names = {"f16dev": F16DEV, "f32": F32, "f64": F64}
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
     results = {}
     for m in modes:
         sm = sched_of(m)
-        results[m] = run_mode(args.size, names[m], args.steps, args.warmup,
-                              SCHED_OVERLAP if sm == "overlap" else SCHED_SERIAL)
+        base, cum = (m[:-4], True) if m.endswith("-cum") else (m, False)
+        results[m] = run_mode(args.size, names[base], args.steps, args.warmup,
+                              SCHED_OVERLAP if sm == "overlap" else SCHED_SERIAL, cumulant_gas=cum)
         results[m]["schedule"] = sm
+        results[m]["collision"] = "BGK liquid, cumulant gas" if cum else "BGK"
     if args.copy_calibration > 0:
         nbytes = int(args.copy_calibration * 2**30)
         a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
@@ -221,11 +227,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if head == "f64" else "f32",
+        "dtype": "f64" if head.startswith("f64") else "f32",
         "data": "synthetic",
         "config": {"workload": f"D3Q27 wavy stratified {args.size}^3, periodic x/y, no-slip z, density ratio 1000, "
                                f"viscosity ratio 50, sigma 1e-3 (throughput configuration)",
-                   "storage": head, "cells": args.size ** 3, "schedule": sched_of(head)},
+                   "storage": head, "cells": args.size ** 3, "schedule": sched_of(head),
+                   "collision": results[head]["collision"]},
         "modes": results,
         "roofline": {"bound": "hbm", "achieved": r["k1_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r["k1_frac"], "traffic": MEASURED_TRAFFIC.get((head, sched_of(head), args.size)),

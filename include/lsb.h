@@ -53,6 +53,12 @@ enum { LSB_F64 = 0, LSB_F32 = 1, LSB_F16DEV = 2, LSB_BF16DEV = 3 };
  * moving with wall_u, Sec. 2.1 eq:bb); free-slip wall (specular reflection). */
 enum { LSB_PERIODIC = 0, LSB_NOSLIP = 1, LSB_FREESLIP = 2 };
 
+/* Collision operator of a phase (Sec. 2.1): BGK with the equilibrium eq:feq,
+ * or the cumulant operator (cumulants of the populations relaxed towards
+ * their Maxwell values: shear cumulants at omega = 1/tau, every other
+ * cumulant at rate one; D3Q27 only).  Both add the same body-force term. */
+enum { LSB_BGK = 0, LSB_CUMULANT = 1 };
+
 /* Problem statement (Sec. 2 and the setups of Sec. 3). */
 typedef struct lsb_params {
   int lattice, storage, nx, ny, nz;
@@ -73,6 +79,9 @@ typedef struct lsb_params {
   double pb0;               /* initial gas pressure baseline */
   int init_hydrostatic;     /* default initial LB density is hydrostatic about the gas centroid */
   int fp16_scale_log2;      /* s = 2^k for LSB_F16DEV (typically 12) */
+  int collision[2];         /* collision operator of each phase [liquid, gas]: LSB_BGK, or
+                               LSB_CUMULANT (Sec. 2.1: cumulants relaxed towards the Maxwell
+                               values, shear rate 1/tau, every other rate one; D3Q27 only) */
 } lsb_params;
 
 typedef struct lsb_plan lsb_plan; /* opaque; owned by the library */
@@ -92,7 +101,8 @@ typedef struct lsb_integrals {
 /* Validate a parameter block and create a plan (host memory only).
  * Errors: LSB_EINVAL for an unknown lattice/storage, a grid smaller than
  * 4 cells per used axis, nz != 1 with D2Q9, unpaired periodic faces,
- * tau <= 1/2, band < 2, negative counts. */
+ * tau <= 1/2, band < 2, negative counts, an unknown collision operator or
+ * LSB_CUMULANT with a lattice other than D3Q27. */
 int lsb_create(const lsb_params* params, lsb_plan** out);
 void lsb_destroy(lsb_plan* plan);
 
@@ -171,9 +181,9 @@ int lsb_get_kernel_timing(lsb_plan* plan, double* total_ms, long* launches);
  * gas centroid after n steps with respect to the surface tension sigma and
  * the initial level set phi0, under the decisions the forward steps took
  * (phase and band tags, cut and wall links, Bouzidi branch, upwind
- * directions, the clamp at +-B, refill events).  D2Q9 with LSB_F64 or
- * LSB_F32 storage only; the reinitialisation is not differentiated
- * (n_reinit must be 0).  Adjoints are FP64.
+ * directions, the clamp at +-B, refill events, the Godunov branches and
+ * subcell-fix set of the reinitialisation).  D2Q9 with LSB_F64 or LSB_F32
+ * storage only.  Adjoints are FP64.
  *
  * Use with time checkpoints (lsb_save_state every K steps of the forward
  * run).  Then, for each segment from the last to the first:

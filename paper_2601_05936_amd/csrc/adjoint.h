@@ -3,8 +3,8 @@
 //
 // The step is reversed sub-step by sub-step under the decisions of the
 // recorded forward step (phase and band tags, cut and wall links, Bouzidi
-// branch, upwind directions, the clamp at +-B, refill events; the
-// reinitialisation is not differentiated and must be off).  Every reverse
+// branch, upwind directions, the clamp at +-B, refill events, the Godunov
+// branches and subcell-fix set of the reinitialisation).  Every reverse
 // kernel takes one output unit (a cell), evaluates the forward arithmetic of
 // that unit once to enumerate the inputs it reads, then once per input with
 // a dual number seeded on that input, and adds the transposed Jacobian
@@ -53,7 +53,10 @@ __device__ inline Dual dfabs(Dual a) { return a.v < 0.0 ? -a : a; }
 // ---------------------------------------------------------------------------
 enum ArrId {
   AR_AIN = 0, AR_MIN, AR_PHI0, AR_GIN, AR_PB, AR_SIG, AR_MNEW, AR_ANEW, AR_PHI1, AR_GNEW, AR_UT, AR_UTOUT, AR_S1, AR_S2,
-  AR_XC0, AR_NUM
+  AR_XC0,
+  // reinitialisation: level set before it (after the advection), and the
+  // pseudo step's level set and RK3 stage values
+  AR_P0, AR_RPHI, AR_RS1, AR_RS2, AR_NUM
 };
 
 template <class R>
@@ -67,7 +70,7 @@ struct View {
   int per[3], bcf[6];
   double wall_u[6][3];
   double omega[2], acc[2][3], rho_phys[2], eta[2];
-  double band, ext_dtau, heps;
+  double band, ext_dtau, heps, reinit_dtau;
 };
 
 constexpr int KSLOT = 3;           // list entries per lane
@@ -97,8 +100,9 @@ struct Acc {
     return (double)v->val[arr][idx];
   }
   __device__ Dual get(int arr, long idx) {
-    // s1 / s2 equal phi_n outside the band of step n
-    if ((arr == AR_S1 || arr == AR_S2) && !(v->tag0[idx] & T_ACT)) arr = AR_PHI0;
+    // the stage values of the advection and the reinitialisation equal
+    // phi_n outside the band of step n (those cells are not updated)
+    if ((arr == AR_S1 || arr == AR_S2 || arr >= AR_P0) && !(v->tag0[idx] & T_ACT)) arr = AR_PHI0;
     const double x = load(arr, idx);
     if (mode == 0) {
       bool hit = false;
@@ -453,6 +457,96 @@ __device__ void rk_stage(Acc<R>& A, int c, int stage, Dual* out) {
   out[0] = o;
 }
 
+// WENO5 of five successive differences (the forward kernel's weights)
+__device__ inline Dual weno5d(Dual v1, Dual v2, Dual v3, Dual v4, Dual v5) {
+  const double eps = 1e-6;
+  const Dual p0 = v1 * Dual(1.0 / 3.0) - v2 * Dual(7.0 / 6.0) + v3 * Dual(11.0 / 6.0);
+  const Dual p1 = -v2 * Dual(1.0 / 6.0) + v3 * Dual(5.0 / 6.0) + v4 * Dual(1.0 / 3.0);
+  const Dual p2 = v3 * Dual(1.0 / 3.0) + v4 * Dual(5.0 / 6.0) - v5 * Dual(1.0 / 6.0);
+  const Dual a0 = v1 - Dual(2.0) * v2 + v3, b0 = v1 - Dual(4.0) * v2 + Dual(3.0) * v3;
+  const Dual a1 = v2 - Dual(2.0) * v3 + v4, b1 = v2 - v4;
+  const Dual a2 = v3 - Dual(2.0) * v4 + v5, b2 = Dual(3.0) * v3 - Dual(4.0) * v4 + v5;
+  const Dual s0 = Dual(13.0 / 12.0) * a0 * a0 + Dual(0.25) * b0 * b0;
+  const Dual s1 = Dual(13.0 / 12.0) * a1 * a1 + Dual(0.25) * b1 * b1;
+  const Dual s2 = Dual(13.0 / 12.0) * a2 * a2 + Dual(0.25) * b2 * b2;
+  const Dual e0 = Dual(eps) + s0, e1 = Dual(eps) + s1, e2 = Dual(eps) + s2;
+  const Dual w0 = Dual(0.1) / (e0 * e0), w1 = Dual(0.6) / (e1 * e1), w2 = Dual(0.3) / (e2 * e2);
+  return (w0 * p0 + w1 * p1 + w2 * p2) / (w0 + w1 + w2);
+}
+
+// One pseudo-time RK3 stage of the reinitialisation at an LS-active cell:
+// stage 1 reads the pseudo step's level set (AR_RPHI), stage 2 its first
+// stage value (AR_RS1), stage 3 its second (AR_RS2); stages 2 and 3 blend
+// with AR_RPHI.  The smoothed sign and the subcell fix next to the zero set
+// use the level set before the reinitialisation (AR_P0); the Godunov
+// branches, the fix set and the clamp at +-B (last stage of the last pseudo
+// step) follow the primal values.
+template <class R>
+__device__ void reinit_stage(Acc<R>& A, int c, int stage, bool last, Dual* out) {
+  const View<R>& v = *A.v;
+  const int x = c % v.nx, y = c / v.nx;
+  const int in = stage == 1 ? AR_RPHI : (stage == 2 ? AR_RS1 : AR_RS2);
+  auto at = [&](int ax, int o) {
+    int p[2] = {x, y};
+    const int n[2] = {v.nx, v.ny};
+    p[ax] = coord_ls(p[ax] + o, n[ax], v.per[ax]);
+    return p[1] * v.nx + p[0];
+  };
+  const Dual ph0 = A.get(AR_P0, c);
+  const Dual S0 = ph0 / dsqrt(ph0 * ph0 + Dual(1.0));
+  const Dual c0 = A.get(in, c);
+  Dual h2(0.0);
+  for (int ax = 0; ax < 2; ++ax) {
+    const Dual m3 = A.get(in, at(ax, -3)), m2 = A.get(in, at(ax, -2)), m1 = A.get(in, at(ax, -1));
+    const Dual q1 = A.get(in, at(ax, 1)), q2 = A.get(in, at(ax, 2)), q3 = A.get(in, at(ax, 3));
+    const Dual dm = weno5d(m2 - m3, m1 - m2, c0 - m1, q1 - c0, q2 - q1);
+    const Dual dp = weno5d(q3 - q2, q2 - q1, q1 - c0, c0 - m1, m1 - m2);
+    Dual aa(0.0), bb(0.0);
+    if (S0.v > 0.0) {
+      if (dm.v > 0.0) aa = dm;
+      if (dp.v < 0.0) bb = dp;
+    } else {
+      if (dm.v < 0.0) aa = dm;
+      if (dp.v > 0.0) bb = dp;
+    }
+    const Dual a2 = aa * aa, b2 = bb * bb;
+    h2 += a2.v > b2.v ? a2 : b2;
+  }
+  Dual rt = -S0 * (dsqrt(h2) - Dual(1.0));
+  // subcell fix: the cell has an axis neighbour across the zero set of phi0
+  const bool g0 = ph0.v >= 0.0;
+  bool fix = false;
+  for (int ax = 0; ax < 2; ++ax)
+    for (int sg = -1; sg <= 1; sg += 2) fix = fix || ((A.load(AR_P0, at(ax, sg)) >= 0.0) != g0);
+  if (fix) {
+    Dual acc(0.0);
+    int cnt = 0;
+    for (int ax = 0; ax < 2; ++ax)
+      for (int sg = -1; sg <= 1; sg += 2) {
+        const int j = at(ax, sg);
+        const Dual pj = A.get(AR_P0, j);
+        if ((pj.v >= 0.0) == g0) continue;
+        acc += ph0 * (c0 - A.get(in, j)) / (ph0 - pj);
+        ++cnt;
+      }
+    rt += Dual(0.5) * (acc / Dual((double)cnt) - c0);
+  }
+  const Dual vv = c0 + Dual(v.reinit_dtau) * rt;
+  Dual o;
+  if (stage == 1) {
+    o = vv;
+  } else if (stage == 2) {
+    o = Dual(0.75) * A.get(AR_RPHI, c) + Dual(0.25) * vv;
+  } else {
+    o = Dual(1.0 / 3.0) * A.get(AR_RPHI, c) + Dual(2.0 / 3.0) * vv;
+    if (last) {
+      if (o.v > v.band) o = Dual(v.band);
+      if (o.v < -v.band) o = Dual(-v.band);
+    }
+  }
+  out[0] = o;
+}
+
 // geometry (normal, curvature) at cell c from the level set `arr`
 template <class R>
 __device__ void geometry(Acc<R>& A, int c, int arr, Dual* out) {
@@ -722,6 +816,28 @@ __global__ __launch_bounds__(256) void k_rk_adj(View<R> v, int stage, const doub
         double yb[1] = {obar[c]};
         reverse_unit<R, 1>(v, yb, [&](Acc<R>& A, Dual* out) { rk_stage(A, c, stage, out); }, overflow);
       });
+}
+
+// reinitialisation stage (3, 2 or 1) of one pseudo step: output adjoint
+// obar on the LS-active cells (the only ones the forward stage updates)
+template <class R>
+__global__ __launch_bounds__(256) void k_reinit_adj(View<R> v, int stage, int last, const double* obar, int* overflow) {
+  for_units(
+      v.N, [&](int c) { return (v.tag0[c] & T_ACT) != 0; },
+      [&](int c) {
+        double yb[1] = {obar[c]};
+        reverse_unit<R, 1>(v, yb, [&](Acc<R>& A, Dual* out) { reinit_stage(A, c, stage, last != 0, out); },
+                           overflow);
+      });
+}
+
+// adjoint of the level set before the reinitialisation on the LS-active
+// cells: the first pseudo step's input plus the smoothed-sign / fix
+// reference (the same values); elsewhere the level set passed through
+__global__ __launch_bounds__(256) void k_reinit_finish(const uint8_t* tag0, const double* rphibar, const double* p0bar,
+                                                       double* phibar, int N) {
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < N; c += gridDim.x * 256)
+    if (tag0[c] & T_ACT) phibar[c] = rphibar[c] + p0bar[c];
 }
 
 // extension sweep: adjoint of the sweep's output (AR_UTOUT) into the

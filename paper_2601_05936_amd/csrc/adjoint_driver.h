@@ -41,9 +41,12 @@ struct AdjDriver {
 
   static void record(lsb_plan* p, int nsteps, hipStream_t st) {
     const int sched = p->schedule;
+    const lsb_params& P = p->P;
     p->schedule = LSB_SCHED_SERIAL;
+    p->adj.reinit_at.assign((size_t)nsteps, 0);
     for (int k = 0; k < nsteps; ++k) {
       snapshot_state(p, k, st);
+      p->adj.reinit_at[k] = P.reinit_every > 0 && P.n_reinit > 0 && ((p->nstep + 1) % P.reinit_every) == 0;
       p->adj.rec_slot = k;
       F::step(p, st);
       p->adj.rec_slot = -1;
@@ -88,6 +91,7 @@ struct AdjDriver {
     }
     v.band = (double)a.band;
     v.ext_dtau = (double)a.ext_dtau;
+    v.reinit_dtau = (double)a.reinit_dtau;
     v.heps = (double)a.heps;
     // adjoint roles: index r holds the adjoint of step n + 1's state, r ^ 1
     // receives that of step n
@@ -164,6 +168,8 @@ struct AdjDriver {
     adj::k_refill_take<R><<<g, 256, 0, st>>>(v, dbl(p, s.o_ytmp));
     adj::k_refill_adj<R><<<gu, 256, 0, st>>>(v, dbl(p, s.o_ytmp), flag);
     adj::k_geometry_adj<R><<<gu, 256, 0, st>>>(v, 1, adj::AR_PHI1, dbl(p, s.o_Gbar[r]), flag);
+    // reinitialisation (on the steps that ran one)
+    if (s.reinit_at[n]) reverse_reinit(p, n, v, st);
     // TVD-RK3 stages, velocity of the last extension sweep
     const size_t lvl = 3 * N * p->bytes_real;
     const int ne = p->P.n_ext;
@@ -199,6 +205,44 @@ struct AdjDriver {
     zero(p, s.o_s1bar, N, st);
     zero(p, s.o_s2bar, N, st);
     s.role = r ^ 1;
+  }
+
+  // Reverse of the reinitialisation of step n: pseudo steps last to first,
+  // stages 3, 2, 1.  On entry phibar[role] holds the adjoint of its output
+  // (phi_{n+1}); on return, on the LS-active cells, the adjoint of its
+  // input (the level set after the advection).
+  static void reverse_reinit(lsb_plan* p, int n, V v, hipStream_t st) {
+    AdjState& s = p->adj;
+    const long N = p->N;
+    const int r = s.role;
+    const int gu = grid_units(p);
+    int* flag = reinterpret_cast<int*>(sc(p) + AdjState::SC_FLAG);
+    char* s0 = slot(p, n);
+    const size_t lvl = (size_t)N * p->bytes_real;
+    const int nr = p->P.n_reinit;
+    v.val[adj::AR_P0] = reinterpret_cast<const R*>(s0 + s.s_p0);
+    v.bar[adj::AR_P0] = dbl(p, s.o_p0bar);
+    v.bar[adj::AR_RS1] = dbl(p, s.o_rs1bar);
+    v.bar[adj::AR_RS2] = dbl(p, s.o_rs2bar);
+    zero(p, s.o_p0bar, N, st);
+    const double* ob = dbl(p, s.o_phibar[r]);
+    int cur = 0;
+    for (int k = nr - 1; k >= 0; --k) {
+      const char* base = s0 + s.s_rein + (size_t)3 * k * lvl;
+      v.val[adj::AR_RPHI] = reinterpret_cast<const R*>(base);
+      v.val[adj::AR_RS1] = reinterpret_cast<const R*>(base + lvl);
+      v.val[adj::AR_RS2] = reinterpret_cast<const R*>(base + 2 * lvl);
+      v.bar[adj::AR_RPHI] = dbl(p, s.o_rphibar[cur]);
+      zero(p, s.o_rphibar[cur], N, st);
+      zero(p, s.o_rs1bar, N, st);
+      zero(p, s.o_rs2bar, N, st);
+      adj::k_reinit_adj<R><<<gu, 256, 0, st>>>(v, 3, k == nr - 1 ? 1 : 0, ob, flag);
+      adj::k_reinit_adj<R><<<gu, 256, 0, st>>>(v, 2, 0, dbl(p, s.o_rs2bar), flag);
+      adj::k_reinit_adj<R><<<gu, 256, 0, st>>>(v, 1, 0, dbl(p, s.o_rs1bar), flag);
+      ob = dbl(p, s.o_rphibar[cur]);
+      cur ^= 1;
+    }
+    adj::k_reinit_finish<<<grid(p), 256, 0, st>>>(v.tag0, ob, dbl(p, s.o_p0bar), dbl(p, s.o_phibar[r]), p->N);
   }
 
   static void reverse(lsb_plan* p, hipStream_t st) {

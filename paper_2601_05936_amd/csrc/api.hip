@@ -94,6 +94,12 @@ int lsb_create(const lsb_params* P, lsb_plan** out) {
   }
   if (P->lattice == LSB_D2Q9 && P->bc[4] != LSB_PERIODIC) return fail(LSB_EINVAL, "2D grids need periodic z faces");
   if (!(P->tau[0] > 0.5) || !(P->tau[1] > 0.5)) return fail(LSB_EINVAL, "tau must exceed 1/2");
+  for (int k = 0; k < 2; ++k) {
+    if (P->collision[k] != LSB_BGK && P->collision[k] != LSB_CUMULANT)
+      return fail(LSB_EINVAL, "unknown collision operator");
+    if (P->collision[k] == LSB_CUMULANT && P->lattice != LSB_D3Q27)
+      return fail(LSB_EINVAL, "the cumulant collision needs D3Q27");
+  }
   if (!(P->rho_phys[0] > 0) || !(P->rho_phys[1] > 0)) return fail(LSB_EINVAL, "physical densities must be positive");
   if (!(P->band >= 2.0)) return fail(LSB_EINVAL, "band must be at least 2 cells");
   if (P->n_ext < 0 || P->n_reinit < 0 || P->reinit_every < 0) return fail(LSB_EINVAL, "negative iteration count");
@@ -567,6 +573,9 @@ static void adj_layout(const lsb_plan* p, int max_steps, lsb::AdjState& s, size_
   s.s_ut = take((size_t)(p->P.n_ext + 1) * 3 * N * rb);
   s.s_s1 = take(N * rb);
   s.s_s2 = take(N * rb);
+  const bool rein = p->P.reinit_every > 0 && p->P.n_reinit > 0;
+  s.s_p0 = take(rein ? N * rb : 0);
+  s.s_rein = take(rein ? (size_t)3 * p->P.n_reinit * N * rb : 0);
   s.stride = o;
   o = 0;
   s.o_snap = take((size_t)(max_steps + 1) * s.stride);
@@ -579,6 +588,10 @@ static void adj_layout(const lsb_plan* p, int max_steps, lsb::AdjState& s, size_
   }
   s.o_s1bar = take(N * sizeof(double));
   s.o_s2bar = take(N * sizeof(double));
+  for (int r = 0; r < 2; ++r) s.o_rphibar[r] = take(rein ? N * sizeof(double) : 0);
+  s.o_rs1bar = take(rein ? N * sizeof(double) : 0);
+  s.o_rs2bar = take(rein ? N * sizeof(double) : 0);
+  s.o_p0bar = take(rein ? N * sizeof(double) : 0);
   s.o_ytmp = take(19 * N * sizeof(double));
   s.o_scal = take(lsb::AdjState::SC_NUM * sizeof(double));
   s.o_partial = take(2 * lsb::AdjState::kInitBlocks * sizeof(double));
@@ -589,8 +602,6 @@ static int adj_check(const lsb_plan* p) {
   if (!p) return fail(LSB_EINVAL, "null plan");
   if (!p->adj_ops)
     return fail(LSB_EINVAL, "the reverse mode needs the D2Q9 lattice with LSB_F64 or LSB_F32 storage");
-  if (p->P.reinit_every > 0 && p->P.n_reinit > 0)
-    return fail(LSB_EINVAL, "the reverse mode does not differentiate the reinitialisation (set n_reinit = 0)");
   return LSB_OK;
 }
 

@@ -189,6 +189,7 @@ struct KArgs {
   int bcf[6];         // face conditions
   R wall_u[6][3];
   R omega[2];
+  int cum[2];         // phase uses the cumulant collision (D3Q27)
   R acc[2][3];
   R rho_phys[2];
   R eta[2];

@@ -27,6 +27,7 @@ struct Driver {
     for (int k = 0; k < 2; ++k) {
       const double nu = (P.tau[k] - 0.5) / 3.0;
       a.omega[k] = (R)((1.0 / 3.0) / (nu + 0.5 / 3.0));
+      a.cum[k] = P.collision[k] == LSB_CUMULANT;
       for (int m = 0; m < 3; ++m) a.acc[k][m] = (R)P.accel[k][m];
       a.rho_phys[k] = (R)P.rho_phys[k];
       a.eta[k] = (R)(P.rho_phys[k] * nu);
@@ -144,8 +145,15 @@ struct Driver {
   static void bulk(const Args& a, bool force, int xchunks, int rows, hipStream_t st) {
     const unsigned g = (unsigned)(xchunks * rows);
     const size_t dyn = ST == LSB_F32 ? 32768 : 0;
-    if (force) k_lb_bulk<LAT, ST, SPLIT, true><<<g, 256, dyn, st>>>(a, xchunks);
-    else k_lb_bulk<LAT, ST, SPLIT, false><<<g, 256, dyn, st>>>(a, xchunks);
+    if constexpr (LAT == LSB_D3Q27) {
+      if (a.cum[0] || a.cum[1]) {
+        if (force) k_lb_bulk<LAT, ST, SPLIT, true, true><<<g, 256, dyn, st>>>(a, xchunks);
+        else k_lb_bulk<LAT, ST, SPLIT, false, true><<<g, 256, dyn, st>>>(a, xchunks);
+        return;
+      }
+    }
+    if (force) k_lb_bulk<LAT, ST, SPLIT, true, false><<<g, 256, dyn, st>>>(a, xchunks);
+    else k_lb_bulk<LAT, ST, SPLIT, false, false><<<g, 256, dyn, st>>>(a, xchunks);
   }
 
   // copy of a step intermediate into the snapshot slot being recorded
@@ -216,10 +224,18 @@ struct Driver {
     }
     // a7: reinitialisation
     if (P.reinit_every > 0 && P.n_reinit > 0 && ((p->nstep + 1) % P.reinit_every) == 0) {
+      // recording: the level set before the reinitialisation, then each
+      // stage's input (phi of the pseudo step, s1, s2)
+      if (recording) rec(p, p->adj.s_p0, a.phi, N * rb, st);
       k_reinit_prep<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
       for (int it = 0; it < P.n_reinit; ++it)
-        for (int stage = 1; stage <= 3; ++stage)
+        for (int stage = 1; stage <= 3; ++stage) {
+          if (recording) {
+            const R* in = stage == 1 ? a.phi : (stage == 2 ? a.s1 : a.s2);
+            rec(p, p->adj.s_rein + (size_t)(3 * it + stage - 1) * N * rb, in, N * rb, st);
+          }
           k_reinit_stage<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a, stage, it == P.n_reinit - 1 ? 1 : 0);
+        }
     }
     k_ls_sync<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
     // a8: classification on the candidate tiles, geometry, refill

@@ -46,8 +46,126 @@ __device__ __forceinline__ T* pop_at(T* base, size_t dir_base, unsigned byte_off
   return reinterpret_cast<T*>(reinterpret_cast<char*>(base + dir_base) + byte_off);
 }
 
-// FORCE = false drops the body-force terms (a launch for zero acceleration).
-template <int LAT, int ST, bool FORCE = true>
+// ---------------------------------------------------------------------------
+// Cumulant collision (Sec. 2.1, D3Q27) with the paper's rates: omega_1 =
+// omega_BGK for the shear (deviatoric second-order) cumulants, one for every
+// other cumulant.  With those rates the post-collision cumulants of order
+// three and more vanish and the second-order ones become
+// cs^2 delta + (1 - omega) dev(kappa_2), so the post-collision central
+// moments are those of a Gaussian with that covariance (sums over pairings),
+// and the populations follow from the central moments by one inverse
+// transform per axis (z, then y, then x), each a three-point relation on the
+// lines of the 3x3x3 moment array.  Every quantity is carried as its
+// deviation from the rest state (populations f - w, central moments minus
+// their rest values), so FP32 arithmetic loses nothing to cancellation.
+// Index of the moment array: a + 3 b + 9 c for the orders (a, b, c) in
+// (x, y, z), or the position (cx + 1) + 3 (cy + 1) + 9 (cz + 1) once all
+// three axes are transformed (the code of the direction).
+// ---------------------------------------------------------------------------
+namespace cum {
+__host__ __device__ constexpr double rest_moment(int a) { return a == 0 ? 1.0 : (a == 1 ? 0.0 : 1.0 / 3.0); }
+__host__ __device__ constexpr double rest_weight(int slot) { return slot == 1 ? 2.0 / 3.0 : 1.0 / 6.0; }
+
+// One line: (g0, g1, g2) are the deviations of the central moments of
+// orders 0, 1, 2 about velocity u (rest values k0r, 0, .); on return they
+// are the deviations of the line's values at c = -1, 0, +1.
+template <class R>
+__device__ __forceinline__ void line(R k0r, R& g0, R& g1, R& g2, R u) {
+  const R k0 = k0r + g0;
+  const R m1 = g1 + u * k0;
+  const R m2 = g2 + u * ((R)2 * g1 + u * k0);
+  const R vm = (R)0.5 * (m2 - m1);
+  const R vz = g0 - m2;
+  const R vp = (R)0.5 * (m2 + m1);
+  g0 = vm;
+  g1 = vz;
+  g2 = vp;
+}
+}  // namespace cum
+
+// d: incoming deviations (paper order); out: post-collision deviations
+// without the body force.
+template <class R>
+__device__ __forceinline__ void cumulant_collide(const R* d, R om, R* out) {
+  using L = Lat<LSB_D3Q27>;
+  R rp = 0, jx = 0, jy = 0, jz = 0, sxx = 0, syy = 0, szz = 0, sxy = 0, sxz = 0, syz = 0;
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
+    const R v = d[i];
+    rp += v;
+    if (cx) { jx += (R)cx * v; sxx += v; }
+    if (cy) { jy += (R)cy * v; syy += v; }
+    if (cz) { jz += (R)cz * v; szz += v; }
+    if (cx * cy) sxy += (R)(cx * cy) * v;
+    if (cx * cz) sxz += (R)(cx * cz) * v;
+    if (cy * cz) syz += (R)(cy * cz) * v;
+  }
+  const R rho = (R)1 + rp;
+  const R inv = (R)1 / rho;
+  const R ux = jx * inv, uy = jy * inv, uz = jz * inv;
+  const R third = (R)(1.0 / 3.0);
+  // central second moments per unit density minus cs^2 delta
+  const R rp3 = rp * third;
+  const R exx = (sxx - rp3) * inv - ux * ux;
+  const R eyy = (syy - rp3) * inv - uy * uy;
+  const R ezz = (szz - rp3) * inv - uz * uz;
+  const R exy = sxy * inv - ux * uy;
+  const R exz = sxz * inv - ux * uz;
+  const R eyz = syz * inv - uy * uz;
+  // post-collision covariance minus cs^2 delta: relaxed deviatoric part
+  // (the trace relaxes to cs^2 at rate one)
+  const R oc = (R)1 - om;
+  const R t3 = (exx + eyy + ezz) * third;
+  const R axx = oc * (exx - t3), ayy = oc * (eyy - t3), azz = oc * (ezz - t3);
+  const R axy = oc * exy, axz = oc * exz, ayz = oc * eyz;
+  // deviations of the central moments (times rho) from the rest values
+  R g[27];
+#pragma unroll
+  for (int m = 0; m < 27; ++m) g[m] = (R)0;
+  g[0] = rp;
+  g[2] = rp3 + rho * axx;
+  g[6] = rp3 + rho * ayy;
+  g[18] = rp3 + rho * azz;
+  g[1 + 3] = rho * axy;
+  g[1 + 9] = rho * axz;
+  g[3 + 9] = rho * ayz;
+  const R rp9 = rp * (R)(1.0 / 9.0);
+  g[2 + 6] = rp9 + rho * ((axx + ayy) * third + axx * ayy + (R)2 * axy * axy);
+  g[2 + 18] = rp9 + rho * ((axx + azz) * third + axx * azz + (R)2 * axz * axz);
+  g[6 + 18] = rp9 + rho * ((ayy + azz) * third + ayy * azz + (R)2 * ayz * ayz);
+  g[2 + 3 + 9] = rho * ((third + axx) * ayz + (R)2 * axy * axz);
+  g[1 + 6 + 9] = rho * ((third + ayy) * axz + (R)2 * axy * ayz);
+  g[1 + 3 + 18] = rho * ((third + azz) * axy + (R)2 * axz * ayz);
+  g[2 + 6 + 18] = rp * (R)(1.0 / 27.0) +
+                  rho * ((axx + ayy + azz) * (R)(1.0 / 9.0) + (axx * ayy + axx * azz + ayy * azz) * third +
+                         axx * ayy * azz + (R)2 * (third + axx) * ayz * ayz + (R)2 * (third + ayy) * axz * axz +
+                         (R)2 * (third + azz) * axy * axy + (R)8 * axy * axz * ayz);
+  // inverse transforms: z orders -> z positions, then y, then x
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      cum::line((R)(cum::rest_moment(a) * cum::rest_moment(b)), g[a + 3 * b], g[a + 3 * b + 9], g[a + 3 * b + 18], uz);
+#pragma unroll
+  for (int zc = 0; zc < 3; ++zc)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      cum::line((R)(cum::rest_moment(a) * cum::rest_weight(zc)), g[a + 9 * zc], g[a + 3 + 9 * zc], g[a + 6 + 9 * zc], uy);
+#pragma unroll
+  for (int zc = 0; zc < 3; ++zc)
+#pragma unroll
+    for (int yc = 0; yc < 3; ++yc)
+      cum::line((R)(cum::rest_weight(yc) * cum::rest_weight(zc)), g[3 * yc + 9 * zc], g[1 + 3 * yc + 9 * zc],
+                g[2 + 3 * yc + 9 * zc], ux);
+#pragma unroll
+  for (int i = 0; i < 27; ++i) out[i] = g[detail::d3q27_code(i)];
+}
+
+// FORCE = false drops the body-force terms (a launch for zero acceleration);
+// CUM = false leaves out the cumulant operator (a launch where both phases
+// use BGK).
+template <int LAT, int ST, bool FORCE = true, bool CUM = true>
 __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args& a, int c, int k, bool active,
                                               typename Step<LAT, ST>::R* d) {
   using S = Step<LAT, ST>;
@@ -83,6 +201,25 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
   const R s = a.scale;
   const size_t N = a.N;
   const unsigned cb = (unsigned)c * (unsigned)sizeof(T);  // byte offset of the cell in a direction array
+  bool cum_phase = false;
+  if constexpr (LAT == LSB_D3Q27 && CUM) cum_phase = sel2(a.cum, k) != 0;
+  if (cum_phase) {
+    R out[Q];
+    cumulant_collide(d, om, out);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      R v = out[i];
+      if (FORCE) {
+        const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
+        R ca = 0;
+        if (cx) ca += (R)cx * fx;
+        if (cy) ca += (R)cy * fy;
+        if (cz) ca += (R)cz * fz;
+        v += (R)wgt<LAT>(i) * ca;
+      }
+      store_pop(pop_at(a.An, (size_t)i * N, cb), C::enc(v, (R)(1.0 / wgt<LAT>(i)), s));
+    }
+  } else {
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int j = opp<LAT>(i);
@@ -109,6 +246,7 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
     }
     store_pop(pop_at(a.An, (size_t)i * N, cb), C::enc(out_i, (R)(1.0 / wgt<LAT>(i)), s));
     store_pop(pop_at(a.An, (size_t)j * N, cb), C::enc(out_j, (R)(1.0 / wgt<LAT>(j)), s));
+  }
   }
   if (active) {
     // strain rate from the second moment of f - f^eq (pairs: 2 x even part)
@@ -232,7 +370,7 @@ __device__ __forceinline__ void for_tile_cells(const Args& a, const int* list, i
 // a2 for one cell with no lattice link to the other phase or through a wall:
 // branch-free gather (per-direction base pointer plus a 32-bit cell offset).
 // ---------------------------------------------------------------------------
-template <int LAT, int ST, bool FORCE = true>
+template <int LAT, int ST, bool FORCE = true, bool CUM = true>
 __device__ __forceinline__ void fast_cell(const typename Step<LAT, ST>::Args& a, int c, int x, int y, int z, uint8_t t) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
@@ -259,7 +397,7 @@ __device__ __forceinline__ void fast_cell(const typename Step<LAT, ST>::Args& a,
     const unsigned off = (unsigned)(rowoff[L::cz(i) + 1][L::cy(i) + 1] + xs[L::cx(i) + 1]) * (unsigned)sizeof(T);
     d[i] = C::dec(*reinterpret_cast<const T*>(Ai + off), (R)wgt<LAT>(i), is);
   }
-  collide_store<LAT, ST, FORCE>(a, c, t & T_GAS, (t & T_ACT) != 0, d);
+  collide_store<LAT, ST, FORCE, CUM>(a, c, t & T_GAS, (t & T_ACT) != 0, d);
 }
 
 // a2/a3 for a wall-adjacent cell with no lattice link to the other phase.
@@ -304,7 +442,7 @@ __device__ __forceinline__ int tile_of(const Args& a, int x, int y, int z) {
 // the interface or refill kernels update, so this part writes no moments and
 // reads nothing the level-set chain writes except the LS-active bit of tags
 // (masked).  It may run concurrently with the level-set chain.
-template <int LAT, int ST, bool SPLIT, bool FORCE>
+template <int LAT, int ST, bool SPLIT, bool FORCE, bool CUM>
 __global__ __launch_bounds__(256) void k_lb_bulk(const typename Step<LAT, ST>::Args a, int xchunks) {
   const unsigned b = remap_xcd(blockIdx.x, gridDim.x);
   const int row = (int)(b / (unsigned)xchunks);
@@ -316,7 +454,7 @@ __global__ __launch_bounds__(256) void k_lb_bulk(const typename Step<LAT, ST>::A
   if (SPLIT && a.cand_prev[tile_of<Step<LAT, ST>::D>(a, x, y, z)]) return;
   const uint8_t t = a.tag[c];
   if (t & (T_SPEC | T_WALL)) return;
-  fast_cell<LAT, ST, FORCE>(a, c, x, y, z, SPLIT ? (uint8_t)(t & ~T_ACT) : t);
+  fast_cell<LAT, ST, FORCE, CUM>(a, c, x, y, z, SPLIT ? (uint8_t)(t & ~T_ACT) : t);
 }
 
 // Band part of the collide-stream: the non-interface, non-wall cells of the
@@ -599,6 +737,9 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
     const R uu = ux * ux + uy * uy + uz * uz;
     const R om = sel2(a.omega, k);
     const R fx = (R)3 * ACC(a, k, 0), fy = (R)3 * ACC(a, k, 1), fz = (R)3 * ACC(a, k, 2);
+    bool cum_phase = false;
+    if constexpr (LAT == LSB_D3Q27) cum_phase = sel2(a.cum, k) != 0;
+    // strain-rate moments of the incoming populations; BGK stores here
     R P0 = 0, P1 = 0, P2 = 0, P3 = 0, P4 = 0, P5 = 0;
 #pragma unroll 1
     for (int i = 0; i < Q; ++i) {
@@ -610,8 +751,26 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
       const R fn = f - deq;
       P0 += cx * cx * fn; P1 += cy * cy * fn; P2 += cz * cz * fn;
       P3 += cx * cy * fn; P4 += cx * cz * fn; P5 += cy * cz * fn;
+      if (cum_phase) continue;
       const R ca = cx * fx + cy * fy + cz * fz;
       store_pop(&a.An[(size_t)i * N + c], C::enc(f - om * fn + w * rho * ca, twinv<LAT, R>(i), s));
+    }
+    if constexpr (LAT == LSB_D3Q27) {
+      if (cum_phase) {
+        R dl[Q], out[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) dl[i] = fl[i * 256 + threadIdx.x];
+        cumulant_collide(dl, om, out);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          using L = typename S::L;
+          R ca = 0;
+          if (L::cx(i)) ca += (R)L::cx(i) * fx;
+          if (L::cy(i)) ca += (R)L::cy(i) * fy;
+          if (L::cz(i)) ca += (R)L::cz(i) * fz;
+          store_pop(&a.An[(size_t)i * N + c], C::enc(out[i] + (R)wgt<LAT>(i) * rho * ca, (R)(1.0 / wgt<LAT>(i)), s));
+        }
+      }
     }
     if (active) {
       const R fac = -(R)1.5 * om * inv;

@@ -52,8 +52,11 @@ struct AdjState {
   int max_steps = 0;
   size_t stride = 0, o_snap = 0;  // snapshot slot size and offset of slot 0
   size_t s_A = 0, s_M = 0, s_phi = 0, s_G = 0, s_tag = 0, s_scal = 0, s_Mn = 0, s_ut = 0, s_s1 = 0, s_s2 = 0;
+  size_t s_p0 = 0, s_rein = 0;  // reinitialisation: level set before it, stage inputs of every pseudo step
   size_t o_Abar[2] = {0, 0}, o_Mbar[2] = {0, 0}, o_phibar[2] = {0, 0}, o_Gbar[2] = {0, 0}, o_utbar[2] = {0, 0};
   size_t o_s1bar = 0, o_s2bar = 0, o_ytmp = 0, o_scal = 0, o_partial = 0;
+  size_t o_rphibar[2] = {0, 0}, o_rs1bar = 0, o_rs2bar = 0, o_p0bar = 0;
+  std::vector<unsigned char> reinit_at;  // per recorded step: the step reinitialised
   int role = 0;       // adjoint buffers holding the adjoint of the latest state
   int nrec = 0;       // steps of the recorded segment
   int rec_slot = -1;  // slot written by the step being recorded

@@ -35,7 +35,7 @@ class Params(C.Structure):
         ("sigma", C.c_double), ("band", C.c_double), ("n_ext", C.c_int), ("ext_dtau", C.c_double),
         ("reinit_every", C.c_int), ("n_reinit", C.c_int), ("reinit_dtau", C.c_double),
         ("heaviside_eps", C.c_double), ("use_pb", C.c_int), ("pb0", C.c_double),
-        ("init_hydrostatic", C.c_int), ("fp16_scale_log2", C.c_int),
+        ("init_hydrostatic", C.c_int), ("fp16_scale_log2", C.c_int), ("collision", C.c_int * 2),
     ]
 
 
@@ -118,6 +118,9 @@ def to_params(p: dict) -> Params:
             for i in range(2):
                 for a in range(3):
                     s.accel[i][a] = float(v[i][a])
+        elif k == "collision":
+            for i in range(2):
+                s.collision[i] = int(v[i])
         else:
             setattr(s, k, v)
     return s

@@ -44,6 +44,8 @@ def _create(p):
 @pytest.mark.parametrize("bad", [
     dict(lattice=7), dict(storage=9), dict(nz=3),  # D2Q9 with nz != 1
     dict(tau=[0.5, 0.8]), dict(band=1.0), dict(bc=[0, 1, 0, 0, 0, 0]), dict(nx=2),
+    dict(collision=[W.BGK, W.CUMULANT]),  # cumulant needs D3Q27
+    dict(collision=[2, W.BGK]),  # unknown operator
 ])
 def test_create_rejects_invalid_parameters(bad):
     p = W.default_params(lattice=W.D2Q9, nx=16, ny=16, nz=1,

@@ -7,7 +7,9 @@ numbers, so on the FP64 path the two must agree to rounding: the gate is
 1e-9 relative for dL/dsigma and for <dL/dphi0, v>, v random on the band
 (numpy default_rng(12345)).  The cases move the interface (cells change
 phase, so the refill is reversed too), have walls of both kinds and the gas
-pressure baseline, and use checkpoint segments with a ragged last one.
+pressure baseline, and use checkpoint segments with a ragged last one; two
+of them run the reinitialisation (its Godunov branches and subcell-fix set
+frozen like every other decision).
 """
 import numpy as np
 import pytest
@@ -30,10 +32,17 @@ def _cases():
     bub = W.seeded_bubble(5, lattice=W.D2Q9, shape=(45, 38, 1), g=1e-4, u_amp=0.03)
     bub["params"].update(reinit_every=0, n_reinit=0)
     rise = W.rising_bubble_2d(nx=48, ny=64, radius=8.0, yc=22.0, g=4e-5, sigma=5e-3, storage=W.F64)
-    return {"seeded": (bub, 30, 12), "rising": (rise, 36, 10)}
+    # the reinitialisation differentiated too: every 5 / 6 steps, 3 pseudo
+    # steps, reinitialised steps at several positions of the segments
+    bub_r = W.seeded_bubble(5, lattice=W.D2Q9, shape=(45, 38, 1), g=1e-4, u_amp=0.03)
+    bub_r["params"].update(reinit_every=5, n_reinit=3)
+    rise_r = W.rising_bubble_2d(nx=48, ny=64, radius=8.0, yc=22.0, g=4e-5, sigma=5e-3, storage=W.F64)
+    rise_r["params"].update(reinit_every=6, n_reinit=3)
+    return {"seeded": (bub, 30, 12), "rising": (rise, 36, 10), "seeded_reinit": (bub_r, 30, 12),
+            "rising_reinit": (rise_r, 36, 10)}
 
 
-@pytest.mark.parametrize("name", ["seeded", "rising"])
+@pytest.mark.parametrize("name", ["seeded", "rising", "seeded_reinit", "rising_reinit"])
 def test_adjoint_matches_oracle_tangent(require_gpu, name):
     import torch
     import oracle as O
