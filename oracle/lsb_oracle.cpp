@@ -396,6 +396,12 @@ struct Sim {
   std::vector<T> nrm, kap;              // interface normal and curvature (LS-active cells)
   std::vector<T> ut, ut2;               // extension velocity
   T sig, Pb;
+  // several bubbles (use_pb = 2): component of each cell in the support of
+  // the smoothed Heaviside (-1 outside), the baseline of each cell's
+  // component, and per component volume, centroid and baseline
+  std::vector<int> bub;
+  std::vector<T> pbc;
+  std::vector<T> bvol, bxc, bpb;
   T xc0[3];
   long nstep = 0;
   bool all_active = false;              // component tests: treat every cell as LS-active
@@ -462,10 +468,12 @@ struct Sim {
   // Phase pressures.  Each phase solver keeps its own LB density near 1; the
   // physical density enters through p = rho_phys cs^2 (rho_LB - 1) (reading:
   // the paper does not say how the density ratio is represented).  The gas
-  // carries the pressure baseline Pb.
-  T pressure(int k, const T& rho) const {
+  // carries the pressure baseline: Pb, or with several bubbles the baseline
+  // of the bubble the cell c belongs to.
+  T baseline(long c) const { return P.use_pb == 2 ? pbc[c] : Pb; }
+  T pressure(int k, const T& rho, long c) const {
     T p = P.rho_phys[k] * CS2 * (rho - 1.0);
-    if (k == 1) p = p + Pb;
+    if (k == 1) p = p + baseline(c);
     return p;
   }
 
@@ -494,8 +502,8 @@ struct Sim {
     // Pressures carried to the link point with each phase's own body
     // acceleration (hydrostatic shift; reading).
     const int o = 1 - k;
-    T p_own = pressure(k, Mr[c]);
-    T p_oth = pressure(o, Mr[s]);
+    T p_own = pressure(k, Mr[c], c);
+    T p_oth = pressure(o, Mr[s], s);
     for (int a = 0; a < 3; ++a) {
       p_own = p_own + P.rho_phys[k] * P.accel[k][a] * (-(double)ci[a]) * q;
       p_oth = p_oth + P.rho_phys[o] * P.accel[o][a] * (double)ci[a] * (1.0 - q);
@@ -989,9 +997,9 @@ struct Sim {
       // stress condition reduced to the Laplace jump.
       T rhoO = Mr1[c];
       T uG[3] = {Mu1[3 * c], Mu1[3 * c + 1], Mu1[3 * c + 2]};
-      T pold = pressure(kold, rhoO);
+      T pold = pressure(kold, rhoO, c);
       T pnew = (knew == 0) ? pold + sig * kap[c] : pold - sig * kap[c];
-      T rhoG = 1.0 + (pnew - (knew == 1 ? Pb : T(0.0))) / (P.rho_phys[knew] * CS2);
+      T rhoG = 1.0 + (pnew - (knew == 1 ? baseline(c) : T(0.0))) / (P.rho_phys[knew] * CS2);
       auto established = [&](long s) { return gas[s] == knew && gas1[s] == knew; };
       bool done = false;
       for (int t = 0; t < nc && !done; ++t) {
@@ -1067,7 +1075,66 @@ struct Sim {
     for (int a = 0; a < 3; ++a) xc[a] = (val(V) > 0.0) ? s[a] / V : T(0.0);
   }
 
+  // Several bubbles (reading; the paper gives no pressure level for the
+  // gas of several bubbles): every connected component of the support of
+  // the smoothed Heaviside (phi > -eps, cells joined by the lattice links,
+  // periodic faces wrapping) is a bubble, numbered by its smallest cell
+  // index, with the baseline of the single-bubble case taken at its own
+  // centroid: Pb_k = pb0 + rho_l a_l . (x_c,k - x_c0), x_c0 the initial
+  // centroid of all gas (the hydrostatic reference of the liquid).
+  void update_bubbles() {
+    const double eps = P.heaviside_eps;
+    bub.assign(N, -1);
+    int nb_ = 0;
+    std::vector<long> queue;
+    for (long c0 = 0; c0 < N; ++c0) {
+      if (bub[c0] >= 0 || !(val(phi[c0]) > -eps)) continue;
+      const int id = nb_++;
+      bub[c0] = id;
+      queue.assign(1, c0);
+      for (size_t h = 0; h < queue.size(); ++h) {
+        int x, y, z;
+        coords(queue[h], x, y, z);
+        for (int i = 0; i < Q; ++i) {
+          if (L.c[i][0] == 0 && L.c[i][1] == 0 && L.c[i][2] == 0) continue;
+          long s;
+          if (!nb(x, y, z, L.c[i][0], L.c[i][1], L.c[i][2], s)) continue;
+          if (bub[s] >= 0 || !(val(phi[s]) > -eps)) continue;
+          bub[s] = id;
+          queue.push_back(s);
+        }
+      }
+    }
+    bvol.assign(nb_, T(0.0));
+    bxc.assign(3 * (size_t)nb_, T(0.0));
+    bpb.assign(nb_, T(0.0));
+    for (long c = 0; c < N; ++c) {
+      if (bub[c] < 0) continue;
+      T h = heaviside(phi[c], eps);
+      int x, y, z;
+      coords(c, x, y, z);
+      const int k = bub[c];
+      bvol[k] += h;
+      bxc[3 * k] += h * (x + 0.5); bxc[3 * k + 1] += h * (y + 0.5); bxc[3 * k + 2] += h * (z + 0.5);
+    }
+    for (int k = 0; k < nb_; ++k) {
+      T pb = T(P.pb0);
+      for (int a = 0; a < 3; ++a) {
+        bxc[3 * k + a] = val(bvol[k]) > 0.0 ? bxc[3 * k + a] / bvol[k] : T(0.0);
+        pb = pb + P.rho_phys[0] * P.accel[0][a] * (bxc[3 * k + a] - xc0[a]);
+      }
+      bpb[k] = pb;
+    }
+    pbc.assign(N, T(0.0));
+    for (long c = 0; c < N; ++c)
+      if (bub[c] >= 0) pbc[c] = bpb[bub[c]];
+  }
+
   void update_pb() {
+    if (P.use_pb == 2) {
+      update_bubbles();
+      return;
+    }
     if (!P.use_pb) return;
     T V, xc[3];
     centroid(V, xc);
@@ -1122,6 +1189,7 @@ struct Sim {
     T V;
     centroid(V, xc0);
     Pb = T(P.pb0);
+    if (P.use_pb == 2) update_bubbles();
     for (long c = 0; c < N; ++c) {
       int x, y, z;
       coords(c, x, y, z);
@@ -1131,9 +1199,12 @@ struct Sim {
       else {
         rho = T(1.0);
         if (P.init_hydrostatic) {
-          // Hydrostatic LB density of each phase about the initial centroid.
+          // Hydrostatic LB density of each phase about the initial centroid
+          // (with several bubbles, a gas cell about its own bubble's).
           double pos[3] = {x + 0.5, y + 0.5, z + 0.5};
-          for (int a = 0; a < 3; ++a) rho = rho + P.accel[k][a] * (pos[a] - xc0[a]) / CS2;
+          const T* ref = xc0;
+          if (P.use_pb == 2 && k == 1 && bub[c] >= 0) ref = &bxc[3 * (size_t)bub[c]];
+          for (int a = 0; a < 3; ++a) rho = rho + P.accel[k][a] * (pos[a] - ref[a]) / CS2;
         }
       }
       T u[3] = {T(0.0), T(0.0), T(0.0)};
@@ -1162,7 +1233,7 @@ struct Sim {
     }
     const int k = gas[c];
     for (int d = 0; d < 3; ++d) u[d] = m[d] / rho - 0.5 * P.accel[k][d];
-    p = pressure(k, rho);
+    p = pressure(k, rho, c);
   }
 };
 
@@ -1242,6 +1313,7 @@ static int check_params(const orc::Params* p) {
   for (int a = 0; a < 3; ++a)
     if ((p->bc[2 * a] == orc::BC_PERIODIC) != (p->bc[2 * a + 1] == orc::BC_PERIODIC)) return -1;
   if (p->tau[0] <= 0.5 || p->tau[1] <= 0.5) return -1;
+  if (p->use_pb < 0 || p->use_pb > 2) return -1;
   for (int k = 0; k < 2; ++k)
     if (p->collision[k] != 0 && (p->collision[k] != 1 || p->lattice != 2)) return -1;
   return 0;
@@ -1340,6 +1412,25 @@ int orc_get_moments(void* h, double* out) {
 
 // Integral quantities: mass[2], gas volume, centroid[3], bubble velocity[3],
 // Pb, max |u|, step.
+// Bubbles (use_pb = 2): count, and per bubble (numbered by smallest cell)
+// volume, centroid[3], baseline; labels[N] the bubble of each cell (-1
+// outside the Heaviside support).  Either output may be NULL.
+int orc_get_bubbles(void* h, int max, int* count, double* out, int* labels) {
+  Sim<double>* s = static_cast<Sim<double>*>(h);
+  if (s->P.use_pb != 2) return -1;
+  const int n = (int)s->bvol.size();
+  *count = n;
+  if (out)
+    for (int k = 0; k < n && k < max; ++k) {
+      out[5 * k] = s->bvol[k];
+      for (int a = 0; a < 3; ++a) out[5 * k + 1 + a] = s->bxc[3 * k + a];
+      out[5 * k + 4] = s->bpb[k];
+    }
+  if (labels)
+    for (long c = 0; c < s->N; ++c) labels[c] = s->bub[c];
+  return 0;
+}
+
 int orc_get_integrals(void* h, double* out) {
   Sim<double>* s = static_cast<Sim<double>*>(h);
   double mass[2] = {0, 0}, V = 0, xs[3] = {0, 0, 0}, us[3] = {0, 0, 0}, umax = 0;

@@ -94,6 +94,7 @@ def _load():
                                 C.POINTER(C.c_int)]
     lib.orc_feq.argtypes = [C.c_int, C.c_double, dp, dp]
     lib.orc_refill_weights.argtypes = [C.c_double, dp]
+    lib.orc_get_bubbles.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), dp, C.POINTER(C.c_int)]
     lib.orc_cumulants_points.argtypes = [C.c_int, dp, dp, dp]
     lib.orc_moments_from_cumulants.argtypes = [dp, dp]
     lib.orc_cumulant_collide.argtypes = [dp, C.c_double, C.c_double, C.c_double, dp, dp]
@@ -309,6 +310,20 @@ class Oracle:
         out = np.zeros(10 * self.N)
         self.lib.orc_get_moments(self.h, _dp(out))
         return out.reshape(self.shape + (10,))
+
+    def bubbles(self):
+        """Several-bubble mode: per bubble (numbered by smallest cell) volume,
+        centroid and baseline, and the bubble of every cell (-1 outside the
+        Heaviside support)."""
+        n = C.c_int()
+        assert self.lib.orc_get_bubbles(self.h, 0, C.byref(n), None, None) == 0
+        out = np.zeros(5 * max(n.value, 1))
+        lab = np.zeros(self.N, dtype=np.int32)
+        assert self.lib.orc_get_bubbles(self.h, n.value, C.byref(n), _dp(out),
+                                        lab.ctypes.data_as(C.POINTER(C.c_int))) == 0
+        b = out[:5 * n.value].reshape(-1, 5)
+        return dict(count=n.value, volume=b[:, 0].copy(), centroid=b[:, 1:4].copy(), pb=b[:, 4].copy(),
+                    labels=lab.reshape(self.shape))
 
     def integrals(self):
         out = np.zeros(16)

@@ -171,6 +171,57 @@ def wavy_phi(p: dict, amplitude: float, dtype=np.float64) -> np.ndarray:
 # Small seeded cases for parity tests.
 # ---------------------------------------------------------------------------
 
+def bubble_cluster(centers, radius, shape, lattice=D2Q9, g=1e-5, sigma=5e-3, rho_ratio=100.0, eta_ratio=10.0,
+                   tau_l=0.6, storage=F64, reinit_every=10, n_reinit=3, collision=None):
+    """Several gas bubbles of one radius in liquid, gravity along -y, one
+    gas-pressure baseline per bubble (use_pb = 2), hydrostatic start; no-slip
+    on the y faces, free slip on the others.  The level set is the union of
+    the bubbles' signed distances, max_k (R - |x - c_k|)."""
+    nx, ny, nz = shape
+    dim = 2 if lattice == D2Q9 else 3
+    rho = [1.0, 1.0 / rho_ratio]
+    eta_l = rho[0] * (tau_l - 0.5) / 3.0
+    bc = [FREESLIP, FREESLIP, NOSLIP, NOSLIP, PERIODIC, PERIODIC] if dim == 2 else \
+         [FREESLIP, FREESLIP, NOSLIP, NOSLIP, FREESLIP, FREESLIP]
+    p = default_params(lattice=lattice, storage=storage, nx=nx, ny=ny, nz=nz, bc=bc, rho_phys=rho,
+                       tau=[tau_l, tau_from_eta(eta_l / eta_ratio, rho[1])],
+                       accel=[[0.0, -g, 0.0], [0.0, -g, 0.0]], sigma=sigma, use_pb=2,
+                       pb0=sigma * (1.0 if dim == 2 else 2.0) / radius, init_hydrostatic=1,
+                       reinit_every=reinit_every, n_reinit=n_reinit,
+                       collision=list(collision) if collision else [BGK, BGK])
+    x, y, z = grid(p)
+    phi = np.full(x.shape, -1e30)
+    for c in centers:
+        d2 = (x - c[0]) ** 2 + (y - c[1]) ** 2 + ((z - c[2]) ** 2 if dim == 3 else 0.0)
+        phi = np.maximum(phi, radius - np.sqrt(d2))
+    return dict(params=p, phi0=phi, rho0=None, u0=None, steps=200,
+                name=f"{len(centers)} bubbles lattice={lattice} {nx}x{ny}x{nz}")
+
+
+def nine_bubble_cluster_3d(d=32, storage=F16DEV, steps=1000):
+    """The paper's cluster of nine rising bubbles (Sec. 3, last case) as a
+    synthetic layout: domain 10 x 20 x 10 bubble diameters, gravity along
+    -y, a lower layer of five bubbles (one at the axis, four on the
+    diagonals 1.5 d off it) two diameters above the floor and an upper layer
+    of four (0.75 d off the axis on the diagonals) two diameters higher;
+    the physical parameters of the single 3D rising bubble (Eo 10,
+    Mo 1e-3, density ratio 1000, viscosity ratio 100) with the paper's 3D
+    pairing of collision operators (BGK liquid, cumulant gas)."""
+    nx, ny, nz = 10 * d, 20 * d, 10 * d
+    R = d / 2.0
+    g = 1e-5
+    ref = rising_bubble_3d(nx=8, ny=8, nz=8, radius=R, zc=4.0, g=g)["params"]
+    cx, cz = nx / 2.0, nz / 2.0
+    y0, y1 = 2.0 * d, 4.0 * d
+    centers = [(cx, y0, cz)] + [(cx + sx * 1.5 * d, y0, cz + sz * 1.5 * d) for sx in (-1, 1) for sz in (-1, 1)]
+    centers += [(cx + sx * 0.75 * d, y1, cz + sz * 0.75 * d) for sx in (-1, 1) for sz in (-1, 1)]
+    w = bubble_cluster(centers, R, (nx, ny, nz), lattice=D3Q27, g=g, sigma=ref["sigma"], rho_ratio=1000.0,
+                       eta_ratio=100.0, tau_l=ref["tau"][0], storage=storage, collision=[BGK, CUMULANT])
+    w["steps"] = steps
+    w["name"] = f"nine-bubble cluster D3Q27 {nx}x{ny}x{nz}"
+    return w
+
+
 def seeded_bubble(seed: int, lattice=D2Q9, shape=(37, 29, 1), storage=F64, gas_inside=True,
                   u_amp=0.02, sigma=2e-3, rho_ratio=10.0, eta_ratio=5.0, g=0.0, walls="mixed"):
     """A randomly placed circle/sphere with a seeded random initial velocity
