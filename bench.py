@@ -42,18 +42,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_mode(size, storage, steps, warmup, schedule, cumulant_gas=False):
+def run_mode(size, storage, steps, warmup, schedule, cumulant_gas=False, workload="wavy"):
     import torch
 
     from paper_2601_05936_amd import workloads as W
     from paper_2601_05936_amd.lsb import Sim
 
-    w = W.wavy_stratified_3d(n=size, storage=storage)
-    p = w["params"]
-    if cumulant_gas:
-        p["collision"] = [W.BGK, W.CUMULANT]
     t0 = time.time()
-    phi0 = torch.from_numpy(W.wavy_phi(p, 8.0 * size / 512.0)).to("cuda:0")
+    if workload == "cluster9":
+        # nine rising bubbles, one gas baseline each (32 cells per diameter)
+        w = W.nine_bubble_cluster_3d(d=32, storage=storage)
+        p = w["params"]
+        phi0 = torch.from_numpy(w["phi0"]).to("cuda:0")
+    else:
+        w = W.wavy_stratified_3d(n=size, storage=storage)
+        p = w["params"]
+        if cumulant_gas:
+            p["collision"] = [W.BGK, W.CUMULANT]
+        phi0 = torch.from_numpy(W.wavy_phi(p, 8.0 * size / 512.0)).to("cuda:0")
     s = Sim(p).set_schedule(schedule).init(phi0)
     del phi0
     torch.cuda.synchronize()
@@ -101,7 +107,11 @@ def run_mode(size, storage, steps, warmup, schedule, cumulant_gas=False):
         active_tiles=counts["active_tiles"],
         mass=[float(m) for m in I["mass"]],
         umax=float(I["umax"]),
+        workload=w["name"],
+        cells=N,
     )
+    if p["use_pb"] == 2:
+        res["bubbles"] = s.bubbles()["count"]
     log(f"[{storage}] {res}")
     del s
     torch.cuda.empty_cache()
@@ -170,9 +180,10 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=512)
-    ap.add_argument("--modes", default="f16dev,f32,f64,f16dev-cum",
+    ap.add_argument("--modes", default="f16dev,f32,f64,f16dev-cum,cluster9",
                     help="storage modes; a '-cum' suffix runs the gas phase with the cumulant collision "
-                         "(the paper's 3D pairing: BGK liquid, cumulant gas)")
+                         "(the paper's 3D pairing: BGK liquid, cumulant gas); 'cluster9' is the nine-bubble "
+                         "cluster (320x640x320, FP16-deviation, cumulant gas, one gas baseline per bubble)")
     ap.add_argument("--schedule", default="auto", choices=["auto", "serial", "overlap"],
                     help="step schedule: one stream, the bulk collide-stream overlapped on a second stream, or "
                          "auto (the faster on this workload: serial for FP16-deviation, overlap for FP32 and FP64)")
@@ -199,6 +210,13 @@ def main():
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
     results = {}
     for m in modes:
+        if m == "cluster9":
+            sm = "serial" if args.schedule == "auto" else args.schedule
+            results[m] = run_mode(args.size, F16DEV, args.steps, args.warmup,
+                                  SCHED_OVERLAP if sm == "overlap" else SCHED_SERIAL, workload="cluster9")
+            results[m]["schedule"] = sm
+            results[m]["collision"] = "BGK liquid, cumulant gas"
+            continue
         sm = sched_of(m)
         base, cum = (m[:-4], True) if m.endswith("-cum") else (m, False)
         results[m] = run_mode(args.size, names[base], args.steps, args.warmup,

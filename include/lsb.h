@@ -59,6 +59,9 @@ enum { LSB_PERIODIC = 0, LSB_NOSLIP = 1, LSB_FREESLIP = 2 };
  * cumulant at rate one; D3Q27 only).  Both add the same body-force term. */
 enum { LSB_BGK = 0, LSB_CUMULANT = 1 };
 
+/* Most bubbles tracked with use_pb = 2. */
+enum { LSB_MAX_BUBBLES = 64 };
+
 /* Problem statement (Sec. 2 and the setups of Sec. 3). */
 typedef struct lsb_params {
   int lattice, storage, nx, ny, nz;
@@ -75,7 +78,10 @@ typedef struct lsb_params {
   int n_reinit;             /* pseudo steps per reinitialisation */
   double reinit_dtau;       /* pseudo time step of the reinitialisation */
   double heaviside_eps;     /* half width of the smoothed Heaviside (Sec. 3.2 integrals) */
-  int use_pb;               /* gas pressure baseline follows the centroid under gravity */
+  int use_pb;               /* gas pressure baseline under gravity: 0 off (pb0 throughout),
+                               1 one baseline from the gas centroid, 2 one per bubble (the
+                               connected components of the smoothed Heaviside's support, each
+                               with the baseline at its own centroid; at most LSB_MAX_BUBBLES) */
   double pb0;               /* initial gas pressure baseline */
   int init_hydrostatic;     /* default initial LB density is hydrostatic about the gas centroid */
   int fp16_scale_log2;      /* s = 2^k for LSB_F16DEV (typically 12) */
@@ -142,6 +148,16 @@ int lsb_get_fields(lsb_plan* plan, double* rho, double* u, double* p, uint8_t* p
  * link to the other phase).  Any pointer may be NULL. */
 int lsb_get_interface(lsb_plan* plan, double* phi, double* normal, double* kappa, uint8_t* tags,
                       int on_device, void* stream);
+
+/* Bubbles (use_pb = 2; Sec. 3.2 integrals per bubble): *count bubbles,
+ * numbered by their smallest cell; out [max][5] (host) per bubble: volume
+ * (sum of the smoothed Heaviside), centroid[3], gas pressure baseline
+ * pb0 + rho_l a_l . (x_c - x_c0); labels [N] (int32, host or device as
+ * on_device): the bubble of each cell, -1 outside the Heaviside support.
+ * out and labels may be NULL.  Synchronises the stream.  LSB_EINVAL unless
+ * use_pb = 2; LSB_EUNSTABLE when more than LSB_MAX_BUBBLES bubbles were
+ * found (the baselines of the rest are missing; *count holds the number). */
+int lsb_get_bubbles(lsb_plan* plan, int max, int* count, double* out, int32_t* labels, int on_device, void* stream);
 
 /* Decoded populations A[i*N + cell] (post-collision, FP64). */
 int lsb_get_populations(lsb_plan* plan, double* out, int on_device, void* stream);

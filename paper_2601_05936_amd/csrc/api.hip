@@ -94,6 +94,7 @@ int lsb_create(const lsb_params* P, lsb_plan** out) {
   }
   if (P->lattice == LSB_D2Q9 && P->bc[4] != LSB_PERIODIC) return fail(LSB_EINVAL, "2D grids need periodic z faces");
   if (!(P->tau[0] > 0.5) || !(P->tau[1] > 0.5)) return fail(LSB_EINVAL, "tau must exceed 1/2");
+  if (P->use_pb < 0 || P->use_pb > 2) return fail(LSB_EINVAL, "use_pb must be 0, 1 or 2");
   for (int k = 0; k < 2; ++k) {
     if (P->collision[k] != LSB_BGK && P->collision[k] != LSB_CUMULANT)
       return fail(LSB_EINVAL, "unknown collision operator");
@@ -173,6 +174,15 @@ int lsb_create(const lsb_params* P, lsb_plan** out) {
   p->off_spec_list = take(N * sizeof(int));
   p->off_flip_list = take(N * sizeof(int));
   p->off_partial = take((size_t)p->red_blocks * 16 * sizeof(double));
+  {
+    // several bubbles: labels, baseline field, roots, partial sums, results
+    const bool nb = P->use_pb == 2;
+    p->off_blab = take(nb ? N * sizeof(int) : 0);
+    p->off_pbc = take(nb ? N * p->bytes_real : 0);
+    p->off_broots = take(nb ? lsb::kMaxBubbles * sizeof(int) : 0);
+    p->off_bpart = take(nb ? (size_t)lsb::kBubbleParts * lsb::kMaxBubbles * 4 * sizeof(double) : 0);
+    p->off_bres = take(nb ? (size_t)lsb::kMaxBubbles * 5 * sizeof(double) : 0);
+  }
   {
     long nw = 0;
     const long ax[3] = {P->nx, P->ny, P->nz};
@@ -356,6 +366,28 @@ int lsb_get_interface(lsb_plan* p, double* phi, double* nrm, double* kap, uint8_
       LSB_HIP(hipStreamSynchronize(st));
     }
   }
+  return LSB_OK;
+}
+
+int lsb_get_bubbles(lsb_plan* p, int max, int* count, double* out, int32_t* labels, int on_device, void* stream) {
+  if (!p || !count) return fail(LSB_EINVAL, "null argument");
+  if (!p->inited) return fail(LSB_ESTATE, "no state");
+  if (p->P.use_pb != 2) return fail(LSB_EINVAL, "lsb_get_bubbles needs use_pb = 2");
+  hipStream_t st = as_stream(stream);
+  double nb = 0.0;
+  LSB_HIP(hipMemcpyAsync(&nb, p->ws + p->off_scal + lsb::SC_NBUB * sizeof(double), sizeof(double),
+                         hipMemcpyDeviceToHost, st));
+  LSB_HIP(hipStreamSynchronize(st));
+  const int n = (int)nb;
+  *count = n;
+  if (n > lsb::kMaxBubbles) return fail(LSB_EUNSTABLE, "more than LSB_MAX_BUBBLES bubbles");
+  if (out && max > 0 && n > 0)
+    LSB_HIP(hipMemcpyAsync(out, p->ws + p->off_bres, (size_t)std::min(n, max) * 5 * sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+  if (labels)
+    LSB_HIP(hipMemcpyAsync(labels, p->ws + p->off_blab, (size_t)p->N * sizeof(int32_t),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+  LSB_HIP(hipStreamSynchronize(st));
   return LSB_OK;
 }
 
@@ -602,6 +634,7 @@ static int adj_check(const lsb_plan* p) {
   if (!p) return fail(LSB_EINVAL, "null plan");
   if (!p->adj_ops)
     return fail(LSB_EINVAL, "the reverse mode needs the D2Q9 lattice with LSB_F64 or LSB_F32 storage");
+  if (p->P.use_pb == 2) return fail(LSB_EINVAL, "the reverse mode takes one gas baseline (use_pb 0 or 1)");
   return LSB_OK;
 }
 

@@ -223,6 +223,12 @@ struct KArgs {
   R* ut_b;
   R* ext_k;                 // per LS-active cell and axis: dtau v_ax towards the upwind neighbour, 0 if none
   R* irec;                  // per interface-adjacent cell: phi, M[10], G[4] of the current state (16 values)
+  // several bubbles (use_pb = 2)
+  int* blab;                // per cell: union-find parent, then the bubble (-1 outside the Heaviside support)
+  int* broots;              // roots of the bubbles, ascending (at most kMaxBubbles)
+  double* bpart;            // per reduction block and bubble: sum H, sum H x[3]
+  double* bres;             // per bubble: volume, centroid[3], baseline
+  R* pbc;                   // per cell: the baseline of its bubble
   double* scal;             // device scalars (see SC_*)
   // lists
   int* counters;            // see CNT_*
@@ -238,13 +244,15 @@ struct KArgs {
   double* partial;          // reduction partials
 };
 
-// device scalar slots
-enum { SC_PB = 0, SC_XC0 = 1, SC_XC = 4, SC_V = 7, SC_COUNT = 16 };
+// device scalar slots (SC_NBUB: bubbles found, may exceed kMaxBubbles)
+enum { SC_PB = 0, SC_XC0 = 1, SC_XC = 4, SC_V = 7, SC_NBUB = 8, SC_COUNT = 16 };
+constexpr int kMaxBubbles = LSB_MAX_BUBBLES;
+constexpr int kBubbleParts = 2048;  // reduction blocks of the per-bubble sums
 // counters: CNT_SPEC, CNT_TILES and CNT_FLIP are cleared before each
 // classification, CNT_CAND before each dilation, CNT_WALL is static.
 // CNT_SPEC and CNT_TILES form one aligned 64-bit word (one atomic reserves
 // slots in both lists).
-enum { CNT_SPEC = 0, CNT_TILES = 1, CNT_FLIP = 2, CNT_CAND = 3, CNT_WALL = 4, CNT_NUM = 8 };
+enum { CNT_SPEC = 0, CNT_TILES = 1, CNT_FLIP = 2, CNT_CAND = 3, CNT_WALL = 4, CNT_BUB = 5, CNT_NUM = 8 };
 
 // Runtime selection from small arrays of the kernel argument block without
 // indexing it dynamically (which would copy the block to scratch memory).

@@ -68,6 +68,11 @@ struct Driver {
     a.ut_b = reinterpret_cast<R*>(w + p->off_ut[1]);
     a.ext_k = reinterpret_cast<R*>(w + p->off_ext_k);
     a.irec = reinterpret_cast<R*>(w + p->off_irec);
+    a.blab = reinterpret_cast<int*>(w + p->off_blab);
+    a.pbc = reinterpret_cast<R*>(w + p->off_pbc);
+    a.broots = reinterpret_cast<int*>(w + p->off_broots);
+    a.bpart = reinterpret_cast<double*>(w + p->off_bpart);
+    a.bres = reinterpret_cast<double*>(w + p->off_bres);
     a.scal = reinterpret_cast<double*>(w + p->off_scal);
     a.counters = reinterpret_cast<int*>(w + p->off_cnt);
     a.tile_act = reinterpret_cast<uint8_t*>(w + (p->tcur ? p->off_tile_act2 : p->off_tile_act));
@@ -127,6 +132,25 @@ struct Driver {
     k_mark_walls<LAT, ST><<<cell_grid(p), 256, 0, st>>>(a);
     centroid(p, 0, st);
     k_set_scalar<LAT, ST><<<1, 1, 0, st>>>(a, SC_PB, p->P.pb0);
+    if (p->P.use_pb == 2) bubbles(p, st);
+  }
+
+  // Several bubbles: label the components of the Heaviside support, their
+  // volumes, centroids and baselines, and the baseline field.
+  static void bubbles(lsb_plan* p, hipStream_t st) {
+    Args a = args(p, p->cur);
+    const lsb_params& P = p->P;
+    const int g = cell_grid(p);
+    k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a, CNT_BUB, 1);
+    k_bub_init<LAT, ST><<<g, 256, 0, st>>>(a);
+    k_bub_union<LAT, ST><<<g, 256, 0, st>>>(a);
+    k_bub_roots<LAT, ST><<<g, 256, 0, st>>>(a);
+    k_bub_sort<LAT, ST><<<1, 64, 0, st>>>(a);
+    k_bub_number<LAT, ST><<<g, 256, 0, st>>>(a);
+    k_bub_partial<LAT, ST><<<kBubbleParts, 256, 0, st>>>(a);
+    k_bub_final<LAT, ST><<<1, kMaxBubbles, 0, st>>>(a, kBubbleParts, P.pb0, P.rho_phys[0], P.accel[0][0],
+                                                    P.accel[0][1], P.accel[0][2]);
+    k_bub_field<LAT, ST><<<g, 256, 0, st>>>(a);
   }
 
   // populations and both moment buffers of the current state (buffer 0)
@@ -245,8 +269,9 @@ struct Driver {
     k_refill<LAT, ST><<<p->grid_cells, 256, 0, st>>>(a);
     p->cur ^= 1;
     p->tcur ^= 1;
-    // a9: centroid and gas pressure baseline
-    if (P.use_pb) centroid(p, 1, st);
+    // a9: centroid and gas pressure baseline (one, or one per bubble)
+    if (P.use_pb == 2) bubbles(p, st);
+    else if (P.use_pb) centroid(p, 1, st);
     pack(p, st);
     ++p->nstep;
   }
@@ -278,6 +303,7 @@ struct Driver {
     k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a, 0, CNT_NUM);
     classify_all(p, st);
     k_mark_walls<LAT, ST><<<cell_grid(p), 256, 0, st>>>(a);
+    if (p->P.use_pb == 2) bubbles(p, st);
   }
 
   static const Ops* table() {

@@ -46,6 +46,14 @@ __device__ __forceinline__ T* pop_at(T* base, size_t dir_base, unsigned byte_off
   return reinterpret_cast<T*>(reinterpret_cast<char*>(base + dir_base) + byte_off);
 }
 
+// gas pressure baseline seen by a gas cell: the single baseline, or with
+// several bubbles that of the cell's bubble
+template <class Args>
+__device__ __forceinline__ auto baseline(const Args& a, int c) {
+  using R = typename std::remove_pointer<decltype(a.pbc)>::type;
+  return a.use_pb == 2 ? a.pbc[c] : (R)a.scal[SC_PB];
+}
+
 // ---------------------------------------------------------------------------
 // Cumulant collision (Sec. 2.1, D3Q27) with the paper's rates: omega_1 =
 // omega_BGK for the shear (deviatoric second-order) cumulants, one for every
@@ -552,9 +560,8 @@ __device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename S
   }
   const R kG = ((R)1 - q) * own.G[3] + q * rs.v[14];
   const int o = 1 - k;
-  const R pb = (R)a.scal[SC_PB];
-  R p_own = sel2(a.iface_pc, k) * own.M[0] + (k == 1 ? pb : (R)0);
-  R p_oth = sel2(a.iface_pc, o) * rs.v[1] + (o == 1 ? pb : (R)0);
+  R p_own = sel2(a.iface_pc, k) * own.M[0] + (k == 1 ? (R)baseline(a, c) : (R)0);
+  R p_oth = sel2(a.iface_pc, o) * rs.v[1] + (o == 1 ? (R)baseline(a, sc) : (R)0);
   for (int m = 0; m < 3; ++m) {
     p_own = p_own + sel2(a.rho_phys, k) * ACC(a, k, m) * (R)(-cc[m]) * q;
     p_oth = p_oth + sel2(a.rho_phys, o) * ACC(a, o, m) * (R)cc[m] * ((R)1 - q);
@@ -1317,9 +1324,9 @@ __global__ __launch_bounds__(256) void k_refill(const typename Step<LAT, ST>::Ar
   const size_t N = a.N;
   const int n = a.counters[CNT_FLIP];
   const R s = a.scale;
-  const R pb = (R)a.scal[SC_PB];
   for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
     const int c = a.flip_list[e];
+    const R pb = (R)baseline(a, c);
     const int x = c % a.nx, y = (c / a.nx) % a.ny, z = c / (a.nx * a.ny);
     const uint8_t t = a.tag[c];
     const int knew = t & T_GAS;
@@ -1514,6 +1521,195 @@ __global__ __launch_bounds__(256) void k_centroid_final(const typename Step<LAT,
 }
 
 // ---------------------------------------------------------------------------
+// Several bubbles (use_pb = 2): the bubbles are the connected components of
+// the smoothed Heaviside's support (phi > -eps) over the lattice links
+// (periodic faces wrap, wall faces cut), each with the single-bubble
+// baseline at its own centroid, Pb_k = pb0 + rho_l a_l . (x_c,k - x_c0).
+// Union-find on the cells: every link joins the two roots by pointing the
+// larger at the smaller (atomicMin), so parents only decrease, every chain
+// ends, and each root is its component's smallest cell, which also fixes the
+// bubbles' numbering (ascending roots).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int bub_parent(const int* lab, int c) {
+  return __hip_atomic_load(lab + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int bub_find(const int* lab, int c) {
+  for (;;) {
+    const int q = bub_parent(lab, c);
+    if (q == c) return c;
+    c = q;  // q < c: strictly decreasing
+  }
+}
+__device__ __forceinline__ void bub_unite(int* lab, int u, int v) {
+  for (;;) {
+    u = bub_find(lab, u);
+    v = bub_find(lab, v);
+    if (u == v) return;
+    if (u > v) { const int t = u; u = v; v = t; }
+    const int old = atomicMin(lab + v, u);
+    if (old == v) return;  // v was a root and now hangs under u
+    v = old;               // v had been linked meanwhile: join its new parent (old < v)
+  }
+}
+
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_bub_init(const typename Step<LAT, ST>::Args a) {
+  const typename Step<LAT, ST>::R eps = a.heps;
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < a.N; c += gridDim.x * 256)
+    a.blab[c] = a.phi[c] > -eps ? c : -1;
+}
+
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_bub_union(const typename Step<LAT, ST>::Args a) {
+  using L = typename Step<LAT, ST>::L;
+  constexpr int Q = Step<LAT, ST>::Q;
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < a.N; c += gridDim.x * 256) {
+    if (a.blab[c] < 0) continue;
+    const int x = c % a.nx, y = (c / a.nx) % a.ny, z = c / (a.nx * a.ny);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (opp<LAT>(i) <= i) continue;  // one direction of each pair (the rest direction has opp == i)
+      const int sx = lb_coord(x - L::cx(i), a.nx, a.per[0]);
+      const int sy = lb_coord(y - L::cy(i), a.ny, a.per[1]);
+      const int sz = lb_coord(z - L::cz(i), a.nz, a.per[2]);
+      if ((sx | sy | sz) < 0) continue;  // through a wall face
+      const int n = (sz * a.ny + sy) * a.nx + sx;
+      if (a.blab[n] < 0) continue;
+      bub_unite(a.blab, c, n);
+    }
+  }
+}
+
+// path compression (every cell of the support points at its root, which
+// keeps each parent an ancestor) and the list of roots (at most
+// kMaxBubbles stored; the count may exceed it)
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_bub_roots(const typename Step<LAT, ST>::Args a) {
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < a.N; c += gridDim.x * 256) {
+    if (a.blab[c] < 0) continue;
+    const int r = bub_find(a.blab, c);
+    if (r == c) {
+      const int k = atomicAdd(&a.counters[CNT_BUB], 1);
+      if (k < kMaxBubbles) a.broots[k] = c;
+    } else {
+      a.blab[c] = r;
+    }
+  }
+}
+
+// sort the stored roots (one thread, at most kMaxBubbles); the count goes to
+// SC_NBUB
+template <int LAT, int ST>
+__global__ void k_bub_sort(const typename Step<LAT, ST>::Args a) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const int n = a.counters[CNT_BUB];
+  a.scal[SC_NBUB] = (double)n;
+  const int m = n < kMaxBubbles ? n : kMaxBubbles;
+  for (int i = 1; i < m; ++i) {
+    const int v = a.broots[i];
+    int j = i - 1;
+    while (j >= 0 && a.broots[j] > v) {
+      a.broots[j + 1] = a.broots[j];
+      --j;
+    }
+    a.broots[j + 1] = v;
+  }
+}
+
+// root -> bubble number (rank of the root); -2 for a bubble beyond the
+// stored ones (the query calls report the overflow)
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_bub_number(const typename Step<LAT, ST>::Args a) {
+  __shared__ int roots[kMaxBubbles];
+  const int n = a.counters[CNT_BUB];
+  const int m = n < kMaxBubbles ? n : kMaxBubbles;
+  for (int i = threadIdx.x; i < m; i += 256) roots[i] = a.broots[i];
+  __syncthreads();
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < a.N; c += gridDim.x * 256) {
+    const int r = a.blab[c];
+    if (r < 0) continue;
+    int lo = 0, hi = m - 1, id = -2;
+    while (lo <= hi) {
+      const int mid = (lo + hi) >> 1;
+      const int v = roots[mid];
+      if (v == r) { id = mid; break; }
+      if (v < r) lo = mid + 1; else hi = mid - 1;
+    }
+    a.blab[c] = id;
+  }
+}
+
+// per reduction block (a contiguous range of cells) and bubble: sum H and
+// sum H x in a fixed order, one pass per bubble present in the range
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_bub_partial(const typename Step<LAT, ST>::Args a) {
+  const int chunk = (a.N + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int c0 = blockIdx.x * chunk;
+  const int c1 = c0 + chunk < a.N ? c0 + chunk : a.N;
+  const double eps = (double)a.heps;
+  __shared__ unsigned long long present;
+  if (threadIdx.x == 0) present = 0ull;
+  __syncthreads();
+  unsigned long long mine = 0ull;
+  for (int c = c0 + (int)threadIdx.x; c < c1; c += 256) {
+    const int id = a.blab[c];
+    if (id >= 0) mine |= 1ull << id;
+  }
+  if (mine) atomicOr(&present, mine);
+  __syncthreads();
+  const unsigned long long mask = present;
+  double* part = a.bpart + (size_t)blockIdx.x * kMaxBubbles * 4;
+  for (int i = threadIdx.x; i < kMaxBubbles * 4; i += 256)
+    if (!((mask >> (i >> 2)) & 1ull)) part[i] = 0.0;
+  for (unsigned long long mk = mask; mk; mk &= mk - 1ull) {
+    const int k = __ffsll((long long)mk) - 1;
+    double v[4] = {0, 0, 0, 0};
+    for (int c = c0 + (int)threadIdx.x; c < c1; c += 256) {
+      if (a.blab[c] != k) continue;
+      const double h = heaviside_d((double)a.phi[c], eps);
+      const int x = c % a.nx, y = (c / a.nx) % a.ny, z = c / (a.nx * a.ny);
+      v[0] += h;
+      v[1] += h * (x + 0.5);
+      v[2] += h * (y + 0.5);
+      v[3] += h * (z + 0.5);
+    }
+    block_sum<4>(v, part + 4 * k);
+  }
+}
+
+// per bubble: volume, centroid and baseline (partials summed in block order)
+template <int LAT, int ST>
+__global__ void k_bub_final(const typename Step<LAT, ST>::Args a, int nparts, double pb0, double rho_l, double al0,
+                            double al1, double al2) {
+  const int k = threadIdx.x;
+  if (k >= kMaxBubbles) return;
+  double v[4] = {0, 0, 0, 0};
+  for (int b = 0; b < nparts; ++b)
+    for (int m = 0; m < 4; ++m) v[m] += a.bpart[((size_t)b * kMaxBubbles + k) * 4 + m];
+  const double al[3] = {al0, al1, al2};
+  double pb = pb0;
+  double* out = a.bres + 5 * k;
+  out[0] = v[0];
+  for (int m = 0; m < 3; ++m) {
+    const double xc = v[0] > 0 ? v[1 + m] / v[0] : 0.0;
+    out[1 + m] = xc;
+    pb = pb + rho_l * al[m] * (xc - a.scal[SC_XC0 + m]);
+  }
+  out[4] = pb;
+}
+
+// per cell: the baseline of its bubble
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_bub_field(const typename Step<LAT, ST>::Args a) {
+  using R = typename Step<LAT, ST>::R;
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < a.N; c += gridDim.x * 256) {
+    const int id = a.blab[c];
+    a.pbc[c] = id >= 0 ? (R)a.bres[5 * id + 4] : (R)0;
+  }
+}
+
+
+// ---------------------------------------------------------------------------
 // Initialisation and output kernels.
 // ---------------------------------------------------------------------------
 template <int LAT, int ST>
@@ -1548,8 +1744,12 @@ __global__ __launch_bounds__(256) void k_init_pop(const typename Step<LAT, ST>::
     else {
       rho = 1.0;
       if (hydro) {
+        // about the initial centroid; a gas cell of one of several bubbles
+        // about its own bubble's
         const double pos[3] = {x + 0.5, y + 0.5, z + 0.5};
-        for (int m = 0; m < 3; ++m) rho = rho + (double)ACC(a, k, m) * (pos[m] - a.scal[SC_XC0 + m]) / (1.0 / 3.0);
+        const double* ref = a.scal + SC_XC0;
+        if (a.use_pb == 2 && k == 1 && a.blab[c] >= 0) ref = a.bres + 5 * a.blab[c] + 1;
+        for (int m = 0; m < 3; ++m) rho = rho + (double)ACC(a, k, m) * (pos[m] - ref[m]) / (1.0 / 3.0);
       }
     }
     double u[3] = {0, 0, 0};
@@ -1595,7 +1795,7 @@ __global__ __launch_bounds__(256) void k_fields(const typename Step<LAT, ST>::Ar
     if (rho_out) rho_out[o] = rho;
     if (u_out)
       for (int d = 0; d < S::D; ++d) u_out[(size_t)S::D * o + d] = m[d] / rho - 0.5 * (double)ACC(a, k, d);
-    if (p_out) p_out[o] = (double)sel2(a.rho_phys, k) / 3.0 * (rho - 1.0) + (k == 1 ? a.scal[SC_PB] : 0.0);
+    if (p_out) p_out[o] = (double)sel2(a.rho_phys, k) / 3.0 * (rho - 1.0) + (k == 1 ? (double)baseline(a, c) : 0.0);
     if (ph_out) ph_out[o] = (uint8_t)k;
   }
 }

@@ -90,6 +90,7 @@ struct lsb_plan {
   size_t off_wall_list;
   size_t off_ext_k;        // extension coefficients of the current step
   size_t off_irec;         // packed interface records [N][16]
+  size_t off_blab = 0, off_broots = 0, off_bpart = 0, off_bres = 0, off_pbc = 0;  // several bubbles
   size_t off_tile_act2;    // second tile-activity buffer
   size_t off_cflag[2];     // candidate-tile flags, by step parity
   int tcur = 0;            // which tile-activity buffer holds this step's flags

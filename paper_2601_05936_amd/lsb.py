@@ -46,13 +46,14 @@ class Integrals(C.Structure):
 
 EXPORTS = [
     "lsb_create", "lsb_destroy", "lsb_workspace_bytes", "lsb_bind", "lsb_init", "lsb_step", "lsb_get_fields",
-    "lsb_get_interface", "lsb_get_populations", "lsb_get_moments", "lsb_get_integrals", "lsb_state_bytes",
+    "lsb_get_interface", "lsb_get_bubbles", "lsb_get_populations", "lsb_get_moments", "lsb_get_integrals", "lsb_state_bytes",
     "lsb_save_state", "lsb_load_state", "lsb_step_count", "lsb_get_counts", "lsb_set_kernel_timing",
     "lsb_get_kernel_timing", "lsb_set_schedule", "lsb_adjoint_workspace_bytes", "lsb_adjoint_bind",
     "lsb_adjoint_record", "lsb_adjoint_seed_centroid", "lsb_adjoint_reverse", "lsb_adjoint_initial",
     "lsb_last_error",
 ]
 SCHED_SERIAL, SCHED_OVERLAP = 0, 1
+MAX_BUBBLES = 64  # LSB_MAX_BUBBLES
 
 _lib = None
 
@@ -80,6 +81,7 @@ def load() -> C.CDLL:
     lib.lsb_get_populations.argtypes = [vp, vp, C.c_int, vp]
     lib.lsb_get_moments.argtypes = [vp, vp, C.c_int, vp]
     lib.lsb_get_integrals.argtypes = [vp, C.POINTER(Integrals), vp]
+    lib.lsb_get_bubbles.argtypes = [vp, C.c_int, C.POINTER(C.c_int), vp, vp, C.c_int, vp]
     lib.lsb_state_bytes.argtypes = [vp, sz]
     lib.lsb_save_state.argtypes = [vp, vp, vp]
     lib.lsb_load_state.argtypes = [vp, vp, vp]
@@ -227,6 +229,21 @@ class Sim:
         _check(self.lib.lsb_get_integrals(self.h, C.byref(I), self.stream()))
         return dict(mass=np.array(I.mass[:]), volume_gas=I.volume_gas, centroid=np.array(I.centroid[:]),
                     vel_b=np.array(I.vel_b[:]), pb=I.pb, umax=I.umax, step=I.step)
+
+    def bubbles(self, labels=False) -> dict:
+        """Several-bubble mode (use_pb = 2): per bubble, numbered by its smallest
+        cell, volume, centroid and gas pressure baseline; with labels, the
+        bubble of every cell (-1 outside the Heaviside support)."""
+        n = C.c_int()
+        out = np.zeros(5 * MAX_BUBBLES)
+        lab = np.zeros(self.N, dtype=np.int32) if labels else None
+        _check(self.lib.lsb_get_bubbles(self.h, MAX_BUBBLES, C.byref(n), C.c_void_p(out.ctypes.data),
+                                        None if lab is None else C.c_void_p(lab.ctypes.data), 0, self.stream()))
+        b = out[:5 * n.value].reshape(-1, 5)
+        res = dict(count=n.value, volume=b[:, 0].copy(), centroid=b[:, 1:4].copy(), pb=b[:, 4].copy())
+        if labels:
+            res["labels"] = lab.reshape(self.shape)
+        return res
 
     def counts(self) -> dict:
         c = (C.c_int * 4)()

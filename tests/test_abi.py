@@ -46,6 +46,7 @@ def _create(p):
     dict(tau=[0.5, 0.8]), dict(band=1.0), dict(bc=[0, 1, 0, 0, 0, 0]), dict(nx=2),
     dict(collision=[W.BGK, W.CUMULANT]),  # cumulant needs D3Q27
     dict(collision=[2, W.BGK]),  # unknown operator
+    dict(use_pb=3),  # unknown baseline mode
 ])
 def test_create_rejects_invalid_parameters(bad):
     p = W.default_params(lattice=W.D2Q9, nx=16, ny=16, nz=1,
@@ -90,3 +91,15 @@ def test_schedule_selection_is_validated():
     assert lib.lsb_set_schedule(h, 7) == lsb.LSB_EINVAL
     assert lib.lsb_set_schedule(None, 0) == lsb.LSB_EINVAL
     lib.lsb_destroy(h)
+
+
+def test_reverse_mode_rejects_per_bubble_baselines():
+    """The reverse mode differentiates one gas baseline (use_pb 0 or 1)."""
+    lib = lsb.load()
+    for mode, want in ((1, lsb.LSB_OK), (2, lsb.LSB_EINVAL)):
+        p = W.default_params(lattice=W.D2Q9, nx=16, ny=16, nz=1, bc=[W.PERIODIC] * 6, use_pb=mode)
+        rc, h = _create(p)
+        assert rc == 0
+        nb = C.c_size_t()
+        assert lib.lsb_adjoint_workspace_bytes(h, 10, C.byref(nb)) == want
+        lib.lsb_destroy(h)
