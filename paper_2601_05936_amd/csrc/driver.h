@@ -148,8 +148,8 @@ struct Driver {
     k_bub_sort<LAT, ST><<<1, 64, 0, st>>>(a);
     k_bub_number<LAT, ST><<<g, 256, 0, st>>>(a);
     k_bub_partial<LAT, ST><<<kBubbleParts, 256, 0, st>>>(a);
-    k_bub_final<LAT, ST><<<1, kMaxBubbles, 0, st>>>(a, kBubbleParts, P.pb0, P.rho_phys[0], P.accel[0][0],
-                                                    P.accel[0][1], P.accel[0][2]);
+    k_bub_final<LAT, ST><<<kMaxBubbles, 256, 0, st>>>(a, kBubbleParts, P.pb0, P.rho_phys[0], P.accel[0][0],
+                                                     P.accel[0][1], P.accel[0][2]);
     k_bub_field<LAT, ST><<<g, 256, 0, st>>>(a);
   }
 

@@ -1533,11 +1533,16 @@ __global__ __launch_bounds__(256) void k_centroid_final(const typename Step<LAT,
 __device__ __forceinline__ int bub_parent(const int* lab, int c) {
   return __hip_atomic_load(lab + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ int bub_find(const int* lab, int c) {
+// root of c with path halving (a cell's parent becomes its grandparent, by
+// atomicMin, so parents still only decrease)
+__device__ __forceinline__ int bub_find(int* lab, int c) {
   for (;;) {
     const int q = bub_parent(lab, c);
     if (q == c) return c;
-    c = q;  // q < c: strictly decreasing
+    const int g = bub_parent(lab, q);
+    if (g == q) return q;
+    atomicMin(lab + c, g);
+    c = g;  // g < q < c: strictly decreasing
   }
 }
 __device__ __forceinline__ void bub_unite(int* lab, int u, int v) {
@@ -1552,11 +1557,31 @@ __device__ __forceinline__ void bub_unite(int* lab, int u, int v) {
   }
 }
 
+// support cells start at the smallest support cell among themselves and
+// their lattice neighbours (a first union step without atomics)
 template <int LAT, int ST>
 __global__ __launch_bounds__(256) void k_bub_init(const typename Step<LAT, ST>::Args a) {
+  using L = typename Step<LAT, ST>::L;
+  constexpr int Q = Step<LAT, ST>::Q;
   const typename Step<LAT, ST>::R eps = a.heps;
-  for (int c = blockIdx.x * 256 + threadIdx.x; c < a.N; c += gridDim.x * 256)
-    a.blab[c] = a.phi[c] > -eps ? c : -1;
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < a.N; c += gridDim.x * 256) {
+    if (!(a.phi[c] > -eps)) {
+      a.blab[c] = -1;
+      continue;
+    }
+    const int x = c % a.nx, y = (c / a.nx) % a.ny, z = c / (a.nx * a.ny);
+    int m = c;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int sx = lb_coord(x - L::cx(i), a.nx, a.per[0]);
+      const int sy = lb_coord(y - L::cy(i), a.ny, a.per[1]);
+      const int sz = lb_coord(z - L::cz(i), a.nz, a.per[2]);
+      if ((sx | sy | sz) < 0) continue;
+      const int n = (sz * a.ny + sy) * a.nx + sx;
+      if (n < m && a.phi[n] > -eps) m = n;
+    }
+    a.blab[c] = m;
+  }
 }
 
 template <int LAT, int ST>
@@ -1677,21 +1702,25 @@ __global__ __launch_bounds__(256) void k_bub_partial(const typename Step<LAT, ST
   }
 }
 
-// per bubble: volume, centroid and baseline (partials summed in block order)
+// per bubble (one block each): volume, centroid and baseline, the partials
+// summed in a fixed order
 template <int LAT, int ST>
-__global__ void k_bub_final(const typename Step<LAT, ST>::Args a, int nparts, double pb0, double rho_l, double al0,
-                            double al1, double al2) {
-  const int k = threadIdx.x;
-  if (k >= kMaxBubbles) return;
+__global__ __launch_bounds__(256) void k_bub_final(const typename Step<LAT, ST>::Args a, int nparts, double pb0,
+                                                   double rho_l, double al0, double al1, double al2) {
+  const int k = blockIdx.x;
+  if (k >= a.counters[CNT_BUB]) return;
   double v[4] = {0, 0, 0, 0};
-  for (int b = 0; b < nparts; ++b)
+  for (int b = threadIdx.x; b < nparts; b += 256)
     for (int m = 0; m < 4; ++m) v[m] += a.bpart[((size_t)b * kMaxBubbles + k) * 4 + m];
+  __shared__ double sum[4];
+  block_sum<4>(v, sum);
+  if (threadIdx.x != 0) return;
   const double al[3] = {al0, al1, al2};
   double pb = pb0;
   double* out = a.bres + 5 * k;
-  out[0] = v[0];
+  out[0] = sum[0];
   for (int m = 0; m < 3; ++m) {
-    const double xc = v[0] > 0 ? v[1 + m] / v[0] : 0.0;
+    const double xc = sum[0] > 0 ? sum[1 + m] / sum[0] : 0.0;
     out[1 + m] = xc;
     pb = pb + rho_l * al[m] * (xc - a.scal[SC_XC0 + m]);
   }
@@ -1704,7 +1733,7 @@ __global__ __launch_bounds__(256) void k_bub_field(const typename Step<LAT, ST>:
   using R = typename Step<LAT, ST>::R;
   for (int c = blockIdx.x * 256 + threadIdx.x; c < a.N; c += gridDim.x * 256) {
     const int id = a.blab[c];
-    a.pbc[c] = id >= 0 ? (R)a.bres[5 * id + 4] : (R)0;
+    if (id >= 0) a.pbc[c] = (R)a.bres[5 * id + 4];  // only gas cells read it (all in the support)
   }
 }
 
