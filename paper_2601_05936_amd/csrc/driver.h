@@ -167,7 +167,9 @@ struct Driver {
   // FP64 is held at four by its registers.
   template <bool SPLIT>
   static void bulk(const Args& a, bool force, int xchunks, int rows, hipStream_t st) {
-    const unsigned g = (unsigned)(xchunks * rows);
+    // whole 256-cell row chunks when nx allows, else consecutive cells
+    if (xchunks * 256 != a.nx) xchunks = 0;
+    const unsigned g = xchunks ? (unsigned)(xchunks * rows) : (unsigned)(((long)a.N + 255) / 256);
     const size_t dyn = ST == LSB_F32 ? 32768 : 0;
     if constexpr (LAT == LSB_D3Q27) {
       if (a.cum[0] || a.cum[1]) {

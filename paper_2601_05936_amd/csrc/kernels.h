@@ -450,15 +450,28 @@ __device__ __forceinline__ int tile_of(const Args& a, int x, int y, int z) {
 // the interface or refill kernels update, so this part writes no moments and
 // reads nothing the level-set chain writes except the LS-active bit of tags
 // (masked).  It may run concurrently with the level-set chain.
+// xchunks > 0: blocks of 256 cells of one x-row (nx a multiple of 256);
+// xchunks == 0: blocks of 256 consecutive cells across rows (any nx, no idle
+// threads at the row ends).
 template <int LAT, int ST, bool SPLIT, bool FORCE, bool CUM>
 __global__ __launch_bounds__(256) void k_lb_bulk(const typename Step<LAT, ST>::Args a, int xchunks) {
   const unsigned b = remap_xcd(blockIdx.x, gridDim.x);
-  const int row = (int)(b / (unsigned)xchunks);
-  const int x = (int)(b - (unsigned)row * xchunks) * 256 + (int)threadIdx.x;
-  if (x >= a.nx) return;
-  const int y = row % a.ny;
-  const int z = row / a.ny;
-  const int c = row * a.nx + x;
+  int c, x, y, z;
+  if (xchunks > 0) {
+    const int row = (int)(b / (unsigned)xchunks);
+    x = (int)(b - (unsigned)row * xchunks) * 256 + (int)threadIdx.x;
+    if (x >= a.nx) return;
+    y = row % a.ny;
+    z = row / a.ny;
+    c = row * a.nx + x;
+  } else {
+    c = (int)(b * 256u + threadIdx.x);
+    if (c >= a.N) return;
+    const int row = c / a.nx;
+    x = c - row * a.nx;
+    y = row % a.ny;
+    z = row / a.ny;
+  }
   if (SPLIT && a.cand_prev[tile_of<Step<LAT, ST>::D>(a, x, y, z)]) return;
   const uint8_t t = a.tag[c];
   if (t & (T_SPEC | T_WALL)) return;
