@@ -205,6 +205,8 @@ struct Driver {
     bool force = false;  // any body acceleration: the bulk launch with force terms
     for (int k = 0; k < 2; ++k)
       for (int m = 0; m < 3; ++m) force = force || P.accel[k][m] != 0.0;
+    // a phase with the cumulant operator: the collide-stream variants with it
+    const bool cum = LAT == LSB_D3Q27 && (a.cum[0] || a.cum[1]);
     // the populations of the previous step are complete (bulk part included)
     (void)hipStreamWaitEvent(st, p->ev_bulk_done, 0);
     if (p->schedule == LSB_SCHED_OVERLAP) {
@@ -213,7 +215,8 @@ struct Driver {
       bulk<true>(a, force, xchunks, rows, p->side);
       timing_end(p, p->side);
       (void)hipEventRecord(p->ev_bulk_done, p->side);
-      k_lb_band<LAT, ST><<<p->grid_tiles, 256, 0, st>>>(a);
+      if (cum) k_lb_band<LAT, ST, true><<<p->grid_tiles, 256, 0, st>>>(a);
+      else k_lb_band<LAT, ST, false><<<p->grid_tiles, 256, 0, st>>>(a);
     } else {
       timing_begin(p, st);
       bulk<false>(a, force, xchunks, rows, st);
@@ -223,8 +226,13 @@ struct Driver {
     // current LS-active tiles); their flags bound the next bulk part
     k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a, CNT_CAND, 1);
     k_dilate<LAT, ST><<<(p->ntiles + 255) / 256, 256, 0, st>>>(a, 0);
-    k_lb_iface<LAT, ST><<<p->grid_cells, 256, 0, st>>>(a);
-    if (p->n_wall_cells > 0) k_lb_wall<LAT, ST><<<p->grid_walls, 256, 0, st>>>(a);
+    if (cum) {
+      k_lb_iface<LAT, ST, true><<<p->grid_cells, 256, 0, st>>>(a);
+      if (p->n_wall_cells > 0) k_lb_wall<LAT, ST, true><<<p->grid_walls, 256, 0, st>>>(a);
+    } else {
+      k_lb_iface<LAT, ST, false><<<p->grid_cells, 256, 0, st>>>(a);
+      if (p->n_wall_cells > 0) k_lb_wall<LAT, ST, false><<<p->grid_walls, 256, 0, st>>>(a);
+    }
     (void)hipEventRecord(p->ev_pop_done, st);
     const bool recording = p->adj.rec_slot >= 0;
     const size_t rb = sizeof(R), N = (size_t)p->N;

@@ -409,7 +409,7 @@ __device__ __forceinline__ void fast_cell(const typename Step<LAT, ST>::Args& a,
 }
 
 // a2/a3 for a wall-adjacent cell with no lattice link to the other phase.
-template <int LAT, int ST>
+template <int LAT, int ST, bool CUM = true>
 __device__ __forceinline__ void wall_cell(const typename Step<LAT, ST>::Args& a, int c, int x, int y, int z, uint8_t t) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
@@ -431,7 +431,7 @@ __device__ __forceinline__ void wall_cell(const typename Step<LAT, ST>::Args& a,
       d[i] = wall_pull<LAT, ST, false>(a, c, x, y, z, i, k);
     }
   }
-  collide_store<LAT, ST>(a, c, k, (t & T_ACT) != 0, d);
+  collide_store<LAT, ST, true, CUM>(a, c, k, (t & T_ACT) != 0, d);
 }
 
 // Tile of a cell.
@@ -482,17 +482,17 @@ __global__ __launch_bounds__(256) void k_lb_bulk(const typename Step<LAT, ST>::A
 // candidate tiles of the previous step's classification (a superset of the
 // LS-active tiles; the moments of LS-active cells feed the level-set kernels
 // of the same step).
-template <int LAT, int ST>
+template <int LAT, int ST, bool CUM>
 __global__ __launch_bounds__(256) void k_lb_band(const typename Step<LAT, ST>::Args a) {
   for_tile_cells<Step<LAT, ST>::D>(a, a.cand_list, a.counters[CNT_CAND], [&](int c, int x, int y, int z) {
     const uint8_t t = a.tag[c];
     if (t & (T_SPEC | T_WALL)) return;
-    fast_cell<LAT, ST>(a, c, x, y, z, t);
+    fast_cell<LAT, ST, true, CUM>(a, c, x, y, z, t);
   });
 }
 
 // Wall-adjacent cells (static list), except interface-adjacent ones.
-template <int LAT, int ST>
+template <int LAT, int ST, bool CUM>
 __global__ __launch_bounds__(256) void k_lb_wall(const typename Step<LAT, ST>::Args a) {
   const int n = a.counters[CNT_WALL];
   for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
@@ -500,7 +500,7 @@ __global__ __launch_bounds__(256) void k_lb_wall(const typename Step<LAT, ST>::A
     const uint8_t t = a.tag[c];
     if (t & T_SPEC) continue;
     const int x = c % a.nx, y = (c / a.nx) % a.ny, z = c / (a.nx * a.ny);
-    wall_cell<LAT, ST>(a, c, x, y, z, t);
+    wall_cell<LAT, ST, CUM>(a, c, x, y, z, t);
   }
 }
 
@@ -573,8 +573,11 @@ __device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename S
   }
   const R kG = ((R)1 - q) * own.G[3] + q * rs.v[14];
   const int o = 1 - k;
-  R p_own = sel2(a.iface_pc, k) * own.M[0] + (k == 1 ? (R)baseline(a, c) : (R)0);
-  R p_oth = sel2(a.iface_pc, o) * rs.v[1] + (o == 1 ? (R)baseline(a, sc) : (R)0);
+  // gas baseline (one, or that of the gas endpoint's bubble)
+  R pb = (R)a.scal[SC_PB];
+  if (a.use_pb == 2) pb = a.pbc[k == 1 ? c : sc];
+  R p_own = sel2(a.iface_pc, k) * own.M[0] + (k == 1 ? pb : (R)0);
+  R p_oth = sel2(a.iface_pc, o) * rs.v[1] + (o == 1 ? pb : (R)0);
   for (int m = 0; m < 3; ++m) {
     p_own = p_own + sel2(a.rho_phys, k) * ACC(a, k, m) * (R)(-cc[m]) * q;
     p_oth = p_oth + sel2(a.rho_phys, o) * ACC(a, o, m) * (R)cc[m] * ((R)1 - q);
@@ -672,7 +675,7 @@ __device__ __forceinline__ typename Step<LAT, ST>::R pull_general(const typename
 // a2-a4 for the listed interface-adjacent cells: a runtime loop over the
 // directions gathers the incoming populations into LDS and the moments, a
 // second loop collides and stores.
-template <int LAT, int ST>
+template <int LAT, int ST, bool CUM>
 __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::Args a) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
@@ -758,7 +761,7 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
     const R om = sel2(a.omega, k);
     const R fx = (R)3 * ACC(a, k, 0), fy = (R)3 * ACC(a, k, 1), fz = (R)3 * ACC(a, k, 2);
     bool cum_phase = false;
-    if constexpr (LAT == LSB_D3Q27) cum_phase = sel2(a.cum, k) != 0;
+    if constexpr (LAT == LSB_D3Q27 && CUM) cum_phase = sel2(a.cum, k) != 0;
     // strain-rate moments of the incoming populations; BGK stores here
     R P0 = 0, P1 = 0, P2 = 0, P3 = 0, P4 = 0, P5 = 0;
 #pragma unroll 1
@@ -775,7 +778,7 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
       const R ca = cx * fx + cy * fy + cz * fz;
       store_pop(&a.An[(size_t)i * N + c], C::enc(f - om * fn + w * rho * ca, twinv<LAT, R>(i), s));
     }
-    if constexpr (LAT == LSB_D3Q27) {
+    if constexpr (LAT == LSB_D3Q27 && CUM) {
       if (cum_phase) {
         R dl[Q], out[Q];
 #pragma unroll
