@@ -31,7 +31,7 @@ struct AdjDriver {
     const AdjState& s = p->adj;
     char* d = slot(p, k);
     const size_t N = (size_t)p->N, rb = p->bytes_real;
-    (void)hipMemcpyAsync(d + s.s_A, p->ws + p->off_A[p->cur], (size_t)p->Q * N * p->bytes_pop, hipMemcpyDeviceToDevice, st);
+    (void)hipMemcpyAsync(d + s.s_A, p->ws + p->off_A[p->cur], p->pop_bytes, hipMemcpyDeviceToDevice, st);
     (void)hipMemcpyAsync(d + s.s_M, p->ws + p->off_M[p->cur], 10 * N * rb, hipMemcpyDeviceToDevice, st);
     (void)hipMemcpyAsync(d + s.s_phi, p->ws + p->off_phi, N * rb, hipMemcpyDeviceToDevice, st);
     (void)hipMemcpyAsync(d + s.s_G, p->ws + p->off_G, 4 * N * rb, hipMemcpyDeviceToDevice, st);

@@ -151,7 +151,10 @@ int lsb_create(const lsb_params* P, lsb_plan** out) {
     o = align256(o + bytes);
     return at;
   };
-  for (int b = 0; b < 2; ++b) p->off_A[b] = take((size_t)p->Q * N * p->bytes_pop);
+  // populations: one array per direction in 2D, 256-cell chunks in 3D
+  const size_t npop = P->lattice == LSB_D2Q9 ? N : (N + 255) / 256 * 256;
+  p->pop_bytes = (size_t)p->Q * npop * p->bytes_pop;
+  for (int b = 0; b < 2; ++b) p->off_A[b] = take(p->pop_bytes);
   p->off_phi = take(N * p->bytes_real);
   p->off_s1 = take(N * p->bytes_real);
   p->off_s2 = take(N * p->bytes_real);
@@ -471,7 +474,7 @@ static size_t state_layout(const lsb_plan* p, size_t* o_pop, size_t* o_phi, size
   const size_t N = (size_t)p->N;
   size_t o = 0;
   *o_hdr = o; o = align256(o + 64);
-  *o_pop = o; o = align256(o + (size_t)p->Q * N * p->bytes_pop);
+  *o_pop = o; o = align256(o + p->pop_bytes);
   *o_phi = o; o = align256(o + N * p->bytes_real);
   *o_M = o; o = align256(o + 10 * N * p->bytes_real);
   *o_scal = o; o = align256(o + lsb::SC_COUNT * sizeof(double));
@@ -495,7 +498,7 @@ int lsb_save_state(lsb_plan* p, void* dst, void* stream) {
   const size_t N = (size_t)p->N;
   long hdr[8] = {0x4c5342, p->nstep, p->N, p->Q, (long)p->bytes_pop, 0, 0, 0};
   LSB_HIP(hipMemcpyAsync(d + o_hdr, hdr, sizeof(hdr), hipMemcpyHostToDevice, st));
-  LSB_HIP(hipMemcpyAsync(d + o_pop, p->ws + p->off_A[p->cur], (size_t)p->Q * N * p->bytes_pop, hipMemcpyDeviceToDevice, st));
+  LSB_HIP(hipMemcpyAsync(d + o_pop, p->ws + p->off_A[p->cur], p->pop_bytes, hipMemcpyDeviceToDevice, st));
   LSB_HIP(hipMemcpyAsync(d + o_phi, p->ws + p->off_phi, N * p->bytes_real, hipMemcpyDeviceToDevice, st));
   LSB_HIP(hipMemcpyAsync(d + o_M, p->ws + p->off_M[p->cur], 10 * N * p->bytes_real, hipMemcpyDeviceToDevice, st));
   LSB_HIP(hipMemcpyAsync(d + o_scal, p->ws + p->off_scal, lsb::SC_COUNT * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -519,7 +522,7 @@ int lsb_load_state(lsb_plan* p, const void* src, void* stream) {
   LSB_HIP(hipStreamSynchronize(p->side));
   p->cur = 0;
   p->tcur = 0;
-  LSB_HIP(hipMemcpyAsync(p->ws + p->off_A[0], s + o_pop, (size_t)p->Q * N * p->bytes_pop, hipMemcpyDeviceToDevice, st));
+  LSB_HIP(hipMemcpyAsync(p->ws + p->off_A[0], s + o_pop, p->pop_bytes, hipMemcpyDeviceToDevice, st));
   LSB_HIP(hipMemcpyAsync(p->ws + p->off_phi, s + o_phi, N * p->bytes_real, hipMemcpyDeviceToDevice, st));
   LSB_HIP(hipMemcpyAsync(p->ws + p->off_s1, s + o_phi, N * p->bytes_real, hipMemcpyDeviceToDevice, st));
   LSB_HIP(hipMemcpyAsync(p->ws + p->off_s2, s + o_phi, N * p->bytes_real, hipMemcpyDeviceToDevice, st));
@@ -595,7 +598,7 @@ static void adj_layout(const lsb_plan* p, int max_steps, lsb::AdjState& s, size_
     o = align256(o + bytes);
     return at;
   };
-  s.s_A = take((size_t)p->Q * N * p->bytes_pop);
+  s.s_A = take(p->pop_bytes);
   s.s_M = take(10 * N * rb);
   s.s_phi = take(N * rb);
   s.s_G = take(4 * N * rb);

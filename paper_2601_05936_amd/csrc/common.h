@@ -74,6 +74,33 @@ __host__ __device__ constexpr double wgt(int i) {
        : (c2<LAT>(i) == 0 ? 8.0 / 27 : c2<LAT>(i) == 1 ? 2.0 / 27 : c2<LAT>(i) == 2 ? 1.0 / 54 : 1.0 / 216);
 }
 
+// ---------------------------------------------------------------------------
+// Population layout.  D2Q9: one array per direction, [q][cell].  D3Q19 and
+// D3Q27: the cells in chunks of 256 consecutive cells, [cell / 256][q]
+// [cell % 256]: the directions of a chunk are stored together, so the
+// loads and stores of a 256-cell block fall into few DRAM pages (the D3Q27
+// FP16 pull pattern runs at 5.83 TB/s this way against 5.31 TB/s with one
+// array per direction).  The 3D layout pads N to a multiple of 256.
+// ---------------------------------------------------------------------------
+template <int LAT>
+__host__ __device__ __forceinline__ size_t pop_cell(int c) {  // element offset of cell c, direction 0
+  if constexpr (LAT == LSB_D2Q9) return (size_t)c;
+  else return (size_t)(c >> 8) * (size_t)(Lat<LAT>::Q << 8) + (size_t)(c & 255);
+}
+template <int LAT>
+__host__ __device__ __forceinline__ size_t pop_dir(int i, size_t N) {  // element offset of direction i
+  if constexpr (LAT == LSB_D2Q9) return (size_t)i * N;
+  else return (size_t)i << 8;
+}
+template <int LAT>
+__host__ __device__ __forceinline__ size_t pidx(int i, int c, size_t N) {
+  return pop_dir<LAT>(i, N) + pop_cell<LAT>(c);
+}
+template <int LAT>
+__host__ __device__ inline size_t pop_elems(size_t N) {  // elements of one population buffer
+  return LAT == LSB_D2Q9 ? (size_t)Lat<LAT>::Q * N : (size_t)Lat<LAT>::Q * ((N + 255) / 256 * 256);
+}
+
 template <int LAT>
 __host__ __device__ constexpr int opp(int i) {
   int j = 0;

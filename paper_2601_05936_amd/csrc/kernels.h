@@ -38,14 +38,6 @@ struct Step {
 // equilibrium, w (rho - 1 + rho (9/2 (c.u)^2 - 3/2 u.u)), and flip the sign of
 // the odd parts (3 w rho c.u and the force 3 w rho c.a).
 // ---------------------------------------------------------------------------
-// Element of direction array `dir_base` (in elements from the population
-// base) at a 32-bit byte offset: the direction base is uniform, so the
-// address is a scalar base plus one 32-bit vector offset.
-template <class T>
-__device__ __forceinline__ T* pop_at(T* base, size_t dir_base, unsigned byte_off) {
-  return reinterpret_cast<T*>(reinterpret_cast<char*>(base + dir_base) + byte_off);
-}
-
 // gas pressure baseline seen by a gas cell: the single baseline, or with
 // several bubbles that of the cell's bubble
 template <class Args>
@@ -208,7 +200,7 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
   const R ux3 = (R)3 * rho * ux, uy3 = (R)3 * rho * uy, uz3 = (R)3 * rho * uz;
   const R s = a.scale;
   const size_t N = a.N;
-  const unsigned cb = (unsigned)c * (unsigned)sizeof(T);  // byte offset of the cell in a direction array
+  const size_t pc = pop_cell<LAT>(c);  // the cell in the population layout
   bool cum_phase = false;
   if constexpr (LAT == LSB_D3Q27 && CUM) cum_phase = sel2(a.cum, k) != 0;
   if (cum_phase) {
@@ -225,7 +217,7 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
         if (cz) ca += (R)cz * fz;
         v += (R)wgt<LAT>(i) * ca;
       }
-      store_pop(pop_at(a.An, (size_t)i * N, cb), C::enc(v, (R)(1.0 / wgt<LAT>(i)), s));
+      store_pop(a.An + pc + pop_dir<LAT>(i, N), C::enc(v, (R)(1.0 / wgt<LAT>(i)), s));
     }
   } else {
 #pragma unroll
@@ -241,7 +233,7 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
     const R even = w * (rp + rho * ((R)4.5 * cu * cu - uu15));
     if (j == i) {
       const R out = omc * d[i] + om * even;
-      store_pop(pop_at(a.An, (size_t)i * N, cb), C::enc(out, (R)(1.0 / wgt<LAT>(i)), s));
+      store_pop(a.An + pc + pop_dir<LAT>(i, N), C::enc(out, (R)(1.0 / wgt<LAT>(i)), s));
       continue;
     }
     const R odd = w * cu3;
@@ -252,8 +244,8 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
       out_i = out_i + fo;
       out_j = out_j - fo;
     }
-    store_pop(pop_at(a.An, (size_t)i * N, cb), C::enc(out_i, (R)(1.0 / wgt<LAT>(i)), s));
-    store_pop(pop_at(a.An, (size_t)j * N, cb), C::enc(out_j, (R)(1.0 / wgt<LAT>(j)), s));
+    store_pop(a.An + pc + pop_dir<LAT>(i, N), C::enc(out_i, (R)(1.0 / wgt<LAT>(i)), s));
+    store_pop(a.An + pc + pop_dir<LAT>(j, N), C::enc(out_j, (R)(1.0 / wgt<LAT>(j)), s));
   }
   }
   if (active) {
@@ -330,14 +322,14 @@ __device__ __forceinline__ typename Step<LAT, ST>::R wall_pull(const typename St
     const int face = 2 * ax + (pos[ax] - cc[ax] < 0 ? 0 : 1);
     if (sel6(a.bcf, face) == LSB_NOSLIP) {
       const R cu = (R)cc[0] * WALLU(a, face, 0) + (R)cc[1] * WALLU(a, face, 1) + (R)cc[2] * WALLU(a, face, 2);
-      return C::dec(a.A[(size_t)j * a.N + c], wj, a.inv_scale) + (R)6 * (R)wgt<LAT>(i) * cu;
+      return C::dec(a.A[pidx<LAT>(j, c, a.N)], wj, a.inv_scale) + (R)6 * (R)wgt<LAT>(i) * cu;
     }
   }
   const int ir = reflect_dir<LAT>(i, mask);
   const int sc = (src[2] * a.ny + src[1]) * a.nx + src[0];
-  if (check_phase && ((a.tag[sc] & T_GAS) != k)) return C::dec(a.A[(size_t)j * a.N + c], wj, a.inv_scale);
+  if (check_phase && ((a.tag[sc] & T_GAS) != k)) return C::dec(a.A[pidx<LAT>(j, c, a.N)], wj, a.inv_scale);
   const R wr = (R)wgt<LAT>(ir);
-  return C::dec(a.A[(size_t)ir * a.N + sc], wr, a.inv_scale);
+  return C::dec(a.A[pidx<LAT>(ir, sc, a.N)], wr, a.inv_scale);
 }
 
 // ---------------------------------------------------------------------------
@@ -397,13 +389,19 @@ __device__ __forceinline__ void fast_cell(const typename Step<LAT, ST>::Args& a,
   for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy) rowoff[dz][dy] = (zs[dz] * a.ny + ys[dy]) * a.nx;
-  // uniform per-direction base plus a 32-bit byte offset per lane (no 64-bit
-  // address arithmetic per load)
+  // uniform per-direction base plus a per-lane offset of the source cell
+  // (one array per direction: a 32-bit byte offset; chunked layout: the
+  // chunk and position of the source cell)
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const char* __restrict__ Ai = reinterpret_cast<const char*>(a.A + (size_t)i * a.N);
-    const unsigned off = (unsigned)(rowoff[L::cz(i) + 1][L::cy(i) + 1] + xs[L::cx(i) + 1]) * (unsigned)sizeof(T);
-    d[i] = C::dec(*reinterpret_cast<const T*>(Ai + off), (R)wgt<LAT>(i), is);
+    const int sc = rowoff[L::cz(i) + 1][L::cy(i) + 1] + xs[L::cx(i) + 1];
+    if constexpr (LAT == LSB_D2Q9) {
+      const char* __restrict__ Ai = reinterpret_cast<const char*>(a.A + (size_t)i * a.N);
+      d[i] = C::dec(*reinterpret_cast<const T*>(Ai + (unsigned)sc * (unsigned)sizeof(T)), (R)wgt<LAT>(i), is);
+    } else {
+      const T* __restrict__ Ai = a.A + pop_dir<LAT>(i, a.N);
+      d[i] = C::dec(Ai[pop_cell<LAT>(sc)], (R)wgt<LAT>(i), is);
+    }
   }
   collide_store<LAT, ST, FORCE, CUM>(a, c, t & T_GAS, (t & T_ACT) != 0, d);
 }
@@ -426,7 +424,7 @@ __device__ __forceinline__ void wall_cell(const typename Step<LAT, ST>::Args& a,
   for (int i = 0; i < Q; ++i) {
     const int sx = xs[L::cx(i) + 1], sy = ys[L::cy(i) + 1], sz = zs[L::cz(i) + 1];
     if ((sx | sy | sz) >= 0) {
-      d[i] = C::dec(a.A[(size_t)i * a.N + (sz * a.ny + sy) * a.nx + sx], (R)wgt<LAT>(i), is);
+      d[i] = C::dec(a.A[pidx<LAT>(i, (sz * a.ny + sy) * a.nx + sx, a.N)], (R)wgt<LAT>(i), is);
     } else {
       d[i] = wall_pull<LAT, ST, false>(a, c, x, y, z, i, k);
     }
@@ -603,7 +601,7 @@ __device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename S
   const R s_own = (k == 0) ? (R)1 : (R)-1;
   const R cu = (R)cc[0] * uG[0] + (R)cc[1] * uG[1] + (R)cc[2] * uG[2];
   const R W = (R)6 * w * (cu + q * ((R)1 - q) * s_own * cSc);
-  const R dj = C::dec(a.A[(size_t)j * N + c], w, a.inv_scale);
+  const R dj = C::dec(a.A[pidx<LAT>(j, c, N)], w, a.inv_scale);
   if (q < (R)0.5) {
     const int fx = lb_coord(x + cc[0], a.nx, a.per[0]);
     const int fy = lb_coord(y + cc[1], a.ny, a.per[1]);
@@ -611,13 +609,13 @@ __device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename S
     if ((fx | fy | fz) >= 0) {
       const int fc = (fz * a.ny + fy) * a.nx + fx;
       if ((a.tag[fc] & T_GAS) == k) {
-        const R djf = C::dec(a.A[(size_t)j * N + fc], w, a.inv_scale);
+        const R djf = C::dec(a.A[pidx<LAT>(j, fc, N)], w, a.inv_scale);
         return (R)2 * q * dj + ((R)1 - (R)2 * q) * djf + W;
       }
     }
     return dj + W;
   }
-  const R di = C::dec(a.A[(size_t)i * N + c], w, a.inv_scale);
+  const R di = C::dec(a.A[pidx<LAT>(i, c, N)], w, a.inv_scale);
   const R i2q = (R)1 / ((R)2 * q);
   return dj * i2q + ((R)2 * q - (R)1) * i2q * di + W * i2q;
 }
@@ -657,18 +655,18 @@ __device__ __forceinline__ typename Step<LAT, ST>::R pull_general(const typename
       const int face = 2 * ax + (pos[ax] - cc[ax] < 0 ? 0 : 1);
       if (sel6(a.bcf, face) == LSB_NOSLIP) {
         const R cu = (R)cc[0] * WALLU(a, face, 0) + (R)cc[1] * WALLU(a, face, 1) + (R)cc[2] * WALLU(a, face, 2);
-        return C::dec(a.A[(size_t)j * a.N + c], w, a.inv_scale) + (R)6 * w * cu;
+        return C::dec(a.A[pidx<LAT>(j, c, a.N)], w, a.inv_scale) + (R)6 * w * cu;
       }
     }
     const int sc = (src[2] * a.ny + src[1]) * a.nx + src[0];
-    if ((a.tag[sc] & T_GAS) != k) return C::dec(a.A[(size_t)j * a.N + c], w, a.inv_scale);
+    if ((a.tag[sc] & T_GAS) != k) return C::dec(a.A[pidx<LAT>(j, c, a.N)], w, a.inv_scale);
     int ir = 0;
     for (int m = 0; m < S::Q; ++m)
       if (tab<LAT>.cx[m] == rc[0] && tab<LAT>.cy[m] == rc[1] && tab<LAT>.cz[m] == rc[2]) ir = m;
-    return C::dec(a.A[(size_t)ir * a.N + sc], w, a.inv_scale);
+    return C::dec(a.A[pidx<LAT>(ir, sc, a.N)], w, a.inv_scale);
   }
   const int sc = (sz * a.ny + sy) * a.nx + sx;
-  if ((a.tag[sc] & T_GAS) == k) return C::dec(a.A[(size_t)i * a.N + sc], w, a.inv_scale);
+  if ((a.tag[sc] & T_GAS) == k) return C::dec(a.A[pidx<LAT>(i, sc, a.N)], w, a.inv_scale);
   return iface_pull<LAT, ST>(a, own, c, x, y, z, sc, i, k);
 }
 
@@ -721,7 +719,7 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
         }
         const int sc = (sz * a.ny + sy) * a.nx + sx;
         const uint8_t ts = a.tag[sc];
-        const T v = a.A[(size_t)i * N + sc];
+        const T v = a.A[pidx<LAT>(i, sc, N)];
         if ((ts & T_GAS) != k) {
           cut |= 1u << i;
           continue;
@@ -776,7 +774,7 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
       P3 += cx * cy * fn; P4 += cx * cz * fn; P5 += cy * cz * fn;
       if (cum_phase) continue;
       const R ca = cx * fx + cy * fy + cz * fz;
-      store_pop(&a.An[(size_t)i * N + c], C::enc(f - om * fn + w * rho * ca, twinv<LAT, R>(i), s));
+      store_pop(&a.An[pidx<LAT>(i, c, N)], C::enc(f - om * fn + w * rho * ca, twinv<LAT, R>(i), s));
     }
     if constexpr (LAT == LSB_D3Q27 && CUM) {
       if (cum_phase) {
@@ -791,7 +789,7 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
           if (L::cx(i)) ca += (R)L::cx(i) * fx;
           if (L::cy(i)) ca += (R)L::cy(i) * fy;
           if (L::cz(i)) ca += (R)L::cz(i) * fz;
-          store_pop(&a.An[(size_t)i * N + c], C::enc(out[i] + (R)wgt<LAT>(i) * rho * ca, (R)(1.0 / wgt<LAT>(i)), s));
+          store_pop(&a.An[pidx<LAT>(i, c, N)], C::enc(out[i] + (R)wgt<LAT>(i) * rho * ca, (R)(1.0 / wgt<LAT>(i)), s));
         }
       }
     }
@@ -1443,9 +1441,9 @@ __global__ __launch_bounds__(256) void k_refill(const typename Step<LAT, ST>::Ar
         // equilibria as deviations from the rest state
         const R de = w * (rr + ((R)1 + rr) * ((R)3 * cur + (R)4.5 * cur * cur - (R)1.5 * uur));
         const R de1 = w * (r1 + ((R)1 + r1) * ((R)3 * cu1 + (R)4.5 * cu1 * cu1 - (R)1.5 * uu1));
-        const R d1 = C::dec(a.An[(size_t)k * N + c1], w, a.inv_scale);
+        const R d1 = C::dec(a.An[pidx<LAT>(k, c1, N)], w, a.inv_scale);
         // f(x_r) = feq(rho_r, u_r) + (f(x1) - feq(x1))
-        a.An[(size_t)k * N + c] = C::enc(de + (d1 - de1), (R)(1.0 / wgt<LAT>(k)), s);
+        a.An[pidx<LAT>(k, c, N)] = C::enc(de + (d1 - de1), (R)(1.0 / wgt<LAT>(k)), s);
       }
       a.Mn[c] = rr;
       for (int m = 0; m < 3; ++m) a.Mn[(1 + m) * N + c] = ur[m];
@@ -1459,7 +1457,7 @@ __global__ __launch_bounds__(256) void k_refill(const typename Step<LAT, ST>::Ar
         const R w = (R)wgt<LAT>(k);
         const R cu = (R)L::cx(k) * uG0 + (R)L::cy(k) * uG1 + (R)L::cz(k) * uG2;
         const R de = w * (rhoG + ((R)1 + rhoG) * ((R)3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu));
-        a.An[(size_t)k * N + c] = C::enc(de, (R)(1.0 / wgt<LAT>(k)), s);
+        a.An[pidx<LAT>(k, c, N)] = C::enc(de, (R)(1.0 / wgt<LAT>(k)), s);
       }
       a.Mn[c] = rhoG;
       for (int m = 0; m < 6; ++m) a.Mn[(4 + m) * N + c] = 0;
@@ -1806,7 +1804,7 @@ __global__ __launch_bounds__(256) void k_init_pop(const typename Step<LAT, ST>::
       const double w = wgt<LAT>(i);
       const double cu = L::cx(i) * u[0] + L::cy(i) * u[1] + L::cz(i) * u[2];
       const double fe = w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-      a.An[(size_t)i * N + c] = C::enc((R)(fe - w), (R)(1.0 / w), s);
+      a.An[pidx<LAT>(i, c, N)] = C::enc((R)(fe - w), (R)(1.0 / w), s);
     }
     R* Ms[2] = {const_cast<R*>(a.M), a.Mn};
     for (int b = 0; b < 2; ++b) {
@@ -1831,7 +1829,7 @@ __global__ __launch_bounds__(256) void k_fields(const typename Step<LAT, ST>::Ar
 #pragma unroll
     for (int i = 0; i < S::Q; ++i) {
       const R w = (R)wgt<LAT>(i);
-      const double f = wgt<LAT>(i) + (double)C::dec(a.A[(size_t)i * a.N + c], w, a.inv_scale);
+      const double f = wgt<LAT>(i) + (double)C::dec(a.A[pidx<LAT>(i, c, a.N)], w, a.inv_scale);
       rho += f;
       m[0] += L::cx(i) * f; m[1] += L::cy(i) * f; m[2] += L::cz(i) * f;
     }
@@ -1857,7 +1855,7 @@ __global__ __launch_bounds__(256) void k_populations(const typename Step<LAT, ST
     for (int i = i0; i < i1; ++i) {
       double w = 0;
       for (int k = 0; k < S::Q; ++k) if (k == i) w = wgt<LAT>(k);
-      out[(size_t)(i - i0) * n + (c - c0)] = w + (double)C::dec(a.A[(size_t)i * a.N + c], (R)w, a.inv_scale);
+      out[(size_t)(i - i0) * n + (c - c0)] = w + (double)C::dec(a.A[pidx<LAT>(i, c, a.N)], (R)w, a.inv_scale);
     }
 }
 
@@ -1878,7 +1876,7 @@ __global__ __launch_bounds__(256) void k_integrals_partial(const typename Step<L
 #pragma unroll
     for (int i = 0; i < S::Q; ++i) {
       const R w = (R)wgt<LAT>(i);
-      const double f = wgt<LAT>(i) + (double)C::dec(a.A[(size_t)i * a.N + c], w, a.inv_scale);
+      const double f = wgt<LAT>(i) + (double)C::dec(a.A[pidx<LAT>(i, c, a.N)], w, a.inv_scale);
       rho += f;
       m[0] += L::cx(i) * f; m[1] += L::cy(i) * f; m[2] += L::cz(i) * f;
     }

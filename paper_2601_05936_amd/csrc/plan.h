@@ -79,6 +79,7 @@ struct lsb_plan {
   int D = 0, Q = 0;
   int N = 0;
   size_t bytes_pop = 0;  // bytes per stored population value
+  size_t pop_bytes = 0;  // bytes of one population buffer (the 3D layout pads N to a multiple of 256)
   size_t bytes_real = 0; // bytes per level-set / moment value
   int tdim[3] = {1, 1, 1};
   int ntile[3] = {1, 1, 1};
