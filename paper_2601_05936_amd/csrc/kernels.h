@@ -392,13 +392,32 @@ __device__ __forceinline__ void fast_cell(const typename Step<LAT, ST>::Args& a,
   // uniform per-direction base plus a per-lane offset of the source cell
   // (one array per direction: a 32-bit byte offset; chunked layout: the
   // chunk and position of the source cell)
+  if constexpr (LAT == LSB_D2Q9) {
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const int sc = rowoff[L::cz(i) + 1][L::cy(i) + 1] + xs[L::cx(i) + 1];
-    if constexpr (LAT == LSB_D2Q9) {
+    for (int i = 0; i < Q; ++i) {
+      const int sc = rowoff[L::cz(i) + 1][L::cy(i) + 1] + xs[L::cx(i) + 1];
       const char* __restrict__ Ai = reinterpret_cast<const char*>(a.A + (size_t)i * a.N);
       d[i] = C::dec(*reinterpret_cast<const T*>(Ai + (unsigned)sc * (unsigned)sizeof(T)), (R)wgt<LAT>(i), is);
-    } else {
+    }
+  } else if ((a.nx & 255) == 0) {
+    // rows start at chunk boundaries: a source cell's offset is its row's
+    // chunk base plus the chunk offset of its x (9 + 3 terms, one add each)
+    size_t rb[3][3], xo[3];
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) rb[dz][dy] = (size_t)(rowoff[dz][dy] >> 8) * (size_t)(Q << 8);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) xo[k] = pop_cell<LAT>(xs[k]);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const T* __restrict__ Ai = a.A + pop_dir<LAT>(i, a.N);
+      d[i] = C::dec(Ai[rb[L::cz(i) + 1][L::cy(i) + 1] + xo[L::cx(i) + 1]], (R)wgt<LAT>(i), is);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int sc = rowoff[L::cz(i) + 1][L::cy(i) + 1] + xs[L::cx(i) + 1];
       const T* __restrict__ Ai = a.A + pop_dir<LAT>(i, a.N);
       d[i] = C::dec(Ai[pop_cell<LAT>(sc)], (R)wgt<LAT>(i), is);
     }
