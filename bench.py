@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # FETCH_SIZE / WRITE_SIZE runs, scaled by a plain 4 GiB copy (fetch x2.000,
 # write x1.000); recorded in profiles/k_lb_bulk_wavy512_d3q27_f16dev_hbm_traffic.md.
 # Valid only for that kernel build, storage, schedule and size: null otherwise.
-MEASURED_TRAFFIC = {("f16dev", "serial", 512): 14677429948}
+MEASURED_TRAFFIC = {("f16dev", "serial", 512): 14675680100}
 
 
 def log(*a):
