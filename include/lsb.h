@@ -93,7 +93,9 @@ typedef struct lsb_params {
 typedef struct lsb_plan lsb_plan; /* opaque; owned by the library */
 
 /* Integral quantities (Sec. 3.2): per-phase mass, Heaviside-weighted gas
- * volume, centroid and bubble velocity, gas pressure baseline, max |u|. */
+ * volume, centroid and bubble velocity of all gas, gas pressure baseline
+ * (use_pb = 1: the one baseline; use_pb = 0 or 2: pb0, the per-bubble
+ * baselines are in lsb_get_bubbles), max |u|. */
 typedef struct lsb_integrals {
   double mass[2];
   double volume_gas;
