@@ -318,8 +318,10 @@ struct TileShape {
   static constexpr int SX = D == 3 ? 5 : 4, SY = D == 3 ? 2 : 4, SZ = D == 3 ? 2 : 0;
   static constexpr int X = 1 << SX, Y = 1 << SY, Z = 1 << SZ;
 };
-// LDS slots of the classification kernel (a tile plus a one-cell halo)
+// largest tile plus one-cell halo, in cells, that the tile kernels accept
 constexpr int kClassifyLds = 1280;
+// candidate tiles per block batch of the classification kernel
+constexpr int kClassifyBatch = 8;
 
 // Append for the lanes of a wavefront with pred set: one atomic per
 // wavefront on the counter; lanes keep their order.  Returns the slot of

@@ -346,17 +346,20 @@ __device__ __forceinline__ void tile_origin(const Args& a, int t, int& x0, int& 
   z0 = tz << TS::SZ;
 }
 
-// Loop body over the cells of the listed tiles:  F(c, x, y, z).  Every lane
-// of a block runs the same number of iterations (tile sizes are multiples
-// of the block size).
+// Loop body over the cells of the listed tiles:  F(c, x, y, z).  Blocks of
+// 256 threads; every lane runs the same number of iterations (tile sizes are
+// multiples of the block size).
 template <int D, class Args, class F>
 __device__ __forceinline__ void for_tile_cells(const Args& a, const int* list, int count, F&& f) {
   using TS = TileShape<D>;
   constexpr int tcells = TS::X * TS::Y * TS::Z;
+  static_assert(tcells % 256 == 0, "tile sizes are multiples of the block size");
   for (int e = blockIdx.x; e < count; e += gridDim.x) {
     int x0, y0, z0;
-    tile_origin<D>(a, list[e], x0, y0, z0);
-    for (int l = threadIdx.x; l < tcells; l += blockDim.x) {
+    // one tile per block: its origin is scalar arithmetic
+    tile_origin<D>(a, __builtin_amdgcn_readfirstlane(list[e]), x0, y0, z0);
+#pragma unroll
+    for (int l = threadIdx.x; l < tcells; l += 256) {
       const int x = x0 + (l & (TS::X - 1));
       const int y = y0 + ((l >> TS::SX) & (TS::Y - 1));
       const int z = z0 + (l >> (TS::SX + TS::SY));
@@ -560,19 +563,56 @@ __device__ __forceinline__ auto load_rec(const Args& a, int c) {
   return *reinterpret_cast<const IfaceRec<R>*>(a.irec + (size_t)16 * c);
 }
 
+// Operands of the bounce-back on one cut link (direction i, source sc in the
+// other phase), loaded before any of them is used so that the loads of
+// several links are in flight together.  The forward neighbour's tag and
+// population are loaded whatever q turns out to be.
 template <int LAT, int ST>
-__device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename Step<LAT, ST>::Args& a,
-                                                                  const OwnCell<typename Step<LAT, ST>::R>& own, int c,
-                                                                  int x, int y, int z, int sc, int i, int k) {
+struct CutLink {
+  using R = typename Step<LAT, ST>::R;
+  using T = typename Step<LAT, ST>::T;
+  IfaceRec<R> rs;  // phi, M, G of the other-phase cell
+  R pb;            // gas baseline (one, or that of the gas endpoint's bubble)
+  T dj, di, djf;   // stored populations: own cell at j and i, forward neighbour at j
+  uint8_t ftag;    // forward neighbour's tag (T_WALL when it lies beyond a wall face)
+};
+
+template <int LAT, int ST>
+__device__ __forceinline__ CutLink<LAT, ST> cut_fetch(const typename Step<LAT, ST>::Args& a, int c, int x, int y,
+                                                      int z, int sc, int i, int k) {
+  const size_t N = a.N;
+  const int j = tab<LAT>.opp[i];
+  CutLink<LAT, ST> L;
+  L.rs = load_rec(a, sc);
+  L.pb = (typename Step<LAT, ST>::R)a.scal[SC_PB];
+  if (a.use_pb == 2) L.pb = a.pbc[k == 1 ? c : sc];
+  L.dj = a.A[pidx<LAT>(j, c, N)];
+  L.di = a.A[pidx<LAT>(i, c, N)];
+  const int fx = lb_coord(x + tab<LAT>.cx[i], a.nx, a.per[0]);
+  const int fy = lb_coord(y + tab<LAT>.cy[i], a.ny, a.per[1]);
+  const int fz = lb_coord(z + tab<LAT>.cz[i], a.nz, a.per[2]);
+  L.ftag = T_WALL;
+  L.djf = L.dj;
+  if ((fx | fy | fz) >= 0) {
+    const int fc = (fz * a.ny + fy) * a.nx + fx;
+    L.ftag = a.tag[fc] & T_GAS;
+    L.djf = a.A[pidx<LAT>(j, fc, N)];
+  }
+  return L;
+}
+
+// Interface bounce-back with the stress jump for one cut link, from its
+// fetched operands.
+template <int LAT, int ST>
+__device__ __forceinline__ typename Step<LAT, ST>::R cut_eval(const typename Step<LAT, ST>::Args& a,
+                                                               const OwnCell<typename Step<LAT, ST>::R>& own,
+                                                               const CutLink<LAT, ST>& L, int i, int k) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
   using C = typename S::C;
-  const size_t N = a.N;
   const int cc[3] = {tab<LAT>.cx[i], tab<LAT>.cy[i], tab<LAT>.cz[i]};
-  const int j = tab<LAT>.opp[i];
-  const R s = a.scale;
   const R w = tw<LAT, R>(i);
-  const IfaceRec<R> rs = load_rec(a, sc);  // phi, M, G of the other-phase cell
+  const IfaceRec<R>& rs = L.rs;
   const R px = own.phi, py = rs.v[0];
   const R q = px / (px - py);
   // interface velocity (linear interpolation of the previous moments)
@@ -590,9 +630,7 @@ __device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename S
   }
   const R kG = ((R)1 - q) * own.G[3] + q * rs.v[14];
   const int o = 1 - k;
-  // gas baseline (one, or that of the gas endpoint's bubble)
-  R pb = (R)a.scal[SC_PB];
-  if (a.use_pb == 2) pb = a.pbc[k == 1 ? c : sc];
+  const R pb = L.pb;
   R p_own = sel2(a.iface_pc, k) * own.M[0] + (k == 1 ? pb : (R)0);
   R p_oth = sel2(a.iface_pc, o) * rs.v[1] + (o == 1 ? pb : (R)0);
   for (int m = 0; m < 3; ++m) {
@@ -620,23 +658,24 @@ __device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename S
   const R s_own = (k == 0) ? (R)1 : (R)-1;
   const R cu = (R)cc[0] * uG[0] + (R)cc[1] * uG[1] + (R)cc[2] * uG[2];
   const R W = (R)6 * w * (cu + q * ((R)1 - q) * s_own * cSc);
-  const R dj = C::dec(a.A[pidx<LAT>(j, c, N)], w, a.inv_scale);
+  const R dj = C::dec(L.dj, w, a.inv_scale);
   if (q < (R)0.5) {
-    const int fx = lb_coord(x + cc[0], a.nx, a.per[0]);
-    const int fy = lb_coord(y + cc[1], a.ny, a.per[1]);
-    const int fz = lb_coord(z + cc[2], a.nz, a.per[2]);
-    if ((fx | fy | fz) >= 0) {
-      const int fc = (fz * a.ny + fy) * a.nx + fx;
-      if ((a.tag[fc] & T_GAS) == k) {
-        const R djf = C::dec(a.A[pidx<LAT>(j, fc, N)], w, a.inv_scale);
-        return (R)2 * q * dj + ((R)1 - (R)2 * q) * djf + W;
-      }
+    if (L.ftag == k) {
+      const R djf = C::dec(L.djf, w, a.inv_scale);
+      return (R)2 * q * dj + ((R)1 - (R)2 * q) * djf + W;
     }
     return dj + W;
   }
-  const R di = C::dec(a.A[pidx<LAT>(i, c, N)], w, a.inv_scale);
+  const R di = C::dec(L.di, w, a.inv_scale);
   const R i2q = (R)1 / ((R)2 * q);
   return dj * i2q + ((R)2 * q - (R)1) * i2q * di + W * i2q;
+}
+
+template <int LAT, int ST>
+__device__ __forceinline__ typename Step<LAT, ST>::R iface_pull(const typename Step<LAT, ST>::Args& a,
+                                                                  const OwnCell<typename Step<LAT, ST>::R>& own, int c,
+                                                                  int x, int y, int z, int sc, int i, int k) {
+  return cut_eval<LAT, ST>(a, own, cut_fetch<LAT, ST>(a, c, x, y, z, sc, i, k), i, k);
 }
 
 // Incoming deviation of direction i (runtime index) for an interface-adjacent
@@ -746,15 +785,24 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
         fl[i * 256 + threadIdx.x] = C::dec(v, (R)wgt<LAT>(i), is);
       }
     }
-    // pass 2: interface bounce-back on the cut links
-    while (cut) {
-      const int i = __ffs(cut) - 1;
-      cut &= cut - 1u;
+    // pass 2: interface bounce-back on the cut links, two at a time: the
+    // loads of both links are issued before either is evaluated
+    auto cut_source = [&](int i) {  // in the domain (not a wall link)
       const int sx = lb_coord(x - tab<LAT>.cx[i], a.nx, a.per[0]);
       const int sy = lb_coord(y - tab<LAT>.cy[i], a.ny, a.per[1]);
       const int sz = lb_coord(z - tab<LAT>.cz[i], a.nz, a.per[2]);
-      const int sc = (sz * a.ny + sy) * a.nx + sx;  // in the domain (not a wall link)
-      fl[i * 256 + threadIdx.x] = iface_pull<LAT, ST>(a, own, c, x, y, z, sc, i, k);
+      return (sz * a.ny + sy) * a.nx + sx;
+    };
+    while (cut) {
+      const int i0 = __ffs(cut) - 1;
+      cut &= cut - 1u;
+      const int i1 = cut ? __ffs(cut) - 1 : -1;
+      cut &= cut - 1u;
+      const CutLink<LAT, ST> L0 = cut_fetch<LAT, ST>(a, c, x, y, z, cut_source(i0), i0, k);
+      CutLink<LAT, ST> L1;
+      if (i1 >= 0) L1 = cut_fetch<LAT, ST>(a, c, x, y, z, cut_source(i1), i1, k);
+      fl[i0 * 256 + threadIdx.x] = cut_eval<LAT, ST>(a, own, L0, i0, k);
+      if (i1 >= 0) fl[i1 * 256 + threadIdx.x] = cut_eval<LAT, ST>(a, own, L1, i1, k);
     }
     // pass 3: links through a wall face
     while (wall) {
@@ -1174,128 +1222,224 @@ __global__ __launch_bounds__(256) void k_dilate(const typename Step<LAT, ST>::Ar
   }
 }
 
+// Candidate tiles are classified kClassifyBatch at a time per block, and the
+// block reserves the list slots of the whole batch with one atomic per list:
+// atomics on one counter from every block serialise on the device (about
+// 12 ns each on MI355X), so one per tile would cost more than the
+// classification itself.
+//
+// The neighbourhood tests run on bit masks: one wavefront ballot per halo row
+// (x along the lanes) gives the row's in-band, gas and liquid cells; OR-ing
+// the 3^(D-1) rows around a tile row gives, bit by bit along x, what its
+// cells' neighbourhoods hold, and a cell reads its three bits at its own x.
 template <int LAT, int ST>
 __global__ __launch_bounds__(256) void k_classify(const typename Step<LAT, ST>::Args a, int record_flips) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
-  using L = typename S::L;
   using TS = TileShape<S::D>;
+  using u64 = unsigned long long;
   constexpr int tcells = TS::X * TS::Y * TS::Z;
   constexpr int ITER = tcells / 256;  // cells per thread
   constexpr int NW = 256 / 64;        // wavefronts per block
+  constexpr int KT = kClassifyBatch;
   constexpr int hz = S::D == 3 ? 1 : 0;
   constexpr int LX = TS::X + 2, LY = TS::Y + 2, LZ = TS::Z + 2 * hz;
-  static_assert(LX * LY * LZ <= kClassifyLds, "classification tile does not fit the LDS buffer");
+  constexpr int NR = LY * LZ;               // halo rows of a tile
+  constexpr int RPW = (NR + NW - 1) / NW;   // halo rows per wavefront
+  constexpr int TR = TS::Y * TS::Z;         // tile rows
+  static_assert(LX <= 64, "a halo row must fit the lanes of one wavefront");
   static_assert(ITER * 256 == tcells, "tile size must be a multiple of the block size");
-  // tile plus a one-cell halo staged in LDS; cells beyond a wall face are
-  // marked invalid (lattice-neighbour semantics: they are skipped)
-  __shared__ R sphi[kClassifyLds];
-  __shared__ int wcnt[2][ITER][NW];  // spec / flip cells per wavefront and pass
-  __shared__ int wact[NW];
-  __shared__ int base[2];
+  static_assert(KT * ITER <= 32, "one flag word per thread holds a batch");
+  static_assert(TR <= 256, "one thread per tile row");
+  constexpr int NE = KT * ITER * NW;        // count entries of a batch
+  static_assert(NE <= 64, "one lane of a wavefront per count entry");
+  // per halo row: in-band, gas and liquid cells (cells beyond a wall face
+  // are none of them: lattice-neighbour semantics, they are skipped)
+  __shared__ u64 rowm[NR][3];
+  // per tile row, over its 3^(D-1) neighbour rows: any in band; gas and
+  // liquid in the rows that differ in at most one of y, z ("edge") and in
+  // the rows that differ in both ("corner", whose lattice links D3Q19 lacks
+  // except along x = 0)
+  __shared__ u64 summ[TR][5];
+  __shared__ int wcnt[2][KT][ITER][NW];  // spec / flip cells per tile, pass and wavefront
+  __shared__ int wact[KT][NW];
+  __shared__ int tiles[KT];
+  __shared__ int pre[2][KT][ITER][NW];   // first list slot of each count entry
   const int count = a.counters[CNT_CAND];
-  const int wave = threadIdx.x >> 6;
+  // wavefront index and tile origins are uniform: scalar arithmetic
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   const R B = a.band;
   const R INVALID = (R)1e30;
-  for (int e = blockIdx.x; e < count; e += gridDim.x) {
-    const int t = a.cand_list[e];
-    int x0, y0, z0;
-    tile_origin<S::D>(a, t, x0, y0, z0);
-    for (int l = threadIdx.x; l < LX * LY * LZ; l += blockDim.x) {
-      const int lx = l % LX, ly = (l / LX) % LY, lz = l / (LX * LY);
-      const int gx = lb_coord(x0 - 1 + lx, a.nx, a.per[0]);
-      const int gy = lb_coord(y0 - 1 + ly, a.ny, a.per[1]);
-      const int gz = lb_coord(z0 - hz + lz, a.nz, a.per[2]);
-      sphi[l] = ((gx | gy | gz) < 0) ? INVALID : a.phi[(gz * a.ny + gy) * a.nx + gx];
-    }
+  for (int e0 = blockIdx.x * KT; e0 < count; e0 += gridDim.x * KT) {
+    const int nk = min(KT, count - e0);
+    if ((int)threadIdx.x < nk) tiles[threadIdx.x] = a.cand_list[e0 + threadIdx.x];
     __syncthreads();
-    bool spec[ITER], flip[ITER];
-    int cell[ITER];
-    bool act_any = false;
+    unsigned sbits = 0u, fbits = 0u;  // bit k * ITER + it: spec / flipped cell
+    for (int k = 0; k < nk; ++k) {
+      int x0, y0, z0;
+      tile_origin<S::D>(a, __builtin_amdgcn_readfirstlane(tiles[k]), x0, y0, z0);
+      // every load of the tile (halo rows along the lanes, previous tags)
+      // is issued before the first is used; a row is a uniform base pointer
+      // plus the lane's x
+      const int gx = lane < LX ? lb_coord(x0 - 1 + lane, a.nx, a.per[0]) : -1;
+      // lane j finds the start of the wavefront's row j (-1 beyond a wall)
+      int roff = -1;
+      {
+        const int r = wave + NW * lane;
+        const int gy = lb_coord(y0 - 1 + r % LY, a.ny, a.per[1]);
+        const int gz = lb_coord(z0 - hz + r / LY, a.nz, a.per[2]);
+        if (lane < RPW && r < NR && (gy | gz) >= 0) roff = (gz * a.ny + gy) * a.nx;
+      }
+      R hv[RPW];
 #pragma unroll
-    for (int it = 0; it < ITER; ++it) {
-      const int l = threadIdx.x + it * 256;
-      const int ix = l & (TS::X - 1), iy = (l >> TS::SX) & (TS::Y - 1), iz = l >> (TS::SX + TS::SY);
-      const int x = x0 + ix, y = y0 + iy, z = z0 + iz;
-      const int c = (z * a.ny + y) * a.nx + x;
-      cell[it] = c;
-      spec[it] = false;
-      flip[it] = false;
-      if (x < a.nx && y < a.ny && z < a.nz) {
-        const int lc = ((iz + hz) * LY + iy + 1) * LX + ix + 1;
-        const R pc = sphi[lc];
-        const int ph = pc >= (R)0 ? 1 : 0;
-        bool act = false;
-        for (int dz = -hz; dz <= hz; ++dz)
-          for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-              const R v = sphi[lc + (dz * LY + dy) * LX + dx];
-              act = act || (v < B && v > -B);
-            }
-        bool sp = false;
+      for (int j = 0; j < RPW; ++j) {
+        const int off = __builtin_amdgcn_readlane(roff, j);
+        hv[j] = INVALID;
+        if (off >= 0 && gx >= 0) hv[j] = (a.phi + (size_t)(unsigned)off)[(unsigned)gx];
+      }
+      // the tile's cells: a uniform corner plus a per-lane offset
+      uint8_t* const tag0 = a.tag + (size_t)(z0 * a.ny + y0) * a.nx + x0;
+      uint8_t tprev[ITER];
 #pragma unroll
-        for (int i = 0; i < S::Q; ++i) {
-          if (c2<LAT>(i) == 0) continue;
-          const R v = sphi[lc - (L::cz(i) * LY + L::cy(i)) * LX - L::cx(i)];
-          if (v != INVALID && ((v >= (R)0 ? 1 : 0) != ph)) sp = true;
+      for (int it = 0; it < ITER; ++it) {
+        const int l = threadIdx.x + it * 256;
+        const int ix = l & (TS::X - 1), iy = (l >> TS::SX) & (TS::Y - 1), iz = l >> (TS::SX + TS::SY);
+        tprev[it] = 0;
+        if (record_flips && x0 + ix < a.nx && y0 + iy < a.ny && z0 + iz < a.nz)
+          tprev[it] = tag0[(unsigned)((iz * a.ny + iy) * a.nx + ix)];
+      }
+#pragma unroll
+      for (int j = 0; j < RPW; ++j) {
+        const int r = wave + NW * j;
+        const R v = hv[j];
+        const bool in = v != INVALID;
+        const u64 mi = __ballot((v < B && v > -B) ? 1 : 0);
+        const u64 mg = __ballot((in && v >= (R)0) ? 1 : 0);
+        const u64 ml = __ballot((in && v < (R)0) ? 1 : 0);
+        if (lane == 0 && r < NR) {
+          rowm[r][0] = mi;
+          rowm[r][1] = mg;
+          rowm[r][2] = ml;
         }
-        // a full classification (record_flips == 0) starts from no previous
-        // tag: the tag memory may be uninitialised (state reload); the wall
-        // bit is set afterwards by k_mark_walls
-        const uint8_t told = record_flips ? a.tag[c] : (uint8_t)ph;
-        const int old = told & T_GAS;
-        a.tag[c] = (uint8_t)(ph | (act ? T_ACT : 0) | (sp ? T_SPEC : 0) | (told & T_WALL) | (old ? T_OLDGAS : 0));
-        act_any = act_any || act;
-        spec[it] = sp;
-        flip[it] = record_flips && ph != old;
       }
-    }
-    // list appends: per-wavefront counts, then one atomic per tile reserves
-    // the tile's slots in the interface-cell and tile lists together
-    unsigned long long smask[ITER], fmask[ITER];
+      __syncthreads();
+      if (threadIdx.x < TR) {
+        const int iy = threadIdx.x % TS::Y, iz = threadIdx.x / TS::Y;
+        u64 m[5] = {0ull, 0ull, 0ull, 0ull, 0ull};
 #pragma unroll
-    for (int it = 0; it < ITER; ++it) {
-      smask[it] = __ballot(spec[it] ? 1 : 0);
-      fmask[it] = __ballot(flip[it] ? 1 : 0);
+        for (int dz = -hz; dz <= hz; ++dz)
+#pragma unroll
+          for (int dy = -1; dy <= 1; ++dy) {
+            const int r = (iz + hz + dz) * LY + iy + 1 + dy;
+            const int corner = (dy != 0 && dz != 0) ? 1 : 0;
+            m[0] |= rowm[r][0];
+            m[1 + corner] |= rowm[r][1];
+            m[3 + corner] |= rowm[r][2];
+          }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) summ[threadIdx.x][q] = m[q];
+      }
+      __syncthreads();
+      bool act_any = false;
+#pragma unroll
+      for (int it = 0; it < ITER; ++it) {
+        const int l = threadIdx.x + it * 256;
+        const int ix = l & (TS::X - 1), iy = (l >> TS::SX) & (TS::Y - 1), iz = l >> (TS::SX + TS::SY);
+        const int x = x0 + ix, y = y0 + iy, z = z0 + iz;
+        bool sp = false, fl = false;
+        if (x < a.nx && y < a.ny && z < a.nz) {
+          const int tr = iz * TS::Y + iy;
+          // bits ix .. ix + 2 of a row mask are the cells x - 1 .. x + 1
+          const int ph = (int)((rowm[(iz + hz) * LY + iy + 1][1] >> (ix + 1)) & 1ull);
+          const bool act = ((summ[tr][0] >> ix) & 7ull) != 0ull;
+          const u64 oe = summ[tr][ph ? 3 : 1], oc = summ[tr][ph ? 4 : 2];
+          if (LAT == LSB_D3Q19) sp = (((oe >> ix) & 7ull) | ((oc >> ix) & 2ull)) != 0ull;
+          else sp = (((oe | oc) >> ix) & 7ull) != 0ull;
+          // a full classification (record_flips == 0) starts from no previous
+          // tag: the tag memory may be uninitialised (state reload); the wall
+          // bit is set afterwards by k_mark_walls
+          const uint8_t told = record_flips ? tprev[it] : (uint8_t)ph;
+          const int old = told & T_GAS;
+          tag0[(unsigned)((iz * a.ny + iy) * a.nx + ix)] = (uint8_t)(ph | (act ? T_ACT : 0) | (sp ? T_SPEC : 0) | (told & T_WALL) | (old ? T_OLDGAS : 0));
+          act_any = act_any || act;
+          fl = record_flips && ph != old;
+        }
+        if (sp) sbits |= 1u << (k * ITER + it);
+        if (fl) fbits |= 1u << (k * ITER + it);
+        const u64 sm = __ballot(sp ? 1 : 0), fm = __ballot(fl ? 1 : 0);
+        if (lane == 0) {
+          wcnt[0][k][it][wave] = __popcll(sm);
+          wcnt[1][k][it][wave] = __popcll(fm);
+        }
+      }
+      const u64 am = __ballot(act_any ? 1 : 0);
+      if (lane == 0) wact[k][wave] = am != 0ull;
+      __syncthreads();  // the next tile restages rowm and summ
+    }
+    // one reservation per list for the batch, made by wavefront 0: lane
+    // (k * ITER + it) * NW + w holds the counts of tile k, pass it and
+    // wavefront w, and an inclusive scan over the lanes gives each entry its
+    // first slot.  counters[CNT_SPEC] (low word) and counters[CNT_TILES]
+    // (high word) share one 64-bit atomic.
+    if (wave == 0) {
+      const bool ent = lane < NE && lane / (ITER * NW) < nk;
+      const int vs = ent ? (&wcnt[0][0][0][0])[lane] : 0;
+      const int vf = ent ? (&wcnt[1][0][0][0])[lane] : 0;
+      int is = vs, ifl = vf;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int ts = __shfl_up(is, d), tf = __shfl_up(ifl, d);
+        if (lane >= d) {
+          is += ts;
+          ifl += tf;
+        }
+      }
+      const int ns = __shfl(is, 63), nf = __shfl(ifl, 63);
+      // tiles with an active cell, in batch order
+      int na = 0;
+      if (lane < nk)
+        for (int w = 0; w < NW; ++w) na |= wact[lane][w];
+      const unsigned long long am = __ballot(na ? 1 : 0);
+      const int nt = __popcll(am);
+      unsigned long long old = 0ull;
+      int fb = 0;
       if (lane == 0) {
-        wcnt[0][it][wave] = __popcll(smask[it]);
-        wcnt[1][it][wave] = __popcll(fmask[it]);
+        if (nt || ns)
+          old = atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[CNT_SPEC]),
+                          ((unsigned long long)nt << 32) | (unsigned long long)ns);
+        if (nf) fb = atomicAdd(&a.counters[CNT_FLIP], nf);
+      }
+      old = __shfl(old, 0);
+      fb = __shfl(fb, 0);
+      if (lane < nk) {
+        a.tile_act_next[tiles[lane]] = na ? 1 : 0;
+        if (na) a.tile_list[(int)(old >> 32) + __popcll(am & ((1ull << lane) - 1ull))] = tiles[lane];
+      }
+      if (lane < NE) {
+        (&pre[0][0][0][0])[lane] = (int)(old & 0xffffffffull) + is - vs;
+        (&pre[1][0][0][0])[lane] = fb + ifl - vf;
       }
     }
-    const unsigned long long amask = __ballot(act_any ? 1 : 0);
-    if (lane == 0) wact[wave] = amask != 0ull;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int ns = 0, nf = 0, na = 0;
-      for (int it = 0; it < ITER; ++it)
-        for (int w = 0; w < NW; ++w) { ns += wcnt[0][it][w]; nf += wcnt[1][it][w]; }
-      for (int w = 0; w < NW; ++w) na |= wact[w];
-      a.tile_act_next[t] = na ? 1 : 0;
-      int sb = 0;
-      if (na || ns) {
-        // counters[CNT_SPEC] (low word) and counters[CNT_TILES] (high word)
-        const unsigned long long inc = ((unsigned long long)(na ? 1 : 0) << 32) | (unsigned long long)ns;
-        const unsigned long long old =
-            atomicAdd(reinterpret_cast<unsigned long long*>(&a.counters[CNT_SPEC]), inc);
-        sb = (int)(old & 0xffffffffull);
-        if (na) a.tile_list[(int)(old >> 32)] = t;
-      }
-      base[0] = sb;
-      base[1] = nf ? atomicAdd(&a.counters[CNT_FLIP], nf) : 0;
-    }
-    __syncthreads();
-    int off[2] = {base[0], base[1]};
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int k = 0; k < nk; ++k) {
+      int x0, y0, z0;
+      tile_origin<S::D>(a, __builtin_amdgcn_readfirstlane(tiles[k]), x0, y0, z0);
 #pragma unroll
-    for (int it = 0; it < ITER; ++it) {
-      int ps = off[0], pf = off[1];
-      for (int w = 0; w < wave; ++w) { ps += wcnt[0][it][w]; pf += wcnt[1][it][w]; }
-      const unsigned long long below = (1ull << lane) - 1ull;
-      if (spec[it]) a.spec_list[ps + __popcll(smask[it] & below)] = cell[it];
-      if (flip[it]) a.flip_list[pf + __popcll(fmask[it] & below)] = cell[it];
-      for (int w = 0; w < NW; ++w) { off[0] += wcnt[0][it][w]; off[1] += wcnt[1][it][w]; }
+      for (int it = 0; it < ITER; ++it) {
+        const bool sp = (sbits >> (k * ITER + it)) & 1u, fl = (fbits >> (k * ITER + it)) & 1u;
+        const unsigned long long sm = __ballot(sp ? 1 : 0), fm = __ballot(fl ? 1 : 0);
+        if (sp || fl) {
+          const int l = threadIdx.x + it * 256;
+          const int x = x0 + (l & (TS::X - 1)), y = y0 + ((l >> TS::SX) & (TS::Y - 1)), z = z0 + (l >> (TS::SX + TS::SY));
+          const int c = (z * a.ny + y) * a.nx + x;
+          if (sp) a.spec_list[pre[0][k][it][wave] + __popcll(sm & below)] = c;
+          if (fl) a.flip_list[pre[1][k][it][wave] + __popcll(fm & below)] = c;
+        }
+      }
     }
-    __syncthreads();
+    __syncthreads();  // wcnt, wact, tiles and pre are reused by the next batch
   }
 }
 
