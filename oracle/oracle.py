@@ -1,4 +1,4 @@
-"""ctypes binding of the CPU oracle (lsb_oracle.cpp).
+"""ctypes binding of the CPU oracle (lsb_oracle.cpp, refine_oracle.cpp).
 
 TEST INFRASTRUCTURE ONLY.  The parameter block below mirrors orc::Params of
 the oracle's own source; it is not shared with the HIP library.
@@ -13,12 +13,13 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lsb_oracle.cpp")
+SRCS = [SRC, os.path.join(HERE, "refine_oracle.cpp")]
 LIB_PATH = os.path.join(HERE, "liblsb_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
     """Compile the oracle with the host compiler (plain C++17, OpenMP)."""
-    cmd = ["g++", "-std=c++17", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", LIB_PATH, SRC]
+    cmd = ["g++", "-std=c++17", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", LIB_PATH] + SRCS
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
@@ -70,7 +71,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
+    if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < max(os.path.getmtime(f) for f in SRCS):
         build()
     lib = C.CDLL(LIB_PATH)
     P = C.POINTER(_Params)
@@ -112,6 +113,12 @@ def _load():
     lib.orc_tan_step.argtypes = [C.c_void_p, C.c_int]
     lib.orc_tan_centroid.argtypes = [C.c_void_p, C.c_int, dp, dp]
     lib.orc_tan_get_pop.argtypes = [C.c_void_p, dp, dp]
+    lib.orc_ref_create.restype = C.c_void_p
+    lib.orc_ref_create.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.c_double, C.c_double]
+    lib.orc_ref_destroy.argtypes = [C.c_void_p]
+    lib.orc_ref_init.argtypes = [C.c_void_p, dp, dp, dp, dp]
+    lib.orc_ref_step.argtypes = [C.c_void_p, C.c_int]
+    lib.orc_ref_get.argtypes = [C.c_void_p, dp, dp]
     _lib = lib
     return lib
 
@@ -359,3 +366,63 @@ class TangentOracle:
         v, t = C.c_double(), C.c_double()
         self.lib.orc_tan_centroid(self.h, int(axis), C.byref(v), C.byref(t))
         return v.value, t.value
+
+
+class RefineOracle:
+    """Two-level static refinement of the D2Q9 BGK solver (ratio 2), FP64.
+
+    Coarse nodes nx x ny, periodic; the fine patch covers the coarse nodes
+    patch = (ia, ib, ja, jb) (inclusive) at half spacing, fine node (i, j) at
+    (ia + i/2, ja + j/2).  Populations are [9][nodes] (x fastest), the
+    paper's D2Q9 ordering.  tau_f = None takes 2 tau_c - 1/2 (constant
+    viscosity); the tests pass another value only to plant a mistake.
+    """
+
+    def __init__(self, nx: int, ny: int, patch, tau_c: float, tau_f=None):
+        lib = _load()
+        self.nx, self.ny = int(nx), int(ny)
+        self.patch = tuple(int(v) for v in patch)
+        ia, ib, ja, jb = self.patch
+        self.mx, self.my = 2 * (ib - ia), 2 * (jb - ja)
+        self.tau_c = float(tau_c)
+        self.tau_f = 2.0 * tau_c - 0.5 if tau_f is None else float(tau_f)
+        pa = (C.c_int * 4)(*self.patch)
+        self._h = lib.orc_ref_create(self.nx, self.ny, pa, self.tau_c, self.tau_f)
+        if not self._h:
+            raise ValueError("invalid refinement configuration")
+        self._lib = lib
+
+    @property
+    def n_coarse(self) -> int:
+        return self.nx * self.ny
+
+    @property
+    def n_fine(self) -> int:
+        return (self.mx + 1) * (self.my + 1)
+
+    def fine_coords(self):
+        """Coarse-unit coordinates (x, y) of the fine nodes, [n_fine] each."""
+        ia, _, ja, _ = self.patch
+        j, i = np.meshgrid(np.arange(self.my + 1), np.arange(self.mx + 1), indexing="ij")
+        return (ia + 0.5 * i).reshape(-1), (ja + 0.5 * j).reshape(-1)
+
+    def init(self, rho_c, u_c, rho_f, u_f):
+        self._keep = [_f64(rho_c, self.n_coarse), _f64(u_c, 2 * self.n_coarse), _f64(rho_f, self.n_fine),
+                      _f64(u_f, 2 * self.n_fine)]
+        self._lib.orc_ref_init(self._h, *[_dp(a) for a in self._keep])
+        return self
+
+    def step(self, n: int = 1):
+        self._lib.orc_ref_step(self._h, int(n))
+        return self
+
+    def populations(self):
+        fc = np.zeros(9 * self.n_coarse)
+        ff = np.zeros(9 * self.n_fine)
+        self._lib.orc_ref_get(self._h, _dp(fc), _dp(ff))
+        return fc.reshape(9, self.ny, self.nx), ff.reshape(9, self.my + 1, self.mx + 1)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            self._lib.orc_ref_destroy(self._h)
+            self._h = None

@@ -1,0 +1,118 @@
+"""Pins of the two-level refinement oracle (D2Q9, BGK, ratio 2) to facts the
+mathematics fixes, independent of the oracle's own formulas.
+
+The paper couples grid levels after Dupuis and Chopard: populations missing
+at a refinement jump come from the other level by spatial and temporal
+interpolation, and the collision frequency of eq. (omega) is taken with each
+level's time step so that the viscosity is the same on both (Sec. 2, lattice
+Boltzmann method).  Pins:
+
+- a uniform state (any density and velocity) is a fixed point of the whole
+  coupled step: catches interpolation weights that do not sum to one, a
+  wrong time level, a wrong equilibrium at the jump;
+- a decaying shear wave across the patch (axis-aligned and diagonal) decays
+  at nu k^2 with nu = (tau_c - 1/2)/3, the single viscosity of eq. (omega);
+  the same oracle with tau_f = tau_c (a planted mistake) misses it by > 8 %;
+- at the jump, the post-collision shear stress of the fine perimeter nodes
+  (where populations are injected) and of the restricted coarse nodes equals
+  the Chapman-Enskog value -(tau - 1) / 3 rho du/dy per level (fine
+  gradients per fine spacing): catches a wrong rescaling of the
+  non-equilibrium part in either direction.
+"""
+import numpy as np
+import pytest
+
+from oracle import RefineOracle
+
+CX = np.array([-1, 1, 0, 0, -1, -1, 1, 1, 0])
+CY = np.array([0, 0, -1, 1, -1, 1, 1, -1, 0])
+W = np.array([1 / 9] * 4 + [1 / 36] * 4 + [4 / 9])
+
+
+def _feq(rho, ux, uy):
+    cu = CX[:, None] * ux + CY[:, None] * uy
+    return W[:, None] * rho * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy))
+
+
+def _moments(f):
+    f = f.reshape(9, -1)
+    rho = f.sum(0)
+    return rho, (CX[:, None] * f).sum(0) / rho, (CY[:, None] * f).sum(0) / rho
+
+
+def _wave(n, patch, tau_c, profile, tau_f=None):
+    """Velocity u = profile(x, y) (2-vector per node) on both levels, rho = 1."""
+    r = RefineOracle(n, n, patch, tau_c, tau_f)
+    J, I = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    uc = np.stack(profile(I.reshape(-1).astype(float), J.reshape(-1).astype(float)), 1)
+    xf, yf = r.fine_coords()
+    uf = np.stack(profile(xf, yf), 1)
+    return r.init(np.ones(n * n), uc, np.ones(len(xf)), uf)
+
+
+def test_uniform_state_is_a_fixed_point():
+    r = RefineOracle(32, 30, (8, 20, 6, 22), 0.7)
+    u = np.array([0.03, -0.02])
+    r.init(np.full(32 * 30, 1.01), np.tile(u, 32 * 30), np.full(r.n_fine, 1.01), np.tile(u, r.n_fine))
+    fc0, ff0 = r.populations()
+    r.step(40)
+    fc, ff = r.populations()
+    assert np.max(np.abs(fc - fc0)) < 1e-14
+    assert np.max(np.abs(ff - ff0)) < 1e-14
+
+
+def _decay_rate(r, n, steps, proj):
+    amps = []
+    J, I = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    for _ in range(steps):
+        r.step(1)
+        fc, _ = r.populations()
+        rho, ux, _ = _moments(fc)
+        amps.append(float((ux * proj(I, J).reshape(-1)).sum() / (proj(I, J) ** 2).sum()))
+    t = np.arange(1, steps + 1)
+    return -np.polyfit(t[steps // 4:], np.log(amps[steps // 4:]), 1)[0]
+
+
+@pytest.mark.parametrize("kind", ["axis", "diagonal"])
+def test_shear_wave_decays_at_one_viscosity(kind):
+    n, tau_c, U, steps = 64, 0.8, 1e-3, 300
+    k = 2 * np.pi / n
+    if kind == "axis":
+        profile = lambda x, y: (U * np.sin(k * y), 0 * y)  # noqa: E731
+        proj = lambda I, J: np.sin(k * J)  # noqa: E731
+        patch, kk = (16, 48, 16, 48), k * k
+    else:
+        profile = lambda x, y: (U * np.sin(k * (x + y)), -U * np.sin(k * (x + y)))  # noqa: E731
+        proj = lambda I, J: np.sin(k * (I + J))  # noqa: E731
+        patch, kk = (13, 45, 19, 47), 2 * k * k
+    nu = (tau_c - 0.5) / 3.0
+    rate = _decay_rate(_wave(n, patch, tau_c, profile), n, steps, proj)
+    assert abs(rate / (nu * kk) - 1) < 0.015, rate / (nu * kk) - 1
+    # planted mistake: the fine level relaxed with the coarse tau
+    bad = _decay_rate(_wave(n, patch, tau_c, profile, tau_f=tau_c), n, steps, proj)
+    assert abs(bad / (nu * kk) - 1) > 0.08
+
+
+def test_stress_at_the_jump_matches_chapman_enskog():
+    n, tau_c, U = 64, 0.8, 1e-3
+    k = 2 * np.pi / n
+    r = _wave(n, (16, 48, 16, 48), tau_c, lambda x, y: (U * np.cos(k * y), 0 * y))
+    r.step(200)
+    fc, ff = r.populations()
+    # fine level: du/dy per fine spacing is half the coarse-unit gradient
+    xf, yf = r.fine_coords()
+    rho, ux, uy = _moments(ff)
+    pxy = (CX[:, None] * CY[:, None] * (ff.reshape(9, -1) - _feq(rho, ux, uy))).sum(0)
+    A = (ux * np.cos(k * yf)).sum() / (np.cos(k * yf) ** 2).sum()
+    expect = (r.tau_f - 1.0) / 3.0 * rho * 0.5 * A * k * np.sin(k * yf)
+    per = (np.isclose(yf, 16) | np.isclose(yf, 48)) & (np.abs(np.sin(k * yf)) > 0.5)
+    assert per.sum() > 10
+    assert np.max(np.abs(pxy[per] - expect[per])) < 0.02 * np.max(np.abs(expect[per]))
+    # coarse level: the restricted nodes just inside the perimeter
+    J, I = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    rho, ux, uy = _moments(fc)
+    pc = (CX[:, None] * CY[:, None] * (fc.reshape(9, -1) - _feq(rho, ux, uy))).sum(0)
+    yc = J.reshape(-1).astype(float)
+    expect_c = (tau_c - 1.0) / 3.0 * rho * A * k * np.sin(k * yc)
+    ring = (((J == 17) | (J == 47)) & (I > 17) & (I < 47)).reshape(-1)
+    assert np.max(np.abs(pc[ring] - expect_c[ring])) < 0.02 * np.max(np.abs(expect_c[ring]))
