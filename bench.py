@@ -147,6 +147,47 @@ def run_adjoint(steps: int, every: int):
     return res
 
 
+def run_refine(steps: int, warmup: int):
+    """Two-level static refinement (D2Q9, BGK, FP64, ratio 2): 2048^2 coarse
+    nodes, periodic, with a fine patch over the coarse nodes [512, 1536]^2
+    (2049^2 fine nodes, two fine steps per coarse step); synthetic smooth
+    shear and density fields.  Node updates per second and the whole step's
+    rate against 144 algorithmic bytes per node update (9 FP64 populations
+    read and written)."""
+    import numpy as np
+    import torch
+
+    from paper_2601_05936_amd.lsb import Refine
+    n, patch, tau_c = 2048, (512, 1536, 512, 1536), 0.6
+    g = Refine(n, n, patch, tau_c)
+    J, I = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    def fields(x, y):
+        s = np.sin(2 * np.pi * y / n)
+        return 1.0 + 0.005 * np.cos(2 * np.pi * x / n), np.stack([0.02 * s, 0.01 * np.sin(2 * np.pi * x / n)], 1)
+    rc, uc = fields(I.reshape(-1).astype(float), J.reshape(-1).astype(float))
+    ia, ib, ja, jb = patch
+    jf, i_f = np.meshgrid(np.arange(g.my + 1), np.arange(g.mx + 1), indexing="ij")
+    rf, uf = fields(ia + 0.5 * i_f.reshape(-1), ja + 0.5 * jf.reshape(-1))
+    g.init(rc, uc, rf, uf)
+    g.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    covered = (ib - ia - 1) * (jb - ja - 1)
+    updates = (n * n - covered) + 2 * g.n_fine
+    gbs = updates * 144 / (ms * 1e-3) / 1e9
+    res = dict(workload="D2Q9 two-level static refinement, 2048^2 coarse, patch [512,1536]^2 (2049^2 fine)",
+               steps=steps, warmup=warmup, ms_per_step=ms, node_updates_per_step=updates,
+               mlups=updates / (ms * 1e-3) / 1e6, gbs=gbs, frac=gbs / HBM_PEAK_GBS, bytes_per_update=144,
+               dtype="f64")
+    log(f"[refine] {res}")
+    return res
+
+
 def cpu_baseline(seconds: float):
     """The CPU oracle (as it stands) on a bounded sample of the workload:
     the same problem at 128^3 (interface amplitude scaled to 2)."""
@@ -190,6 +231,8 @@ def main():
                          "overlap otherwise)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="reverse-mode run length (0: skip)")
+    ap.add_argument("--refine-steps", type=int, default=100,
+                    help="two-level refinement run length in coarse steps (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (counter calibration)")
@@ -261,6 +304,8 @@ def main():
     }
     if args.adjoint_steps > 0:
         out["adjoint"] = run_adjoint(args.adjoint_steps, 100)
+    if args.refine_steps > 0:
+        out["refine"] = run_refine(args.refine_steps, 10)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

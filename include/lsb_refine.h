@@ -1,0 +1,91 @@
+/* Two-level static grid refinement of the lattice Boltzmann solver (C ABI).
+ *
+ * The paper refines its lattice Boltzmann grid after Dupuis and Chopard:
+ * distributions missing at a refinement jump are obtained by spatial and
+ * temporal interpolation between the known neighbouring distributions, and
+ * the collision frequency of eq. (omega) is taken with each level's time
+ * step so that the viscosity is the same on all levels (Sec. 2, lattice
+ * Boltzmann method).  This module runs that coupling for one static fine
+ * patch, refinement ratio 2, D2Q9, BGK collision (eq. (feq) equilibrium),
+ * FP64, in a coarse grid periodic on both axes.  The fine level sub-cycles:
+ * two fine steps per coarse step, with tau_f = 2 tau_c - 1/2.
+ *
+ * Geometry (cell-vertex): coarse node (I, J), I in [0, nx), J in [0, ny);
+ * the patch covers the coarse nodes [ia, ib] x [ja, jb] (inclusive) at half
+ * spacing, fine node (i, j) at coarse coordinates (ia + i/2, ja + j/2),
+ * i in [0, 2 (ib - ia)], j in [0, 2 (jb - ja)].  Coarse nodes strictly
+ * inside the box are covered (their populations are restricted from the
+ * coincident fine nodes); those on its boundary are perimeter nodes.
+ *
+ * One coarse step: every uncovered coarse node pulls and collides with
+ * tau_c, the perimeter nodes keeping their pre-collision populations; then
+ * two fine steps, where a fine perimeter node takes each population whose
+ * source lies outside the patch from the coarse perimeter: linear in time
+ * (the mean of the two coarse time levels, then the new one), the mean of
+ * the two coarse nodes beside an odd fine node along the edge, and the
+ * non-equilibrium part about the equilibrium of the interpolated moments
+ * scaled by tau_f / (2 tau_c); the second fine step writes each covered
+ * coarse node f_eq + 2 (tau_c - 1) / tau_f (f - f_eq) from the coincident
+ * fine node's pre-collision populations f.
+ *
+ * Conventions as in lsb.h: every function returns LSB_OK (0) or a negative
+ * code of lsb.h (message from lsb_last_error); calls that take a stream
+ * enqueue work on it and return without waiting; the library allocates no
+ * device memory (the caller binds a workspace).
+ */
+#ifndef LSB_REFINE_H
+#define LSB_REFINE_H
+
+#include <stddef.h>
+
+#include "lsb.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lsb_ref_params {
+  int nx, ny;       /* coarse nodes; 4 <= nx, 4 <= ny <= 65535 */
+  int patch[4];     /* ia, ib, ja, jb: coarse node box of the fine patch, inclusive;
+                       1 <= ia, ib <= nx - 2, ib - ia >= 2 (same for j), 2 (jb - ja) < 65535 */
+  double tau_c;     /* coarse relaxation time, > 1/2 */
+} lsb_ref_params;
+
+typedef struct lsb_ref lsb_ref;
+
+/* Validates the parameters and creates a handle (host memory only).
+ * LSB_EINVAL for a NULL pointer or parameters outside the ranges above. */
+int lsb_ref_create(const lsb_ref_params* params, lsb_ref** out);
+void lsb_ref_destroy(lsb_ref* ref);
+
+/* Device workspace the caller provides: both levels' populations twice
+ * (double buffers) and the coarse perimeter's pre-collision sets at two time
+ * levels.  The library keeps the pointer; the caller keeps ownership and
+ * must keep it alive while the handle is used.  LSB_ENOMEM if it is too
+ * small. */
+int lsb_ref_workspace_bytes(const lsb_ref* ref, size_t* bytes);
+int lsb_ref_bind(lsb_ref* ref, void* device_workspace, size_t bytes);
+
+/* Equilibrium initial state from device arrays: rho_c [nx*ny], u_c
+ * [nx*ny*2] (x, y per node, x fastest over the nodes), rho_f and u_f the
+ * same over the fine nodes ((2(ib-ia)+1) * (2(jb-ja)+1), i fastest).  The
+ * coarse perimeter's pre-collision sets start at those equilibria.
+ * LSB_ESTATE before lsb_ref_bind. */
+int lsb_ref_init(lsb_ref* ref, const double* rho_c, const double* u_c, const double* rho_f, const double* u_f,
+                 void* stream);
+
+/* nsteps coarse steps (2 nsteps fine steps).  LSB_ESTATE before
+ * lsb_ref_init. */
+int lsb_ref_step(lsb_ref* ref, int nsteps, void* stream);
+
+/* Post-collision populations of both levels into device arrays, [9][nodes]
+ * in the paper's D2Q9 ordering (rest direction last): coarse [9][ny][nx]
+ * (covered nodes hold the restricted values), fine [9][2(jb-ja)+1][2(ib-ia)+1].
+ * Either pointer may be NULL.  LSB_ESTATE before lsb_ref_init. */
+int lsb_ref_get_populations(lsb_ref* ref, double* coarse, double* fine, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSB_REFINE_H */

@@ -1,7 +1,7 @@
 """Thin Python binding of liblsb.so (argument marshalling only).
 
 Every step of the method runs in the HIP kernels behind the C ABI of
-include/lsb.h; this module only converts parameters, hands over torch device
+include/lsb.h and include/lsb_refine.h; this module only converts parameters, hands over torch device
 memory (the caller-owned workspace) and stream handles, and wraps results.
 It fails loudly when the built library is missing: there is no fallback.
 """
@@ -51,7 +51,14 @@ EXPORTS = [
     "lsb_get_kernel_timing", "lsb_set_schedule", "lsb_adjoint_workspace_bytes", "lsb_adjoint_bind",
     "lsb_adjoint_record", "lsb_adjoint_seed_centroid", "lsb_adjoint_reverse", "lsb_adjoint_initial",
     "lsb_last_error",
+    "lsb_ref_create", "lsb_ref_destroy", "lsb_ref_workspace_bytes", "lsb_ref_bind", "lsb_ref_init", "lsb_ref_step",
+    "lsb_ref_get_populations",
 ]
+
+
+class RefParams(C.Structure):
+    """Mirror of lsb_ref_params (include/lsb_refine.h)."""
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("patch", C.c_int * 4), ("tau_c", C.c_double)]
 SCHED_SERIAL, SCHED_OVERLAP = 0, 1
 MAX_BUBBLES = 64  # LSB_MAX_BUBBLES
 
@@ -98,6 +105,15 @@ def load() -> C.CDLL:
     lib.lsb_adjoint_reverse.argtypes = [vp, vp]
     lib.lsb_adjoint_initial.argtypes = [vp, vp, vp, C.c_int, vp, dp, vp]
     lib.lsb_last_error.restype = C.c_char_p
+    R = C.POINTER(RefParams)
+    lib.lsb_ref_create.argtypes = [R, C.POINTER(vp)]
+    lib.lsb_ref_destroy.argtypes = [vp]
+    lib.lsb_ref_destroy.restype = None
+    lib.lsb_ref_workspace_bytes.argtypes = [vp, sz]
+    lib.lsb_ref_bind.argtypes = [vp, vp, C.c_size_t]
+    lib.lsb_ref_init.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.lsb_ref_step.argtypes = [vp, C.c_int, vp]
+    lib.lsb_ref_get_populations.argtypes = [vp, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -305,3 +321,64 @@ class Sim:
 
     def load_state(self, buf):
         _check(self.lib.lsb_load_state(self.h, C.c_void_p(buf.data_ptr()), self.stream()))
+
+
+class Refine:
+    """Two-level static refinement (D2Q9, BGK, FP64, ratio 2) on one GPU:
+    the coarse grid nx x ny (periodic) and a fine patch over the coarse
+    nodes patch = (ia, ib, ja, jb).  Device memory is a torch uint8 tensor
+    (the caller-owned workspace); calls run on torch's current stream."""
+
+    def __init__(self, nx: int, ny: int, patch, tau_c: float, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.device = torch.device(device)
+        self.nx, self.ny = int(nx), int(ny)
+        self.patch = tuple(int(v) for v in patch)
+        ia, ib, ja, jb = self.patch
+        self.mx, self.my = 2 * (ib - ia), 2 * (jb - ja)
+        self.n_coarse, self.n_fine = self.nx * self.ny, (self.mx + 1) * (self.my + 1)
+        self._cp = RefParams(self.nx, self.ny, (C.c_int * 4)(*self.patch), float(tau_c))
+        h = C.c_void_p()
+        _check(self.lib.lsb_ref_create(C.byref(self._cp), C.byref(h)))
+        self.h = h
+        nb = C.c_size_t()
+        _check(self.lib.lsb_ref_workspace_bytes(self.h, C.byref(nb)))
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        _check(self.lib.lsb_ref_bind(self.h, C.c_void_p(self.ws.data_ptr()), nb.value))
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.lsb_ref_destroy(self.h)
+            self.h = None
+
+    def stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _dev(self, a, n):
+        t = self.torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)) if isinstance(a, np.ndarray) \
+            else a.reshape(-1).to(self.torch.float64)
+        assert t.numel() == n, (t.numel(), n)
+        return t.to(self.device).contiguous()
+
+    def init(self, rho_c, u_c, rho_f, u_f):
+        """rho [nodes], u [nodes, 2] per level (numpy or torch)."""
+        t = [self._dev(rho_c, self.n_coarse), self._dev(u_c, 2 * self.n_coarse), self._dev(rho_f, self.n_fine),
+             self._dev(u_f, 2 * self.n_fine)]
+        _check(self.lib.lsb_ref_init(self.h, *[C.c_void_p(x.data_ptr()) for x in t], self.stream()))
+        self.torch.cuda.current_stream(self.device).synchronize()
+        return self
+
+    def step(self, n: int = 1):
+        _check(self.lib.lsb_ref_step(self.h, int(n), self.stream()))
+        return self
+
+    def populations(self, as_numpy=True):
+        t = self.torch
+        fc = t.empty(9 * self.n_coarse, dtype=t.float64, device=self.device)
+        ff = t.empty(9 * self.n_fine, dtype=t.float64, device=self.device)
+        _check(self.lib.lsb_ref_get_populations(self.h, C.c_void_p(fc.data_ptr()), C.c_void_p(ff.data_ptr()),
+                                                self.stream()))
+        fc, ff = fc.reshape(9, self.ny, self.nx), ff.reshape(9, self.my + 1, self.mx + 1)
+        return (fc.cpu().numpy(), ff.cpu().numpy()) if as_numpy else (fc, ff)

@@ -1,4 +1,4 @@
-"""The C-ABI library loads and exports every entry point include/lsb.h
+"""The C-ABI library loads and exports every entry point include/*.h
 declares; parameter validation and the workspace layout need no GPU."""
 import ctypes as C
 import os
@@ -13,7 +13,8 @@ HEADER = os.path.join(ROOT, "include", "lsb.h")
 
 
 def declared_symbols():
-    text = open(HEADER).read()
+    inc = os.path.join(ROOT, "include")
+    text = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     return sorted(set(re.findall(r"\b(lsb_[a-z_0-9]+)\s*\(", text)))
 
 
