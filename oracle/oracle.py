@@ -114,7 +114,7 @@ def _load():
     lib.orc_tan_centroid.argtypes = [C.c_void_p, C.c_int, dp, dp]
     lib.orc_tan_get_pop.argtypes = [C.c_void_p, dp, dp]
     lib.orc_ref_create.restype = C.c_void_p
-    lib.orc_ref_create.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.c_double, C.c_double]
+    lib.orc_ref_create.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_double, C.c_double]
     lib.orc_ref_destroy.argtypes = [C.c_void_p]
     lib.orc_ref_init.argtypes = [C.c_void_p, dp, dp, dp, dp]
     lib.orc_ref_step.argtypes = [C.c_void_p, C.c_int]
@@ -369,46 +369,56 @@ class TangentOracle:
 
 
 class RefineOracle:
-    """Two-level static refinement of the D2Q9 BGK solver (ratio 2), FP64.
+    """Two-level static refinement of the BGK solver (ratio 2), FP64.
 
-    Coarse nodes nx x ny, periodic; the fine patch covers the coarse nodes
-    patch = (ia, ib, ja, jb) (inclusive) at half spacing, fine node (i, j) at
-    (ia + i/2, ja + j/2).  Populations are [9][nodes] (x fastest), the
-    paper's D2Q9 ordering.  tau_f = None takes 2 tau_c - 1/2 (constant
-    viscosity); the tests pass another value only to plant a mistake.
+    lattice 0 (D2Q9), 1 (D3Q19) or 2 (D3Q27).  Coarse nodes nx x ny (x nz),
+    periodic; the fine patch covers the coarse nodes patch = (ia, ib, ja, jb)
+    (+ (ka, kb) in 3D), inclusive, at half spacing, fine node (i, j, k) at
+    (ia + i/2, ja + j/2, ka + k/2).  Populations are [Q][nodes] (x fastest),
+    the paper's ordering; velocities [nodes][D].  tau_f = None takes
+    2 tau_c - 1/2 (constant viscosity); the tests pass another value only to
+    plant a mistake.
     """
 
-    def __init__(self, nx: int, ny: int, patch, tau_c: float, tau_f=None):
+    def __init__(self, nx: int, ny: int, patch, tau_c: float, tau_f=None, lattice: int = 0, nz: int = 1):
         lib = _load()
-        self.nx, self.ny = int(nx), int(ny)
-        self.patch = tuple(int(v) for v in patch)
-        ia, ib, ja, jb = self.patch
-        self.mx, self.my = 2 * (ib - ia), 2 * (jb - ja)
+        self.lattice = int(lattice)
+        self.D, self.Q = (2, 9) if self.lattice == 0 else (3, 19 if self.lattice == 1 else 27)
+        self.nx, self.ny, self.nz = int(nx), int(ny), (int(nz) if self.D == 3 else 1)
+        p = tuple(int(v) for v in patch)
+        self.patch = p if self.D == 3 else p[:4]
+        ia, ib, ja, jb = p[:4]
+        ka, kb = (p[4], p[5]) if self.D == 3 else (0, 0)
+        self.mx, self.my, self.mz = 2 * (ib - ia), 2 * (jb - ja), 2 * (kb - ka)
         self.tau_c = float(tau_c)
         self.tau_f = 2.0 * tau_c - 0.5 if tau_f is None else float(tau_f)
-        pa = (C.c_int * 4)(*self.patch)
-        self._h = lib.orc_ref_create(self.nx, self.ny, pa, self.tau_c, self.tau_f)
+        n3 = (C.c_int * 3)(self.nx, self.ny, self.nz)
+        p6 = (C.c_int * 6)(ia, ib, ja, jb, ka, kb)
+        self._h = lib.orc_ref_create(self.lattice, n3, p6, self.tau_c, self.tau_f)
         if not self._h:
             raise ValueError("invalid refinement configuration")
         self._lib = lib
 
     @property
     def n_coarse(self) -> int:
-        return self.nx * self.ny
+        return self.nx * self.ny * self.nz
 
     @property
     def n_fine(self) -> int:
-        return (self.mx + 1) * (self.my + 1)
+        return (self.mx + 1) * (self.my + 1) * (self.mz + 1)
 
     def fine_coords(self):
-        """Coarse-unit coordinates (x, y) of the fine nodes, [n_fine] each."""
-        ia, _, ja, _ = self.patch
-        j, i = np.meshgrid(np.arange(self.my + 1), np.arange(self.mx + 1), indexing="ij")
-        return (ia + 0.5 * i).reshape(-1), (ja + 0.5 * j).reshape(-1)
+        """Coarse-unit coordinates of the fine nodes, [n_fine] each: (x, y) in
+        2D, (x, y, z) in 3D."""
+        ia, ja = self.patch[0], self.patch[2]
+        ka = self.patch[4] if self.D == 3 else 0
+        k, j, i = np.meshgrid(np.arange(self.mz + 1), np.arange(self.my + 1), np.arange(self.mx + 1), indexing="ij")
+        xyz = (ia + 0.5 * i.reshape(-1), ja + 0.5 * j.reshape(-1), ka + 0.5 * k.reshape(-1))
+        return xyz[:self.D]
 
     def init(self, rho_c, u_c, rho_f, u_f):
-        self._keep = [_f64(rho_c, self.n_coarse), _f64(u_c, 2 * self.n_coarse), _f64(rho_f, self.n_fine),
-                      _f64(u_f, 2 * self.n_fine)]
+        self._keep = [_f64(rho_c, self.n_coarse), _f64(u_c, self.D * self.n_coarse), _f64(rho_f, self.n_fine),
+                      _f64(u_f, self.D * self.n_fine)]
         self._lib.orc_ref_init(self._h, *[_dp(a) for a in self._keep])
         return self
 
@@ -417,10 +427,13 @@ class RefineOracle:
         return self
 
     def populations(self):
-        fc = np.zeros(9 * self.n_coarse)
-        ff = np.zeros(9 * self.n_fine)
+        fc = np.zeros(self.Q * self.n_coarse)
+        ff = np.zeros(self.Q * self.n_fine)
         self._lib.orc_ref_get(self._h, _dp(fc), _dp(ff))
-        return fc.reshape(9, self.ny, self.nx), ff.reshape(9, self.my + 1, self.mx + 1)
+        if self.D == 2:
+            return fc.reshape(self.Q, self.ny, self.nx), ff.reshape(self.Q, self.my + 1, self.mx + 1)
+        return (fc.reshape(self.Q, self.nz, self.ny, self.nx),
+                ff.reshape(self.Q, self.mz + 1, self.my + 1, self.mx + 1))
 
     def __del__(self):
         if getattr(self, "_h", None):

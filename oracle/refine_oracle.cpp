@@ -1,5 +1,5 @@
 // CPU oracle: two-level static grid refinement of the lattice Boltzmann
-// solver (D2Q9, BGK, FP64), ratio 2.  Test infrastructure only: the tests,
+// solver (D2Q9, D3Q19, D3Q27; BGK, FP64), ratio 2.  Test infrastructure only: the tests,
 // the smoke check and the benchmark's CPU-baseline leg call it; the product
 // path never does.
 //
@@ -13,19 +13,20 @@
 // below are the reading this build takes (node layout, interpolation order,
 // rescaling of the non-equilibrium part, order of the sub-steps):
 //
-//   nodes      coarse (I, J), periodic on both axes; the fine patch covers
-//              the coarse nodes [ia, ib] x [ja, jb] at half spacing, fine
-//              node (i, j) at (ia + i/2, ja + j/2), i in [0, 2(ib-ia)],
-//              j in [0, 2(jb-ja)]; coarse nodes strictly inside the box are
-//              covered, those on its boundary are perimeter nodes.
+//   nodes      coarse (I, J, K), periodic on every axis; the fine patch
+//              covers the coarse nodes [ia, ib] x [ja, jb] (x [ka, kb]) at
+//              half spacing, fine node (i, j, k) at (ia + i/2, ja + j/2,
+//              ka + k/2); coarse nodes strictly inside the box are covered,
+//              those on its boundary are perimeter nodes.
 //   coarse     every uncovered coarse node pulls, keeps its pre-collision
 //   step       populations G(t+1) if it is a perimeter node, and collides
 //              with tau_c.
 //   fine       two sub-steps (t + 1/2, t + 1); a fine perimeter node takes
 //   sub-steps  each population whose source lies outside the patch from G:
-//              in time (G(t) + G(t+1))/2, then G(t+1); along an edge the
-//              mean of the two coarse perimeter nodes beside an odd fine
-//              node; the non-equilibrium part about the equilibrium of the
+//              in time (G(t) + G(t+1))/2, then G(t+1); in space, along
+//              each odd fine coordinate the mean of the two coarse nodes
+//              beside it (2 or, at a face centre, 4 coarse nodes); the
+//              non-equilibrium part about the equilibrium of the
 //              interpolated moments scaled by the ratio of tau dt between
 //              the levels, tau_f / (2 tau_c).  Collision with tau_f.
 //   restrict   in the second sub-step, a fine node on a covered coarse node
@@ -36,142 +37,154 @@
 #include <cmath>
 #include <vector>
 
+// the oracle's velocity sets in the paper's ordering (lsb_oracle.cpp)
+extern "C" int orc_lattice(int lattice, int* D, int* Q, int* c, double* w, int* opp);
+
 namespace ref {
 
-constexpr int Q = 9;
-// D2Q9 in the paper's ordering, rest direction last
-constexpr int CX[Q] = {-1, 1, 0, 0, -1, -1, 1, 1, 0};
-constexpr int CY[Q] = {0, 0, -1, 1, -1, 1, 1, -1, 0};
-constexpr double W[Q] = {1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 4.0 / 9};
-
-// eq. (feq) with c_s^2 = 1/3
-void feq(double rho, double ux, double uy, double* out) {
-  const double uu = ux * ux + uy * uy;
-  for (int q = 0; q < Q; ++q) {
-    const double cu = CX[q] * ux + CY[q] * uy;
-    out[q] = W[q] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-  }
-}
-
-void moments(const double* f, double& rho, double& ux, double& uy) {
-  rho = 0.0;
-  double mx = 0.0, my = 0.0;
-  for (int q = 0; q < Q; ++q) {
-    rho += f[q];
-    mx += CX[q] * f[q];
-    my += CY[q] * f[q];
-  }
-  ux = mx / rho;
-  uy = my / rho;
-}
+constexpr int QMAX = 27;
 
 struct Ref {
-  int nx, ny, ia, ib, ja, jb, mx, my;
+  int D = 2, Q = 9;
+  int cx[QMAX], cy[QMAX], cz[QMAX];
+  double w[QMAX];
+  int nx, ny, nz, ia, ib, ja, jb, ka, kb, mx, my, mz;
   double tc, tf;
-  std::vector<double> fc, ff;  // post-collision populations [q][node]
+  std::vector<double> fc, ff;  // post-collision populations [q][node], x fastest
   std::vector<double> g0, g1;  // coarse pre-collision populations over the patch box, times t and t+1
 
-  long nc() const { return (long)nx * ny; }
-  long nf() const { return (long)(mx + 1) * (my + 1); }
-  long nb() const { return (long)(ib - ia + 1) * (jb - ja + 1); }
-  long box(int I, int J) const { return (long)(J - ja) * (ib - ia + 1) + (I - ia); }
-  bool covered(int I, int J) const { return I > ia && I < ib && J > ja && J < jb; }
-  bool perimeter(int I, int J) const {
-    return I >= ia && I <= ib && J >= ja && J <= jb && (I == ia || I == ib || J == ja || J == jb);
+  long nc() const { return (long)nx * ny * nz; }
+  long nf() const { return (long)(mx + 1) * (my + 1) * (mz + 1); }
+  long nb() const { return (long)(ib - ia + 1) * (jb - ja + 1) * (kb - ka + 1); }
+  long cidx(int I, int J, int K) const { return ((long)K * ny + J) * nx + I; }
+  long fidx(int i, int j, int k) const { return ((long)k * (my + 1) + j) * (mx + 1) + i; }
+  long box(int I, int J, int K) const { return ((long)(K - ka) * (jb - ja + 1) + (J - ja)) * (ib - ia + 1) + (I - ia); }
+  bool in_box(int I, int J, int K) const {
+    return I >= ia && I <= ib && J >= ja && J <= jb && (D == 2 || (K >= ka && K <= kb));
+  }
+  bool covered(int I, int J, int K) const {
+    return I > ia && I < ib && J > ja && J < jb && (D == 2 || (K > ka && K < kb));
+  }
+  bool perimeter(int I, int J, int K) const { return in_box(I, J, K) && !covered(I, J, K); }
+
+  // eq. (feq) with c_s^2 = 1/3
+  void feq(double rho, double ux, double uy, double uz, double* out) const {
+    const double uu = ux * ux + uy * uy + uz * uz;
+    for (int q = 0; q < Q; ++q) {
+      const double cu = cx[q] * ux + cy[q] * uy + cz[q] * uz;
+      out[q] = w[q] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    }
+  }
+  void moments(const double* f, double& rho, double& ux, double& uy, double& uz) const {
+    rho = 0.0;
+    double mxs = 0.0, mys = 0.0, mzs = 0.0;
+    for (int q = 0; q < Q; ++q) {
+      rho += f[q];
+      mxs += cx[q] * f[q];
+      mys += cy[q] * f[q];
+      mzs += cz[q] * f[q];
+    }
+    ux = mxs / rho;
+    uy = mys / rho;
+    uz = mzs / rho;
   }
 
+  // u holds D components per node
   void init(const double* rc, const double* uc, const double* rf, const double* uf) {
     fc.assign(Q * nc(), 0.0);
     ff.assign(Q * nf(), 0.0);
     g0.assign(Q * nb(), 0.0);
     g1.assign(Q * nb(), 0.0);
-    double e[Q];
-    for (int J = 0; J < ny; ++J)
-      for (int I = 0; I < nx; ++I) {
-        const long n = (long)J * nx + I;
-        feq(rc[n], uc[2 * n], uc[2 * n + 1], e);
-        for (int q = 0; q < Q; ++q) fc[q * nc() + n] = e[q];
-        if (perimeter(I, J))
-          for (int q = 0; q < Q; ++q) g0[q * nb() + box(I, J)] = e[q];
-      }
+    double e[QMAX];
+    for (int K = 0; K < nz; ++K)
+      for (int J = 0; J < ny; ++J)
+        for (int I = 0; I < nx; ++I) {
+          const long n = cidx(I, J, K);
+          feq(rc[n], uc[D * n], uc[D * n + 1], D == 3 ? uc[D * n + 2] : 0.0, e);
+          for (int q = 0; q < Q; ++q) fc[q * nc() + n] = e[q];
+          if (perimeter(I, J, K))
+            for (int q = 0; q < Q; ++q) g0[q * nb() + box(I, J, K)] = e[q];
+        }
     for (long n = 0; n < nf(); ++n) {
-      feq(rf[n], uf[2 * n], uf[2 * n + 1], e);
+      feq(rf[n], uf[D * n], uf[D * n + 1], D == 3 ? uf[D * n + 2] : 0.0, e);
       for (int q = 0; q < Q; ++q) ff[q * nf() + n] = e[q];
     }
   }
 
-  // interpolated coarse pre-collision set at fine perimeter node (i, j):
-  // weights a (time t) and b (time t + 1)
-  void coarse_set(int i, int j, double a, double b, double* H) const {
-    auto node = [&](int I, int J, double s) {
-      for (int q = 0; q < Q; ++q) H[q] += s * (a * g0[q * nb() + box(I, J)] + b * g1[q * nb() + box(I, J)]);
-    };
+  // interpolated coarse pre-collision set at fine perimeter node (i, j, k):
+  // time weights a (t) and b (t + 1); along each odd coordinate the mean of
+  // the two coarse nodes beside it (z outermost, x innermost)
+  void coarse_set(int i, int j, int k, double a, double b, double* H) const {
     for (int q = 0; q < Q; ++q) H[q] = 0.0;
-    if (i % 2 == 0 && j % 2 == 0) {
-      node(ia + i / 2, ja + j / 2, 1.0);
-    } else if (i % 2 != 0) {  // on a horizontal edge
-      node(ia + (i - 1) / 2, ja + j / 2, 0.5);
-      node(ia + (i + 1) / 2, ja + j / 2, 0.5);
-    } else {  // on a vertical edge
-      node(ia + i / 2, ja + (j - 1) / 2, 0.5);
-      node(ia + i / 2, ja + (j + 1) / 2, 0.5);
-    }
+    const int ox = i & 1, oy = j & 1, oz = k & 1;
+    const double s = (ox ? 0.5 : 1.0) * (oy ? 0.5 : 1.0) * (oz ? 0.5 : 1.0);
+    for (int dz = 0; dz <= oz; ++dz)
+      for (int dy = 0; dy <= oy; ++dy)
+        for (int dx = 0; dx <= ox; ++dx) {
+          const int I = ia + (i - ox) / 2 + dx, J = ja + (j - oy) / 2 + dy, K = ka + (k - oz) / 2 + dz;
+          const long bx = box(I, J, K);
+          for (int q = 0; q < Q; ++q) H[q] += s * (a * g0[q * nb() + bx] + b * g1[q * nb() + bx]);
+        }
   }
+
+  bool outside(int si, int sj, int sk) const { return si < 0 || si > mx || sj < 0 || sj > my || sk < 0 || sk > mz; }
 
   void step() {
     // coarse step t -> t+1 on the uncovered nodes
     std::vector<double> nfc = fc;
-    double f[Q], e[Q];
-    for (int J = 0; J < ny; ++J)
-      for (int I = 0; I < nx; ++I) {
-        if (covered(I, J)) continue;
-        const long n = (long)J * nx + I;
-        for (int q = 0; q < Q; ++q) {
-          const int sI = ((I - CX[q]) % nx + nx) % nx, sJ = ((J - CY[q]) % ny + ny) % ny;
-          f[q] = fc[q * nc() + (long)sJ * nx + sI];
+    double f[QMAX], e[QMAX];
+    for (int K = 0; K < nz; ++K)
+      for (int J = 0; J < ny; ++J)
+        for (int I = 0; I < nx; ++I) {
+          if (covered(I, J, K)) continue;
+          const long n = cidx(I, J, K);
+          for (int q = 0; q < Q; ++q) {
+            const int sI = ((I - cx[q]) % nx + nx) % nx, sJ = ((J - cy[q]) % ny + ny) % ny;
+            const int sK = ((K - cz[q]) % nz + nz) % nz;
+            f[q] = fc[q * nc() + cidx(sI, sJ, sK)];
+          }
+          if (perimeter(I, J, K))
+            for (int q = 0; q < Q; ++q) g1[q * nb() + box(I, J, K)] = f[q];
+          double rho, ux, uy, uz;
+          moments(f, rho, ux, uy, uz);
+          feq(rho, ux, uy, uz, e);
+          for (int q = 0; q < Q; ++q) nfc[q * nc() + n] = f[q] - (f[q] - e[q]) / tc;
         }
-        if (perimeter(I, J))
-          for (int q = 0; q < Q; ++q) g1[q * nb() + box(I, J)] = f[q];
-        double rho, ux, uy;
-        moments(f, rho, ux, uy);
-        feq(rho, ux, uy, e);
-        for (int q = 0; q < Q; ++q) nfc[q * nc() + n] = f[q] - (f[q] - e[q]) / tc;
-      }
     // two fine sub-steps
     for (int s = 1; s <= 2; ++s) {
       const double a = s == 1 ? 0.5 : 0.0, b = s == 1 ? 0.5 : 1.0;
       std::vector<double> nff(ff.size());
-      for (int j = 0; j <= my; ++j)
-        for (int i = 0; i <= mx; ++i) {
-          const long n = (long)j * (mx + 1) + i;
-          bool missing = false;
-          for (int q = 0; q < Q; ++q) {
-            const int si = i - CX[q], sj = j - CY[q];
-            if (si < 0 || si > mx || sj < 0 || sj > my) {
-              missing = true;
-              continue;
-            }
-            f[q] = ff[q * nf() + (long)sj * (mx + 1) + si];
-          }
-          if (missing) {
-            double H[Q], eh[Q], rh, uxh, uyh;
-            coarse_set(i, j, a, b, H);
-            moments(H, rh, uxh, uyh);
-            feq(rh, uxh, uyh, eh);
+      for (int k = 0; k <= mz; ++k)
+        for (int j = 0; j <= my; ++j)
+          for (int i = 0; i <= mx; ++i) {
+            const long n = fidx(i, j, k);
+            bool missing = false;
             for (int q = 0; q < Q; ++q) {
-              const int si = i - CX[q], sj = j - CY[q];
-              if (si < 0 || si > mx || sj < 0 || sj > my) f[q] = eh[q] + tf / (2.0 * tc) * (H[q] - eh[q]);
+              const int si = i - cx[q], sj = j - cy[q], sk = k - cz[q];
+              if (outside(si, sj, sk)) {
+                missing = true;
+                continue;
+              }
+              f[q] = ff[q * nf() + fidx(si, sj, sk)];
+            }
+            if (missing) {
+              double H[QMAX], eh[QMAX], rh, uxh, uyh, uzh;
+              coarse_set(i, j, k, a, b, H);
+              moments(H, rh, uxh, uyh, uzh);
+              feq(rh, uxh, uyh, uzh, eh);
+              for (int q = 0; q < Q; ++q)
+                if (outside(i - cx[q], j - cy[q], k - cz[q])) f[q] = eh[q] + tf / (2.0 * tc) * (H[q] - eh[q]);
+            }
+            double rho, ux, uy, uz;
+            moments(f, rho, ux, uy, uz);
+            feq(rho, ux, uy, uz, e);
+            for (int q = 0; q < Q; ++q) nff[q * nf() + n] = f[q] - (f[q] - e[q]) / tf;
+            if (s == 2 && i % 2 == 0 && j % 2 == 0 && k % 2 == 0 &&
+                covered(ia + i / 2, ja + j / 2, ka + k / 2)) {
+              const long m = cidx(ia + i / 2, ja + j / 2, ka + k / 2);
+              for (int q = 0; q < Q; ++q) nfc[q * nc() + m] = e[q] + 2.0 * (tc - 1.0) / tf * (f[q] - e[q]);
             }
           }
-          double rho, ux, uy;
-          moments(f, rho, ux, uy);
-          feq(rho, ux, uy, e);
-          for (int q = 0; q < Q; ++q) nff[q * nf() + n] = f[q] - (f[q] - e[q]) / tf;
-          if (s == 2 && i % 2 == 0 && j % 2 == 0 && covered(ia + i / 2, ja + j / 2)) {
-            const long m = (long)(ja + j / 2) * nx + ia + i / 2;
-            for (int q = 0; q < Q; ++q) nfc[q * nc() + m] = e[q] + 2.0 * (tc - 1.0) / tf * (f[q] - e[q]);
-          }
-        }
       ff.swap(nff);
     }
     fc.swap(nfc);
@@ -183,21 +196,42 @@ struct Ref {
 
 extern "C" {
 
+// lattice: 0 D2Q9, 1 D3Q19, 2 D3Q27 (the oracle's numbering); n = (nx, ny,
+// nz) with nz = 1 in 2D; patch = (ia, ib, ja, jb, ka, kb), ka = kb = 0 in 2D.
 // tau_f <= 0 selects the constant-viscosity value 2 tau_c - 1/2; the tests
 // pass another value only to check that a pin catches a wrong one.
-void* orc_ref_create(int nx, int ny, const int* patch, double tau_c, double tau_f) {
-  if (nx < 4 || ny < 4 || !patch) return nullptr;
-  const int ia = patch[0], ib = patch[1], ja = patch[2], jb = patch[3];
-  if (ia < 1 || ib > nx - 2 || ib - ia < 2 || ja < 1 || jb > ny - 2 || jb - ja < 2 || !(tau_c > 0.5)) return nullptr;
+void* orc_ref_create(int lattice, const int* n, const int* patch, double tau_c, double tau_f) {
+  if (!n || !patch) return nullptr;
   ref::Ref* r = new ref::Ref();
-  r->nx = nx;
-  r->ny = ny;
-  r->ia = ia;
-  r->ib = ib;
-  r->ja = ja;
-  r->jb = jb;
-  r->mx = 2 * (ib - ia);
-  r->my = 2 * (jb - ja);
+  int c[3 * ref::QMAX], opp[ref::QMAX];
+  if (orc_lattice(lattice, &r->D, &r->Q, c, r->w, opp) != 0) {
+    delete r;
+    return nullptr;
+  }
+  for (int q = 0; q < r->Q; ++q) {
+    r->cx[q] = c[3 * q];
+    r->cy[q] = c[3 * q + 1];
+    r->cz[q] = c[3 * q + 2];
+  }
+  r->nx = n[0];
+  r->ny = n[1];
+  r->nz = r->D == 3 ? n[2] : 1;
+  r->ia = patch[0];
+  r->ib = patch[1];
+  r->ja = patch[2];
+  r->jb = patch[3];
+  r->ka = r->D == 3 ? patch[4] : 0;
+  r->kb = r->D == 3 ? patch[5] : 0;
+  const bool ok = r->nx >= 4 && r->ny >= 4 && (r->D == 2 || r->nz >= 4) && r->ia >= 1 && r->ib <= r->nx - 2 &&
+                  r->ib - r->ia >= 2 && r->ja >= 1 && r->jb <= r->ny - 2 && r->jb - r->ja >= 2 &&
+                  (r->D == 2 || (r->ka >= 1 && r->kb <= r->nz - 2 && r->kb - r->ka >= 2)) && tau_c > 0.5;
+  if (!ok) {
+    delete r;
+    return nullptr;
+  }
+  r->mx = 2 * (r->ib - r->ia);
+  r->my = 2 * (r->jb - r->ja);
+  r->mz = 2 * (r->kb - r->ka);
   r->tc = tau_c;
   r->tf = tau_f > 0.0 ? tau_f : 2.0 * tau_c - 0.5;
   return r;
