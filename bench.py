@@ -188,6 +188,46 @@ def run_refine(steps: int, warmup: int):
     return res
 
 
+def run_refine3d(steps: int, warmup: int):
+    """The same two-level refinement in 3D: D3Q27, 192^3 coarse nodes with a
+    fine patch over [48, 144]^3 (193^3 fine nodes); synthetic smooth
+    fields.  Node updates per second and the whole step's rate against
+    27 x 16 = 432 algorithmic bytes per node update."""
+    import numpy as np
+    import torch
+
+    from paper_2601_05936_amd.lsb import D3Q27, Refine
+    n, patch, tau_c = 192, (48, 144, 48, 144, 48, 144), 0.6
+    g = Refine(n, n, patch, tau_c, lattice=D3Q27, nz=n)
+
+    def fields(x, y, z):
+        return (1.0 + 0.005 * np.cos(2 * np.pi * x / n),
+                np.stack([0.02 * np.sin(2 * np.pi * y / n), 0.01 * np.sin(2 * np.pi * z / n),
+                          0.01 * np.sin(2 * np.pi * x / n)], 1))
+    K, J, I = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    rc, uc = fields(I.reshape(-1).astype(float), J.reshape(-1).astype(float), K.reshape(-1).astype(float))
+    k, j, i = np.meshgrid(np.arange(g.mz + 1), np.arange(g.my + 1), np.arange(g.mx + 1), indexing="ij")
+    rf, uf = fields(48 + 0.5 * i.reshape(-1), 48 + 0.5 * j.reshape(-1), 48 + 0.5 * k.reshape(-1))
+    g.init(rc, uc, rf, uf)
+    del K, J, I, k, j, i, rc, uc, rf, uf
+    g.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    updates = (n ** 3 - 95 ** 3) + 2 * g.n_fine
+    gbs = updates * 432 / (ms * 1e-3) / 1e9
+    res = dict(workload="D3Q27 two-level static refinement, 192^3 coarse, patch [48,144]^3 (193^3 fine)",
+               steps=steps, warmup=warmup, ms_per_step=ms, node_updates_per_step=updates,
+               mlups=updates / (ms * 1e-3) / 1e6, gbs=gbs, frac=gbs / HBM_PEAK_GBS, bytes_per_update=432,
+               dtype="f64")
+    log(f"[refine3d] {res}")
+    return res
+
+
 def cpu_baseline(seconds: float):
     """The CPU oracle (as it stands) on a bounded sample of the workload:
     the same problem at 128^3 (interface amplitude scaled to 2)."""
@@ -232,7 +272,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="reverse-mode run length (0: skip)")
     ap.add_argument("--refine-steps", type=int, default=100,
-                    help="two-level refinement run length in coarse steps (0: skip)")
+                    help="two-level refinement run length in coarse steps, 2D and 3D legs (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (counter calibration)")
@@ -306,6 +346,7 @@ def main():
         out["adjoint"] = run_adjoint(args.adjoint_steps, 100)
     if args.refine_steps > 0:
         out["refine"] = run_refine(args.refine_steps, 10)
+        out["refine3d"] = run_refine3d(args.refine_steps, 10)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -6,25 +6,28 @@
  * the collision frequency of eq. (omega) is taken with each level's time
  * step so that the viscosity is the same on all levels (Sec. 2, lattice
  * Boltzmann method).  This module runs that coupling for one static fine
- * patch, refinement ratio 2, D2Q9, BGK collision (eq. (feq) equilibrium),
- * FP64, in a coarse grid periodic on both axes.  The fine level sub-cycles:
- * two fine steps per coarse step, with tau_f = 2 tau_c - 1/2.
+ * patch, refinement ratio 2, D2Q9, D3Q19 or D3Q27, BGK collision (eq. (feq)
+ * equilibrium), FP64, in a coarse grid periodic on every axis.  The fine
+ * level sub-cycles: two fine steps per coarse step, with
+ * tau_f = 2 tau_c - 1/2.
  *
- * Geometry (cell-vertex): coarse node (I, J), I in [0, nx), J in [0, ny);
- * the patch covers the coarse nodes [ia, ib] x [ja, jb] (inclusive) at half
- * spacing, fine node (i, j) at coarse coordinates (ia + i/2, ja + j/2),
- * i in [0, 2 (ib - ia)], j in [0, 2 (jb - ja)].  Coarse nodes strictly
- * inside the box are covered (their populations are restricted from the
- * coincident fine nodes); those on its boundary are perimeter nodes.
+ * Geometry (cell-vertex): coarse node (I, J, K), I in [0, nx), J in
+ * [0, ny), K in [0, nz); the patch covers the coarse nodes [ia, ib] x
+ * [ja, jb] (x [ka, kb]) at half spacing, fine node (i, j, k) at coarse
+ * coordinates (ia + i/2, ja + j/2, ka + k/2), i in [0, 2 (ib - ia)], and
+ * so on.  Coarse nodes strictly inside the box are covered (their
+ * populations are restricted from the coincident fine nodes); those on its
+ * boundary are perimeter nodes.
  *
  * One coarse step: every uncovered coarse node pulls and collides with
  * tau_c, the perimeter nodes keeping their pre-collision populations; then
  * two fine steps, where a fine perimeter node takes each population whose
  * source lies outside the patch from the coarse perimeter: linear in time
- * (the mean of the two coarse time levels, then the new one), the mean of
- * the two coarse nodes beside an odd fine node along the edge, and the
- * non-equilibrium part about the equilibrium of the interpolated moments
- * scaled by tau_f / (2 tau_c); the second fine step writes each covered
+ * (the mean of the two coarse time levels, then the new one), along each
+ * odd fine coordinate the mean of the two coarse nodes beside it (2, or 4
+ * at a face centre), and the non-equilibrium part about the equilibrium of
+ * the interpolated moments scaled by tau_f / (2 tau_c); the second fine
+ * step writes each covered
  * coarse node f_eq + 2 (tau_c - 1) / tau_f (f - f_eq) from the coincident
  * fine node's pre-collision populations f.
  *
@@ -45,16 +48,19 @@ extern "C" {
 #endif
 
 typedef struct lsb_ref_params {
-  int nx, ny;       /* coarse nodes; 4 <= nx, 4 <= ny <= 65535 */
-  int patch[4];     /* ia, ib, ja, jb: coarse node box of the fine patch, inclusive;
-                       1 <= ia, ib <= nx - 2, ib - ia >= 2 (same for j), 2 (jb - ja) < 65535 */
+  int lattice;      /* LSB_D2Q9, LSB_D3Q19 or LSB_D3Q27 */
+  int nx, ny, nz;   /* coarse nodes, >= 4 per axis; nz = 1 for D2Q9 */
+  int patch[6];     /* ia, ib, ja, jb, ka, kb: coarse node box of the fine patch, inclusive;
+                       1 <= ia, ib <= nx - 2, ib - ia >= 2, the same for j and (3D) k;
+                       ka, kb ignored for D2Q9 */
   double tau_c;     /* coarse relaxation time, > 1/2 */
 } lsb_ref_params;
 
 typedef struct lsb_ref lsb_ref;
 
 /* Validates the parameters and creates a handle (host memory only).
- * LSB_EINVAL for a NULL pointer or parameters outside the ranges above. */
+ * LSB_EINVAL for a NULL pointer, an unknown lattice, parameters outside
+ * the ranges above, or a level of more than 2^31 nodes. */
 int lsb_ref_create(const lsb_ref_params* params, lsb_ref** out);
 void lsb_ref_destroy(lsb_ref* ref);
 
@@ -66,10 +72,11 @@ void lsb_ref_destroy(lsb_ref* ref);
 int lsb_ref_workspace_bytes(const lsb_ref* ref, size_t* bytes);
 int lsb_ref_bind(lsb_ref* ref, void* device_workspace, size_t bytes);
 
-/* Equilibrium initial state from device arrays: rho_c [nx*ny], u_c
- * [nx*ny*2] (x, y per node, x fastest over the nodes), rho_f and u_f the
- * same over the fine nodes ((2(ib-ia)+1) * (2(jb-ja)+1), i fastest).  The
- * coarse perimeter's pre-collision sets start at those equilibria.
+/* Equilibrium initial state from device arrays: rho_c [nx*ny*nz], u_c
+ * [nx*ny*nz*D] (D components per node, x fastest over the nodes), rho_f and
+ * u_f the same over the fine nodes ((2(ib-ia)+1) (2(jb-ja)+1) (2(kb-ka)+1)
+ * in 3D, i fastest).  The coarse perimeter's pre-collision sets start at
+ * those equilibria.
  * LSB_ESTATE before lsb_ref_bind. */
 int lsb_ref_init(lsb_ref* ref, const double* rho_c, const double* u_c, const double* rho_f, const double* u_f,
                  void* stream);
@@ -78,9 +85,10 @@ int lsb_ref_init(lsb_ref* ref, const double* rho_c, const double* u_c, const dou
  * lsb_ref_init. */
 int lsb_ref_step(lsb_ref* ref, int nsteps, void* stream);
 
-/* Post-collision populations of both levels into device arrays, [9][nodes]
- * in the paper's D2Q9 ordering (rest direction last): coarse [9][ny][nx]
- * (covered nodes hold the restricted values), fine [9][2(jb-ja)+1][2(ib-ia)+1].
+/* Post-collision populations of both levels into device arrays, [Q][nodes]
+ * in the paper's direction ordering (rest direction last): coarse
+ * [Q][nz][ny][nx] (covered nodes hold the restricted values), fine
+ * [Q][2(kb-ka)+1][2(jb-ja)+1][2(ib-ia)+1] (one z layer in 2D).
  * Either pointer may be NULL.  LSB_ESTATE before lsb_ref_init. */
 int lsb_ref_get_populations(lsb_ref* ref, double* coarse, double* fine, void* stream);
 

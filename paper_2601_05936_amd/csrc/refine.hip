@@ -1,5 +1,6 @@
 // refine.hip -- two-level static grid refinement of the lattice Boltzmann
-// solver (D2Q9, BGK, FP64, ratio 2) behind the C ABI of lsb_refine.h.
+// solver (D2Q9, D3Q19, D3Q27; BGK, FP64, ratio 2) behind the C ABI of
+// lsb_refine.h.
 //
 // The coupling of the levels follows the approach the paper adopts for its
 // refinement jumps (Sec. 2, lattice Boltzmann method): populations missing
@@ -7,23 +8,25 @@
 // and the collision frequency eq. (omega) is taken per level for a single
 // viscosity (tau_f = 2 tau_c - 1/2).  lsb_refine.h states the steps.
 //
-// Per coarse step, bandwidth-bound FP64 streams (72 B read and 72 B written
+// Per coarse step, bandwidth-bound FP64 streams (Q x 8 B read and written
 // per node update) and one small perimeter launch:
 //   k_ref_coarse  pull + BGK on the uncovered coarse nodes; the perimeter
 //                 nodes also keep their pre-collision sets (G(t+1));
 //   k_ref_edge    per fine perimeter node, the populations whose source lies
 //                 outside the patch, from G, stored where the pull reads
-//                 them: a one-node ghost ring around the fine arrays;
+//                 them: a one-node ghost shell around the fine arrays; both
+//                 fine sub-steps' shells in one launch;
 //   k_ref_fine    pull + BGK on the fine nodes (no branch on the perimeter);
 //                 the second sub-step restricts onto the covered coarse
 //                 nodes.
-// One row segment of 256 nodes per block (x along the lanes), so every
+// One x-row segment of 256 nodes per block (x along the lanes), so every
 // population plane is read and written in contiguous 2 KB runs; blocks are
 // ordered so that each XCD streams a contiguous band of rows.
 #include <hip/hip_runtime.h>
 
 #include <string>
 
+#include "common.h"
 #include "../../include/lsb_refine.h"
 
 namespace lsb {
@@ -32,17 +35,15 @@ void set_error(const std::string& msg);
 
 namespace {
 
-constexpr int Q = 9;
-// D2Q9 in the paper's ordering, rest direction last
-__device__ constexpr int CX[Q] = {-1, 1, 0, 0, -1, -1, 1, 1, 0};
-__device__ constexpr int CY[Q] = {0, 0, -1, 1, -1, 1, 1, -1, 0};
-__device__ constexpr double WQ[Q] = {1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 4.0 / 9};
+using lsb::Lat;
+using lsb::wgt;
 
 struct RefArgs {
-  int nx, ny, ia, ib, ja, jb, mx, my;  // fine nodes (mx + 1) x (my + 1)
-  int bw;                              // patch box width ib - ia + 1
-  int fw;                              // fine row pitch with the ghost ring, mx + 3
-  long nc, nf, nb;                     // nodes: coarse, fine (with the ghost ring), patch box
+  int D;
+  int nx, ny, nz, ia, ib, ja, jb, ka, kb, mx, my, mz;  // fine nodes (mx + 1) x (my + 1) x (mz + 1)
+  int bw, bh;                                          // patch box extents in x, y
+  int fw, fh;                                          // fine pitches with the ghost shell: mx + 3, my + 3
+  long nc, nf, nb;                                     // nodes: coarse, fine (with the shell), patch box
   double tc, tf;
   const double* fc_in;
   double* fc_out;
@@ -54,165 +55,216 @@ struct RefArgs {
 
 // Blocks are dispatched round-robin over the 8 XCDs; logical block L of a
 // row-major (row, segment) order goes to one XCD's contiguous share, so the
-// rows a block pulls from (y - 1, y, y + 1) sit in the same L2.  A bijection
-// of [0, nb) for any nb.
+// rows a block pulls from sit in the same L2.  A bijection of [0, nb) for
+// any nb.
 __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
   const unsigned x = b & 7u, k = b >> 3, q = nb >> 3, r = nb & 7u;
   return x * q + (x < r ? x : r) + k;
 }
 
-__device__ __forceinline__ void moments(const double* f, double& rho, double& ux, double& uy) {
+template <int LAT>
+__device__ __forceinline__ void moments(const double* f, double& rho, double& ux, double& uy, double& uz) {
+  using L = Lat<LAT>;
   rho = 0.0;
-  double mx = 0.0, my = 0.0;
+  double mx = 0.0, my = 0.0, mz = 0.0;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
+  for (int q = 0; q < L::Q; ++q) {
     rho += f[q];
-    mx += CX[q] * f[q];
-    my += CY[q] * f[q];
+    mx += L::cx(q) * f[q];
+    my += L::cy(q) * f[q];
+    mz += L::cz(q) * f[q];
   }
   ux = mx / rho;
   uy = my / rho;
+  uz = mz / rho;
 }
 
 // eq. (feq), c_s^2 = 1/3
-__device__ __forceinline__ void equilibrium(double rho, double ux, double uy, double* e) {
-  const double uu = ux * ux + uy * uy;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const double cu = CX[q] * ux + CY[q] * uy;
-    e[q] = WQ[q] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-  }
+template <int LAT>
+__device__ __forceinline__ double equilibrium(int q, double rho, double ux, double uy, double uz) {
+  using L = Lat<LAT>;
+  const double uu = ux * ux + uy * uy + uz * uz;
+  const double cu = L::cx(q) * ux + L::cy(q) * uy + L::cz(q) * uz;
+  return wgt<LAT>(q) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
 }
 
+__device__ __forceinline__ long box_index(const RefArgs& a, int I, int J, int K) {
+  return ((long)(K - a.ka) * a.bh + (J - a.ja)) * a.bw + (I - a.ia);
+}
+
+__device__ __forceinline__ bool covered(const RefArgs& a, int I, int J, int K) {
+  return I > a.ia && I < a.ib && J > a.ja && J < a.jb && (a.D == 2 || (K > a.ka && K < a.kb));
+}
+
+__device__ __forceinline__ bool in_box(const RefArgs& a, int I, int J, int K) {
+  return I >= a.ia && I <= a.ib && J >= a.ja && J <= a.jb && (a.D == 2 || (K >= a.ka && K <= a.kb));
+}
+
+__device__ __forceinline__ long fine_index(const RefArgs& a, int i, int j, int k) {
+  return ((long)(k + (a.D == 3 ? 1 : 0)) * a.fh + (j + 1)) * a.fw + i + 1;
+}
+
+template <int LAT>
 __global__ __launch_bounds__(256) void k_ref_init(RefArgs a, const double* rho_c, const double* u_c,
                                                   const double* rho_f, const double* u_f, double* fc, double* ff,
                                                   double* g0) {
-  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
-  double e[Q];
-  if (blockIdx.z == 0) {
-    if (x >= a.nx || y >= a.ny) return;
-    const long n = (long)y * a.nx + x;
-    equilibrium(rho_c[n], u_c[2 * n], u_c[2 * n + 1], e);
+  constexpr int Q = Lat<LAT>::Q, D = Lat<LAT>::D;
+  const long nfc = (long)(a.mx + 1) * (a.my + 1) * (a.mz + 1);
+  for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < a.nc + nfc; t += (long)gridDim.x * 256) {
+    const bool coarse = t < a.nc;
+    const long n = coarse ? t : t - a.nc;
+    const double* r = coarse ? rho_c : rho_f;
+    const double* u = coarse ? u_c : u_f;
+    const double ux = u[D * n], uy = u[D * n + 1], uz = D == 3 ? u[D * n + 2] : 0.0;
+    if (coarse) {
+      const int I = (int)(n % a.nx), J = (int)((n / a.nx) % a.ny), K = (int)(n / ((long)a.nx * a.ny));
+      const bool per = in_box(a, I, J, K) && !covered(a, I, J, K);
+      const long b = per ? box_index(a, I, J, K) : 0;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) fc[q * a.nc + n] = e[q];
-    const bool inb = x >= a.ia && x <= a.ib && y >= a.ja && y <= a.jb;
-    if (inb && (x == a.ia || x == a.ib || y == a.ja || y == a.jb)) {
-      const long b = (long)(y - a.ja) * a.bw + (x - a.ia);
+      for (int q = 0; q < Q; ++q) {
+        const double e = equilibrium<LAT>(q, r[n], ux, uy, uz);
+        fc[q * a.nc + n] = e;
+        if (per) g0[q * a.nb + b] = e;
+      }
+    } else {
+      const int i = (int)(n % (a.mx + 1)), j = (int)((n / (a.mx + 1)) % (a.my + 1));
+      const int k = (int)(n / ((long)(a.mx + 1) * (a.my + 1)));
+      const long p = fine_index(a, i, j, k);
 #pragma unroll
-      for (int q = 0; q < Q; ++q) g0[q * a.nb + b] = e[q];
+      for (int q = 0; q < Q; ++q) ff[q * a.nf + p] = equilibrium<LAT>(q, r[n], ux, uy, uz);
     }
-  } else {
-    if (x > a.mx || y > a.my) return;
-    const long n = (long)y * (a.mx + 1) + x;
-    equilibrium(rho_f[n], u_f[2 * n], u_f[2 * n + 1], e);
-    const long p = (long)(y + 1) * a.fw + x + 1;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) ff[q * a.nf + p] = e[q];
   }
 }
 
 // uncovered coarse nodes: pull (periodic), keep the perimeter's pre-collision
 // set, collide with tau_c
+template <int LAT>
 __global__ __launch_bounds__(256) void k_ref_coarse(RefArgs a, int segs) {
-  const int L = (int)xcd_block(blockIdx.x, gridDim.x);
-  const int y = L / segs, x = (L - y * segs) * 256 + (int)threadIdx.x;
+  using L = Lat<LAT>;
+  constexpr int Q = L::Q;
+  const int Lb = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int row = Lb / segs, x = (Lb - row * segs) * 256 + (int)threadIdx.x;
   if (x >= a.nx) return;
-  const bool inb = x >= a.ia && x <= a.ib && y >= a.ja && y <= a.jb;
-  if (inb && x > a.ia && x < a.ib && y > a.ja && y < a.jb) return;  // covered: restricted from the fine level
-  const int xs[3] = {x + 1 == a.nx ? 0 : x + 1, x, x == 0 ? a.nx - 1 : x - 1};  // source x for c_x = -1, 0, 1
+  const int y = row % a.ny, z = row / a.ny;
+  const bool inb = in_box(a, x, y, z);
+  if (inb && covered(a, x, y, z)) return;  // restricted from the fine level
+  const int xs[3] = {x + 1 == a.nx ? 0 : x + 1, x, x == 0 ? a.nx - 1 : x - 1};  // source for c = -1, 0, 1
   const int ys[3] = {y + 1 == a.ny ? 0 : y + 1, y, y == 0 ? a.ny - 1 : y - 1};
+  const int zs[3] = {z + 1 == a.nz ? 0 : z + 1, z, z == 0 ? a.nz - 1 : z - 1};
   double f[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) f[q] = a.fc_in[q * a.nc + (long)ys[CY[q] + 1] * a.nx + xs[CX[q] + 1]];
+  for (int q = 0; q < Q; ++q)
+    f[q] = a.fc_in[q * a.nc + ((long)zs[L::cz(q) + 1] * a.ny + ys[L::cy(q) + 1]) * a.nx + xs[L::cx(q) + 1]];
   if (inb) {
-    const long b = (long)(y - a.ja) * a.bw + (x - a.ia);
+    const long b = box_index(a, x, y, z);
 #pragma unroll
     for (int q = 0; q < Q; ++q) a.g1[q * a.nb + b] = f[q];
   }
-  double rho, ux, uy, e[Q];
-  moments(f, rho, ux, uy);
-  equilibrium(rho, ux, uy, e);
-  const long n = (long)y * a.nx + x;
+  double rho, ux, uy, uz;
+  moments<LAT>(f, rho, ux, uy, uz);
+  const long n = ((long)z * a.ny + y) * a.nx + x;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) a.fc_out[q * a.nc + n] = f[q] - (f[q] - e[q]) / a.tc;
+  for (int q = 0; q < Q; ++q) a.fc_out[q * a.nc + n] = f[q] - (f[q] - equilibrium<LAT>(q, rho, ux, uy, uz)) / a.tc;
 }
 
 // fine perimeter nodes: the populations whose source lies outside the patch
-// (time weights wa on G(t), wb on G(t+1)), written into the ghost ring of the
-// fine buffer that sub-step reads, where k_ref_fine pulls them from; both
-// sub-steps in one launch (the ghost rings are disjoint from what the fine
-// steps write, and G(t), G(t+1) are known once the coarse step is done).
-// Thread t walks the perimeter: the rows j = 0 and j = my, then the columns
-// i = 0 and i = mx.
+// (time weights wa on G(t), wb on G(t+1)), written into the ghost shell of
+// the fine buffer that sub-step reads, where k_ref_fine pulls them from;
+// both sub-steps in one launch (blockIdx.y), since the shells are disjoint
+// from what the fine steps write and G(t), G(t+1) are known once the coarse
+// step is done.  Each surface node has one owner: the x faces take all their
+// nodes, the y faces those with 0 < i < mx, the z faces (3D) those with
+// 0 < i < mx and 0 < j < my.
+template <int LAT>
 __global__ __launch_bounds__(256) void k_ref_edge(RefArgs a, double* ff1, double* ff2) {
-  // blockIdx.y = 0: sub-step 1 (t + 1/2, into ff1); 1: sub-step 2 (t + 1, into ff2)
+  using L = Lat<LAT>;
+  constexpr int Q = L::Q;
   const double wa = blockIdx.y == 0 ? 0.5 : 0.0, wb = blockIdx.y == 0 ? 0.5 : 1.0;
   double* ff = blockIdx.y == 0 ? ff1 : ff2;
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  const int nr = a.mx + 1, ncol = a.my - 1;
-  if (t >= 2 * nr + 2 * ncol) return;
-  int i, j;
-  if (t < 2 * nr) {
-    i = t < nr ? t : t - nr;
-    j = t < nr ? 0 : a.my;
+  long t = (long)blockIdx.x * 256 + threadIdx.x;
+  const long ax = (long)(a.my + 1) * (a.mz + 1), ay = (long)(a.mx - 1) * (a.mz + 1);
+  const long az = a.D == 3 ? (long)(a.mx - 1) * (a.my - 1) : 0;
+  int i, j, k;
+  if (t < 2 * ax) {
+    const long u = t % ax;
+    i = t < ax ? 0 : a.mx;
+    j = (int)(u % (a.my + 1));
+    k = (int)(u / (a.my + 1));
+  } else if ((t -= 2 * ax) < 2 * ay) {
+    const long u = t % ay;
+    j = t < ay ? 0 : a.my;
+    i = 1 + (int)(u % (a.mx - 1));
+    k = (int)(u / (a.mx - 1));
+  } else if ((t -= 2 * ay) < 2 * az) {
+    const long u = t % az;
+    k = t < az ? 0 : a.mz;
+    i = 1 + (int)(u % (a.mx - 1));
+    j = 1 + (int)(u / (a.mx - 1));
   } else {
-    const int u = t - 2 * nr;
-    i = u < ncol ? 0 : a.mx;
-    j = 1 + (u < ncol ? u : u - ncol);
+    return;
   }
-  // the coarse set at this node: one coarse node, or the mean of the two
-  // beside an odd node along its edge
+  // the coarse set at this node: along each odd coordinate the mean of the
+  // two coarse nodes beside it (z outermost, x innermost)
+  const int ox = i & 1, oy = j & 1, oz = k & 1;
+  const double s = (ox ? 0.5 : 1.0) * (oy ? 0.5 : 1.0) * (oz ? 0.5 : 1.0);
   double H[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) H[q] = 0.0;
-  auto node = [&](int I, int J, double s) {
-    const long b = (long)(J - a.ja) * a.bw + (I - a.ia);
+  for (int dz = 0; dz <= oz; ++dz)
+    for (int dy = 0; dy <= oy; ++dy)
+      for (int dx = 0; dx <= ox; ++dx) {
+        const long b = box_index(a, a.ia + (i - ox) / 2 + dx, a.ja + (j - oy) / 2 + dy, a.ka + (k - oz) / 2 + dz);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) H[q] += s * (wa * a.g0[q * a.nb + b] + wb * a.g1[q * a.nb + b]);
-  };
-  if (!(i & 1) && !(j & 1)) {
-    node(a.ia + i / 2, a.ja + j / 2, 1.0);
-  } else if (i & 1) {
-    node(a.ia + (i - 1) / 2, a.ja + j / 2, 0.5);
-    node(a.ia + (i + 1) / 2, a.ja + j / 2, 0.5);
-  } else {
-    node(a.ia + i / 2, a.ja + (j - 1) / 2, 0.5);
-    node(a.ia + i / 2, a.ja + (j + 1) / 2, 0.5);
-  }
-  double rh, uxh, uyh, eh[Q];
-  moments(H, rh, uxh, uyh);
-  equilibrium(rh, uxh, uyh, eh);
+        for (int q = 0; q < Q; ++q) H[q] += s * (wa * a.g0[q * a.nb + b] + wb * a.g1[q * a.nb + b]);
+      }
+  double rh, uxh, uyh, uzh;
+  moments<LAT>(H, rh, uxh, uyh, uzh);
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int si = i - CX[q], sj = j - CY[q];
-    if (si < 0 || si > a.mx || sj < 0 || sj > a.my)
-      ff[q * a.nf + (long)(sj + 1) * a.fw + si + 1] = eh[q] + a.tf / (2.0 * a.tc) * (H[q] - eh[q]);
+    const int si = i - L::cx(q), sj = j - L::cy(q), sk = k - L::cz(q);
+    if (si < 0 || si > a.mx || sj < 0 || sj > a.my || sk < 0 || sk > a.mz) {
+      const double eh = equilibrium<LAT>(q, rh, uxh, uyh, uzh);
+      ff[q * a.nf + fine_index(a, si, sj, sk)] = eh + a.tf / (2.0 * a.tc) * (H[q] - eh);
+    }
   }
 }
 
-// fine nodes: pull (the ghost ring holds the perimeter's inward populations),
+// fine nodes: pull (the ghost shell holds the perimeter's inward populations),
 // collide with tau_f; with restrict_ set, the fine nodes on covered coarse
 // nodes write those nodes' post-collision populations
+template <int LAT>
 __global__ __launch_bounds__(256) void k_ref_fine(RefArgs a, int segs, int restrict_) {
-  const int L = (int)xcd_block(blockIdx.x, gridDim.x);
-  const int j = L / segs, i = (L - j * segs) * 256 + (int)threadIdx.x;
+  using L = Lat<LAT>;
+  constexpr int Q = L::Q;
+  const int Lb = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int row = Lb / segs, i = (Lb - row * segs) * 256 + (int)threadIdx.x;
   if (i > a.mx) return;
-  const long p = (long)(j + 1) * a.fw + i + 1;
+  const int j = row % (a.my + 1), k = row / (a.my + 1);
+  const long p = fine_index(a, i, j, k);
+  const long plane = (long)a.fw * a.fh;
   double f[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) f[q] = a.ff_in[q * a.nf + p - CY[q] * a.fw - CX[q]];
-  double rho, ux, uy, e[Q];
-  moments(f, rho, ux, uy);
-  equilibrium(rho, ux, uy, e);
+  for (int q = 0; q < Q; ++q) f[q] = a.ff_in[q * a.nf + p - L::cz(q) * plane - L::cy(q) * a.fw - L::cx(q)];
+  double rho, ux, uy, uz;
+  moments<LAT>(f, rho, ux, uy, uz);
+  const bool rs = restrict_ && !(i & 1) && !(j & 1) && !(k & 1) && covered(a, a.ia + i / 2, a.ja + j / 2, a.ka + k / 2);
+  const long m = rs ? ((long)(a.ka + k / 2) * a.ny + a.ja + j / 2) * a.nx + a.ia + i / 2 : 0;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) a.ff_out[q * a.nf + p] = f[q] - (f[q] - e[q]) / a.tf;
-  if (restrict_ && !(i & 1) && !(j & 1)) {
-    const int I = a.ia + i / 2, J = a.ja + j / 2;
-    if (I > a.ia && I < a.ib && J > a.ja && J < a.jb) {
-      const long m = (long)J * a.nx + I;
-#pragma unroll
-      for (int q = 0; q < Q; ++q) a.fc_out[q * a.nc + m] = e[q] + 2.0 * (a.tc - 1.0) / a.tf * (f[q] - e[q]);
-    }
+  for (int q = 0; q < Q; ++q) {
+    const double e = equilibrium<LAT>(q, rho, ux, uy, uz);
+    a.ff_out[q * a.nf + p] = f[q] - (f[q] - e) / a.tf;
+    if (rs) a.fc_out[q * a.nc + m] = e + 2.0 * (a.tc - 1.0) / a.tf * (f[q] - e);
+  }
+}
+
+// the fine nodes without the ghost shell, [Q][nodes]
+__global__ __launch_bounds__(256) void k_ref_unpad(RefArgs a, int Q, const double* ff, double* out) {
+  const long n1 = (long)(a.mx + 1) * (a.my + 1) * (a.mz + 1);
+  for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < Q * n1; t += (long)gridDim.x * 256) {
+    const long q = t / n1, n = t - q * n1;
+    const int i = (int)(n % (a.mx + 1)), j = (int)((n / (a.mx + 1)) % (a.my + 1));
+    const int k = (int)(n / ((long)(a.mx + 1) * (a.my + 1)));
+    out[t] = ff[q * a.nf + fine_index(a, i, j, k)];
   }
 }
 
@@ -223,11 +275,14 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+int q_of(int lattice) { return lattice == LSB_D2Q9 ? 9 : (lattice == LSB_D3Q19 ? 19 : 27); }
+
 }  // namespace
 
 struct lsb_ref {
   lsb_ref_params P;
   RefArgs base;
+  int Q = 9;
   char* ws = nullptr;
   size_t ws_bytes = 0;
   double* fc[2] = {nullptr, nullptr};
@@ -239,9 +294,9 @@ struct lsb_ref {
 
 namespace {
 size_t sizes(const lsb_ref* r, size_t* fcb, size_t* ffb, size_t* gb) {
-  *fcb = align256(sizeof(double) * Q * (size_t)r->base.nc);
-  *ffb = align256(sizeof(double) * Q * (size_t)r->base.nf);
-  *gb = align256(sizeof(double) * Q * (size_t)r->base.nb);
+  *fcb = align256(sizeof(double) * r->Q * (size_t)r->base.nc);
+  *ffb = align256(sizeof(double) * r->Q * (size_t)r->base.nf);
+  *gb = align256(sizeof(double) * r->Q * (size_t)r->base.nb);
   return 2 * (*fcb + *ffb + *gb);
 }
 
@@ -250,6 +305,46 @@ int check_launch() {
   if (e != hipSuccess) return fail(LSB_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
   return LSB_OK;
 }
+
+unsigned grid_for(long n) {
+  const long g = (n + 255) / 256;
+  return (unsigned)(g < 8192 ? (g > 0 ? g : 1) : 8192);
+}
+
+template <int LAT>
+void launch_init(lsb_ref* r, const double* rc, const double* uc, const double* rf, const double* uf, hipStream_t st) {
+  const RefArgs& b = r->base;
+  const long total = b.nc + (long)(b.mx + 1) * (b.my + 1) * (b.mz + 1);
+  k_ref_init<LAT><<<grid_for(total), 256, 0, st>>>(b, rc, uc, rf, uf, r->fc[0], r->ff[0], r->g[0]);
+}
+
+template <int LAT>
+void launch_steps(lsb_ref* r, int nsteps, hipStream_t st) {
+  const RefArgs& b = r->base;
+  const int sc = (b.nx + 255) / 256, sf = (b.mx + 1 + 255) / 256;
+  const unsigned gc = (unsigned)((long)sc * b.ny * b.nz), gf = (unsigned)((long)sf * (b.my + 1) * (b.mz + 1));
+  const long surf = 2L * (b.my + 1) * (b.mz + 1) + 2L * (b.mx - 1) * (b.mz + 1) +
+                    (b.D == 3 ? 2L * (b.mx - 1) * (b.my - 1) : 0L);
+  const dim3 ge((unsigned)((surf + 255) / 256), 2);
+  for (int s = 0; s < nsteps; ++s) {
+    RefArgs a = b;
+    a.fc_in = r->fc[r->cur];
+    a.fc_out = r->fc[r->cur ^ 1];
+    a.g0 = r->g[r->cur];
+    a.g1 = r->g[r->cur ^ 1];
+    k_ref_coarse<LAT><<<gc, 256, 0, st>>>(a, sc);
+    // inward populations of both fine sub-steps: G halfway in time, then G(t+1)
+    k_ref_edge<LAT><<<ge, 256, 0, st>>>(a, r->ff[0], r->ff[1]);
+    a.ff_in = r->ff[0];
+    a.ff_out = r->ff[1];
+    k_ref_fine<LAT><<<gf, 256, 0, st>>>(a, sf, 0);
+    // sub-step 2 also restricts onto the covered coarse nodes
+    a.ff_in = r->ff[1];
+    a.ff_out = r->ff[0];
+    k_ref_fine<LAT><<<gf, 256, 0, st>>>(a, sf, 1);
+    r->cur ^= 1;
+  }
+}
 }  // namespace
 
 extern "C" {
@@ -257,29 +352,46 @@ extern "C" {
 int lsb_ref_create(const lsb_ref_params* P, lsb_ref** out) {
   if (!P || !out) return fail(LSB_EINVAL, "null pointer");
   *out = nullptr;
-  const int nx = P->nx, ny = P->ny, ia = P->patch[0], ib = P->patch[1], ja = P->patch[2], jb = P->patch[3];
-  if (nx < 4 || ny < 4 || ny > 65535) return fail(LSB_EINVAL, "coarse grid must be at least 4 x 4 with ny <= 65535");
-  if (ia < 1 || ib > nx - 2 || ib - ia < 2 || ja < 1 || jb > ny - 2 || jb - ja < 2)
-    return fail(LSB_EINVAL, "patch must lie inside the coarse grid with one node to spare and span >= 2 cells");
-  if (2 * (jb - ja) >= 65535) return fail(LSB_EINVAL, "patch too tall");
+  if (P->lattice != LSB_D2Q9 && P->lattice != LSB_D3Q19 && P->lattice != LSB_D3Q27)
+    return fail(LSB_EINVAL, "unknown lattice");
+  const bool three = P->lattice != LSB_D2Q9;
+  const int nx = P->nx, ny = P->ny, nz = three ? P->nz : 1;
+  const int ia = P->patch[0], ib = P->patch[1], ja = P->patch[2], jb = P->patch[3];
+  const int ka = three ? P->patch[4] : 0, kb = three ? P->patch[5] : 0;
+  if (nx < 4 || ny < 4 || (three && nz < 4) || (!three && P->nz != 1))
+    return fail(LSB_EINVAL, "coarse grid must be at least 4 nodes per axis (nz = 1 in 2D)");
+  if (ia < 1 || ib > nx - 2 || ib - ia < 2 || ja < 1 || jb > ny - 2 || jb - ja < 2 ||
+      (three && (ka < 1 || kb > nz - 2 || kb - ka < 2)))
+    return fail(LSB_EINVAL, "patch must lie inside the coarse grid with one node to spare and span >= 2 cells per axis");
   if (!(P->tau_c > 0.5)) return fail(LSB_EINVAL, "tau_c must exceed 1/2");
+  const long mx = 2L * (ib - ia), my = 2L * (jb - ja), mz = 2L * (kb - ka);
+  if ((long)nx * ny * nz > (1L << 31) || (mx + 3) * (my + 3) * (three ? mz + 3 : 1) > (1L << 31))
+    return fail(LSB_EINVAL, "grid too large");
   lsb_ref* r = new lsb_ref();
   r->P = *P;
+  r->Q = q_of(P->lattice);
   RefArgs& a = r->base;
   a = RefArgs{};
+  a.D = three ? 3 : 2;
   a.nx = nx;
   a.ny = ny;
+  a.nz = nz;
   a.ia = ia;
   a.ib = ib;
   a.ja = ja;
   a.jb = jb;
-  a.mx = 2 * (ib - ia);
-  a.my = 2 * (jb - ja);
+  a.ka = ka;
+  a.kb = kb;
+  a.mx = (int)mx;
+  a.my = (int)my;
+  a.mz = (int)mz;
   a.bw = ib - ia + 1;
+  a.bh = jb - ja + 1;
   a.fw = a.mx + 3;
-  a.nc = (long)nx * ny;
-  a.nf = (long)a.fw * (a.my + 3);
-  a.nb = (long)a.bw * (jb - ja + 1);
+  a.fh = a.my + 3;
+  a.nc = (long)nx * ny * nz;
+  a.nf = (long)a.fw * a.fh * (three ? a.mz + 3 : 1);
+  a.nb = (long)a.bw * a.bh * (kb - ka + 1);
   a.tc = P->tau_c;
   a.tf = 2.0 * P->tau_c - 0.5;
   *out = r;
@@ -319,10 +431,12 @@ int lsb_ref_init(lsb_ref* r, const double* rho_c, const double* u_c, const doubl
   if (!r || !rho_c || !u_c || !rho_f || !u_f) return fail(LSB_EINVAL, "null pointer");
   if (!r->ws) return fail(LSB_ESTATE, "lsb_ref_init before lsb_ref_bind");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const RefArgs& a = r->base;
-  const int w = a.nx > a.mx + 1 ? a.nx : a.mx + 1, h = a.ny > a.my + 1 ? a.ny : a.my + 1;
   r->cur = 0;
-  k_ref_init<<<dim3((w + 255) / 256, h, 2), 256, 0, st>>>(a, rho_c, u_c, rho_f, u_f, r->fc[0], r->ff[0], r->g[0]);
+  switch (r->P.lattice) {
+    case LSB_D2Q9: launch_init<LSB_D2Q9>(r, rho_c, u_c, rho_f, u_f, st); break;
+    case LSB_D3Q19: launch_init<LSB_D3Q19>(r, rho_c, u_c, rho_f, u_f, st); break;
+    default: launch_init<LSB_D3Q27>(r, rho_c, u_c, rho_f, u_f, st); break;
+  }
   if (int e = check_launch()) return e;
   r->inited = true;
   return LSB_OK;
@@ -333,27 +447,10 @@ int lsb_ref_step(lsb_ref* r, int nsteps, void* stream) {
   if (!r->inited) return fail(LSB_ESTATE, "lsb_ref_step before lsb_ref_init");
   if (nsteps < 0) return fail(LSB_EINVAL, "negative step count");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const RefArgs& b = r->base;
-  const int sc = (b.nx + 255) / 256, sf = (b.mx + 1 + 255) / 256;
-  const unsigned gc = (unsigned)(sc * b.ny), gf = (unsigned)(sf * (b.my + 1));
-  const dim3 ge((unsigned)((2 * (b.mx + 1) + 2 * (b.my - 1) + 255) / 256), 2);
-  for (int s = 0; s < nsteps; ++s) {
-    RefArgs a = b;
-    a.fc_in = r->fc[r->cur];
-    a.fc_out = r->fc[r->cur ^ 1];
-    a.g0 = r->g[r->cur];
-    a.g1 = r->g[r->cur ^ 1];
-    k_ref_coarse<<<gc, 256, 0, st>>>(a, sc);
-    // inward populations of both fine sub-steps: G halfway in time, then G(t+1)
-    k_ref_edge<<<ge, 256, 0, st>>>(a, r->ff[0], r->ff[1]);
-    a.ff_in = r->ff[0];
-    a.ff_out = r->ff[1];
-    k_ref_fine<<<gf, 256, 0, st>>>(a, sf, 0);
-    // sub-step 2 also restricts onto the covered coarse nodes
-    a.ff_in = r->ff[1];
-    a.ff_out = r->ff[0];
-    k_ref_fine<<<gf, 256, 0, st>>>(a, sf, 1);
-    r->cur ^= 1;
+  switch (r->P.lattice) {
+    case LSB_D2Q9: launch_steps<LSB_D2Q9>(r, nsteps, st); break;
+    case LSB_D3Q19: launch_steps<LSB_D3Q19>(r, nsteps, st); break;
+    default: launch_steps<LSB_D3Q27>(r, nsteps, st); break;
   }
   return check_launch();
 }
@@ -362,17 +459,14 @@ int lsb_ref_get_populations(lsb_ref* r, double* coarse, double* fine, void* stre
   if (!r) return fail(LSB_EINVAL, "null pointer");
   if (!r->inited) return fail(LSB_ESTATE, "lsb_ref_get_populations before lsb_ref_init");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (coarse && hipMemcpyAsync(coarse, r->fc[r->cur], sizeof(double) * Q * (size_t)r->base.nc,
+  if (coarse && hipMemcpyAsync(coarse, r->fc[r->cur], sizeof(double) * r->Q * (size_t)r->base.nc,
                                hipMemcpyDeviceToDevice, st) != hipSuccess)
     return fail(LSB_EDEVICE, "copy of the coarse populations failed");
   if (fine) {
-    // the fine nodes without the ghost ring, plane by plane
     const RefArgs& b = r->base;
-    const size_t w = sizeof(double) * (size_t)(b.mx + 1), h = (size_t)(b.my + 1);
-    for (int q = 0; q < Q; ++q)
-      if (hipMemcpy2DAsync(fine + (size_t)q * (b.mx + 1) * h, w, r->ff[0] + q * b.nf + b.fw + 1,
-                           sizeof(double) * (size_t)b.fw, w, h, hipMemcpyDeviceToDevice, st) != hipSuccess)
-        return fail(LSB_EDEVICE, "copy of the fine populations failed");
+    const long n1 = (long)(b.mx + 1) * (b.my + 1) * (b.mz + 1);
+    k_ref_unpad<<<grid_for(r->Q * n1), 256, 0, st>>>(b, r->Q, r->ff[0], fine);
+    if (int e = check_launch()) return e;
   }
   return LSB_OK;
 }

@@ -58,7 +58,8 @@ EXPORTS = [
 
 class RefParams(C.Structure):
     """Mirror of lsb_ref_params (include/lsb_refine.h)."""
-    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("patch", C.c_int * 4), ("tau_c", C.c_double)]
+    _fields_ = [("lattice", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("patch", C.c_int * 6),
+                ("tau_c", C.c_double)]
 SCHED_SERIAL, SCHED_OVERLAP = 0, 1
 MAX_BUBBLES = 64  # LSB_MAX_BUBBLES
 
@@ -324,22 +325,27 @@ class Sim:
 
 
 class Refine:
-    """Two-level static refinement (D2Q9, BGK, FP64, ratio 2) on one GPU:
-    the coarse grid nx x ny (periodic) and a fine patch over the coarse
-    nodes patch = (ia, ib, ja, jb).  Device memory is a torch uint8 tensor
-    (the caller-owned workspace); calls run on torch's current stream."""
+    """Two-level static refinement (BGK, FP64, ratio 2) on one GPU: lattice
+    D2Q9, D3Q19 or D3Q27; the coarse grid nx x ny (x nz), periodic, and a
+    fine patch over the coarse nodes patch = (ia, ib, ja, jb[, ka, kb]).
+    Device memory is a torch uint8 tensor (the caller-owned workspace);
+    calls run on torch's current stream."""
 
-    def __init__(self, nx: int, ny: int, patch, tau_c: float, device="cuda:0"):
+    def __init__(self, nx: int, ny: int, patch, tau_c: float, device="cuda:0", lattice: int = D2Q9, nz: int = 1):
         import torch
         self.torch = torch
         self.lib = load()
         self.device = torch.device(device)
-        self.nx, self.ny = int(nx), int(ny)
-        self.patch = tuple(int(v) for v in patch)
-        ia, ib, ja, jb = self.patch
-        self.mx, self.my = 2 * (ib - ia), 2 * (jb - ja)
-        self.n_coarse, self.n_fine = self.nx * self.ny, (self.mx + 1) * (self.my + 1)
-        self._cp = RefParams(self.nx, self.ny, (C.c_int * 4)(*self.patch), float(tau_c))
+        self.lattice = int(lattice)
+        self.D, self.Q = (2, 9) if self.lattice == D2Q9 else (3, 19 if self.lattice == D3Q19 else 27)
+        self.nx, self.ny, self.nz = int(nx), int(ny), (int(nz) if self.D == 3 else 1)
+        p = tuple(int(v) for v in patch) + (0, 0)
+        ia, ib, ja, jb, ka, kb = p[:6] if self.D == 3 else p[:4] + (0, 0)
+        self.patch = (ia, ib, ja, jb, ka, kb)
+        self.mx, self.my, self.mz = 2 * (ib - ia), 2 * (jb - ja), 2 * (kb - ka)
+        self.n_coarse = self.nx * self.ny * self.nz
+        self.n_fine = (self.mx + 1) * (self.my + 1) * (self.mz + 1)
+        self._cp = RefParams(self.lattice, self.nx, self.ny, self.nz, (C.c_int * 6)(*self.patch), float(tau_c))
         h = C.c_void_p()
         _check(self.lib.lsb_ref_create(C.byref(self._cp), C.byref(h)))
         self.h = h
@@ -363,9 +369,9 @@ class Refine:
         return t.to(self.device).contiguous()
 
     def init(self, rho_c, u_c, rho_f, u_f):
-        """rho [nodes], u [nodes, 2] per level (numpy or torch)."""
-        t = [self._dev(rho_c, self.n_coarse), self._dev(u_c, 2 * self.n_coarse), self._dev(rho_f, self.n_fine),
-             self._dev(u_f, 2 * self.n_fine)]
+        """rho [nodes], u [nodes, D] per level (numpy or torch)."""
+        t = [self._dev(rho_c, self.n_coarse), self._dev(u_c, self.D * self.n_coarse), self._dev(rho_f, self.n_fine),
+             self._dev(u_f, self.D * self.n_fine)]
         _check(self.lib.lsb_ref_init(self.h, *[C.c_void_p(x.data_ptr()) for x in t], self.stream()))
         self.torch.cuda.current_stream(self.device).synchronize()
         return self
@@ -376,9 +382,13 @@ class Refine:
 
     def populations(self, as_numpy=True):
         t = self.torch
-        fc = t.empty(9 * self.n_coarse, dtype=t.float64, device=self.device)
-        ff = t.empty(9 * self.n_fine, dtype=t.float64, device=self.device)
+        fc = t.empty(self.Q * self.n_coarse, dtype=t.float64, device=self.device)
+        ff = t.empty(self.Q * self.n_fine, dtype=t.float64, device=self.device)
         _check(self.lib.lsb_ref_get_populations(self.h, C.c_void_p(fc.data_ptr()), C.c_void_p(ff.data_ptr()),
                                                 self.stream()))
-        fc, ff = fc.reshape(9, self.ny, self.nx), ff.reshape(9, self.my + 1, self.mx + 1)
+        if self.D == 2:
+            fc, ff = fc.reshape(self.Q, self.ny, self.nx), ff.reshape(self.Q, self.my + 1, self.mx + 1)
+        else:
+            fc = fc.reshape(self.Q, self.nz, self.ny, self.nx)
+            ff = ff.reshape(self.Q, self.mz + 1, self.my + 1, self.mx + 1)
         return (fc.cpu().numpy(), ff.cpu().numpy()) if as_numpy else (fc, ff)

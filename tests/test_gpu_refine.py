@@ -1,15 +1,16 @@
-"""Two-level static refinement (D2Q9, BGK, FP64, ratio 2) on the GPU against
-the CPU oracle, element by element on both levels.
+"""Two-level static refinement (D2Q9, D3Q19, D3Q27; BGK, FP64, ratio 2) on
+the GPU against the CPU oracle, element by element on both levels.
 
 The coupling follows the Dupuis-Chopard approach the paper adopts for its
 refinement jumps (Sec. 2, lattice Boltzmann method); lsb_refine.h states
 the steps.  Cases: a small grid, a grid wider than one 256-lane block (the
 fine rows span two blocks with a ragged tail), the minimal 2 x 2-cell patch,
-and the benchmark's configuration (2048^2 coarse nodes, a 1024^2-cell patch,
-about 8.4 M node updates per coarse step), which the oracle still finishes
-in seconds.  Bar: max |f_gpu - f_oracle| <= 1e-13 (populations are O(0.1);
-the two sides differ only in the rounding of fused multiply-adds, measured
-at a few 1e-16 per step).
+and the benchmark's configurations (2D: 2048^2 coarse nodes with a
+1024^2-cell patch; 3D: D3Q27 192^3 with a 96^3-cell patch), which the oracle
+still finishes in seconds; in 3D also D3Q19 and a minimal patch.  Bar:
+max |f_gpu - f_oracle| <= 1e-13 (populations are O(0.1); the two sides
+differ only in the rounding of fused multiply-adds, measured at a few 1e-16
+per step).
 """
 import numpy as np
 import pytest
@@ -85,3 +86,56 @@ def test_refine_uniform_state_is_fixed(require_gpu):
     g.step(3)
     c1, f1 = g.populations()
     assert np.max(np.abs(c1 - c0)) < 1e-15 and np.max(np.abs(f1 - f0)) < 1e-15
+
+
+# --- 3D: D3Q19 and D3Q27, face interpolation ---
+
+def _fields3(n3, lattice, patch, seed, amp=0.02):
+    nx, ny, nz = n3
+    rng = np.random.default_rng(seed)
+    kk = rng.integers(1, 3, (4, 3))
+    ph = rng.uniform(0, 2 * np.pi, 4)
+
+    def sample(x, y, z):
+        s = [np.sin(2 * np.pi * (kk[m, 0] * x / nx + kk[m, 1] * y / ny + kk[m, 2] * z / nz) + ph[m]) for m in range(4)]
+        return 1.0 + 0.5 * amp * s[0], np.stack([amp * s[1], amp * s[2], amp * s[3]], 1)
+
+    K, J, I = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    rc, uc = sample(I.reshape(-1).astype(float), J.reshape(-1).astype(float), K.reshape(-1).astype(float))
+    o = RefineOracle(nx, ny, patch, 0.7, lattice=lattice, nz=nz)
+    rf, uf = sample(*o.fine_coords())
+    return rc, uc, rf, uf
+
+
+def _run_both3(n3, lattice, patch, tau_c, steps, seed):
+    from paper_2601_05936_amd.lsb import Refine
+    nx, ny, nz = n3
+    rc, uc, rf, uf = _fields3(n3, lattice, patch, seed)
+    o = RefineOracle(nx, ny, patch, tau_c, lattice=lattice, nz=nz).init(rc, uc, rf, uf)
+    g = Refine(nx, ny, patch, tau_c, lattice=lattice, nz=nz).init(rc, uc, rf, uf)
+    o.step(steps)
+    g.step(steps)
+    return o.populations(), g.populations()
+
+
+@pytest.mark.parametrize("lattice,n3,patch,tau_c,steps", [
+    (1, (20, 18, 16), (5, 12, 4, 13, 6, 11), 0.7, 12),
+    (2, (20, 18, 16), (5, 12, 4, 13, 6, 11), 0.62, 12),
+    (2, (300, 12, 10), (100, 290, 3, 8, 3, 6), 0.9, 6),  # fine rows of 381 nodes: two blocks, ragged tail
+    (2, (9, 8, 8), (2, 4, 2, 4, 3, 5), 0.8, 10),          # the minimal patch
+])
+def test_refine_3d_matches_oracle(require_gpu, lattice, n3, patch, tau_c, steps):
+    (oc, of), (gc, gf) = _run_both3(n3, lattice, patch, tau_c, steps, seed=sum(n3))
+    ec, ef = np.max(np.abs(gc - oc)), np.max(np.abs(gf - of))
+    print(f"refine D3Q{19 if lattice == 1 else 27} {n3} patch {patch}: coarse {ec:.2e} fine {ef:.2e}", flush=True)
+    assert ec <= TOL and ef <= TOL
+
+
+def test_refine_3d_benchmark_configuration(require_gpu):
+    """D3Q27, 192^3 coarse nodes, patch over [48, 144]^3 (193^3 fine nodes),
+    the launch configuration of the benchmark's 3D leg, 2 coarse steps."""
+    n3, patch = (192, 192, 192), (48, 144, 48, 144, 48, 144)
+    (oc, of), (gc, gf) = _run_both3(n3, 2, patch, 0.6, 2, seed=11)
+    ec, ef = np.max(np.abs(gc - oc)), np.max(np.abs(gf - of))
+    print(f"refine D3Q27 192^3: coarse {ec:.2e} fine {ef:.2e}", flush=True)
+    assert ec <= TOL and ef <= TOL
