@@ -11,7 +11,8 @@
 // Per coarse step, bandwidth-bound FP64 streams (Q x 8 B read and written
 // per node update) and one small perimeter launch:
 //   k_ref_coarse  pull + BGK on the uncovered coarse nodes; the perimeter
-//                 nodes also keep their pre-collision sets (G(t+1));
+//                 nodes also keep their pre-collision sets (G(t+1)), stored
+//                 face by face;
 //   k_ref_edge    per fine perimeter node, the populations whose source lies
 //                 outside the patch, from G, stored where the pull reads
 //                 them: a one-node ghost shell around the fine arrays; both
@@ -41,15 +42,16 @@ using lsb::wgt;
 struct RefArgs {
   int D;
   int nx, ny, nz, ia, ib, ja, jb, ka, kb, mx, my, mz;  // fine nodes (mx + 1) x (my + 1) x (mz + 1)
-  int bw, bh;                                          // patch box extents in x, y
+  int bw, bh, bd;                                      // patch box extents in x, y, z (bd = 1 in 2D)
   int fw, fh;                                          // fine pitches with the ghost shell: mx + 3, my + 3
-  long nc, nf, nb;                                     // nodes: coarse, fine (with the shell), patch box
+  long nc, nf, nb;                                     // nodes: coarse, fine (with the shell), box surface
+  long fo[6];                                          // start of each face's nodes in the surface arrays
   double tc, tf;
   const double* fc_in;
   double* fc_out;
   const double* ff_in;
   double* ff_out;
-  const double* g0;  // coarse pre-collision sets over the patch box, time t
+  const double* g0;  // coarse pre-collision sets on the box surface, time t
   double* g1;        // time t + 1
 };
 
@@ -88,8 +90,28 @@ __device__ __forceinline__ double equilibrium(int q, double rho, double ux, doub
   return wgt<LAT>(q) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
 }
 
-__device__ __forceinline__ long box_index(const RefArgs& a, int I, int J, int K) {
-  return ((long)(K - a.ka) * a.bh + (J - a.ja)) * a.bw + (I - a.ia);
+// The coarse perimeter's sets are stored face by face, each face a 2D array
+// whose fastest index runs along the face (y on the x faces, x on the y and
+// z faces), so the threads of a face read consecutive entries.  Faces: 0/1
+// at I = ia / ib, 2/3 at J = ja / jb, 4/5 at K = ka / kb (3D).  A node on an
+// edge or corner of the box is stored on each of its faces.
+__device__ __forceinline__ long face_index(const RefArgs& a, int f, int I, int J, int K) {
+  if (f < 2) return a.fo[f] + (long)(K - a.ka) * a.bh + (J - a.ja);
+  if (f < 4) return a.fo[f] + (long)(K - a.ka) * a.bw + (I - a.ia);
+  return a.fo[f] + (long)(J - a.ja) * a.bw + (I - a.ia);
+}
+
+// stores set v (Q values) of perimeter node (I, J, K) on each face it lies on
+template <int Q>
+__device__ __forceinline__ void store_faces(const RefArgs& a, double* g, int I, int J, int K, const double* v) {
+  const bool on[6] = {I == a.ia, I == a.ib, J == a.ja, J == a.jb, a.D == 3 && K == a.ka, a.D == 3 && K == a.kb};
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    if (!on[f]) continue;
+    const long b = face_index(a, f, I, J, K);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) g[q * a.nb + b] = v[q];
+  }
 }
 
 __device__ __forceinline__ bool covered(const RefArgs& a, int I, int J, int K) {
@@ -118,14 +140,13 @@ __global__ __launch_bounds__(256) void k_ref_init(RefArgs a, const double* rho_c
     const double ux = u[D * n], uy = u[D * n + 1], uz = D == 3 ? u[D * n + 2] : 0.0;
     if (coarse) {
       const int I = (int)(n % a.nx), J = (int)((n / a.nx) % a.ny), K = (int)(n / ((long)a.nx * a.ny));
-      const bool per = in_box(a, I, J, K) && !covered(a, I, J, K);
-      const long b = per ? box_index(a, I, J, K) : 0;
+      double e[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        const double e = equilibrium<LAT>(q, r[n], ux, uy, uz);
-        fc[q * a.nc + n] = e;
-        if (per) g0[q * a.nb + b] = e;
+        e[q] = equilibrium<LAT>(q, r[n], ux, uy, uz);
+        fc[q * a.nc + n] = e[q];
       }
+      if (in_box(a, I, J, K) && !covered(a, I, J, K)) store_faces<Q>(a, g0, I, J, K, e);
     } else {
       const int i = (int)(n % (a.mx + 1)), j = (int)((n / (a.mx + 1)) % (a.my + 1));
       const int k = (int)(n / ((long)(a.mx + 1) * (a.my + 1)));
@@ -155,11 +176,7 @@ __global__ __launch_bounds__(256) void k_ref_coarse(RefArgs a, int segs) {
 #pragma unroll
   for (int q = 0; q < Q; ++q)
     f[q] = a.fc_in[q * a.nc + ((long)zs[L::cz(q) + 1] * a.ny + ys[L::cy(q) + 1]) * a.nx + xs[L::cx(q) + 1]];
-  if (inb) {
-    const long b = box_index(a, x, y, z);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) a.g1[q * a.nb + b] = f[q];
-  }
+  if (inb) store_faces<Q>(a, a.g1, x, y, z, f);
   double rho, ux, uy, uz;
   moments<LAT>(f, rho, ux, uy, uz);
   const long n = ((long)z * a.ny + y) * a.nx + x;
@@ -184,19 +201,22 @@ __global__ __launch_bounds__(256) void k_ref_edge(RefArgs a, double* ff1, double
   long t = (long)blockIdx.x * 256 + threadIdx.x;
   const long ax = (long)(a.my + 1) * (a.mz + 1), ay = (long)(a.mx - 1) * (a.mz + 1);
   const long az = a.D == 3 ? (long)(a.mx - 1) * (a.my - 1) : 0;
-  int i, j, k;
+  int i, j, k, face;
   if (t < 2 * ax) {
     const long u = t % ax;
+    face = t < ax ? 0 : 1;
     i = t < ax ? 0 : a.mx;
     j = (int)(u % (a.my + 1));
     k = (int)(u / (a.my + 1));
   } else if ((t -= 2 * ax) < 2 * ay) {
     const long u = t % ay;
+    face = t < ay ? 2 : 3;
     j = t < ay ? 0 : a.my;
     i = 1 + (int)(u % (a.mx - 1));
     k = (int)(u / (a.mx - 1));
   } else if ((t -= 2 * ay) < 2 * az) {
     const long u = t % az;
+    face = t < az ? 4 : 5;
     k = t < az ? 0 : a.mz;
     i = 1 + (int)(u % (a.mx - 1));
     j = 1 + (int)(u / (a.mx - 1));
@@ -204,7 +224,8 @@ __global__ __launch_bounds__(256) void k_ref_edge(RefArgs a, double* ff1, double
     return;
   }
   // the coarse set at this node: along each odd coordinate the mean of the
-  // two coarse nodes beside it (z outermost, x innermost)
+  // two coarse nodes beside it (z outermost, x innermost), all on the node's
+  // face
   const int ox = i & 1, oy = j & 1, oz = k & 1;
   const double s = (ox ? 0.5 : 1.0) * (oy ? 0.5 : 1.0) * (oz ? 0.5 : 1.0);
   double H[Q];
@@ -213,7 +234,7 @@ __global__ __launch_bounds__(256) void k_ref_edge(RefArgs a, double* ff1, double
   for (int dz = 0; dz <= oz; ++dz)
     for (int dy = 0; dy <= oy; ++dy)
       for (int dx = 0; dx <= ox; ++dx) {
-        const long b = box_index(a, a.ia + (i - ox) / 2 + dx, a.ja + (j - oy) / 2 + dy, a.ka + (k - oz) / 2 + dz);
+        const long b = face_index(a, face, a.ia + (i - ox) / 2 + dx, a.ja + (j - oy) / 2 + dy, a.ka + (k - oz) / 2 + dz);
 #pragma unroll
         for (int q = 0; q < Q; ++q) H[q] += s * (wa * a.g0[q * a.nb + b] + wb * a.g1[q * a.nb + b]);
       }
@@ -391,7 +412,18 @@ int lsb_ref_create(const lsb_ref_params* P, lsb_ref** out) {
   a.fh = a.my + 3;
   a.nc = (long)nx * ny * nz;
   a.nf = (long)a.fw * a.fh * (three ? a.mz + 3 : 1);
-  a.nb = (long)a.bw * a.bh * (kb - ka + 1);
+  a.bd = kb - ka + 1;
+  {
+    // face sizes: x faces bh x bd, y faces bw x bd, z faces (3D) bw x bh
+    const long sz[6] = {(long)a.bh * a.bd, (long)a.bh * a.bd, (long)a.bw * a.bd, (long)a.bw * a.bd,
+                        three ? (long)a.bw * a.bh : 0L, three ? (long)a.bw * a.bh : 0L};
+    long o = 0;
+    for (int f = 0; f < 6; ++f) {
+      a.fo[f] = o;
+      o += sz[f];
+    }
+    a.nb = o;
+  }
   a.tc = P->tau_c;
   a.tf = 2.0 * P->tau_c - 0.5;
   *out = r;
