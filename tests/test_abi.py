@@ -104,3 +104,53 @@ def test_reverse_mode_rejects_per_bubble_baselines():
         nb = C.c_size_t()
         assert lib.lsb_adjoint_workspace_bytes(h, 10, C.byref(nb)) == want
         lib.lsb_destroy(h)
+
+
+def _ref_create(**kw):
+    p = dict(lattice=lsb.D2Q9, nx=32, ny=24, nz=1, patch=(8, 20, 6, 16, 0, 0), tau_c=0.7)
+    p.update(kw)
+    cp = lsb.RefParams(p["lattice"], p["nx"], p["ny"], p["nz"], (C.c_int * 6)(*p["patch"]), p["tau_c"])
+    h = C.c_void_p()
+    rc = lsb.load().lsb_ref_create(C.byref(cp), C.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("bad", [
+    dict(lattice=5), dict(nx=3), dict(nz=2),                                   # 2D needs nz = 1
+    dict(patch=(0, 20, 6, 16, 0, 0)), dict(patch=(8, 31, 6, 16, 0, 0)),        # no spare node at the edge
+    dict(patch=(8, 9, 6, 16, 0, 0)),                                            # fewer than 2 cells
+    dict(tau_c=0.5),
+    dict(lattice=lsb.D3Q27, nz=16, patch=(8, 20, 6, 16, 0, 9)),                 # 3D: ka < 1
+    dict(lattice=lsb.D3Q19, nz=3, patch=(8, 20, 6, 16, 1, 2)),                  # 3D: nz < 4
+])
+def test_refine_create_rejects_invalid_parameters(bad):
+    rc, h = _ref_create(**bad)
+    assert rc == lsb.LSB_EINVAL
+    assert lsb.load().lsb_last_error().decode()
+
+
+def test_refine_workspace_layout():
+    """Workspace = 2 x (coarse + fine with a one-node ghost shell + the box
+    surface), Q doubles per node, each part aligned to 256 bytes."""
+    def up(v):
+        return (v + 255) // 256 * 256
+    lib = lsb.load()
+    for lat, Q, n3, patch in [(lsb.D2Q9, 9, (32, 24, 1), (8, 20, 6, 16, 0, 0)),
+                              (lsb.D3Q27, 27, (20, 18, 16), (5, 12, 4, 13, 6, 11))]:
+        rc, h = _ref_create(lattice=lat, nx=n3[0], ny=n3[1], nz=n3[2], patch=patch)
+        assert rc == lsb.LSB_OK
+        nb = C.c_size_t()
+        assert lib.lsb_ref_workspace_bytes(h, C.byref(nb)) == lsb.LSB_OK
+        ia, ib, ja, jb, ka, kb = patch
+        mx, my, mz = 2 * (ib - ia), 2 * (jb - ja), 2 * (kb - ka)
+        nc = n3[0] * n3[1] * n3[2]
+        if lat == lsb.D2Q9:
+            nf = (mx + 3) * (my + 3)
+            ns = 2 * (jb - ja + 1) + 2 * (ib - ia + 1)
+        else:
+            bw, bh, bd = ib - ia + 1, jb - ja + 1, kb - ka + 1
+            nf = (mx + 3) * (my + 3) * (mz + 3)
+            ns = 2 * bh * bd + 2 * bw * bd + 2 * bw * bh
+        assert nb.value == 2 * (up(8 * Q * nc) + up(8 * Q * nf) + up(8 * Q * ns))
+        assert lib.lsb_ref_bind(h, C.c_void_p(1 << 20), nb.value - 1) == lsb.LSB_ENOMEM
+        lib.lsb_ref_destroy(h)
