@@ -905,28 +905,39 @@ __global__ __launch_bounds__(256) void k_ext_seed(const typename Step<LAT, ST>::
   using R = typename S::R;
   const size_t N = a.N;
   for_tile_cells<S::D>(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
+    // every load (own tag, moments, phi, normal, both neighbours' tags on
+    // each axis) is issued before the cell's class is known
     const uint8_t t = a.tag[c];
+    R mn[3];
+    for (int m = 0; m < 3; ++m) mn[m] = a.Mn[(1 + m) * N + c];
+    const R ph = a.phi[c];
+    const int pos[3] = {x, y, z};
+    const int n[3] = {a.nx, a.ny, a.nz};
+    R gv[3] = {0, 0, 0};
+    bool act_lo[3] = {false, false, false}, act_hi[3] = {false, false, false};
+    for (int ax = 0; ax < S::D; ++ax) {
+      gv[ax] = a.G[ax * N + c];
+      for (int sd = -1; sd <= 1; sd += 2) {
+        // a neighbour beyond a wall reads the cell itself (no branch around
+        // the load) and counts as inactive
+        const int sv = lb_coord(pos[ax] + sd, sel3(n, ax), sel3(a.per, ax));
+        int p2[3] = {x, y, z};
+        p2[ax] = sv >= 0 ? sv : pos[ax];
+        const uint8_t tn = a.tag[(p2[2] * a.ny + p2[1]) * a.nx + p2[0]];
+        const bool on = (sv >= 0) & ((tn & T_ACT) != 0);
+        (sd < 0 ? act_lo : act_hi)[ax] = on;
+      }
+    }
     if ((t & (T_ACT | T_SPEC)) != T_ACT) return;
-    for (int m = 0; m < 3; ++m) a.ut_a[m * N + c] = a.Mn[(1 + m) * N + c];
+    for (int m = 0; m < 3; ++m) a.ut_a[m * N + c] = mn[m];
     // coefficients of the sweeps (phi and n are fixed over them): dtau v_ax
     // with v = S(phi) n; 0 where v_ax is 0 or the upwind neighbour is beyond
     // a wall or not LS-active
-    const R ph = a.phi[c];
     const R sg = ph / sqrt(ph * ph + (R)1);
-    const int pos[3] = {x, y, z};
-    const int n[3] = {a.nx, a.ny, a.nz};
     for (int ax = 0; ax < S::D; ++ax) {
-      const R v = sg * a.G[ax * N + c];
+      const R v = sg * gv[ax];
       R kk = 0;
-      if (v != (R)0) {
-        const int sv = lb_coord(pos[ax] + (v > (R)0 ? -1 : 1), sel3(n, ax), sel3(a.per, ax));
-        if (sv >= 0) {
-          int p2[3] = {x, y, z};
-          p2[ax] = sv;
-          const int nc = (p2[2] * a.ny + p2[1]) * a.nx + p2[0];
-          if (a.tag[nc] & T_ACT) kk = a.ext_dtau * v;
-        }
-      }
+      if (v != (R)0 && (v > (R)0 ? act_lo[ax] : act_hi[ax])) kk = a.ext_dtau * v;
       a.ext_k[ax * N + c] = kk;
     }
   });
@@ -1010,14 +1021,10 @@ __global__ __launch_bounds__(256) void k_ext_iter(const typename Step<LAT, ST>::
 // Non-active cells keep phi = s1 = s2 (maintained by k_ls_sync).
 // ---------------------------------------------------------------------------
 template <class R>
-__device__ __forceinline__ R upwind5(const R* f, int c, int stride_m3, int stride_m2, int stride_m1, int stride_p1,
-                                     int stride_p2, int stride_p3, bool positive) {
+__device__ __forceinline__ R upwind5(R fm3, R fm2, R fm1, R f0, R fp1, R fp2, R fp3, bool positive) {
   const R r60 = (R)(1.0 / 60.0);
-  if (positive)
-    return ((R)-2 * f[stride_m3] + (R)15 * f[stride_m2] - (R)60 * f[stride_m1] + (R)20 * f[c] + (R)30 * f[stride_p1] -
-            (R)3 * f[stride_p2]) * r60;
-  return ((R)3 * f[stride_m2] - (R)30 * f[stride_m1] - (R)20 * f[c] + (R)60 * f[stride_p1] - (R)15 * f[stride_p2] +
-          (R)2 * f[stride_p3]) * r60;
+  if (positive) return ((R)-2 * fm3 + (R)15 * fm2 - (R)60 * fm1 + (R)20 * f0 + (R)30 * fp1 - (R)3 * fp2) * r60;
+  return ((R)3 * fm2 - (R)30 * fm1 - (R)20 * f0 + (R)60 * fp1 - (R)15 * fp2 + (R)2 * fp3) * r60;
 }
 
 template <class Args>
@@ -1035,14 +1042,16 @@ __global__ __launch_bounds__(256) void k_rk3_stage(const typename Step<LAT, ST>:
   const size_t N = a.N;
   const R* in = stage == 1 ? a.phi : (stage == 2 ? a.s1 : a.s2);
   R* out = stage == 1 ? a.s1 : (stage == 2 ? a.s2 : a.phi);
+  // every load is issued before the cell's activity is known (the store
+  // alone depends on it): one memory round trip per cell instead of three
   for_tile_cells<S::D>(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
-    if (!(a.tag[c] & T_ACT)) return;
+    const bool act = (a.tag[c] & T_ACT) != 0;
     R r = 0;
     for (int ax = 0; ax < S::D; ++ax) {
       const R u = ut[ax * N + c];
-      const R dd = upwind5<R>(in, c, ls_index(a, x, y, z, ax, -3), ls_index(a, x, y, z, ax, -2),
-                              ls_index(a, x, y, z, ax, -1), ls_index(a, x, y, z, ax, 1), ls_index(a, x, y, z, ax, 2),
-                              ls_index(a, x, y, z, ax, 3), u >= (R)0);
+      const R dd = upwind5<R>(in[ls_index(a, x, y, z, ax, -3)], in[ls_index(a, x, y, z, ax, -2)],
+                              in[ls_index(a, x, y, z, ax, -1)], in[c], in[ls_index(a, x, y, z, ax, 1)],
+                              in[ls_index(a, x, y, z, ax, 2)], in[ls_index(a, x, y, z, ax, 3)], u >= (R)0);
       r = r - u * dd;
     }
     const R v = in[c] + r;
@@ -1054,7 +1063,7 @@ __global__ __launch_bounds__(256) void k_rk3_stage(const typename Step<LAT, ST>:
       if (o > a.band) o = a.band;
       if (o < -a.band) o = -a.band;
     }
-    out[c] = o;
+    if (act) out[c] = o;
   });
 }
 
@@ -1110,6 +1119,8 @@ __global__ __launch_bounds__(256) void k_reinit_stage(const typename Step<LAT, S
   R* out = stage == 1 ? a.s1 : (stage == 2 ? a.s2 : a.phi);
   const R beta = (R)0.5;
   const R dt = a.reinit_dtau;
+  // (unlike the RK3 stage, loading before the activity test loses here: the
+  // WENO arithmetic would run on the inactive cells of active tiles too)
   for_tile_cells<S::D>(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
     if (!(a.tag[c] & T_ACT)) return;
     const R ph0 = a.p0[c];
@@ -1167,8 +1178,9 @@ __global__ __launch_bounds__(256) void k_reinit_stage(const typename Step<LAT, S
 template <int LAT, int ST>
 __global__ __launch_bounds__(256) void k_ls_sync(const typename Step<LAT, ST>::Args a) {
   for_tile_cells<Step<LAT, ST>::D>(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int, int, int) {
-    if (!(a.tag[c] & T_ACT)) return;
+    const bool act = (a.tag[c] & T_ACT) != 0;
     const auto v = a.phi[c];
+    if (!act) return;
     a.s1[c] = v;
     a.s2[c] = v;
     a.p0[c] = v;
@@ -1451,8 +1463,10 @@ __global__ __launch_bounds__(256) void k_geometry(const typename Step<LAT, ST>::
   using S = Step<LAT, ST>;
   using R = typename S::R;
   const size_t N = a.N;
+  // the stencil is loaded before the cell's activity is known (only the
+  // stores depend on it)
   for_tile_cells<S::D>(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
-    if (!(a.tag[c] & T_ACT)) return;
+    const bool act = (a.tag[c] & T_ACT) != 0;
     auto at = [&](int dx, int dy, int dz) {
       const int sx = ls_coord(x + dx, a.nx, a.per[0]);
       const int sy = ls_coord(y + dy, a.ny, a.per[1]);
@@ -1474,6 +1488,7 @@ __global__ __launch_bounds__(256) void k_geometry(const typename Step<LAT, ST>::
     }
     const R g2 = gx * gx + gy * gy + gz * gz;
     const R g = sqrt(g2);
+    if (!act) return;
     if (g < (R)1e-12) {
       a.G[c] = 0; a.G[N + c] = 0; a.G[2 * N + c] = 0; a.G[3 * N + c] = 0;
       return;
