@@ -525,6 +525,9 @@ __global__ __launch_bounds__(256) void k_lb_wall(const typename Step<LAT, ST>::A
 }
 
 // Marks wall-adjacent cells (a link leaves through a wall face) and lists them.
+// Every lane of a wavefront runs the same iterations except in the last,
+// where the lanes past N have left the loop (wave_append ballots the active
+// lanes only).
 template <int LAT, int ST>
 __global__ __launch_bounds__(256) void k_mark_walls(const typename Step<LAT, ST>::Args a) {
   for (int c = blockIdx.x * 256 + threadIdx.x; c < a.N; c += gridDim.x * 256) {
@@ -534,7 +537,10 @@ __global__ __launch_bounds__(256) void k_mark_walls(const typename Step<LAT, ST>
     const bool wz = !a.per[2] && (z == 0 || z == a.nz - 1);
     const bool wall = wx || wy || wz;
     a.tag[c] = (uint8_t)((a.tag[c] & ~T_WALL) | (wall ? T_WALL : 0));
-    if (wall) a.wall_list[atomicAdd(&a.counters[CNT_WALL], 1)] = c;
+    // one append per wavefront, lanes in cell order: the list comes in runs
+    // of consecutive cells, which the wall kernel reads coalesced
+    const int slot = wave_append(&a.counters[CNT_WALL], wall);
+    if (wall) a.wall_list[slot] = c;
   }
 }
 
@@ -960,16 +966,25 @@ __global__ __launch_bounds__(256) void k_ext_seed_iface(const typename Step<LAT,
     const int k = a.tag[c] & T_GAS;
     const R pc = a.phi[c];
     const R uc[3] = {a.Mn[N + c], a.Mn[2 * N + c], a.Mn[3 * N + c]};
-    R acc[3] = {0, 0, 0};
-    int cnt = 0;
+    // the neighbours' tags first, all in flight together (a source beyond a
+    // wall reads the cell itself and is skipped), then the cut links' values
+    int src[S::Q];
+    uint8_t tn[S::Q];
+#pragma unroll
     for (int i = 0; i < S::Q; ++i) {
-      if (c2<LAT>(i) == 0) continue;
       const int sx = lb_coord(x - L::cx(i), a.nx, a.per[0]);
       const int sy = lb_coord(y - L::cy(i), a.ny, a.per[1]);
       const int sz = lb_coord(z - L::cz(i), a.nz, a.per[2]);
-      if ((sx | sy | sz) < 0) continue;
-      const int sc = (sz * a.ny + sy) * a.nx + sx;
-      if ((a.tag[sc] & T_GAS) == k) continue;
+      const bool in = (sx | sy | sz) >= 0;
+      src[i] = in ? (sz * a.ny + sy) * a.nx + sx : -1;
+      tn[i] = a.tag[in ? src[i] : c];
+    }
+    R acc[3] = {0, 0, 0};
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < S::Q; ++i) {
+      if (c2<LAT>(i) == 0 || src[i] < 0 || (tn[i] & T_GAS) == k) continue;
+      const int sc = src[i];
       const R q = pc / (pc - a.phi[sc]);
       for (int m = 0; m < 3; ++m) acc[m] += ((R)1 - q) * uc[m] + q * a.Mn[(1 + m) * N + sc];
       ++cnt;
