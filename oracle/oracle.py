@@ -119,6 +119,8 @@ def _load():
     lib.orc_ref_init.argtypes = [C.c_void_p, dp, dp, dp, dp]
     lib.orc_ref_step.argtypes = [C.c_void_p, C.c_int]
     lib.orc_ref_get.argtypes = [C.c_void_p, dp, dp]
+    lib.orc_ref_sensor.argtypes = [C.c_void_p, dp, C.c_double, C.c_int, C.POINTER(C.c_int)]
+    lib.orc_ref_remesh.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
     _lib = lib
     return lib
 
@@ -424,6 +426,28 @@ class RefineOracle:
 
     def step(self, n: int = 1):
         self._lib.orc_ref_step(self._h, int(n))
+        return self
+
+    def sensor(self, phi, d_ref: float, margin: int):
+        """Patch box (6 ints) of the level-set sensor on the coarse level set
+        phi [n_coarse], or None when no node is tagged."""
+        out = (C.c_int * 6)()
+        keep = _f64(phi, self.n_coarse)
+        if not self._lib.orc_ref_sensor(self._h, _dp(keep), float(d_ref), int(margin), out):
+            return None
+        return tuple(out)
+
+    def remesh(self, patch):
+        """Re-mesh onto patch (6 ints; ka, kb ignored in 2D)."""
+        p = tuple(int(v) for v in patch) + (0, 0)
+        p6 = (C.c_int * 6)(*p[:6])
+        if self._lib.orc_ref_remesh(self._h, p6) != 0:
+            raise ValueError("patch does not fit the grid")
+        ia, ib, ja, jb, ka, kb = p[:6]
+        if self.D == 2:
+            ka = kb = 0
+        self.patch = (ia, ib, ja, jb, ka, kb) if self.D == 3 else (ia, ib, ja, jb)
+        self.mx, self.my, self.mz = 2 * (ib - ia), 2 * (jb - ja), 2 * (kb - ka)
         return self
 
     def populations(self):

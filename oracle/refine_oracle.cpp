@@ -190,6 +190,120 @@ struct Ref {
     fc.swap(nfc);
     g0.swap(g1);
   }
+
+  // Level-set refinement sensor (Sec. 3, adaptive mesh refinement): a coarse
+  // node is tagged for refinement where it lies in the gas or within d_ref
+  // of it.  This build's level set is negative in the liquid and >= 0 in the
+  // gas, the opposite of the sign the sensor is written with, so the test is
+  // phi >= -d_ref.  The patch is the tagged nodes' bounding box grown by
+  // margin nodes, clamped to keep one node to spare at each grid face and
+  // widened to at least two cells per axis; out = (ia, ib, ja, jb, ka, kb).
+  // Returns false (out untouched) when no node is tagged.
+  bool sensor_box(const double* phi, double d_ref, int margin, int* out) const {
+    int lo[3] = {nx, ny, nz}, hi[3] = {-1, -1, -1};
+    for (int K = 0; K < nz; ++K)
+      for (int J = 0; J < ny; ++J)
+        for (int I = 0; I < nx; ++I) {
+          if (!(phi[cidx(I, J, K)] >= -d_ref)) continue;
+          const int p[3] = {I, J, K};
+          for (int d = 0; d < 3; ++d) {
+            if (p[d] < lo[d]) lo[d] = p[d];
+            if (p[d] > hi[d]) hi[d] = p[d];
+          }
+        }
+    if (hi[0] < 0) return false;
+    const int n[3] = {nx, ny, nz};
+    for (int d = 0; d < D; ++d) {
+      int a = lo[d] - margin, b = hi[d] + margin;
+      if (a < 1) a = 1;
+      if (b > n[d] - 2) b = n[d] - 2;
+      while (b - a < 2) {
+        if (b < n[d] - 2) ++b;
+        else --a;
+      }
+      out[2 * d] = a;
+      out[2 * d + 1] = b;
+    }
+    if (D == 2) out[4] = out[5] = 0;
+    return true;
+  }
+
+  // Re-meshing onto a new patch box at the end of a coarse step (state at
+  // time t: post-collision populations of both levels, the covered coarse
+  // nodes holding restricted values).  New fine nodes inside the old patch
+  // keep the old fine populations; the others take the coarse populations
+  // interpolated like the perimeter's (the mean of the 2, 4 or 8 coarse
+  // nodes around an off-grid fine node), their non-equilibrium part scaled
+  // by the post-collision ratio (tau_f - 1) / (2 (tau_c - 1)) about the
+  // equilibrium of the interpolated moments (the equilibrium alone when
+  // tau_c = 1, where the coarse post-collision state holds no
+  // non-equilibrium part).  The new perimeter's pre-collision sets G(t) come
+  // from the coarse post-collision populations by inverting the BGK step,
+  // f_eq + tau_c / (tau_c - 1) (f - f_eq) (f_eq at tau_c = 1).  Covered
+  // coarse nodes are restricted again at the end of the next step; coarse
+  // nodes the patch no longer covers keep their restricted values.
+  void remesh(const int* np) {
+    const int oia = ia, oib = ib, oja = ja, ojb = jb, oka = ka, okb = kb, omx = mx, omy = my, omz = mz;
+    const std::vector<double> off = ff;
+    const long onf = nf();
+    ia = np[0];
+    ib = np[1];
+    ja = np[2];
+    jb = np[3];
+    ka = D == 3 ? np[4] : 0;
+    kb = D == 3 ? np[5] : 0;
+    mx = 2 * (ib - ia);
+    my = 2 * (jb - ja);
+    mz = 2 * (kb - ka);
+    ff.assign(Q * nf(), 0.0);
+    g0.assign(Q * nb(), 0.0);
+    g1.assign(Q * nb(), 0.0);
+    double H[QMAX], e[QMAX];
+    const bool flat = tc == 1.0;
+    const double up = flat ? 0.0 : (tf - 1.0) / (2.0 * (tc - 1.0));
+    for (int k = 0; k <= mz; ++k)
+      for (int j = 0; j <= my; ++j)
+        for (int i = 0; i <= mx; ++i) {
+          // coarse-unit position times two
+          const int X2 = 2 * ia + i, Y2 = 2 * ja + j, Z2 = 2 * ka + k;
+          const int oi = X2 - 2 * oia, oj = Y2 - 2 * oja, ok = Z2 - 2 * oka;
+          const long n = fidx(i, j, k);
+          if (oi >= 0 && oi <= omx && oj >= 0 && oj <= omy && ok >= 0 && ok <= omz) {
+            const long on = ((long)ok * (omy + 1) + oj) * (omx + 1) + oi;
+            for (int q = 0; q < Q; ++q) ff[q * nf() + n] = off[q * onf + on];
+            continue;
+          }
+          const int ox = X2 & 1, oy = Y2 & 1, oz = Z2 & 1;
+          const double s = (ox ? 0.5 : 1.0) * (oy ? 0.5 : 1.0) * (oz ? 0.5 : 1.0);
+          for (int q = 0; q < Q; ++q) H[q] = 0.0;
+          for (int dz = 0; dz <= oz; ++dz)
+            for (int dy = 0; dy <= oy; ++dy)
+              for (int dx = 0; dx <= ox; ++dx) {
+                const long m = cidx((X2 - ox) / 2 + dx, (Y2 - oy) / 2 + dy, (Z2 - oz) / 2 + dz);
+                for (int q = 0; q < Q; ++q) H[q] += s * fc[q * nc() + m];
+              }
+          double rho, ux, uy, uz;
+          moments(H, rho, ux, uy, uz);
+          feq(rho, ux, uy, uz, e);
+          for (int q = 0; q < Q; ++q) ff[q * nf() + n] = e[q] + up * (H[q] - e[q]);
+        }
+    const double down = flat ? 0.0 : tc / (tc - 1.0);
+    for (int K = ka; K <= (D == 3 ? kb : 0); ++K)
+      for (int J = ja; J <= jb; ++J)
+        for (int I = ia; I <= ib; ++I) {
+          if (!perimeter(I, J, K)) continue;
+          const long m = cidx(I, J, K);
+          double f[QMAX];
+          for (int q = 0; q < Q; ++q) f[q] = fc[q * nc() + m];
+          double rho, ux, uy, uz;
+          moments(f, rho, ux, uy, uz);
+          feq(rho, ux, uy, uz, e);
+          for (int q = 0; q < Q; ++q) g0[q * nb() + box(I, J, K)] = e[q] + down * (f[q] - e[q]);
+        }
+    (void)oib;
+    (void)ojb;
+    (void)okb;
+  }
 };
 
 }  // namespace ref
@@ -247,6 +361,22 @@ int orc_ref_init(void* h, const double* rho_c, const double* u_c, const double* 
 int orc_ref_step(void* h, int n) {
   ref::Ref* r = static_cast<ref::Ref*>(h);
   for (int s = 0; s < n; ++s) r->step();
+  return 0;
+}
+
+// sensor box from a coarse level set (out: ia, ib, ja, jb, ka, kb); returns 1
+// when a node is tagged, 0 otherwise
+int orc_ref_sensor(void* h, const double* phi, double d_ref, int margin, int* out) {
+  return static_cast<ref::Ref*>(h)->sensor_box(phi, d_ref, margin, out) ? 1 : 0;
+}
+
+// re-mesh onto the patch (ia, ib, ja, jb, ka, kb); -1 if it does not fit the grid
+int orc_ref_remesh(void* h, const int* patch) {
+  ref::Ref* r = static_cast<ref::Ref*>(h);
+  const int n[3] = {r->nx, r->ny, r->nz};
+  for (int d = 0; d < r->D; ++d)
+    if (patch[2 * d] < 1 || patch[2 * d + 1] > n[d] - 2 || patch[2 * d + 1] - patch[2 * d] < 2) return -1;
+  r->remesh(patch);
   return 0;
 }
 

@@ -193,3 +193,67 @@ def test_stress_at_the_jump_matches_chapman_enskog_3d(lattice):
     face = np.isclose(yf, 9) | np.isclose(yf, 23)
     assert face.sum() > 100
     assert np.max(np.abs(pxy[face] - expect[face])) < 0.02 * np.max(np.abs(expect[face]))
+
+
+# --- level-set sensor and re-meshing ---
+
+@pytest.mark.parametrize("lattice", [0, 2])
+def test_remesh_keeps_a_uniform_state(lattice):
+    if lattice == 0:
+        r = RefineOracle(32, 30, (8, 20, 6, 22), 0.7)
+        u, new = np.array([0.03, -0.02]), (5, 25, 4, 18)
+    else:
+        r = RefineOracle(20, 18, (5, 12, 4, 13, 6, 11), 0.7, lattice=2, nz=16)
+        u, new = np.array([0.03, -0.02, 0.01]), (3, 15, 6, 14, 4, 12)
+    r.init(np.full(r.n_coarse, 1.01), np.tile(u, r.n_coarse), np.full(r.n_fine, 1.01), np.tile(u, r.n_fine))
+    r.step(3)
+    fc0, ff0 = r.populations()
+    r.remesh(new)
+    r.step(3)
+    fc, ff = r.populations()
+    e = ff0.reshape(ff0.shape[0], -1)[:, :1]
+    assert np.max(np.abs(fc - fc0)) < 1e-14
+    assert np.max(np.abs(ff.reshape(ff.shape[0], -1) - e)) < 1e-14
+
+
+def test_sensor_box_is_the_bounding_box_of_the_gas_and_its_margin():
+    """Gas where phi >= 0 (the level set's sign in this build); a node is
+    tagged where phi >= -d_ref; the box is grown by the margin and clamped
+    to keep one node at each face.  Checked by brute force on a disk."""
+    n = 64
+    J, I = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    phi = 7.2 - np.hypot(I - 30.3, J - 27.6)
+    r = RefineOracle(n, n, (10, 20, 10, 20), 0.7)
+    for d_ref, margin in [(0.0, 0), (3.0, 2), (50.0, 1)]:
+        m = phi >= -d_ref
+        want = (max(1, I[m].min() - margin), min(n - 2, I[m].max() + margin),
+                max(1, J[m].min() - margin), min(n - 2, J[m].max() + margin), 0, 0)
+        assert r.sensor(phi.reshape(-1), d_ref, margin) == want
+    assert r.sensor(np.full(n * n, -1.0), 0.5, 1) is None          # nothing tagged
+    # the gas alone at d_ref = 0: every node of the box's extreme rows is gas
+    box = r.sensor(phi.reshape(-1), 0.0, 0)
+    assert phi[:, box[0]].max() >= 0 and phi[:, box[0] - 1].max() < 0
+
+
+def test_remesh_continues_a_shear_wave():
+    """Re-meshing a decaying shear wave onto a larger patch: the new fine
+    nodes carry the Chapman-Enskog stress of the fine level (the
+    non-equilibrium rescaling at the re-mesh) within 2 %, and the wave keeps
+    decaying at nu k^2 within 1.5 %."""
+    n, tau_c, U = 64, 0.8, 1e-3
+    k = 2 * np.pi / n
+    r = _wave(n, (16, 48, 16, 48), tau_c, lambda x, y: (U * np.cos(k * y), 0 * y))
+    r.step(150)
+    r.remesh((10, 54, 8, 56))
+    fc, ff = r.populations()
+    xf, yf = r.fine_coords()
+    rho, ux, uy = _moments(ff)
+    pxy = (CX[:, None] * CY[:, None] * (ff.reshape(9, -1) - _feq(rho, ux, uy))).sum(0)
+    A = (ux * np.cos(k * yf)).sum() / (np.cos(k * yf) ** 2).sum()
+    expect = (r.tau_f - 1.0) / 3.0 * rho * 0.5 * A * k * np.sin(k * yf)
+    new = ~((xf >= 16) & (xf <= 48) & (yf >= 16) & (yf <= 48)) & (np.abs(np.sin(k * yf)) > 0.5)
+    assert new.sum() > 100
+    assert np.max(np.abs(pxy[new] - expect[new])) < 0.02 * np.max(np.abs(expect[new]))
+    proj = lambda I, J: np.cos(k * J)  # noqa: E731
+    rate = _decay_rate(r, n, 150, proj)
+    assert abs(rate / ((tau_c - 0.5) / 3.0 * k * k) - 1) < 0.015
