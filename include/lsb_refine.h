@@ -54,6 +54,9 @@ typedef struct lsb_ref_params {
                        1 <= ia, ib <= nx - 2, ib - ia >= 2, the same for j and (3D) k;
                        ka, kb ignored for D2Q9 */
   double tau_c;     /* coarse relaxation time, > 1/2 */
+  int max_extent[3]; /* largest patch extents (coarse cells per axis) that lsb_ref_remesh may
+                        choose; 0 or anything below the initial patch's extent keeps that
+                        extent; at most n - 3 */
 } lsb_ref_params;
 
 typedef struct lsb_ref lsb_ref;
@@ -65,8 +68,8 @@ int lsb_ref_create(const lsb_ref_params* params, lsb_ref** out);
 void lsb_ref_destroy(lsb_ref* ref);
 
 /* Device workspace the caller provides: both levels' populations twice
- * (double buffers) and the coarse perimeter's pre-collision sets at two time
- * levels.  The library keeps the pointer; the caller keeps ownership and
+ * (double buffers, the fine level sized for the largest patch) and the
+ * coarse perimeter's pre-collision sets at two time levels.  The library keeps the pointer; the caller keeps ownership and
  * must keep it alive while the handle is used.  LSB_ENOMEM if it is too
  * small. */
 int lsb_ref_workspace_bytes(const lsb_ref* ref, size_t* bytes);
@@ -84,6 +87,28 @@ int lsb_ref_init(lsb_ref* ref, const double* rho_c, const double* u_c, const dou
 /* nsteps coarse steps (2 nsteps fine steps).  LSB_ESTATE before
  * lsb_ref_init. */
 int lsb_ref_step(lsb_ref* ref, int nsteps, void* stream);
+
+/* Level-set refinement sensor (Sec. 3, adaptive mesh refinement): from a
+ * level set on the coarse nodes (device array [nx*ny*nz], negative in the
+ * liquid, >= 0 in the gas: the opposite of the sign the paper's sensor is
+ * written with), the coarse nodes with phi >= -d_ref (the gas and a band of
+ * width d_ref around it) are tagged, and patch (host, 6 ints: ia, ib, ja,
+ * jb, ka, kb; ka = kb = 0 in 2D) receives their bounding box grown by margin
+ * nodes, clamped to keep one node at each grid face and widened to two
+ * cells per axis; the current patch when no node is tagged.  Synchronises
+ * the stream.  LSB_EINVAL for a NULL pointer or a negative margin. */
+int lsb_ref_sensor(lsb_ref* ref, const double* phi, double d_ref, int margin, int* patch, void* stream);
+
+/* Re-meshing onto a new patch (host, 6 ints as above) between coarse steps:
+ * fine nodes inside the old patch keep their populations; the others take
+ * the coarse post-collision populations interpolated like the perimeter's
+ * (the mean of the 2, 4 or 8 coarse nodes around an off-grid node), the
+ * non-equilibrium part scaled by (tau_f - 1) / (2 (tau_c - 1)) about the
+ * equilibrium of the interpolated moments (the equilibrium alone at
+ * tau_c = 1); the new perimeter's pre-collision sets come from inverting
+ * the coarse BGK step.  LSB_EINVAL for a patch outside the grid or larger
+ * than max_extent; LSB_ESTATE before lsb_ref_init. */
+int lsb_ref_remesh(lsb_ref* ref, const int* patch, void* stream);
 
 /* Post-collision populations of both levels into device arrays, [Q][nodes]
  * in the paper's direction ordering (rest direction last): coarse

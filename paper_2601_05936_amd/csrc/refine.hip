@@ -289,6 +289,158 @@ __global__ __launch_bounds__(256) void k_ref_unpad(RefArgs a, int Q, const doubl
   }
 }
 
+// Level-set refinement sensor (Sec. 3, adaptive mesh refinement): coarse
+// nodes in the gas or within d_ref of it are tagged.  The level set here is
+// >= 0 in the gas, the opposite of the sign the sensor is written with, so
+// the test is phi >= -d_ref.  Per block the bounding box of the tagged nodes
+// (lo x, y, z then hi x, y, z; lo = n, hi = -1 when none).
+constexpr int kSensorBlocks = 1024;
+
+__device__ __forceinline__ int block_min(int v, int* sh) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = min(v, __shfl_xor(v, d));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  v = min(min(sh[0], sh[1]), min(sh[2], sh[3]));
+  __syncthreads();
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_ref_sensor(RefArgs a, const double* phi, double d_ref, int* part) {
+  __shared__ int sh[4];
+  // his are reduced as minima of -x (start +1: -1 when nothing is tagged)
+  int v[6] = {a.nx, a.ny, a.nz, 1, 1, 1};
+  for (long n = (long)blockIdx.x * 256 + threadIdx.x; n < a.nc; n += (long)gridDim.x * 256) {
+    if (!(phi[n] >= -d_ref)) continue;
+    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
+    v[0] = min(v[0], x);
+    v[1] = min(v[1], y);
+    v[2] = min(v[2], z);
+    v[3] = min(v[3], -x);
+    v[4] = min(v[4], -y);
+    v[5] = min(v[5], -z);
+  }
+  for (int d = 0; d < 6; ++d) {
+    const int m = block_min(v[d], sh);
+    if (threadIdx.x == 0) part[blockIdx.x * 6 + d] = m;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ref_sensor_final(int nparts, const int* part, int* box) {
+  __shared__ int sh[4];
+  for (int d = 0; d < 6; ++d) {
+    int v = 0x7fffffff;
+    for (int b = threadIdx.x; b < nparts; b += 256) v = min(v, part[b * 6 + d]);
+    v = block_min(v, sh);
+    if (threadIdx.x == 0) box[d] = d < 3 ? v : -v;
+  }
+}
+
+// Re-meshing (state at the end of a coarse step): new fine nodes inside the
+// old patch keep the old fine populations; the others take the coarse
+// post-collision populations interpolated like the perimeter's (the mean of
+// the 2, 4 or 8 coarse nodes around an off-grid node), the non-equilibrium
+// part scaled by (tau_f - 1) / (2 (tau_c - 1)) about the equilibrium of the
+// interpolated moments (the equilibrium alone at tau_c = 1).  Old geometry:
+// o (its fine buffer off).
+template <int LAT>
+__global__ __launch_bounds__(256) void k_ref_remesh_fine(RefArgs a, RefArgs o, const double* off, double* ff) {
+  using L = Lat<LAT>;
+  constexpr int Q = L::Q;
+  const long n1 = (long)(a.mx + 1) * (a.my + 1) * (a.mz + 1);
+  const bool flat = a.tc == 1.0;
+  const double up = flat ? 0.0 : (a.tf - 1.0) / (2.0 * (a.tc - 1.0));
+  for (long n = (long)blockIdx.x * 256 + threadIdx.x; n < n1; n += (long)gridDim.x * 256) {
+    const int i = (int)(n % (a.mx + 1)), j = (int)((n / (a.mx + 1)) % (a.my + 1));
+    const int k = (int)(n / ((long)(a.mx + 1) * (a.my + 1)));
+    const int X2 = 2 * a.ia + i, Y2 = 2 * a.ja + j, Z2 = 2 * a.ka + k;  // twice the coarse-unit position
+    const int oi = X2 - 2 * o.ia, oj = Y2 - 2 * o.ja, ok = Z2 - 2 * o.ka;
+    const long p = fine_index(a, i, j, k);
+    if (oi >= 0 && oi <= o.mx && oj >= 0 && oj <= o.my && ok >= 0 && ok <= o.mz) {
+      const long op = fine_index(o, oi, oj, ok);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) ff[q * a.nf + p] = off[q * o.nf + op];
+      continue;
+    }
+    const int ox = X2 & 1, oy = Y2 & 1, oz = Z2 & 1;
+    const double s = (ox ? 0.5 : 1.0) * (oy ? 0.5 : 1.0) * (oz ? 0.5 : 1.0);
+    double H[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) H[q] = 0.0;
+    for (int dz = 0; dz <= oz; ++dz)
+      for (int dy = 0; dy <= oy; ++dy)
+        for (int dx = 0; dx <= ox; ++dx) {
+          const long m = ((long)((Z2 - oz) / 2 + dz) * a.ny + (Y2 - oy) / 2 + dy) * a.nx + (X2 - ox) / 2 + dx;
+#pragma unroll
+          for (int q = 0; q < Q; ++q) H[q] += s * a.fc_in[q * a.nc + m];
+        }
+    double rho, ux, uy, uz;
+    moments<LAT>(H, rho, ux, uy, uz);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const double e = equilibrium<LAT>(q, rho, ux, uy, uz);
+      ff[q * a.nf + p] = e + up * (H[q] - e);
+    }
+  }
+}
+
+// the new perimeter's pre-collision sets G(t) from the coarse post-collision
+// populations, inverting the BGK step: f_eq + tau_c / (tau_c - 1) (f - f_eq)
+// (f_eq at tau_c = 1)
+template <int LAT>
+__global__ __launch_bounds__(256) void k_ref_remesh_g(RefArgs a, double* g) {
+  using L = Lat<LAT>;
+  constexpr int Q = L::Q;
+  const long nbox = (long)a.bw * a.bh * a.bd;
+  const bool flat = a.tc == 1.0;
+  const double down = flat ? 0.0 : a.tc / (a.tc - 1.0);
+  for (long n = (long)blockIdx.x * 256 + threadIdx.x; n < nbox; n += (long)gridDim.x * 256) {
+    const int I = a.ia + (int)(n % a.bw), J = a.ja + (int)((n / a.bw) % a.bh), K = a.ka + (int)(n / ((long)a.bw * a.bh));
+    if (covered(a, I, J, K)) continue;
+    const long m = ((long)K * a.ny + J) * a.nx + I;
+    double f[Q], v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) f[q] = a.fc_in[q * a.nc + m];
+    double rho, ux, uy, uz;
+    moments<LAT>(f, rho, ux, uy, uz);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const double e = equilibrium<LAT>(q, rho, ux, uy, uz);
+      v[q] = e + down * (f[q] - e);
+    }
+    store_faces<Q>(a, g, I, J, K, v);
+  }
+}
+
+// derived geometry of a patch (ia, ib, ja, jb, ka, kb)
+void set_patch(RefArgs& a, const int* patch) {
+  const bool three = a.D == 3;
+  a.ia = patch[0];
+  a.ib = patch[1];
+  a.ja = patch[2];
+  a.jb = patch[3];
+  a.ka = three ? patch[4] : 0;
+  a.kb = three ? patch[5] : 0;
+  a.mx = 2 * (a.ib - a.ia);
+  a.my = 2 * (a.jb - a.ja);
+  a.mz = 2 * (a.kb - a.ka);
+  a.bw = a.ib - a.ia + 1;
+  a.bh = a.jb - a.ja + 1;
+  a.bd = a.kb - a.ka + 1;
+  a.fw = a.mx + 3;
+  a.fh = a.my + 3;
+  a.nf = (long)a.fw * a.fh * (three ? a.mz + 3 : 1);
+  // face sizes: x faces bh x bd, y faces bw x bd, z faces (3D) bw x bh
+  const long sz[6] = {(long)a.bh * a.bd, (long)a.bh * a.bd, (long)a.bw * a.bd, (long)a.bw * a.bd,
+                      three ? (long)a.bw * a.bh : 0L, three ? (long)a.bw * a.bh : 0L};
+  long o = 0;
+  for (int f = 0; f < 6; ++f) {
+    a.fo[f] = o;
+    o += sz[f];
+  }
+  a.nb = o;
+}
+
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 int fail(int code, const std::string& msg) {
@@ -304,6 +456,9 @@ struct lsb_ref {
   lsb_ref_params P;
   RefArgs base;
   int Q = 9;
+  int ext[3] = {0, 0, 0};  // largest patch extents (coarse cells per axis) the workspace holds
+  long fcap = 0, bcap = 0;  // fine nodes with the shell, box-surface nodes, at those extents
+  int* sens = nullptr;      // sensor partial boxes (kSensorBlocks x 6) and the reduced box (6)
   char* ws = nullptr;
   size_t ws_bytes = 0;
   double* fc[2] = {nullptr, nullptr};
@@ -316,9 +471,9 @@ struct lsb_ref {
 namespace {
 size_t sizes(const lsb_ref* r, size_t* fcb, size_t* ffb, size_t* gb) {
   *fcb = align256(sizeof(double) * r->Q * (size_t)r->base.nc);
-  *ffb = align256(sizeof(double) * r->Q * (size_t)r->base.nf);
-  *gb = align256(sizeof(double) * r->Q * (size_t)r->base.nb);
-  return 2 * (*fcb + *ffb + *gb);
+  *ffb = align256(sizeof(double) * r->Q * (size_t)r->fcap);
+  *gb = align256(sizeof(double) * r->Q * (size_t)r->bcap);
+  return 2 * (*fcb + *ffb + *gb) + align256(sizeof(int) * 6 * (kSensorBlocks + 1));
 }
 
 int check_launch() {
@@ -385,47 +540,32 @@ int lsb_ref_create(const lsb_ref_params* P, lsb_ref** out) {
       (three && (ka < 1 || kb > nz - 2 || kb - ka < 2)))
     return fail(LSB_EINVAL, "patch must lie inside the coarse grid with one node to spare and span >= 2 cells per axis");
   if (!(P->tau_c > 0.5)) return fail(LSB_EINVAL, "tau_c must exceed 1/2");
-  const long mx = 2L * (ib - ia), my = 2L * (jb - ja), mz = 2L * (kb - ka);
-  if ((long)nx * ny * nz > (1L << 31) || (mx + 3) * (my + 3) * (three ? mz + 3 : 1) > (1L << 31))
-    return fail(LSB_EINVAL, "grid too large");
+  if ((long)nx * ny * nz > (1L << 31)) return fail(LSB_EINVAL, "grid too large");
+  int ext[3] = {ib - ia, jb - ja, three ? kb - ka : 0};
+  for (int d = 0; d < (three ? 3 : 2); ++d) {
+    const int n = d == 0 ? nx : (d == 1 ? ny : nz);
+    if (P->max_extent[d] < 0 || P->max_extent[d] > n - 3) return fail(LSB_EINVAL, "max_extent outside [0, n - 3]");
+    if (P->max_extent[d] > ext[d]) ext[d] = P->max_extent[d];
+  }
+  const long cap = (2L * ext[0] + 3) * (2L * ext[1] + 3) * (three ? 2L * ext[2] + 3 : 1);
+  if (cap > (1L << 31)) return fail(LSB_EINVAL, "grid too large");
   lsb_ref* r = new lsb_ref();
   r->P = *P;
   r->Q = q_of(P->lattice);
+  for (int d = 0; d < 3; ++d) r->ext[d] = ext[d];
+  r->fcap = cap;
+  r->bcap = 2L * (ext[1] + 1) * (ext[2] + 1) + 2L * (ext[0] + 1) * (ext[2] + 1) +
+            (three ? 2L * (ext[0] + 1) * (ext[1] + 1) : 0L);
   RefArgs& a = r->base;
   a = RefArgs{};
   a.D = three ? 3 : 2;
   a.nx = nx;
   a.ny = ny;
   a.nz = nz;
-  a.ia = ia;
-  a.ib = ib;
-  a.ja = ja;
-  a.jb = jb;
-  a.ka = ka;
-  a.kb = kb;
-  a.mx = (int)mx;
-  a.my = (int)my;
-  a.mz = (int)mz;
-  a.bw = ib - ia + 1;
-  a.bh = jb - ja + 1;
-  a.fw = a.mx + 3;
-  a.fh = a.my + 3;
   a.nc = (long)nx * ny * nz;
-  a.nf = (long)a.fw * a.fh * (three ? a.mz + 3 : 1);
-  a.bd = kb - ka + 1;
-  {
-    // face sizes: x faces bh x bd, y faces bw x bd, z faces (3D) bw x bh
-    const long sz[6] = {(long)a.bh * a.bd, (long)a.bh * a.bd, (long)a.bw * a.bd, (long)a.bw * a.bd,
-                        three ? (long)a.bw * a.bh : 0L, three ? (long)a.bw * a.bh : 0L};
-    long o = 0;
-    for (int f = 0; f < 6; ++f) {
-      a.fo[f] = o;
-      o += sz[f];
-    }
-    a.nb = o;
-  }
   a.tc = P->tau_c;
   a.tf = 2.0 * P->tau_c - 0.5;
+  set_patch(a, P->patch);
   *out = r;
   return LSB_OK;
 }
@@ -452,6 +592,7 @@ int lsb_ref_bind(lsb_ref* r, void* ws, size_t bytes) {
     r->g[k] = reinterpret_cast<double*>(p);
     p += gb;
   }
+  r->sens = reinterpret_cast<int*>(p);
   r->ws = static_cast<char*>(ws);
   r->ws_bytes = bytes;
   r->inited = false;
@@ -500,6 +641,82 @@ int lsb_ref_get_populations(lsb_ref* r, double* coarse, double* fine, void* stre
     k_ref_unpad<<<grid_for(r->Q * n1), 256, 0, st>>>(b, r->Q, r->ff[0], fine);
     if (int e = check_launch()) return e;
   }
+  return LSB_OK;
+}
+
+int lsb_ref_sensor(lsb_ref* r, const double* phi, double d_ref, int margin, int* patch, void* stream) {
+  if (!r || !phi || !patch) return fail(LSB_EINVAL, "null pointer");
+  if (!r->ws) return fail(LSB_ESTATE, "lsb_ref_sensor before lsb_ref_bind");
+  if (margin < 0) return fail(LSB_EINVAL, "negative margin");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const RefArgs& a = r->base;
+  k_ref_sensor<<<kSensorBlocks, 256, 0, st>>>(a, phi, d_ref, r->sens);
+  k_ref_sensor_final<<<1, 256, 0, st>>>(kSensorBlocks, r->sens, r->sens + 6 * kSensorBlocks);
+  if (int e = check_launch()) return e;
+  int box[6];
+  if (hipMemcpyAsync(box, r->sens + 6 * kSensorBlocks, sizeof(box), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(LSB_EDEVICE, "sensor read-back failed");
+  const int cur[6] = {a.ia, a.ib, a.ja, a.jb, a.ka, a.kb};
+  if (box[0] >= a.nx) {  // nothing tagged: the patch stays
+    for (int d = 0; d < 6; ++d) patch[d] = cur[d];
+    return LSB_OK;
+  }
+  const int n[3] = {a.nx, a.ny, a.nz};
+  int out[6] = {0, 0, 0, 0, 0, 0};
+  for (int d = 0; d < a.D; ++d) {
+    int lo = box[d] - margin, hi = box[3 + d] + margin;
+    if (lo < 1) lo = 1;
+    if (hi > n[d] - 2) hi = n[d] - 2;
+    while (hi - lo < 2) {  // at least two cells (n >= 5 holds: the grid took a valid patch)
+      if (hi < n[d] - 2) ++hi;
+      else --lo;
+    }
+    out[2 * d] = lo;
+    out[2 * d + 1] = hi;
+  }
+  for (int d = 0; d < 6; ++d) patch[d] = out[d];
+  return LSB_OK;
+}
+
+int lsb_ref_remesh(lsb_ref* r, const int* patch, void* stream) {
+  if (!r || !patch) return fail(LSB_EINVAL, "null pointer");
+  if (!r->inited) return fail(LSB_ESTATE, "lsb_ref_remesh before lsb_ref_init");
+  const RefArgs& b = r->base;
+  const int n[3] = {b.nx, b.ny, b.nz};
+  for (int d = 0; d < b.D; ++d) {
+    const int lo = patch[2 * d], hi = patch[2 * d + 1];
+    if (lo < 1 || hi > n[d] - 2 || hi - lo < 2)
+      return fail(LSB_EINVAL, "patch must lie inside the coarse grid with one node to spare and span >= 2 cells per axis");
+    if (hi - lo > r->ext[d]) return fail(LSB_EINVAL, "patch larger than the workspace's maximum extents");
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const RefArgs o = b;
+  RefArgs a = b;
+  set_patch(a, patch);
+  a.fc_in = r->fc[r->cur];
+  const long n1 = (long)(a.mx + 1) * (a.my + 1) * (a.mz + 1), nbox = (long)a.bw * a.bh * a.bd;
+  switch (r->P.lattice) {
+    case LSB_D2Q9:
+      k_ref_remesh_fine<LSB_D2Q9><<<grid_for(n1), 256, 0, st>>>(a, o, r->ff[0], r->ff[1]);
+      k_ref_remesh_g<LSB_D2Q9><<<grid_for(nbox), 256, 0, st>>>(a, r->g[r->cur]);
+      break;
+    case LSB_D3Q19:
+      k_ref_remesh_fine<LSB_D3Q19><<<grid_for(n1), 256, 0, st>>>(a, o, r->ff[0], r->ff[1]);
+      k_ref_remesh_g<LSB_D3Q19><<<grid_for(nbox), 256, 0, st>>>(a, r->g[r->cur]);
+      break;
+    default:
+      k_ref_remesh_fine<LSB_D3Q27><<<grid_for(n1), 256, 0, st>>>(a, o, r->ff[0], r->ff[1]);
+      k_ref_remesh_g<LSB_D3Q27><<<grid_for(nbox), 256, 0, st>>>(a, r->g[r->cur]);
+      break;
+  }
+  if (int e = check_launch()) return e;
+  double* t = r->ff[0];
+  r->ff[0] = r->ff[1];
+  r->ff[1] = t;
+  a.fc_in = nullptr;
+  r->base = a;
+  for (int d = 0; d < 6; ++d) r->P.patch[d] = b.D == 3 || d < 4 ? patch[d] : 0;
   return LSB_OK;
 }
 

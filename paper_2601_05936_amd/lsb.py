@@ -52,14 +52,14 @@ EXPORTS = [
     "lsb_adjoint_record", "lsb_adjoint_seed_centroid", "lsb_adjoint_reverse", "lsb_adjoint_initial",
     "lsb_last_error",
     "lsb_ref_create", "lsb_ref_destroy", "lsb_ref_workspace_bytes", "lsb_ref_bind", "lsb_ref_init", "lsb_ref_step",
-    "lsb_ref_get_populations",
+    "lsb_ref_get_populations", "lsb_ref_sensor", "lsb_ref_remesh",
 ]
 
 
 class RefParams(C.Structure):
     """Mirror of lsb_ref_params (include/lsb_refine.h)."""
     _fields_ = [("lattice", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("patch", C.c_int * 6),
-                ("tau_c", C.c_double)]
+                ("tau_c", C.c_double), ("max_extent", C.c_int * 3)]
 SCHED_SERIAL, SCHED_OVERLAP = 0, 1
 MAX_BUBBLES = 64  # LSB_MAX_BUBBLES
 
@@ -115,6 +115,8 @@ def load() -> C.CDLL:
     lib.lsb_ref_init.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.lsb_ref_step.argtypes = [vp, C.c_int, vp]
     lib.lsb_ref_get_populations.argtypes = [vp, vp, vp, vp]
+    lib.lsb_ref_sensor.argtypes = [vp, vp, C.c_double, C.c_int, C.POINTER(C.c_int), vp]
+    lib.lsb_ref_remesh.argtypes = [vp, C.POINTER(C.c_int), vp]
     _lib = lib
     return lib
 
@@ -331,7 +333,8 @@ class Refine:
     Device memory is a torch uint8 tensor (the caller-owned workspace);
     calls run on torch's current stream."""
 
-    def __init__(self, nx: int, ny: int, patch, tau_c: float, device="cuda:0", lattice: int = D2Q9, nz: int = 1):
+    def __init__(self, nx: int, ny: int, patch, tau_c: float, device="cuda:0", lattice: int = D2Q9, nz: int = 1,
+                 max_extent=(0, 0, 0)):
         import torch
         self.torch = torch
         self.lib = load()
@@ -345,7 +348,8 @@ class Refine:
         self.mx, self.my, self.mz = 2 * (ib - ia), 2 * (jb - ja), 2 * (kb - ka)
         self.n_coarse = self.nx * self.ny * self.nz
         self.n_fine = (self.mx + 1) * (self.my + 1) * (self.mz + 1)
-        self._cp = RefParams(self.lattice, self.nx, self.ny, self.nz, (C.c_int * 6)(*self.patch), float(tau_c))
+        self._cp = RefParams(self.lattice, self.nx, self.ny, self.nz, (C.c_int * 6)(*self.patch), float(tau_c),
+                             (C.c_int * 3)(*[int(v) for v in max_extent]))
         h = C.c_void_p()
         _check(self.lib.lsb_ref_create(C.byref(self._cp), C.byref(h)))
         self.h = h
@@ -378,6 +382,26 @@ class Refine:
 
     def step(self, n: int = 1):
         _check(self.lib.lsb_ref_step(self.h, int(n), self.stream()))
+        return self
+
+    def sensor(self, phi, d_ref: float, margin: int):
+        """Patch box (6 ints) of the level-set sensor on the coarse level set
+        phi [n_coarse] (numpy or torch); the current patch when no node is
+        tagged."""
+        t_phi = self._dev(phi, self.n_coarse)
+        out = (C.c_int * 6)()
+        _check(self.lib.lsb_ref_sensor(self.h, C.c_void_p(t_phi.data_ptr()), float(d_ref), int(margin), out,
+                                       self.stream()))
+        return tuple(out)
+
+    def remesh(self, patch):
+        """Re-mesh onto patch (6 ints; ka, kb ignored in 2D)."""
+        p = (tuple(int(v) for v in patch) + (0, 0))[:6]
+        _check(self.lib.lsb_ref_remesh(self.h, (C.c_int * 6)(*p), self.stream()))
+        ia, ib, ja, jb, ka, kb = p if self.D == 3 else p[:4] + (0, 0)
+        self.patch = (ia, ib, ja, jb, ka, kb)
+        self.mx, self.my, self.mz = 2 * (ib - ia), 2 * (jb - ja), 2 * (kb - ka)
+        self.n_fine = (self.mx + 1) * (self.my + 1) * (self.mz + 1)
         return self
 
     def populations(self, as_numpy=True):

@@ -109,7 +109,8 @@ def test_reverse_mode_rejects_per_bubble_baselines():
 def _ref_create(**kw):
     p = dict(lattice=lsb.D2Q9, nx=32, ny=24, nz=1, patch=(8, 20, 6, 16, 0, 0), tau_c=0.7)
     p.update(kw)
-    cp = lsb.RefParams(p["lattice"], p["nx"], p["ny"], p["nz"], (C.c_int * 6)(*p["patch"]), p["tau_c"])
+    cp = lsb.RefParams(p["lattice"], p["nx"], p["ny"], p["nz"], (C.c_int * 6)(*p["patch"]), p["tau_c"],
+                       (C.c_int * 3)(*p.get("max_extent", (0, 0, 0))))
     h = C.c_void_p()
     rc = lsb.load().lsb_ref_create(C.byref(cp), C.byref(h))
     return rc, h
@@ -122,6 +123,7 @@ def _ref_create(**kw):
     dict(tau_c=0.5),
     dict(lattice=lsb.D3Q27, nz=16, patch=(8, 20, 6, 16, 0, 9)),                 # 3D: ka < 1
     dict(lattice=lsb.D3Q19, nz=3, patch=(8, 20, 6, 16, 1, 2)),                  # 3D: nz < 4
+    dict(max_extent=(30, 0, 0)),                                                # beyond n - 3
 ])
 def test_refine_create_rejects_invalid_parameters(bad):
     rc, h = _ref_create(**bad)
@@ -131,7 +133,8 @@ def test_refine_create_rejects_invalid_parameters(bad):
 
 def test_refine_workspace_layout():
     """Workspace = 2 x (coarse + fine with a one-node ghost shell + the box
-    surface), Q doubles per node, each part aligned to 256 bytes."""
+    surface), Q doubles per node, each part aligned to 256 bytes, sized for
+    the largest patch, plus the sensor's partial boxes."""
     def up(v):
         return (v + 255) // 256 * 256
     lib = lsb.load()
@@ -151,6 +154,6 @@ def test_refine_workspace_layout():
             bw, bh, bd = ib - ia + 1, jb - ja + 1, kb - ka + 1
             nf = (mx + 3) * (my + 3) * (mz + 3)
             ns = 2 * bh * bd + 2 * bw * bd + 2 * bw * bh
-        assert nb.value == 2 * (up(8 * Q * nc) + up(8 * Q * nf) + up(8 * Q * ns))
+        assert nb.value == 2 * (up(8 * Q * nc) + up(8 * Q * nf) + up(8 * Q * ns)) + up(4 * 6 * 1025)
         assert lib.lsb_ref_bind(h, C.c_void_p(1 << 20), nb.value - 1) == lsb.LSB_ENOMEM
         lib.lsb_ref_destroy(h)

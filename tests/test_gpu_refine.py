@@ -139,3 +139,65 @@ def test_refine_3d_benchmark_configuration(require_gpu):
     ec, ef = np.max(np.abs(gc - oc)), np.max(np.abs(gf - of))
     print(f"refine D3Q27 192^3: coarse {ec:.2e} fine {ef:.2e}", flush=True)
     assert ec <= TOL and ef <= TOL
+
+
+# --- level-set sensor and re-meshing ---
+
+@pytest.mark.parametrize("lattice,n3,patch,max_ext,steps", [
+    (0, (64, 56, 1), (20, 30, 18, 28), (50, 50, 0), 6),
+    (2, (30, 28, 26), (10, 16, 9, 15, 8, 14), (24, 24, 22), 4),
+])
+def test_refine_sensor_and_remesh_match_oracle(require_gpu, lattice, n3, patch, max_ext, steps):
+    """Steps, the level-set sensor on a gas sphere (box compared with the
+    oracle's), re-meshing onto it, more steps, then a shrunk and shifted
+    patch; both levels against the oracle after each phase."""
+    from paper_2601_05936_amd.lsb import Refine
+    nx, ny, nz = n3
+    if lattice == 0:
+        rc, uc, rf, uf = _fields(nx, ny, patch, seed=5)
+        o = RefineOracle(nx, ny, patch, 0.7)
+        g = Refine(nx, ny, patch, 0.7, max_extent=max_ext)
+        J, I = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+        phi = 9.5 - np.hypot(I - 33.2, J - 24.7)
+    else:
+        rc, uc, rf, uf = _fields3(n3, lattice, patch, seed=6)
+        o = RefineOracle(nx, ny, patch, 0.7, lattice=lattice, nz=nz)
+        g = Refine(nx, ny, patch, 0.7, lattice=lattice, nz=nz, max_extent=max_ext)
+        K, J, I = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        phi = 5.5 - np.sqrt((I - 14.6) ** 2 + (J - 13.2) ** 2 + (K - 12.9) ** 2)
+    o.init(rc, uc, rf, uf)
+    g.init(rc, uc, rf, uf)
+
+    def check(label):
+        (oc, of), (gc, gf) = o.populations(), g.populations()
+        ec, ef = np.max(np.abs(gc - oc)), np.max(np.abs(gf - of))
+        print(f"remesh D={g.D} {label}: coarse {ec:.2e} fine {ef:.2e}", flush=True)
+        assert gf.shape == of.shape and ec <= TOL and ef <= TOL
+
+    o.step(steps)
+    g.step(steps)
+    check("before")
+    box = g.sensor(phi.reshape(-1), 2.0, 1)
+    assert box == o.sensor(phi.reshape(-1), 2.0, 1)
+    assert box[:4] != tuple(patch[:4])
+    o.remesh(box)
+    g.remesh(box)
+    check("re-meshed")
+    o.step(steps)
+    g.step(steps)
+    check("after")
+    small = tuple(v + (1 if d % 2 == 0 else -2) for d, v in enumerate(box[:2 * g.D]))
+    o.remesh(small)
+    g.remesh(small)
+    o.step(steps)
+    g.step(steps)
+    check("shrunk")
+
+
+def test_refine_remesh_rejects_patches_beyond_the_workspace(require_gpu):
+    from paper_2601_05936_amd.lsb import LsbError, Refine
+    g = Refine(40, 40, (10, 20, 10, 20), 0.7, max_extent=(14, 14, 0))
+    g.init(np.ones(g.n_coarse), np.zeros(2 * g.n_coarse), np.ones(g.n_fine), np.zeros(2 * g.n_fine))
+    with pytest.raises(LsbError):
+        g.remesh((5, 20, 10, 20))      # 15 cells in x > 14
+    g.remesh((6, 20, 10, 24))          # 14 x 14 fits
