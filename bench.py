@@ -280,8 +280,8 @@ def main():
                          "cluster (320x640x320, FP16-deviation, cumulant gas, one gas baseline per bubble)")
     ap.add_argument("--schedule", default="auto", choices=["auto", "serial", "overlap"],
                     help="step schedule: one stream, the bulk collide-stream overlapped on a second stream, or "
-                         "auto (the faster on this workload: serial for FP16-deviation with BGK, where the two tie, "
-                         "overlap otherwise)")
+                         "auto (the faster on this workload, measured: serial for FP16-deviation storage, overlap "
+                         "for FP32 and FP64)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="reverse-mode run length (0: skip)")
     ap.add_argument("--refine-steps", type=int, default=100,
@@ -301,7 +301,7 @@ def main():
     from paper_2601_05936_amd.workloads import F16DEV, F32, F64
     def sched_of(mode):
         if args.schedule == "auto":
-            return "serial" if mode == "f16dev" else "overlap"
+            return "serial" if mode.startswith("f16dev") else "overlap"
         return args.schedule
     names = {"f16dev": F16DEV, "f32": F32, "f64": F64}
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
