@@ -121,6 +121,11 @@ def _load():
     lib.orc_ref_get.argtypes = [C.c_void_p, dp, dp]
     lib.orc_ref_sensor.argtypes = [C.c_void_p, dp, C.c_double, C.c_int, C.POINTER(C.c_int)]
     lib.orc_ref_remesh.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
+    lib.orc_mref_create.restype = C.c_void_p
+    lib.orc_mref_create.argtypes = [C.c_int, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int), C.c_double,
+                                    C.POINTER(C.c_double)]
+    lib.orc_mref_init.argtypes = [C.c_void_p, C.POINTER(dp), C.POINTER(dp)]
+    lib.orc_mref_get.argtypes = [C.c_void_p, C.c_int, dp]
     _lib = lib
     return lib
 
@@ -371,14 +376,18 @@ class TangentOracle:
 
 
 class RefineOracle:
-    """Two-level static refinement of the BGK solver (ratio 2), FP64.
+    """Static refinement of the BGK solver (ratio 2), FP64, two to four
+    nested levels.
 
     lattice 0 (D2Q9), 1 (D3Q19) or 2 (D3Q27).  Coarse nodes nx x ny (x nz),
-    periodic; the fine patch covers the coarse nodes patch = (ia, ib, ja, jb)
-    (+ (ka, kb) in 3D), inclusive, at half spacing, fine node (i, j, k) at
-    (ia + i/2, ja + j/2, ka + k/2).  Populations are [Q][nodes] (x fastest),
-    the paper's ordering; velocities [nodes][D].  tau_f = None takes
-    2 tau_c - 1/2 (constant viscosity); the tests pass another value only to
+    periodic.  patch is one box (ia, ib, ja, jb) (+ (ka, kb) in 3D), the
+    coarse nodes the fine level covers, inclusive, at half spacing (fine node
+    (i, j, k) at (ia + i/2, ja + j/2, ka + k/2)); or a list of such boxes,
+    level 1 first, each in its parent level's node coordinates.  Populations
+    are [Q][nodes] (x fastest), the paper's ordering; velocities [nodes][D].
+    tau_f = None takes 2 tau - 1/2 from level to level (constant viscosity);
+    a number overrides level 1's, a list (one entry per refined level, None
+    for the derived value) any level's: the tests pass other values only to
     plant a mistake.
     """
 
@@ -387,41 +396,93 @@ class RefineOracle:
         self.lattice = int(lattice)
         self.D, self.Q = (2, 9) if self.lattice == 0 else (3, 19 if self.lattice == 1 else 27)
         self.nx, self.ny, self.nz = int(nx), int(ny), (int(nz) if self.D == 3 else 1)
-        p = tuple(int(v) for v in patch)
-        self.patch = p if self.D == 3 else p[:4]
-        ia, ib, ja, jb = p[:4]
-        ka, kb = (p[4], p[5]) if self.D == 3 else (0, 0)
-        self.mx, self.my, self.mz = 2 * (ib - ia), 2 * (jb - ja), 2 * (kb - ka)
-        self.tau_c = float(tau_c)
-        self.tau_f = 2.0 * tau_c - 0.5 if tau_f is None else float(tau_f)
+        boxes = [patch] if np.isscalar(patch[0]) else list(patch)
+        self.boxes = []
+        for bx in boxes:
+            p = tuple(int(v) for v in bx)
+            self.boxes.append(p[:6] if self.D == 3 else p[:4] + (0, 0))
+        self.levels = len(self.boxes) + 1
+        over = [None] * (self.levels - 1)
+        if tau_f is not None:
+            if np.isscalar(tau_f):
+                over[0] = float(tau_f)
+            else:
+                over = [None if t is None else float(t) for t in tau_f]
+        self.taus = [float(tau_c)]
+        for l in range(1, self.levels):
+            self.taus.append(2.0 * self.taus[-1] - 0.5 if over[l - 1] is None else over[l - 1])
         n3 = (C.c_int * 3)(self.nx, self.ny, self.nz)
-        p6 = (C.c_int * 6)(ia, ib, ja, jb, ka, kb)
-        self._h = lib.orc_ref_create(self.lattice, n3, p6, self.tau_c, self.tau_f)
+        flat = [v for bx in self.boxes for v in bx]
+        pp = (C.c_int * len(flat))(*flat)
+        tt = (C.c_double * self.levels)(*self.taus)
+        self._h = lib.orc_mref_create(self.lattice, n3, self.levels, pp, float(tau_c), tt)
         if not self._h:
             raise ValueError("invalid refinement configuration")
         self._lib = lib
+        self._sync_level1()
+
+    def _sync_level1(self):
+        ia, ib, ja, jb, ka, kb = self.boxes[0]
+        self.patch = self.boxes[0] if self.D == 3 else self.boxes[0][:4]
+        self.mx, self.my, self.mz = 2 * (ib - ia), 2 * (jb - ja), 2 * (kb - ka)
+
+    @property
+    def tau_c(self) -> float:
+        return self.taus[0]
+
+    @property
+    def tau_f(self) -> float:
+        return self.taus[1]
+
+    def shape(self, level: int):
+        """Nodes per axis (x, y, z) of a level."""
+        if level == 0:
+            return self.nx, self.ny, self.nz
+        ia, ib, ja, jb, ka, kb = self.boxes[level - 1]
+        return 2 * (ib - ia) + 1, 2 * (jb - ja) + 1, 2 * (kb - ka) + 1
+
+    def n_level(self, level: int) -> int:
+        return int(np.prod(self.shape(level)))
 
     @property
     def n_coarse(self) -> int:
-        return self.nx * self.ny * self.nz
+        return self.n_level(0)
 
     @property
     def n_fine(self) -> int:
-        return (self.mx + 1) * (self.my + 1) * (self.mz + 1)
+        return self.n_level(1)
 
-    def fine_coords(self):
-        """Coarse-unit coordinates of the fine nodes, [n_fine] each: (x, y) in
-        2D, (x, y, z) in 3D."""
-        ia, ja = self.patch[0], self.patch[2]
-        ka = self.patch[4] if self.D == 3 else 0
-        k, j, i = np.meshgrid(np.arange(self.mz + 1), np.arange(self.my + 1), np.arange(self.mx + 1), indexing="ij")
-        xyz = (ia + 0.5 * i.reshape(-1), ja + 0.5 * j.reshape(-1), ka + 0.5 * k.reshape(-1))
+    def coords(self, level: int):
+        """Coarse-unit coordinates of a level's nodes, [nodes] each: (x, y)
+        in 2D, (x, y, z) in 3D."""
+        o, h = np.zeros(3), 1.0
+        for l in range(1, level + 1):
+            bx = self.boxes[l - 1]
+            o = o + h * np.array([bx[0], bx[2], bx[4]], dtype=float)
+            h *= 0.5
+        sx, sy, sz = self.shape(level)
+        k, j, i = np.meshgrid(np.arange(sz), np.arange(sy), np.arange(sx), indexing="ij")
+        xyz = (o[0] + h * i.reshape(-1), o[1] + h * j.reshape(-1), o[2] + h * k.reshape(-1))
         return xyz[:self.D]
 
-    def init(self, rho_c, u_c, rho_f, u_f):
-        self._keep = [_f64(rho_c, self.n_coarse), _f64(u_c, self.D * self.n_coarse), _f64(rho_f, self.n_fine),
-                      _f64(u_f, self.D * self.n_fine)]
-        self._lib.orc_ref_init(self._h, *[_dp(a) for a in self._keep])
+    def fine_coords(self):
+        """Coarse-unit coordinates of level 1's nodes."""
+        return self.coords(1)
+
+    def init(self, rho_c, u_c, rho_f, u_f, *deeper):
+        """Equilibrium state from rho and u on every level: the coarse and
+        level-1 arrays, then (rho, u) of each deeper level."""
+        arrs = [rho_c, u_c, rho_f, u_f] + list(deeper)
+        if len(arrs) != 2 * self.levels:
+            raise ValueError("one (rho, u) pair per level expected")
+        self._keep = []
+        for l in range(self.levels):
+            n = self.n_level(l)
+            self._keep += [_f64(arrs[2 * l], n), _f64(arrs[2 * l + 1], self.D * n)]
+        dpt = C.POINTER(C.c_double)
+        rho = (dpt * self.levels)(*[_dp(self._keep[2 * l]) for l in range(self.levels)])
+        u = (dpt * self.levels)(*[_dp(self._keep[2 * l + 1]) for l in range(self.levels)])
+        self._lib.orc_mref_init(self._h, rho, u)
         return self
 
     def step(self, n: int = 1):
@@ -438,7 +499,8 @@ class RefineOracle:
         return tuple(out)
 
     def remesh(self, patch):
-        """Re-mesh onto patch (6 ints; ka, kb ignored in 2D)."""
+        """Re-mesh a two-level hierarchy onto patch (6 ints; ka, kb ignored in
+        2D)."""
         p = tuple(int(v) for v in patch) + (0, 0)
         p6 = (C.c_int * 6)(*p[:6])
         if self._lib.orc_ref_remesh(self._h, p6) != 0:
@@ -446,18 +508,21 @@ class RefineOracle:
         ia, ib, ja, jb, ka, kb = p[:6]
         if self.D == 2:
             ka = kb = 0
-        self.patch = (ia, ib, ja, jb, ka, kb) if self.D == 3 else (ia, ib, ja, jb)
-        self.mx, self.my, self.mz = 2 * (ib - ia), 2 * (jb - ja), 2 * (kb - ka)
+        self.boxes[0] = (ia, ib, ja, jb, ka, kb)
+        self._sync_level1()
         return self
 
+    def level(self, l: int):
+        """Post-collision populations of level l, [Q][(nz,) ny, nx]."""
+        sx, sy, sz = self.shape(l)
+        f = np.zeros(self.Q * sx * sy * sz)
+        self._lib.orc_mref_get(self._h, int(l), _dp(f))
+        return f.reshape(self.Q, sy, sx) if self.D == 2 else f.reshape(self.Q, sz, sy, sx)
+
     def populations(self):
-        fc = np.zeros(self.Q * self.n_coarse)
-        ff = np.zeros(self.Q * self.n_fine)
-        self._lib.orc_ref_get(self._h, _dp(fc), _dp(ff))
-        if self.D == 2:
-            return fc.reshape(self.Q, self.ny, self.nx), ff.reshape(self.Q, self.my + 1, self.mx + 1)
-        return (fc.reshape(self.Q, self.nz, self.ny, self.nx),
-                ff.reshape(self.Q, self.mz + 1, self.my + 1, self.mx + 1))
+        """Post-collision populations of every level (coarse first); the
+        covered nodes hold the restricted values."""
+        return tuple(self.level(l) for l in range(self.levels))
 
     def __del__(self):
         if getattr(self, "_h", None):

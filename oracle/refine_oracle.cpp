@@ -1,5 +1,5 @@
-// CPU oracle: two-level static grid refinement of the lattice Boltzmann
-// solver (D2Q9, D3Q19, D3Q27; BGK, FP64), ratio 2.  Test infrastructure only: the tests,
+// CPU oracle: static grid refinement of the lattice Boltzmann solver (D2Q9,
+// D3Q19, D3Q27; BGK, FP64), ratio 2, two or more nested levels.  Test infrastructure only: the tests,
 // the smoke check and the benchmark's CPU-baseline leg call it; the product
 // path never does.
 //
@@ -34,6 +34,15 @@
 //              fine pre-collision non-equilibrium part scaled back by
 //              2 tau_c / tau_f, then collided with tau_c, which is
 //              f_eq + 2 (tau_c - 1) / tau_f (f - f_eq).
+//   nesting    a level may hold a finer patch of its own, a box of its own
+//              nodes with one node to spare at each side; every pair of
+//              adjacent levels is coupled as above (tau doubles minus 1/2
+//              from level to level), and a level's sub-step is followed by
+//              its child's two sub-steps, the second of which restricts
+//              into the level's new populations.  A level restricts into
+//              its parent from its own pre-collision populations, which at
+//              nodes covered by its child come from the child's restriction
+//              (the levels hand their data down one jump at a time).
 #include <cmath>
 #include <vector>
 
@@ -43,22 +52,24 @@ extern "C" int orc_lattice(int lattice, int* D, int* Q, int* c, double* w, int* 
 namespace ref {
 
 constexpr int QMAX = 27;
+constexpr int LMAX = 4;
 
-struct Ref {
-  int D = 2, Q = 9;
-  int cx[QMAX], cy[QMAX], cz[QMAX];
-  double w[QMAX];
-  int nx, ny, nz, ia, ib, ja, jb, ka, kb, mx, my, mz;
-  double tc, tf;
-  std::vector<double> fc, ff;  // post-collision populations [q][node], x fastest
-  std::vector<double> g0, g1;  // coarse pre-collision populations over the patch box, times t and t+1
+// one grid level: nodes (i, j, k), i in [0, mx], and for a refined level its
+// box [ia, ib] x [ja, jb] (x [ka, kb]) in the parent's node coordinates, node
+// (i, j, k) sitting at the parent's (ia + i/2, ja + j/2, ka + k/2)
+struct Level {
+  int D = 2;
+  int mx = 0, my = 0, mz = 0;
+  int ia = 0, ib = 0, ja = 0, jb = 0, ka = 0, kb = 0;
+  double tau = 1.0;
+  std::vector<double> f;       // post-collision populations [q][node], x fastest
+  std::vector<double> g0, g1;  // the parent's pre-collision sets over the box, times t and t + 1
 
-  long nc() const { return (long)nx * ny * nz; }
-  long nf() const { return (long)(mx + 1) * (my + 1) * (mz + 1); }
+  long n() const { return (long)(mx + 1) * (my + 1) * (mz + 1); }
+  long idx(int i, int j, int k) const { return ((long)k * (my + 1) + j) * (mx + 1) + i; }
   long nb() const { return (long)(ib - ia + 1) * (jb - ja + 1) * (kb - ka + 1); }
-  long cidx(int I, int J, int K) const { return ((long)K * ny + J) * nx + I; }
-  long fidx(int i, int j, int k) const { return ((long)k * (my + 1) + j) * (mx + 1) + i; }
   long box(int I, int J, int K) const { return ((long)(K - ka) * (jb - ja + 1) + (J - ja)) * (ib - ia + 1) + (I - ia); }
+  // parent-node tests
   bool in_box(int I, int J, int K) const {
     return I >= ia && I <= ib && J >= ja && J <= jb && (D == 2 || (K >= ka && K <= kb));
   }
@@ -66,6 +77,26 @@ struct Ref {
     return I > ia && I < ib && J > ja && J < jb && (D == 2 || (K > ka && K < kb));
   }
   bool perimeter(int I, int J, int K) const { return in_box(I, J, K) && !covered(I, J, K); }
+  bool outside(int si, int sj, int sk) const { return si < 0 || si > mx || sj < 0 || sj > my || sk < 0 || sk > mz; }
+  void set_box(const int* p) {
+    ia = p[0];
+    ib = p[1];
+    ja = p[2];
+    jb = p[3];
+    ka = D == 3 ? p[4] : 0;
+    kb = D == 3 ? p[5] : 0;
+    mx = 2 * (ib - ia);
+    my = 2 * (jb - ja);
+    mz = 2 * (kb - ka);
+  }
+};
+
+struct Ref {
+  int D = 2, Q = 9;
+  int cx[QMAX], cy[QMAX], cz[QMAX];
+  double w[QMAX];
+  int L = 2;
+  Level lv[LMAX];  // lv[0]: the periodic coarse grid
 
   // eq. (feq) with c_s^2 = 1/3
   void feq(double rho, double ux, double uy, double uz, double* out) const {
@@ -89,106 +120,120 @@ struct Ref {
     uz = mzs / rho;
   }
 
-  // u holds D components per node
-  void init(const double* rc, const double* uc, const double* rf, const double* uf) {
-    fc.assign(Q * nc(), 0.0);
-    ff.assign(Q * nf(), 0.0);
-    g0.assign(Q * nb(), 0.0);
-    g1.assign(Q * nb(), 0.0);
+  // equilibrium state from rho[l] and u[l] (D components per node) on every
+  // level; each refined level's G(t) is its parent's initial populations on
+  // the box perimeter
+  void init(const double* const* rho, const double* const* u) {
     double e[QMAX];
-    for (int K = 0; K < nz; ++K)
-      for (int J = 0; J < ny; ++J)
-        for (int I = 0; I < nx; ++I) {
-          const long n = cidx(I, J, K);
-          feq(rc[n], uc[D * n], uc[D * n + 1], D == 3 ? uc[D * n + 2] : 0.0, e);
-          for (int q = 0; q < Q; ++q) fc[q * nc() + n] = e[q];
-          if (perimeter(I, J, K))
-            for (int q = 0; q < Q; ++q) g0[q * nb() + box(I, J, K)] = e[q];
-        }
-    for (long n = 0; n < nf(); ++n) {
-      feq(rf[n], uf[D * n], uf[D * n + 1], D == 3 ? uf[D * n + 2] : 0.0, e);
-      for (int q = 0; q < Q; ++q) ff[q * nf() + n] = e[q];
+    for (int l = 0; l < L; ++l) {
+      Level& v = lv[l];
+      v.f.assign(Q * v.n(), 0.0);
+      for (long n = 0; n < v.n(); ++n) {
+        feq(rho[l][n], u[l][D * n], u[l][D * n + 1], D == 3 ? u[l][D * n + 2] : 0.0, e);
+        for (int q = 0; q < Q; ++q) v.f[q * v.n() + n] = e[q];
+      }
+    }
+    for (int l = 1; l < L; ++l) {
+      Level& c = lv[l];
+      const Level& p = lv[l - 1];
+      c.g0.assign(Q * c.nb(), 0.0);
+      c.g1.assign(Q * c.nb(), 0.0);
+      for (int K = c.ka; K <= c.kb; ++K)
+        for (int J = c.ja; J <= c.jb; ++J)
+          for (int I = c.ia; I <= c.ib; ++I)
+            if (c.perimeter(I, J, K))
+              for (int q = 0; q < Q; ++q) c.g0[q * c.nb() + c.box(I, J, K)] = p.f[q * p.n() + p.idx(I, J, K)];
     }
   }
 
-  // interpolated coarse pre-collision set at fine perimeter node (i, j, k):
-  // time weights a (t) and b (t + 1); along each odd coordinate the mean of
-  // the two coarse nodes beside it (z outermost, x innermost)
-  void coarse_set(int i, int j, int k, double a, double b, double* H) const {
+  // interpolated parent pre-collision set at perimeter node (i, j, k) of
+  // level c: time weights a (t) and b (t + 1); along each odd coordinate the
+  // mean of the two parent nodes beside it (z outermost, x innermost)
+  void coarse_set(const Level& c, int i, int j, int k, double a, double b, double* H) const {
     for (int q = 0; q < Q; ++q) H[q] = 0.0;
     const int ox = i & 1, oy = j & 1, oz = k & 1;
     const double s = (ox ? 0.5 : 1.0) * (oy ? 0.5 : 1.0) * (oz ? 0.5 : 1.0);
     for (int dz = 0; dz <= oz; ++dz)
       for (int dy = 0; dy <= oy; ++dy)
         for (int dx = 0; dx <= ox; ++dx) {
-          const int I = ia + (i - ox) / 2 + dx, J = ja + (j - oy) / 2 + dy, K = ka + (k - oz) / 2 + dz;
-          const long bx = box(I, J, K);
-          for (int q = 0; q < Q; ++q) H[q] += s * (a * g0[q * nb() + bx] + b * g1[q * nb() + bx]);
+          const long bx = c.box(c.ia + (i - ox) / 2 + dx, c.ja + (j - oy) / 2 + dy, c.ka + (k - oz) / 2 + dz);
+          for (int q = 0; q < Q; ++q) H[q] += s * (a * c.g0[q * c.nb() + bx] + b * c.g1[q * c.nb() + bx]);
         }
   }
 
-  bool outside(int si, int sj, int sk) const { return si < 0 || si > mx || sj < 0 || sj > my || sk < 0 || sk > mz; }
-
-  void step() {
-    // coarse step t -> t+1 on the uncovered nodes
-    std::vector<double> nfc = fc;
+  // One time step of level l, returning its new post-collision populations.
+  // Level 0 pulls periodically and skips the nodes its child covers; a
+  // refined level takes the populations whose source lies outside its box
+  // from the parent's G (time weights a, b), and with restrict_ writes the
+  // parent's covered nodes into parent_new.  Nodes on the child's perimeter
+  // store their pre-collision sets as the child's G(t + 1).
+  std::vector<double> step_level(int l, double a, double b, bool restrict_, std::vector<double>* parent_new) {
+    Level& v = lv[l];
+    Level* c = l + 1 < L ? &lv[l + 1] : nullptr;
+    const Level* p = l > 0 ? &lv[l - 1] : nullptr;
+    std::vector<double> out = v.f;
     double f[QMAX], e[QMAX];
-    for (int K = 0; K < nz; ++K)
-      for (int J = 0; J < ny; ++J)
-        for (int I = 0; I < nx; ++I) {
-          if (covered(I, J, K)) continue;
-          const long n = cidx(I, J, K);
+    for (int k = 0; k <= v.mz; ++k)
+      for (int j = 0; j <= v.my; ++j)
+        for (int i = 0; i <= v.mx; ++i) {
+          if (l == 0 && c && c->covered(i, j, k)) continue;
+          bool missing = false;
           for (int q = 0; q < Q; ++q) {
-            const int sI = ((I - cx[q]) % nx + nx) % nx, sJ = ((J - cy[q]) % ny + ny) % ny;
-            const int sK = ((K - cz[q]) % nz + nz) % nz;
-            f[q] = fc[q * nc() + cidx(sI, sJ, sK)];
+            int si = i - cx[q], sj = j - cy[q], sk = k - cz[q];
+            if (l == 0) {
+              si = (si + v.mx + 1) % (v.mx + 1);
+              sj = (sj + v.my + 1) % (v.my + 1);
+              sk = (sk + v.mz + 1) % (v.mz + 1);
+            } else if (v.outside(si, sj, sk)) {
+              missing = true;
+              continue;
+            }
+            f[q] = v.f[q * v.n() + v.idx(si, sj, sk)];
           }
-          if (perimeter(I, J, K))
-            for (int q = 0; q < Q; ++q) g1[q * nb() + box(I, J, K)] = f[q];
+          if (missing) {
+            double H[QMAX], eh[QMAX], rh, uxh, uyh, uzh;
+            coarse_set(v, i, j, k, a, b, H);
+            moments(H, rh, uxh, uyh, uzh);
+            feq(rh, uxh, uyh, uzh, eh);
+            for (int q = 0; q < Q; ++q)
+              if (v.outside(i - cx[q], j - cy[q], k - cz[q])) f[q] = eh[q] + v.tau / (2.0 * p->tau) * (H[q] - eh[q]);
+          }
+          if (c && c->perimeter(i, j, k))
+            for (int q = 0; q < Q; ++q) c->g1[q * c->nb() + c->box(i, j, k)] = f[q];
           double rho, ux, uy, uz;
           moments(f, rho, ux, uy, uz);
           feq(rho, ux, uy, uz, e);
-          for (int q = 0; q < Q; ++q) nfc[q * nc() + n] = f[q] - (f[q] - e[q]) / tc;
-        }
-    // two fine sub-steps
-    for (int s = 1; s <= 2; ++s) {
-      const double a = s == 1 ? 0.5 : 0.0, b = s == 1 ? 0.5 : 1.0;
-      std::vector<double> nff(ff.size());
-      for (int k = 0; k <= mz; ++k)
-        for (int j = 0; j <= my; ++j)
-          for (int i = 0; i <= mx; ++i) {
-            const long n = fidx(i, j, k);
-            bool missing = false;
-            for (int q = 0; q < Q; ++q) {
-              const int si = i - cx[q], sj = j - cy[q], sk = k - cz[q];
-              if (outside(si, sj, sk)) {
-                missing = true;
-                continue;
-              }
-              f[q] = ff[q * nf() + fidx(si, sj, sk)];
-            }
-            if (missing) {
-              double H[QMAX], eh[QMAX], rh, uxh, uyh, uzh;
-              coarse_set(i, j, k, a, b, H);
-              moments(H, rh, uxh, uyh, uzh);
-              feq(rh, uxh, uyh, uzh, eh);
-              for (int q = 0; q < Q; ++q)
-                if (outside(i - cx[q], j - cy[q], k - cz[q])) f[q] = eh[q] + tf / (2.0 * tc) * (H[q] - eh[q]);
-            }
-            double rho, ux, uy, uz;
-            moments(f, rho, ux, uy, uz);
-            feq(rho, ux, uy, uz, e);
-            for (int q = 0; q < Q; ++q) nff[q * nf() + n] = f[q] - (f[q] - e[q]) / tf;
-            if (s == 2 && i % 2 == 0 && j % 2 == 0 && k % 2 == 0 &&
-                covered(ia + i / 2, ja + j / 2, ka + k / 2)) {
-              const long m = cidx(ia + i / 2, ja + j / 2, ka + k / 2);
-              for (int q = 0; q < Q; ++q) nfc[q * nc() + m] = e[q] + 2.0 * (tc - 1.0) / tf * (f[q] - e[q]);
-            }
+          const long n = v.idx(i, j, k);
+          for (int q = 0; q < Q; ++q) out[q * v.n() + n] = f[q] - (f[q] - e[q]) / v.tau;
+          if (restrict_ && i % 2 == 0 && j % 2 == 0 && k % 2 == 0 && v.covered(v.ia + i / 2, v.ja + j / 2, v.ka + k / 2)) {
+            const long m = p->idx(v.ia + i / 2, v.ja + j / 2, v.ka + k / 2);
+            for (int q = 0; q < Q; ++q)
+              (*parent_new)[q * p->n() + m] = e[q] + 2.0 * (p->tau - 1.0) / v.tau * (f[q] - e[q]);
           }
-      ff.swap(nff);
+        }
+    return out;
+  }
+
+  // the two sub-steps of refined level l within one step of its parent,
+  // each followed by the child's two sub-steps
+  void advance(int l, std::vector<double>& parent_new) {
+    for (int s = 1; s <= 2; ++s) {
+      std::vector<double> nf = step_level(l, s == 1 ? 0.5 : 0.0, s == 1 ? 0.5 : 1.0, s == 2, &parent_new);
+      if (l + 1 < L) {
+        advance(l + 1, nf);
+        lv[l + 1].g0.swap(lv[l + 1].g1);
+      }
+      lv[l].f.swap(nf);
     }
-    fc.swap(nfc);
-    g0.swap(g1);
+  }
+
+  void step() {
+    std::vector<double> nf = step_level(0, 0.0, 0.0, false, nullptr);
+    if (L > 1) {
+      advance(1, nf);
+      lv[1].g0.swap(lv[1].g1);
+    }
+    lv[0].f.swap(nf);
   }
 
   // Level-set refinement sensor (Sec. 3, adaptive mesh refinement): a coarse
@@ -200,19 +245,20 @@ struct Ref {
   // widened to at least two cells per axis; out = (ia, ib, ja, jb, ka, kb).
   // Returns false (out untouched) when no node is tagged.
   bool sensor_box(const double* phi, double d_ref, int margin, int* out) const {
-    int lo[3] = {nx, ny, nz}, hi[3] = {-1, -1, -1};
-    for (int K = 0; K < nz; ++K)
-      for (int J = 0; J < ny; ++J)
-        for (int I = 0; I < nx; ++I) {
-          if (!(phi[cidx(I, J, K)] >= -d_ref)) continue;
-          const int p[3] = {I, J, K};
+    const Level& g = lv[0];
+    const int n[3] = {g.mx + 1, g.my + 1, g.mz + 1};
+    int lo[3] = {n[0], n[1], n[2]}, hi[3] = {-1, -1, -1};
+    for (int K = 0; K < n[2]; ++K)
+      for (int J = 0; J < n[1]; ++J)
+        for (int I = 0; I < n[0]; ++I) {
+          if (!(phi[g.idx(I, J, K)] >= -d_ref)) continue;
+          const int pt[3] = {I, J, K};
           for (int d = 0; d < 3; ++d) {
-            if (p[d] < lo[d]) lo[d] = p[d];
-            if (p[d] > hi[d]) hi[d] = p[d];
+            if (pt[d] < lo[d]) lo[d] = pt[d];
+            if (pt[d] > hi[d]) hi[d] = pt[d];
           }
         }
     if (hi[0] < 0) return false;
-    const int n[3] = {nx, ny, nz};
     for (int d = 0; d < D; ++d) {
       int a = lo[d] - margin, b = hi[d] + margin;
       if (a < 1) a = 1;
@@ -228,49 +274,42 @@ struct Ref {
     return true;
   }
 
-  // Re-meshing onto a new patch box at the end of a coarse step (state at
-  // time t: post-collision populations of both levels, the covered coarse
-  // nodes holding restricted values).  New fine nodes inside the old patch
-  // keep the old fine populations; the others take the coarse populations
-  // interpolated like the perimeter's (the mean of the 2, 4 or 8 coarse
-  // nodes around an off-grid fine node), their non-equilibrium part scaled
-  // by the post-collision ratio (tau_f - 1) / (2 (tau_c - 1)) about the
-  // equilibrium of the interpolated moments (the equilibrium alone when
-  // tau_c = 1, where the coarse post-collision state holds no
-  // non-equilibrium part).  The new perimeter's pre-collision sets G(t) come
-  // from the coarse post-collision populations by inverting the BGK step,
-  // f_eq + tau_c / (tau_c - 1) (f - f_eq) (f_eq at tau_c = 1).  Covered
-  // coarse nodes are restricted again at the end of the next step; coarse
-  // nodes the patch no longer covers keep their restricted values.
+  // Re-meshing of a two-level hierarchy onto a new patch box at the end of a
+  // coarse step (state at time t: post-collision populations of both
+  // levels, the covered coarse nodes holding restricted values).  New fine
+  // nodes inside the old patch keep the old fine populations; the others
+  // take the coarse populations interpolated like the perimeter's (the mean
+  // of the 2, 4 or 8 coarse nodes around an off-grid fine node), their
+  // non-equilibrium part scaled by the post-collision ratio
+  // (tau_f - 1) / (2 (tau_c - 1)) about the equilibrium of the interpolated
+  // moments (the equilibrium alone when tau_c = 1, where the coarse
+  // post-collision state holds no non-equilibrium part).  The new
+  // perimeter's pre-collision sets G(t) come from the coarse post-collision
+  // populations by inverting the BGK step, f_eq + tau_c / (tau_c - 1)
+  // (f - f_eq) (f_eq at tau_c = 1).  Covered coarse nodes are restricted
+  // again at the end of the next step; coarse nodes the patch no longer
+  // covers keep their restricted values.
   void remesh(const int* np) {
-    const int oia = ia, oib = ib, oja = ja, ojb = jb, oka = ka, okb = kb, omx = mx, omy = my, omz = mz;
-    const std::vector<double> off = ff;
-    const long onf = nf();
-    ia = np[0];
-    ib = np[1];
-    ja = np[2];
-    jb = np[3];
-    ka = D == 3 ? np[4] : 0;
-    kb = D == 3 ? np[5] : 0;
-    mx = 2 * (ib - ia);
-    my = 2 * (jb - ja);
-    mz = 2 * (kb - ka);
-    ff.assign(Q * nf(), 0.0);
-    g0.assign(Q * nb(), 0.0);
-    g1.assign(Q * nb(), 0.0);
+    const Level& g = lv[0];
+    Level& v = lv[1];
+    const Level o = v;  // the old patch and its populations
+    v.set_box(np);
+    v.f.assign(Q * v.n(), 0.0);
+    v.g0.assign(Q * v.nb(), 0.0);
+    v.g1.assign(Q * v.nb(), 0.0);
     double H[QMAX], e[QMAX];
+    const double tc = g.tau, tf = v.tau;
     const bool flat = tc == 1.0;
     const double up = flat ? 0.0 : (tf - 1.0) / (2.0 * (tc - 1.0));
-    for (int k = 0; k <= mz; ++k)
-      for (int j = 0; j <= my; ++j)
-        for (int i = 0; i <= mx; ++i) {
+    for (int k = 0; k <= v.mz; ++k)
+      for (int j = 0; j <= v.my; ++j)
+        for (int i = 0; i <= v.mx; ++i) {
           // coarse-unit position times two
-          const int X2 = 2 * ia + i, Y2 = 2 * ja + j, Z2 = 2 * ka + k;
-          const int oi = X2 - 2 * oia, oj = Y2 - 2 * oja, ok = Z2 - 2 * oka;
-          const long n = fidx(i, j, k);
-          if (oi >= 0 && oi <= omx && oj >= 0 && oj <= omy && ok >= 0 && ok <= omz) {
-            const long on = ((long)ok * (omy + 1) + oj) * (omx + 1) + oi;
-            for (int q = 0; q < Q; ++q) ff[q * nf() + n] = off[q * onf + on];
+          const int X2 = 2 * v.ia + i, Y2 = 2 * v.ja + j, Z2 = 2 * v.ka + k;
+          const int oi = X2 - 2 * o.ia, oj = Y2 - 2 * o.ja, ok = Z2 - 2 * o.ka;
+          const long n = v.idx(i, j, k);
+          if (!o.outside(oi, oj, ok)) {
+            for (int q = 0; q < Q; ++q) v.f[q * v.n() + n] = o.f[q * o.n() + o.idx(oi, oj, ok)];
             continue;
           }
           const int ox = X2 & 1, oy = Y2 & 1, oz = Z2 & 1;
@@ -279,30 +318,27 @@ struct Ref {
           for (int dz = 0; dz <= oz; ++dz)
             for (int dy = 0; dy <= oy; ++dy)
               for (int dx = 0; dx <= ox; ++dx) {
-                const long m = cidx((X2 - ox) / 2 + dx, (Y2 - oy) / 2 + dy, (Z2 - oz) / 2 + dz);
-                for (int q = 0; q < Q; ++q) H[q] += s * fc[q * nc() + m];
+                const long m = g.idx((X2 - ox) / 2 + dx, (Y2 - oy) / 2 + dy, (Z2 - oz) / 2 + dz);
+                for (int q = 0; q < Q; ++q) H[q] += s * g.f[q * g.n() + m];
               }
           double rho, ux, uy, uz;
           moments(H, rho, ux, uy, uz);
           feq(rho, ux, uy, uz, e);
-          for (int q = 0; q < Q; ++q) ff[q * nf() + n] = e[q] + up * (H[q] - e[q]);
+          for (int q = 0; q < Q; ++q) v.f[q * v.n() + n] = e[q] + up * (H[q] - e[q]);
         }
     const double down = flat ? 0.0 : tc / (tc - 1.0);
-    for (int K = ka; K <= (D == 3 ? kb : 0); ++K)
-      for (int J = ja; J <= jb; ++J)
-        for (int I = ia; I <= ib; ++I) {
-          if (!perimeter(I, J, K)) continue;
-          const long m = cidx(I, J, K);
+    for (int K = v.ka; K <= v.kb; ++K)
+      for (int J = v.ja; J <= v.jb; ++J)
+        for (int I = v.ia; I <= v.ib; ++I) {
+          if (!v.perimeter(I, J, K)) continue;
+          const long m = g.idx(I, J, K);
           double f[QMAX];
-          for (int q = 0; q < Q; ++q) f[q] = fc[q * nc() + m];
+          for (int q = 0; q < Q; ++q) f[q] = g.f[q * g.n() + m];
           double rho, ux, uy, uz;
           moments(f, rho, ux, uy, uz);
           feq(rho, ux, uy, uz, e);
-          for (int q = 0; q < Q; ++q) g0[q * nb() + box(I, J, K)] = e[q] + down * (f[q] - e[q]);
+          for (int q = 0; q < Q; ++q) v.g0[q * v.nb() + v.box(I, J, K)] = e[q] + down * (f[q] - e[q]);
         }
-    (void)oib;
-    (void)ojb;
-    (void)okb;
   }
 };
 
@@ -311,11 +347,14 @@ struct Ref {
 extern "C" {
 
 // lattice: 0 D2Q9, 1 D3Q19, 2 D3Q27 (the oracle's numbering); n = (nx, ny,
-// nz) with nz = 1 in 2D; patch = (ia, ib, ja, jb, ka, kb), ka = kb = 0 in 2D.
-// tau_f <= 0 selects the constant-viscosity value 2 tau_c - 1/2; the tests
-// pass another value only to check that a pin catches a wrong one.
-void* orc_ref_create(int lattice, const int* n, const int* patch, double tau_c, double tau_f) {
-  if (!n || !patch) return nullptr;
+// nz) with nz = 1 in 2D; levels in [2, 4]; patches[6 (l - 1) ...] = (ia, ib,
+// ja, jb, ka, kb) of level l in level l - 1's node coordinates (ka = kb = 0
+// in 2D), each with one node to spare at every side of its parent (level 0:
+// 1 <= ia, ib <= nx - 2) and at least two cells per axis.  tau[l] <= 0 (or
+// tau == NULL) selects the constant-viscosity value 2 tau[l-1] - 1/2; the
+// tests pass another value only to check that a pin catches a wrong one.
+void* orc_mref_create(int lattice, const int* n, int levels, const int* patches, double tau_c, const double* tau) {
+  if (!n || !patches || levels < 2 || levels > ref::LMAX || !(tau_c > 0.5)) return nullptr;
   ref::Ref* r = new ref::Ref();
   int c[3 * ref::QMAX], opp[ref::QMAX];
   if (orc_lattice(lattice, &r->D, &r->Q, c, r->w, opp) != 0) {
@@ -327,35 +366,48 @@ void* orc_ref_create(int lattice, const int* n, const int* patch, double tau_c, 
     r->cy[q] = c[3 * q + 1];
     r->cz[q] = c[3 * q + 2];
   }
-  r->nx = n[0];
-  r->ny = n[1];
-  r->nz = r->D == 3 ? n[2] : 1;
-  r->ia = patch[0];
-  r->ib = patch[1];
-  r->ja = patch[2];
-  r->jb = patch[3];
-  r->ka = r->D == 3 ? patch[4] : 0;
-  r->kb = r->D == 3 ? patch[5] : 0;
-  const bool ok = r->nx >= 4 && r->ny >= 4 && (r->D == 2 || r->nz >= 4) && r->ia >= 1 && r->ib <= r->nx - 2 &&
-                  r->ib - r->ia >= 2 && r->ja >= 1 && r->jb <= r->ny - 2 && r->jb - r->ja >= 2 &&
-                  (r->D == 2 || (r->ka >= 1 && r->kb <= r->nz - 2 && r->kb - r->ka >= 2)) && tau_c > 0.5;
+  r->L = levels;
+  for (int l = 0; l < levels; ++l) r->lv[l].D = r->D;
+  ref::Level& g = r->lv[0];
+  g.mx = n[0] - 1;
+  g.my = n[1] - 1;
+  g.mz = r->D == 3 ? n[2] - 1 : 0;
+  g.tau = tau_c;
+  bool ok = g.mx >= 3 && g.my >= 3 && (r->D == 2 || g.mz >= 3);
+  for (int l = 1; l < levels && ok; ++l) {
+    const ref::Level& p = r->lv[l - 1];
+    ref::Level& v = r->lv[l];
+    v.set_box(patches + 6 * (l - 1));
+    v.tau = tau && tau[l] > 0.0 ? tau[l] : 2.0 * p.tau - 0.5;
+    ok = v.ia >= 1 && v.ib <= p.mx - 1 && v.ib - v.ia >= 2 && v.ja >= 1 && v.jb <= p.my - 1 && v.jb - v.ja >= 2 &&
+         (r->D == 2 || (v.ka >= 1 && v.kb <= p.mz - 1 && v.kb - v.ka >= 2));
+  }
   if (!ok) {
     delete r;
     return nullptr;
   }
-  r->mx = 2 * (r->ib - r->ia);
-  r->my = 2 * (r->jb - r->ja);
-  r->mz = 2 * (r->kb - r->ka);
-  r->tc = tau_c;
-  r->tf = tau_f > 0.0 ? tau_f : 2.0 * tau_c - 0.5;
   return r;
+}
+
+// two levels: patch of level 1, tau_f <= 0 for 2 tau_c - 1/2
+void* orc_ref_create(int lattice, const int* n, const int* patch, double tau_c, double tau_f) {
+  const double tau[2] = {tau_c, tau_f};
+  return orc_mref_create(lattice, n, 2, patch, tau_c, tau);
 }
 
 void orc_ref_destroy(void* h) { delete static_cast<ref::Ref*>(h); }
 
-int orc_ref_init(void* h, const double* rho_c, const double* u_c, const double* rho_f, const double* u_f) {
-  static_cast<ref::Ref*>(h)->init(rho_c, u_c, rho_f, u_f);
+// rho[l] [nodes of level l], u[l] [nodes][D] for every level
+int orc_mref_init(void* h, const double* const* rho, const double* const* u) {
+  static_cast<ref::Ref*>(h)->init(rho, u);
   return 0;
+}
+
+int orc_ref_init(void* h, const double* rho_c, const double* u_c, const double* rho_f, const double* u_f) {
+  const double* rho[2] = {rho_c, rho_f};
+  const double* u[2] = {u_c, u_f};
+  if (static_cast<ref::Ref*>(h)->L != 2) return -1;
+  return orc_mref_init(h, rho, u);
 }
 
 int orc_ref_step(void* h, int n) {
@@ -370,22 +422,31 @@ int orc_ref_sensor(void* h, const double* phi, double d_ref, int margin, int* ou
   return static_cast<ref::Ref*>(h)->sensor_box(phi, d_ref, margin, out) ? 1 : 0;
 }
 
-// re-mesh onto the patch (ia, ib, ja, jb, ka, kb); -1 if it does not fit the grid
+// re-mesh a two-level hierarchy onto the patch (ia, ib, ja, jb, ka, kb); -1
+// if it does not fit the grid or the hierarchy has more levels
 int orc_ref_remesh(void* h, const int* patch) {
   ref::Ref* r = static_cast<ref::Ref*>(h);
-  const int n[3] = {r->nx, r->ny, r->nz};
+  if (r->L != 2) return -1;
+  const ref::Level& g = r->lv[0];
+  const int n[3] = {g.mx + 1, g.my + 1, g.mz + 1};
   for (int d = 0; d < r->D; ++d)
     if (patch[2 * d] < 1 || patch[2 * d + 1] > n[d] - 2 || patch[2 * d + 1] - patch[2 * d] < 2) return -1;
   r->remesh(patch);
   return 0;
 }
 
-// populations [Q][nodes] of both levels (post-collision; the covered coarse
-// nodes hold the restricted values)
-int orc_ref_get(void* h, double* fc, double* ff) {
+// post-collision populations [Q][nodes] of one level (the covered nodes hold
+// the restricted values)
+int orc_mref_get(void* h, int level, double* out) {
   const ref::Ref* r = static_cast<const ref::Ref*>(h);
-  for (size_t k = 0; k < r->fc.size(); ++k) fc[k] = r->fc[k];
-  for (size_t k = 0; k < r->ff.size(); ++k) ff[k] = r->ff[k];
+  if (level < 0 || level >= r->L) return -1;
+  const std::vector<double>& f = r->lv[level].f;
+  for (size_t k = 0; k < f.size(); ++k) out[k] = f[k];
   return 0;
+}
+
+int orc_ref_get(void* h, double* fc, double* ff) {
+  orc_mref_get(h, 0, fc);
+  return orc_mref_get(h, 1, ff);
 }
 }
