@@ -1,4 +1,5 @@
-/* Two-level static grid refinement of the lattice Boltzmann solver (C ABI).
+/* Static grid refinement of the lattice Boltzmann solver, two to four
+ * nested levels (C ABI).
  *
  * The paper refines its lattice Boltzmann grid after Dupuis and Chopard:
  * distributions missing at a refinement jump are obtained by spatial and
@@ -31,6 +32,15 @@
  * coarse node f_eq + 2 (tau_c - 1) / tau_f (f - f_eq) from the coincident
  * fine node's pre-collision populations f.
  *
+ * Nested levels: level 1 may hold a patch of level 2 (and level 2 one of
+ * level 3), a box of its own nodes with one node to spare at every side;
+ * each pair of adjacent levels is coupled as above, tau doubles minus 1/2
+ * from level to level, and every sub-step of a level is followed by its
+ * child's two sub-steps, the second of which restricts into the level's new
+ * populations.  A level restricts into its parent from its own
+ * pre-collision populations (at nodes its child covers, those come from the
+ * child's restriction).
+ *
  * Conventions as in lsb.h: every function returns LSB_OK (0) or a negative
  * code of lsb.h (message from lsb_last_error); calls that take a stream
  * enqueue work on it and return without waiting; the library allocates no
@@ -47,6 +57,8 @@
 extern "C" {
 #endif
 
+#define LSB_REF_MAX_LEVELS 4
+
 typedef struct lsb_ref_params {
   int lattice;      /* LSB_D2Q9, LSB_D3Q19 or LSB_D3Q27 */
   int nx, ny, nz;   /* coarse nodes, >= 4 per axis; nz = 1 for D2Q9 */
@@ -57,34 +69,45 @@ typedef struct lsb_ref_params {
   int max_extent[3]; /* largest patch extents (coarse cells per axis) that lsb_ref_remesh may
                         choose; 0 or anything below the initial patch's extent keeps that
                         extent; at most n - 3 */
+  int levels;       /* 2 .. LSB_REF_MAX_LEVELS (0 is read as 2) */
+  int inner[LSB_REF_MAX_LEVELS - 2][6]; /* inner[l - 2]: box of level l in level l - 1's node
+                        coordinates (nodes 0 .. m per axis, m = twice the parent box's
+                        extent): 1 <= a, b <= m - 1, b - a >= 2 per axis; ka, kb ignored in
+                        2D; unused entries ignored */
 } lsb_ref_params;
 
 typedef struct lsb_ref lsb_ref;
 
 /* Validates the parameters and creates a handle (host memory only).
  * LSB_EINVAL for a NULL pointer, an unknown lattice, parameters outside
- * the ranges above, or a level of more than 2^31 nodes. */
+ * the ranges above, or a level of more than 2^31 nodes (with the ghost
+ * shell). */
 int lsb_ref_create(const lsb_ref_params* params, lsb_ref** out);
 void lsb_ref_destroy(lsb_ref* ref);
 
-/* Device workspace the caller provides: both levels' populations twice
- * (double buffers, the fine level sized for the largest patch) and the
- * coarse perimeter's pre-collision sets at two time levels.  The library keeps the pointer; the caller keeps ownership and
- * must keep it alive while the handle is used.  LSB_ENOMEM if it is too
- * small. */
+/* Device workspace the caller provides: every level's populations twice
+ * (double buffers, level 1 sized for the largest patch) and each refined
+ * level's perimeter sets from its parent at two time levels.  The library
+ * keeps the pointer; the caller keeps ownership and must keep it alive
+ * while the handle is used.  LSB_ENOMEM if it is too small. */
 int lsb_ref_workspace_bytes(const lsb_ref* ref, size_t* bytes);
 int lsb_ref_bind(lsb_ref* ref, void* device_workspace, size_t bytes);
 
-/* Equilibrium initial state from device arrays: rho_c [nx*ny*nz], u_c
- * [nx*ny*nz*D] (D components per node, x fastest over the nodes), rho_f and
- * u_f the same over the fine nodes ((2(ib-ia)+1) (2(jb-ja)+1) (2(kb-ka)+1)
- * in 3D, i fastest).  The coarse perimeter's pre-collision sets start at
- * those equilibria.
- * LSB_ESTATE before lsb_ref_bind. */
+/* Equilibrium initial state of a two-level hierarchy from device arrays:
+ * rho_c [nx*ny*nz], u_c [nx*ny*nz*D] (D components per node, x fastest over
+ * the nodes), rho_f and u_f the same over the fine nodes ((2(ib-ia)+1)
+ * (2(jb-ja)+1) (2(kb-ka)+1) in 3D, i fastest).  The coarse perimeter's
+ * pre-collision sets start at those equilibria.
+ * LSB_ESTATE before lsb_ref_bind; LSB_EINVAL with more than two levels. */
 int lsb_ref_init(lsb_ref* ref, const double* rho_c, const double* u_c, const double* rho_f, const double* u_f,
                  void* stream);
 
-/* nsteps coarse steps (2 nsteps fine steps).  LSB_ESTATE before
+/* The same for any number of levels: rho[l] and u[l] (host arrays of
+ * `levels` device pointers) over level l's nodes, laid out as above.
+ * LSB_ESTATE before lsb_ref_bind. */
+int lsb_ref_init_levels(lsb_ref* ref, const double* const* rho, const double* const* u, void* stream);
+
+/* nsteps coarse steps (2^l nsteps steps of level l).  LSB_ESTATE before
  * lsb_ref_init. */
 int lsb_ref_step(lsb_ref* ref, int nsteps, void* stream);
 
@@ -107,7 +130,8 @@ int lsb_ref_sensor(lsb_ref* ref, const double* phi, double d_ref, int margin, in
  * equilibrium of the interpolated moments (the equilibrium alone at
  * tau_c = 1); the new perimeter's pre-collision sets come from inverting
  * the coarse BGK step.  LSB_EINVAL for a patch outside the grid or larger
- * than max_extent; LSB_ESTATE before lsb_ref_init. */
+ * than max_extent, or a hierarchy of more than two levels; LSB_ESTATE
+ * before lsb_ref_init. */
 int lsb_ref_remesh(lsb_ref* ref, const int* patch, void* stream);
 
 /* Post-collision populations of both levels into device arrays, [Q][nodes]
@@ -116,6 +140,11 @@ int lsb_ref_remesh(lsb_ref* ref, const int* patch, void* stream);
  * [Q][2(kb-ka)+1][2(jb-ja)+1][2(ib-ia)+1] (one z layer in 2D).
  * Either pointer may be NULL.  LSB_ESTATE before lsb_ref_init. */
 int lsb_ref_get_populations(lsb_ref* ref, double* coarse, double* fine, void* stream);
+
+/* Post-collision populations of one level (0 = coarse) into a device array,
+ * [Q][nodes of that level] as above.  LSB_EINVAL for a level outside
+ * [0, levels); LSB_ESTATE before lsb_ref_init. */
+int lsb_ref_get_level(lsb_ref* ref, int level, double* out, void* stream);
 
 #ifdef __cplusplus
 }

@@ -1,6 +1,6 @@
-// refine.hip -- two-level static grid refinement of the lattice Boltzmann
-// solver (D2Q9, D3Q19, D3Q27; BGK, FP64, ratio 2) behind the C ABI of
-// lsb_refine.h.
+// refine.hip -- static grid refinement of the lattice Boltzmann solver
+// (D2Q9, D3Q19, D3Q27; BGK, FP64, ratio 2; two to four nested levels) behind
+// the C ABI of lsb_refine.h.
 //
 // The coupling of the levels follows the approach the paper adopts for its
 // refinement jumps (Sec. 2, lattice Boltzmann method): populations missing
@@ -20,6 +20,9 @@
 //   k_ref_fine    pull + BGK on the fine nodes (no branch on the perimeter);
 //                 the second sub-step restricts onto the covered coarse
 //                 nodes.
+// With nested levels a refined level is also the parent of the next: its
+// k_ref_fine keeps the child perimeter's sets as k_ref_coarse does, and each
+// of its sub-steps is followed by the child's edge and two fine launches.
 // One x-row segment of 256 nodes per block (x along the lanes), so every
 // population plane is read and written in contiguous 2 KB runs; blocks are
 // ordered so that each XCD streams a contiguous band of rows.
@@ -39,9 +42,15 @@ namespace {
 using lsb::Lat;
 using lsb::wgt;
 
+// One pair of adjacent levels: the parent (coarse) and its patch (fine).
+// Parent node (I, J, K) sits at po + (K ph + J) pw + I of a population plane
+// of nc entries: for the periodic coarse grid pw = nx, ph = ny, po = 0; for
+// a refined parent its padded pitches and the offset of its node (0, 0, 0).
 struct RefArgs {
   int D;
-  int nx, ny, nz, ia, ib, ja, jb, ka, kb, mx, my, mz;  // fine nodes (mx + 1) x (my + 1) x (mz + 1)
+  int nx, ny, nz, ia, ib, ja, jb, ka, kb, mx, my, mz;  // parent nodes per axis; fine nodes (mx + 1) x (my + 1) x (mz + 1)
+  int pw, ph;                                          // parent pitches
+  long po;                                             // parent node (0, 0, 0)
   int bw, bh, bd;                                      // patch box extents in x, y, z (bd = 1 in 2D)
   int fw, fh;                                          // fine pitches with the ghost shell: mx + 3, my + 3
   long nc, nf, nb;                                     // nodes: coarse, fine (with the shell), box surface
@@ -126,34 +135,31 @@ __device__ __forceinline__ long fine_index(const RefArgs& a, int i, int j, int k
   return ((long)(k + (a.D == 3 ? 1 : 0)) * a.fh + (j + 1)) * a.fw + i + 1;
 }
 
+// One level's nodes in its population arrays: sx x sy x sz nodes, node
+// (i, j, k) at po + (k ph + j) pw + i of planes of n entries.
+struct Grid {
+  int sx, sy, sz, pw, ph;
+  long po, n;
+};
+
+// equilibrium initial state of one level; with a child, the child
+// perimeter's sets G(t) are those equilibria
 template <int LAT>
-__global__ __launch_bounds__(256) void k_ref_init(RefArgs a, const double* rho_c, const double* u_c,
-                                                  const double* rho_f, const double* u_f, double* fc, double* ff,
-                                                  double* g0) {
+__global__ __launch_bounds__(256) void k_ref_init_level(Grid g, const double* rho, const double* u, double* f,
+                                                        int has_child, RefArgs c, double* cg0) {
   constexpr int Q = Lat<LAT>::Q, D = Lat<LAT>::D;
-  const long nfc = (long)(a.mx + 1) * (a.my + 1) * (a.mz + 1);
-  for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < a.nc + nfc; t += (long)gridDim.x * 256) {
-    const bool coarse = t < a.nc;
-    const long n = coarse ? t : t - a.nc;
-    const double* r = coarse ? rho_c : rho_f;
-    const double* u = coarse ? u_c : u_f;
+  const long nn = (long)g.sx * g.sy * g.sz;
+  for (long n = (long)blockIdx.x * 256 + threadIdx.x; n < nn; n += (long)gridDim.x * 256) {
+    const int i = (int)(n % g.sx), j = (int)((n / g.sx) % g.sy), k = (int)(n / ((long)g.sx * g.sy));
     const double ux = u[D * n], uy = u[D * n + 1], uz = D == 3 ? u[D * n + 2] : 0.0;
-    if (coarse) {
-      const int I = (int)(n % a.nx), J = (int)((n / a.nx) % a.ny), K = (int)(n / ((long)a.nx * a.ny));
-      double e[Q];
+    const long p = g.po + ((long)k * g.ph + j) * g.pw + i;
+    double e[Q];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        e[q] = equilibrium<LAT>(q, r[n], ux, uy, uz);
-        fc[q * a.nc + n] = e[q];
-      }
-      if (in_box(a, I, J, K) && !covered(a, I, J, K)) store_faces<Q>(a, g0, I, J, K, e);
-    } else {
-      const int i = (int)(n % (a.mx + 1)), j = (int)((n / (a.mx + 1)) % (a.my + 1));
-      const int k = (int)(n / ((long)(a.mx + 1) * (a.my + 1)));
-      const long p = fine_index(a, i, j, k);
-#pragma unroll
-      for (int q = 0; q < Q; ++q) ff[q * a.nf + p] = equilibrium<LAT>(q, r[n], ux, uy, uz);
+    for (int q = 0; q < Q; ++q) {
+      e[q] = equilibrium<LAT>(q, rho[n], ux, uy, uz);
+      f[q * g.n + p] = e[q];
     }
+    if (has_child && in_box(c, i, j, k) && !covered(c, i, j, k)) store_faces<Q>(c, cg0, i, j, k, e);
   }
 }
 
@@ -252,9 +258,12 @@ __global__ __launch_bounds__(256) void k_ref_edge(RefArgs a, double* ff1, double
 
 // fine nodes: pull (the ghost shell holds the perimeter's inward populations),
 // collide with tau_f; with restrict_ set, the fine nodes on covered coarse
-// nodes write those nodes' post-collision populations
-template <int LAT>
-__global__ __launch_bounds__(256) void k_ref_fine(RefArgs a, int segs, int restrict_) {
+// nodes write those nodes' post-collision populations.  With a child patch
+// (c: this level as its parent), the nodes on the child's perimeter keep
+// their pre-collision sets (the child's G(t+1)) and the nodes it covers store
+// nothing (the child's restriction writes them).
+template <int LAT, bool CHILD>
+__global__ __launch_bounds__(256) void k_ref_fine(RefArgs a, RefArgs c, int segs, int restrict_) {
   using L = Lat<LAT>;
   constexpr int Q = L::Q;
   const int Lb = (int)xcd_block(blockIdx.x, gridDim.x);
@@ -266,14 +275,19 @@ __global__ __launch_bounds__(256) void k_ref_fine(RefArgs a, int segs, int restr
   double f[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) f[q] = a.ff_in[q * a.nf + p - L::cz(q) * plane - L::cy(q) * a.fw - L::cx(q)];
+  bool keep = true;
+  if (CHILD && in_box(c, i, j, k)) {
+    if (covered(c, i, j, k)) keep = false;
+    else store_faces<Q>(c, c.g1, i, j, k, f);
+  }
   double rho, ux, uy, uz;
   moments<LAT>(f, rho, ux, uy, uz);
   const bool rs = restrict_ && !(i & 1) && !(j & 1) && !(k & 1) && covered(a, a.ia + i / 2, a.ja + j / 2, a.ka + k / 2);
-  const long m = rs ? ((long)(a.ka + k / 2) * a.ny + a.ja + j / 2) * a.nx + a.ia + i / 2 : 0;
+  const long m = rs ? a.po + ((long)(a.ka + k / 2) * a.ph + a.ja + j / 2) * a.pw + a.ia + i / 2 : 0;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const double e = equilibrium<LAT>(q, rho, ux, uy, uz);
-    a.ff_out[q * a.nf + p] = f[q] - (f[q] - e) / a.tf;
+    if (keep) a.ff_out[q * a.nf + p] = f[q] - (f[q] - e) / a.tf;
     if (rs) a.fc_out[q * a.nc + m] = e + 2.0 * (a.tc - 1.0) / a.tf * (f[q] - e);
   }
 }
@@ -454,7 +468,9 @@ int q_of(int lattice) { return lattice == LSB_D2Q9 ? 9 : (lattice == LSB_D3Q19 ?
 
 struct lsb_ref {
   lsb_ref_params P;
-  RefArgs base;
+  RefArgs base;  // levels 0 and 1
+  int L = 2;
+  RefArgs deep[LSB_REF_MAX_LEVELS];  // deep[l], l >= 2: levels l - 1 and l
   int Q = 9;
   int ext[3] = {0, 0, 0};  // largest patch extents (coarse cells per axis) the workspace holds
   long fcap = 0, bcap = 0;  // fine nodes with the shell, box-surface nodes, at those extents
@@ -464,7 +480,10 @@ struct lsb_ref {
   double* fc[2] = {nullptr, nullptr};
   double* ff[2] = {nullptr, nullptr};
   double* g[2] = {nullptr, nullptr};
+  double* dff[LSB_REF_MAX_LEVELS][2] = {};
+  double* dg[LSB_REF_MAX_LEVELS][2] = {};
   int cur = 0;  // fc[cur] and g[cur] are the current coarse state and G(t); ff[0] the fine state
+  int dcur[LSB_REF_MAX_LEVELS] = {};  // dg[l][dcur[l]] is level l's G(t); dff[l][0] its state
   bool inited = false;
 };
 
@@ -473,7 +492,36 @@ size_t sizes(const lsb_ref* r, size_t* fcb, size_t* ffb, size_t* gb) {
   *fcb = align256(sizeof(double) * r->Q * (size_t)r->base.nc);
   *ffb = align256(sizeof(double) * r->Q * (size_t)r->fcap);
   *gb = align256(sizeof(double) * r->Q * (size_t)r->bcap);
-  return 2 * (*fcb + *ffb + *gb) + align256(sizeof(int) * 6 * (kSensorBlocks + 1));
+  size_t t = 2 * (*fcb + *ffb + *gb) + align256(sizeof(int) * 6 * (kSensorBlocks + 1));
+  for (int l = 2; l < r->L; ++l)
+    t += 2 * (align256(sizeof(double) * r->Q * (size_t)r->deep[l].nf) +
+              align256(sizeof(double) * r->Q * (size_t)r->deep[l].nb));
+  return t;
+}
+
+// the pair args of level l >= 1 (level l - 1 as the parent)
+const RefArgs& pair_of(const lsb_ref* r, int l) { return l == 1 ? r->base : r->deep[l]; }
+
+// a refined level as the parent of the next
+void set_parent(RefArgs& a, const RefArgs& pp) {
+  a.nx = pp.mx + 1;
+  a.ny = pp.my + 1;
+  a.nz = pp.mz + 1;
+  a.pw = pp.fw;
+  a.ph = pp.fh;
+  a.po = (pp.D == 3 ? (long)pp.fh * pp.fw : 0L) + pp.fw + 1;
+  a.nc = pp.nf;
+  a.tc = pp.tf;
+  a.tf = 2.0 * pp.tf - 0.5;
+}
+
+Grid grid_of(const lsb_ref* r, int l) {
+  if (l == 0) {
+    const RefArgs& b = r->base;
+    return Grid{b.nx, b.ny, b.nz, b.nx, b.ny, 0L, b.nc};
+  }
+  const RefArgs& a = pair_of(r, l);
+  return Grid{a.mx + 1, a.my + 1, a.mz + 1, a.fw, a.fh, (a.D == 3 ? (long)a.fh * a.fw : 0L) + a.fw + 1, a.nf};
 }
 
 int check_launch() {
@@ -488,20 +536,56 @@ unsigned grid_for(long n) {
 }
 
 template <int LAT>
-void launch_init(lsb_ref* r, const double* rc, const double* uc, const double* rf, const double* uf, hipStream_t st) {
-  const RefArgs& b = r->base;
-  const long total = b.nc + (long)(b.mx + 1) * (b.my + 1) * (b.mz + 1);
-  k_ref_init<LAT><<<grid_for(total), 256, 0, st>>>(b, rc, uc, rf, uf, r->fc[0], r->ff[0], r->g[0]);
+void launch_init(lsb_ref* r, const double* const* rho, const double* const* u, hipStream_t st) {
+  for (int l = 0; l < r->L; ++l) {
+    const Grid g = grid_of(r, l);
+    double* f = l == 0 ? r->fc[0] : (l == 1 ? r->ff[0] : r->dff[l][0]);
+    const bool child = l + 1 < r->L;
+    const RefArgs& c = child ? pair_of(r, l + 1) : r->base;
+    double* cg0 = !child ? nullptr : (l == 0 ? r->g[0] : r->dg[l + 1][0]);
+    k_ref_init_level<LAT><<<grid_for((long)g.sx * g.sy * g.sz), 256, 0, st>>>(g, rho[l], u[l], f, child ? 1 : 0, c,
+                                                                                cg0);
+  }
+}
+
+// the two sub-steps of refined level l within one step of its parent (whose
+// new populations, parent_out, receive the restriction), each followed by
+// the child's
+template <int LAT>
+void advance(lsb_ref* r, int l, double* parent_out, hipStream_t st) {
+  RefArgs A = pair_of(r, l);
+  double** ffl = l == 1 ? r->ff : r->dff[l];
+  A.g0 = l == 1 ? r->g[r->cur] : r->dg[l][r->dcur[l]];
+  A.g1 = l == 1 ? r->g[r->cur ^ 1] : r->dg[l][r->dcur[l] ^ 1];
+  A.fc_out = parent_out;
+  const int sf = (A.mx + 1 + 255) / 256;
+  const unsigned gf = (unsigned)((long)sf * (A.my + 1) * (A.mz + 1));
+  const long surf = 2L * (A.my + 1) * (A.mz + 1) + 2L * (A.mx - 1) * (A.mz + 1) +
+                    (A.D == 3 ? 2L * (A.mx - 1) * (A.my - 1) : 0L);
+  // inward populations of both sub-steps: G halfway in time, then G(t+1)
+  k_ref_edge<LAT><<<dim3((unsigned)((surf + 255) / 256), 2), 256, 0, st>>>(A, ffl[0], ffl[1]);
+  const bool child = l + 1 < r->L;
+  for (int s = 0; s < 2; ++s) {
+    A.ff_in = ffl[s];
+    A.ff_out = ffl[s ^ 1];
+    // sub-step 2 also restricts onto the parent's covered nodes
+    if (child) {
+      RefArgs C = r->deep[l + 1];
+      C.g1 = r->dg[l + 1][r->dcur[l + 1] ^ 1];
+      k_ref_fine<LAT, true><<<gf, 256, 0, st>>>(A, C, sf, s);
+      advance<LAT>(r, l + 1, ffl[s ^ 1], st);
+      r->dcur[l + 1] ^= 1;
+    } else {
+      k_ref_fine<LAT, false><<<gf, 256, 0, st>>>(A, A, sf, s);
+    }
+  }
 }
 
 template <int LAT>
 void launch_steps(lsb_ref* r, int nsteps, hipStream_t st) {
   const RefArgs& b = r->base;
-  const int sc = (b.nx + 255) / 256, sf = (b.mx + 1 + 255) / 256;
-  const unsigned gc = (unsigned)((long)sc * b.ny * b.nz), gf = (unsigned)((long)sf * (b.my + 1) * (b.mz + 1));
-  const long surf = 2L * (b.my + 1) * (b.mz + 1) + 2L * (b.mx - 1) * (b.mz + 1) +
-                    (b.D == 3 ? 2L * (b.mx - 1) * (b.my - 1) : 0L);
-  const dim3 ge((unsigned)((surf + 255) / 256), 2);
+  const int sc = (b.nx + 255) / 256;
+  const unsigned gc = (unsigned)((long)sc * b.ny * b.nz);
   for (int s = 0; s < nsteps; ++s) {
     RefArgs a = b;
     a.fc_in = r->fc[r->cur];
@@ -509,15 +593,7 @@ void launch_steps(lsb_ref* r, int nsteps, hipStream_t st) {
     a.g0 = r->g[r->cur];
     a.g1 = r->g[r->cur ^ 1];
     k_ref_coarse<LAT><<<gc, 256, 0, st>>>(a, sc);
-    // inward populations of both fine sub-steps: G halfway in time, then G(t+1)
-    k_ref_edge<LAT><<<ge, 256, 0, st>>>(a, r->ff[0], r->ff[1]);
-    a.ff_in = r->ff[0];
-    a.ff_out = r->ff[1];
-    k_ref_fine<LAT><<<gf, 256, 0, st>>>(a, sf, 0);
-    // sub-step 2 also restricts onto the covered coarse nodes
-    a.ff_in = r->ff[1];
-    a.ff_out = r->ff[0];
-    k_ref_fine<LAT><<<gf, 256, 0, st>>>(a, sf, 1);
+    advance<LAT>(r, 1, r->fc[r->cur ^ 1], st);
     r->cur ^= 1;
   }
 }
@@ -565,7 +641,34 @@ int lsb_ref_create(const lsb_ref_params* P, lsb_ref** out) {
   a.nc = (long)nx * ny * nz;
   a.tc = P->tau_c;
   a.tf = 2.0 * P->tau_c - 0.5;
+  a.pw = nx;
+  a.ph = ny;
+  a.po = 0;
   set_patch(a, P->patch);
+  r->L = P->levels == 0 ? 2 : P->levels;
+  if (r->L < 2 || r->L > LSB_REF_MAX_LEVELS) {
+    delete r;
+    return fail(LSB_EINVAL, "levels must be 2 .. LSB_REF_MAX_LEVELS");
+  }
+  for (int l = 2; l < r->L; ++l) {
+    const RefArgs& pp = pair_of(r, l - 1);
+    const int* bx = P->inner[l - 2];
+    const int m[3] = {pp.mx, pp.my, pp.mz};
+    for (int d = 0; d < (three ? 3 : 2); ++d)
+      if (bx[2 * d] < 1 || bx[2 * d + 1] > m[d] - 1 || bx[2 * d + 1] - bx[2 * d] < 2) {
+        delete r;
+        return fail(LSB_EINVAL, "an inner patch must lie inside its parent level with one node to spare and span >= 2 cells per axis");
+      }
+    RefArgs& c = r->deep[l];
+    c = RefArgs{};
+    c.D = a.D;
+    set_parent(c, pp);
+    set_patch(c, bx);
+    if (c.nf > (1L << 31)) {
+      delete r;
+      return fail(LSB_EINVAL, "grid too large");
+    }
+  }
   *out = r;
   return LSB_OK;
 }
@@ -593,26 +696,45 @@ int lsb_ref_bind(lsb_ref* r, void* ws, size_t bytes) {
     p += gb;
   }
   r->sens = reinterpret_cast<int*>(p);
+  p += align256(sizeof(int) * 6 * (kSensorBlocks + 1));
+  for (int l = 2; l < r->L; ++l)
+    for (int k = 0; k < 2; ++k) {
+      r->dff[l][k] = reinterpret_cast<double*>(p);
+      p += align256(sizeof(double) * r->Q * (size_t)r->deep[l].nf);
+      r->dg[l][k] = reinterpret_cast<double*>(p);
+      p += align256(sizeof(double) * r->Q * (size_t)r->deep[l].nb);
+    }
   r->ws = static_cast<char*>(ws);
   r->ws_bytes = bytes;
   r->inited = false;
   return LSB_OK;
 }
 
-int lsb_ref_init(lsb_ref* r, const double* rho_c, const double* u_c, const double* rho_f, const double* u_f,
-                 void* stream) {
-  if (!r || !rho_c || !u_c || !rho_f || !u_f) return fail(LSB_EINVAL, "null pointer");
+int lsb_ref_init_levels(lsb_ref* r, const double* const* rho, const double* const* u, void* stream) {
+  if (!r || !rho || !u) return fail(LSB_EINVAL, "null pointer");
+  for (int l = 0; l < r->L; ++l)
+    if (!rho[l] || !u[l]) return fail(LSB_EINVAL, "null pointer");
   if (!r->ws) return fail(LSB_ESTATE, "lsb_ref_init before lsb_ref_bind");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   r->cur = 0;
+  for (int l = 0; l < LSB_REF_MAX_LEVELS; ++l) r->dcur[l] = 0;
   switch (r->P.lattice) {
-    case LSB_D2Q9: launch_init<LSB_D2Q9>(r, rho_c, u_c, rho_f, u_f, st); break;
-    case LSB_D3Q19: launch_init<LSB_D3Q19>(r, rho_c, u_c, rho_f, u_f, st); break;
-    default: launch_init<LSB_D3Q27>(r, rho_c, u_c, rho_f, u_f, st); break;
+    case LSB_D2Q9: launch_init<LSB_D2Q9>(r, rho, u, st); break;
+    case LSB_D3Q19: launch_init<LSB_D3Q19>(r, rho, u, st); break;
+    default: launch_init<LSB_D3Q27>(r, rho, u, st); break;
   }
   if (int e = check_launch()) return e;
   r->inited = true;
   return LSB_OK;
+}
+
+int lsb_ref_init(lsb_ref* r, const double* rho_c, const double* u_c, const double* rho_f, const double* u_f,
+                 void* stream) {
+  if (!r || !rho_c || !u_c || !rho_f || !u_f) return fail(LSB_EINVAL, "null pointer");
+  if (r->L != 2) return fail(LSB_EINVAL, "lsb_ref_init takes two levels; use lsb_ref_init_levels");
+  const double* rho[2] = {rho_c, rho_f};
+  const double* u[2] = {u_c, u_f};
+  return lsb_ref_init_levels(r, rho, u, stream);
 }
 
 int lsb_ref_step(lsb_ref* r, int nsteps, void* stream) {
@@ -642,6 +764,18 @@ int lsb_ref_get_populations(lsb_ref* r, double* coarse, double* fine, void* stre
     if (int e = check_launch()) return e;
   }
   return LSB_OK;
+}
+
+int lsb_ref_get_level(lsb_ref* r, int level, double* out, void* stream) {
+  if (!r || !out) return fail(LSB_EINVAL, "null pointer");
+  if (level < 0 || level >= r->L) return fail(LSB_EINVAL, "level outside [0, levels)");
+  if (!r->inited) return fail(LSB_ESTATE, "lsb_ref_get_level before lsb_ref_init");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (level == 0) return lsb_ref_get_populations(r, out, nullptr, stream);
+  const RefArgs& a = pair_of(r, level);
+  const long n1 = (long)(a.mx + 1) * (a.my + 1) * (a.mz + 1);
+  k_ref_unpad<<<grid_for(r->Q * n1), 256, 0, st>>>(a, r->Q, level == 1 ? r->ff[0] : r->dff[level][0], out);
+  return check_launch();
 }
 
 int lsb_ref_sensor(lsb_ref* r, const double* phi, double d_ref, int margin, int* patch, void* stream) {
@@ -682,6 +816,7 @@ int lsb_ref_sensor(lsb_ref* r, const double* phi, double d_ref, int margin, int*
 int lsb_ref_remesh(lsb_ref* r, const int* patch, void* stream) {
   if (!r || !patch) return fail(LSB_EINVAL, "null pointer");
   if (!r->inited) return fail(LSB_ESTATE, "lsb_ref_remesh before lsb_ref_init");
+  if (r->L != 2) return fail(LSB_EINVAL, "re-meshing takes a two-level hierarchy");
   const RefArgs& b = r->base;
   const int n[3] = {b.nx, b.ny, b.nz};
   for (int d = 0; d < b.D; ++d) {

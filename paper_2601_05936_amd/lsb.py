@@ -52,14 +52,18 @@ EXPORTS = [
     "lsb_adjoint_record", "lsb_adjoint_seed_centroid", "lsb_adjoint_reverse", "lsb_adjoint_initial",
     "lsb_last_error",
     "lsb_ref_create", "lsb_ref_destroy", "lsb_ref_workspace_bytes", "lsb_ref_bind", "lsb_ref_init", "lsb_ref_step",
-    "lsb_ref_get_populations", "lsb_ref_sensor", "lsb_ref_remesh",
+    "lsb_ref_get_populations", "lsb_ref_sensor", "lsb_ref_remesh", "lsb_ref_init_levels", "lsb_ref_get_level",
 ]
+
+
+REF_MAX_LEVELS = 4  # LSB_REF_MAX_LEVELS
 
 
 class RefParams(C.Structure):
     """Mirror of lsb_ref_params (include/lsb_refine.h)."""
     _fields_ = [("lattice", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("patch", C.c_int * 6),
-                ("tau_c", C.c_double), ("max_extent", C.c_int * 3)]
+                ("tau_c", C.c_double), ("max_extent", C.c_int * 3), ("levels", C.c_int),
+                ("inner", (C.c_int * 6) * (REF_MAX_LEVELS - 2))]
 SCHED_SERIAL, SCHED_OVERLAP = 0, 1
 MAX_BUBBLES = 64  # LSB_MAX_BUBBLES
 
@@ -117,6 +121,8 @@ def load() -> C.CDLL:
     lib.lsb_ref_get_populations.argtypes = [vp, vp, vp, vp]
     lib.lsb_ref_sensor.argtypes = [vp, vp, C.c_double, C.c_int, C.POINTER(C.c_int), vp]
     lib.lsb_ref_remesh.argtypes = [vp, C.POINTER(C.c_int), vp]
+    lib.lsb_ref_init_levels.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
+    lib.lsb_ref_get_level.argtypes = [vp, C.c_int, vp, vp]
     _lib = lib
     return lib
 
@@ -327,11 +333,13 @@ class Sim:
 
 
 class Refine:
-    """Two-level static refinement (BGK, FP64, ratio 2) on one GPU: lattice
-    D2Q9, D3Q19 or D3Q27; the coarse grid nx x ny (x nz), periodic, and a
-    fine patch over the coarse nodes patch = (ia, ib, ja, jb[, ka, kb]).
-    Device memory is a torch uint8 tensor (the caller-owned workspace);
-    calls run on torch's current stream."""
+    """Static refinement (BGK, FP64, ratio 2) on one GPU: lattice D2Q9, D3Q19
+    or D3Q27; the coarse grid nx x ny (x nz), periodic, and a fine patch over
+    the coarse nodes patch = (ia, ib, ja, jb[, ka, kb]); or nested patches, a
+    list of such boxes (level 1 first, each in its parent level's node
+    coordinates; two to four levels in all).  Device memory is a torch
+    uint8 tensor (the caller-owned workspace); calls run on torch's current
+    stream."""
 
     def __init__(self, nx: int, ny: int, patch, tau_c: float, device="cuda:0", lattice: int = D2Q9, nz: int = 1,
                  max_extent=(0, 0, 0)):
@@ -342,14 +350,18 @@ class Refine:
         self.lattice = int(lattice)
         self.D, self.Q = (2, 9) if self.lattice == D2Q9 else (3, 19 if self.lattice == D3Q19 else 27)
         self.nx, self.ny, self.nz = int(nx), int(ny), (int(nz) if self.D == 3 else 1)
-        p = tuple(int(v) for v in patch) + (0, 0)
-        ia, ib, ja, jb, ka, kb = p[:6] if self.D == 3 else p[:4] + (0, 0)
-        self.patch = (ia, ib, ja, jb, ka, kb)
-        self.mx, self.my, self.mz = 2 * (ib - ia), 2 * (jb - ja), 2 * (kb - ka)
-        self.n_coarse = self.nx * self.ny * self.nz
-        self.n_fine = (self.mx + 1) * (self.my + 1) * (self.mz + 1)
-        self._cp = RefParams(self.lattice, self.nx, self.ny, self.nz, (C.c_int * 6)(*self.patch), float(tau_c),
-                             (C.c_int * 3)(*[int(v) for v in max_extent]))
+        boxes = [patch] if np.isscalar(patch[0]) else list(patch)
+        self.boxes = []
+        for bx in boxes:
+            p = tuple(int(v) for v in bx) + (0, 0)
+            self.boxes.append(p[:6] if self.D == 3 else p[:4] + (0, 0))
+        self.levels = len(self.boxes) + 1
+        inner = ((C.c_int * 6) * (REF_MAX_LEVELS - 2))()
+        for l, bx in enumerate(self.boxes[1:REF_MAX_LEVELS - 1]):
+            inner[l] = (C.c_int * 6)(*bx)
+        self._cp = RefParams(self.lattice, self.nx, self.ny, self.nz, (C.c_int * 6)(*self.boxes[0]), float(tau_c),
+                             (C.c_int * 3)(*[int(v) for v in max_extent]), self.levels, inner)
+        self._sync_level1()
         h = C.c_void_p()
         _check(self.lib.lsb_ref_create(C.byref(self._cp), C.byref(h)))
         self.h = h
@@ -357,6 +369,23 @@ class Refine:
         _check(self.lib.lsb_ref_workspace_bytes(self.h, C.byref(nb)))
         self.ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
         _check(self.lib.lsb_ref_bind(self.h, C.c_void_p(self.ws.data_ptr()), nb.value))
+
+    def _sync_level1(self):
+        ia, ib, ja, jb, ka, kb = self.boxes[0]
+        self.patch = self.boxes[0]
+        self.mx, self.my, self.mz = 2 * (ib - ia), 2 * (jb - ja), 2 * (kb - ka)
+        self.n_coarse = self.nx * self.ny * self.nz
+        self.n_fine = (self.mx + 1) * (self.my + 1) * (self.mz + 1)
+
+    def shape(self, level: int):
+        """Nodes per axis (x, y, z) of a level."""
+        if level == 0:
+            return self.nx, self.ny, self.nz
+        ia, ib, ja, jb, ka, kb = self.boxes[level - 1]
+        return 2 * (ib - ia) + 1, 2 * (jb - ja) + 1, 2 * (kb - ka) + 1
+
+    def n_level(self, level: int) -> int:
+        return int(np.prod(self.shape(level)))
 
     def __del__(self):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -372,11 +401,20 @@ class Refine:
         assert t.numel() == n, (t.numel(), n)
         return t.to(self.device).contiguous()
 
-    def init(self, rho_c, u_c, rho_f, u_f):
-        """rho [nodes], u [nodes, D] per level (numpy or torch)."""
-        t = [self._dev(rho_c, self.n_coarse), self._dev(u_c, self.D * self.n_coarse), self._dev(rho_f, self.n_fine),
-             self._dev(u_f, self.D * self.n_fine)]
-        _check(self.lib.lsb_ref_init(self.h, *[C.c_void_p(x.data_ptr()) for x in t], self.stream()))
+    def init(self, rho_c, u_c, rho_f, u_f, *deeper):
+        """rho [nodes], u [nodes, D] per level (numpy or torch): the coarse
+        and level-1 arrays, then (rho, u) of each deeper level."""
+        arrs = [rho_c, u_c, rho_f, u_f] + list(deeper)
+        if len(arrs) != 2 * self.levels:
+            raise ValueError("one (rho, u) pair per level expected")
+        t = []
+        for l in range(self.levels):
+            n = self.n_level(l)
+            t += [self._dev(arrs[2 * l], n), self._dev(arrs[2 * l + 1], self.D * n)]
+        vp = C.c_void_p
+        rho = (vp * self.levels)(*[t[2 * l].data_ptr() for l in range(self.levels)])
+        u = (vp * self.levels)(*[t[2 * l + 1].data_ptr() for l in range(self.levels)])
+        _check(self.lib.lsb_ref_init_levels(self.h, rho, u, self.stream()))
         self.torch.cuda.current_stream(self.device).synchronize()
         return self
 
@@ -395,24 +433,23 @@ class Refine:
         return tuple(out)
 
     def remesh(self, patch):
-        """Re-mesh onto patch (6 ints; ka, kb ignored in 2D)."""
+        """Re-mesh a two-level hierarchy onto patch (6 ints; ka, kb ignored in
+        2D)."""
         p = (tuple(int(v) for v in patch) + (0, 0))[:6]
         _check(self.lib.lsb_ref_remesh(self.h, (C.c_int * 6)(*p), self.stream()))
-        ia, ib, ja, jb, ka, kb = p if self.D == 3 else p[:4] + (0, 0)
-        self.patch = (ia, ib, ja, jb, ka, kb)
-        self.mx, self.my, self.mz = 2 * (ib - ia), 2 * (jb - ja), 2 * (kb - ka)
-        self.n_fine = (self.mx + 1) * (self.my + 1) * (self.mz + 1)
+        self.boxes[0] = p if self.D == 3 else p[:4] + (0, 0)
+        self._sync_level1()
         return self
 
-    def populations(self, as_numpy=True):
+    def level(self, l: int, as_numpy=True):
+        """Post-collision populations of level l, [Q][(nz,) ny, nx]."""
         t = self.torch
-        fc = t.empty(self.Q * self.n_coarse, dtype=t.float64, device=self.device)
-        ff = t.empty(self.Q * self.n_fine, dtype=t.float64, device=self.device)
-        _check(self.lib.lsb_ref_get_populations(self.h, C.c_void_p(fc.data_ptr()), C.c_void_p(ff.data_ptr()),
-                                                self.stream()))
-        if self.D == 2:
-            fc, ff = fc.reshape(self.Q, self.ny, self.nx), ff.reshape(self.Q, self.my + 1, self.mx + 1)
-        else:
-            fc = fc.reshape(self.Q, self.nz, self.ny, self.nx)
-            ff = ff.reshape(self.Q, self.mz + 1, self.my + 1, self.mx + 1)
-        return (fc.cpu().numpy(), ff.cpu().numpy()) if as_numpy else (fc, ff)
+        sx, sy, sz = self.shape(l)
+        f = t.empty(self.Q * sx * sy * sz, dtype=t.float64, device=self.device)
+        _check(self.lib.lsb_ref_get_level(self.h, int(l), C.c_void_p(f.data_ptr()), self.stream()))
+        f = f.reshape(self.Q, sy, sx) if self.D == 2 else f.reshape(self.Q, sz, sy, sx)
+        return f.cpu().numpy() if as_numpy else f
+
+    def populations(self, as_numpy=True):
+        """Every level's post-collision populations, coarse first."""
+        return tuple(self.level(l, as_numpy) for l in range(self.levels))

@@ -109,8 +109,11 @@ def test_reverse_mode_rejects_per_bubble_baselines():
 def _ref_create(**kw):
     p = dict(lattice=lsb.D2Q9, nx=32, ny=24, nz=1, patch=(8, 20, 6, 16, 0, 0), tau_c=0.7)
     p.update(kw)
+    inner = ((C.c_int * 6) * (lsb.REF_MAX_LEVELS - 2))()
+    for l, bx in enumerate(p.get("inner", ())):
+        inner[l] = (C.c_int * 6)(*bx)
     cp = lsb.RefParams(p["lattice"], p["nx"], p["ny"], p["nz"], (C.c_int * 6)(*p["patch"]), p["tau_c"],
-                       (C.c_int * 3)(*p.get("max_extent", (0, 0, 0))))
+                       (C.c_int * 3)(*p.get("max_extent", (0, 0, 0))), p.get("levels", 0), inner)
     h = C.c_void_p()
     rc = lsb.load().lsb_ref_create(C.byref(cp), C.byref(h))
     return rc, h
@@ -124,6 +127,13 @@ def _ref_create(**kw):
     dict(lattice=lsb.D3Q27, nz=16, patch=(8, 20, 6, 16, 0, 9)),                 # 3D: ka < 1
     dict(lattice=lsb.D3Q19, nz=3, patch=(8, 20, 6, 16, 1, 2)),                  # 3D: nz < 4
     dict(max_extent=(30, 0, 0)),                                                # beyond n - 3
+    dict(levels=1), dict(levels=5),
+    dict(levels=3, inner=[(0, 10, 2, 12, 0, 0)]),                               # level 2 touches level 1's edge
+    dict(levels=3, inner=[(2, 24, 2, 12, 0, 0)]),                               # level 1 has nodes 0 .. 24
+    dict(levels=3, inner=[(2, 3, 2, 12, 0, 0)]),                                # fewer than 2 cells
+    dict(levels=4, inner=[(2, 20, 2, 12, 0, 0), (1, 36, 3, 9, 0, 0)]),         # level 2 has nodes 0 .. 36
+    dict(lattice=lsb.D3Q19, nz=16, patch=(8, 20, 6, 16, 4, 12), levels=3,
+         inner=[(2, 20, 2, 12, 3, 16)]),                                        # 3D: kb > m - 1
 ])
 def test_refine_create_rejects_invalid_parameters(bad):
     rc, h = _ref_create(**bad)
@@ -157,3 +167,37 @@ def test_refine_workspace_layout():
         assert nb.value == 2 * (up(8 * Q * nc) + up(8 * Q * nf) + up(8 * Q * ns)) + up(4 * 6 * 1025)
         assert lib.lsb_ref_bind(h, C.c_void_p(1 << 20), nb.value - 1) == lsb.LSB_ENOMEM
         lib.lsb_ref_destroy(h)
+
+
+def test_refine_nested_workspace_layout():
+    """Nested levels append, per deeper level, 2 x (its nodes with the ghost
+    shell + its box surface) to the two-level layout."""
+    def up(v):
+        return (v + 255) // 256 * 256
+    lib = lsb.load()
+    base = dict(lattice=lsb.D3Q27, nx=20, ny=18, nz=16, patch=(5, 12, 4, 13, 6, 11))
+    rc, h2 = _ref_create(**base)
+    assert rc == lsb.LSB_OK
+    n2 = C.c_size_t()
+    assert lib.lsb_ref_workspace_bytes(h2, C.byref(n2)) == lsb.LSB_OK
+    boxes = [(2, 12, 3, 15, 1, 9), (4, 18, 2, 20, 3, 14)]
+    rc, h = _ref_create(levels=4, inner=boxes, **base)
+    assert rc == lsb.LSB_OK, lib.lsb_last_error()
+    nb = C.c_size_t()
+    assert lib.lsb_ref_workspace_bytes(h, C.byref(nb)) == lsb.LSB_OK
+    extra = 0
+    for ia, ib, ja, jb, ka, kb in boxes:
+        mx, my, mz = 2 * (ib - ia), 2 * (jb - ja), 2 * (kb - ka)
+        bw, bh, bd = ib - ia + 1, jb - ja + 1, kb - ka + 1
+        nf = (mx + 3) * (my + 3) * (mz + 3)
+        ns = 2 * bh * bd + 2 * bw * bd + 2 * bw * bh
+        extra += 2 * (up(8 * 27 * nf) + up(8 * 27 * ns))
+    assert nb.value == n2.value + extra
+    # two-level entry points refuse the deeper hierarchy before any device access
+    dummy = C.c_void_p(1)
+    assert lib.lsb_ref_init(h, dummy, dummy, dummy, dummy, None) == lsb.LSB_EINVAL
+    assert "lsb_ref_init_levels" in lib.lsb_last_error().decode()
+    assert lib.lsb_ref_get_level(h, 4, C.c_void_p(1), None) == lsb.LSB_EINVAL
+    assert lib.lsb_ref_get_level(h, 3, C.c_void_p(1), None) == lsb.LSB_ESTATE
+    lib.lsb_ref_destroy(h)
+    lib.lsb_ref_destroy(h2)

@@ -1,5 +1,6 @@
-"""Two-level static refinement (D2Q9, D3Q19, D3Q27; BGK, FP64, ratio 2) on
-the GPU against the CPU oracle, element by element on both levels.
+"""Static refinement (D2Q9, D3Q19, D3Q27; BGK, FP64, ratio 2; two to four
+nested levels) on the GPU against the CPU oracle, element by element on
+every level.
 
 The coupling follows the Dupuis-Chopard approach the paper adopts for its
 refinement jumps (Sec. 2, lattice Boltzmann method); lsb_refine.h states
@@ -7,7 +8,11 @@ the steps.  Cases: a small grid, a grid wider than one 256-lane block (the
 fine rows span two blocks with a ragged tail), the minimal 2 x 2-cell patch,
 and the benchmark's configurations (2D: 2048^2 coarse nodes with a
 1024^2-cell patch; 3D: D3Q27 192^3 with a 96^3-cell patch), which the oracle
-still finishes in seconds; in 3D also D3Q19 and a minimal patch.  Bar:
+still finishes in seconds; in 3D also D3Q19 and a minimal patch.  Nested
+levels: three and four levels in 2D and 3D, rows of the innermost level
+spanning three blocks with a ragged tail, minimal inner patches, and the
+benchmark's three-level configuration (2048^2 coarse, a 1024^2-cell level
+1, a 512^2-coarse-cell level 2 with 2049^2 nodes).  Bar:
 max |f_gpu - f_oracle| <= 1e-13 (populations are O(0.1); the two sides
 differ only in the rounding of fused multiply-adds, measured at a few 1e-16
 per step).
@@ -201,3 +206,89 @@ def test_refine_remesh_rejects_patches_beyond_the_workspace(require_gpu):
     with pytest.raises(LsbError):
         g.remesh((5, 20, 10, 20))      # 15 cells in x > 14
     g.remesh((6, 20, 10, 24))          # 14 x 14 fits
+
+
+# --- nested levels ---
+
+def _fields_nested(o, seed, amp=0.02):
+    """Smooth random density and velocity sampled on every level of oracle o."""
+    rng = np.random.default_rng(seed)
+    n = np.array([o.nx, o.ny, o.nz], dtype=float)
+    kk = rng.integers(1, 3, (4, 3))
+    ph = rng.uniform(0, 2 * np.pi, 4)
+    args = []
+    for lv in range(o.levels):
+        xyz = list(o.coords(lv)) + [0.0] * (3 - o.D)
+        s = [np.sin(2 * np.pi * sum(kk[m, d] * xyz[d] / n[d] for d in range(3)) + ph[m]) for m in range(4)]
+        u = np.stack([amp * s[1], amp * s[2], amp * s[3]][:o.D], 1)
+        args += [1.0 + 0.5 * amp * s[0], u]
+    return args
+
+
+def _run_nested(lattice, n3, boxes, tau_c, steps, seed):
+    from paper_2601_05936_amd.lsb import Refine
+    nx, ny, nz = n3
+    o = RefineOracle(nx, ny, boxes, tau_c, lattice=lattice, nz=nz)
+    args = _fields_nested(o, seed)
+    g = Refine(nx, ny, boxes, tau_c, lattice=lattice, nz=nz)
+    o.init(*args)
+    g.init(*args)
+    o.step(steps)
+    g.step(steps)
+    return o.populations(), g.populations()
+
+
+@pytest.mark.parametrize("lattice,n3,boxes,tau_c,steps", [
+    (0, (40, 36, 1), [(8, 30, 7, 28), (3, 40, 4, 38)], 0.7, 10),
+    (0, (300, 30, 1), [(50, 250, 4, 25), (10, 390, 3, 40)], 0.62, 4),   # level-2 rows of 761 nodes
+    (0, (30, 30, 1), [(6, 22, 5, 21), (3, 27, 4, 30), (2, 44, 3, 50)], 0.8, 6),   # four levels
+    (0, (12, 12, 1), [(3, 6, 2, 5), (1, 3, 1, 3)], 0.9, 8),             # minimal inner patch
+    (1, (14, 14, 14), [(3, 10, 4, 11, 2, 9), (2, 12, 1, 12, 3, 11)], 0.7, 6),
+    (2, (20, 18, 16), [(5, 12, 4, 13, 6, 11), (2, 12, 3, 15, 1, 9)], 0.62, 4),
+    (2, (10, 10, 10), [(2, 6, 2, 6, 2, 6), (2, 5, 2, 6, 1, 4), (1, 4, 2, 5, 1, 4)], 0.75, 3),  # four levels
+])
+def test_nested_matches_oracle(require_gpu, lattice, n3, boxes, tau_c, steps):
+    ref, got = _run_nested(lattice, n3, boxes, tau_c, steps, seed=sum(n3) + len(boxes))
+    errs = [float(np.max(np.abs(g - o))) for o, g in zip(ref, got)]
+    print(f"nested D={2 if lattice == 0 else 3} Q{ref[0].shape[0]} {n3} {len(boxes) + 1} levels: "
+          + " ".join(f"{e:.2e}" for e in errs), flush=True)
+    assert all(g.shape == o.shape for o, g in zip(ref, got))
+    assert max(errs) <= TOL
+
+
+def test_nested_benchmark_configuration(require_gpu):
+    """2048^2 coarse nodes, level 1 over [512, 1536]^2, level 2 over level-1
+    nodes [512, 1536]^2 (2049^2 nodes each), the launch configuration of the
+    benchmark's three-level leg, 2 coarse steps."""
+    ref, got = _run_nested(0, (2048, 2048, 1), [(512, 1536, 512, 1536)] * 2, 0.6, 2, seed=3)
+    errs = [float(np.max(np.abs(g - o))) for o, g in zip(ref, got)]
+    print("nested 2048^2 three levels: " + " ".join(f"{e:.2e}" for e in errs), flush=True)
+    assert max(errs) <= TOL
+
+
+def test_nested_uniform_state_is_fixed(require_gpu):
+    from paper_2601_05936_amd.lsb import Refine
+    boxes = [(5, 12, 4, 13, 6, 11), (2, 12, 3, 15, 1, 9)]
+    g = Refine(20, 18, boxes, 0.7, lattice=2, nz=16)
+    u = np.array([0.04, -0.03, 0.02])
+    args = []
+    for lv in range(3):
+        args += [np.full(g.n_level(lv), 1.02), np.tile(u, g.n_level(lv))]
+    g.init(*args)
+    f0 = g.populations()
+    g.step(3)
+    for a, b in zip(g.populations(), f0):
+        assert np.max(np.abs(a - b)) < 1e-15
+
+
+def test_nested_rejects_two_level_calls(require_gpu):
+    from paper_2601_05936_amd.lsb import LsbError, Refine
+    g = Refine(30, 30, [(6, 22, 5, 21), (3, 27, 4, 30)], 0.7)
+    with pytest.raises(LsbError):
+        g.remesh((5, 20, 5, 20))   # before init: state error
+    args = []
+    for lv in range(3):
+        args += [np.ones(g.n_level(lv)), np.zeros(2 * g.n_level(lv))]
+    g.init(*args)
+    with pytest.raises(LsbError):
+        g.remesh((5, 20, 5, 20))   # re-meshing takes two levels
