@@ -241,6 +241,54 @@ def run_refine3d(steps: int, warmup: int):
     return res
 
 
+def run_refine_nested(steps: int, warmup: int):
+    """Three nested levels (D2Q9, BGK, FP64, ratio 2 at each jump): 2048^2
+    coarse nodes, periodic; level 1 over the coarse nodes [512, 1536]^2
+    (2049^2 nodes); level 2 over level 1's nodes [512, 1536]^2 (2049^2
+    nodes at a quarter of the coarse spacing, four steps per coarse step);
+    synthetic smooth shear and density fields.  Node updates per second and
+    the whole step's rate against 144 algorithmic bytes per node update
+    (covered nodes are not updated)."""
+    import numpy as np
+    import torch
+
+    from paper_2601_05936_amd.lsb import Refine
+    n, box, tau_c = 2048, (512, 1536, 512, 1536), 0.6
+    g = Refine(n, n, [box, box], tau_c)
+
+    def fields(x, y):
+        s = np.sin(2 * np.pi * y / n)
+        return 1.0 + 0.005 * np.cos(2 * np.pi * x / n), np.stack([0.02 * s, 0.01 * np.sin(2 * np.pi * x / n)], 1)
+    args = []
+    ox, oy, h = 0.0, 0.0, 1.0
+    for lv in range(3):
+        if lv:
+            ox, oy, h = ox + h * box[0], oy + h * box[2], 0.5 * h
+        sx, sy, _ = g.shape(lv)
+        J, I = np.meshgrid(np.arange(sy), np.arange(sx), indexing="ij")
+        args += list(fields(ox + h * I.reshape(-1), oy + h * J.reshape(-1)))
+    g.init(*args)
+    del args
+    g.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    cov = (box[1] - box[0] - 1) * (box[3] - box[2] - 1)
+    updates = (n * n - cov) + 2 * (g.n_level(1) - cov) + 4 * g.n_level(2)
+    gbs = updates * 144 / (ms * 1e-3) / 1e9
+    res = dict(workload="D2Q9 three-level static refinement, 2048^2 coarse, level 1 [512,1536]^2 (2049^2), "
+                        "level 2 [512,1536]^2 of level 1 (2049^2)",
+               steps=steps, warmup=warmup, ms_per_step=ms, node_updates_per_step=updates,
+               mlups=updates / (ms * 1e-3) / 1e6, gbs=gbs, frac=gbs / HBM_PEAK_GBS, bytes_per_update=144,
+               dtype="f64")
+    log(f"[refine_nested] {res}")
+    return res
+
+
 def cpu_baseline(seconds: float):
     """The CPU oracle (as it stands) on a bounded sample of the workload:
     the same problem at 128^3 (interface amplitude scaled to 2)."""
@@ -285,7 +333,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="reverse-mode run length (0: skip)")
     ap.add_argument("--refine-steps", type=int, default=100,
-                    help="two-level refinement run length in coarse steps, 2D and 3D legs (0: skip)")
+                    help="refinement run length in coarse steps: two-level 2D and 3D legs, three-level "
+                         "2D leg (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (counter calibration)")
@@ -360,6 +409,7 @@ def main():
     if args.refine_steps > 0:
         out["refine"] = run_refine(args.refine_steps, 10)
         out["refine3d"] = run_refine3d(args.refine_steps, 10)
+        out["refine_nested"] = run_refine_nested(args.refine_steps, 10)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
