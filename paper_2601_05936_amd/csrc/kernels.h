@@ -994,7 +994,11 @@ __global__ __launch_bounds__(256) void k_ext_seed_iface(const typename Step<LAT,
 }
 
 // One forward-Euler sweep of the first-order upwind extension; interface
-// cells are held.  Reads ut_a, writes ut_b.
+// cells are held.  Reads ut_a, writes ut_b.  The upwind neighbours'
+// velocities of all axes are loaded together, with no branch on the
+// coefficients (an axis with a zero coefficient reads the cell itself); the
+// compiler still tests the tag first, which keeps inactive lanes from
+// loading at all (issuing every load ahead of that test measured slower).
 template <int LAT, int ST>
 __global__ __launch_bounds__(256) void k_ext_iter(const typename Step<LAT, ST>::Args a) {
   using S = Step<LAT, ST>;
@@ -1002,30 +1006,31 @@ __global__ __launch_bounds__(256) void k_ext_iter(const typename Step<LAT, ST>::
   const size_t N = a.N;
   for_tile_cells<S::D>(a, a.tile_list, a.counters[CNT_TILES], [&](int c, int x, int y, int z) {
     const uint8_t t = a.tag[c];
-    if (!(t & T_ACT)) return;
-    R u[3] = {a.ut_a[c], a.ut_a[N + c], a.ut_a[2 * N + c]};
-    if (!(t & T_SPEC)) {
-      const int pos[3] = {x, y, z};
-      const int n[3] = {a.nx, a.ny, a.nz};
-      R out[3] = {u[0], u[1], u[2]};
-      for (int ax = 0; ax < S::D; ++ax) {
-        const R kk = a.ext_k[ax * N + c];
-        if (kk == (R)0) continue;
-        const int sv = lb_coord(pos[ax] + (kk > (R)0 ? -1 : 1), sel3(n, ax), sel3(a.per, ax));
-        int p2[3] = {x, y, z};
-        p2[ax] = sv;
-        const int nc = (p2[2] * a.ny + p2[1]) * a.nx + p2[0];
-        for (int m = 0; m < 3; ++m) {
-          const R un = a.ut_a[m * N + nc];
-          const R diff = kk > (R)0 ? (u[m] - un) : (un - u[m]);
-          out[m] -= kk * diff;
-        }
-      }
-      u[0] = out[0]; u[1] = out[1]; u[2] = out[2];
+    const R u[3] = {a.ut_a[c], a.ut_a[N + c], a.ut_a[2 * N + c]};
+    R kk[S::D];
+    for (int ax = 0; ax < S::D; ++ax) kk[ax] = a.ext_k[ax * N + c];
+    const int pos[3] = {x, y, z};
+    const int n[3] = {a.nx, a.ny, a.nz};
+    R un[S::D][3];
+    for (int ax = 0; ax < S::D; ++ax) {
+      const int sv = lb_coord(pos[ax] + (kk[ax] > (R)0 ? -1 : 1), sel3(n, ax), sel3(a.per, ax));
+      int p2[3] = {x, y, z};
+      p2[ax] = ((kk[ax] != (R)0) & (sv >= 0)) ? sv : pos[ax];
+      const int nc = (p2[2] * a.ny + p2[1]) * a.nx + p2[0];
+      for (int m = 0; m < 3; ++m) un[ax][m] = a.ut_a[m * N + nc];
     }
-    a.ut_b[c] = u[0];
-    a.ut_b[N + c] = u[1];
-    a.ut_b[2 * N + c] = u[2];
+    R out[3] = {u[0], u[1], u[2]};
+    for (int ax = 0; ax < S::D; ++ax)
+      for (int m = 0; m < 3; ++m) {
+        const R diff = kk[ax] > (R)0 ? (u[m] - un[ax][m]) : (un[ax][m] - u[m]);
+        const R v = out[m] - kk[ax] * diff;
+        out[m] = kk[ax] != (R)0 ? v : out[m];
+      }
+    if (!(t & T_ACT)) return;
+    const bool held = (t & T_SPEC) != 0;
+    a.ut_b[c] = held ? u[0] : out[0];
+    a.ut_b[N + c] = held ? u[1] : out[1];
+    a.ut_b[2 * N + c] = held ? u[2] : out[2];
   });
 }
 
