@@ -126,6 +126,8 @@ def _load():
                                     C.POINTER(C.c_double)]
     lib.orc_mref_init.argtypes = [C.c_void_p, C.POINTER(dp), C.POINTER(dp)]
     lib.orc_mref_get.argtypes = [C.c_void_p, C.c_int, dp]
+    lib.orc_ref_sensor_levels.argtypes = [C.c_void_p, dp, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    lib.orc_ref_remesh_levels.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
     _lib = lib
     return lib
 
@@ -509,6 +511,32 @@ class RefineOracle:
         if self.D == 2:
             ka = kb = 0
         self.boxes[0] = (ia, ib, ja, jb, ka, kb)
+        self._sync_level1()
+        return self
+
+    def sensor_levels(self, phi, d_ref: float, margins):
+        """Boxes of every refined level (6 ints each, each in its parent's
+        node coordinates) from the level-set sensor on the coarse level set,
+        with margins[l - 1] coarse nodes for level l; None when no node is
+        tagged."""
+        nl = self.levels - 1
+        out = (C.c_int * (6 * nl))()
+        mg = (C.c_int * nl)(*[int(m) for m in margins])
+        keep = _f64(phi, self.n_coarse)
+        if not self._lib.orc_ref_sensor_levels(self._h, _dp(keep), float(d_ref), mg, out):
+            return None
+        return [tuple(out[6 * l:6 * l + 6]) for l in range(nl)]
+
+    def remesh_levels(self, boxes):
+        """Re-mesh every refined level onto boxes (6 ints each, level 1
+        first, each in its new parent's node coordinates)."""
+        flat = []
+        for bx in boxes:
+            p = (tuple(int(v) for v in bx) + (0, 0))[:6]
+            flat += list(p if self.D == 3 else p[:4] + (0, 0))
+        if self._lib.orc_ref_remesh_levels(self._h, (C.c_int * len(flat))(*flat)) != 0:
+            raise ValueError("a box does not fit its parent")
+        self.boxes = [tuple(flat[6 * l:6 * l + 6]) for l in range(len(boxes))]
         self._sync_level1()
         return self
 

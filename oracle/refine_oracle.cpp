@@ -274,71 +274,143 @@ struct Ref {
     return true;
   }
 
-  // Re-meshing of a two-level hierarchy onto a new patch box at the end of a
-  // coarse step (state at time t: post-collision populations of both
-  // levels, the covered coarse nodes holding restricted values).  New fine
-  // nodes inside the old patch keep the old fine populations; the others
-  // take the coarse populations interpolated like the perimeter's (the mean
-  // of the 2, 4 or 8 coarse nodes around an off-grid fine node), their
-  // non-equilibrium part scaled by the post-collision ratio
-  // (tau_f - 1) / (2 (tau_c - 1)) about the equilibrium of the interpolated
-  // moments (the equilibrium alone when tau_c = 1, where the coarse
-  // post-collision state holds no non-equilibrium part).  The new
-  // perimeter's pre-collision sets G(t) come from the coarse post-collision
-  // populations by inverting the BGK step, f_eq + tau_c / (tau_c - 1)
-  // (f - f_eq) (f_eq at tau_c = 1).  Covered coarse nodes are restricted
-  // again at the end of the next step; coarse nodes the patch no longer
-  // covers keep their restricted values.
-  void remesh(const int* np) {
+  // origin of each level's nodes in that level's spacing, counted from
+  // coarse node 0: o[0] = 0, o[l] = 2 (o[l-1] + box corner of level l)
+  void origins(long o[LMAX][3]) const {
+    for (int d = 0; d < 3; ++d) o[0][d] = 0;
+    for (int l = 1; l < L; ++l) {
+      o[l][0] = 2 * (o[l - 1][0] + lv[l].ia);
+      o[l][1] = 2 * (o[l - 1][1] + lv[l].ja);
+      o[l][2] = 2 * (o[l - 1][2] + lv[l].ka);
+    }
+  }
+
+  // Level-set sensor for every refined level: the tagged coarse nodes'
+  // bounding box (as sensor_box) grown by margins[l - 1] coarse nodes for
+  // level l, written in the parent's node coordinates (a coarse position X
+  // is parent node 2^(l-1) X - o[l-1]) and clamped to keep one parent node
+  // to spare at each side, at least two cells per axis; out holds 6 ints per
+  // level.  Levels are taken in order, each inside the one just computed.
+  bool sensor_boxes(const double* phi, double d_ref, const int* margins, int* out) const {
+    int box[6];
+    if (!sensor_box(phi, d_ref, margins[0], box)) return false;
+    for (int d = 0; d < 6; ++d) out[d] = box[d];
+    // the tagged box itself (margin 0, unclamped)
     const Level& g = lv[0];
-    Level& v = lv[1];
-    const Level o = v;  // the old patch and its populations
-    v.set_box(np);
-    v.f.assign(Q * v.n(), 0.0);
-    v.g0.assign(Q * v.nb(), 0.0);
-    v.g1.assign(Q * v.nb(), 0.0);
-    double H[QMAX], e[QMAX];
-    const double tc = g.tau, tf = v.tau;
-    const bool flat = tc == 1.0;
-    const double up = flat ? 0.0 : (tf - 1.0) / (2.0 * (tc - 1.0));
-    for (int k = 0; k <= v.mz; ++k)
-      for (int j = 0; j <= v.my; ++j)
-        for (int i = 0; i <= v.mx; ++i) {
-          // coarse-unit position times two
-          const int X2 = 2 * v.ia + i, Y2 = 2 * v.ja + j, Z2 = 2 * v.ka + k;
-          const int oi = X2 - 2 * o.ia, oj = Y2 - 2 * o.ja, ok = Z2 - 2 * o.ka;
-          const long n = v.idx(i, j, k);
-          if (!o.outside(oi, oj, ok)) {
-            for (int q = 0; q < Q; ++q) v.f[q * v.n() + n] = o.f[q * o.n() + o.idx(oi, oj, ok)];
-            continue;
+    const int n[3] = {g.mx + 1, g.my + 1, g.mz + 1};
+    int lo[3] = {n[0], n[1], n[2]}, hi[3] = {-1, -1, -1};
+    for (int K = 0; K < n[2]; ++K)
+      for (int J = 0; J < n[1]; ++J)
+        for (int I = 0; I < n[0]; ++I) {
+          if (!(phi[g.idx(I, J, K)] >= -d_ref)) continue;
+          const int pt[3] = {I, J, K};
+          for (int d = 0; d < 3; ++d) {
+            if (pt[d] < lo[d]) lo[d] = pt[d];
+            if (pt[d] > hi[d]) hi[d] = pt[d];
           }
-          const int ox = X2 & 1, oy = Y2 & 1, oz = Z2 & 1;
-          const double s = (ox ? 0.5 : 1.0) * (oy ? 0.5 : 1.0) * (oz ? 0.5 : 1.0);
-          for (int q = 0; q < Q; ++q) H[q] = 0.0;
-          for (int dz = 0; dz <= oz; ++dz)
-            for (int dy = 0; dy <= oy; ++dy)
-              for (int dx = 0; dx <= ox; ++dx) {
-                const long m = g.idx((X2 - ox) / 2 + dx, (Y2 - oy) / 2 + dy, (Z2 - oz) / 2 + dz);
-                for (int q = 0; q < Q; ++q) H[q] += s * g.f[q * g.n() + m];
-              }
-          double rho, ux, uy, uz;
-          moments(H, rho, ux, uy, uz);
-          feq(rho, ux, uy, uz, e);
-          for (int q = 0; q < Q; ++q) v.f[q * v.n() + n] = e[q] + up * (H[q] - e[q]);
         }
-    const double down = flat ? 0.0 : tc / (tc - 1.0);
-    for (int K = v.ka; K <= v.kb; ++K)
-      for (int J = v.ja; J <= v.jb; ++J)
-        for (int I = v.ia; I <= v.ib; ++I) {
-          if (!v.perimeter(I, J, K)) continue;
-          const long m = g.idx(I, J, K);
-          double f[QMAX];
-          for (int q = 0; q < Q; ++q) f[q] = g.f[q * g.n() + m];
-          double rho, ux, uy, uz;
-          moments(f, rho, ux, uy, uz);
-          feq(rho, ux, uy, uz, e);
-          for (int q = 0; q < Q; ++q) v.g0[q * v.nb() + v.box(I, J, K)] = e[q] + down * (f[q] - e[q]);
+    long org[3] = {0, 0, 0};  // origin of the parent level (level 0 first)
+    int pm[3] = {0, 0, 0};    // parent's last node index per axis
+    long scale = 1;           // 2^(l-1)
+    for (int l = 2; l < L; ++l) {
+      const int* pb = out + 6 * (l - 2);  // the parent's box, in its own parent's coordinates
+      for (int d = 0; d < D; ++d) {
+        org[d] = 2 * (org[d] + pb[2 * d]);
+        pm[d] = 2 * (pb[2 * d + 1] - pb[2 * d]);
+      }
+      scale *= 2;
+      int* ob = out + 6 * (l - 1);
+      for (int d = 0; d < D; ++d) {
+        long a = scale * (lo[d] - margins[l - 1]) - org[d], b = scale * (hi[d] + margins[l - 1]) - org[d];
+        if (a < 1) a = 1;
+        if (b > pm[d] - 1) b = pm[d] - 1;
+        while (b - a < 2) {
+          if (b < pm[d] - 1) ++b;
+          else --a;
         }
+        ob[2 * d] = (int)a;
+        ob[2 * d + 1] = (int)b;
+      }
+      if (D == 2) ob[4] = ob[5] = 0;
+    }
+    return true;
+  }
+
+  // Re-meshing onto new boxes at the end of a coarse step (state at time t:
+  // post-collision populations of every level, covered nodes holding
+  // restricted values), level 1 first, each level inside its re-meshed
+  // parent; boxes holds 6 ints per refined level in the parent's node
+  // coordinates.  A new node of level l at a position the old level l
+  // covered keeps the old populations; the others take the parent's
+  // populations interpolated like the perimeter's (the mean of the 2, 4 or 8
+  // parent nodes around an off-grid node), their non-equilibrium part scaled
+  // by the post-collision ratio (tau_l - 1) / (2 (tau_{l-1} - 1)) about the
+  // equilibrium of the interpolated moments (the equilibrium alone when
+  // tau_{l-1} = 1, where the parent's post-collision state holds no
+  // non-equilibrium part).  Each level's new perimeter sets G(t) come from
+  // the parent's post-collision populations by inverting the BGK step,
+  // f_eq + tau / (tau - 1) (f - f_eq) with the parent's tau (f_eq at
+  // tau = 1).  Covered nodes are restricted again at the end of the next
+  // step; nodes a level no longer covers keep their restricted values.
+  void remesh_levels(const int* boxes) {
+    long oo[LMAX][3], on[LMAX][3];
+    origins(oo);
+    const std::vector<Level> old(lv, lv + L);
+    for (int d = 0; d < 3; ++d) on[0][d] = 0;
+    for (int l = 1; l < L; ++l) {
+      const Level& p = lv[l - 1];
+      Level& v = lv[l];
+      const Level& o = old[l];
+      v.set_box(boxes + 6 * (l - 1));
+      on[l][0] = 2 * (on[l - 1][0] + v.ia);
+      on[l][1] = 2 * (on[l - 1][1] + v.ja);
+      on[l][2] = 2 * (on[l - 1][2] + v.ka);
+      v.f.assign(Q * v.n(), 0.0);
+      v.g0.assign(Q * v.nb(), 0.0);
+      v.g1.assign(Q * v.nb(), 0.0);
+      double H[QMAX], e[QMAX];
+      const double tc = p.tau, tf = v.tau;
+      const bool flat = tc == 1.0;
+      const double up = flat ? 0.0 : (tf - 1.0) / (2.0 * (tc - 1.0));
+      for (int k = 0; k <= v.mz; ++k)
+        for (int j = 0; j <= v.my; ++j)
+          for (int i = 0; i <= v.mx; ++i) {
+            const long n = v.idx(i, j, k);
+            const long oi = on[l][0] + i - oo[l][0], oj = on[l][1] + j - oo[l][1], ok = on[l][2] + k - oo[l][2];
+            if (!o.outside((int)oi, (int)oj, (int)ok)) {
+              for (int q = 0; q < Q; ++q) v.f[q * v.n() + n] = o.f[q * o.n() + o.idx((int)oi, (int)oj, (int)ok)];
+              continue;
+            }
+            // position in the parent's node units, times two
+            const int X2 = 2 * v.ia + i, Y2 = 2 * v.ja + j, Z2 = 2 * v.ka + k;
+            const int ox = X2 & 1, oy = Y2 & 1, oz = Z2 & 1;
+            const double s = (ox ? 0.5 : 1.0) * (oy ? 0.5 : 1.0) * (oz ? 0.5 : 1.0);
+            for (int q = 0; q < Q; ++q) H[q] = 0.0;
+            for (int dz = 0; dz <= oz; ++dz)
+              for (int dy = 0; dy <= oy; ++dy)
+                for (int dx = 0; dx <= ox; ++dx) {
+                  const long m = p.idx((X2 - ox) / 2 + dx, (Y2 - oy) / 2 + dy, (Z2 - oz) / 2 + dz);
+                  for (int q = 0; q < Q; ++q) H[q] += s * p.f[q * p.n() + m];
+                }
+            double rho, ux, uy, uz;
+            moments(H, rho, ux, uy, uz);
+            feq(rho, ux, uy, uz, e);
+            for (int q = 0; q < Q; ++q) v.f[q * v.n() + n] = e[q] + up * (H[q] - e[q]);
+          }
+      const double down = flat ? 0.0 : tc / (tc - 1.0);
+      for (int K = v.ka; K <= v.kb; ++K)
+        for (int J = v.ja; J <= v.jb; ++J)
+          for (int I = v.ia; I <= v.ib; ++I) {
+            if (!v.perimeter(I, J, K)) continue;
+            const long m = p.idx(I, J, K);
+            double f[QMAX];
+            for (int q = 0; q < Q; ++q) f[q] = p.f[q * p.n() + m];
+            double rho, ux, uy, uz;
+            moments(f, rho, ux, uy, uz);
+            feq(rho, ux, uy, uz, e);
+            for (int q = 0; q < Q; ++q) v.g0[q * v.nb() + v.box(I, J, K)] = e[q] + down * (f[q] - e[q]);
+          }
+    }
   }
 };
 
@@ -426,12 +498,35 @@ int orc_ref_sensor(void* h, const double* phi, double d_ref, int margin, int* ou
 // if it does not fit the grid or the hierarchy has more levels
 int orc_ref_remesh(void* h, const int* patch) {
   ref::Ref* r = static_cast<ref::Ref*>(h);
-  if (r->L != 2) return -1;
+  if (r->L != 2 || r->lv[0].f.empty()) return -1;
   const ref::Level& g = r->lv[0];
   const int n[3] = {g.mx + 1, g.my + 1, g.mz + 1};
   for (int d = 0; d < r->D; ++d)
     if (patch[2 * d] < 1 || patch[2 * d + 1] > n[d] - 2 || patch[2 * d + 1] - patch[2 * d] < 2) return -1;
-  r->remesh(patch);
+  r->remesh_levels(patch);
+  return 0;
+}
+
+// nested sensor: margins[l - 1] (coarse nodes) for level l; out receives 6
+// ints per refined level; returns 1 when a node is tagged, 0 otherwise
+int orc_ref_sensor_levels(void* h, const double* phi, double d_ref, const int* margins, int* out) {
+  return static_cast<ref::Ref*>(h)->sensor_boxes(phi, d_ref, margins, out) ? 1 : 0;
+}
+
+// nested re-mesh onto boxes (6 ints per refined level, each in its new
+// parent's node coordinates); -1 if a box does not fit its parent
+int orc_ref_remesh_levels(void* h, const int* boxes) {
+  ref::Ref* r = static_cast<ref::Ref*>(h);
+  const ref::Level& g = r->lv[0];
+  if (g.f.empty()) return -1;  // not initialised
+  int last[3] = {g.mx, g.my, g.mz};  // the parent's last node index per axis
+  for (int l = 1; l < r->L; ++l) {
+    const int* b = boxes + 6 * (l - 1);
+    for (int d = 0; d < r->D; ++d)
+      if (b[2 * d] < 1 || b[2 * d + 1] > last[d] - 1 || b[2 * d + 1] - b[2 * d] < 2) return -1;
+    for (int d = 0; d < r->D; ++d) last[d] = 2 * (b[2 * d + 1] - b[2 * d]);
+  }
+  r->remesh_levels(boxes);
   return 0;
 }
 

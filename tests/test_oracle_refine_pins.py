@@ -28,7 +28,13 @@ the first) decays at the one viscosity within 1.5 % in 2D and 3D, and a
 planted tau_2 = tau_1 on the innermost level misses it by > 8 % in 2D
 (measured 9.9 % / 11.6 %); the stress of the innermost perimeter (gradients
 per quarter spacing) and of the level-1 nodes restricted from it matches
-Chapman-Enskog within 2 % (measured 0.06 % and 0.07 %).
+Chapman-Enskog within 2 % (measured 0.06 % and 0.07 %).  Nested sensor and
+re-meshing: uniform states survive a re-mesh of every level (D2Q9, D3Q27);
+the sensor's boxes equal the brute-force margined bounding box on each
+level and fit their parents; a three-level shear wave re-meshed onto larger,
+shifted boxes carries each level's Chapman-Enskog stress on its new nodes
+within 2 % (measured 0.31 % and 0.06 %) and decays on at nu k^2 within
+1.5 % (0.62 %).
 """
 import numpy as np
 import pytest
@@ -364,3 +370,83 @@ def test_nested_shear_wave_decays_at_one_viscosity_3d():
     rate = -np.polyfit(t[steps // 4:], np.log(amps[steps // 4:]), 1)[0]
     nu = (tau_c - 0.5) / 3.0
     assert abs(rate / (nu * k * k) - 1) < 0.015, rate / (nu * k * k) - 1
+
+
+# --- nested levels: sensor and re-meshing ---
+
+@pytest.mark.parametrize("lattice", [0, 2])
+def test_nested_remesh_keeps_a_uniform_state(lattice):
+    if lattice == 0:
+        n, boxes, new = 30, [(6, 22, 5, 21), (3, 27, 4, 30)], [(4, 24, 6, 25), (5, 34, 2, 30)]
+    else:
+        n, boxes, new = 14, [(3, 10, 4, 11, 2, 9), (2, 12, 1, 12, 3, 11)], [(2, 11, 3, 10, 3, 10), (3, 15, 2, 11, 1, 12)]
+    u = np.array([0.03, -0.02, 0.01])[:2 if lattice == 0 else 3]
+    r = _nested(n, boxes, 0.7, lambda *x: tuple(np.full(len(x[0]), v) for v in u), lattice=lattice)
+    r.step(2)
+    e = [f.reshape(f.shape[0], -1)[:, :1] for f in r.populations()]
+    r.remesh_levels(new)
+    r.step(2)
+    for f, e0 in zip(r.populations(), e):
+        assert np.max(np.abs(f.reshape(f.shape[0], -1) - e0)) < 1e-14
+
+
+def test_nested_sensor_boxes_are_the_margined_bounding_box_on_each_level():
+    """Brute force on a disk: level 1 takes the bounding box of {phi >=
+    -d_ref} grown by margin 1 and clamped one node inside the grid; level l
+    covers the same box grown by its own margin, in its parent's node
+    coordinates (coarse X -> 2^(l-1) X - origin of the parent), clamped one
+    node inside the parent; every box fits its parent (re-meshing accepts
+    it), and where no clamp applies the level covers the grown box."""
+    n = 64
+    J, I = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    phi = 7.2 - np.hypot(I - 30.3, J - 27.6)
+    for margins in [(6, 3, 1), (2, 2, 2), (40, 4, 1)]:
+        r = _nested(n, [(10, 50, 10, 50), (10, 70, 10, 70), (10, 110, 10, 110)], 0.7,
+                    lambda x, y: (0 * x, 0 * y))
+        d_ref = 1.5
+        got = r.sensor_levels(phi.reshape(-1), d_ref, margins)
+        m = phi >= -d_ref
+        lo = np.array([I[m].min(), J[m].min()])
+        hi = np.array([I[m].max(), J[m].max()])
+        org, last, scale = np.zeros(2, dtype=int), np.array([n - 1, n - 1]), 1
+        for l, mg in enumerate(margins, start=1):
+            a = scale * (lo - mg) - org
+            b = scale * (hi + mg) - org
+            a, b = np.maximum(a, 1), np.minimum(b, last - 1)
+            want = (a[0], b[0], a[1], b[1], 0, 0)
+            assert got[l - 1] == tuple(int(v) for v in want), (l, got[l - 1], want)
+            # covers the grown box (in coarse units) wherever no clamp applied
+            x0 = (org + a) / scale
+            x1 = (org + b) / scale
+            assert np.all((x0 <= lo - mg) | (a == 1)) and np.all((x1 >= hi + mg) | (b == last - 1))
+            org, last, scale = 2 * (org + a), 2 * (b - a), 2 * scale
+        r.remesh_levels(got)            # every box fits its new parent
+    assert RefineOracle(n, n, [(10, 50, 10, 50), (10, 70, 10, 70)], 0.7).sensor_levels(
+        np.full(n * n, -5.0), 1.0, (1, 1)) is None
+
+
+def test_nested_remesh_continues_a_shear_wave():
+    """Three levels re-meshed onto larger, shifted boxes: the new nodes of
+    both refined levels carry their level's Chapman-Enskog stress within 2 %
+    and the wave keeps decaying at nu k^2 within 1.5 %."""
+    n, tau_c, U = 64, 0.8, 1e-3
+    k = 2 * np.pi / n
+    r = _nested(n, _BOX3, tau_c, lambda x, y: (U * np.cos(k * y), 0 * y))
+    r.step(150)
+    old = [r.coords(lv) for lv in (1, 2)]
+    r.remesh_levels([(8, 56, 10, 54), (12, 84, 20, 76)])
+    for lv in (1, 2):
+        f = r.level(lv)
+        x, y = r.coords(lv)
+        rho, ux, uy = _moments(f)
+        pxy = (CX[:, None] * CY[:, None] * (f.reshape(9, -1) - _feq(rho, ux, uy))).sum(0)
+        A = (ux * np.cos(k * y)).sum() / (np.cos(k * y) ** 2).sum()
+        expect = (r.taus[lv] - 1.0) / 3.0 * rho * 0.5 ** lv * A * k * np.sin(k * y)
+        ox, oy = old[lv - 1]
+        inside = (x >= ox.min()) & (x <= ox.max()) & (y >= oy.min()) & (y <= oy.max())
+        new = ~inside & (np.abs(np.sin(k * y)) > 0.5)
+        assert new.sum() > 100
+        assert np.max(np.abs(pxy[new] - expect[new])) < 0.02 * np.max(np.abs(expect[new])), lv
+    proj = lambda I, J: np.cos(k * J)  # noqa: E731
+    rate = _decay_rate(r, n, 150, proj)
+    assert abs(rate / ((tau_c - 0.5) / 3.0 * k * k) - 1) < 0.015
