@@ -74,6 +74,10 @@ typedef struct lsb_ref_params {
                         coordinates (nodes 0 .. m per axis, m = twice the parent box's
                         extent): 1 <= a, b <= m - 1, b - a >= 2 per axis; ka, kb ignored in
                         2D; unused entries ignored */
+  int max_inner_extent[LSB_REF_MAX_LEVELS - 2][3]; /* largest extents (parent cells per axis) that
+                        lsb_ref_remesh_levels may choose for level l (entry l - 2); 0 or
+                        anything below the initial box's extent keeps that extent; at most
+                        twice the parent's largest extent minus 2 */
 } lsb_ref_params;
 
 typedef struct lsb_ref lsb_ref;
@@ -133,6 +137,31 @@ int lsb_ref_sensor(lsb_ref* ref, const double* phi, double d_ref, int margin, in
  * than max_extent, or a hierarchy of more than two levels; LSB_ESTATE
  * before lsb_ref_init. */
 int lsb_ref_remesh(lsb_ref* ref, const int* patch, void* stream);
+
+/* The sensor for every refined level: the tagged coarse nodes' bounding box
+ * (as lsb_ref_sensor, tagging phi >= -d_ref) grown by margins[l - 1] coarse
+ * nodes for level l, written in the parent's node coordinates (coarse node
+ * X is node 2^(l-1) X - o of the parent, o its first node's index in its
+ * own spacing counted from coarse node 0), clamped to keep one parent node
+ * at each side and widened to two cells per axis; levels in order, each
+ * inside the one computed before it.  boxes (host) receives 6 ints per
+ * refined level, ka = kb = 0 in 2D; the current boxes when no node is
+ * tagged.  Synchronises the stream.  LSB_EINVAL for a NULL pointer or a
+ * negative margin. */
+int lsb_ref_sensor_levels(lsb_ref* ref, const double* phi, double d_ref, const int* margins, int* boxes,
+                          void* stream);
+
+/* Re-meshing of every refined level (boxes: host, 6 ints per refined level,
+ * each in its new parent's node coordinates), level 1 first, each inside
+ * its re-meshed parent, with the rules of lsb_ref_remesh per pair of
+ * levels: a new node at a position the old level covered keeps its
+ * populations, the others are interpolated from the parent's post-collision
+ * populations with the non-equilibrium part scaled by
+ * (tau_l - 1) / (2 (tau_{l-1} - 1)), and each level's perimeter sets come
+ * from inverting the parent's BGK step.  LSB_EINVAL for a box outside its
+ * parent (one node to spare, two cells per axis) or beyond the workspace's
+ * extents; LSB_ESTATE before lsb_ref_init. */
+int lsb_ref_remesh_levels(lsb_ref* ref, const int* boxes, void* stream);
 
 /* Post-collision populations of both levels into device arrays, [Q][nodes]
  * in the paper's direction ordering (rest direction last): coarse

@@ -350,15 +350,18 @@ __global__ __launch_bounds__(256) void k_ref_sensor_final(int nparts, const int*
   }
 }
 
-// Re-meshing (state at the end of a coarse step): new fine nodes inside the
-// old patch keep the old fine populations; the others take the coarse
-// post-collision populations interpolated like the perimeter's (the mean of
-// the 2, 4 or 8 coarse nodes around an off-grid node), the non-equilibrium
-// part scaled by (tau_f - 1) / (2 (tau_c - 1)) about the equilibrium of the
-// interpolated moments (the equilibrium alone at tau_c = 1).  Old geometry:
-// o (its fine buffer off).
+// Re-meshing of one refined level (state at the end of a coarse step, the
+// parent already re-meshed): new nodes at positions the old level covered
+// keep the old populations; the others take the parent's post-collision
+// populations interpolated like the perimeter's (the mean of the 2, 4 or 8
+// parent nodes around an off-grid node), the non-equilibrium part scaled by
+// (tau_f - 1) / (2 (tau_c - 1)) about the equilibrium of the interpolated
+// moments (the equilibrium alone at tau_c = 1).  Old geometry: o (its
+// buffer off); sx, sy, sz: how far the parent's first node moved, in this
+// level's spacing (0 for level 1).
 template <int LAT>
-__global__ __launch_bounds__(256) void k_ref_remesh_fine(RefArgs a, RefArgs o, const double* off, double* ff) {
+__global__ __launch_bounds__(256) void k_ref_remesh_fine(RefArgs a, RefArgs o, int sx, int sy, int sz,
+                                                         const double* off, double* ff) {
   using L = Lat<LAT>;
   constexpr int Q = L::Q;
   const long n1 = (long)(a.mx + 1) * (a.my + 1) * (a.mz + 1);
@@ -367,8 +370,8 @@ __global__ __launch_bounds__(256) void k_ref_remesh_fine(RefArgs a, RefArgs o, c
   for (long n = (long)blockIdx.x * 256 + threadIdx.x; n < n1; n += (long)gridDim.x * 256) {
     const int i = (int)(n % (a.mx + 1)), j = (int)((n / (a.mx + 1)) % (a.my + 1));
     const int k = (int)(n / ((long)(a.mx + 1) * (a.my + 1)));
-    const int X2 = 2 * a.ia + i, Y2 = 2 * a.ja + j, Z2 = 2 * a.ka + k;  // twice the coarse-unit position
-    const int oi = X2 - 2 * o.ia, oj = Y2 - 2 * o.ja, ok = Z2 - 2 * o.ka;
+    const int X2 = 2 * a.ia + i, Y2 = 2 * a.ja + j, Z2 = 2 * a.ka + k;  // twice the parent-unit position
+    const int oi = X2 - 2 * o.ia + sx, oj = Y2 - 2 * o.ja + sy, ok = Z2 - 2 * o.ka + sz;
     const long p = fine_index(a, i, j, k);
     if (oi >= 0 && oi <= o.mx && oj >= 0 && oj <= o.my && ok >= 0 && ok <= o.mz) {
       const long op = fine_index(o, oi, oj, ok);
@@ -384,7 +387,7 @@ __global__ __launch_bounds__(256) void k_ref_remesh_fine(RefArgs a, RefArgs o, c
     for (int dz = 0; dz <= oz; ++dz)
       for (int dy = 0; dy <= oy; ++dy)
         for (int dx = 0; dx <= ox; ++dx) {
-          const long m = ((long)((Z2 - oz) / 2 + dz) * a.ny + (Y2 - oy) / 2 + dy) * a.nx + (X2 - ox) / 2 + dx;
+          const long m = a.po + ((long)((Z2 - oz) / 2 + dz) * a.ph + (Y2 - oy) / 2 + dy) * a.pw + (X2 - ox) / 2 + dx;
 #pragma unroll
           for (int q = 0; q < Q; ++q) H[q] += s * a.fc_in[q * a.nc + m];
         }
@@ -398,9 +401,9 @@ __global__ __launch_bounds__(256) void k_ref_remesh_fine(RefArgs a, RefArgs o, c
   }
 }
 
-// the new perimeter's pre-collision sets G(t) from the coarse post-collision
-// populations, inverting the BGK step: f_eq + tau_c / (tau_c - 1) (f - f_eq)
-// (f_eq at tau_c = 1)
+// the new perimeter's pre-collision sets G(t) from the parent's
+// post-collision populations, inverting the BGK step:
+// f_eq + tau_c / (tau_c - 1) (f - f_eq) (f_eq at tau_c = 1)
 template <int LAT>
 __global__ __launch_bounds__(256) void k_ref_remesh_g(RefArgs a, double* g) {
   using L = Lat<LAT>;
@@ -411,7 +414,7 @@ __global__ __launch_bounds__(256) void k_ref_remesh_g(RefArgs a, double* g) {
   for (long n = (long)blockIdx.x * 256 + threadIdx.x; n < nbox; n += (long)gridDim.x * 256) {
     const int I = a.ia + (int)(n % a.bw), J = a.ja + (int)((n / a.bw) % a.bh), K = a.ka + (int)(n / ((long)a.bw * a.bh));
     if (covered(a, I, J, K)) continue;
-    const long m = ((long)K * a.ny + J) * a.nx + I;
+    const long m = a.po + ((long)K * a.ph + J) * a.pw + I;
     double f[Q], v[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) f[q] = a.fc_in[q * a.nc + m];
@@ -480,6 +483,8 @@ struct lsb_ref {
   double* fc[2] = {nullptr, nullptr};
   double* ff[2] = {nullptr, nullptr};
   double* g[2] = {nullptr, nullptr};
+  int dext[LSB_REF_MAX_LEVELS][3] = {};  // capacity extents (parent cells) of the deeper levels
+  long dcap[LSB_REF_MAX_LEVELS] = {}, dbcap[LSB_REF_MAX_LEVELS] = {};
   double* dff[LSB_REF_MAX_LEVELS][2] = {};
   double* dg[LSB_REF_MAX_LEVELS][2] = {};
   int cur = 0;  // fc[cur] and g[cur] are the current coarse state and G(t); ff[0] the fine state
@@ -494,8 +499,7 @@ size_t sizes(const lsb_ref* r, size_t* fcb, size_t* ffb, size_t* gb) {
   *gb = align256(sizeof(double) * r->Q * (size_t)r->bcap);
   size_t t = 2 * (*fcb + *ffb + *gb) + align256(sizeof(int) * 6 * (kSensorBlocks + 1));
   for (int l = 2; l < r->L; ++l)
-    t += 2 * (align256(sizeof(double) * r->Q * (size_t)r->deep[l].nf) +
-              align256(sizeof(double) * r->Q * (size_t)r->deep[l].nb));
+    t += 2 * (align256(sizeof(double) * r->Q * (size_t)r->dcap[l]) + align256(sizeof(double) * r->Q * (size_t)r->dbcap[l]));
   return t;
 }
 
@@ -597,6 +601,109 @@ void launch_steps(lsb_ref* r, int nsteps, hipStream_t st) {
     r->cur ^= 1;
   }
 }
+
+// the sensor's reduction: the bounding box of the tagged coarse nodes (lo x,
+// y, z then hi x, y, z); *tagged false when none is
+int sensor_bbox(lsb_ref* r, const double* phi, double d_ref, hipStream_t st, int* box, bool* tagged) {
+  const RefArgs& a = r->base;
+  k_ref_sensor<<<kSensorBlocks, 256, 0, st>>>(a, phi, d_ref, r->sens);
+  k_ref_sensor_final<<<1, 256, 0, st>>>(kSensorBlocks, r->sens, r->sens + 6 * kSensorBlocks);
+  if (int e = check_launch()) return e;
+  if (hipMemcpyAsync(box, r->sens + 6 * kSensorBlocks, 6 * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(LSB_EDEVICE, "sensor read-back failed");
+  *tagged = box[0] < a.nx;
+  return LSB_OK;
+}
+
+// level 1's box from the tagged box: grown by margin, clamped one node
+// inside the grid, at least two cells per axis; the current patch when
+// nothing is tagged
+void level1_box(const lsb_ref* r, const int* box, bool tagged, int margin, int* patch) {
+  const RefArgs& a = r->base;
+  const int cur[6] = {a.ia, a.ib, a.ja, a.jb, a.ka, a.kb};
+  if (!tagged) {
+    for (int d = 0; d < 6; ++d) patch[d] = cur[d];
+    return;
+  }
+  const int n[3] = {a.nx, a.ny, a.nz};
+  int out[6] = {0, 0, 0, 0, 0, 0};
+  for (int d = 0; d < a.D; ++d) {
+    int lo = box[d] - margin, hi = box[3 + d] + margin;
+    if (lo < 1) lo = 1;
+    if (hi > n[d] - 2) hi = n[d] - 2;
+    while (hi - lo < 2) {  // at least two cells (n >= 5 holds: the grid took a valid patch)
+      if (hi < n[d] - 2) ++hi;
+      else --lo;
+    }
+    out[2 * d] = lo;
+    out[2 * d + 1] = hi;
+  }
+  for (int d = 0; d < 6; ++d) patch[d] = out[d];
+}
+
+// re-meshing of every refined level onto boxes (6 ints per level), level 1
+// first, each inside its re-meshed parent
+int remesh_levels(lsb_ref* r, const int* boxes, hipStream_t st) {
+  const RefArgs& b = r->base;
+  const int D = b.D;
+  int last[3] = {b.nx - 1, b.ny - 1, b.nz - 1};  // the parent's last node index per axis
+  for (int l = 1; l < r->L; ++l) {
+    const int* bx = boxes + 6 * (l - 1);
+    const int* cap = l == 1 ? r->ext : r->dext[l];
+    for (int d = 0; d < D; ++d) {
+      const int lo = bx[2 * d], hi = bx[2 * d + 1];
+      if (lo < 1 || hi > last[d] - 1 || hi - lo < 2)
+        return fail(LSB_EINVAL, "a box must lie inside its parent with one node to spare and span >= 2 cells per axis");
+      if (hi - lo > cap[d]) return fail(LSB_EINVAL, "box larger than the workspace's maximum extents");
+    }
+    for (int d = 0; d < D; ++d) last[d] = 2 * (bx[2 * d + 1] - bx[2 * d]);
+  }
+  RefArgs O[LSB_REF_MAX_LEVELS], A[LSB_REF_MAX_LEVELS];
+  for (int l = 1; l < r->L; ++l) O[l] = pair_of(r, l);
+  int shift[3] = {0, 0, 0};
+  for (int l = 1; l < r->L; ++l) {
+    A[l] = O[l];
+    if (l >= 2) set_parent(A[l], A[l - 1]);
+    set_patch(A[l], boxes + 6 * (l - 1));
+    A[l].fc_in = l == 1 ? r->fc[r->cur] : (l == 2 ? r->ff[0] : r->dff[l - 1][0]);
+    double** buf = l == 1 ? r->ff : r->dff[l];
+    double* g = l == 1 ? r->g[r->cur] : r->dg[l][r->dcur[l]];
+    const long n1 = (long)(A[l].mx + 1) * (A[l].my + 1) * (A[l].mz + 1), nbox = (long)A[l].bw * A[l].bh * A[l].bd;
+    switch (r->P.lattice) {
+      case LSB_D2Q9:
+        k_ref_remesh_fine<LSB_D2Q9><<<grid_for(n1), 256, 0, st>>>(A[l], O[l], shift[0], shift[1], shift[2], buf[0], buf[1]);
+        k_ref_remesh_g<LSB_D2Q9><<<grid_for(nbox), 256, 0, st>>>(A[l], g);
+        break;
+      case LSB_D3Q19:
+        k_ref_remesh_fine<LSB_D3Q19><<<grid_for(n1), 256, 0, st>>>(A[l], O[l], shift[0], shift[1], shift[2], buf[0], buf[1]);
+        k_ref_remesh_g<LSB_D3Q19><<<grid_for(nbox), 256, 0, st>>>(A[l], g);
+        break;
+      default:
+        k_ref_remesh_fine<LSB_D3Q27><<<grid_for(n1), 256, 0, st>>>(A[l], O[l], shift[0], shift[1], shift[2], buf[0], buf[1]);
+        k_ref_remesh_g<LSB_D3Q27><<<grid_for(nbox), 256, 0, st>>>(A[l], g);
+        break;
+    }
+    if (int e = check_launch()) return e;
+    double* t = buf[0];
+    buf[0] = buf[1];
+    buf[1] = t;
+    // how far this level's first node moved, in the child's spacing
+    shift[0] = 2 * (shift[0] + 2 * (A[l].ia - O[l].ia));
+    shift[1] = 2 * (shift[1] + 2 * (A[l].ja - O[l].ja));
+    shift[2] = 2 * (shift[2] + 2 * (A[l].ka - O[l].ka));
+  }
+  for (int l = 1; l < r->L; ++l) {
+    A[l].fc_in = nullptr;
+    if (l == 1) r->base = A[l];
+    else r->deep[l] = A[l];
+  }
+  for (int d = 0; d < 6; ++d) r->P.patch[d] = D == 3 || d < 4 ? boxes[d] : 0;
+  for (int l = 2; l < r->L; ++l)
+    for (int d = 0; d < 6; ++d) r->P.inner[l - 2][d] = D == 3 || d < 4 ? boxes[6 * (l - 1) + d] : 0;
+  return LSB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -664,7 +771,22 @@ int lsb_ref_create(const lsb_ref_params* P, lsb_ref** out) {
     c.D = a.D;
     set_parent(c, pp);
     set_patch(c, bx);
-    if (c.nf > (1L << 31)) {
+    // capacity: the larger of the box and max_inner_extent, at most what the
+    // parent's capacity admits
+    const int* pe = l == 2 ? r->ext : r->dext[l - 1];
+    int* e = r->dext[l];
+    for (int d = 0; d < 3; ++d) {
+      e[d] = d < (three ? 3 : 2) ? bx[2 * d + 1] - bx[2 * d] : 0;
+      const int mx = P->max_inner_extent[l - 2][d];
+      if (d < (three ? 3 : 2) && (mx < 0 || mx > 2 * pe[d] - 2)) {
+        delete r;
+        return fail(LSB_EINVAL, "max_inner_extent outside [0, twice the parent's largest extent - 2]");
+      }
+      if (d < (three ? 3 : 2) && mx > e[d]) e[d] = mx;
+    }
+    r->dcap[l] = (2L * e[0] + 3) * (2L * e[1] + 3) * (three ? 2L * e[2] + 3 : 1);
+    r->dbcap[l] = 2L * (e[1] + 1) * (e[2] + 1) + 2L * (e[0] + 1) * (e[2] + 1) + (three ? 2L * (e[0] + 1) * (e[1] + 1) : 0L);
+    if (r->dcap[l] > (1L << 31)) {
       delete r;
       return fail(LSB_EINVAL, "grid too large");
     }
@@ -700,9 +822,9 @@ int lsb_ref_bind(lsb_ref* r, void* ws, size_t bytes) {
   for (int l = 2; l < r->L; ++l)
     for (int k = 0; k < 2; ++k) {
       r->dff[l][k] = reinterpret_cast<double*>(p);
-      p += align256(sizeof(double) * r->Q * (size_t)r->deep[l].nf);
+      p += align256(sizeof(double) * r->Q * (size_t)r->dcap[l]);
       r->dg[l][k] = reinterpret_cast<double*>(p);
-      p += align256(sizeof(double) * r->Q * (size_t)r->deep[l].nb);
+      p += align256(sizeof(double) * r->Q * (size_t)r->dbcap[l]);
     }
   r->ws = static_cast<char*>(ws);
   r->ws_bytes = bytes;
@@ -782,77 +904,69 @@ int lsb_ref_sensor(lsb_ref* r, const double* phi, double d_ref, int margin, int*
   if (!r || !phi || !patch) return fail(LSB_EINVAL, "null pointer");
   if (!r->ws) return fail(LSB_ESTATE, "lsb_ref_sensor before lsb_ref_bind");
   if (margin < 0) return fail(LSB_EINVAL, "negative margin");
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const RefArgs& a = r->base;
-  k_ref_sensor<<<kSensorBlocks, 256, 0, st>>>(a, phi, d_ref, r->sens);
-  k_ref_sensor_final<<<1, 256, 0, st>>>(kSensorBlocks, r->sens, r->sens + 6 * kSensorBlocks);
-  if (int e = check_launch()) return e;
   int box[6];
-  if (hipMemcpyAsync(box, r->sens + 6 * kSensorBlocks, sizeof(box), hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return fail(LSB_EDEVICE, "sensor read-back failed");
-  const int cur[6] = {a.ia, a.ib, a.ja, a.jb, a.ka, a.kb};
-  if (box[0] >= a.nx) {  // nothing tagged: the patch stays
-    for (int d = 0; d < 6; ++d) patch[d] = cur[d];
+  bool tagged = false;
+  if (int e = sensor_bbox(r, phi, d_ref, reinterpret_cast<hipStream_t>(stream), box, &tagged)) return e;
+  level1_box(r, box, tagged, margin, patch);
+  return LSB_OK;
+}
+
+int lsb_ref_sensor_levels(lsb_ref* r, const double* phi, double d_ref, const int* margins, int* boxes,
+                          void* stream) {
+  if (!r || !phi || !margins || !boxes) return fail(LSB_EINVAL, "null pointer");
+  if (!r->ws) return fail(LSB_ESTATE, "lsb_ref_sensor_levels before lsb_ref_bind");
+  for (int l = 1; l < r->L; ++l)
+    if (margins[l - 1] < 0) return fail(LSB_EINVAL, "negative margin");
+  int box[6];
+  bool tagged = false;
+  if (int e = sensor_bbox(r, phi, d_ref, reinterpret_cast<hipStream_t>(stream), box, &tagged)) return e;
+  if (!tagged) {  // nothing tagged: every level stays
+    for (int l = 1; l < r->L; ++l) {
+      const RefArgs& a = pair_of(r, l);
+      const int cur[6] = {a.ia, a.ib, a.ja, a.jb, a.ka, a.kb};
+      for (int d = 0; d < 6; ++d) boxes[6 * (l - 1) + d] = cur[d];
+    }
     return LSB_OK;
   }
-  const int n[3] = {a.nx, a.ny, a.nz};
-  int out[6] = {0, 0, 0, 0, 0, 0};
-  for (int d = 0; d < a.D; ++d) {
-    int lo = box[d] - margin, hi = box[3 + d] + margin;
-    if (lo < 1) lo = 1;
-    if (hi > n[d] - 2) hi = n[d] - 2;
-    while (hi - lo < 2) {  // at least two cells (n >= 5 holds: the grid took a valid patch)
-      if (hi < n[d] - 2) ++hi;
-      else --lo;
+  level1_box(r, box, true, margins[0], boxes);
+  // deeper levels: the tagged box grown by the level's margin, in the
+  // parent's node coordinates (coarse X -> parent node scale X - org)
+  const int D = r->base.D;
+  long org[3] = {0, 0, 0};
+  long scale = 1;
+  for (int l = 2; l < r->L; ++l) {
+    const int* pb = boxes + 6 * (l - 2);
+    int* ob = boxes + 6 * (l - 1);
+    scale *= 2;
+    for (int d = 0; d < 6; ++d) ob[d] = 0;
+    for (int d = 0; d < D; ++d) {
+      org[d] = 2 * (org[d] + pb[2 * d]);
+      const long last = 2L * (pb[2 * d + 1] - pb[2 * d]);  // the parent's last node
+      long lo = scale * (box[d] - margins[l - 1]) - org[d], hi = scale * (box[3 + d] + margins[l - 1]) - org[d];
+      if (lo < 1) lo = 1;
+      if (hi > last - 1) hi = last - 1;
+      while (hi - lo < 2) {  // the parent spans >= 2 cells, so >= 4 of this level's
+        if (hi < last - 1) ++hi;
+        else --lo;
+      }
+      ob[2 * d] = (int)lo;
+      ob[2 * d + 1] = (int)hi;
     }
-    out[2 * d] = lo;
-    out[2 * d + 1] = hi;
   }
-  for (int d = 0; d < 6; ++d) patch[d] = out[d];
   return LSB_OK;
 }
 
 int lsb_ref_remesh(lsb_ref* r, const int* patch, void* stream) {
   if (!r || !patch) return fail(LSB_EINVAL, "null pointer");
   if (!r->inited) return fail(LSB_ESTATE, "lsb_ref_remesh before lsb_ref_init");
-  if (r->L != 2) return fail(LSB_EINVAL, "re-meshing takes a two-level hierarchy");
-  const RefArgs& b = r->base;
-  const int n[3] = {b.nx, b.ny, b.nz};
-  for (int d = 0; d < b.D; ++d) {
-    const int lo = patch[2 * d], hi = patch[2 * d + 1];
-    if (lo < 1 || hi > n[d] - 2 || hi - lo < 2)
-      return fail(LSB_EINVAL, "patch must lie inside the coarse grid with one node to spare and span >= 2 cells per axis");
-    if (hi - lo > r->ext[d]) return fail(LSB_EINVAL, "patch larger than the workspace's maximum extents");
-  }
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const RefArgs o = b;
-  RefArgs a = b;
-  set_patch(a, patch);
-  a.fc_in = r->fc[r->cur];
-  const long n1 = (long)(a.mx + 1) * (a.my + 1) * (a.mz + 1), nbox = (long)a.bw * a.bh * a.bd;
-  switch (r->P.lattice) {
-    case LSB_D2Q9:
-      k_ref_remesh_fine<LSB_D2Q9><<<grid_for(n1), 256, 0, st>>>(a, o, r->ff[0], r->ff[1]);
-      k_ref_remesh_g<LSB_D2Q9><<<grid_for(nbox), 256, 0, st>>>(a, r->g[r->cur]);
-      break;
-    case LSB_D3Q19:
-      k_ref_remesh_fine<LSB_D3Q19><<<grid_for(n1), 256, 0, st>>>(a, o, r->ff[0], r->ff[1]);
-      k_ref_remesh_g<LSB_D3Q19><<<grid_for(nbox), 256, 0, st>>>(a, r->g[r->cur]);
-      break;
-    default:
-      k_ref_remesh_fine<LSB_D3Q27><<<grid_for(n1), 256, 0, st>>>(a, o, r->ff[0], r->ff[1]);
-      k_ref_remesh_g<LSB_D3Q27><<<grid_for(nbox), 256, 0, st>>>(a, r->g[r->cur]);
-      break;
-  }
-  if (int e = check_launch()) return e;
-  double* t = r->ff[0];
-  r->ff[0] = r->ff[1];
-  r->ff[1] = t;
-  a.fc_in = nullptr;
-  r->base = a;
-  for (int d = 0; d < 6; ++d) r->P.patch[d] = b.D == 3 || d < 4 ? patch[d] : 0;
-  return LSB_OK;
+  if (r->L != 2) return fail(LSB_EINVAL, "re-meshing takes a two-level hierarchy; use lsb_ref_remesh_levels");
+  return remesh_levels(r, patch, reinterpret_cast<hipStream_t>(stream));
+}
+
+int lsb_ref_remesh_levels(lsb_ref* r, const int* boxes, void* stream) {
+  if (!r || !boxes) return fail(LSB_EINVAL, "null pointer");
+  if (!r->inited) return fail(LSB_ESTATE, "lsb_ref_remesh_levels before lsb_ref_init");
+  return remesh_levels(r, boxes, reinterpret_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

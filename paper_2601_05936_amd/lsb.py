@@ -53,6 +53,7 @@ EXPORTS = [
     "lsb_last_error",
     "lsb_ref_create", "lsb_ref_destroy", "lsb_ref_workspace_bytes", "lsb_ref_bind", "lsb_ref_init", "lsb_ref_step",
     "lsb_ref_get_populations", "lsb_ref_sensor", "lsb_ref_remesh", "lsb_ref_init_levels", "lsb_ref_get_level",
+    "lsb_ref_sensor_levels", "lsb_ref_remesh_levels",
 ]
 
 
@@ -63,7 +64,8 @@ class RefParams(C.Structure):
     """Mirror of lsb_ref_params (include/lsb_refine.h)."""
     _fields_ = [("lattice", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("patch", C.c_int * 6),
                 ("tau_c", C.c_double), ("max_extent", C.c_int * 3), ("levels", C.c_int),
-                ("inner", (C.c_int * 6) * (REF_MAX_LEVELS - 2))]
+                ("inner", (C.c_int * 6) * (REF_MAX_LEVELS - 2)),
+                ("max_inner_extent", (C.c_int * 3) * (REF_MAX_LEVELS - 2))]
 SCHED_SERIAL, SCHED_OVERLAP = 0, 1
 MAX_BUBBLES = 64  # LSB_MAX_BUBBLES
 
@@ -123,6 +125,8 @@ def load() -> C.CDLL:
     lib.lsb_ref_remesh.argtypes = [vp, C.POINTER(C.c_int), vp]
     lib.lsb_ref_init_levels.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
     lib.lsb_ref_get_level.argtypes = [vp, C.c_int, vp, vp]
+    lib.lsb_ref_sensor_levels.argtypes = [vp, vp, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_int), vp]
+    lib.lsb_ref_remesh_levels.argtypes = [vp, C.POINTER(C.c_int), vp]
     _lib = lib
     return lib
 
@@ -342,7 +346,7 @@ class Refine:
     stream."""
 
     def __init__(self, nx: int, ny: int, patch, tau_c: float, device="cuda:0", lattice: int = D2Q9, nz: int = 1,
-                 max_extent=(0, 0, 0)):
+                 max_extent=(0, 0, 0), max_inner_extent=()):
         import torch
         self.torch = torch
         self.lib = load()
@@ -359,8 +363,11 @@ class Refine:
         inner = ((C.c_int * 6) * (REF_MAX_LEVELS - 2))()
         for l, bx in enumerate(self.boxes[1:REF_MAX_LEVELS - 1]):
             inner[l] = (C.c_int * 6)(*bx)
+        mie = ((C.c_int * 3) * (REF_MAX_LEVELS - 2))()
+        for l, e in enumerate(list(max_inner_extent)[:REF_MAX_LEVELS - 2]):
+            mie[l] = (C.c_int * 3)(*[int(v) for v in e])
         self._cp = RefParams(self.lattice, self.nx, self.ny, self.nz, (C.c_int * 6)(*self.boxes[0]), float(tau_c),
-                             (C.c_int * 3)(*[int(v) for v in max_extent]), self.levels, inner)
+                             (C.c_int * 3)(*[int(v) for v in max_extent]), self.levels, inner, mie)
         self._sync_level1()
         h = C.c_void_p()
         _check(self.lib.lsb_ref_create(C.byref(self._cp), C.byref(h)))
@@ -438,6 +445,31 @@ class Refine:
         p = (tuple(int(v) for v in patch) + (0, 0))[:6]
         _check(self.lib.lsb_ref_remesh(self.h, (C.c_int * 6)(*p), self.stream()))
         self.boxes[0] = p if self.D == 3 else p[:4] + (0, 0)
+        self._sync_level1()
+        return self
+
+    def sensor_levels(self, phi, d_ref: float, margins):
+        """Boxes of every refined level (6 ints each, each in its parent's
+        node coordinates) from the level-set sensor on the coarse level set
+        phi [n_coarse], margins[l - 1] coarse nodes for level l; the current
+        boxes when no node is tagged."""
+        nl = self.levels - 1
+        t_phi = self._dev(phi, self.n_coarse)
+        out = (C.c_int * (6 * nl))()
+        mg = (C.c_int * nl)(*[int(m) for m in margins])
+        _check(self.lib.lsb_ref_sensor_levels(self.h, C.c_void_p(t_phi.data_ptr()), float(d_ref), mg, out,
+                                              self.stream()))
+        return [tuple(out[6 * l:6 * l + 6]) for l in range(nl)]
+
+    def remesh_levels(self, boxes):
+        """Re-mesh every refined level onto boxes (6 ints each, level 1
+        first, each in its new parent's node coordinates)."""
+        flat = []
+        for bx in boxes:
+            p = (tuple(int(v) for v in bx) + (0, 0))[:6]
+            flat += list(p if self.D == 3 else p[:4] + (0, 0))
+        _check(self.lib.lsb_ref_remesh_levels(self.h, (C.c_int * len(flat))(*flat), self.stream()))
+        self.boxes = [tuple(flat[6 * l:6 * l + 6]) for l in range(len(boxes))]
         self._sync_level1()
         return self
 

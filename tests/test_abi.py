@@ -112,8 +112,11 @@ def _ref_create(**kw):
     inner = ((C.c_int * 6) * (lsb.REF_MAX_LEVELS - 2))()
     for l, bx in enumerate(p.get("inner", ())):
         inner[l] = (C.c_int * 6)(*bx)
+    mie = ((C.c_int * 3) * (lsb.REF_MAX_LEVELS - 2))()
+    for l, e in enumerate(p.get("max_inner_extent", ())):
+        mie[l] = (C.c_int * 3)(*e)
     cp = lsb.RefParams(p["lattice"], p["nx"], p["ny"], p["nz"], (C.c_int * 6)(*p["patch"]), p["tau_c"],
-                       (C.c_int * 3)(*p.get("max_extent", (0, 0, 0))), p.get("levels", 0), inner)
+                       (C.c_int * 3)(*p.get("max_extent", (0, 0, 0))), p.get("levels", 0), inner, mie)
     h = C.c_void_p()
     rc = lsb.load().lsb_ref_create(C.byref(cp), C.byref(h))
     return rc, h
@@ -134,6 +137,8 @@ def _ref_create(**kw):
     dict(levels=4, inner=[(2, 20, 2, 12, 0, 0), (1, 36, 3, 9, 0, 0)]),         # level 2 has nodes 0 .. 36
     dict(lattice=lsb.D3Q19, nz=16, patch=(8, 20, 6, 16, 4, 12), levels=3,
          inner=[(2, 20, 2, 12, 3, 16)]),                                        # 3D: kb > m - 1
+    dict(levels=3, inner=[(2, 20, 2, 12, 0, 0)], max_inner_extent=[(23, 0, 0)]),  # > 2 x 12 - 2
+    dict(levels=3, inner=[(2, 20, 2, 12, 0, 0)], max_inner_extent=[(0, -1, 0)]),
 ])
 def test_refine_create_rejects_invalid_parameters(bad):
     rc, h = _ref_create(**bad)
@@ -193,6 +198,16 @@ def test_refine_nested_workspace_layout():
         ns = 2 * bh * bd + 2 * bw * bd + 2 * bw * bh
         extra += 2 * (up(8 * 27 * nf) + up(8 * 27 * ns))
     assert nb.value == n2.value + extra
+    # max_inner_extent sizes a deeper level for its largest box
+    rc, h3 = _ref_create(levels=3, inner=boxes[:1], max_inner_extent=[(12, 14, 8)], **base)
+    assert rc == lsb.LSB_OK
+    n3 = C.c_size_t()
+    assert lib.lsb_ref_workspace_bytes(h3, C.byref(n3)) == lsb.LSB_OK
+    e = (12, 14, 8)
+    nf = (2 * e[0] + 3) * (2 * e[1] + 3) * (2 * e[2] + 3)
+    ns = 2 * (e[1] + 1) * (e[2] + 1) + 2 * (e[0] + 1) * (e[2] + 1) + 2 * (e[0] + 1) * (e[1] + 1)
+    assert n3.value == n2.value + 2 * (up(8 * 27 * nf) + up(8 * 27 * ns))
+    lib.lsb_ref_destroy(h3)
     # two-level entry points refuse the deeper hierarchy before any device access
     dummy = C.c_void_p(1)
     assert lib.lsb_ref_init(h, dummy, dummy, dummy, dummy, None) == lsb.LSB_EINVAL

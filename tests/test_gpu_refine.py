@@ -292,3 +292,62 @@ def test_nested_rejects_two_level_calls(require_gpu):
     g.init(*args)
     with pytest.raises(LsbError):
         g.remesh((5, 20, 5, 20))   # re-meshing takes two levels
+
+
+@pytest.mark.parametrize("lattice,n3,boxes,max_ext,max_inner,margins", [
+    (0, (64, 56, 1), [(20, 30, 18, 28), (4, 16, 5, 15)], (40, 40, 0), [(60, 60, 0)], (3, 1)),
+    (2, (30, 28, 26), [(10, 16, 9, 15, 8, 14), (2, 10, 3, 9, 2, 10)], (24, 24, 22), [(40, 40, 40)], (2, 1)),
+])
+def test_nested_sensor_and_remesh_match_oracle(require_gpu, lattice, n3, boxes, max_ext, max_inner, margins):
+    """Three levels: steps, the sensor's boxes on a gas disk/sphere against
+    the oracle's, re-meshing every level onto them, steps, then onto the
+    boxes of a narrower band (smaller d_ref), steps; every level against the
+    oracle after each phase."""
+    from paper_2601_05936_amd.lsb import Refine
+    nx, ny, nz = n3
+    o = RefineOracle(nx, ny, boxes, 0.7, lattice=lattice, nz=nz)
+    args = _fields_nested(o, seed=9)
+    g = Refine(nx, ny, boxes, 0.7, lattice=lattice, nz=nz, max_extent=max_ext, max_inner_extent=max_inner)
+    o.init(*args)
+    g.init(*args)
+    if lattice == 0:
+        J, I = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+        phi = 9.5 - np.hypot(I - 33.2, J - 24.7)
+    else:
+        K, J, I = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        phi = 5.5 - np.sqrt((I - 14.6) ** 2 + (J - 13.2) ** 2 + (K - 12.9) ** 2)
+
+    def check(label):
+        errs = [float(np.max(np.abs(b - a))) for a, b in zip(o.populations(), g.populations())]
+        print(f"nested remesh D={g.D} {label}: " + " ".join(f"{e:.2e}" for e in errs), flush=True)
+        assert max(errs) <= TOL
+
+    o.step(4)
+    g.step(4)
+    check("before")
+    for d_ref in (2.0, 0.5):
+        got = g.sensor_levels(phi.reshape(-1), d_ref, margins)
+        want = o.sensor_levels(phi.reshape(-1), d_ref, margins)
+        assert got == want, (got, want)
+        o.remesh_levels(want)
+        g.remesh_levels(got)
+        check(f"re-meshed (d_ref {d_ref})")
+        o.step(3)
+        g.step(3)
+        check(f"after (d_ref {d_ref})")
+
+
+def test_nested_remesh_rejects_boxes_beyond_the_workspace(require_gpu):
+    from paper_2601_05936_amd.lsb import LsbError, Refine
+    boxes = [(10, 20, 10, 20), (4, 12, 4, 12)]
+    g = Refine(40, 40, boxes, 0.7, max_extent=(14, 14, 0), max_inner_extent=[(10, 10, 0)])
+    args = []
+    for lv in range(3):
+        args += [np.ones(g.n_level(lv)), np.zeros(2 * g.n_level(lv))]
+    g.init(*args)
+    with pytest.raises(LsbError):
+        g.remesh_levels([(10, 20, 10, 20), (4, 15, 4, 12)])   # 11 cells > 10
+    with pytest.raises(LsbError):
+        g.remesh_levels([(10, 20, 10, 20), (4, 20, 4, 12)])   # beyond level 1's last node - 1
+    g.remesh_levels([(6, 20, 10, 24), (2, 12, 16, 26)])      # fits
+    assert g.boxes[1][:4] == (2, 12, 16, 26)
