@@ -52,7 +52,7 @@ struct RefArgs {
   int pw, ph;                                          // parent pitches
   long po;                                             // parent node (0, 0, 0)
   int bw, bh, bd;                                      // patch box extents in x, y, z (bd = 1 in 2D)
-  int fw, fh;                                          // fine pitches with the ghost shell: mx + 3, my + 3
+  int fw, fh;                                          // fine pitches with the ghost shell: row_pitch(mx), my + 3
   long nc, nf, nb;                                     // nodes: coarse, fine (with the shell), box surface
   long fo[6];                                          // start of each face's nodes in the surface arrays
   double tc, tf;
@@ -131,8 +131,15 @@ __device__ __forceinline__ bool in_box(const RefArgs& a, int I, int J, int K) {
   return I >= a.ia && I <= a.ib && J >= a.ja && J <= a.jb && (a.D == 2 || (K >= a.ka && K <= a.kb));
 }
 
+// A refined level's rows start their node 0 at column 16 of a pitch that is
+// a multiple of 16 doubles, so a 256-node row segment is 128-byte aligned;
+// columns 15 and mx + 17 hold the ghost shell.
+constexpr int kRowOrigin = 16;
+
+__host__ __device__ __forceinline__ int row_pitch(int mx) { return (mx + kRowOrigin + 2 + 15) & ~15; }
+
 __device__ __forceinline__ long fine_index(const RefArgs& a, int i, int j, int k) {
-  return ((long)(k + (a.D == 3 ? 1 : 0)) * a.fh + (j + 1)) * a.fw + i + 1;
+  return ((long)(k + (a.D == 3 ? 1 : 0)) * a.fh + (j + 1)) * a.fw + i + kRowOrigin;
 }
 
 // One level's nodes in its population arrays: sx x sy x sz nodes, node
@@ -444,7 +451,7 @@ void set_patch(RefArgs& a, const int* patch) {
   a.bw = a.ib - a.ia + 1;
   a.bh = a.jb - a.ja + 1;
   a.bd = a.kb - a.ka + 1;
-  a.fw = a.mx + 3;
+  a.fw = row_pitch(a.mx);
   a.fh = a.my + 3;
   a.nf = (long)a.fw * a.fh * (three ? a.mz + 3 : 1);
   // face sizes: x faces bh x bd, y faces bw x bd, z faces (3D) bw x bh
@@ -513,7 +520,7 @@ void set_parent(RefArgs& a, const RefArgs& pp) {
   a.nz = pp.mz + 1;
   a.pw = pp.fw;
   a.ph = pp.fh;
-  a.po = (pp.D == 3 ? (long)pp.fh * pp.fw : 0L) + pp.fw + 1;
+  a.po = (pp.D == 3 ? (long)pp.fh * pp.fw : 0L) + pp.fw + kRowOrigin;
   a.nc = pp.nf;
   a.tc = pp.tf;
   a.tf = 2.0 * pp.tf - 0.5;
@@ -525,7 +532,7 @@ Grid grid_of(const lsb_ref* r, int l) {
     return Grid{b.nx, b.ny, b.nz, b.nx, b.ny, 0L, b.nc};
   }
   const RefArgs& a = pair_of(r, l);
-  return Grid{a.mx + 1, a.my + 1, a.mz + 1, a.fw, a.fh, (a.D == 3 ? (long)a.fh * a.fw : 0L) + a.fw + 1, a.nf};
+  return Grid{a.mx + 1, a.my + 1, a.mz + 1, a.fw, a.fh, (a.D == 3 ? (long)a.fh * a.fw : 0L) + a.fw + kRowOrigin, a.nf};
 }
 
 int check_launch() {
@@ -730,7 +737,7 @@ int lsb_ref_create(const lsb_ref_params* P, lsb_ref** out) {
     if (P->max_extent[d] < 0 || P->max_extent[d] > n - 3) return fail(LSB_EINVAL, "max_extent outside [0, n - 3]");
     if (P->max_extent[d] > ext[d]) ext[d] = P->max_extent[d];
   }
-  const long cap = (2L * ext[0] + 3) * (2L * ext[1] + 3) * (three ? 2L * ext[2] + 3 : 1);
+  const long cap = (long)row_pitch(2 * ext[0]) * (2L * ext[1] + 3) * (three ? 2L * ext[2] + 3 : 1);
   if (cap > (1L << 31)) return fail(LSB_EINVAL, "grid too large");
   lsb_ref* r = new lsb_ref();
   r->P = *P;
@@ -784,7 +791,7 @@ int lsb_ref_create(const lsb_ref_params* P, lsb_ref** out) {
       }
       if (d < (three ? 3 : 2) && mx > e[d]) e[d] = mx;
     }
-    r->dcap[l] = (2L * e[0] + 3) * (2L * e[1] + 3) * (three ? 2L * e[2] + 3 : 1);
+    r->dcap[l] = (long)row_pitch(2 * e[0]) * (2L * e[1] + 3) * (three ? 2L * e[2] + 3 : 1);
     r->dbcap[l] = 2L * (e[1] + 1) * (e[2] + 1) + 2L * (e[0] + 1) * (e[2] + 1) + (three ? 2L * (e[0] + 1) * (e[1] + 1) : 0L);
     if (r->dcap[l] > (1L << 31)) {
       delete r;

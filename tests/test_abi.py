@@ -106,6 +106,11 @@ def test_reverse_mode_rejects_per_bubble_baselines():
         lib.lsb_destroy(h)
 
 
+def _pitch(mx):
+    """Row pitch of a refined level: node 0 at column 16, rounded up to 16."""
+    return (mx + 18 + 15) // 16 * 16
+
+
 def _ref_create(**kw):
     p = dict(lattice=lsb.D2Q9, nx=32, ny=24, nz=1, patch=(8, 20, 6, 16, 0, 0), tau_c=0.7)
     p.update(kw)
@@ -149,7 +154,8 @@ def test_refine_create_rejects_invalid_parameters(bad):
 def test_refine_workspace_layout():
     """Workspace = 2 x (coarse + fine with a one-node ghost shell + the box
     surface), Q doubles per node, each part aligned to 256 bytes, sized for
-    the largest patch, plus the sensor's partial boxes."""
+    the largest patch, plus the sensor's partial boxes.  Fine rows start
+    node 0 at column 16 of a pitch rounded up to 16 doubles."""
     def up(v):
         return (v + 255) // 256 * 256
     lib = lsb.load()
@@ -163,11 +169,11 @@ def test_refine_workspace_layout():
         mx, my, mz = 2 * (ib - ia), 2 * (jb - ja), 2 * (kb - ka)
         nc = n3[0] * n3[1] * n3[2]
         if lat == lsb.D2Q9:
-            nf = (mx + 3) * (my + 3)
+            nf = _pitch(mx) * (my + 3)
             ns = 2 * (jb - ja + 1) + 2 * (ib - ia + 1)
         else:
             bw, bh, bd = ib - ia + 1, jb - ja + 1, kb - ka + 1
-            nf = (mx + 3) * (my + 3) * (mz + 3)
+            nf = _pitch(mx) * (my + 3) * (mz + 3)
             ns = 2 * bh * bd + 2 * bw * bd + 2 * bw * bh
         assert nb.value == 2 * (up(8 * Q * nc) + up(8 * Q * nf) + up(8 * Q * ns)) + up(4 * 6 * 1025)
         assert lib.lsb_ref_bind(h, C.c_void_p(1 << 20), nb.value - 1) == lsb.LSB_ENOMEM
@@ -194,7 +200,7 @@ def test_refine_nested_workspace_layout():
     for ia, ib, ja, jb, ka, kb in boxes:
         mx, my, mz = 2 * (ib - ia), 2 * (jb - ja), 2 * (kb - ka)
         bw, bh, bd = ib - ia + 1, jb - ja + 1, kb - ka + 1
-        nf = (mx + 3) * (my + 3) * (mz + 3)
+        nf = _pitch(mx) * (my + 3) * (mz + 3)
         ns = 2 * bh * bd + 2 * bw * bd + 2 * bw * bh
         extra += 2 * (up(8 * 27 * nf) + up(8 * 27 * ns))
     assert nb.value == n2.value + extra
@@ -204,7 +210,7 @@ def test_refine_nested_workspace_layout():
     n3 = C.c_size_t()
     assert lib.lsb_ref_workspace_bytes(h3, C.byref(n3)) == lsb.LSB_OK
     e = (12, 14, 8)
-    nf = (2 * e[0] + 3) * (2 * e[1] + 3) * (2 * e[2] + 3)
+    nf = _pitch(2 * e[0]) * (2 * e[1] + 3) * (2 * e[2] + 3)
     ns = 2 * (e[1] + 1) * (e[2] + 1) + 2 * (e[0] + 1) * (e[2] + 1) + 2 * (e[0] + 1) * (e[1] + 1)
     assert n3.value == n2.value + 2 * (up(8 * 27 * nf) + up(8 * 27 * ns))
     lib.lsb_ref_destroy(h3)
