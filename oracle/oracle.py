@@ -124,6 +124,9 @@ def _load():
     lib.orc_mref_create.restype = C.c_void_p
     lib.orc_mref_create.argtypes = [C.c_int, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int), C.c_double,
                                     C.POINTER(C.c_double)]
+    lib.orc_tree_create.restype = C.c_void_p
+    lib.orc_tree_create.argtypes = [C.c_int, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                    C.c_double, C.POINTER(C.c_double)]
     lib.orc_mref_init.argtypes = [C.c_void_p, C.POINTER(dp), C.POINTER(dp)]
     lib.orc_mref_get.argtypes = [C.c_void_p, C.c_int, dp]
     lib.orc_ref_sensor_levels.argtypes = [C.c_void_p, dp, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_int)]
@@ -385,15 +388,19 @@ class RefineOracle:
     periodic.  patch is one box (ia, ib, ja, jb) (+ (ka, kb) in 3D), the
     coarse nodes the fine level covers, inclusive, at half spacing (fine node
     (i, j, k) at (ia + i/2, ja + j/2, ka + k/2)); or a list of such boxes,
-    level 1 first, each in its parent level's node coordinates.  Populations
-    are [Q][nodes] (x fastest), the paper's ordering; velocities [nodes][D].
+    level 1 first, each in its parent level's node coordinates.  With
+    parents (one index per box: 0 for the coarse grid, else an earlier box,
+    counted from 1) the boxes form a tree: several disjoint boxes may refine
+    one grid.  Populations are [Q][nodes] (x fastest), the paper's ordering;
+    velocities [nodes][D].
     tau_f = None takes 2 tau - 1/2 from level to level (constant viscosity);
     a number overrides level 1's, a list (one entry per refined level, None
     for the derived value) any level's: the tests pass other values only to
     plant a mistake.
     """
 
-    def __init__(self, nx: int, ny: int, patch, tau_c: float, tau_f=None, lattice: int = 0, nz: int = 1):
+    def __init__(self, nx: int, ny: int, patch, tau_c: float, tau_f=None, lattice: int = 0, nz: int = 1,
+                 parents=None):
         lib = _load()
         self.lattice = int(lattice)
         self.D, self.Q = (2, 9) if self.lattice == 0 else (3, 19 if self.lattice == 1 else 27)
@@ -404,6 +411,7 @@ class RefineOracle:
             p = tuple(int(v) for v in bx)
             self.boxes.append(p[:6] if self.D == 3 else p[:4] + (0, 0))
         self.levels = len(self.boxes) + 1
+        self.parents = list(range(len(self.boxes))) if parents is None else [int(v) for v in parents]
         over = [None] * (self.levels - 1)
         if tau_f is not None:
             if np.isscalar(tau_f):
@@ -412,12 +420,14 @@ class RefineOracle:
                 over = [None if t is None else float(t) for t in tau_f]
         self.taus = [float(tau_c)]
         for l in range(1, self.levels):
-            self.taus.append(2.0 * self.taus[-1] - 0.5 if over[l - 1] is None else over[l - 1])
+            par = self.parents[l - 1] if 0 <= self.parents[l - 1] < l else 0
+            self.taus.append(2.0 * self.taus[par] - 0.5 if over[l - 1] is None else over[l - 1])
         n3 = (C.c_int * 3)(self.nx, self.ny, self.nz)
         flat = [v for bx in self.boxes for v in bx]
         pp = (C.c_int * len(flat))(*flat)
         tt = (C.c_double * self.levels)(*self.taus)
-        self._h = lib.orc_mref_create(self.lattice, n3, self.levels, pp, float(tau_c), tt)
+        par = (C.c_int * len(self.parents))(*self.parents)
+        self._h = lib.orc_tree_create(self.lattice, n3, len(self.boxes), par, pp, float(tau_c), tt)
         if not self._h:
             raise ValueError("invalid refinement configuration")
         self._lib = lib
@@ -457,8 +467,13 @@ class RefineOracle:
     def coords(self, level: int):
         """Coarse-unit coordinates of a level's nodes, [nodes] each: (x, y)
         in 2D, (x, y, z) in 3D."""
+        path = []
+        l = level
+        while l > 0:
+            path.append(l)
+            l = self.parents[l - 1]
         o, h = np.zeros(3), 1.0
-        for l in range(1, level + 1):
+        for l in reversed(path):
             bx = self.boxes[l - 1]
             o = o + h * np.array([bx[0], bx[2], bx[4]], dtype=float)
             h *= 0.5
@@ -523,7 +538,10 @@ class RefineOracle:
         out = (C.c_int * (6 * nl))()
         mg = (C.c_int * nl)(*[int(m) for m in margins])
         keep = _f64(phi, self.n_coarse)
-        if not self._lib.orc_ref_sensor_levels(self._h, _dp(keep), float(d_ref), mg, out):
+        rc = self._lib.orc_ref_sensor_levels(self._h, _dp(keep), float(d_ref), mg, out)
+        if rc < 0:
+            raise ValueError("the sensor's boxes need a chain of nested levels")
+        if not rc:
             return None
         return [tuple(out[6 * l:6 * l + 6]) for l in range(nl)]
 

@@ -52,7 +52,8 @@ extern "C" int orc_lattice(int lattice, int* D, int* Q, int* c, double* w, int* 
 namespace ref {
 
 constexpr int QMAX = 27;
-constexpr int LMAX = 4;
+constexpr int LMAX = 4;   // levels of a chain
+constexpr int BMAX = 16;  // grids of a tree: the coarse grid and up to 15 boxes
 
 // one grid level: nodes (i, j, k), i in [0, mx], and for a refined level its
 // box [ia, ib] x [ja, jb] (x [ka, kb]) in the parent's node coordinates, node
@@ -62,6 +63,8 @@ struct Level {
   int mx = 0, my = 0, mz = 0;
   int ia = 0, ib = 0, ja = 0, jb = 0, ka = 0, kb = 0;
   double tau = 1.0;
+  int parent = -1;             // index of the parent grid (-1: the coarse grid itself)
+  std::vector<int> kids;       // boxes refining this grid (disjoint, one node apart at least)
   std::vector<double> f;       // post-collision populations [q][node], x fastest
   std::vector<double> g0, g1;  // the parent's pre-collision sets over the box, times t and t + 1
 
@@ -95,8 +98,15 @@ struct Ref {
   int D = 2, Q = 9;
   int cx[QMAX], cy[QMAX], cz[QMAX];
   double w[QMAX];
-  int L = 2;
-  Level lv[LMAX];  // lv[0]: the periodic coarse grid
+  int L = 2;        // grids: the coarse grid and the boxes
+  Level lv[BMAX];   // lv[0]: the periodic coarse grid; a box's parent has a smaller index
+
+  // every box refines the one before it (a chain of nested levels)
+  bool chain() const {
+    for (int l = 1; l < L; ++l)
+      if (lv[l].parent != l - 1) return false;
+    return true;
+  }
 
   // eq. (feq) with c_s^2 = 1/3
   void feq(double rho, double ux, double uy, double uz, double* out) const {
@@ -135,7 +145,7 @@ struct Ref {
     }
     for (int l = 1; l < L; ++l) {
       Level& c = lv[l];
-      const Level& p = lv[l - 1];
+      const Level& p = lv[c.parent];
       c.g0.assign(Q * c.nb(), 0.0);
       c.g1.assign(Q * c.nb(), 0.0);
       for (int K = c.ka; K <= c.kb; ++K)
@@ -161,22 +171,23 @@ struct Ref {
         }
   }
 
-  // One time step of level l, returning its new post-collision populations.
-  // Level 0 pulls periodically and skips the nodes its child covers; a
-  // refined level takes the populations whose source lies outside its box
-  // from the parent's G (time weights a, b), and with restrict_ writes the
-  // parent's covered nodes into parent_new.  Nodes on the child's perimeter
-  // store their pre-collision sets as the child's G(t + 1).
+  // One time step of grid l, returning its new post-collision populations.
+  // The coarse grid pulls periodically and skips the nodes its boxes cover;
+  // a box takes the populations whose source lies outside it from the
+  // parent's G (time weights a, b), and with restrict_ writes the parent's
+  // covered nodes into parent_new.  Nodes on a child box's perimeter store
+  // their pre-collision sets as that child's G(t + 1).
   std::vector<double> step_level(int l, double a, double b, bool restrict_, std::vector<double>* parent_new) {
     Level& v = lv[l];
-    Level* c = l + 1 < L ? &lv[l + 1] : nullptr;
-    const Level* p = l > 0 ? &lv[l - 1] : nullptr;
+    const Level* p = l > 0 ? &lv[v.parent] : nullptr;
     std::vector<double> out = v.f;
     double f[QMAX], e[QMAX];
     for (int k = 0; k <= v.mz; ++k)
       for (int j = 0; j <= v.my; ++j)
         for (int i = 0; i <= v.mx; ++i) {
-          if (l == 0 && c && c->covered(i, j, k)) continue;
+          bool skip = false;
+          for (int kd : v.kids) skip = skip || (l == 0 && lv[kd].covered(i, j, k));
+          if (skip) continue;
           bool missing = false;
           for (int q = 0; q < Q; ++q) {
             int si = i - cx[q], sj = j - cy[q], sk = k - cz[q];
@@ -198,8 +209,11 @@ struct Ref {
             for (int q = 0; q < Q; ++q)
               if (v.outside(i - cx[q], j - cy[q], k - cz[q])) f[q] = eh[q] + v.tau / (2.0 * p->tau) * (H[q] - eh[q]);
           }
-          if (c && c->perimeter(i, j, k))
-            for (int q = 0; q < Q; ++q) c->g1[q * c->nb() + c->box(i, j, k)] = f[q];
+          for (int kd : v.kids) {
+            Level& c = lv[kd];
+            if (c.perimeter(i, j, k))
+              for (int q = 0; q < Q; ++q) c.g1[q * c.nb() + c.box(i, j, k)] = f[q];
+          }
           double rho, ux, uy, uz;
           moments(f, rho, ux, uy, uz);
           feq(rho, ux, uy, uz, e);
@@ -214,14 +228,14 @@ struct Ref {
     return out;
   }
 
-  // the two sub-steps of refined level l within one step of its parent,
-  // each followed by the child's two sub-steps
+  // the two sub-steps of box l within one step of its parent, each
+  // followed by its child boxes' two sub-steps (one child after the other)
   void advance(int l, std::vector<double>& parent_new) {
     for (int s = 1; s <= 2; ++s) {
       std::vector<double> nf = step_level(l, s == 1 ? 0.5 : 0.0, s == 1 ? 0.5 : 1.0, s == 2, &parent_new);
-      if (l + 1 < L) {
-        advance(l + 1, nf);
-        lv[l + 1].g0.swap(lv[l + 1].g1);
+      for (int kd : lv[l].kids) {
+        advance(kd, nf);
+        lv[kd].g0.swap(lv[kd].g1);
       }
       lv[l].f.swap(nf);
     }
@@ -229,9 +243,9 @@ struct Ref {
 
   void step() {
     std::vector<double> nf = step_level(0, 0.0, 0.0, false, nullptr);
-    if (L > 1) {
-      advance(1, nf);
-      lv[1].g0.swap(lv[1].g1);
+    for (int kd : lv[0].kids) {
+      advance(kd, nf);
+      lv[kd].g0.swap(lv[kd].g1);
     }
     lv[0].f.swap(nf);
   }
@@ -418,15 +432,15 @@ struct Ref {
 
 extern "C" {
 
-// lattice: 0 D2Q9, 1 D3Q19, 2 D3Q27 (the oracle's numbering); n = (nx, ny,
-// nz) with nz = 1 in 2D; levels in [2, 4]; patches[6 (l - 1) ...] = (ia, ib,
-// ja, jb, ka, kb) of level l in level l - 1's node coordinates (ka = kb = 0
-// in 2D), each with one node to spare at every side of its parent (level 0:
-// 1 <= ia, ib <= nx - 2) and at least two cells per axis.  tau[l] <= 0 (or
-// tau == NULL) selects the constant-viscosity value 2 tau[l-1] - 1/2; the
-// tests pass another value only to check that a pin catches a wrong one.
-void* orc_mref_create(int lattice, const int* n, int levels, const int* patches, double tau_c, const double* tau) {
-  if (!n || !patches || levels < 2 || levels > ref::LMAX || !(tau_c > 0.5)) return nullptr;
+// A tree of boxes: box b (1 .. nbox) refines grid parents[b - 1] (0: the
+// coarse grid, else an earlier box) over boxes[6 (b - 1) ...] = (ia, ib, ja,
+// jb, ka, kb) of the parent's nodes (ka = kb = 0 in 2D), with one node to
+// spare at every side of the parent, at least two cells per axis, and
+// siblings at least one parent node apart.  tau[b] <= 0 (or tau == NULL)
+// selects the constant-viscosity value 2 tau[parent] - 1/2.
+void* orc_tree_create(int lattice, const int* n, int nbox, const int* parents, const int* boxes, double tau_c,
+                      const double* tau) {
+  if (!n || (nbox > 0 && (!parents || !boxes)) || nbox < 1 || nbox + 1 > ref::BMAX || !(tau_c > 0.5)) return nullptr;
   ref::Ref* r = new ref::Ref();
   int c[3 * ref::QMAX], opp[ref::QMAX];
   if (orc_lattice(lattice, &r->D, &r->Q, c, r->w, opp) != 0) {
@@ -438,27 +452,52 @@ void* orc_mref_create(int lattice, const int* n, int levels, const int* patches,
     r->cy[q] = c[3 * q + 1];
     r->cz[q] = c[3 * q + 2];
   }
-  r->L = levels;
-  for (int l = 0; l < levels; ++l) r->lv[l].D = r->D;
+  r->L = nbox + 1;
+  for (int l = 0; l < r->L; ++l) r->lv[l].D = r->D;
   ref::Level& g = r->lv[0];
   g.mx = n[0] - 1;
   g.my = n[1] - 1;
   g.mz = r->D == 3 ? n[2] - 1 : 0;
   g.tau = tau_c;
   bool ok = g.mx >= 3 && g.my >= 3 && (r->D == 2 || g.mz >= 3);
-  for (int l = 1; l < levels && ok; ++l) {
-    const ref::Level& p = r->lv[l - 1];
+  for (int l = 1; l < r->L && ok; ++l) {
     ref::Level& v = r->lv[l];
-    v.set_box(patches + 6 * (l - 1));
+    v.parent = parents[l - 1];
+    ok = v.parent >= 0 && v.parent < l;
+    if (!ok) break;
+    const ref::Level& p = r->lv[v.parent];
+    v.set_box(boxes + 6 * (l - 1));
     v.tau = tau && tau[l] > 0.0 ? tau[l] : 2.0 * p.tau - 0.5;
     ok = v.ia >= 1 && v.ib <= p.mx - 1 && v.ib - v.ia >= 2 && v.ja >= 1 && v.jb <= p.my - 1 && v.jb - v.ja >= 2 &&
          (r->D == 2 || (v.ka >= 1 && v.kb <= p.mz - 1 && v.kb - v.ka >= 2));
+    // siblings at least one parent node apart on some axis
+    for (int o : r->lv[v.parent].kids) {
+      const ref::Level& w = r->lv[o];
+      const bool apart = v.ib + 2 <= w.ia || w.ib + 2 <= v.ia || v.jb + 2 <= w.ja || w.jb + 2 <= v.ja ||
+                         (r->D == 3 && (v.kb + 2 <= w.ka || w.kb + 2 <= v.ka));
+      ok = ok && apart;
+    }
+    r->lv[v.parent].kids.push_back(l);
   }
   if (!ok) {
     delete r;
     return nullptr;
   }
   return r;
+}
+
+// lattice: 0 D2Q9, 1 D3Q19, 2 D3Q27 (the oracle's numbering); n = (nx, ny,
+// nz) with nz = 1 in 2D; levels in [2, 4]; patches[6 (l - 1) ...] = (ia, ib,
+// ja, jb, ka, kb) of level l in level l - 1's node coordinates (ka = kb = 0
+// in 2D), each with one node to spare at every side of its parent (level 0:
+// 1 <= ia, ib <= nx - 2) and at least two cells per axis.  tau[l] <= 0 (or
+// tau == NULL) selects the constant-viscosity value 2 tau[l-1] - 1/2; the
+// tests pass another value only to check that a pin catches a wrong one.
+void* orc_mref_create(int lattice, const int* n, int levels, const int* patches, double tau_c, const double* tau) {
+  if (levels < 2 || levels > ref::LMAX) return nullptr;
+  int parents[ref::LMAX];
+  for (int l = 1; l < levels; ++l) parents[l - 1] = l - 1;
+  return orc_tree_create(lattice, n, levels - 1, parents, patches, tau_c, tau);
 }
 
 // two levels: patch of level 1, tau_f <= 0 for 2 tau_c - 1/2
@@ -498,7 +537,7 @@ int orc_ref_sensor(void* h, const double* phi, double d_ref, int margin, int* ou
 // if it does not fit the grid or the hierarchy has more levels
 int orc_ref_remesh(void* h, const int* patch) {
   ref::Ref* r = static_cast<ref::Ref*>(h);
-  if (r->L != 2 || r->lv[0].f.empty()) return -1;
+  if (r->L != 2 || !r->chain() || r->lv[0].f.empty()) return -1;
   const ref::Level& g = r->lv[0];
   const int n[3] = {g.mx + 1, g.my + 1, g.mz + 1};
   for (int d = 0; d < r->D; ++d)
@@ -510,6 +549,7 @@ int orc_ref_remesh(void* h, const int* patch) {
 // nested sensor: margins[l - 1] (coarse nodes) for level l; out receives 6
 // ints per refined level; returns 1 when a node is tagged, 0 otherwise
 int orc_ref_sensor_levels(void* h, const double* phi, double d_ref, const int* margins, int* out) {
+  if (!static_cast<ref::Ref*>(h)->chain()) return -1;
   return static_cast<ref::Ref*>(h)->sensor_boxes(phi, d_ref, margins, out) ? 1 : 0;
 }
 
@@ -518,7 +558,7 @@ int orc_ref_sensor_levels(void* h, const double* phi, double d_ref, const int* m
 int orc_ref_remesh_levels(void* h, const int* boxes) {
   ref::Ref* r = static_cast<ref::Ref*>(h);
   const ref::Level& g = r->lv[0];
-  if (g.f.empty()) return -1;  // not initialised
+  if (g.f.empty() || !r->chain()) return -1;  // not initialised, or not a chain of levels
   int last[3] = {g.mx, g.my, g.mz};  // the parent's last node index per axis
   for (int l = 1; l < r->L; ++l) {
     const int* b = boxes + 6 * (l - 1);
