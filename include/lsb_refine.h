@@ -58,6 +58,7 @@ extern "C" {
 #endif
 
 #define LSB_REF_MAX_LEVELS 4
+#define LSB_REF_MAX_BOXES 15
 
 typedef struct lsb_ref_params {
   int lattice;      /* LSB_D2Q9, LSB_D3Q19 or LSB_D3Q27 */
@@ -87,6 +88,21 @@ typedef struct lsb_ref lsb_ref;
  * the ranges above, or a level of more than 2^31 nodes (with the ghost
  * shell). */
 int lsb_ref_create(const lsb_ref_params* params, lsb_ref** out);
+
+/* A tree of boxes instead of a chain: box b (1 .. nbox) refines grid
+ * parents[b - 1] (0: the coarse grid, else an earlier box; parents[0] = 0)
+ * over boxes[6 (b - 1) ...] = (ia, ib, ja, jb, ka, kb) of that grid's nodes,
+ * with one node to spare at every side, at least two cells per axis, at
+ * most 8 boxes per grid, and the boxes refining one grid at least one of
+ * its nodes apart (each pair of grids is coupled as above; a grid's
+ * sub-step is followed by each of its boxes' two sub-steps in turn).
+ * params gives the lattice, the coarse grid, tau_c and box 1's max_extent;
+ * its patch, levels, inner and max_inner_extent are not read.  Grid b's
+ * arrays in lsb_ref_init_levels and lsb_ref_get_level are box b's; the
+ * sensor and re-meshing take chains only (LSB_EINVAL for a tree).
+ * LSB_EINVAL for anything outside these ranges. */
+int lsb_ref_create_tree(const lsb_ref_params* params, int nbox, const int* parents, const int* boxes,
+                        lsb_ref** out);
 void lsb_ref_destroy(lsb_ref* ref);
 
 /* Device workspace the caller provides: every level's populations twice

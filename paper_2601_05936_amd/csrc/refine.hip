@@ -64,6 +64,22 @@ struct RefArgs {
   double* g1;        // time t + 1
 };
 
+// The boxes refining one grid, as its kernels see them: each box's extent in
+// the grid's node coordinates, its perimeter-set faces and where the sets of
+// the time level being written go (g).
+constexpr int kMaxKids = 8;
+
+struct KidBox {
+  int D, ia, ib, ja, jb, ka, kb, bw, bh;
+  long fo[6], nb;
+  double* g;
+};
+
+struct Kids {
+  int n;
+  KidBox k[kMaxKids];
+};
+
 // Blocks are dispatched round-robin over the 8 XCDs; logical block L of a
 // row-major (row, segment) order goes to one XCD's contiguous share, so the
 // rows a block pulls from sit in the same L2.  A bijection of [0, nb) for
@@ -104,15 +120,16 @@ __device__ __forceinline__ double equilibrium(int q, double rho, double ux, doub
 // z faces), so the threads of a face read consecutive entries.  Faces: 0/1
 // at I = ia / ib, 2/3 at J = ja / jb, 4/5 at K = ka / kb (3D).  A node on an
 // edge or corner of the box is stored on each of its faces.
-__device__ __forceinline__ long face_index(const RefArgs& a, int f, int I, int J, int K) {
+template <class B>
+__device__ __forceinline__ long face_index(const B& a, int f, int I, int J, int K) {
   if (f < 2) return a.fo[f] + (long)(K - a.ka) * a.bh + (J - a.ja);
   if (f < 4) return a.fo[f] + (long)(K - a.ka) * a.bw + (I - a.ia);
   return a.fo[f] + (long)(J - a.ja) * a.bw + (I - a.ia);
 }
 
 // stores set v (Q values) of perimeter node (I, J, K) on each face it lies on
-template <int Q>
-__device__ __forceinline__ void store_faces(const RefArgs& a, double* g, int I, int J, int K, const double* v) {
+template <int Q, class B>
+__device__ __forceinline__ void store_faces(const B& a, double* g, int I, int J, int K, const double* v) {
   const bool on[6] = {I == a.ia, I == a.ib, J == a.ja, J == a.jb, a.D == 3 && K == a.ka, a.D == 3 && K == a.kb};
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
@@ -123,11 +140,13 @@ __device__ __forceinline__ void store_faces(const RefArgs& a, double* g, int I, 
   }
 }
 
-__device__ __forceinline__ bool covered(const RefArgs& a, int I, int J, int K) {
+template <class B>
+__device__ __forceinline__ bool covered(const B& a, int I, int J, int K) {
   return I > a.ia && I < a.ib && J > a.ja && J < a.jb && (a.D == 2 || (K > a.ka && K < a.kb));
 }
 
-__device__ __forceinline__ bool in_box(const RefArgs& a, int I, int J, int K) {
+template <class B>
+__device__ __forceinline__ bool in_box(const B& a, int I, int J, int K) {
   return I >= a.ia && I <= a.ib && J >= a.ja && J <= a.jb && (a.D == 2 || (K >= a.ka && K <= a.kb));
 }
 
@@ -149,11 +168,11 @@ struct Grid {
   long po, n;
 };
 
-// equilibrium initial state of one level; with a child, the child
-// perimeter's sets G(t) are those equilibria
+// equilibrium initial state of one grid; its boxes' perimeter sets G(t) are
+// those equilibria
 template <int LAT>
 __global__ __launch_bounds__(256) void k_ref_init_level(Grid g, const double* rho, const double* u, double* f,
-                                                        int has_child, RefArgs c, double* cg0) {
+                                                        Kids kids) {
   constexpr int Q = Lat<LAT>::Q, D = Lat<LAT>::D;
   const long nn = (long)g.sx * g.sy * g.sz;
   for (long n = (long)blockIdx.x * 256 + threadIdx.x; n < nn; n += (long)gridDim.x * 256) {
@@ -166,22 +185,25 @@ __global__ __launch_bounds__(256) void k_ref_init_level(Grid g, const double* rh
       e[q] = equilibrium<LAT>(q, rho[n], ux, uy, uz);
       f[q * g.n + p] = e[q];
     }
-    if (has_child && in_box(c, i, j, k) && !covered(c, i, j, k)) store_faces<Q>(c, cg0, i, j, k, e);
+    for (int b = 0; b < kids.n; ++b)
+      if (in_box(kids.k[b], i, j, k) && !covered(kids.k[b], i, j, k)) store_faces<Q>(kids.k[b], kids.k[b].g, i, j, k, e);
   }
 }
 
-// uncovered coarse nodes: pull (periodic), keep the perimeter's pre-collision
-// set, collide with tau_c
+// uncovered coarse nodes: pull (periodic), keep the pre-collision sets of
+// the boxes' perimeter nodes, collide with tau_c
 template <int LAT>
-__global__ __launch_bounds__(256) void k_ref_coarse(RefArgs a, int segs) {
+__global__ __launch_bounds__(256) void k_ref_coarse(RefArgs a, Kids kids, int segs) {
   using L = Lat<LAT>;
   constexpr int Q = L::Q;
   const int Lb = (int)xcd_block(blockIdx.x, gridDim.x);
   const int row = Lb / segs, x = (Lb - row * segs) * 256 + (int)threadIdx.x;
   if (x >= a.nx) return;
   const int y = row % a.ny, z = row / a.ny;
-  const bool inb = in_box(a, x, y, z);
-  if (inb && covered(a, x, y, z)) return;  // restricted from the fine level
+  int kid = -1;  // the box whose perimeter or interior holds the node (boxes are disjoint)
+  for (int b = 0; b < kids.n; ++b)
+    if (in_box(kids.k[b], x, y, z)) kid = b;
+  if (kid >= 0 && covered(kids.k[kid], x, y, z)) return;  // restricted from the fine level
   const int xs[3] = {x + 1 == a.nx ? 0 : x + 1, x, x == 0 ? a.nx - 1 : x - 1};  // source for c = -1, 0, 1
   const int ys[3] = {y + 1 == a.ny ? 0 : y + 1, y, y == 0 ? a.ny - 1 : y - 1};
   const int zs[3] = {z + 1 == a.nz ? 0 : z + 1, z, z == 0 ? a.nz - 1 : z - 1};
@@ -189,7 +211,7 @@ __global__ __launch_bounds__(256) void k_ref_coarse(RefArgs a, int segs) {
 #pragma unroll
   for (int q = 0; q < Q; ++q)
     f[q] = a.fc_in[q * a.nc + ((long)zs[L::cz(q) + 1] * a.ny + ys[L::cy(q) + 1]) * a.nx + xs[L::cx(q) + 1]];
-  if (inb) store_faces<Q>(a, a.g1, x, y, z, f);
+  if (kid >= 0) store_faces<Q>(kids.k[kid], kids.k[kid].g, x, y, z, f);
   double rho, ux, uy, uz;
   moments<LAT>(f, rho, ux, uy, uz);
   const long n = ((long)z * a.ny + y) * a.nx + x;
@@ -265,12 +287,12 @@ __global__ __launch_bounds__(256) void k_ref_edge(RefArgs a, double* ff1, double
 
 // fine nodes: pull (the ghost shell holds the perimeter's inward populations),
 // collide with tau_f; with restrict_ set, the fine nodes on covered coarse
-// nodes write those nodes' post-collision populations.  With a child patch
-// (c: this level as its parent), the nodes on the child's perimeter keep
-// their pre-collision sets (the child's G(t+1)) and the nodes it covers store
+// nodes write those nodes' post-collision populations.  With child boxes
+// (this level as their parent), the nodes on a child's perimeter keep their
+// pre-collision sets (the child's G(t+1)) and the nodes a child covers store
 // nothing (the child's restriction writes them).
 template <int LAT, bool CHILD>
-__global__ __launch_bounds__(256) void k_ref_fine(RefArgs a, RefArgs c, int segs, int restrict_) {
+__global__ __launch_bounds__(256) void k_ref_fine(RefArgs a, Kids kids, int segs, int restrict_) {
   using L = Lat<LAT>;
   constexpr int Q = L::Q;
   const int Lb = (int)xcd_block(blockIdx.x, gridDim.x);
@@ -283,9 +305,14 @@ __global__ __launch_bounds__(256) void k_ref_fine(RefArgs a, RefArgs c, int segs
 #pragma unroll
   for (int q = 0; q < Q; ++q) f[q] = a.ff_in[q * a.nf + p - L::cz(q) * plane - L::cy(q) * a.fw - L::cx(q)];
   bool keep = true;
-  if (CHILD && in_box(c, i, j, k)) {
-    if (covered(c, i, j, k)) keep = false;
-    else store_faces<Q>(c, c.g1, i, j, k, f);
+  if (CHILD) {
+    int kid = -1;
+    for (int b = 0; b < kids.n; ++b)
+      if (in_box(kids.k[b], i, j, k)) kid = b;
+    if (kid >= 0) {
+      if (covered(kids.k[kid], i, j, k)) keep = false;
+      else store_faces<Q>(kids.k[kid], kids.k[kid].g, i, j, k, f);
+    }
   }
   double rho, ux, uy, uz;
   moments<LAT>(f, rho, ux, uy, uz);
@@ -476,11 +503,15 @@ int q_of(int lattice) { return lattice == LSB_D2Q9 ? 9 : (lattice == LSB_D3Q19 ?
 
 }  // namespace
 
+constexpr int kMaxGrids = LSB_REF_MAX_BOXES + 1;
+
 struct lsb_ref {
   lsb_ref_params P;
-  RefArgs base;  // levels 0 and 1
-  int L = 2;
-  RefArgs deep[LSB_REF_MAX_LEVELS];  // deep[l], l >= 2: levels l - 1 and l
+  RefArgs base;  // the coarse grid and box 1
+  int L = 2;     // grids: the coarse grid and L - 1 boxes
+  int par[kMaxGrids] = {};      // par[b]: the grid box b refines (0: the coarse grid)
+  bool chain = true;            // every box refines the one before it
+  RefArgs deep[kMaxGrids];      // deep[b], b >= 2: box b and its parent
   int Q = 9;
   int ext[3] = {0, 0, 0};  // largest patch extents (coarse cells per axis) the workspace holds
   long fcap = 0, bcap = 0;  // fine nodes with the shell, box-surface nodes, at those extents
@@ -490,12 +521,12 @@ struct lsb_ref {
   double* fc[2] = {nullptr, nullptr};
   double* ff[2] = {nullptr, nullptr};
   double* g[2] = {nullptr, nullptr};
-  int dext[LSB_REF_MAX_LEVELS][3] = {};  // capacity extents (parent cells) of the deeper levels
-  long dcap[LSB_REF_MAX_LEVELS] = {}, dbcap[LSB_REF_MAX_LEVELS] = {};
-  double* dff[LSB_REF_MAX_LEVELS][2] = {};
-  double* dg[LSB_REF_MAX_LEVELS][2] = {};
-  int cur = 0;  // fc[cur] and g[cur] are the current coarse state and G(t); ff[0] the fine state
-  int dcur[LSB_REF_MAX_LEVELS] = {};  // dg[l][dcur[l]] is level l's G(t); dff[l][0] its state
+  int dext[kMaxGrids][3] = {};  // capacity extents (parent cells) of boxes 2 ..
+  long dcap[kMaxGrids] = {}, dbcap[kMaxGrids] = {};
+  double* dff[kMaxGrids][2] = {};
+  double* dg[kMaxGrids][2] = {};
+  int cur = 0;  // fc[cur] and g[cur] are the current coarse state and box 1's G(t); ff[0] box 1's state
+  int dcur[kMaxGrids] = {};  // dg[b][dcur[b]] is box b's G(t); dff[b][0] its state
   bool inited = false;
 };
 
@@ -510,10 +541,23 @@ size_t sizes(const lsb_ref* r, size_t* fcb, size_t* ffb, size_t* gb) {
   return t;
 }
 
-// the pair args of level l >= 1 (level l - 1 as the parent)
+// the pair args of box l >= 1 (with its parent)
 const RefArgs& pair_of(const lsb_ref* r, int l) { return l == 1 ? r->base : r->deep[l]; }
 
-// a refined level as the parent of the next
+// the coarse grid (as described by box 1's args) as a box's parent
+void set_parent_root(RefArgs& a, const RefArgs& b) {
+  a.nx = b.nx;
+  a.ny = b.ny;
+  a.nz = b.nz;
+  a.pw = b.nx;
+  a.ph = b.ny;
+  a.po = 0;
+  a.nc = b.nc;
+  a.tc = b.tc;
+  a.tf = b.tf;
+}
+
+// a box (pair args pp) as the parent of another
 void set_parent(RefArgs& a, const RefArgs& pp) {
   a.nx = pp.mx + 1;
   a.ny = pp.my + 1;
@@ -546,28 +590,50 @@ unsigned grid_for(long n) {
   return (unsigned)(g < 8192 ? (g > 0 ? g : 1) : 8192);
 }
 
+// box b's perimeter sets: G(t) (next = 0) or G(t+1) (next = 1)
+double* gbuf(const lsb_ref* r, int b, int next) { return b == 1 ? r->g[r->cur ^ next] : r->dg[b][r->dcur[b] ^ next]; }
+
+// the boxes refining grid gi, with the perimeter-set buffers of time level next
+Kids kids_of(const lsb_ref* r, int gi, int next) {
+  Kids k{};
+  for (int b = 1; b < r->L; ++b) {
+    if (r->par[b] != gi) continue;
+    const RefArgs& a = pair_of(r, b);
+    KidBox& c = k.k[k.n++];
+    c.D = a.D;
+    c.ia = a.ia;
+    c.ib = a.ib;
+    c.ja = a.ja;
+    c.jb = a.jb;
+    c.ka = a.ka;
+    c.kb = a.kb;
+    c.bw = a.bw;
+    c.bh = a.bh;
+    for (int f = 0; f < 6; ++f) c.fo[f] = a.fo[f];
+    c.nb = a.nb;
+    c.g = gbuf(r, b, next);
+  }
+  return k;
+}
+
 template <int LAT>
 void launch_init(lsb_ref* r, const double* const* rho, const double* const* u, hipStream_t st) {
   for (int l = 0; l < r->L; ++l) {
     const Grid g = grid_of(r, l);
     double* f = l == 0 ? r->fc[0] : (l == 1 ? r->ff[0] : r->dff[l][0]);
-    const bool child = l + 1 < r->L;
-    const RefArgs& c = child ? pair_of(r, l + 1) : r->base;
-    double* cg0 = !child ? nullptr : (l == 0 ? r->g[0] : r->dg[l + 1][0]);
-    k_ref_init_level<LAT><<<grid_for((long)g.sx * g.sy * g.sz), 256, 0, st>>>(g, rho[l], u[l], f, child ? 1 : 0, c,
-                                                                                cg0);
+    k_ref_init_level<LAT><<<grid_for((long)g.sx * g.sy * g.sz), 256, 0, st>>>(g, rho[l], u[l], f, kids_of(r, l, 0));
   }
 }
 
-// the two sub-steps of refined level l within one step of its parent (whose
-// new populations, parent_out, receive the restriction), each followed by
-// the child's
+// the two sub-steps of box l within one step of its parent (whose new
+// populations, parent_out, receive the restriction), each followed by the
+// two sub-steps of each of its own boxes
 template <int LAT>
 void advance(lsb_ref* r, int l, double* parent_out, hipStream_t st) {
   RefArgs A = pair_of(r, l);
   double** ffl = l == 1 ? r->ff : r->dff[l];
-  A.g0 = l == 1 ? r->g[r->cur] : r->dg[l][r->dcur[l]];
-  A.g1 = l == 1 ? r->g[r->cur ^ 1] : r->dg[l][r->dcur[l] ^ 1];
+  A.g0 = gbuf(r, l, 0);
+  A.g1 = gbuf(r, l, 1);
   A.fc_out = parent_out;
   const int sf = (A.mx + 1 + 255) / 256;
   const unsigned gf = (unsigned)((long)sf * (A.my + 1) * (A.mz + 1));
@@ -575,19 +641,20 @@ void advance(lsb_ref* r, int l, double* parent_out, hipStream_t st) {
                     (A.D == 3 ? 2L * (A.mx - 1) * (A.my - 1) : 0L);
   // inward populations of both sub-steps: G halfway in time, then G(t+1)
   k_ref_edge<LAT><<<dim3((unsigned)((surf + 255) / 256), 2), 256, 0, st>>>(A, ffl[0], ffl[1]);
-  const bool child = l + 1 < r->L;
   for (int s = 0; s < 2; ++s) {
     A.ff_in = ffl[s];
     A.ff_out = ffl[s ^ 1];
     // sub-step 2 also restricts onto the parent's covered nodes
-    if (child) {
-      RefArgs C = r->deep[l + 1];
-      C.g1 = r->dg[l + 1][r->dcur[l + 1] ^ 1];
-      k_ref_fine<LAT, true><<<gf, 256, 0, st>>>(A, C, sf, s);
-      advance<LAT>(r, l + 1, ffl[s ^ 1], st);
-      r->dcur[l + 1] ^= 1;
+    const Kids K = kids_of(r, l, 1);
+    if (K.n > 0) {
+      k_ref_fine<LAT, true><<<gf, 256, 0, st>>>(A, K, sf, s);
+      for (int c = 2; c < r->L; ++c)
+        if (r->par[c] == l) {
+          advance<LAT>(r, c, ffl[s ^ 1], st);
+          r->dcur[c] ^= 1;
+        }
     } else {
-      k_ref_fine<LAT, false><<<gf, 256, 0, st>>>(A, A, sf, s);
+      k_ref_fine<LAT, false><<<gf, 256, 0, st>>>(A, K, sf, s);
     }
   }
 }
@@ -601,11 +668,13 @@ void launch_steps(lsb_ref* r, int nsteps, hipStream_t st) {
     RefArgs a = b;
     a.fc_in = r->fc[r->cur];
     a.fc_out = r->fc[r->cur ^ 1];
-    a.g0 = r->g[r->cur];
-    a.g1 = r->g[r->cur ^ 1];
-    k_ref_coarse<LAT><<<gc, 256, 0, st>>>(a, sc);
-    advance<LAT>(r, 1, r->fc[r->cur ^ 1], st);
-    r->cur ^= 1;
+    k_ref_coarse<LAT><<<gc, 256, 0, st>>>(a, kids_of(r, 0, 1), sc);
+    for (int c = 1; c < r->L; ++c)
+      if (r->par[c] == 0) {
+        advance<LAT>(r, c, r->fc[r->cur ^ 1], st);
+        if (c != 1) r->dcur[c] ^= 1;
+      }
+    r->cur ^= 1;  // box 1's perimeter sets turn with the coarse state
   }
 }
 
@@ -711,19 +780,23 @@ int remesh_levels(lsb_ref* r, const int* boxes, hipStream_t st) {
   return LSB_OK;
 }
 
-}  // namespace
 
-extern "C" {
-
-int lsb_ref_create(const lsb_ref_params* P, lsb_ref** out) {
-  if (!P || !out) return fail(LSB_EINVAL, "null pointer");
+// Validates a tree of boxes and creates the handle.  Box 1 takes P's grid,
+// tau_c and max_extent; with inner_caps, box b >= 2 (a chain) is sized by
+// P->max_inner_extent[b - 2], else by its own extent.
+int create_tree(const lsb_ref_params* P, int nbox, const int* parents, const int* boxes, bool inner_caps,
+                lsb_ref** out) {
   *out = nullptr;
   if (P->lattice != LSB_D2Q9 && P->lattice != LSB_D3Q19 && P->lattice != LSB_D3Q27)
     return fail(LSB_EINVAL, "unknown lattice");
+  if (nbox < 1 || nbox > LSB_REF_MAX_BOXES) return fail(LSB_EINVAL, "1 .. LSB_REF_MAX_BOXES boxes");
+  if (parents[0] != 0) return fail(LSB_EINVAL, "box 1 must refine the coarse grid");
   const bool three = P->lattice != LSB_D2Q9;
+  const int dims = three ? 3 : 2;
   const int nx = P->nx, ny = P->ny, nz = three ? P->nz : 1;
-  const int ia = P->patch[0], ib = P->patch[1], ja = P->patch[2], jb = P->patch[3];
-  const int ka = three ? P->patch[4] : 0, kb = three ? P->patch[5] : 0;
+  const int* b1 = boxes;
+  const int ia = b1[0], ib = b1[1], ja = b1[2], jb = b1[3];
+  const int ka = three ? b1[4] : 0, kb = three ? b1[5] : 0;
   if (nx < 4 || ny < 4 || (three && nz < 4) || (!three && P->nz != 1))
     return fail(LSB_EINVAL, "coarse grid must be at least 4 nodes per axis (nz = 1 in 2D)");
   if (ia < 1 || ib > nx - 2 || ib - ia < 2 || ja < 1 || jb > ny - 2 || jb - ja < 2 ||
@@ -732,7 +805,7 @@ int lsb_ref_create(const lsb_ref_params* P, lsb_ref** out) {
   if (!(P->tau_c > 0.5)) return fail(LSB_EINVAL, "tau_c must exceed 1/2");
   if ((long)nx * ny * nz > (1L << 31)) return fail(LSB_EINVAL, "grid too large");
   int ext[3] = {ib - ia, jb - ja, three ? kb - ka : 0};
-  for (int d = 0; d < (three ? 3 : 2); ++d) {
+  for (int d = 0; d < dims; ++d) {
     const int n = d == 0 ? nx : (d == 1 ? ny : nz);
     if (P->max_extent[d] < 0 || P->max_extent[d] > n - 3) return fail(LSB_EINVAL, "max_extent outside [0, n - 3]");
     if (P->max_extent[d] > ext[d]) ext[d] = P->max_extent[d];
@@ -758,48 +831,92 @@ int lsb_ref_create(const lsb_ref_params* P, lsb_ref** out) {
   a.pw = nx;
   a.ph = ny;
   a.po = 0;
-  set_patch(a, P->patch);
-  r->L = P->levels == 0 ? 2 : P->levels;
-  if (r->L < 2 || r->L > LSB_REF_MAX_LEVELS) {
+  set_patch(a, b1);
+  r->L = nbox + 1;
+  r->par[1] = 0;
+  auto refuse = [&](const char* msg) {
     delete r;
-    return fail(LSB_EINVAL, "levels must be 2 .. LSB_REF_MAX_LEVELS");
-  }
+    return fail(LSB_EINVAL, msg);
+  };
+  int nkids[kMaxGrids] = {};
+  nkids[0] = 1;
   for (int l = 2; l < r->L; ++l) {
-    const RefArgs& pp = pair_of(r, l - 1);
-    const int* bx = P->inner[l - 2];
-    const int m[3] = {pp.mx, pp.my, pp.mz};
-    for (int d = 0; d < (three ? 3 : 2); ++d)
-      if (bx[2 * d] < 1 || bx[2 * d + 1] > m[d] - 1 || bx[2 * d + 1] - bx[2 * d] < 2) {
-        delete r;
-        return fail(LSB_EINVAL, "an inner patch must lie inside its parent level with one node to spare and span >= 2 cells per axis");
-      }
+    const int p = parents[l - 1];
+    if (p < 0 || p >= l) return refuse("a box's parent must be the coarse grid or an earlier box");
+    if (++nkids[p] > kMaxKids) return refuse("at most 8 boxes refine one grid");
+    r->par[l] = p;
+    if (p != l - 1) r->chain = false;
+    const int* bx = boxes + 6 * (l - 1);
+    int m[3];
+    if (p == 0) {
+      m[0] = nx - 1;
+      m[1] = ny - 1;
+      m[2] = nz - 1;
+    } else {
+      const RefArgs& pp = pair_of(r, p);
+      m[0] = pp.mx;
+      m[1] = pp.my;
+      m[2] = pp.mz;
+    }
+    for (int d = 0; d < dims; ++d)
+      if (bx[2 * d] < 1 || bx[2 * d + 1] > m[d] - 1 || bx[2 * d + 1] - bx[2 * d] < 2)
+        return refuse("an inner patch must lie inside its parent with one node to spare and span >= 2 cells per axis");
+    // siblings at least one parent node apart on some axis
+    for (int o = 1; o < l; ++o) {
+      if (r->par[o] != p) continue;
+      const RefArgs& w = pair_of(r, o);
+      const int wl[3] = {w.ia, w.ja, w.ka}, wh[3] = {w.ib, w.jb, w.kb};
+      bool apart = false;
+      for (int d = 0; d < dims; ++d) apart = apart || bx[2 * d + 1] + 2 <= wl[d] || wh[d] + 2 <= bx[2 * d];
+      if (!apart) return refuse("boxes refining one grid must be at least one node apart");
+    }
     RefArgs& c = r->deep[l];
     c = RefArgs{};
     c.D = a.D;
-    set_parent(c, pp);
+    if (p == 0) set_parent_root(c, a);
+    else set_parent(c, pair_of(r, p));
     set_patch(c, bx);
-    // capacity: the larger of the box and max_inner_extent, at most what the
-    // parent's capacity admits
-    const int* pe = l == 2 ? r->ext : r->dext[l - 1];
+    // capacity: the larger of the box and max_inner_extent (chains), at most
+    // what the parent's capacity admits
     int* e = r->dext[l];
-    for (int d = 0; d < 3; ++d) {
-      e[d] = d < (three ? 3 : 2) ? bx[2 * d + 1] - bx[2 * d] : 0;
-      const int mx = P->max_inner_extent[l - 2][d];
-      if (d < (three ? 3 : 2) && (mx < 0 || mx > 2 * pe[d] - 2)) {
-        delete r;
-        return fail(LSB_EINVAL, "max_inner_extent outside [0, twice the parent's largest extent - 2]");
+    for (int d = 0; d < 3; ++d) e[d] = d < dims ? bx[2 * d + 1] - bx[2 * d] : 0;
+    if (inner_caps) {
+      const int* pe = p == 1 ? r->ext : r->dext[p];
+      for (int d = 0; d < dims; ++d) {
+        const int mx = P->max_inner_extent[l - 2][d];
+        if (mx < 0 || mx > 2 * pe[d] - 2)
+          return refuse("max_inner_extent outside [0, twice the parent's largest extent - 2]");
+        if (mx > e[d]) e[d] = mx;
       }
-      if (d < (three ? 3 : 2) && mx > e[d]) e[d] = mx;
     }
     r->dcap[l] = (long)row_pitch(2 * e[0]) * (2L * e[1] + 3) * (three ? 2L * e[2] + 3 : 1);
     r->dbcap[l] = 2L * (e[1] + 1) * (e[2] + 1) + 2L * (e[0] + 1) * (e[2] + 1) + (three ? 2L * (e[0] + 1) * (e[1] + 1) : 0L);
-    if (r->dcap[l] > (1L << 31)) {
-      delete r;
-      return fail(LSB_EINVAL, "grid too large");
-    }
+    if (r->dcap[l] > (1L << 31)) return refuse("grid too large");
   }
   *out = r;
   return LSB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lsb_ref_create_tree(const lsb_ref_params* P, int nbox, const int* parents, const int* boxes, lsb_ref** out) {
+  if (!P || !out || !parents || !boxes) return fail(LSB_EINVAL, "null pointer");
+  return create_tree(P, nbox, parents, boxes, false, out);
+}
+
+int lsb_ref_create(const lsb_ref_params* P, lsb_ref** out) {
+  if (!P || !out) return fail(LSB_EINVAL, "null pointer");
+  *out = nullptr;
+  const int L = P->levels == 0 ? 2 : P->levels;
+  if (L < 2 || L > LSB_REF_MAX_LEVELS) return fail(LSB_EINVAL, "levels must be 2 .. LSB_REF_MAX_LEVELS");
+  int parents[LSB_REF_MAX_LEVELS], boxes[6 * LSB_REF_MAX_LEVELS];
+  for (int b = 1; b < L; ++b) {
+    parents[b - 1] = b - 1;
+    for (int d = 0; d < 6; ++d) boxes[6 * (b - 1) + d] = b == 1 ? P->patch[d] : P->inner[b - 2][d];
+  }
+  return create_tree(P, L - 1, parents, boxes, true, out);
 }
 
 void lsb_ref_destroy(lsb_ref* r) { delete r; }
@@ -922,6 +1039,7 @@ int lsb_ref_sensor_levels(lsb_ref* r, const double* phi, double d_ref, const int
                           void* stream) {
   if (!r || !phi || !margins || !boxes) return fail(LSB_EINVAL, "null pointer");
   if (!r->ws) return fail(LSB_ESTATE, "lsb_ref_sensor_levels before lsb_ref_bind");
+  if (!r->chain) return fail(LSB_EINVAL, "the sensor's boxes need a chain of nested levels, not a tree");
   for (int l = 1; l < r->L; ++l)
     if (margins[l - 1] < 0) return fail(LSB_EINVAL, "negative margin");
   int box[6];
@@ -973,6 +1091,7 @@ int lsb_ref_remesh(lsb_ref* r, const int* patch, void* stream) {
 int lsb_ref_remesh_levels(lsb_ref* r, const int* boxes, void* stream) {
   if (!r || !boxes) return fail(LSB_EINVAL, "null pointer");
   if (!r->inited) return fail(LSB_ESTATE, "lsb_ref_remesh_levels before lsb_ref_init");
+  if (!r->chain) return fail(LSB_EINVAL, "re-meshing takes a chain of nested levels, not a tree");
   return remesh_levels(r, boxes, reinterpret_cast<hipStream_t>(stream));
 }
 

@@ -53,7 +53,7 @@ EXPORTS = [
     "lsb_last_error",
     "lsb_ref_create", "lsb_ref_destroy", "lsb_ref_workspace_bytes", "lsb_ref_bind", "lsb_ref_init", "lsb_ref_step",
     "lsb_ref_get_populations", "lsb_ref_sensor", "lsb_ref_remesh", "lsb_ref_init_levels", "lsb_ref_get_level",
-    "lsb_ref_sensor_levels", "lsb_ref_remesh_levels",
+    "lsb_ref_sensor_levels", "lsb_ref_remesh_levels", "lsb_ref_create_tree",
 ]
 
 
@@ -127,6 +127,7 @@ def load() -> C.CDLL:
     lib.lsb_ref_get_level.argtypes = [vp, C.c_int, vp, vp]
     lib.lsb_ref_sensor_levels.argtypes = [vp, vp, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_int), vp]
     lib.lsb_ref_remesh_levels.argtypes = [vp, C.POINTER(C.c_int), vp]
+    lib.lsb_ref_create_tree.argtypes = [R, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(vp)]
     _lib = lib
     return lib
 
@@ -341,12 +342,14 @@ class Refine:
     or D3Q27; the coarse grid nx x ny (x nz), periodic, and a fine patch over
     the coarse nodes patch = (ia, ib, ja, jb[, ka, kb]); or nested patches, a
     list of such boxes (level 1 first, each in its parent level's node
-    coordinates; two to four levels in all).  Device memory is a torch
+    coordinates; two to four levels in all); or, with parents (one index per
+    box: 0 for the coarse grid, else an earlier box counted from 1), a tree
+    of up to 15 boxes.  Device memory is a torch
     uint8 tensor (the caller-owned workspace); calls run on torch's current
     stream."""
 
     def __init__(self, nx: int, ny: int, patch, tau_c: float, device="cuda:0", lattice: int = D2Q9, nz: int = 1,
-                 max_extent=(0, 0, 0), max_inner_extent=()):
+                 max_extent=(0, 0, 0), max_inner_extent=(), parents=None):
         import torch
         self.torch = torch
         self.lib = load()
@@ -360,17 +363,25 @@ class Refine:
             p = tuple(int(v) for v in bx) + (0, 0)
             self.boxes.append(p[:6] if self.D == 3 else p[:4] + (0, 0))
         self.levels = len(self.boxes) + 1
+        self.parents = list(range(len(self.boxes))) if parents is None else [int(v) for v in parents]
         inner = ((C.c_int * 6) * (REF_MAX_LEVELS - 2))()
-        for l, bx in enumerate(self.boxes[1:REF_MAX_LEVELS - 1]):
+        for l, bx in enumerate(self.boxes[1:REF_MAX_LEVELS - 1] if parents is None else []):
             inner[l] = (C.c_int * 6)(*bx)
         mie = ((C.c_int * 3) * (REF_MAX_LEVELS - 2))()
         for l, e in enumerate(list(max_inner_extent)[:REF_MAX_LEVELS - 2]):
             mie[l] = (C.c_int * 3)(*[int(v) for v in e])
         self._cp = RefParams(self.lattice, self.nx, self.ny, self.nz, (C.c_int * 6)(*self.boxes[0]), float(tau_c),
-                             (C.c_int * 3)(*[int(v) for v in max_extent]), self.levels, inner, mie)
+                             (C.c_int * 3)(*[int(v) for v in max_extent]), self.levels if parents is None else 0,
+                             inner, mie)
         self._sync_level1()
         h = C.c_void_p()
-        _check(self.lib.lsb_ref_create(C.byref(self._cp), C.byref(h)))
+        if parents is None:
+            _check(self.lib.lsb_ref_create(C.byref(self._cp), C.byref(h)))
+        else:
+            flat = [v for bx in self.boxes for v in bx]
+            _check(self.lib.lsb_ref_create_tree(C.byref(self._cp), len(self.boxes),
+                                                (C.c_int * len(self.parents))(*self.parents),
+                                                (C.c_int * len(flat))(*flat), C.byref(h)))
         self.h = h
         nb = C.c_size_t()
         _check(self.lib.lsb_ref_workspace_bytes(self.h, C.byref(nb)))

@@ -222,3 +222,59 @@ def test_refine_nested_workspace_layout():
     assert lib.lsb_ref_get_level(h, 3, C.c_void_p(1), None) == lsb.LSB_ESTATE
     lib.lsb_ref_destroy(h)
     lib.lsb_ref_destroy(h2)
+
+
+def _tree_create(parents, boxes, **kw):
+    p = dict(lattice=lsb.D2Q9, nx=48, ny=40, nz=1, tau_c=0.7)
+    p.update(kw)
+    cp = lsb.RefParams(p["lattice"], p["nx"], p["ny"], p["nz"], (C.c_int * 6)(), p["tau_c"], (C.c_int * 3)(), 0,
+                       ((C.c_int * 6) * (lsb.REF_MAX_LEVELS - 2))(), ((C.c_int * 3) * (lsb.REF_MAX_LEVELS - 2))())
+    flat = [v for bx in boxes for v in bx]
+    h = C.c_void_p()
+    rc = lsb.load().lsb_ref_create_tree(C.byref(cp), len(boxes), (C.c_int * len(parents))(*parents),
+                                        (C.c_int * len(flat))(*flat), C.byref(h))
+    return rc, h
+
+
+_SIB = [(4, 16, 6, 30, 0, 0), (18, 40, 4, 20, 0, 0), (3, 20, 5, 40, 0, 0)]
+
+
+@pytest.mark.parametrize("parents,boxes", [
+    ([1, 0, 1], _SIB),                                              # box 1 must refine the coarse grid
+    ([0, 2, 1], _SIB),                                              # a parent must come first
+    ([0, 0, 1], [_SIB[0], (17, 40, 4, 20, 0, 0), _SIB[2]]),         # siblings without a node between
+    ([0, 0, 1], [_SIB[0], _SIB[1], (3, 24, 5, 40, 0, 0)]),          # box 3 beyond box 1's last node - 1
+    ([0] * 9, [(1 + 5 * b, 4 + 5 * b, 2, 8, 0, 0) for b in range(9)]),   # nine boxes on one grid
+    ([0] * 16, [(1, 3, 2, 8, 0, 0)] * 16),                          # more than 15 boxes
+])
+def test_refine_tree_rejects_invalid_trees(parents, boxes):
+    rc, h = _tree_create(parents, boxes)
+    assert rc == lsb.LSB_EINVAL
+    assert lsb.load().lsb_last_error().decode()
+
+
+def test_refine_tree_layout_and_chain_only_calls():
+    """A tree's workspace is the two-level layout of box 1 plus, per further
+    box, 2 x (its nodes with the ghost shell + its box surface); the sensor
+    and re-meshing refuse trees before any device access."""
+    def up(v):
+        return (v + 255) // 256 * 256
+    lib = lsb.load()
+    rc, h = _tree_create([0, 0, 1], _SIB)
+    assert rc == lsb.LSB_OK, lib.lsb_last_error()
+    rc2, h2 = _ref_create(nx=48, ny=40, patch=_SIB[0])
+    assert rc2 == lsb.LSB_OK
+    nb, nb2 = C.c_size_t(), C.c_size_t()
+    assert lib.lsb_ref_workspace_bytes(h, C.byref(nb)) == lsb.LSB_OK
+    assert lib.lsb_ref_workspace_bytes(h2, C.byref(nb2)) == lsb.LSB_OK
+    extra = 0
+    for ia, ib, ja, jb, _, _ in _SIB[1:]:
+        mx, my = 2 * (ib - ia), 2 * (jb - ja)
+        extra += 2 * (up(8 * 9 * _pitch(mx) * (my + 3)) + up(8 * 9 * (2 * (jb - ja + 1) + 2 * (ib - ia + 1))))
+    assert nb.value == nb2.value + extra
+    assert lib.lsb_ref_bind(h, C.c_void_p(1 << 20), nb.value) == lsb.LSB_OK   # stores the pointer only
+    out = (C.c_int * 18)()
+    assert lib.lsb_ref_sensor_levels(h, C.c_void_p(1), 0.5, (C.c_int * 3)(1, 1, 1), out, None) == lsb.LSB_EINVAL
+    assert "tree" in lib.lsb_last_error().decode()
+    lib.lsb_ref_destroy(h)
+    lib.lsb_ref_destroy(h2)

@@ -351,3 +351,40 @@ def test_nested_remesh_rejects_boxes_beyond_the_workspace(require_gpu):
         g.remesh_levels([(10, 20, 10, 20), (4, 20, 4, 12)])   # beyond level 1's last node - 1
     g.remesh_levels([(6, 20, 10, 24), (2, 12, 16, 26)])      # fits
     assert g.boxes[1][:4] == (2, 12, 16, 26)
+
+
+# --- trees: several boxes refining one grid ---
+
+@pytest.mark.parametrize("lattice,n3,boxes,parents,tau_c,steps", [
+    (0, (48, 40, 1), [(4, 16, 6, 30), (18, 40, 4, 20), (3, 20, 5, 40)], [0, 0, 1], 0.7, 8),
+    (0, (48, 48, 1), [(5, 19, 8, 40), (28, 42, 8, 40), (4, 20, 6, 50), (8, 24, 6, 50)], [0, 0, 1, 2], 0.7, 6),
+    (0, (400, 30, 1), [(10, 150, 4, 25), (160, 390, 3, 20), (20, 270, 3, 30), (30, 440, 4, 28)], [0, 0, 1, 2], 0.62, 3),
+    (2, (24, 20, 18), [(3, 9, 4, 14, 3, 12), (11, 20, 3, 10, 4, 13), (2, 10, 3, 12, 2, 14)], [0, 0, 2], 0.7, 3),
+    (1, (16, 16, 16), [(2, 6, 3, 12, 2, 13), (8, 13, 2, 9, 4, 10)], [0, 0], 0.8, 4),
+])
+def test_tree_matches_oracle(require_gpu, lattice, n3, boxes, parents, tau_c, steps):
+    from paper_2601_05936_amd.lsb import Refine
+    nx, ny, nz = n3
+    o = RefineOracle(nx, ny, boxes, tau_c, lattice=lattice, nz=nz, parents=parents)
+    args = _fields_nested(o, seed=sum(n3) + 3 * len(boxes))
+    g = Refine(nx, ny, boxes, tau_c, lattice=lattice, nz=nz, parents=parents)
+    o.init(*args)
+    g.init(*args)
+    o.step(steps)
+    g.step(steps)
+    errs = [float(np.max(np.abs(b - a))) for a, b in zip(o.populations(), g.populations())]
+    print(f"tree D={2 if lattice == 0 else 3} {n3} parents {parents}: " + " ".join(f"{e:.2e}" for e in errs), flush=True)
+    assert max(errs) <= TOL
+
+
+def test_tree_refuses_the_sensor_and_remeshing(require_gpu):
+    from paper_2601_05936_amd.lsb import LsbError, Refine
+    g = Refine(48, 40, [(4, 16, 6, 30), (18, 40, 4, 20)], 0.7, parents=[0, 0])
+    args = []
+    for lv in range(3):
+        args += [np.ones(g.n_level(lv)), np.zeros(2 * g.n_level(lv))]
+    g.init(*args)
+    with pytest.raises(LsbError):
+        g.sensor_levels(np.zeros(48 * 40), 1.0, (1, 1))
+    with pytest.raises(LsbError):
+        g.remesh_levels([(4, 16, 6, 30), (18, 40, 4, 20)])
