@@ -289,6 +289,49 @@ def run_refine_nested(steps: int, warmup: int):
     return res
 
 
+def run_refine_tree(steps: int, warmup: int):
+    """A tree of boxes (D2Q9, BGK, FP64): 2048^2 coarse nodes, periodic, with
+    nine disjoint 200^2-cell boxes on a 3 x 3 lattice (401^2 nodes each, as
+    around a cluster of nine bubbles); synthetic smooth shear and density
+    fields.  Node updates per second and the whole step's rate against 144
+    algorithmic bytes per node update (covered nodes are not updated)."""
+    import numpy as np
+    import torch
+
+    from paper_2601_05936_amd.lsb import Refine
+    n, tau_c = 2048, 0.6
+    boxes = [(224 + 600 * a, 424 + 600 * a, 224 + 600 * b, 424 + 600 * b) for b in range(3) for a in range(3)]
+    g = Refine(n, n, boxes, tau_c, parents=[0] * 9)
+
+    def fields(x, y):
+        s = np.sin(2 * np.pi * y / n)
+        return 1.0 + 0.005 * np.cos(2 * np.pi * x / n), np.stack([0.02 * s, 0.01 * np.sin(2 * np.pi * x / n)], 1)
+    J, I = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    args = list(fields(I.reshape(-1).astype(float), J.reshape(-1).astype(float)))
+    for bx in boxes:
+        sx, sy, _ = g.shape(1)
+        jj, ii = np.meshgrid(np.arange(sy), np.arange(sx), indexing="ij")
+        args += list(fields(bx[0] + 0.5 * ii.reshape(-1), bx[2] + 0.5 * jj.reshape(-1)))
+    g.init(*args)
+    del args
+    g.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    updates = (n * n - 9 * 199 * 199) + 2 * 9 * g.n_level(1)
+    gbs = updates * 144 / (ms * 1e-3) / 1e9
+    res = dict(workload="D2Q9 refinement tree, 2048^2 coarse, nine 200^2-cell boxes (401^2 nodes each)",
+               steps=steps, warmup=warmup, ms_per_step=ms, node_updates_per_step=updates,
+               mlups=updates / (ms * 1e-3) / 1e6, gbs=gbs, frac=gbs / HBM_PEAK_GBS, bytes_per_update=144,
+               launches_per_step=1 + 9 * 3, dtype="f64")
+    log(f"[refine_tree] {res}")
+    return res
+
+
 def cpu_baseline(seconds: float):
     """The CPU oracle (as it stands) on a bounded sample of the workload:
     the same problem at 128^3 (interface amplitude scaled to 2)."""
@@ -334,7 +377,7 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=2000, help="reverse-mode run length (0: skip)")
     ap.add_argument("--refine-steps", type=int, default=100,
                     help="refinement run length in coarse steps: two-level 2D and 3D legs, three-level "
-                         "2D leg (0: skip)")
+                         "2D leg, nine-box 2D tree (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (counter calibration)")
@@ -410,6 +453,7 @@ def main():
         out["refine"] = run_refine(args.refine_steps, 10)
         out["refine3d"] = run_refine3d(args.refine_steps, 10)
         out["refine_nested"] = run_refine_nested(args.refine_steps, 10)
+        out["refine_tree"] = run_refine_tree(args.refine_steps, 10)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

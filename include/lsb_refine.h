@@ -92,9 +92,8 @@ int lsb_ref_create(const lsb_ref_params* params, lsb_ref** out);
 /* A tree of boxes instead of a chain: box b (1 .. nbox) refines grid
  * parents[b - 1] (0: the coarse grid, else an earlier box; parents[0] = 0)
  * over boxes[6 (b - 1) ...] = (ia, ib, ja, jb, ka, kb) of that grid's nodes,
- * with one node to spare at every side, at least two cells per axis, at
- * most 8 boxes per grid, and the boxes refining one grid at least one of
- * its nodes apart (each pair of grids is coupled as above; a grid's
+ * with one node to spare at every side, at least two cells per axis, and
+ * the boxes refining one grid at least one of its nodes apart (each pair of grids is coupled as above; a grid's
  * sub-step is followed by each of its boxes' two sub-steps in turn).
  * params gives the lattice, the coarse grid, tau_c and box 1's max_extent;
  * its patch, levels, inner and max_inner_extent are not read.  Grid b's

@@ -67,7 +67,7 @@ struct RefArgs {
 // The boxes refining one grid, as its kernels see them: each box's extent in
 // the grid's node coordinates, its perimeter-set faces and where the sets of
 // the time level being written go (g).
-constexpr int kMaxKids = 8;
+constexpr int kMaxKids = LSB_REF_MAX_BOXES;
 
 struct KidBox {
   int D, ia, ib, ja, jb, ka, kb, bw, bh;
@@ -843,7 +843,7 @@ int create_tree(const lsb_ref_params* P, int nbox, const int* parents, const int
   for (int l = 2; l < r->L; ++l) {
     const int p = parents[l - 1];
     if (p < 0 || p >= l) return refuse("a box's parent must be the coarse grid or an earlier box");
-    if (++nkids[p] > kMaxKids) return refuse("at most 8 boxes refine one grid");
+    if (++nkids[p] > kMaxKids) return refuse("too many boxes refine one grid");
     r->par[l] = p;
     if (p != l - 1) r->chain = false;
     const int* bx = boxes + 6 * (l - 1);

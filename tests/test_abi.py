@@ -244,7 +244,6 @@ _SIB = [(4, 16, 6, 30, 0, 0), (18, 40, 4, 20, 0, 0), (3, 20, 5, 40, 0, 0)]
     ([0, 2, 1], _SIB),                                              # a parent must come first
     ([0, 0, 1], [_SIB[0], (17, 40, 4, 20, 0, 0), _SIB[2]]),         # siblings without a node between
     ([0, 0, 1], [_SIB[0], _SIB[1], (3, 24, 5, 40, 0, 0)]),          # box 3 beyond box 1's last node - 1
-    ([0] * 9, [(1 + 5 * b, 4 + 5 * b, 2, 8, 0, 0) for b in range(9)]),   # nine boxes on one grid
     ([0] * 16, [(1, 3, 2, 8, 0, 0)] * 16),                          # more than 15 boxes
 ])
 def test_refine_tree_rejects_invalid_trees(parents, boxes):
