@@ -126,9 +126,17 @@ int lsb_ref_init(lsb_ref* ref, const double* rho_c, const double* u_c, const dou
  * LSB_ESTATE before lsb_ref_bind. */
 int lsb_ref_init_levels(lsb_ref* ref, const double* const* rho, const double* const* u, void* stream);
 
-/* nsteps coarse steps (2^l nsteps steps of level l).  LSB_ESTATE before
- * lsb_ref_init. */
+/* nsteps coarse steps (2^l nsteps steps of level l).  A coarse step is
+ * launched as a HIP graph (two graphs, one per parity of the double
+ * buffers, captured on the first call after lsb_ref_bind, lsb_ref_init or
+ * a re-mesh; the graphs are runtime objects, not device memory of the
+ * library).  LSB_ESTATE before lsb_ref_init; LSB_EDEVICE if a capture or a
+ * launch fails. */
 int lsb_ref_step(lsb_ref* ref, int nsteps, void* stream);
+
+/* Graph launches on (on != 0, the default) or plain kernel launches; both
+ * give the same results bit for bit. */
+int lsb_ref_set_graphs(lsb_ref* ref, int on);
 
 /* Level-set refinement sensor (Sec. 3, adaptive mesh refinement): from a
  * level set on the coarse nodes (device array [nx*ny*nz], negative in the

@@ -528,6 +528,18 @@ struct lsb_ref {
   int cur = 0;  // fc[cur] and g[cur] are the current coarse state and box 1's G(t); ff[0] box 1's state
   int dcur[kMaxGrids] = {};  // dg[b][dcur[b]] is box b's G(t); dff[b][0] its state
   bool inited = false;
+  // One coarse step as a HIP graph per parity of the buffer state (the
+  // state repeats every two steps), captured on first use on a private
+  // stream and launched on the caller's; rebuilt after a re-mesh.
+  bool use_graphs = true;
+  bool graphs_ready = false;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int after_cur[2] = {0, 0};
+  int after_dcur[2][kMaxGrids] = {};
+  ~lsb_ref() {
+    for (int k = 0; k < 2; ++k)
+      if (gexec[k]) (void)hipGraphExecDestroy(gexec[k]);
+  }
 };
 
 namespace {
@@ -625,11 +637,45 @@ void launch_init(lsb_ref* r, const double* const* rho, const double* const* u, h
   }
 }
 
+// While a step is captured into a graph, the boxes refining one grid run on
+// branches of their own (they share no data within a parent step: each
+// reads its own perimeter sets and writes its own arrays and the parent
+// nodes it covers): box c on stream s[c], forked from and joined to the
+// parent's stream with events.
+struct Cap {
+  hipStream_t s[kMaxGrids];
+  hipEvent_t fork[kMaxGrids], done[kMaxGrids];
+};
+
+template <int LAT>
+void advance(lsb_ref* r, int l, double* parent_out, hipStream_t st, Cap* cap);
+
+// the boxes refining grid gi, their two sub-steps each, after the grid's
+// step or sub-step (new populations parent_out)
+template <int LAT>
+void run_kids(lsb_ref* r, int gi, double* parent_out, hipStream_t st, Cap* cap) {
+  int n = 0;
+  for (int c = 1; c < r->L; ++c) n += r->par[c] == gi;
+  if (!cap || n < 2) {
+    for (int c = 1; c < r->L; ++c)
+      if (r->par[c] == gi) advance<LAT>(r, c, parent_out, st, cap);
+    return;
+  }
+  (void)hipEventRecord(cap->fork[gi], st);
+  for (int c = 1; c < r->L; ++c) {
+    if (r->par[c] != gi) continue;
+    (void)hipStreamWaitEvent(cap->s[c], cap->fork[gi], 0);
+    advance<LAT>(r, c, parent_out, cap->s[c], cap);
+    (void)hipEventRecord(cap->done[c], cap->s[c]);
+    (void)hipStreamWaitEvent(st, cap->done[c], 0);
+  }
+}
+
 // the two sub-steps of box l within one step of its parent (whose new
 // populations, parent_out, receive the restriction), each followed by the
 // two sub-steps of each of its own boxes
 template <int LAT>
-void advance(lsb_ref* r, int l, double* parent_out, hipStream_t st) {
+void advance(lsb_ref* r, int l, double* parent_out, hipStream_t st, Cap* cap) {
   RefArgs A = pair_of(r, l);
   double** ffl = l == 1 ? r->ff : r->dff[l];
   A.g0 = gbuf(r, l, 0);
@@ -648,11 +694,9 @@ void advance(lsb_ref* r, int l, double* parent_out, hipStream_t st) {
     const Kids K = kids_of(r, l, 1);
     if (K.n > 0) {
       k_ref_fine<LAT, true><<<gf, 256, 0, st>>>(A, K, sf, s);
+      run_kids<LAT>(r, l, ffl[s ^ 1], st, cap);
       for (int c = 2; c < r->L; ++c)
-        if (r->par[c] == l) {
-          advance<LAT>(r, c, ffl[s ^ 1], st);
-          r->dcur[c] ^= 1;
-        }
+        if (r->par[c] == l) r->dcur[c] ^= 1;
     } else {
       k_ref_fine<LAT, false><<<gf, 256, 0, st>>>(A, K, sf, s);
     }
@@ -660,7 +704,7 @@ void advance(lsb_ref* r, int l, double* parent_out, hipStream_t st) {
 }
 
 template <int LAT>
-void launch_steps(lsb_ref* r, int nsteps, hipStream_t st) {
+void launch_steps(lsb_ref* r, int nsteps, hipStream_t st, Cap* cap = nullptr) {
   const RefArgs& b = r->base;
   const int sc = (b.nx + 255) / 256;
   const unsigned gc = (unsigned)((long)sc * b.ny * b.nz);
@@ -669,13 +713,97 @@ void launch_steps(lsb_ref* r, int nsteps, hipStream_t st) {
     a.fc_in = r->fc[r->cur];
     a.fc_out = r->fc[r->cur ^ 1];
     k_ref_coarse<LAT><<<gc, 256, 0, st>>>(a, kids_of(r, 0, 1), sc);
-    for (int c = 1; c < r->L; ++c)
-      if (r->par[c] == 0) {
-        advance<LAT>(r, c, r->fc[r->cur ^ 1], st);
-        if (c != 1) r->dcur[c] ^= 1;
-      }
+    run_kids<LAT>(r, 0, r->fc[r->cur ^ 1], st, cap);
+    for (int c = 2; c < r->L; ++c)
+      if (r->par[c] == 0) r->dcur[c] ^= 1;
     r->cur ^= 1;  // box 1's perimeter sets turn with the coarse state
   }
+}
+
+void drop_graphs(lsb_ref* r) {
+  for (int k = 0; k < 2; ++k)
+    if (r->gexec[k]) {
+      (void)hipGraphExecDestroy(r->gexec[k]);
+      r->gexec[k] = nullptr;
+    }
+  r->graphs_ready = false;
+}
+
+// captures one coarse step from each parity of the state (capturing runs
+// nothing on the device but moves the host's buffer bookkeeping as the step
+// does; two captures bring it back to where it started, which is checked)
+template <int LAT>
+int build_graphs(lsb_ref* r) {
+  const int cur0 = r->cur;
+  int dcur0[kMaxGrids];
+  for (int b = 0; b < kMaxGrids; ++b) dcur0[b] = r->dcur[b];
+  auto restore = [&]() {
+    r->cur = cur0;
+    for (int b = 0; b < kMaxGrids; ++b) r->dcur[b] = dcur0[b];
+  };
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(LSB_EDEVICE, "stream creation failed");
+  Cap cap{};
+  int made = 0;
+  bool ok = true;
+  for (; made < r->L && ok; ++made)
+    ok = hipStreamCreateWithFlags(&cap.s[made], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&cap.fork[made], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&cap.done[made], hipEventDisableTiming) == hipSuccess;
+  int rc = ok ? LSB_OK : fail(LSB_EDEVICE, "stream or event creation failed");
+  for (int k = 0; k < 2 && rc == LSB_OK; ++k) {
+    const int p = r->cur;
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      rc = fail(LSB_EDEVICE, "graph capture failed to start");
+      break;
+    }
+    launch_steps<LAT>(r, 1, cs, &cap);
+    if (hipStreamEndCapture(cs, &graph) != hipSuccess || !graph) {
+      rc = fail(LSB_EDEVICE, "graph capture failed");
+      break;
+    }
+    if (hipGraphInstantiate(&r->gexec[p], graph, nullptr, nullptr, 0) != hipSuccess) {
+      r->gexec[p] = nullptr;
+      rc = fail(LSB_EDEVICE, "graph instantiation failed");
+    }
+    (void)hipGraphDestroy(graph);
+    r->after_cur[p] = r->cur;
+    for (int b = 0; b < kMaxGrids; ++b) r->after_dcur[p][b] = r->dcur[b];
+  }
+  (void)hipStreamDestroy(cs);
+  for (int k = 0; k < made; ++k) {
+    if (cap.s[k]) (void)hipStreamDestroy(cap.s[k]);
+    if (cap.fork[k]) (void)hipEventDestroy(cap.fork[k]);
+    if (cap.done[k]) (void)hipEventDestroy(cap.done[k]);
+  }
+  bool back = r->cur == cur0;
+  for (int b = 0; b < kMaxGrids; ++b) back = back && r->dcur[b] == dcur0[b];
+  restore();
+  if (rc != LSB_OK || !back || !r->gexec[0] || !r->gexec[1]) {
+    drop_graphs(r);
+    return rc != LSB_OK ? rc : fail(LSB_EDEVICE, "graph capture did not return to the starting state");
+  }
+  r->graphs_ready = true;
+  return LSB_OK;
+}
+
+// nsteps coarse steps: graph launches, or plain launches when graphs are off
+template <int LAT>
+int run_steps(lsb_ref* r, int nsteps, hipStream_t st) {
+  if (!r->use_graphs) {
+    launch_steps<LAT>(r, nsteps, st);
+    return check_launch();
+  }
+  if (!r->graphs_ready)
+    if (int e = build_graphs<LAT>(r)) return e;
+  for (int s = 0; s < nsteps; ++s) {
+    const int p = r->cur;
+    if (hipGraphLaunch(r->gexec[p], st) != hipSuccess) return fail(LSB_EDEVICE, "graph launch failed");
+    r->cur = r->after_cur[p];
+    for (int b = 0; b < kMaxGrids; ++b) r->dcur[b] = r->after_dcur[p][b];
+  }
+  return LSB_OK;
 }
 
 // the sensor's reduction: the bounding box of the tagged coarse nodes (lo x,
@@ -721,6 +849,7 @@ void level1_box(const lsb_ref* r, const int* box, bool tagged, int margin, int* 
 // re-meshing of every refined level onto boxes (6 ints per level), level 1
 // first, each inside its re-meshed parent
 int remesh_levels(lsb_ref* r, const int* boxes, hipStream_t st) {
+  drop_graphs(r);
   const RefArgs& b = r->base;
   const int D = b.D;
   int last[3] = {b.nx - 1, b.ny - 1, b.nz - 1};  // the parent's last node index per axis
@@ -952,6 +1081,7 @@ int lsb_ref_bind(lsb_ref* r, void* ws, size_t bytes) {
     }
   r->ws = static_cast<char*>(ws);
   r->ws_bytes = bytes;
+  drop_graphs(r);
   r->inited = false;
   return LSB_OK;
 }
@@ -963,7 +1093,8 @@ int lsb_ref_init_levels(lsb_ref* r, const double* const* rho, const double* cons
   if (!r->ws) return fail(LSB_ESTATE, "lsb_ref_init before lsb_ref_bind");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   r->cur = 0;
-  for (int l = 0; l < LSB_REF_MAX_LEVELS; ++l) r->dcur[l] = 0;
+  for (int l = 0; l < kMaxGrids; ++l) r->dcur[l] = 0;
+  drop_graphs(r);
   switch (r->P.lattice) {
     case LSB_D2Q9: launch_init<LSB_D2Q9>(r, rho, u, st); break;
     case LSB_D3Q19: launch_init<LSB_D3Q19>(r, rho, u, st); break;
@@ -989,11 +1120,17 @@ int lsb_ref_step(lsb_ref* r, int nsteps, void* stream) {
   if (nsteps < 0) return fail(LSB_EINVAL, "negative step count");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   switch (r->P.lattice) {
-    case LSB_D2Q9: launch_steps<LSB_D2Q9>(r, nsteps, st); break;
-    case LSB_D3Q19: launch_steps<LSB_D3Q19>(r, nsteps, st); break;
-    default: launch_steps<LSB_D3Q27>(r, nsteps, st); break;
+    case LSB_D2Q9: return run_steps<LSB_D2Q9>(r, nsteps, st);
+    case LSB_D3Q19: return run_steps<LSB_D3Q19>(r, nsteps, st);
+    default: return run_steps<LSB_D3Q27>(r, nsteps, st);
   }
-  return check_launch();
+}
+
+int lsb_ref_set_graphs(lsb_ref* r, int on) {
+  if (!r) return fail(LSB_EINVAL, "null pointer");
+  r->use_graphs = on != 0;
+  if (!r->use_graphs) drop_graphs(r);
+  return LSB_OK;
 }
 
 int lsb_ref_get_populations(lsb_ref* r, double* coarse, double* fine, void* stream) {

@@ -53,7 +53,7 @@ EXPORTS = [
     "lsb_last_error",
     "lsb_ref_create", "lsb_ref_destroy", "lsb_ref_workspace_bytes", "lsb_ref_bind", "lsb_ref_init", "lsb_ref_step",
     "lsb_ref_get_populations", "lsb_ref_sensor", "lsb_ref_remesh", "lsb_ref_init_levels", "lsb_ref_get_level",
-    "lsb_ref_sensor_levels", "lsb_ref_remesh_levels", "lsb_ref_create_tree",
+    "lsb_ref_sensor_levels", "lsb_ref_remesh_levels", "lsb_ref_create_tree", "lsb_ref_set_graphs",
 ]
 
 
@@ -128,6 +128,7 @@ def load() -> C.CDLL:
     lib.lsb_ref_sensor_levels.argtypes = [vp, vp, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_int), vp]
     lib.lsb_ref_remesh_levels.argtypes = [vp, C.POINTER(C.c_int), vp]
     lib.lsb_ref_create_tree.argtypes = [R, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(vp)]
+    lib.lsb_ref_set_graphs.argtypes = [vp, C.c_int]
     _lib = lib
     return lib
 
@@ -457,6 +458,11 @@ class Refine:
         _check(self.lib.lsb_ref_remesh(self.h, (C.c_int * 6)(*p), self.stream()))
         self.boxes[0] = p if self.D == 3 else p[:4] + (0, 0)
         self._sync_level1()
+        return self
+
+    def set_graphs(self, on: bool):
+        """Coarse steps as HIP graph launches (default) or plain launches."""
+        _check(self.lib.lsb_ref_set_graphs(self.h, 1 if on else 0))
         return self
 
     def sensor_levels(self, phi, d_ref: float, margins):

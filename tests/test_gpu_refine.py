@@ -388,3 +388,37 @@ def test_tree_refuses_the_sensor_and_remeshing(require_gpu):
         g.sensor_levels(np.zeros(48 * 40), 1.0, (1, 1))
     with pytest.raises(LsbError):
         g.remesh_levels([(4, 16, 6, 30), (18, 40, 4, 20)])
+
+
+@pytest.mark.parametrize("kind", ["tree", "chain"])
+def test_graph_steps_match_plain_launches(require_gpu, kind):
+    """Coarse steps replayed from the two captured graphs against plain
+    launches, bit for bit, one step per call with a read-back (and so a
+    synchronisation) between replays, across a re-mesh that rebuilds the
+    graphs (chain) and against the oracle at the end."""
+    from paper_2601_05936_amd.lsb import Refine
+    if kind == "tree":
+        n3, boxes, parents, kw = (48, 40, 1), [(4, 16, 6, 30), (18, 40, 4, 20), (3, 20, 5, 40)], [0, 0, 1], {}
+    else:
+        n3, boxes, parents = (40, 36, 1), [(8, 30, 7, 28), (3, 40, 4, 38)], None
+        kw = dict(max_extent=(30, 30, 0), max_inner_extent=[(50, 50, 0)])
+    nx, ny, nz = n3
+    o = RefineOracle(nx, ny, boxes, 0.7, parents=parents)
+    args = _fields_nested(o, seed=21)
+    o.init(*args)
+    gr = Refine(nx, ny, boxes, 0.7, parents=parents, **kw).init(*args)
+    pl = Refine(nx, ny, boxes, 0.7, parents=parents, **kw).set_graphs(False).init(*args)
+    for s in range(5):
+        o.step(1)
+        gr.step(1)
+        pl.step(1)
+        for a, b in zip(gr.populations(), pl.populations()):
+            assert np.array_equal(a, b), s
+        if kind == "chain" and s == 2:
+            new = [(6, 31, 5, 29), (4, 44, 6, 40)]
+            o.remesh_levels(new)
+            gr.remesh_levels(new)
+            pl.remesh_levels(new)
+    errs = [float(np.max(np.abs(b - a))) for a, b in zip(o.populations(), gr.populations())]
+    print(f"graph steps {kind}: " + " ".join(f"{e:.2e}" for e in errs), flush=True)
+    assert max(errs) <= TOL
