@@ -378,6 +378,8 @@ def main():
     ap.add_argument("--refine-steps", type=int, default=100,
                     help="refinement run length in coarse steps: two-level 2D and 3D legs, three-level "
                          "2D leg, nine-box 2D tree (0: skip)")
+    ap.add_argument("--refine-legs", default="2d,3d,nested,tree",
+                    help="refinement legs to run: 2d, 3d (two levels), nested (three levels), tree (nine boxes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (counter calibration)")
@@ -450,10 +452,11 @@ def main():
     if args.adjoint_steps > 0:
         out["adjoint"] = run_adjoint(args.adjoint_steps, 100)
     if args.refine_steps > 0:
-        out["refine"] = run_refine(args.refine_steps, 10)
-        out["refine3d"] = run_refine3d(args.refine_steps, 10)
-        out["refine_nested"] = run_refine_nested(args.refine_steps, 10)
-        out["refine_tree"] = run_refine_tree(args.refine_steps, 10)
+        legs = {"2d": ("refine", run_refine), "3d": ("refine3d", run_refine3d),
+                "nested": ("refine_nested", run_refine_nested), "tree": ("refine_tree", run_refine_tree)}
+        for leg in [v.strip() for v in args.refine_legs.split(",") if v.strip()]:
+            key, fn = legs[leg]
+            out[key] = fn(args.refine_steps, 10)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
