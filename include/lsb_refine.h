@@ -97,8 +97,10 @@ int lsb_ref_create(const lsb_ref_params* params, lsb_ref** out);
  * sub-step is followed by each of its boxes' two sub-steps in turn).
  * params gives the lattice, the coarse grid, tau_c and box 1's max_extent;
  * its patch, levels, inner and max_inner_extent are not read.  Grid b's
- * arrays in lsb_ref_init_levels and lsb_ref_get_level are box b's; the
- * sensor and re-meshing take chains only (LSB_EINVAL for a tree).
+ * arrays in lsb_ref_init_levels and lsb_ref_get_level are box b's;
+ * lsb_ref_remesh_levels re-meshes a tree (box 1 up to max_extent, every
+ * other box up to its initial extents), the sensor takes chains only
+ * (LSB_EINVAL for a tree).
  * LSB_EINVAL for anything outside these ranges. */
 int lsb_ref_create_tree(const lsb_ref_params* params, int nbox, const int* parents, const int* boxes,
                         lsb_ref** out);
@@ -174,10 +176,11 @@ int lsb_ref_remesh(lsb_ref* ref, const int* patch, void* stream);
 int lsb_ref_sensor_levels(lsb_ref* ref, const double* phi, double d_ref, const int* margins, int* boxes,
                           void* stream);
 
-/* Re-meshing of every refined level (boxes: host, 6 ints per refined level,
- * each in its new parent's node coordinates), level 1 first, each inside
- * its re-meshed parent, with the rules of lsb_ref_remesh per pair of
- * levels: a new node at a position the old level covered keeps its
+/* Re-meshing of every box of a chain or a tree (boxes: host, 6 ints per
+ * box, each in its new parent's node coordinates; the tree's shape stays),
+ * box 1 first, each inside its re-meshed parent and, in a tree, at least
+ * one parent node from its siblings, with the rules of lsb_ref_remesh per
+ * pair of grids: a new node at a position the old level covered keeps its
  * populations, the others are interpolated from the parent's post-collision
  * populations with the non-equilibrium part scaled by
  * (tau_l - 1) / (2 (tau_{l-1} - 1)), and each level's perimeter sets come

@@ -290,12 +290,13 @@ struct Ref {
 
   // origin of each level's nodes in that level's spacing, counted from
   // coarse node 0: o[0] = 0, o[l] = 2 (o[l-1] + box corner of level l)
-  void origins(long o[LMAX][3]) const {
+  void origins(long o[BMAX][3]) const {
     for (int d = 0; d < 3; ++d) o[0][d] = 0;
     for (int l = 1; l < L; ++l) {
-      o[l][0] = 2 * (o[l - 1][0] + lv[l].ia);
-      o[l][1] = 2 * (o[l - 1][1] + lv[l].ja);
-      o[l][2] = 2 * (o[l - 1][2] + lv[l].ka);
+      const int p = lv[l].parent;
+      o[l][0] = 2 * (o[p][0] + lv[l].ia);
+      o[l][1] = 2 * (o[p][1] + lv[l].ja);
+      o[l][2] = 2 * (o[p][2] + lv[l].ka);
     }
   }
 
@@ -352,9 +353,9 @@ struct Ref {
 
   // Re-meshing onto new boxes at the end of a coarse step (state at time t:
   // post-collision populations of every level, covered nodes holding
-  // restricted values), level 1 first, each level inside its re-meshed
-  // parent; boxes holds 6 ints per refined level in the parent's node
-  // coordinates.  A new node of level l at a position the old level l
+  // restricted values), box 1 first, each box inside its re-meshed parent
+  // (a chain of levels or a tree, whose shape stays); boxes holds 6 ints per
+  // box in the parent's node coordinates.  A new node of level l at a position the old level l
   // covered keeps the old populations; the others take the parent's
   // populations interpolated like the perimeter's (the mean of the 2, 4 or 8
   // parent nodes around an off-grid node), their non-equilibrium part scaled
@@ -367,18 +368,18 @@ struct Ref {
   // tau = 1).  Covered nodes are restricted again at the end of the next
   // step; nodes a level no longer covers keep their restricted values.
   void remesh_levels(const int* boxes) {
-    long oo[LMAX][3], on[LMAX][3];
+    long oo[BMAX][3], on[BMAX][3];
     origins(oo);
     const std::vector<Level> old(lv, lv + L);
     for (int d = 0; d < 3; ++d) on[0][d] = 0;
     for (int l = 1; l < L; ++l) {
-      const Level& p = lv[l - 1];
       Level& v = lv[l];
+      const Level& p = lv[v.parent];
       const Level& o = old[l];
       v.set_box(boxes + 6 * (l - 1));
-      on[l][0] = 2 * (on[l - 1][0] + v.ia);
-      on[l][1] = 2 * (on[l - 1][1] + v.ja);
-      on[l][2] = 2 * (on[l - 1][2] + v.ka);
+      on[l][0] = 2 * (on[v.parent][0] + v.ia);
+      on[l][1] = 2 * (on[v.parent][1] + v.ja);
+      on[l][2] = 2 * (on[v.parent][2] + v.ka);
       v.f.assign(Q * v.n(), 0.0);
       v.g0.assign(Q * v.nb(), 0.0);
       v.g1.assign(Q * v.nb(), 0.0);
@@ -557,14 +558,24 @@ int orc_ref_sensor_levels(void* h, const double* phi, double d_ref, const int* m
 // parent's node coordinates); -1 if a box does not fit its parent
 int orc_ref_remesh_levels(void* h, const int* boxes) {
   ref::Ref* r = static_cast<ref::Ref*>(h);
-  const ref::Level& g = r->lv[0];
-  if (g.f.empty() || !r->chain()) return -1;  // not initialised, or not a chain of levels
-  int last[3] = {g.mx, g.my, g.mz};  // the parent's last node index per axis
+  if (r->lv[0].f.empty()) return -1;  // not initialised
+  int last[ref::BMAX][3];  // each grid's last node index per axis, after the re-mesh
+  last[0][0] = r->lv[0].mx;
+  last[0][1] = r->lv[0].my;
+  last[0][2] = r->lv[0].mz;
   for (int l = 1; l < r->L; ++l) {
     const int* b = boxes + 6 * (l - 1);
+    const int p = r->lv[l].parent;
     for (int d = 0; d < r->D; ++d)
-      if (b[2 * d] < 1 || b[2 * d + 1] > last[d] - 1 || b[2 * d + 1] - b[2 * d] < 2) return -1;
-    for (int d = 0; d < r->D; ++d) last[d] = 2 * (b[2 * d + 1] - b[2 * d]);
+      if (b[2 * d] < 1 || b[2 * d + 1] > last[p][d] - 1 || b[2 * d + 1] - b[2 * d] < 2) return -1;
+    for (int o = 1; o < l; ++o) {  // siblings stay one parent node apart
+      if (r->lv[o].parent != p) continue;
+      const int* w = boxes + 6 * (o - 1);
+      bool apart = false;
+      for (int d = 0; d < r->D; ++d) apart = apart || b[2 * d + 1] + 2 <= w[2 * d] || w[2 * d + 1] + 2 <= b[2 * d];
+      if (!apart) return -1;
+    }
+    for (int d = 0; d < 3; ++d) last[l][d] = d < r->D ? 2 * (b[2 * d + 1] - b[2 * d]) : 0;
   }
   r->remesh_levels(boxes);
   return 0;

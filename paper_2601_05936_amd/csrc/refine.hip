@@ -846,46 +846,66 @@ void level1_box(const lsb_ref* r, const int* box, bool tagged, int margin, int* 
   for (int d = 0; d < 6; ++d) patch[d] = out[d];
 }
 
-// re-meshing of every refined level onto boxes (6 ints per level), level 1
-// first, each inside its re-meshed parent
+// re-meshing of every box onto boxes (6 ints per box, in the parent's node
+// coordinates), box 1 first, each inside its re-meshed parent (the shape of
+// a chain or tree stays)
 int remesh_levels(lsb_ref* r, const int* boxes, hipStream_t st) {
   drop_graphs(r);
   const RefArgs& b = r->base;
   const int D = b.D;
-  int last[3] = {b.nx - 1, b.ny - 1, b.nz - 1};  // the parent's last node index per axis
+  int last[kMaxGrids][3] = {};  // each grid's last node index per axis, after the re-mesh
+  last[0][0] = b.nx - 1;
+  last[0][1] = b.ny - 1;
+  last[0][2] = b.nz - 1;
   for (int l = 1; l < r->L; ++l) {
     const int* bx = boxes + 6 * (l - 1);
     const int* cap = l == 1 ? r->ext : r->dext[l];
+    const int p = r->par[l];
     for (int d = 0; d < D; ++d) {
       const int lo = bx[2 * d], hi = bx[2 * d + 1];
-      if (lo < 1 || hi > last[d] - 1 || hi - lo < 2)
+      if (lo < 1 || hi > last[p][d] - 1 || hi - lo < 2)
         return fail(LSB_EINVAL, "a box must lie inside its parent with one node to spare and span >= 2 cells per axis");
       if (hi - lo > cap[d]) return fail(LSB_EINVAL, "box larger than the workspace's maximum extents");
     }
-    for (int d = 0; d < D; ++d) last[d] = 2 * (bx[2 * d + 1] - bx[2 * d]);
+    for (int o = 1; o < l; ++o) {
+      if (r->par[o] != p) continue;
+      const int* w = boxes + 6 * (o - 1);
+      bool apart = false;
+      for (int d = 0; d < D; ++d) apart = apart || bx[2 * d + 1] + 2 <= w[2 * d] || w[2 * d + 1] + 2 <= bx[2 * d];
+      if (!apart) return fail(LSB_EINVAL, "boxes refining one grid must be at least one node apart");
+    }
+    for (int d = 0; d < D; ++d) last[l][d] = 2 * (bx[2 * d + 1] - bx[2 * d]);
   }
-  RefArgs O[LSB_REF_MAX_LEVELS], A[LSB_REF_MAX_LEVELS];
+  RefArgs O[kMaxGrids], A[kMaxGrids];
   for (int l = 1; l < r->L; ++l) O[l] = pair_of(r, l);
-  int shift[3] = {0, 0, 0};
+  int shift[kMaxGrids][3] = {};  // how far box l's parent's first node moved, in box l's spacing
   for (int l = 1; l < r->L; ++l) {
+    const int p = r->par[l];
     A[l] = O[l];
-    if (l >= 2) set_parent(A[l], A[l - 1]);
+    if (p == 0) set_parent_root(A[l], r->base);
+    else set_parent(A[l], A[p]);
     set_patch(A[l], boxes + 6 * (l - 1));
-    A[l].fc_in = l == 1 ? r->fc[r->cur] : (l == 2 ? r->ff[0] : r->dff[l - 1][0]);
+    A[l].fc_in = p == 0 ? r->fc[r->cur] : (p == 1 ? r->ff[0] : r->dff[p][0]);
+    if (p != 0) {
+      shift[l][0] = 2 * (shift[p][0] + 2 * (A[p].ia - O[p].ia));
+      shift[l][1] = 2 * (shift[p][1] + 2 * (A[p].ja - O[p].ja));
+      shift[l][2] = 2 * (shift[p][2] + 2 * (A[p].ka - O[p].ka));
+    }
     double** buf = l == 1 ? r->ff : r->dff[l];
-    double* g = l == 1 ? r->g[r->cur] : r->dg[l][r->dcur[l]];
+    double* g = gbuf(r, l, 0);
+    const int* sh = shift[l];
     const long n1 = (long)(A[l].mx + 1) * (A[l].my + 1) * (A[l].mz + 1), nbox = (long)A[l].bw * A[l].bh * A[l].bd;
     switch (r->P.lattice) {
       case LSB_D2Q9:
-        k_ref_remesh_fine<LSB_D2Q9><<<grid_for(n1), 256, 0, st>>>(A[l], O[l], shift[0], shift[1], shift[2], buf[0], buf[1]);
+        k_ref_remesh_fine<LSB_D2Q9><<<grid_for(n1), 256, 0, st>>>(A[l], O[l], sh[0], sh[1], sh[2], buf[0], buf[1]);
         k_ref_remesh_g<LSB_D2Q9><<<grid_for(nbox), 256, 0, st>>>(A[l], g);
         break;
       case LSB_D3Q19:
-        k_ref_remesh_fine<LSB_D3Q19><<<grid_for(n1), 256, 0, st>>>(A[l], O[l], shift[0], shift[1], shift[2], buf[0], buf[1]);
+        k_ref_remesh_fine<LSB_D3Q19><<<grid_for(n1), 256, 0, st>>>(A[l], O[l], sh[0], sh[1], sh[2], buf[0], buf[1]);
         k_ref_remesh_g<LSB_D3Q19><<<grid_for(nbox), 256, 0, st>>>(A[l], g);
         break;
       default:
-        k_ref_remesh_fine<LSB_D3Q27><<<grid_for(n1), 256, 0, st>>>(A[l], O[l], shift[0], shift[1], shift[2], buf[0], buf[1]);
+        k_ref_remesh_fine<LSB_D3Q27><<<grid_for(n1), 256, 0, st>>>(A[l], O[l], sh[0], sh[1], sh[2], buf[0], buf[1]);
         k_ref_remesh_g<LSB_D3Q27><<<grid_for(nbox), 256, 0, st>>>(A[l], g);
         break;
     }
@@ -893,10 +913,6 @@ int remesh_levels(lsb_ref* r, const int* boxes, hipStream_t st) {
     double* t = buf[0];
     buf[0] = buf[1];
     buf[1] = t;
-    // how far this level's first node moved, in the child's spacing
-    shift[0] = 2 * (shift[0] + 2 * (A[l].ia - O[l].ia));
-    shift[1] = 2 * (shift[1] + 2 * (A[l].ja - O[l].ja));
-    shift[2] = 2 * (shift[2] + 2 * (A[l].ka - O[l].ka));
   }
   for (int l = 1; l < r->L; ++l) {
     A[l].fc_in = nullptr;
@@ -904,8 +920,9 @@ int remesh_levels(lsb_ref* r, const int* boxes, hipStream_t st) {
     else r->deep[l] = A[l];
   }
   for (int d = 0; d < 6; ++d) r->P.patch[d] = D == 3 || d < 4 ? boxes[d] : 0;
-  for (int l = 2; l < r->L; ++l)
-    for (int d = 0; d < 6; ++d) r->P.inner[l - 2][d] = D == 3 || d < 4 ? boxes[6 * (l - 1) + d] : 0;
+  if (r->chain)  // the parameter block describes chains only
+    for (int l = 2; l < r->L && l < LSB_REF_MAX_LEVELS; ++l)
+      for (int d = 0; d < 6; ++d) r->P.inner[l - 2][d] = D == 3 || d < 4 ? boxes[6 * (l - 1) + d] : 0;
   return LSB_OK;
 }
 
@@ -1228,7 +1245,6 @@ int lsb_ref_remesh(lsb_ref* r, const int* patch, void* stream) {
 int lsb_ref_remesh_levels(lsb_ref* r, const int* boxes, void* stream) {
   if (!r || !boxes) return fail(LSB_EINVAL, "null pointer");
   if (!r->inited) return fail(LSB_ESTATE, "lsb_ref_remesh_levels before lsb_ref_init");
-  if (!r->chain) return fail(LSB_EINVAL, "re-meshing takes a chain of nested levels, not a tree");
   return remesh_levels(r, boxes, reinterpret_cast<hipStream_t>(stream));
 }
 

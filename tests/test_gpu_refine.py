@@ -377,7 +377,7 @@ def test_tree_matches_oracle(require_gpu, lattice, n3, boxes, parents, tau_c, st
     assert max(errs) <= TOL
 
 
-def test_tree_refuses_the_sensor_and_remeshing(require_gpu):
+def test_tree_refuses_the_sensor(require_gpu):
     from paper_2601_05936_amd.lsb import LsbError, Refine
     g = Refine(48, 40, [(4, 16, 6, 30), (18, 40, 4, 20)], 0.7, parents=[0, 0])
     args = []
@@ -386,8 +386,38 @@ def test_tree_refuses_the_sensor_and_remeshing(require_gpu):
     g.init(*args)
     with pytest.raises(LsbError):
         g.sensor_levels(np.zeros(48 * 40), 1.0, (1, 1))
-    with pytest.raises(LsbError):
-        g.remesh_levels([(4, 16, 6, 30), (18, 40, 4, 20)])
+    with pytest.raises(LsbError):   # siblings one node too close
+        g.remesh_levels([(4, 17, 6, 30), (18, 40, 4, 20)])
+
+
+@pytest.mark.parametrize("lattice,n3,boxes,parents,new", [
+    (0, (40, 40, 1), [(4, 16, 6, 30), (20, 34, 4, 20), (3, 20, 5, 40)], [0, 0, 1],
+     [(5, 16, 4, 28), (20, 34, 6, 22), (2, 19, 8, 42)]),
+    (2, (24, 20, 18), [(3, 9, 4, 14, 3, 12), (11, 20, 3, 10, 4, 13), (2, 10, 3, 12, 2, 14)], [0, 0, 2],
+     [(2, 9, 5, 14, 3, 11), (11, 19, 4, 11, 4, 12), (3, 11, 3, 11, 2, 14)]),
+])
+def test_tree_remesh_matches_oracle(require_gpu, lattice, n3, boxes, parents, new):
+    """Steps, a re-mesh of every box of a tree (boxes no larger than before:
+    a tree's workspace holds its initial boxes), steps; every grid against
+    the oracle after each phase."""
+    from paper_2601_05936_amd.lsb import Refine
+    nx, ny, nz = n3
+    o = RefineOracle(nx, ny, boxes, 0.7, lattice=lattice, nz=nz, parents=parents)
+    args = _fields_nested(o, seed=33)
+    g = Refine(nx, ny, boxes, 0.7, lattice=lattice, nz=nz, parents=parents,
+               max_extent=(14, 14, 10) if lattice else (14, 26, 0))
+    o.init(*args)
+    g.init(*args)
+    for phase in ("before", "re-meshed", "after"):
+        if phase == "re-meshed":
+            o.remesh_levels(new)
+            g.remesh_levels(new)
+        else:
+            o.step(3)
+            g.step(3)
+        errs = [float(np.max(np.abs(b - a))) for a, b in zip(o.populations(), g.populations())]
+        print(f"tree remesh D={g.D} {phase}: " + " ".join(f"{e:.2e}" for e in errs), flush=True)
+        assert max(errs) <= TOL
 
 
 @pytest.mark.parametrize("kind", ["tree", "chain"])
