@@ -377,6 +377,25 @@ def test_tree_matches_oracle(require_gpu, lattice, n3, boxes, parents, tau_c, st
     assert max(errs) <= TOL
 
 
+def test_tree_benchmark_configuration(require_gpu):
+    """The benchmark's tree leg: 2048^2 coarse nodes, nine 200^2-cell boxes
+    on a 3 x 3 lattice (401^2 nodes each), stepped from the captured graphs
+    with the boxes on parallel branches; 2 coarse steps against the oracle."""
+    from paper_2601_05936_amd.lsb import Refine
+    n = 2048
+    boxes = [(224 + 600 * a, 424 + 600 * a, 224 + 600 * b, 424 + 600 * b) for b in range(3) for a in range(3)]
+    o = RefineOracle(n, n, boxes, 0.6, parents=[0] * 9)
+    args = _fields_nested(o, seed=41)
+    g = Refine(n, n, boxes, 0.6, parents=[0] * 9)
+    o.init(*args)
+    g.init(*args)
+    o.step(2)
+    g.step(2)
+    errs = [float(np.max(np.abs(b - a))) for a, b in zip(o.populations(), g.populations())]
+    print("tree 2048^2 nine boxes: " + " ".join(f"{e:.2e}" for e in errs), flush=True)
+    assert max(errs) <= TOL
+
+
 def test_tree_refuses_the_sensor(require_gpu):
     from paper_2601_05936_amd.lsb import LsbError, Refine
     g = Refine(48, 40, [(4, 16, 6, 30), (18, 40, 4, 20)], 0.7, parents=[0, 0])
