@@ -131,6 +131,9 @@ def _load():
     lib.orc_mref_get.argtypes = [C.c_void_p, C.c_int, dp]
     lib.orc_ref_sensor_levels.argtypes = [C.c_void_p, dp, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     lib.orc_ref_remesh_levels.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
+    lib.orc_ref_sensor_seeded.restype = C.c_int
+    lib.orc_ref_sensor_seeded.argtypes = [C.c_void_p, dp, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_int),
+                                          C.POINTER(C.c_int)]
     _lib = lib
     return lib
 
@@ -544,6 +547,19 @@ class RefineOracle:
         if not rc:
             return None
         return [tuple(out[6 * l:6 * l + 6]) for l in range(nl)]
+
+    def sensor_seeded(self, phi, d_ref: float, margin: int, seeds):
+        """Boxes for a tree of root boxes (6 ints each): tagged coarse nodes
+        go to their nearest seed (seeds: coarse nodes, (x, y[, z]) each),
+        each seed's bounding box grown by margin and clamped, boxes closer
+        than one node merged."""
+        sd = [tuple(int(v) for v in p) + (0,) * (3 - len(p)) for p in seeds]
+        flat = [v for p in sd for v in p]
+        out = (C.c_int * (6 * len(sd)))()
+        keep = _f64(phi, self.n_coarse)
+        nb = self._lib.orc_ref_sensor_seeded(self._h, _dp(keep), float(d_ref), int(margin), len(sd),
+                                             (C.c_int * len(flat))(*flat), out)
+        return [tuple(out[6 * k:6 * k + 6]) for k in range(nb)]
 
     def remesh_levels(self, boxes):
         """Re-mesh every refined level onto boxes (6 ints each, level 1

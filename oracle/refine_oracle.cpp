@@ -43,6 +43,7 @@
 //              its parent from its own pre-collision populations, which at
 //              nodes covered by its child come from the child's restriction
 //              (the levels hand their data down one jump at a time).
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -286,6 +287,78 @@ struct Ref {
     }
     if (D == 2) out[4] = out[5] = 0;
     return true;
+  }
+
+  // Sensor for a tree of root boxes: every tagged coarse node (phi >=
+  // -d_ref, as sensor_box) belongs to its nearest seed (seeds are coarse
+  // nodes; squared distances compared exactly, ties to the lower index);
+  // each seed with tagged nodes gives their bounding box grown by margin,
+  // clamped one node inside the grid and widened to two cells per axis;
+  // boxes closer than one node apart are merged into their union box until
+  // every pair is apart (a merged box takes the earlier one's place).
+  // out: 6 ints per box; returns the number of boxes.
+  int sensor_seeded(const double* phi, double d_ref, int margin, int ns, const int* seeds, int* out) const {
+    const Level& g = lv[0];
+    const int n[3] = {g.mx + 1, g.my + 1, g.mz + 1};
+    std::vector<int> lo(3 * ns), hi(3 * ns, -1);
+    for (int k = 0; k < ns; ++k)
+      for (int d = 0; d < 3; ++d) lo[3 * k + d] = n[d];
+    for (int K = 0; K < n[2]; ++K)
+      for (int J = 0; J < n[1]; ++J)
+        for (int I = 0; I < n[0]; ++I) {
+          if (!(phi[g.idx(I, J, K)] >= -d_ref)) continue;
+          int best = 0;
+          long bd = -1;
+          for (int k = 0; k < ns; ++k) {
+            const long dx = I - seeds[3 * k], dy = J - seeds[3 * k + 1], dz = K - seeds[3 * k + 2];
+            const long dd = dx * dx + dy * dy + dz * dz;
+            if (bd < 0 || dd < bd) {
+              bd = dd;
+              best = k;
+            }
+          }
+          const int pt[3] = {I, J, K};
+          for (int d = 0; d < 3; ++d) {
+            if (pt[d] < lo[3 * best + d]) lo[3 * best + d] = pt[d];
+            if (pt[d] > hi[3 * best + d]) hi[3 * best + d] = pt[d];
+          }
+        }
+    std::vector<std::vector<int>> boxes;
+    for (int k = 0; k < ns; ++k) {
+      if (hi[3 * k] < 0) continue;
+      std::vector<int> b(6, 0);
+      for (int d = 0; d < D; ++d) {
+        int a = lo[3 * k + d] - margin, c = hi[3 * k + d] + margin;
+        if (a < 1) a = 1;
+        if (c > n[d] - 2) c = n[d] - 2;
+        while (c - a < 2) {
+          if (c < n[d] - 2) ++c;
+          else --a;
+        }
+        b[2 * d] = a;
+        b[2 * d + 1] = c;
+      }
+      boxes.push_back(b);
+    }
+    for (bool merged = true; merged;) {
+      merged = false;
+      for (size_t a = 0; a < boxes.size() && !merged; ++a)
+        for (size_t b = a + 1; b < boxes.size() && !merged; ++b) {
+          bool apart = false;
+          for (int d = 0; d < D; ++d)
+            apart = apart || boxes[a][2 * d + 1] + 2 <= boxes[b][2 * d] || boxes[b][2 * d + 1] + 2 <= boxes[a][2 * d];
+          if (apart) continue;
+          for (int d = 0; d < D; ++d) {
+            boxes[a][2 * d] = std::min(boxes[a][2 * d], boxes[b][2 * d]);
+            boxes[a][2 * d + 1] = std::max(boxes[a][2 * d + 1], boxes[b][2 * d + 1]);
+          }
+          boxes.erase(boxes.begin() + (long)b);
+          merged = true;
+        }
+    }
+    for (size_t k = 0; k < boxes.size(); ++k)
+      for (int d = 0; d < 6; ++d) out[6 * k + d] = boxes[k][d];
+    return (int)boxes.size();
   }
 
   // origin of each level's nodes in that level's spacing, counted from
@@ -545,6 +618,12 @@ int orc_ref_remesh(void* h, const int* patch) {
     if (patch[2 * d] < 1 || patch[2 * d + 1] > n[d] - 2 || patch[2 * d + 1] - patch[2 * d] < 2) return -1;
   r->remesh_levels(patch);
   return 0;
+}
+
+// seeded sensor (boxes for a tree of root boxes): seeds are ns coarse nodes
+// (3 ints each); out receives 6 ints per box; returns the number of boxes
+int orc_ref_sensor_seeded(void* h, const double* phi, double d_ref, int margin, int ns, const int* seeds, int* out) {
+  return static_cast<ref::Ref*>(h)->sensor_seeded(phi, d_ref, margin, ns, seeds, out);
 }
 
 // nested sensor: margins[l - 1] (coarse nodes) for level l; out receives 6

@@ -572,3 +572,36 @@ def test_tree_remesh_keeps_a_uniform_state_and_the_mirror_symmetry():
     r.remesh_levels([(4, 30, 8, 56), (36, 60, 10, 50), (10, 40, 12, 80)])
     rate = _decay_rate(r, 64, 200, lambda I, J: np.sin(k * J))
     assert abs(rate / ((tau_c - 0.5) / 3.0 * k * k) - 1) < 0.025
+
+
+def test_seeded_sensor_gives_one_box_per_seed_and_merges_close_ones():
+    """Brute force on three disks of gas: each tagged node goes to its
+    nearest seed; each seed's box is its nodes' bounding box grown by the
+    margin; two disks whose grown boxes come within one node merge into
+    their union; a seed with no tagged node gives no box."""
+    n = 96
+    J, I = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    disks = [(20.3, 24.6, 6.5), (70.2, 30.1, 8.2), (45.5, 75.4, 5.1)]
+    phi = np.max([r - np.hypot(I - x, J - y) for x, y, r in disks], axis=0)
+    o = _tree(n, [(4, 16, 6, 30)], [0], 0.7, lambda x, y: (0 * x, 0 * y))
+    seeds = [(20, 25), (70, 30), (45, 75), (90, 5)]
+    d_ref, margin = 1.0, 2
+    got = o.sensor_seeded(phi.reshape(-1), d_ref, margin, seeds)
+    tagged = phi >= -d_ref
+    d2 = np.stack([(I - sx) ** 2 + (J - sy) ** 2 for sx, sy in seeds])
+    owner = np.argmin(d2, axis=0)
+    want = []
+    for k in range(len(seeds)):
+        m = tagged & (owner == k)
+        if not m.any():
+            continue
+        want.append((max(1, I[m].min() - margin), min(n - 2, I[m].max() + margin),
+                     max(1, J[m].min() - margin), min(n - 2, J[m].max() + margin), 0, 0))
+    assert got == want and len(got) == 3
+    # the disks' boxes fit a tree of root boxes
+    _tree(n, [b[:4] for b in got], [0] * len(got), 0.7, lambda x, y: (0 * x, 0 * y))
+    # two close disks: their grown boxes overlap, one union box
+    phi2 = np.max([r - np.hypot(I - x, J - y) for x, y, r in [(30.0, 40.0, 6.0), (46.0, 41.0, 6.0)]], axis=0)
+    got2 = o.sensor_seeded(phi2.reshape(-1), d_ref, margin, [(30, 40), (46, 41)])
+    m = phi2 >= -d_ref
+    assert got2 == [(I[m].min() - margin, I[m].max() + margin, J[m].min() - margin, J[m].max() + margin, 0, 0)]
