@@ -176,6 +176,22 @@ int lsb_ref_remesh(lsb_ref* ref, const int* patch, void* stream);
 int lsb_ref_sensor_levels(lsb_ref* ref, const double* phi, double d_ref, const int* margins, int* boxes,
                           void* stream);
 
+/* The sensor for a tree of boxes refining the coarse grid: every tagged
+ * coarse node (phi >= -d_ref, as lsb_ref_sensor) belongs to its nearest
+ * seed (seeds: host, nseeds coarse nodes of 3 ints, z ignored in 2D, for
+ * example the rounded centroids of bubbles; squared distances compared as
+ * integers, ties to the lower index); each seed with tagged nodes gives
+ * their bounding box grown by margin, clamped one node inside the grid and
+ * widened to two cells per axis; boxes closer than one node apart merge
+ * into their union (in the earlier box's place) until every pair is apart.
+ * boxes (host, 6 ints per box, room for nseeds) and *nboxes receive the
+ * result, the input of lsb_ref_create_tree (parents all 0) or of
+ * lsb_ref_remesh_levels on a tree of that many root boxes.  Synchronises
+ * the stream.  LSB_EINVAL for a NULL pointer, a negative margin or nseeds
+ * outside [1, LSB_REF_MAX_BOXES]; LSB_ESTATE before lsb_ref_bind. */
+int lsb_ref_sensor_seeded(lsb_ref* ref, const double* phi, double d_ref, int margin, int nseeds, const int* seeds,
+                          int* boxes, int* nboxes, void* stream);
+
 /* Re-meshing of every box of a chain or a tree (boxes: host, 6 ints per
  * box, each in its new parent's node coordinates; the tree's shape stays),
  * box 1 first, each inside its re-meshed parent and, in a tree, at least

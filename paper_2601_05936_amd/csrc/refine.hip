@@ -28,6 +28,7 @@
 // ordered so that each XCD streams a contiguous band of rows.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 
 #include "common.h"
@@ -374,14 +375,74 @@ __global__ __launch_bounds__(256) void k_ref_sensor(RefArgs a, const double* phi
   }
 }
 
-__global__ __launch_bounds__(256) void k_ref_sensor_final(int nparts, const int* part, int* box) {
+// Seeded sensor: every tagged node belongs to its nearest seed (a coarse
+// node; squared distances in 64-bit integers, ties to the lower index); per
+// block and seed the bounding box of its nodes, reduced as k_ref_sensor
+// does.  part: [block][seed][6].
+constexpr int kMaxSeeds = LSB_REF_MAX_BOXES;
+
+struct Seeds {
+  int n;
+  int p[kMaxSeeds][3];
+};
+
+__global__ __launch_bounds__(256) void k_ref_sensor_seeded(RefArgs a, const double* phi, double d_ref, Seeds sd,
+                                                           int* part) {
   __shared__ int sh[4];
-  for (int d = 0; d < 6; ++d) {
-    int v = 0x7fffffff;
-    for (int b = threadIdx.x; b < nparts; b += 256) v = min(v, part[b * 6 + d]);
-    v = block_min(v, sh);
-    if (threadIdx.x == 0) box[d] = d < 3 ? v : -v;
+  int v[kMaxSeeds][6];
+#pragma unroll
+  for (int k = 0; k < kMaxSeeds; ++k) {
+    v[k][0] = a.nx;
+    v[k][1] = a.ny;
+    v[k][2] = a.nz;
+    v[k][3] = v[k][4] = v[k][5] = 1;
   }
+  for (long n = (long)blockIdx.x * 256 + threadIdx.x; n < a.nc; n += (long)gridDim.x * 256) {
+    if (!(phi[n] >= -d_ref)) continue;
+    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long)a.nx * a.ny));
+    int best = 0;
+    long bd = -1;
+    for (int k = 0; k < sd.n; ++k) {
+      const long dx = x - sd.p[k][0], dy = y - sd.p[k][1], dz = z - sd.p[k][2];
+      const long dd = dx * dx + dy * dy + dz * dz;
+      if (bd < 0 || dd < bd) {
+        bd = dd;
+        best = k;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxSeeds; ++k)
+      if (best == k) {
+        v[k][0] = min(v[k][0], x);
+        v[k][1] = min(v[k][1], y);
+        v[k][2] = min(v[k][2], z);
+        v[k][3] = min(v[k][3], -x);
+        v[k][4] = min(v[k][4], -y);
+        v[k][5] = min(v[k][5], -z);
+      }
+  }
+  for (int k = 0; k < sd.n; ++k) {
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      int w = v[0][d];  // v[k][d] without a runtime index into the registers
+#pragma unroll
+      for (int j = 1; j < kMaxSeeds; ++j) w = j == k ? v[j][d] : w;
+      const int m = block_min(w, sh);
+      if (threadIdx.x == 0) part[((long)blockIdx.x * kMaxSeeds + k) * 6 + d] = m;
+    }
+  }
+}
+
+// reduces nslots boxes over nparts blocks: part [block][slot][6] -> box [slot][6]
+__global__ __launch_bounds__(256) void k_ref_sensor_final(int nparts, int nslots, int stride, const int* part, int* box) {
+  __shared__ int sh[4];
+  for (int k = 0; k < nslots; ++k)
+    for (int d = 0; d < 6; ++d) {
+      int v = 0x7fffffff;
+      for (int b = threadIdx.x; b < nparts; b += 256) v = min(v, part[((long)b * stride + k) * 6 + d]);
+      v = block_min(v, sh);
+      if (threadIdx.x == 0) box[k * 6 + d] = d < 3 ? v : -v;
+    }
 }
 
 // Re-meshing of one refined level (state at the end of a coarse step, the
@@ -515,7 +576,7 @@ struct lsb_ref {
   int Q = 9;
   int ext[3] = {0, 0, 0};  // largest patch extents (coarse cells per axis) the workspace holds
   long fcap = 0, bcap = 0;  // fine nodes with the shell, box-surface nodes, at those extents
-  int* sens = nullptr;      // sensor partial boxes (kSensorBlocks x 6) and the reduced box (6)
+  int* sens = nullptr;      // sensor partial boxes (kSensorBlocks x 15 x 6) and the reduced boxes (15 x 6)
   char* ws = nullptr;
   size_t ws_bytes = 0;
   double* fc[2] = {nullptr, nullptr};
@@ -547,7 +608,7 @@ size_t sizes(const lsb_ref* r, size_t* fcb, size_t* ffb, size_t* gb) {
   *fcb = align256(sizeof(double) * r->Q * (size_t)r->base.nc);
   *ffb = align256(sizeof(double) * r->Q * (size_t)r->fcap);
   *gb = align256(sizeof(double) * r->Q * (size_t)r->bcap);
-  size_t t = 2 * (*fcb + *ffb + *gb) + align256(sizeof(int) * 6 * (kSensorBlocks + 1));
+  size_t t = 2 * (*fcb + *ffb + *gb) + align256(sizeof(int) * 6 * kMaxSeeds * (kSensorBlocks + 1));
   for (int l = 2; l < r->L; ++l)
     t += 2 * (align256(sizeof(double) * r->Q * (size_t)r->dcap[l]) + align256(sizeof(double) * r->Q * (size_t)r->dbcap[l]));
   return t;
@@ -811,9 +872,9 @@ int run_steps(lsb_ref* r, int nsteps, hipStream_t st) {
 int sensor_bbox(lsb_ref* r, const double* phi, double d_ref, hipStream_t st, int* box, bool* tagged) {
   const RefArgs& a = r->base;
   k_ref_sensor<<<kSensorBlocks, 256, 0, st>>>(a, phi, d_ref, r->sens);
-  k_ref_sensor_final<<<1, 256, 0, st>>>(kSensorBlocks, r->sens, r->sens + 6 * kSensorBlocks);
+  k_ref_sensor_final<<<1, 256, 0, st>>>(kSensorBlocks, 1, 1, r->sens, r->sens + 6 * kMaxSeeds * kSensorBlocks);
   if (int e = check_launch()) return e;
-  if (hipMemcpyAsync(box, r->sens + 6 * kSensorBlocks, 6 * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+  if (hipMemcpyAsync(box, r->sens + 6 * kMaxSeeds * kSensorBlocks, 6 * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return fail(LSB_EDEVICE, "sensor read-back failed");
   *tagged = box[0] < a.nx;
@@ -1088,7 +1149,7 @@ int lsb_ref_bind(lsb_ref* r, void* ws, size_t bytes) {
     p += gb;
   }
   r->sens = reinterpret_cast<int*>(p);
-  p += align256(sizeof(int) * 6 * (kSensorBlocks + 1));
+  p += align256(sizeof(int) * 6 * kMaxSeeds * (kSensorBlocks + 1));
   for (int l = 2; l < r->L; ++l)
     for (int k = 0; k < 2; ++k) {
       r->dff[l][k] = reinterpret_cast<double*>(p);
@@ -1186,6 +1247,72 @@ int lsb_ref_sensor(lsb_ref* r, const double* phi, double d_ref, int margin, int*
   bool tagged = false;
   if (int e = sensor_bbox(r, phi, d_ref, reinterpret_cast<hipStream_t>(stream), box, &tagged)) return e;
   level1_box(r, box, tagged, margin, patch);
+  return LSB_OK;
+}
+
+int lsb_ref_sensor_seeded(lsb_ref* r, const double* phi, double d_ref, int margin, int nseeds, const int* seeds,
+                          int* boxes, int* nboxes, void* stream) {
+  if (!r || !phi || !seeds || !boxes || !nboxes) return fail(LSB_EINVAL, "null pointer");
+  if (!r->ws) return fail(LSB_ESTATE, "lsb_ref_sensor_seeded before lsb_ref_bind");
+  if (margin < 0) return fail(LSB_EINVAL, "negative margin");
+  if (nseeds < 1 || nseeds > kMaxSeeds) return fail(LSB_EINVAL, "1 .. LSB_REF_MAX_BOXES seeds");
+  const RefArgs& a = r->base;
+  const int n[3] = {a.nx, a.ny, a.nz};
+  Seeds sd{};
+  sd.n = nseeds;
+  for (int k = 0; k < nseeds; ++k)
+    for (int d = 0; d < 3; ++d) sd.p[k][d] = d < a.D ? seeds[3 * k + d] : 0;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int* out = r->sens + 6 * kMaxSeeds * kSensorBlocks;
+  k_ref_sensor_seeded<<<kSensorBlocks, 256, 0, st>>>(a, phi, d_ref, sd, r->sens);
+  k_ref_sensor_final<<<1, 256, 0, st>>>(kSensorBlocks, nseeds, kMaxSeeds, r->sens, out);
+  if (int e = check_launch()) return e;
+  int bb[kMaxSeeds][6];
+  if (hipMemcpyAsync(bb, out, sizeof(int) * 6 * nseeds, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(LSB_EDEVICE, "sensor read-back failed");
+  // one box per seed with tagged nodes, grown, clamped one node inside the
+  // grid, at least two cells per axis
+  int nb = 0;
+  int bx[kMaxSeeds][6];
+  for (int k = 0; k < nseeds; ++k) {
+    if (bb[k][0] >= a.nx) continue;  // no node of this seed
+    for (int d = 0; d < 6; ++d) bx[nb][d] = 0;
+    for (int d = 0; d < a.D; ++d) {
+      int lo = bb[k][d] - margin, hi = bb[k][3 + d] + margin;
+      if (lo < 1) lo = 1;
+      if (hi > n[d] - 2) hi = n[d] - 2;
+      while (hi - lo < 2) {
+        if (hi < n[d] - 2) ++hi;
+        else --lo;
+      }
+      bx[nb][2 * d] = lo;
+      bx[nb][2 * d + 1] = hi;
+    }
+    ++nb;
+  }
+  // boxes closer than one node apart merge into their union (in the earlier
+  // one's place) until every pair is apart
+  for (bool merged = true; merged;) {
+    merged = false;
+    for (int i = 0; i < nb && !merged; ++i)
+      for (int j = i + 1; j < nb && !merged; ++j) {
+        bool apart = false;
+        for (int d = 0; d < a.D; ++d) apart = apart || bx[i][2 * d + 1] + 2 <= bx[j][2 * d] || bx[j][2 * d + 1] + 2 <= bx[i][2 * d];
+        if (apart) continue;
+        for (int d = 0; d < a.D; ++d) {
+          bx[i][2 * d] = std::min(bx[i][2 * d], bx[j][2 * d]);
+          bx[i][2 * d + 1] = std::max(bx[i][2 * d + 1], bx[j][2 * d + 1]);
+        }
+        for (int m = j; m + 1 < nb; ++m)
+          for (int d = 0; d < 6; ++d) bx[m][d] = bx[m + 1][d];
+        --nb;
+        merged = true;
+      }
+  }
+  for (int k = 0; k < nb; ++k)
+    for (int d = 0; d < 6; ++d) boxes[6 * k + d] = bx[k][d];
+  *nboxes = nb;
   return LSB_OK;
 }
 

@@ -54,6 +54,7 @@ EXPORTS = [
     "lsb_ref_create", "lsb_ref_destroy", "lsb_ref_workspace_bytes", "lsb_ref_bind", "lsb_ref_init", "lsb_ref_step",
     "lsb_ref_get_populations", "lsb_ref_sensor", "lsb_ref_remesh", "lsb_ref_init_levels", "lsb_ref_get_level",
     "lsb_ref_sensor_levels", "lsb_ref_remesh_levels", "lsb_ref_create_tree", "lsb_ref_set_graphs",
+    "lsb_ref_sensor_seeded",
 ]
 
 
@@ -129,6 +130,8 @@ def load() -> C.CDLL:
     lib.lsb_ref_remesh_levels.argtypes = [vp, C.POINTER(C.c_int), vp]
     lib.lsb_ref_create_tree.argtypes = [R, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(vp)]
     lib.lsb_ref_set_graphs.argtypes = [vp, C.c_int]
+    lib.lsb_ref_sensor_seeded.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_int),
+                                          C.POINTER(C.c_int), C.POINTER(C.c_int), vp]
     _lib = lib
     return lib
 
@@ -477,6 +480,20 @@ class Refine:
         _check(self.lib.lsb_ref_sensor_levels(self.h, C.c_void_p(t_phi.data_ptr()), float(d_ref), mg, out,
                                               self.stream()))
         return [tuple(out[6 * l:6 * l + 6]) for l in range(nl)]
+
+    def sensor_seeded(self, phi, d_ref: float, margin: int, seeds):
+        """Boxes for a tree of root boxes (6 ints each) from the level-set
+        sensor on the coarse level set phi [n_coarse]: tagged nodes go to
+        their nearest seed (coarse nodes, (x, y[, z]) each), each seed's box
+        grown by margin and clamped, boxes closer than one node merged."""
+        sd = [tuple(int(v) for v in p) + (0,) * (3 - len(p)) for p in seeds]
+        flat = [v for p in sd for v in p]
+        t_phi = self._dev(phi, self.n_coarse)
+        out = (C.c_int * (6 * len(sd)))()
+        nb = C.c_int()
+        _check(self.lib.lsb_ref_sensor_seeded(self.h, C.c_void_p(t_phi.data_ptr()), float(d_ref), int(margin), len(sd),
+                                              (C.c_int * len(flat))(*flat), out, C.byref(nb), self.stream()))
+        return [tuple(out[6 * k:6 * k + 6]) for k in range(nb.value)]
 
     def remesh_levels(self, boxes):
         """Re-mesh every refined level onto boxes (6 ints each, level 1

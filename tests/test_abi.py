@@ -175,7 +175,7 @@ def test_refine_workspace_layout():
             bw, bh, bd = ib - ia + 1, jb - ja + 1, kb - ka + 1
             nf = _pitch(mx) * (my + 3) * (mz + 3)
             ns = 2 * bh * bd + 2 * bw * bd + 2 * bw * bh
-        assert nb.value == 2 * (up(8 * Q * nc) + up(8 * Q * nf) + up(8 * Q * ns)) + up(4 * 6 * 1025)
+        assert nb.value == 2 * (up(8 * Q * nc) + up(8 * Q * nf) + up(8 * Q * ns)) + up(4 * 6 * 15 * 1025)
         assert lib.lsb_ref_bind(h, C.c_void_p(1 << 20), nb.value - 1) == lsb.LSB_ENOMEM
         lib.lsb_ref_destroy(h)
 

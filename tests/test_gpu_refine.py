@@ -471,3 +471,52 @@ def test_graph_steps_match_plain_launches(require_gpu, kind):
     errs = [float(np.max(np.abs(b - a))) for a, b in zip(o.populations(), gr.populations())]
     print(f"graph steps {kind}: " + " ".join(f"{e:.2e}" for e in errs), flush=True)
     assert max(errs) <= TOL
+
+
+@pytest.mark.parametrize("lattice", [0, 2])
+def test_seeded_sensor_matches_oracle_and_drives_a_tree(require_gpu, lattice):
+    """The seeded sensor's boxes against the oracle's (gas disks/spheres,
+    one seed each, plus a seed with no tagged node), a tree built on them,
+    steps, a second sensor call with the gas moved and a re-mesh of the tree
+    onto its boxes, steps; every grid against the oracle."""
+    from paper_2601_05936_amd.lsb import Refine
+    if lattice == 0:
+        n3 = (96, 96, 1)
+        J, I = np.meshgrid(np.arange(96), np.arange(96), indexing="ij")
+        K = 0 * I
+        blobs = [(20.3, 24.6, 0, 6.5), (70.2, 30.1, 0, 8.2), (45.5, 75.4, 0, 5.1)]
+        seeds = [(20, 25, 0), (70, 30, 0), (45, 75, 0), (90, 5, 0)]
+    else:
+        n3 = (40, 36, 32)
+        K, J, I = np.meshgrid(np.arange(32), np.arange(36), np.arange(40), indexing="ij")
+        blobs = [(11.2, 12.7, 15.1, 4.2), (27.6, 22.3, 14.4, 4.8)]
+        seeds = [(11, 13, 15), (28, 22, 14)]
+    nx, ny, nz = n3
+
+    def gas(shift):
+        return np.max([r - np.sqrt((I - x - shift) ** 2 + (J - y) ** 2 + (K - z) ** 2) for x, y, z, r in blobs],
+                      axis=0).reshape(-1)
+    # a one-box tree holds the coarse grid for the sensor calls
+    probe_o = RefineOracle(nx, ny, [(2, 6, 2, 6, 2, 6)], 0.7, lattice=lattice, nz=nz)
+    probe_g = Refine(nx, ny, [(2, 6, 2, 6, 2, 6)], 0.7, lattice=lattice, nz=nz)
+    want = probe_o.sensor_seeded(gas(0.0), 1.5, 2, seeds)
+    got = probe_g.sensor_seeded(gas(0.0), 1.5, 2, seeds)
+    assert got == want and len(got) == len(blobs), (got, want)
+    parents = [0] * len(got)
+    o = RefineOracle(nx, ny, got, 0.7, lattice=lattice, nz=nz, parents=parents)
+    args = _fields_nested(o, seed=51)
+    g = Refine(nx, ny, got, 0.7, lattice=lattice, nz=nz, parents=parents)
+    o.init(*args)
+    g.init(*args)
+    o.step(3)
+    g.step(3)
+    moved_o = o.sensor_seeded(gas(-1.0), 1.0, 1, seeds)       # smaller boxes: within the tree's workspace
+    moved_g = g.sensor_seeded(gas(-1.0), 1.0, 1, seeds)
+    assert moved_g == moved_o and len(moved_g) == len(got)
+    o.remesh_levels(moved_o)
+    g.remesh_levels(moved_g)
+    o.step(3)
+    g.step(3)
+    errs = [float(np.max(np.abs(b - a))) for a, b in zip(o.populations(), g.populations())]
+    print(f"seeded sensor D={g.D}: boxes {got} -> {moved_g}; " + " ".join(f"{e:.2e}" for e in errs), flush=True)
+    assert max(errs) <= TOL
