@@ -1,5 +1,6 @@
 // CPU oracle: static grid refinement of the lattice Boltzmann solver (D2Q9,
-// D3Q19, D3Q27; BGK, FP64), ratio 2, two or more nested levels.  Test infrastructure only: the tests,
+// D3Q19, D3Q27; BGK, FP64), ratio 2, nested levels or a tree of boxes, with
+// the level-set sensor and re-meshing.  Test infrastructure only: the tests,
 // the smoke check and the benchmark's CPU-baseline leg call it; the product
 // path never does.
 //
@@ -34,12 +35,13 @@
 //              fine pre-collision non-equilibrium part scaled back by
 //              2 tau_c / tau_f, then collided with tau_c, which is
 //              f_eq + 2 (tau_c - 1) / tau_f (f - f_eq).
-//   nesting    a level may hold a finer patch of its own, a box of its own
+//   nesting    a grid may hold finer boxes of its own (one, or several at
+//              least one of its nodes apart: a tree), each a box of its
 //              nodes with one node to spare at each side; every pair of
-//              adjacent levels is coupled as above (tau doubles minus 1/2
-//              from level to level), and a level's sub-step is followed by
-//              its child's two sub-steps, the second of which restricts
-//              into the level's new populations.  A level restricts into
+//              adjacent grids is coupled as above (tau doubles minus 1/2
+//              from level to level), and a grid's sub-step is followed by
+//              each of its boxes' two sub-steps, the second of which
+//              restricts into the grid's new populations.  A level restricts into
 //              its parent from its own pre-collision populations, which at
 //              nodes covered by its child come from the child's restriction
 //              (the levels hand their data down one jump at a time).

@@ -12,7 +12,11 @@ still finishes in seconds; in 3D also D3Q19 and a minimal patch.  Nested
 levels: three and four levels in 2D and 3D, rows of the innermost level
 spanning three blocks with a ragged tail, minimal inner patches, and the
 benchmark's three-level configuration (2048^2 coarse, a 1024^2-cell level
-1, a 512^2-coarse-cell level 2 with 2049^2 nodes).  Bar:
+1, a 512^2-coarse-cell level 2 with 2049^2 nodes).  Trees of boxes (several
+boxes per grid, nested boxes under some), including the benchmark's
+nine-box tree; the level-set sensors (one box, one per level, one per
+seed) and re-meshing of chains and trees; graph-launched steps against
+plain launches, bit for bit.  Bar:
 max |f_gpu - f_oracle| <= 1e-13 (populations are O(0.1); the two sides
 differ only in the rounding of fused multiply-adds, measured at a few 1e-16
 per step).
