@@ -277,3 +277,19 @@ def test_refine_tree_layout_and_chain_only_calls():
     assert "tree" in lib.lsb_last_error().decode()
     lib.lsb_ref_destroy(h)
     lib.lsb_ref_destroy(h2)
+
+
+def test_refine_seeded_sensor_validates_before_device_access():
+    lib = lsb.load()
+    rc, h = _tree_create([0, 0, 1], _SIB)
+    assert rc == lsb.LSB_OK
+    out, nb = (C.c_int * 96)(), C.c_int()
+    seeds = (C.c_int * 48)()
+    assert lib.lsb_ref_sensor_seeded(h, C.c_void_p(1), 0.5, 1, 2, seeds, out, C.byref(nb), None) == lsb.LSB_ESTATE
+    nbytes = C.c_size_t()
+    assert lib.lsb_ref_workspace_bytes(h, C.byref(nbytes)) == lsb.LSB_OK
+    assert lib.lsb_ref_bind(h, C.c_void_p(1 << 20), nbytes.value) == lsb.LSB_OK
+    for ns, margin in [(0, 1), (16, 1), (2, -1)]:
+        assert lib.lsb_ref_sensor_seeded(h, C.c_void_p(1), 0.5, margin, ns, seeds, out, C.byref(nb), None) == lsb.LSB_EINVAL
+    assert lib.lsb_ref_sensor_seeded(h, None, 0.5, 1, 2, seeds, out, C.byref(nb), None) == lsb.LSB_EINVAL
+    lib.lsb_ref_destroy(h)
