@@ -324,10 +324,24 @@ def run_refine_tree(steps: int, warmup: int):
     ms = e0.elapsed_time(e1) / steps
     updates = (n * n - 9 * 199 * 199) + 2 * 9 * g.n_level(1)
     gbs = updates * 144 / (ms * 1e-3) / 1e9
+    # one adaptive cycle per call: the seeded sensor on nine gas disks (one
+    # seed each, at the boxes' centres) moving by 8 coarse nodes between
+    # calls, and the re-meshing of the tree onto its boxes
+    seeds = [((b[0] + b[1]) // 2, (b[2] + b[3]) // 2) for b in boxes]
+    phis = [torch.as_tensor(np.max([90.0 - np.hypot(I - (sx + dx), J - sy) for sx, sy in seeds], axis=0).reshape(-1))
+            .to("cuda:0") for dx in (0.0, 8.0)]
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for r in range(6):
+        nb = g.sensor_seeded(phis[r % 2], 4.0, 6, seeds)
+        g.remesh_levels(nb)
+    torch.cuda.synchronize()
+    cycle_ms = (time.time() - t0) / 6 * 1e3
     res = dict(workload="D2Q9 refinement tree, 2048^2 coarse, nine 200^2-cell boxes (401^2 nodes each)",
                steps=steps, warmup=warmup, ms_per_step=ms, node_updates_per_step=updates,
                mlups=updates / (ms * 1e-3) / 1e6, gbs=gbs, frac=gbs / HBM_PEAK_GBS, bytes_per_update=144,
-               launches_per_step=1 + 9 * 3, dtype="f64")
+               launches_per_step=1 + 9 * 3, dtype="f64", sensor_remesh_ms=cycle_ms,
+               sensor_remesh_boxes=[list(b) for b in nb])
     log(f"[refine_tree] {res}")
     return res
 
