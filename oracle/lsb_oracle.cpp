@@ -522,10 +522,13 @@ struct Sim {
     // changes an interface cell's pressure by k Delta with
     // k = rho cs^2 q(1-q) sum_i 6 w_i (c_i.n)^2 / (2 eta) <= rho / (24 eta),
     // and the lagged iteration x' = x - k x_prev has roots of modulus sqrt(k),
-    // so it diverges for k > 1 (eta_bar < rho / 24: every workload with tau
-    // near 1/2).  Reading: the divisor of this part is floored at
+    // so it can diverge only for k > 1, i.e. eta_bar < rho_max / 24.
+    // Reading: where eta_bar >= rho_max / 24 the bound keeps k <= 1 and the
+    // divisor is eq:Sdecomp's own eta_bar; below it (every workload with tau
+    // near 1/2 and a large density ratio) the divisor is raised to
     // rho_max cs^2 / 4, which bounds k by 1/2 (roots of modulus 0.71).
-    const double eta_p = std::max(eta_bar, std::max(P.rho_phys[0], P.rho_phys[1]) * CS2 / 4.0);
+    const double rho_max = std::max(P.rho_phys[0], P.rho_phys[1]);
+    const double eta_p = eta_bar >= rho_max / 24.0 ? eta_bar : rho_max * CS2 / 4.0;
     T E = ((p_g - p_l) + sig * kG) / (2.0 * eta_p);
     T Sb[6];
     for (int m = 0; m < 6; ++m) Sb[m] = 0.5 * (MS[6 * c + m] + MS[6 * s + m]);
@@ -711,17 +714,26 @@ struct Sim {
         T sg = phi[c] / sqrt(phi[c] * phi[c] + 1.0);
         for (int ax = 0; ax < D; ++ax) {
           T v = sg * nrm[3 * c + ax];
+          if (val(v) == 0.0) continue;
+          const int d = val(v) > 0.0 ? -1 : 1;  // towards the upwind neighbour
           int e[3] = {0, 0, 0};
+          e[ax] = d;
           long s;
-          if (val(v) > 0.0) {
-            e[ax] = -1;
-            if (!nb(x, y, z, e[0], e[1], e[2], s) || !is_act(s)) continue;
-            for (int a = 0; a < 3; ++a) ut2[3 * c + a] -= P.ext_dtau * v * (ut[3 * c + a] - ut[3 * s + a]);
-          } else if (val(v) < 0.0) {
-            e[ax] = 1;
-            if (!nb(x, y, z, e[0], e[1], e[2], s) || !is_act(s)) continue;
-            for (int a = 0; a < 3; ++a) ut2[3 * c + a] -= P.ext_dtau * v * (ut[3 * s + a] - ut[3 * c + a]);
+          // Upwind neighbour's velocity.  Across a free-slip face the face is
+          // a mirror plane: the neighbour is the cell's own image, with the
+          // component normal to the face reversed.  Across a no-slip face,
+          // or towards a cell outside the band, the axis is skipped (zero
+          // gradient).  (Reading: the paper does not treat walls here.)
+          T un[3];
+          if (nb(x, y, z, e[0], e[1], e[2], s)) {
+            if (!is_act(s)) continue;
+            for (int a = 0; a < 3; ++a) un[a] = ut[3 * s + a];
+          } else {
+            if (P.bc[2 * ax + (d > 0 ? 1 : 0)] != BC_FREESLIP) continue;
+            for (int a = 0; a < 3; ++a) un[a] = (a == ax) ? -ut[3 * c + a] : ut[3 * c + a];
           }
+          for (int a = 0; a < 3; ++a)
+            ut2[3 * c + a] -= P.ext_dtau * v * (d < 0 ? ut[3 * c + a] - un[a] : un[a] - ut[3 * c + a]);
         }
       }
       std::swap(ut, ut2);
@@ -1519,6 +1531,37 @@ int orc_extend(const orc::Params* p, const double* phi, const unsigned char* fix
   std::vector<unsigned char> icell(fixed, fixed + s.N);
   s.extension_iterate(icell);
   for (long c = 0; c < 3 * s.N; ++c) u[c] = s.ut[c];
+  return 0;
+}
+
+// Refill (Sec. 2.4) on a crafted state, through the step's own refill():
+// phi_new (N) is the level set after transport (its sign gives the new phase,
+// its geometry the normal and curvature), old_gas (N) the phase tags before
+// it (0 liquid, 1 gas), pop (Q*N, [i*N + cell]) the post-collision
+// populations of the step, rho (N), u (3N) and S (6N) the moments of the
+// step's collision, pb the gas pressure baseline.  Cells whose tag changes
+// are refilled in place in pop, rho, u and S.
+int orc_refill(const orc::Params* p, const double* phi_new, const unsigned char* old_gas, double* pop,
+               double* rho, double* u, double* S, double pb) {
+  if (check_params(p)) return -1;
+  Sim<double> s(*p);
+  s.all_active = true;
+  for (long c = 0; c < s.N; ++c) {
+    s.phi[c] = phi_new[c];
+    s.gas[c] = old_gas[c] ? 1 : 0;
+    s.gas1[c] = phi_new[c] >= 0.0 ? 1 : 0;
+    s.Mr1[c] = rho[c];
+  }
+  s.geometry();
+  for (long c = 0; c < 3 * s.N; ++c) s.Mu1[c] = u[c];
+  for (long c = 0; c < 6 * s.N; ++c) s.MS1[c] = S[c];
+  for (long c = 0; c < (long)s.Q * s.N; ++c) s.An[c] = pop[c];
+  s.Pb = pb;
+  s.refill();
+  for (long c = 0; c < (long)s.Q * s.N; ++c) pop[c] = s.An[c];
+  for (long c = 0; c < s.N; ++c) rho[c] = s.Mr1[c];
+  for (long c = 0; c < 3 * s.N; ++c) u[c] = s.Mu1[c];
+  for (long c = 0; c < 6 * s.N; ++c) S[c] = s.MS1[c];
   return 0;
 }
 

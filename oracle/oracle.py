@@ -106,6 +106,7 @@ def _load():
     lib.orc_advect.argtypes = [P, dp, dp, C.c_int]
     lib.orc_reinit.argtypes = [P, dp, C.c_int]
     lib.orc_extend.argtypes = [P, dp, ub, dp]
+    lib.orc_refill.argtypes = [P, dp, ub, dp, dp, dp, dp, C.c_double]
     lib.orc_tan_create.restype = C.c_void_p
     lib.orc_tan_create.argtypes = [P]
     lib.orc_tan_destroy.argtypes = [C.c_void_p]
@@ -262,6 +263,25 @@ def extend(p: dict, phi, fixed, u):
     u = _f64(u, 3 * N).copy()
     assert lib.orc_extend(C.byref(_params(p)), _dp(phi), fx.ctypes.data_as(C.POINTER(C.c_ubyte)), _dp(u)) == 0
     return u.reshape(p["nz"], p["ny"], p["nx"], 3)
+
+
+def refill(p: dict, phi_new, old_gas, pop, rho, u, S=None, pb: float = 0.0):
+    """Refill (Sec. 2.4) on a crafted state through the oracle step's own
+    refill: phi_new (N) gives the new phase and the geometry, old_gas (N)
+    the tags before the step, pop (Q, N) the post-collision populations,
+    rho (N), u (N, 3) and S (N, 6) the collision's moments.  Returns the
+    refilled (pop, rho, u, S)."""
+    lib = _load()
+    N = _ncell(p)
+    phi = _f64(phi_new, N)
+    g = np.ascontiguousarray(old_gas, dtype=np.uint8).reshape(N)
+    pop = _f64(pop).reshape(-1).copy()
+    rho = _f64(rho, N).copy()
+    u = _f64(u, 3 * N).copy()
+    S = np.zeros(6 * N) if S is None else _f64(S, 6 * N).copy()
+    assert lib.orc_refill(C.byref(_params(p)), _dp(phi), g.ctypes.data_as(C.POINTER(C.c_ubyte)), _dp(pop),
+                          _dp(rho), _dp(u), _dp(S), float(pb)) == 0
+    return pop.reshape(-1, N), rho, u.reshape(N, 3), S.reshape(N, 6)
 
 
 class Oracle:

@@ -218,7 +218,7 @@ __device__ Dual iface_pull(Acc<R>& A, int c, int x, int y, int sc, int i, int k)
   const double eta_bar = 0.5 * (v.eta[0] + v.eta[1]);
   const double jeta = v.eta[1] - v.eta[0];
   const double rmax = v.rho_phys[0] > v.rho_phys[1] ? v.rho_phys[0] : v.rho_phys[1];
-  const double eta_p = eta_bar > rmax / 12.0 ? eta_bar : rmax / 12.0;
+  const double eta_p = eta_bar >= rmax / 24.0 ? eta_bar : rmax / 12.0;
   const Dual sig = A.get(AR_SIG, 0);
   const Dual E = ((p_g - p_l) + sig * kG) / Dual(2.0 * eta_p);
   Dual Sb[6];
@@ -401,13 +401,16 @@ __device__ void ext_sweep(Acc<R>& A, int c, Dual* out) {
     if (vv.v == 0.0) continue;
     const int dir = vv.v > 0.0 ? -1 : 1;
     const int s = coord_lb(pos[ax] + dir, n[ax], v.per[ax]);
-    if (s < 0) continue;
+    // beyond a free-slip face: the cell's mirror image (normal component
+    // reversed); beyond a no-slip face: skipped
+    if (s < 0 && v.bcf[2 * ax + (dir > 0 ? 1 : 0)] != LSB_FREESLIP) continue;
     int p2[2] = {x, y};
-    p2[ax] = s;
+    p2[ax] = s < 0 ? pos[ax] : s;
     const int nc = p2[1] * v.nx + p2[0];
     if (!(v.tag0[nc] & T_ACT)) continue;
     for (int m = 0; m < 3; ++m) {
-      const Dual un = A.get(AR_UT, m * N + nc);
+      const Dual w = A.get(AR_UT, m * N + nc);
+      const Dual un = (s < 0 && m == ax) ? Dual(0.0) - w : w;
       const Dual diff = vv.v > 0.0 ? (u[m] - un) : (un - u[m]);
       o[m] = o[m] - Dual(v.ext_dtau) * vv * diff;
     }

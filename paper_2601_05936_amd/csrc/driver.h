@@ -34,11 +34,13 @@ struct Driver {
     }
     a.sigma = (R)P.sigma;
     {
-      // interface-coupling constants (pressure jump divisor floored at
-      // rho_max cs^2 / 4 = rho_max / 12, see iface_pull)
-      const double eta_bar = 0.5 * ((double)a.eta[0] + (double)a.eta[1]);
+      // interface-coupling constants: the pressure jump's divisor is the
+      // mean viscosity where eta_bar >= rho_max / 24 (the lagged pressure
+      // feedback then has gain <= 1), else rho_max cs^2 / 4 = rho_max / 12
+      // (gain <= 1/2), see iface_pull
+      const double eta_bar = 0.5 * (P.rho_phys[0] * (P.tau[0] - 0.5) / 3.0 + P.rho_phys[1] * (P.tau[1] - 0.5) / 3.0);
       const double rmax = P.rho_phys[0] > P.rho_phys[1] ? P.rho_phys[0] : P.rho_phys[1];
-      const double eta_p = eta_bar > rmax / 12.0 ? eta_bar : rmax / 12.0;
+      const double eta_p = eta_bar >= rmax / 24.0 ? eta_bar : rmax / 12.0;
       for (int k = 0; k < 2; ++k) a.iface_pc[k] = (R)(P.rho_phys[k] / 3.0);
       a.iface_inv2etap = (R)(1.0 / (2.0 * eta_p));
       a.iface_acoef = (R)(-((double)a.eta[1] - (double)a.eta[0]) / eta_bar);

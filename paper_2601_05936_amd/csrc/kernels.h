@@ -646,8 +646,9 @@ __device__ __forceinline__ typename Step<LAT, ST>::R cut_eval(const typename Ste
   const R p_l = (k == 0) ? p_own : p_oth;
   const R p_g = (k == 0) ? p_oth : p_own;
   // pressure part of the normal jump: divisor 2 eta_p with eta_p the mean
-  // viscosity floored at rho_max cs^2 / 4, so that the lagged explicit
-  // pressure feedback has gain k <= 1/2 (constants of the argument block)
+  // viscosity, raised to rho_max cs^2 / 4 where the mean viscosity is below
+  // rho_max / 24, so that the lagged explicit pressure feedback has gain
+  // k <= 1 (constants of the argument block)
   const R E = ((p_g - p_l) + a.sigma * kG) * a.iface_inv2etap;
   R Sb[6];
   for (int m = 0; m < 6; ++m) Sb[m] = (R)0.5 * (own.M[4 + m] + rs.v[5 + m]);
@@ -925,12 +926,15 @@ __global__ __launch_bounds__(256) void k_ext_seed(const typename Step<LAT, ST>::
       gv[ax] = a.G[ax * N + c];
       for (int sd = -1; sd <= 1; sd += 2) {
         // a neighbour beyond a wall reads the cell itself (no branch around
-        // the load) and counts as inactive
+        // the load); beyond a free-slip face it is the cell's mirror image
+        // (the sweep reverses its normal component), beyond a no-slip face
+        // it counts as inactive
         const int sv = lb_coord(pos[ax] + sd, sel3(n, ax), sel3(a.per, ax));
         int p2[3] = {x, y, z};
         p2[ax] = sv >= 0 ? sv : pos[ax];
         const uint8_t tn = a.tag[(p2[2] * a.ny + p2[1]) * a.nx + p2[0]];
-        const bool on = (sv >= 0) & ((tn & T_ACT) != 0);
+        const bool mirror = sel6(a.bcf, 2 * ax + (sd > 0 ? 1 : 0)) == LSB_FREESLIP;
+        const bool on = ((sv >= 0) | mirror) & ((tn & T_ACT) != 0);
         (sd < 0 ? act_lo : act_hi)[ax] = on;
       }
     }
@@ -938,7 +942,7 @@ __global__ __launch_bounds__(256) void k_ext_seed(const typename Step<LAT, ST>::
     for (int m = 0; m < 3; ++m) a.ut_a[m * N + c] = mn[m];
     // coefficients of the sweeps (phi and n are fixed over them): dtau v_ax
     // with v = S(phi) n; 0 where v_ax is 0 or the upwind neighbour is beyond
-    // a wall or not LS-active
+    // a no-slip face or not LS-active
     const R sg = ph / sqrt(ph * ph + (R)1);
     for (int ax = 0; ax < S::D; ++ax) {
       const R v = sg * gv[ax];
@@ -1017,7 +1021,12 @@ __global__ __launch_bounds__(256) void k_ext_iter(const typename Step<LAT, ST>::
       int p2[3] = {x, y, z};
       p2[ax] = ((kk[ax] != (R)0) & (sv >= 0)) ? sv : pos[ax];
       const int nc = (p2[2] * a.ny + p2[1]) * a.nx + p2[0];
-      for (int m = 0; m < 3; ++m) un[ax][m] = a.ut_a[m * N + nc];
+      // beyond a face (a nonzero coefficient there means a free-slip face)
+      // the neighbour is the cell's mirror image: normal component reversed
+      for (int m = 0; m < 3; ++m) {
+        const R w = a.ut_a[m * N + nc];
+        un[ax][m] = (m == ax && sv < 0) ? -w : w;
+      }
     }
     R out[3] = {u[0], u[1], u[2]};
     for (int ax = 0; ax < S::D; ++ax)
