@@ -200,10 +200,14 @@ int lsb_ref_sensor_seeded(lsb_ref* ref, const double* phi, double d_ref, int mar
  * populations, the others are interpolated from the parent's post-collision
  * populations with the non-equilibrium part scaled by
  * (tau_l - 1) / (2 (tau_{l-1} - 1)), and each level's perimeter sets come
- * from inverting the parent's BGK step.  LSB_EINVAL for a box outside its
- * parent (one node to spare, two cells per axis) or beyond the workspace's
- * extents; LSB_ESTATE before lsb_ref_init. */
-int lsb_ref_remesh_levels(lsb_ref* ref, const int* boxes, void* stream);
+ * from inverting the parent's BGK step.  nboxes is the number of boxes
+ * given and must equal the hierarchy's refined grids (levels - 1; the
+ * seeded sensor may return fewer boxes than a tree has when boxes merge:
+ * such a result needs a new tree, lsb_ref_create_tree).  LSB_EINVAL for
+ * nboxes != levels - 1 (checked first, before any other access), a box
+ * outside its parent (one node to spare, two cells per axis) or beyond the
+ * workspace's extents; LSB_ESTATE before lsb_ref_init. */
+int lsb_ref_remesh_levels(lsb_ref* ref, const int* boxes, int nboxes, void* stream);
 
 /* Post-collision populations of both levels into device arrays, [Q][nodes]
  * in the paper's direction ordering (rest direction last): coarse

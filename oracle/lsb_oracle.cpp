@@ -405,6 +405,24 @@ struct Sim {
   T xc0[3];
   long nstep = 0;
   bool all_active = false;              // component tests: treat every cell as LS-active
+  // Decision trace, for finite-difference checks that must not cross a
+  // branch: every branch a value decides folds (site, outcome) into the
+  // deciding cell's word (each word written by one thread only); the end of
+  // a step folds the words and the tags into one hash per step.
+  mutable std::vector<uint64_t> dcell;
+  std::vector<uint64_t> dlog;
+  void decide(long c, unsigned site, long outcome) const {
+    dcell[c] = dcell[c] * 0x100000001B3ull + (uint64_t)site * 0x9E3779B97F4A7C15ull + (uint64_t)(outcome + 7);
+  }
+  void fold_decisions() {
+    uint64_t h = 0xCBF29CE484222325ull;
+    for (long c = 0; c < N; ++c) {
+      h = (h ^ dcell[c]) * 0x100000001B3ull;
+      h = (h ^ (uint64_t)(gas[c] + 2 * act[c])) * 0x100000001B3ull;
+      dcell[c] = 0;
+    }
+    dlog.push_back(h);
+  }
 
   explicit Sim(const Params& p) : P(p) {
     L = make_lattice(p.lattice);
@@ -424,6 +442,7 @@ struct Sim {
     Mr1 = Mr; Mu1 = Mu; MS1 = MS;
     nrm.assign(3 * N, T(0.0)); kap.assign(N, T(0.0));
     ut.assign(3 * N, T(0.0)); ut2 = ut;
+    dcell.assign(N, 0);
     sig = T(p.sigma); Pb = T(p.pb0);
     for (int a = 0; a < 3; ++a) xc0[a] = T(0.0);
   }
@@ -556,10 +575,14 @@ struct Sim {
     // linear interpolation), which keeps both branches equal at q = 1/2.
     if (val(q) < 0.5) {
       long far;
-      if (nb(x, y, z, ci[0], ci[1], ci[2], far) && gas[far] == k)
+      if (nb(x, y, z, ci[0], ci[1], ci[2], far) && gas[far] == k) {
+        decide(c, 1, 1);
         return 2.0 * q * A[(size_t)j * N + c] + (1.0 - 2.0 * q) * A[(size_t)j * N + far] + W;
+      }
+      decide(c, 1, 2);
       return A[(size_t)j * N + c] + W;  // thin film: halfway bounce-back
     }
+    decide(c, 1, 0);
     return A[(size_t)j * N + c] / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * A[(size_t)i * N + c] +
            W / (2.0 * q);
   }
@@ -714,6 +737,7 @@ struct Sim {
         T sg = phi[c] / sqrt(phi[c] * phi[c] + 1.0);
         for (int ax = 0; ax < D; ++ax) {
           T v = sg * nrm[3 * c + ax];
+          decide(c, 2, val(v) > 0.0 ? 1 : (val(v) < 0.0 ? -1 : 0));
           if (val(v) == 0.0) continue;
           const int d = val(v) > 0.0 ? -1 : 1;  // towards the upwind neighbour
           int e[3] = {0, 0, 0};
@@ -764,6 +788,7 @@ struct Sim {
       T r = T(0.0);
       for (int ax = 0; ax < D; ++ax) {
         T u = ut[3 * c + ax];
+        decide(c, 3, val(u) >= 0.0);
         r = r - u * d_upwind5(ph, x, y, z, ax, val(u) >= 0.0);
       }
       out[c] = r;
@@ -787,6 +812,7 @@ struct Sim {
     const double B = P.band;
     for (long c = 0; c < N; ++c) {
       if (!is_act(c)) continue;
+      decide(c, 4, val(phi[c]) > B ? 1 : (val(phi[c]) < -B ? -1 : 0));
       if (val(phi[c]) > B) phi[c] = T(B);
       if (val(phi[c]) < -B) phi[c] = T(-B);
     }
@@ -1021,18 +1047,21 @@ struct Sim {
         if (!nb(x, y, z, e[0], e[1], e[2], x1) || !established(x1)) continue;
         bool two = nb(x, y, z, 2 * e[0], 2 * e[1], 2 * e[2], x2) && established(x2);
         T q;
+        int qb = 0;
         if (nb(x, y, z, -e[0], -e[1], -e[2], xm) && ((val(phi[xm]) >= 0.0) != (val(phi[c]) >= 0.0))) {
           q = phi[c] / (phi[c] - phi[xm]);
         } else {
           double len = std::sqrt((double)(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]));
           T en = (e[0] * nrm[3 * c] + e[1] * nrm[3 * c + 1] + e[2] * nrm[3 * c + 2]) / len;
           T aen = fabs(en);
-          if (val(aen) < 1e-12) q = T(1.0);
+          if (val(aen) < 1e-12) { q = T(1.0); qb = 1; }
           else {
             q = fabs(phi[c]) / (aen * len);
-            if (val(q) > 1.0) q = T(1.0);
+            qb = 2;
+            if (val(q) > 1.0) { q = T(1.0); qb = 3; }
           }
         }
+        decide(c, 5, 16 * i + 4 * (two ? 1 : 0) + qb);
         T w0, w1, w2 = T(0.0);
         if (two) {
           w0 = 2.0 / ((q + 1.0) * (q + 2.0));
@@ -1063,6 +1092,7 @@ struct Sim {
         done = true;
       }
       if (!done) {
+        decide(c, 5, -1);
         T fe[27];
         equilibrium(L, rhoG, uG, fe);
         for (int k = 0; k < Q; ++k) An[(size_t)k * N + c] = fe[k];
@@ -1077,6 +1107,8 @@ struct Sim {
     V = T(0.0);
     T s[3] = {T(0.0), T(0.0), T(0.0)};
     for (long c = 0; c < N; ++c) {
+      const double pe = val(phi[c]);
+      decide(c, 6, pe <= -P.heaviside_eps ? -1 : (pe >= P.heaviside_eps ? 1 : 0));
       T h = heaviside(phi[c], P.heaviside_eps);
       if (val(h) == 0.0) continue;
       int x, y, z;
@@ -1117,6 +1149,7 @@ struct Sim {
         }
       }
     }
+    for (long c = 0; c < N; ++c) decide(c, 7, bub[c]);
     bvol.assign(nb_, T(0.0));
     bxc.assign(3 * (size_t)nb_, T(0.0));
     bpb.assign(nb_, T(0.0));
@@ -1184,6 +1217,7 @@ struct Sim {
     std::swap(Mr, Mr1); std::swap(Mu, Mu1); std::swap(MS, MS1);
     std::swap(gas, gas1); std::swap(act, act1);
     update_pb();
+    fold_decisions();
     ++nstep;
   }
 
@@ -1351,6 +1385,15 @@ int orc_step(void* h, int n) {
 long orc_nstep(void* h) { return static_cast<Sim<double>*>(h)->nstep; }
 
 // Populations A[i*N + cell].
+// Decision trace: one hash per step taken (see Sim::decide); returns the
+// number of steps, writes at most max hashes.
+long orc_decisions(void* h, uint64_t* out, long max) {
+  Sim<double>* s = static_cast<Sim<double>*>(h);
+  const long n = (long)s->dlog.size();
+  for (long k = 0; k < n && k < max; ++k) out[k] = s->dlog[k];
+  return n;
+}
+
 int orc_get_pop(void* h, double* out) {
   Sim<double>* s = static_cast<Sim<double>*>(h);
   std::memcpy(out, s->A.data(), sizeof(double) * s->A.size());

@@ -85,6 +85,8 @@ def _load():
     lib.orc_nstep.restype = C.c_long
     lib.orc_nstep.argtypes = [C.c_void_p]
     lib.orc_get_pop.argtypes = [C.c_void_p, dp]
+    lib.orc_decisions.restype = C.c_long
+    lib.orc_decisions.argtypes = [C.c_void_p, C.POINTER(C.c_uint64), C.c_long]
     lib.orc_get_sample.argtypes = [C.c_void_p, C.POINTER(C.c_long), C.c_int, dp, dp, C.POINTER(C.c_ubyte)]
     lib.orc_get_sample.restype = C.c_int
     lib.orc_get_fields.argtypes = [C.c_void_p, dp, dp, dp, ub]
@@ -131,7 +133,7 @@ def _load():
     lib.orc_mref_init.argtypes = [C.c_void_p, C.POINTER(dp), C.POINTER(dp)]
     lib.orc_mref_get.argtypes = [C.c_void_p, C.c_int, dp]
     lib.orc_ref_sensor_levels.argtypes = [C.c_void_p, dp, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_int)]
-    lib.orc_ref_remesh_levels.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
+    lib.orc_ref_remesh_levels.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.c_int]
     lib.orc_ref_sensor_seeded.restype = C.c_int
     lib.orc_ref_sensor_seeded.argtypes = [C.c_void_p, dp, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_int),
                                           C.POINTER(C.c_int)]
@@ -313,6 +315,15 @@ class Oracle:
     @property
     def nstep(self):
         return self.lib.orc_nstep(self.h)
+
+    def decisions(self) -> np.ndarray:
+        """One 64-bit hash per step taken of every decision the step's values
+        made (tags, bounce-back branches, upwind directions, clamps, refill
+        directions and fallbacks, Heaviside regions, bubble labels)."""
+        n = self.lib.orc_decisions(self.h, None, 0)
+        out = np.zeros(max(n, 1), dtype=np.uint64)
+        self.lib.orc_decisions(self.h, out.ctypes.data_as(C.POINTER(C.c_uint64)), n)
+        return out[:n]
 
     def populations(self):
         out = np.zeros(self.Q * self.N)
@@ -583,13 +594,16 @@ class RefineOracle:
 
     def remesh_levels(self, boxes):
         """Re-mesh every refined level onto boxes (6 ints each, level 1
-        first, each in its new parent's node coordinates)."""
+        first, each in its new parent's node coordinates), one box per
+        refined grid."""
+        if len(boxes) != self.levels - 1:
+            raise ValueError(f"{len(boxes)} boxes for {self.levels - 1} refined grids: the tree needs rebuilding")
         flat = []
         for bx in boxes:
             p = (tuple(int(v) for v in bx) + (0, 0))[:6]
             flat += list(p if self.D == 3 else p[:4] + (0, 0))
-        if self._lib.orc_ref_remesh_levels(self._h, (C.c_int * len(flat))(*flat)) != 0:
-            raise ValueError("a box does not fit its parent")
+        if self._lib.orc_ref_remesh_levels(self._h, (C.c_int * max(1, len(flat)))(*flat), len(boxes)) != 0:
+            raise ValueError("the boxes do not match the refined grids, or a box does not fit its parent")
         self.boxes = [tuple(flat[6 * l:6 * l + 6]) for l in range(len(boxes))]
         self._sync_level1()
         return self

@@ -635,10 +635,12 @@ int orc_ref_sensor_levels(void* h, const double* phi, double d_ref, const int* m
   return static_cast<ref::Ref*>(h)->sensor_boxes(phi, d_ref, margins, out) ? 1 : 0;
 }
 
-// nested re-mesh onto boxes (6 ints per refined level, each in its new
-// parent's node coordinates); -1 if a box does not fit its parent
-int orc_ref_remesh_levels(void* h, const int* boxes) {
+// nested re-mesh onto boxes (nboxes boxes of 6 ints, one per refined grid,
+// each in its new parent's node coordinates); -1 if the count differs from
+// the refined grids or a box does not fit its parent
+int orc_ref_remesh_levels(void* h, const int* boxes, int nboxes) {
   ref::Ref* r = static_cast<ref::Ref*>(h);
+  if (nboxes != r->L - 1) return -1;
   if (r->lv[0].f.empty()) return -1;  // not initialised
   int last[ref::BMAX][3];  // each grid's last node index per axis, after the re-mesh
   last[0][0] = r->lv[0].mx;

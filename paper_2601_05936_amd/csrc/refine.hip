@@ -1369,8 +1369,9 @@ int lsb_ref_remesh(lsb_ref* r, const int* patch, void* stream) {
   return remesh_levels(r, patch, reinterpret_cast<hipStream_t>(stream));
 }
 
-int lsb_ref_remesh_levels(lsb_ref* r, const int* boxes, void* stream) {
+int lsb_ref_remesh_levels(lsb_ref* r, const int* boxes, int nboxes, void* stream) {
   if (!r || !boxes) return fail(LSB_EINVAL, "null pointer");
+  if (nboxes != r->L - 1) return fail(LSB_EINVAL, "lsb_ref_remesh_levels: the number of boxes differs from the refined grids");
   if (!r->inited) return fail(LSB_ESTATE, "lsb_ref_remesh_levels before lsb_ref_init");
   return remesh_levels(r, boxes, reinterpret_cast<hipStream_t>(stream));
 }

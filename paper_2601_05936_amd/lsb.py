@@ -127,7 +127,7 @@ def load() -> C.CDLL:
     lib.lsb_ref_init_levels.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
     lib.lsb_ref_get_level.argtypes = [vp, C.c_int, vp, vp]
     lib.lsb_ref_sensor_levels.argtypes = [vp, vp, C.c_double, C.POINTER(C.c_int), C.POINTER(C.c_int), vp]
-    lib.lsb_ref_remesh_levels.argtypes = [vp, C.POINTER(C.c_int), vp]
+    lib.lsb_ref_remesh_levels.argtypes = [vp, C.POINTER(C.c_int), C.c_int, vp]
     lib.lsb_ref_create_tree.argtypes = [R, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(vp)]
     lib.lsb_ref_set_graphs.argtypes = [vp, C.c_int]
     lib.lsb_ref_sensor_seeded.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_int),
@@ -497,12 +497,16 @@ class Refine:
 
     def remesh_levels(self, boxes):
         """Re-mesh every refined level onto boxes (6 ints each, level 1
-        first, each in its new parent's node coordinates)."""
+        first, each in its new parent's node coordinates), one box per
+        refined grid (the seeded sensor returns fewer when boxes merge:
+        that result needs a new tree)."""
+        if len(boxes) != self.levels - 1:
+            raise ValueError(f"{len(boxes)} boxes for {self.levels - 1} refined grids: the tree needs rebuilding")
         flat = []
         for bx in boxes:
             p = (tuple(int(v) for v in bx) + (0, 0))[:6]
             flat += list(p if self.D == 3 else p[:4] + (0, 0))
-        _check(self.lib.lsb_ref_remesh_levels(self.h, (C.c_int * len(flat))(*flat), self.stream()))
+        _check(self.lib.lsb_ref_remesh_levels(self.h, (C.c_int * max(1, len(flat)))(*flat), len(boxes), self.stream()))
         self.boxes = [tuple(flat[6 * l:6 * l + 6]) for l in range(len(boxes))]
         self._sync_level1()
         return self

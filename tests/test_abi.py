@@ -293,3 +293,23 @@ def test_refine_seeded_sensor_validates_before_device_access():
         assert lib.lsb_ref_sensor_seeded(h, C.c_void_p(1), 0.5, margin, ns, seeds, out, C.byref(nb), None) == lsb.LSB_EINVAL
     assert lib.lsb_ref_sensor_seeded(h, None, 0.5, 1, 2, seeds, out, C.byref(nb), None) == lsb.LSB_EINVAL
     lib.lsb_ref_destroy(h)
+
+
+def test_refine_remesh_levels_checks_the_box_count_first():
+    """Re-meshing takes exactly one box per refined grid: a seeded sensor
+    result with merged boxes (fewer than the tree has) is refused before any
+    device access, and so is a longer list."""
+    lib = lsb.load()
+    rc, h = _tree_create([0, 0, 1], _SIB)
+    assert rc == lsb.LSB_OK
+    flat = [v for bx in _SIB for v in bx]
+    arr = (C.c_int * len(flat))(*flat)
+    for n in (0, 1, 2, 4):
+        assert lib.lsb_ref_remesh_levels(h, arr, n, None) == lsb.LSB_EINVAL
+        assert "number of boxes" in lib.lsb_last_error().decode()
+    assert lib.lsb_ref_remesh_levels(h, arr, 3, None) == lsb.LSB_ESTATE   # right count, not initialised
+    g = lsb.Refine.__new__(lsb.Refine)
+    g.levels = 4
+    with pytest.raises(ValueError, match="rebuilding"):
+        lsb.Refine.remesh_levels(g, _SIB[:2])
+    lib.lsb_ref_destroy(h)

@@ -297,38 +297,48 @@ def test_identical_fluids_interface_nearly_transparent():
 # a4/a5: Laplace law
 # ---------------------------------------------------------------------------
 
-def laplace_case(lat, n, R, sigma, steps):
+def laplace_case(lat, n, R, sigma, steps, bubble=False):
+    """A static droplet (or bubble) started from uniform LB density 1 in both
+    phases, i.e. not at the answer: the pressure jump must build up through
+    the interface coupling alone."""
     rho = [1.0, 0.1]
     p = W.default_params(lattice=lat, nx=n, ny=n, nz=1 if lat == W.D2Q9 else n, rho_phys=rho,
                          tau=[0.8, W.tau_from_eta(0.1 / 30, rho[1])], sigma=sigma)
     x, y, z = W.grid(p)
-    if lat == W.D2Q9:
-        phi = np.sqrt((x - n / 2) ** 2 + (y - n / 2) ** 2) - R
-        dp = sigma / R
-    else:
-        phi = np.sqrt((x - n / 2) ** 2 + (y - n / 2) ** 2 + (z - n / 2) ** 2) - R
-        dp = 2 * sigma / R
-    o = O.Oracle(p, phi, rho0=np.where(phi < 0, 1 + dp / (rho[0] / 3), 1.0))
+    r = np.sqrt((x - n / 2) ** 2 + (y - n / 2) ** 2 + (0.0 if lat == W.D2Q9 else (z - n / 2) ** 2))
+    phi = (R - r) if bubble else (r - R)
+    dp = sigma / R if lat == W.D2Q9 else 2 * sigma / R
+    o = O.Oracle(p, phi)
     o.step(steps)
     f = o.fields()
     I = o.interface()
-    return f["p"][I["phi"] < -3].mean() - f["p"][I["phi"] > 3].mean(), dp, o
+    inner, outer = (I["phi"] > 3, I["phi"] < -3) if bubble else (I["phi"] < -3, I["phi"] > 3)
+    return f["p"][inner].mean() - f["p"][outer].mean(), dp, o
 
 
 def test_laplace_2d_droplets():
-    """Pressure jump across a static 2D droplet: sigma * div n = sigma / R."""
+    """Pressure jump across a static 2D droplet: sigma * div n = sigma / R
+    (measured within 0.4% after 4000 steps from a uniform start)."""
     ratios = []
     for R in (8.0, 12.0):
-        dpn, dpe, o = laplace_case(W.D2Q9, 48, R, 1e-2, 1500)
-        assert abs(dpn / dpe - 1) < 0.05
+        dpn, dpe, o = laplace_case(W.D2Q9, 48, R, 1e-2, 4000)
+        assert abs(dpn / dpe - 1) < 0.02, (R, dpn / dpe)
         assert o.integrals()["umax"] < 1e-4
         ratios.append(dpn * R)
-    assert abs(ratios[0] / ratios[1] - 1) < 0.05  # linear in 1/R
+    assert abs(ratios[0] / ratios[1] - 1) < 0.02  # linear in 1/R
+
+
+def test_laplace_2d_bubble():
+    """The gas inside a static 2D bubble is higher by sigma / R."""
+    dpn, dpe, o = laplace_case(W.D2Q9, 48, 10.0, 1e-2, 4000, bubble=True)
+    assert abs(dpn / dpe - 1) < 0.02, dpn / dpe
 
 
 def test_laplace_3d_droplet():
-    dpn, dpe, o = laplace_case(W.D3Q19, 28, 8.0, 1e-2, 300)
-    assert abs(dpn / dpe - 1) < 0.05
+    """2 sigma / R across a sphere (measured within 0.5% after 1500 steps
+    from a uniform start)."""
+    dpn, dpe, o = laplace_case(W.D3Q19, 28, 8.0, 1e-2, 1500)
+    assert abs(dpn / dpe - 1) < 0.02, dpn / dpe
 
 
 # ---------------------------------------------------------------------------

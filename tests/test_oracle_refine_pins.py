@@ -605,3 +605,7 @@ def test_seeded_sensor_gives_one_box_per_seed_and_merges_close_ones():
     got2 = o.sensor_seeded(phi2.reshape(-1), d_ref, margin, [(30, 40), (46, 41)])
     m = phi2 >= -d_ref
     assert got2 == [(I[m].min() - margin, I[m].max() + margin, J[m].min() - margin, J[m].max() + margin, 0, 0)]
+    # a tree of two boxes cannot be re-meshed onto the merged result (one box)
+    t2 = _tree(n, [(20, 36, 30, 50), (40, 56, 30, 50)], [0, 0], 0.7, lambda x, y: (0 * x, 0 * y))
+    with pytest.raises(ValueError, match="rebuilding"):
+        t2.remesh_levels(got2)
