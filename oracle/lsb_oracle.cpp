@@ -36,11 +36,13 @@
 // "parity unpinned".
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <functional>
 #include <map>
+#include <memory>
 #include <vector>
 
 namespace orc {
@@ -370,11 +372,15 @@ enum { TAG_GAS = 1, TAG_ACTIVE = 2, TAG_IFACE = 4 };
 // quantities, Sec. 3.2); the smoothed form is the classical one of
 // Sussman, Smereka and Osher (1994).
 template <class T>
+static T heaviside_mid(const T& phi, double eps) {
+  const double pi = 3.14159265358979323846;
+  return 0.5 * (1.0 + phi / eps + sin(pi * phi / eps) / pi);
+}
+template <class T>
 static T heaviside(const T& phi, double eps) {
   if (val(phi) < -eps) return T(0.0);
   if (val(phi) > eps) return T(1.0);
-  const double pi = 3.14159265358979323846;
-  return 0.5 * (1.0 + phi / eps + sin(pi * phi / eps) / pi);
+  return heaviside_mid(phi, eps);
 }
 
 // --------------------------------------------------------------------------
@@ -405,15 +411,61 @@ struct Sim {
   T xc0[3];
   long nstep = 0;
   bool all_active = false;              // component tests: treat every cell as LS-active
-  // Decision trace, for finite-difference checks that must not cross a
-  // branch: every branch a value decides folds (site, outcome) into the
-  // deciding cell's word (each word written by one thread only); the end of
-  // a step folds the words and the tags into one hash per step.
+  // Decisions, for finite-difference checks of the frozen-decision
+  // derivative.  Every branch that a value decides (tags, bounce-back
+  // branch, upwind directions, clamp, refill direction and fallback,
+  // Heaviside region, bubble labels, Godunov branches and subcell-fix set
+  // of the reinitialisation) goes through decide(): its (site, outcome) is
+  // folded into the deciding cell's word (each word is written by one
+  // thread only), and the end of init and of every step folds the words and
+  // the tags into one hash.  In record mode the outcomes and tags are also
+  // kept; in replay mode a recorded run's outcomes and tags are imposed, so
+  // a perturbed run takes exactly the recorded branches.
+  struct DStep {
+    std::vector<int> cells, start;  // cells with decisions, their first entry
+    std::vector<unsigned char> site;
+    std::vector<int> out;
+    std::vector<unsigned char> tags;  // phase + 2 LS-active, one byte per cell
+  };
+  int dmode = 0;  // 0 hash only, 1 record, 2 replay
   mutable std::vector<uint64_t> dcell;
+  mutable std::vector<std::vector<std::pair<unsigned char, int>>> dcur;
+  std::shared_ptr<std::vector<DStep>> rlog;
+  size_t rstep = 0;
+  mutable std::vector<int> rcur, rend;
+  mutable std::atomic<bool> rbad{false};
   std::vector<uint64_t> dlog;
-  void decide(long c, unsigned site, long outcome) const {
+  long decide(long c, unsigned site, long outcome) const {
+    if (dmode == 2) {
+      const DStep& d = (*rlog)[rstep];
+      if (rcur[c] < rend[c] && d.site[rcur[c]] == site) outcome = d.out[rcur[c]++];
+      else rbad = true;
+    } else if (dmode == 1) {
+      dcur[c].push_back({(unsigned char)site, (int)outcome});
+    }
     dcell[c] = dcell[c] * 0x100000001B3ull + (uint64_t)site * 0x9E3779B97F4A7C15ull + (uint64_t)(outcome + 7);
+    return outcome;
   }
+  void begin_decisions() {
+    if (dmode != 2) return;
+    if (rstep >= rlog->size()) { rbad = true; return; }
+    const DStep& d = (*rlog)[rstep];
+    for (size_t k = 0; k < d.cells.size(); ++k) {
+      rcur[d.cells[k]] = d.start[k];
+      rend[d.cells[k]] = (k + 1 < d.cells.size()) ? d.start[k + 1] : (int)d.out.size();
+    }
+  }
+  // tags of the classification: recorded, or imposed from the record
+  void decide_tags(std::vector<unsigned char>& g, std::vector<unsigned char>& a) {
+    if (dmode == 1) {
+      dtags.resize(N);
+      for (long c = 0; c < N; ++c) dtags[c] = (unsigned char)(g[c] + 2 * a[c]);
+    } else if (dmode == 2 && rstep < rlog->size()) {
+      const std::vector<unsigned char>& t = (*rlog)[rstep].tags;
+      for (long c = 0; c < N; ++c) { g[c] = t[c] & 1; a[c] = (t[c] >> 1) & 1; }
+    }
+  }
+  std::vector<unsigned char> dtags;
   void fold_decisions() {
     uint64_t h = 0xCBF29CE484222325ull;
     for (long c = 0; c < N; ++c) {
@@ -422,6 +474,31 @@ struct Sim {
       dcell[c] = 0;
     }
     dlog.push_back(h);
+    if (dmode == 1) {
+      DStep d;
+      for (long c = 0; c < N; ++c) {
+        if (dcur[c].empty()) continue;
+        d.cells.push_back((int)c);
+        d.start.push_back((int)d.out.size());
+        for (auto& e : dcur[c]) { d.site.push_back(e.first); d.out.push_back(e.second); }
+        dcur[c].clear();
+      }
+      d.tags.swap(dtags);
+      rlog->push_back(std::move(d));
+    } else if (dmode == 2 && rstep < rlog->size()) {
+      const DStep& d = (*rlog)[rstep];
+      for (size_t k = 0; k < d.cells.size(); ++k) {
+        const long c = d.cells[k];
+        if (rcur[c] != rend[c]) rbad = true;  // recorded decisions left over
+        rcur[c] = rend[c] = 0;
+      }
+      ++rstep;
+    }
+  }
+  void set_decision_mode(int mode, const std::shared_ptr<std::vector<DStep>>& src) {
+    dmode = mode;
+    if (mode == 1) { rlog = std::make_shared<std::vector<DStep>>(); dcur.assign(N, {}); }
+    if (mode == 2) { rlog = src; rstep = 0; rcur.assign(N, 0); rend.assign(N, 0); }
   }
 
   explicit Sim(const Params& p) : P(p) {
@@ -573,16 +650,11 @@ struct Sim {
     // Interpolated bounce-back, eq:bb.  Reading of the q >= 1/2 branch: the
     // second population is the reflected one at the cell itself (Bouzidi's
     // linear interpolation), which keeps both branches equal at q = 1/2.
-    if (val(q) < 0.5) {
-      long far;
-      if (nb(x, y, z, ci[0], ci[1], ci[2], far) && gas[far] == k) {
-        decide(c, 1, 1);
-        return 2.0 * q * A[(size_t)j * N + c] + (1.0 - 2.0 * q) * A[(size_t)j * N + far] + W;
-      }
-      decide(c, 1, 2);
-      return A[(size_t)j * N + c] + W;  // thin film: halfway bounce-back
-    }
-    decide(c, 1, 0);
+    long far = 0;
+    const bool far_in = nb(x, y, z, ci[0], ci[1], ci[2], far) && gas[far] == k;
+    const long br = decide(c, 1, val(q) < 0.5 ? (far_in ? 1 : 2) : 0);
+    if (br == 1) return 2.0 * q * A[(size_t)j * N + c] + (1.0 - 2.0 * q) * A[(size_t)j * N + far] + W;
+    if (br == 2) return A[(size_t)j * N + c] + W;  // thin film: halfway bounce-back
     return A[(size_t)j * N + c] / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * A[(size_t)i * N + c] +
            W / (2.0 * q);
   }
@@ -737,9 +809,9 @@ struct Sim {
         T sg = phi[c] / sqrt(phi[c] * phi[c] + 1.0);
         for (int ax = 0; ax < D; ++ax) {
           T v = sg * nrm[3 * c + ax];
-          decide(c, 2, val(v) > 0.0 ? 1 : (val(v) < 0.0 ? -1 : 0));
-          if (val(v) == 0.0) continue;
-          const int d = val(v) > 0.0 ? -1 : 1;  // towards the upwind neighbour
+          const long sv = decide(c, 2, val(v) > 0.0 ? 1 : (val(v) < 0.0 ? -1 : 0));
+          if (sv == 0) continue;
+          const int d = sv > 0 ? -1 : 1;  // towards the upwind neighbour
           int e[3] = {0, 0, 0};
           e[ax] = d;
           long s;
@@ -788,8 +860,8 @@ struct Sim {
       T r = T(0.0);
       for (int ax = 0; ax < D; ++ax) {
         T u = ut[3 * c + ax];
-        decide(c, 3, val(u) >= 0.0);
-        r = r - u * d_upwind5(ph, x, y, z, ax, val(u) >= 0.0);
+        const bool up = decide(c, 3, val(u) >= 0.0) != 0;
+        r = r - u * d_upwind5(ph, x, y, z, ax, up);
       }
       out[c] = r;
     }
@@ -812,9 +884,9 @@ struct Sim {
     const double B = P.band;
     for (long c = 0; c < N; ++c) {
       if (!is_act(c)) continue;
-      decide(c, 4, val(phi[c]) > B ? 1 : (val(phi[c]) < -B ? -1 : 0));
-      if (val(phi[c]) > B) phi[c] = T(B);
-      if (val(phi[c]) < -B) phi[c] = T(-B);
+      const long cl = decide(c, 4, val(phi[c]) > B ? 1 : (val(phi[c]) < -B ? -1 : 0));
+      if (cl > 0) phi[c] = T(B);
+      if (cl < 0) phi[c] = T(-B);
     }
   }
 
@@ -853,18 +925,22 @@ struct Sim {
     const std::vector<T> p0 = phi;
     const double beta = 0.5;
     std::vector<unsigned char> fix(N, 0);
+    std::vector<int> fixmask(N, 0);  // neighbours across the zero set of phi0, per (axis, side)
 #pragma omp parallel for schedule(static)
     for (long c = 0; c < N; ++c) {
       if (!is_act(c)) continue;
       int x, y, z;
       coords(c, x, y, z);
       bool g0 = val(p0[c]) >= 0.0;
+      long mask = 0;
       for (int ax = 0; ax < D; ++ax)
         for (int sgn = -1; sgn <= 1; sgn += 2) {
           int e[3] = {0, 0, 0};
           e[ax] = sgn;
-          if ((val(p0[ls_nb(x, y, z, e[0], e[1], e[2])]) >= 0.0) != g0) fix[c] = 1;
+          if ((val(p0[ls_nb(x, y, z, e[0], e[1], e[2])]) >= 0.0) != g0) mask |= 1L << (2 * ax + (sgn > 0));
         }
+      fixmask[c] = (int)decide(c, 9, mask);
+      fix[c] = fixmask[c] != 0;
     }
     std::vector<T> r(N), p1(N), p2(N);
     auto rate = [&](const std::vector<T>& ph, std::vector<T>& out) {
@@ -875,6 +951,10 @@ struct Sim {
         coords(c, x, y, z);
         T S0 = p0[c] / sqrt(p0[c] * p0[c] + 1.0);
         T h2 = T(0.0);
+        // Godunov branches, four bits per axis: sign of S(phi0), the kept
+        // one-sided derivatives (nonzero or clipped) and the larger one
+        T dms[3], dps[3];
+        long code = 0;
         for (int ax = 0; ax < D; ++ax) {
           auto at = [&](int o) {
             int e[3] = {0, 0, 0};
@@ -882,23 +962,23 @@ struct Sim {
             return ph[ls_nb(x, y, z, e[0], e[1], e[2])];
           };
           T m3 = at(-3), m2 = at(-2), m1 = at(-1), c0 = at(0), p1v = at(1), p2v = at(2), p3 = at(3);
-          T dm = weno5(m2 - m3, m1 - m2, c0 - m1, p1v - c0, p2v - p1v);
-          T dp = weno5(p3 - p2v, p2v - p1v, p1v - c0, c0 - m1, m1 - m2);
-          T t;
-          if (val(S0) > 0.0) {
-            T a = val(dm) > 0.0 ? dm : T(0.0);
-            T b = val(dp) < 0.0 ? dp : T(0.0);
-            t = val(a * a) > val(b * b) ? a * a : b * b;
-          } else {
-            T a = val(dm) < 0.0 ? dm : T(0.0);
-            T b = val(dp) > 0.0 ? dp : T(0.0);
-            t = val(a * a) > val(b * b) ? a * a : b * b;
-          }
-          h2 = h2 + t;
+          dms[ax] = weno5(m2 - m3, m1 - m2, c0 - m1, p1v - c0, p2v - p1v);
+          dps[ax] = weno5(p3 - p2v, p2v - p1v, p1v - c0, c0 - m1, m1 - m2);
+          const bool pos = val(S0) > 0.0;
+          const bool ka = pos ? val(dms[ax]) > 0.0 : val(dms[ax]) < 0.0;
+          const bool kb = pos ? val(dps[ax]) < 0.0 : val(dps[ax]) > 0.0;
+          const double av = ka ? val(dms[ax]) : 0.0, bv = kb ? val(dps[ax]) : 0.0;
+          code |= (long)((pos ? 1 : 0) | (ka ? 2 : 0) | (kb ? 4 : 0) | (av * av > bv * bv ? 8 : 0)) << (4 * ax);
+        }
+        code = decide(c, 8, code);
+        for (int ax = 0; ax < D; ++ax) {
+          const long bits = (code >> (4 * ax)) & 15;
+          T a = (bits & 2) ? dms[ax] : T(0.0);
+          T b = (bits & 4) ? dps[ax] : T(0.0);
+          h2 = h2 + ((bits & 8) ? a * a : b * b);
         }
         T rt = -S0 * (sqrt(h2) - 1.0);
         if (fix[c]) {
-          bool g0 = val(p0[c]) >= 0.0;
           T acc = T(0.0);
           int cnt = 0;
           for (int ax = 0; ax < D; ++ax)
@@ -906,7 +986,7 @@ struct Sim {
               int e[3] = {0, 0, 0};
               e[ax] = sgn;
               long j = ls_nb(x, y, z, e[0], e[1], e[2]);
-              if ((val(p0[j]) >= 0.0) == g0) continue;
+              if (!(fixmask[c] & (1 << (2 * ax + (sgn > 0))))) continue;
               acc = acc + p0[c] * (ph[c] - ph[j]) / (p0[c] - p0[j]);
               ++cnt;
             }
@@ -1039,29 +1119,58 @@ struct Sim {
       T pnew = (knew == 0) ? pold + sig * kap[c] : pold - sig * kap[c];
       T rhoG = 1.0 + (pnew - (knew == 1 ? baseline(c) : T(0.0))) / (P.rho_phys[knew] * CS2);
       auto established = [&](long s) { return gas[s] == knew && gas1[s] == knew; };
-      bool done = false;
-      for (int t = 0; t < nc && !done; ++t) {
-        const int i = order[t];
-        const int* e = L.c[i];
-        long x1 = 0, x2 = 0, xm = 0;
-        if (!nb(x, y, z, e[0], e[1], e[2], x1) || !established(x1)) continue;
-        bool two = nb(x, y, z, 2 * e[0], 2 * e[1], 2 * e[2], x2) && established(x2);
-        T q;
-        int qb = 0;
+      // Wall distance q along e: from the level set across x - e when it
+      // changes sign there (branch 0), else the normal distance |phi| / |e.n|
+      // along e, capped at one spacing (branches 1-3).
+      auto q_branch = [&](const int* e, T& q) {
+        long xm = 0;
         if (nb(x, y, z, -e[0], -e[1], -e[2], xm) && ((val(phi[xm]) >= 0.0) != (val(phi[c]) >= 0.0))) {
           q = phi[c] / (phi[c] - phi[xm]);
-        } else {
+          return 0;
+        }
+        double len = std::sqrt((double)(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]));
+        T en = (e[0] * nrm[3 * c] + e[1] * nrm[3 * c + 1] + e[2] * nrm[3 * c + 2]) / len;
+        T aen = fabs(en);
+        if (val(aen) < 1e-12) { q = T(1.0); return 1; }
+        q = fabs(phi[c]) / (aen * len);
+        if (val(q) > 1.0) { q = T(1.0); return 3; }
+        return 2;
+      };
+      // The choice: the first direction in order of alignment whose
+      // neighbour x + e is established, quadratic if x + 2e is too, and the
+      // q branch; -1 when no direction qualifies.
+      long code = -1;
+      for (int t = 0; t < nc; ++t) {
+        const int i = order[t];
+        const int* e = L.c[i];
+        long x1 = 0, x2 = 0;
+        if (!nb(x, y, z, e[0], e[1], e[2], x1) || !established(x1)) continue;
+        bool two = nb(x, y, z, 2 * e[0], 2 * e[1], 2 * e[2], x2) && established(x2);
+        T qd;
+        code = 16 * i + 4 * (two ? 1 : 0) + q_branch(e, qd);
+        break;
+      }
+      code = decide(c, 5, code);
+      if (code >= 0) {
+        const int i = (int)(code / 16);
+        const bool two = ((code / 4) % 4) != 0;
+        const int qb = (int)(code % 4);
+        const int* e = L.c[i];
+        long x1 = 0, x2 = 0;
+        nb(x, y, z, e[0], e[1], e[2], x1);
+        if (two) nb(x, y, z, 2 * e[0], 2 * e[1], 2 * e[2], x2);
+        T q;
+        if (qb == 0) {
+          long xm = 0;
+          nb(x, y, z, -e[0], -e[1], -e[2], xm);
+          q = phi[c] / (phi[c] - phi[xm]);
+        } else if (qb == 2) {
           double len = std::sqrt((double)(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]));
           T en = (e[0] * nrm[3 * c] + e[1] * nrm[3 * c + 1] + e[2] * nrm[3 * c + 2]) / len;
-          T aen = fabs(en);
-          if (val(aen) < 1e-12) { q = T(1.0); qb = 1; }
-          else {
-            q = fabs(phi[c]) / (aen * len);
-            qb = 2;
-            if (val(q) > 1.0) { q = T(1.0); qb = 3; }
-          }
+          q = fabs(phi[c]) / (fabs(en) * len);
+        } else {
+          q = T(1.0);
         }
-        decide(c, 5, 16 * i + 4 * (two ? 1 : 0) + qb);
         T w0, w1, w2 = T(0.0);
         if (two) {
           w0 = 2.0 / ((q + 1.0) * (q + 2.0));
@@ -1089,10 +1198,7 @@ struct Sim {
         Mr1[c] = rr;
         for (int a = 0; a < 3; ++a) Mu1[3 * c + a] = ur[a];
         for (int mm = 0; mm < 6; ++mm) MS1[6 * c + mm] = MS1[6 * x1 + mm];
-        done = true;
-      }
-      if (!done) {
-        decide(c, 5, -1);
+      } else {
         T fe[27];
         equilibrium(L, rhoG, uG, fe);
         for (int k = 0; k < Q; ++k) An[(size_t)k * N + c] = fe[k];
@@ -1108,8 +1214,9 @@ struct Sim {
     T s[3] = {T(0.0), T(0.0), T(0.0)};
     for (long c = 0; c < N; ++c) {
       const double pe = val(phi[c]);
-      decide(c, 6, pe <= -P.heaviside_eps ? -1 : (pe >= P.heaviside_eps ? 1 : 0));
-      T h = heaviside(phi[c], P.heaviside_eps);
+      const long reg = decide(c, 6, pe < -P.heaviside_eps ? -1 : (pe > P.heaviside_eps ? 1 : 0));
+      if (reg < 0) continue;
+      T h = reg > 0 ? T(1.0) : heaviside_mid(phi[c], P.heaviside_eps);
       if (val(h) == 0.0) continue;
       int x, y, z;
       coords(c, x, y, z);
@@ -1149,7 +1256,8 @@ struct Sim {
         }
       }
     }
-    for (long c = 0; c < N; ++c) decide(c, 7, bub[c]);
+    for (long c = 0; c < N; ++c)
+      if (decide(c, 7, bub[c]) != bub[c]) rbad = true;  // labels are checked, not imposed
     bvol.assign(nb_, T(0.0));
     bxc.assign(3 * (size_t)nb_, T(0.0));
     bpb.assign(nb_, T(0.0));
@@ -1204,11 +1312,13 @@ struct Sim {
   //  8 gas centroid and pressure baseline
   // ------------------------------------------------------------------
   void step() {
+    begin_decisions();
     lb_step();
     extension();
     advect();
     if (P.reinit_every > 0 && ((nstep + 1) % P.reinit_every) == 0 && P.n_reinit > 0) reinit();
     classify(gas1, act1);
+    decide_tags(gas1, act1);
     std::swap(act, act1);  // geometry runs on the new band
     geometry();
     std::swap(act, act1);
@@ -1230,7 +1340,9 @@ struct Sim {
       if (val(p) < -B) p = T(-B);
       phi[c] = p;
     }
+    begin_decisions();
     classify(gas, act);
+    decide_tags(gas, act);
     geometry();
     T V;
     centroid(V, xc0);
@@ -1264,6 +1376,7 @@ struct Sim {
     }
     Mr1 = Mr; Mu1 = Mu; MS1 = MS;
     nstep = 0;
+    fold_decisions();
   }
 
   // Macroscopic output: rho = sum A, u = sum c A / rho - a_k / 2 (the
@@ -1385,8 +1498,28 @@ int orc_step(void* h, int n) {
 long orc_nstep(void* h) { return static_cast<Sim<double>*>(h)->nstep; }
 
 // Populations A[i*N + cell].
-// Decision trace: one hash per step taken (see Sim::decide); returns the
-// number of steps, writes at most max hashes.
+// Decision record / replay (finite differences of the frozen-decision
+// program): mode 1 records the decisions of the run that follows (call
+// before orc_init), mode 2 imposes those recorded by src.  Returns -1 for a
+// replay without a record.
+int orc_set_decisions(void* h, int mode, void* src) {
+  Sim<double>* s = static_cast<Sim<double>*>(h);
+  if (mode == 2) {
+    Sim<double>* r = static_cast<Sim<double>*>(src);
+    if (!r || r->dmode != 1 || !r->rlog) return -1;
+    s->set_decision_mode(2, r->rlog);
+  } else {
+    s->set_decision_mode(mode, nullptr);
+  }
+  return 0;
+}
+
+// 1 if a replayed run met a decision site the record does not hold (the
+// runs took different paths), else 0.
+int orc_replay_failed(void* h) { return static_cast<Sim<double>*>(h)->rbad ? 1 : 0; }
+
+// Decision trace: one hash for the initial state and one per step taken
+// (see Sim::decide); returns the count, writes at most max hashes.
 long orc_decisions(void* h, uint64_t* out, long max) {
   Sim<double>* s = static_cast<Sim<double>*>(h);
   const long n = (long)s->dlog.size();

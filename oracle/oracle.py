@@ -85,6 +85,8 @@ def _load():
     lib.orc_nstep.restype = C.c_long
     lib.orc_nstep.argtypes = [C.c_void_p]
     lib.orc_get_pop.argtypes = [C.c_void_p, dp]
+    lib.orc_set_decisions.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
+    lib.orc_replay_failed.argtypes = [C.c_void_p]
     lib.orc_decisions.restype = C.c_long
     lib.orc_decisions.argtypes = [C.c_void_p, C.POINTER(C.c_uint64), C.c_long]
     lib.orc_get_sample.argtypes = [C.c_void_p, C.POINTER(C.c_long), C.c_int, dp, dp, C.POINTER(C.c_ubyte)]
@@ -289,7 +291,10 @@ def refill(p: dict, phi_new, old_gas, pop, rho, u, S=None, pb: float = 0.0):
 class Oracle:
     """One oracle simulation (FP64)."""
 
-    def __init__(self, params: dict, phi0, rho0=None, u0=None):
+    def __init__(self, params: dict, phi0, rho0=None, u0=None, record=False, replay=None):
+        """record: keep every decision of this run (tags, branches); replay:
+        an Oracle created with record=True whose decisions this run takes
+        (the frozen-decision program, for finite differences)."""
         self.lib = _load()
         self.p = dict(params)
         self._cp = _params(self.p)
@@ -299,10 +304,20 @@ class Oracle:
         self.N = _ncell(self.p)
         self.shape = (self.p["nz"], self.p["ny"], self.p["nx"])
         self.D, self.Q = lattice(self.p["lattice"])[:2]
+        if record:
+            self.lib.orc_set_decisions(self.h, 1, None)
+        if replay is not None:
+            self._replay_src = replay  # the record lives as long as the replaying run
+            if self.lib.orc_set_decisions(self.h, 2, replay.h) != 0:
+                raise ValueError("replay needs an Oracle created with record=True")
         phi0 = _f64(phi0, self.N)
         rho0 = _f64(rho0, self.N)
         u0 = _f64(u0, 3 * self.N)
         assert self.lib.orc_init(self.h, _dp(phi0), _dp(rho0), _dp(u0)) == 0
+
+    def replay_failed(self) -> bool:
+        """True if a replayed run met a decision the record does not hold."""
+        return bool(self.lib.orc_replay_failed(self.h))
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -150,15 +150,29 @@ def _full_grid_gradients(steps, storages):
     return w, out
 
 
+def _fd_golden(steps):
+    import json
+    import os
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "rising_bubble_2d_fd.json")))
+    return next(c for c in d["cases"] if c["steps"] == steps)
+
+
+TOL_FD = 1e-4
+
+
 def test_rising_bubble_full_grid_gradient_gates(require_gpu):
-    """The differentiation workload's grid (256x512 D2Q9 rising bubble,
-    checkpoints every 100 steps, L = gas centroid height) over 500 steps:
-    FP64 dL/dsigma and <dL/dphi0, v> against the oracle tangent (1e-9);
-    FP32-state gradient against the FP64 one (1e-4)."""
+    """The differentiation workload (256x512 D2Q9 rising bubble, checkpoints
+    every 100 steps, L = gas centroid height) over 500 steps.  FP64 path:
+    dL/dsigma and <dL/dphi0, v> against the oracle tangent (1e-9) and
+    against the oracle's central finite differences with replayed decisions
+    (h = 1e-4, stored by tests/golden/make_rising_bubble_fd.py; 1e-4).  FP32
+    state: the same finite differences at 1e-4 and the FP64 gradient at
+    1e-4."""
     import oracle as O
     steps = 500
     w, g = _full_grid_gradients(steps, (W.F64, W.F32))
     p = w["params"]
+    fd = _fd_golden(steps)
     t = O.TangentOracle(p, w["phi0"], dsigma=1.0)
     t.step(steps)
     L_orc, dL_sigma = t.centroid(1)
@@ -167,39 +181,72 @@ def test_rising_bubble_full_grid_gradient_gates(require_gpu):
     t2.step(steps)
     _, dL_v = t2.centroid(1)
     L64, ds64, dp64 = g[W.F64]
+    dv64 = float(np.sum(dp64 * v))
     e_sig = abs(ds64 - dL_sigma) / abs(dL_sigma)
-    e_v = abs(float(np.sum(dp64 * v)) - dL_v) / abs(dL_v)
-    f_sig = abs(g[W.F32][1] - ds64) / abs(ds64)
+    e_v = abs(dv64 - dL_v) / abs(dL_v)
+    fd_sig = abs(ds64 - fd["dL_dsigma"]) / abs(fd["dL_dsigma"])
+    fd_v = abs(dv64 - fd["dL_dphi0_dot_v"]) / abs(fd["dL_dphi0_dot_v"])
+    ds32, dv32 = g[W.F32][1], float(np.sum(g[W.F32][2] * v))
+    fd32_sig = abs(ds32 - fd["dL_dsigma"]) / abs(fd["dL_dsigma"])
+    fd32_v = abs(dv32 - fd["dL_dphi0_dot_v"]) / abs(fd["dL_dphi0_dot_v"])
+    f_sig = abs(ds32 - ds64) / abs(ds64)
     f_phi = np.max(np.abs(g[W.F32][2] - dp64)) / np.max(np.abs(dp64))
-    print("L", L64, L_orc, "dL/dsigma", ds64, dL_sigma, "rel", e_sig, "<dL/dphi0,v> rel", e_v, "FP32 forward rel",
-          f_sig, f_phi, flush=True)
-    assert abs(L64 - L_orc) < 1e-10 * abs(L_orc)
+    print("L", L64, L_orc, fd["L"], "dL/dsigma", ds64, dL_sigma, fd["dL_dsigma"], "tangent rel", e_sig, "FD rel", fd_sig,
+          "<dL/dphi0,v>", dv64, dL_v, fd["dL_dphi0_dot_v"], "tangent rel", e_v, "FD rel", fd_v,
+          "FP32 vs FD", fd32_sig, fd32_v, "FP32 vs FP64", f_sig, f_phi, flush=True)
+    assert abs(L64 - L_orc) < 1e-10 * abs(L_orc) and abs(L64 - fd["L"]) < 1e-10 * abs(L_orc)
     assert e_sig < TOL_TANGENT and e_v < TOL_TANGENT
+    assert fd_sig < TOL_FD and fd_v < TOL_FD
+    assert fd32_sig < TOL_FD and fd32_v < TOL_FD
     assert f_sig < 1e-4 and f_phi < 1e-4
 
 
 def test_rising_bubble_2000_steps_gradient(require_gpu):
-    """The full differentiation workload (2000 steps).  The derivative of the
-    rise height grows about a hundredfold over the run and amplifies
-    trajectory differences: perturbing phi0 by 1e-13 changes the oracle's
-    own tangent by 1.2e-10 relative while L changes by 1.9e-14 (ratio
-    6.5e3).  The FP64 GPU trajectory differs from the oracle's by ~5e-12 in
-    L, so the tangent gate here is that ratio times the measured primal
-    difference (with a factor 2 margin), not 1e-9; the FP32-state gradient
-    (measured 2.4e-3 for dL/dsigma) is bounded at 1e-2."""
+    """The full differentiation workload (2000 steps), FP64 path, against
+    the oracle's central finite differences with replayed decisions (h =
+    1e-6: after 2000 steps the replayed runs stay in the linear range only
+    up to about 1e-5; stored by tests/golden/make_rising_bubble_fd.py): 1e-4
+    for dL/dsigma and for <dL/dphi0, v>.  Against the oracle's tangent the
+    difference is reported: the derivative of the rise height grows about
+    twentyfold from step 500 to 2000 and amplifies trajectory differences
+    (perturbing phi0 by 1e-13 changes the oracle's own tangent by 1.2e-10
+    relative while L changes by 1.9e-14, ratio 6.5e3), so two independent
+    FP64 implementations whose L differ by ~5e-12 agree on the tangent only
+    to that ratio times the primal difference."""
     import oracle as O
     steps = 2000
-    w, g = _full_grid_gradients(steps, (W.F64, W.F32))
+    w, g = _full_grid_gradients(steps, (W.F64,))
     p = w["params"]
+    fd = _fd_golden(steps)
+    v = _band_direction(w["phi0"], p["band"])
     t = O.TangentOracle(p, w["phi0"], dsigma=1.0)
     t.step(steps)
     L_orc, dL_sigma = t.centroid(1)
     L64, ds64, dp64 = g[W.F64]
+    dv64 = float(np.sum(dp64 * v))
     e_L = abs(L64 - L_orc) / abs(L_orc)
     e_sig = abs(ds64 - dL_sigma) / abs(dL_sigma)
-    f_sig = abs(g[W.F32][1] - ds64) / abs(ds64)
-    print("L", L64, L_orc, "rel", e_L, "dL/dsigma", ds64, dL_sigma, "rel", e_sig, "FP32 forward rel", f_sig,
-          flush=True)
+    fd_sig = abs(ds64 - fd["dL_dsigma"]) / abs(fd["dL_dsigma"])
+    fd_v = abs(dv64 - fd["dL_dphi0_dot_v"]) / abs(fd["dL_dphi0_dot_v"])
+    print("L", L64, L_orc, "rel", e_L, "dL/dsigma", ds64, dL_sigma, fd["dL_dsigma"], "tangent rel", e_sig,
+          "FD rel", fd_sig, "<dL/dphi0,v>", dv64, fd["dL_dphi0_dot_v"], "FD rel", fd_v, flush=True)
     assert e_L < 1e-10
+    assert fd_sig < TOL_FD and fd_v < TOL_FD
     assert e_sig < max(TOL_TANGENT, 2 * 6.5e3 * e_L)
-    assert f_sig < 1e-2
+
+
+@pytest.mark.xfail(strict=False, reason="known miss: over 2000 steps the FP32 state's rounding (~1e-7 relative per "
+                   "step) is amplified like any trajectory perturbation (ratio ~6.5e3 on the tangent); measured "
+                   "2.4e-3 for dL/dsigma against the 1e-4 target")
+def test_rising_bubble_2000_steps_fp32_forward_gradient(require_gpu):
+    """FP32 forward state, FP64 adjoint, over the full 2000 steps, against
+    the oracle's finite differences: target 1e-4."""
+    steps = 2000
+    w, g = _full_grid_gradients(steps, (W.F32,))
+    fd = _fd_golden(steps)
+    v = _band_direction(w["phi0"], w["params"]["band"])
+    ds32, dv32 = g[W.F32][1], float(np.sum(g[W.F32][2] * v))
+    e_sig = abs(ds32 - fd["dL_dsigma"]) / abs(fd["dL_dsigma"])
+    e_v = abs(dv32 - fd["dL_dphi0_dot_v"]) / abs(fd["dL_dphi0_dot_v"])
+    print("FP32 forward, 2000 steps: dL/dsigma rel", e_sig, "<dL/dphi0,v> rel", e_v, flush=True)
+    assert e_sig < TOL_FD and e_v < TOL_FD

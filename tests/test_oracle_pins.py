@@ -610,3 +610,46 @@ def test_tangent_matches_central_difference():
     hs = 1e-6 * p["sigma"]
     fd_sig = (centroid(w["phi0"], p["sigma"] + hs) - centroid(w["phi0"], p["sigma"] - hs)) / (2 * hs)
     assert abs(tan - (fd_phi + fd_sig)) < 1e-5 * max(1.0, abs(tan))
+
+
+def test_decision_replay_freezes_the_program():
+    """Decision replay (the frozen-decision program of the reverse mode):
+    a replayed unperturbed run reproduces the recorded one bit for bit; a
+    perturbation that flips decisions in a free run (different decision
+    hashes) keeps every decision of the record when replayed; and the
+    replayed central difference converges to the dual-number tangent where
+    the free-running one does not (its decisions flipped)."""
+    w = W.rising_bubble_2d(nx=48, ny=64, radius=8.0, yc=22.0, g=4e-5, sigma=5e-3, storage=W.F64)
+    p = w["params"]
+    steps = 60
+    base = O.Oracle(p, w["phi0"], record=True)
+    base.step(steps)
+    L0 = base.integrals()["centroid"][1]
+    same = O.Oracle(p, w["phi0"], replay=base)
+    same.step(steps)
+    assert same.integrals()["centroid"][1] == L0 and not same.replay_failed()
+    np.testing.assert_array_equal(same.decisions(), base.decisions())
+    assert len(base.decisions()) == steps + 1
+    sig = p["sigma"]
+    h = 2e-2
+    free = [O.Oracle(dict(p, sigma=sig * (1 + s * h)), w["phi0"]) for s in (1, -1)]
+    rep = [O.Oracle(dict(p, sigma=sig * (1 + s * h)), w["phi0"], replay=base) for s in (1, -1)]
+    for o in free + rep:
+        o.step(steps)
+    assert any((o.decisions() != base.decisions()).any() for o in free)
+    for o in rep:
+        assert not o.replay_failed()
+        np.testing.assert_array_equal(o.decisions(), base.decisions())
+    t = O.TangentOracle(p, w["phi0"], dsigma=1.0)
+    t.step(steps)
+    tan = t.centroid(1)[1]
+    fd_rep = (rep[0].integrals()["centroid"][1] - rep[1].integrals()["centroid"][1]) / (2 * h * sig)
+    fd_free = (free[0].integrals()["centroid"][1] - free[1].integrals()["centroid"][1]) / (2 * h * sig)
+    hs = 1e-5
+    rs = [O.Oracle(dict(p, sigma=sig * (1 + s * hs)), w["phi0"], replay=base) for s in (1, -1)]
+    for o in rs:
+        o.step(steps)
+    fd_small = (rs[0].integrals()["centroid"][1] - rs[1].integrals()["centroid"][1]) / (2 * hs * sig)
+    assert abs(fd_small - tan) < 1e-6 * abs(tan), (fd_small, tan)
+    assert abs(fd_rep - tan) < 1e-2 * abs(tan), (fd_rep, tan)  # O(h^2) of a 2% step
+    print("tangent", tan, "replayed FD", fd_small, fd_rep, "free FD", fd_free)
