@@ -171,6 +171,24 @@ int lsb_get_moments(lsb_plan* plan, double* out, int on_device, void* stream);
 /* Integral quantities, FP64, synchronises the stream. */
 int lsb_get_integrals(lsb_plan* plan, lsb_integrals* out, void* stream);
 
+/* lsb_get_integrals without allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * it): no device or host allocation and no synchronisation; the work is
+ * queued on the stream.  The reduction's partial sums use a static device
+ * array of the library (LSB_INTEGRALS_STATIC_BLOCKS x 16 + 16 doubles,
+ * 64.1 KiB, held on each GPU the library runs on until the process ends)
+ * instead of the workspace, added in the same fixed order, so the values
+ * equal lsb_get_integrals' bit for bit.  out (device, 16 doubles, caller
+ * owned): mass[2], volume_gas, centroid[3], vel_b[3], pb, umax, the number
+ * of cells failing the stability test, 4 zeros.  All calls on one GPU
+ * share the array: calls that overlap on one GPU (concurrent streams or
+ * threads) race.  LSB_EINVAL for a NULL argument or a plan whose reduction
+ * grid exceeds LSB_INTEGRALS_STATIC_BLOCKS (checked before any device
+ * access); LSB_ESTATE before lsb_init; LSB_EDEVICE if the array's device
+ * address cannot be obtained. */
+#define LSB_INTEGRALS_STATIC_BLOCKS 512
+int lsb_get_integrals_static(lsb_plan* plan, double* out, void* stream);
+
 /* Checkpoint / resume: device-to-device copy of the full state into or out
  * of a caller buffer of lsb_state_bytes bytes. */
 int lsb_state_bytes(const lsb_plan* plan, size_t* bytes);

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -441,7 +442,7 @@ int lsb_get_integrals(lsb_plan* p, lsb_integrals* out, void* stream) {
   if (!p || !out) return fail(LSB_EINVAL, "null argument");
   if (!p->inited) return fail(LSB_ESTATE, "no state");
   hipStream_t st = as_stream(stream);
-  p->ops->integrals_partial(p, st);
+  p->ops->integrals_partial(p, nullptr, st);
   LSB_HIP(hipGetLastError());
   std::vector<double> part((size_t)p->red_blocks * 16);
   LSB_HIP(hipMemcpyAsync(part.data(), p->ws + p->off_partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -466,6 +467,87 @@ int lsb_get_integrals(lsb_plan* p, lsb_integrals* out, void* stream) {
   out->umax = umax;
   out->step = p->nstep;
   return LSB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Integrals without allocation (lsb_get_integrals_static).  The reduction's
+// partial sums go to this file-scope device array instead of the plan's
+// workspace: LSB_INTEGRALS_STATIC_BLOCKS blocks of 16 doubles, then 16 for
+// the result.  Each GPU holds its own copy until the process ends; in host
+// code `scratch` is only a symbol, its device address on the current device
+// comes from hipGetSymbolAddress (kept per device).  Every block of the
+// partial kernel writes all the slots that the final kernel reads, so nothing
+// needs clearing between calls.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[LSB_INTEGRALS_STATIC_BLOCKS * 16 + 16];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (looked up once per device)
+int scratch_address(double** out) {
+  int dev = 0;
+  LSB_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(LSB_EDEVICE, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    LSB_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(LSB_EDEVICE, "hipGetSymbolAddress returned no address for the static scratch");
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return LSB_OK;
+}
+
+// The host reduction of lsb_get_integrals on the device: one thread per
+// slot adds the blocks' partial sums in block order (slot 9: maximum), so
+// the result has the same bits; then the derived quantities.
+__global__ void k_integrals_static_final(const double* part, int nblocks, const double* pb, double* res,
+                                         double* out) {
+  const int m = threadIdx.x;
+  if (m < 11) {
+    double v = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+      const double x = part[16 * (size_t)b + m];
+      v = (m == 9) ? (v < x ? x : v) : v + x;  // the host side's std::max(v, x)
+    }
+    res[m] = v;
+  }
+  __syncthreads();
+  if (m == 0) {
+    const double V = res[2];
+    out[0] = res[0];
+    out[1] = res[1];
+    out[2] = V;
+    for (int a = 0; a < 3; ++a) {
+      out[3 + a] = V > 0 ? res[3 + a] / V : 0.0;
+      out[6 + a] = V > 0 ? res[6 + a] / V : 0.0;
+    }
+    out[9] = *pb;
+    out[10] = res[9];
+    out[11] = res[10];
+    for (int k = 12; k < 16; ++k) out[k] = 0.0;
+  }
+}
+}  // namespace
+
+int lsb_get_integrals_static(lsb_plan* p, double* out, void* stream) {
+  if (!p || !out) return fail(LSB_EINVAL, "null argument");
+  if (p->red_blocks > LSB_INTEGRALS_STATIC_BLOCKS)
+    return fail(LSB_EINVAL, "the plan's reduction grid exceeds LSB_INTEGRALS_STATIC_BLOCKS");
+  if (!p->inited) return fail(LSB_ESTATE, "no state");
+  double* s = nullptr;
+  if (int r = scratch_address(&s)) return r;
+  hipStream_t st = as_stream(stream);
+  double* part = s;
+  double* res = s + (size_t)LSB_INTEGRALS_STATIC_BLOCKS * 16;
+  p->ops->integrals_partial(p, part, st);
+  const double* pb = reinterpret_cast<const double*>(p->ws + p->off_scal + lsb::SC_PB * sizeof(double));
+  k_integrals_static_final<<<1, 64, 0, st>>>(part, p->red_blocks, pb, res, out);
+  return check_launch();
 }
 
 // State image: populations, phi, moments, scalars (device) plus a small

@@ -301,8 +301,10 @@ struct Driver {
   static void moments(lsb_plan* p, double* out, int c0, int c1, hipStream_t st) {
     k_export_moments<LAT, ST><<<cell_grid(p), 256, 0, st>>>(args(p, p->cur), out, c0, c1);
   }
-  static void integrals_partial(lsb_plan* p, hipStream_t st) {
-    k_integrals_partial<LAT, ST><<<p->red_blocks, 256, 0, st>>>(args(p, p->cur));
+  static void integrals_partial(lsb_plan* p, double* partial, hipStream_t st) {
+    Args a = args(p, p->cur);
+    if (partial) a.partial = partial;
+    k_integrals_partial<LAT, ST><<<p->red_blocks, 256, 0, st>>>(a);
   }
   // interface records of the current state (read by the next collide-stream)
   static void pack(lsb_plan* p, hipStream_t st) {

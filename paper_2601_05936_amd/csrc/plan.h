@@ -26,7 +26,8 @@ struct Ops {
   void (*populations)(lsb_plan*, double* out, int i0, int i1, int c0, int c1, hipStream_t);
   void (*interface)(lsb_plan*, double* phi, double* nrm, double* kap, uint8_t* tags, int c0, int c1, hipStream_t);
   void (*moments)(lsb_plan*, double* out, int c0, int c1, hipStream_t);
-  void (*integrals_partial)(lsb_plan*, hipStream_t);
+  // partial: 16 doubles per reduction block; nullptr = the workspace's region
+  void (*integrals_partial)(lsb_plan*, double* partial, hipStream_t);
   void (*rebuild)(lsb_plan*, hipStream_t);
   void (*pack)(lsb_plan*, hipStream_t);  // interface records of the current state
 };

@@ -46,7 +46,7 @@ class Integrals(C.Structure):
 
 EXPORTS = [
     "lsb_create", "lsb_destroy", "lsb_workspace_bytes", "lsb_bind", "lsb_init", "lsb_step", "lsb_get_fields",
-    "lsb_get_interface", "lsb_get_bubbles", "lsb_get_populations", "lsb_get_moments", "lsb_get_integrals", "lsb_state_bytes",
+    "lsb_get_interface", "lsb_get_bubbles", "lsb_get_populations", "lsb_get_moments", "lsb_get_integrals", "lsb_get_integrals_static", "lsb_state_bytes",
     "lsb_save_state", "lsb_load_state", "lsb_step_count", "lsb_get_counts", "lsb_set_kernel_timing",
     "lsb_get_kernel_timing", "lsb_set_schedule", "lsb_adjoint_workspace_bytes", "lsb_adjoint_bind",
     "lsb_adjoint_record", "lsb_adjoint_seed_centroid", "lsb_adjoint_reverse", "lsb_adjoint_initial",
@@ -96,6 +96,7 @@ def load() -> C.CDLL:
     lib.lsb_get_populations.argtypes = [vp, vp, C.c_int, vp]
     lib.lsb_get_moments.argtypes = [vp, vp, C.c_int, vp]
     lib.lsb_get_integrals.argtypes = [vp, C.POINTER(Integrals), vp]
+    lib.lsb_get_integrals_static.argtypes = [vp, vp, vp]
     lib.lsb_get_bubbles.argtypes = [vp, C.c_int, C.POINTER(C.c_int), vp, vp, C.c_int, vp]
     lib.lsb_state_bytes.argtypes = [vp, sz]
     lib.lsb_save_state.argtypes = [vp, vp, vp]
@@ -263,6 +264,13 @@ class Sim:
         _check(self.lib.lsb_get_integrals(self.h, C.byref(I), self.stream()))
         return dict(mass=np.array(I.mass[:]), volume_gas=I.volume_gas, centroid=np.array(I.centroid[:]),
                     vel_b=np.array(I.vel_b[:]), pb=I.pb, umax=I.umax, step=I.step)
+
+    def integrals_static(self, out):
+        """lsb_get_integrals_static into `out`, a float64 device tensor of 16
+        values (no allocation in the library, nothing synchronised)."""
+        assert out.dtype == self.torch.float64 and out.is_cuda and out.numel() >= 16 and out.is_contiguous()
+        _check(self.lib.lsb_get_integrals_static(self.h, C.c_void_p(out.data_ptr()), self.stream()))
+        return out
 
     def bubbles(self, labels=False) -> dict:
         """Several-bubble mode (use_pb = 2): per bubble, numbered by its smallest

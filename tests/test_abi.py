@@ -94,6 +94,19 @@ def test_schedule_selection_is_validated():
     lib.lsb_destroy(h)
 
 
+def test_static_integrals_validate_before_device_access():
+    """The no-allocation integrals entry point refuses NULL arguments and a
+    plan without state before touching the device."""
+    p = W.default_params(lattice=W.D2Q9, nx=16, ny=16, nz=1)
+    rc, h = _create(p)
+    assert rc == 0
+    lib = lsb.load()
+    assert lib.lsb_get_integrals_static(None, C.c_void_p(1 << 20), None) == lsb.LSB_EINVAL
+    assert lib.lsb_get_integrals_static(h, None, None) == lsb.LSB_EINVAL
+    assert lib.lsb_get_integrals_static(h, C.c_void_p(1 << 20), None) == lsb.LSB_ESTATE
+    lib.lsb_destroy(h)
+
+
 def test_reverse_mode_rejects_per_bubble_baselines():
     """The reverse mode differentiates one gas baseline (use_pb 0 or 1)."""
     lib = lsb.load()
