@@ -344,6 +344,7 @@ static void cumulant_collide(const Lattice& L, const T* f, double omega1, double
 // phase 1 the gas (phi >= 0).
 // --------------------------------------------------------------------------
 enum { BC_PERIODIC = 0, BC_NOSLIP = 1, BC_FREESLIP = 2 };
+constexpr double BAND_SNAP = 1e-3;  // width of the band edge held at +-B (cells)
 
 struct Params {
   int lattice, storage, nx, ny, nz;
@@ -880,11 +881,17 @@ struct Sim {
     clamp_band();
   }
 
+  // The band's edge is held at exactly +-B: a value beyond B - BAND_SNAP
+  // (in magnitude) is set to +-B (reading: the paper's narrow band has an
+  // edge; holding it exactly keeps sub-rounding drifts of the edge cells,
+  // which a reduced-precision level set cannot follow, out of the
+  // reinitialisation stencils that reach the edge).
   void clamp_band() {
     const double B = P.band;
+    const double Bs = B - BAND_SNAP;
     for (long c = 0; c < N; ++c) {
       if (!is_act(c)) continue;
-      const long cl = decide(c, 4, val(phi[c]) > B ? 1 : (val(phi[c]) < -B ? -1 : 0));
+      const long cl = decide(c, 4, val(phi[c]) > Bs ? 1 : (val(phi[c]) < -Bs ? -1 : 0));
       if (cl > 0) phi[c] = T(B);
       if (cl < 0) phi[c] = T(-B);
     }
@@ -1336,8 +1343,8 @@ struct Sim {
     const double B = P.band;
     for (long c = 0; c < N; ++c) {
       T p = phi0[c];
-      if (val(p) > B) p = T(B);
-      if (val(p) < -B) p = T(-B);
+      if (val(p) > B - BAND_SNAP) p = T(B);
+      if (val(p) < -(B - BAND_SNAP)) p = T(-B);
       phi[c] = p;
     }
     begin_decisions();

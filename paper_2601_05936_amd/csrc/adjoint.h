@@ -70,7 +70,7 @@ struct View {
   int per[3], bcf[6];
   double wall_u[6][3];
   double omega[2], acc[2][3], rho_phys[2], eta[2];
-  double band, ext_dtau, heps, reinit_dtau;
+  double band, band_snap, ext_dtau, heps, reinit_dtau;
 };
 
 constexpr int KSLOT = 3;           // list entries per lane
@@ -454,8 +454,8 @@ __device__ void rk_stage(Acc<R>& A, int c, int stage, Dual* out) {
   else if (stage == 2) o = Dual(0.75) * A.get(AR_PHI0, c) + Dual(0.25) * vv;
   else {
     o = Dual(1.0 / 3.0) * A.get(AR_PHI0, c) + Dual(2.0 / 3.0) * vv;
-    if (o.v > v.band) o = Dual(v.band);
-    if (o.v < -v.band) o = Dual(-v.band);
+    if (o.v > v.band_snap) o = Dual(v.band);
+    if (o.v < -v.band_snap) o = Dual(-v.band);
   }
   out[0] = o;
 }
@@ -543,8 +543,8 @@ __device__ void reinit_stage(Acc<R>& A, int c, int stage, bool last, Dual* out) 
   } else {
     o = Dual(1.0 / 3.0) * A.get(AR_RPHI, c) + Dual(2.0 / 3.0) * vv;
     if (last) {
-      if (o.v > v.band) o = Dual(v.band);
-      if (o.v < -v.band) o = Dual(-v.band);
+      if (o.v > v.band_snap) o = Dual(v.band);
+      if (o.v < -v.band_snap) o = Dual(-v.band);
     }
   }
   out[0] = o;
@@ -1072,7 +1072,7 @@ __global__ __launch_bounds__(256) void k_phi0_grad(const double* phibar, const d
                                                    double* out) {
   for (int c = blockIdx.x * 256 + threadIdx.x; c < N; c += gridDim.x * 256) {
     const double p = phi0[c];
-    out[c] = (p >= -band && p <= band) ? phibar[c] : 0.0;
+    out[c] = (p >= -(band - kBandSnap) && p <= band - kBandSnap) ? phibar[c] : 0.0;
   }
 }
 

@@ -90,6 +90,7 @@ struct AdjDriver {
       for (int m = 0; m < 3; ++m) v.acc[k][m] = (double)a.acc[k][m];
     }
     v.band = (double)a.band;
+    v.band_snap = (double)a.band_snap;
     v.ext_dtau = (double)a.ext_dtau;
     v.reinit_dtau = (double)a.reinit_dtau;
     v.heps = (double)a.heps;

@@ -246,16 +246,13 @@ int lsb_init(lsb_plan* p, const double* phi0, const double* rho0, const double* 
   p->tcur = 0;
   p->nstep = 0;
   LSB_HIP(hipStreamSynchronize(p->side));
+  // stage host arrays through the (not yet used) second population buffer
+  char* stg = p->ws + p->off_A[1];
+  const size_t cap = staging_bytes(p);
   if (on_device) {
     p->ops->init_phi(p, phi0, 0, N, st);
     LSB_HIP(hipGetLastError());
-    p->ops->init_band(p, st);
-    LSB_HIP(hipGetLastError());
-    p->ops->init_pop(p, rho0, u0, 0, N, st);
   } else {
-    // stage host arrays through the (not yet used) second population buffer
-    char* stg = p->ws + p->off_A[1];
-    const size_t cap = staging_bytes(p);
     const int chunk_phi = (int)std::min<size_t>(N, cap / sizeof(double));
     for (int c0 = 0; c0 < N; c0 += chunk_phi) {
       const int c1 = std::min(N, c0 + chunk_phi);
@@ -263,8 +260,15 @@ int lsb_init(lsb_plan* p, const double* phi0, const double* rho0, const double* 
       p->ops->init_phi(p, reinterpret_cast<double*>(stg), c0, c1, st);
       LSB_HIP(hipStreamSynchronize(st));
     }
-    p->ops->init_band(p, st);
-    LSB_HIP(hipGetLastError());
+  }
+  p->ops->init_band(p, st);
+  LSB_HIP(hipGetLastError());
+  auto init_populations = [&]() -> int {
+    if (on_device) {
+      p->ops->init_pop(p, rho0, u0, 0, N, st);
+      LSB_HIP(hipGetLastError());
+      return LSB_OK;
+    }
     const int chunk = (int)std::min<size_t>(N, cap / (4 * sizeof(double)));
     for (int c0 = 0; c0 < N; c0 += chunk) {
       const int c1 = std::min(N, c0 + chunk);
@@ -275,7 +279,35 @@ int lsb_init(lsb_plan* p, const double* phi0, const double* rho0, const double* 
       p->ops->init_pop(p, rho0 ? r : nullptr, u0 ? u : nullptr, c0, c1, st);
       LSB_HIP(hipStreamSynchronize(st));
     }
+    return LSB_OK;
+  };
+  p->rho_ref[0] = p->rho_ref[1] = 1.0;
+  if (int r = init_populations()) return r;
+  if (p->P.storage == LSB_F16DEV || p->P.storage == LSB_BF16DEV) {
+    // The codec's reference density of each phase: its mean initial LB
+    // density (fixed reduction grid, so the value is deterministic); the
+    // populations are initialised again in that frame.
+    p->ops->integrals_partial(p, nullptr, st);
+    LSB_HIP(hipGetLastError());
+    std::vector<double> part((size_t)p->red_blocks * 16);
+    LSB_HIP(hipMemcpyAsync(part.data(), p->ws + p->off_partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    LSB_HIP(hipStreamSynchronize(st));
+    double mass[2] = {0, 0}, cnt[2] = {0, 0};
+    for (int b = 0; b < p->red_blocks; ++b)
+      for (int k = 0; k < 2; ++k) {
+        mass[k] += part[16 * (size_t)b + k];
+        cnt[k] += part[16 * (size_t)b + 11 + k];
+      }
+    for (int k = 0; k < 2; ++k) {
+      const double m = cnt[k] > 0 ? mass[k] / cnt[k] : 1.0;
+      p->rho_ref[k] = (std::isfinite(m) && m > 0) ? m : 1.0;
+    }
+    if (p->rho_ref[0] != 1.0 || p->rho_ref[1] != 1.0)
+      if (int r = init_populations()) return r;
   }
+  // the reference densities travel with the state image (scalar slots)
+  LSB_HIP(hipMemcpyAsync(p->ws + p->off_scal + lsb::SC_RREF * sizeof(double), p->rho_ref, 2 * sizeof(double),
+                         hipMemcpyHostToDevice, st));
   p->ops->pack(p, st);
   LSB_HIP(hipGetLastError());
   LSB_HIP(hipStreamSynchronize(st));
@@ -611,6 +643,10 @@ int lsb_load_state(lsb_plan* p, const void* src, void* stream) {
   LSB_HIP(hipMemcpyAsync(p->ws + p->off_p0, s + o_phi, N * p->bytes_real, hipMemcpyDeviceToDevice, st));
   LSB_HIP(hipMemcpyAsync(p->ws + p->off_M[0], s + o_M, 10 * N * p->bytes_real, hipMemcpyDeviceToDevice, st));
   LSB_HIP(hipMemcpyAsync(p->ws + p->off_scal, s + o_scal, lsb::SC_COUNT * sizeof(double), hipMemcpyDeviceToDevice, st));
+  double rr[2] = {1.0, 1.0};
+  LSB_HIP(hipMemcpyAsync(rr, s + o_scal + lsb::SC_RREF * sizeof(double), sizeof(rr), hipMemcpyDeviceToHost, st));
+  LSB_HIP(hipStreamSynchronize(st));
+  for (int k = 0; k < 2; ++k) p->rho_ref[k] = (std::isfinite(rr[k]) && rr[k] > 0) ? rr[k] : 1.0;
   p->nstep = hdr[1];  // before the rebuild: the candidate flags are kept by step parity
   p->ops->rebuild(p, st);
   p->ops->pack(p, st);

@@ -225,10 +225,18 @@ struct KArgs {
   R iface_inv2etap;   // 1 / (2 eta_p), eta_p the floored divisor of the pressure jump
   R iface_acoef;      // -[eta] / eta_bar
   R band;
+  R band_snap;        // band - kBandSnap: beyond it (in magnitude) phi is held at +-band
   R ext_dtau, reinit_dtau;
   R heps;
   R scale;            // storage scale s
   R inv_scale;        // 1 / s
+  // Reference density of each phase's stored deviations: a population of
+  // phase k is stored as f - w_i rho_ref[k] (FP16 / BF16 storage: the
+  // phase's mean initial LB density; 1 for FP32 / FP64 storage), and the
+  // collide-stream kernels carry deviations in that frame.  rref_m1 =
+  // rho_ref - 1 (exact).
+  R rho_ref[2];
+  R rref_m1[2];
   int use_pb;
   // tiles
   int tdim[3];        // tile extents
@@ -272,7 +280,8 @@ struct KArgs {
 };
 
 // device scalar slots (SC_NBUB: bubbles found, may exceed kMaxBubbles)
-enum { SC_PB = 0, SC_XC0 = 1, SC_XC = 4, SC_V = 7, SC_NBUB = 8, SC_COUNT = 16 };
+// SC_RREF: the codec's reference density of each phase (two slots)
+enum { SC_PB = 0, SC_XC0 = 1, SC_XC = 4, SC_V = 7, SC_NBUB = 8, SC_RREF = 9, SC_COUNT = 16 };
 constexpr int kMaxBubbles = LSB_MAX_BUBBLES;
 constexpr int kBubbleParts = 2048;  // reduction blocks of the per-bubble sums
 // counters: CNT_SPEC, CNT_TILES and CNT_FLIP are cleared before each
@@ -296,6 +305,12 @@ __device__ __forceinline__ V sel6(const V (&v)[6], int i) {
 #define WALLU(a, f, m)                                                                                  \
   ((f) < 3 ? ((f) == 0 ? (a).wall_u[0][m] : ((f) == 1 ? (a).wall_u[1][m] : (a).wall_u[2][m]))           \
            : ((f) == 3 ? (a).wall_u[3][m] : ((f) == 4 ? (a).wall_u[4][m] : (a).wall_u[5][m])))
+
+// Width of the band edge that is held at exactly +-B (cells): level-set
+// values within it of +-B are set to +-B after transport and reinitialisation
+// and at initialisation, so that drifts below a reduced-precision level
+// set's resolution at |phi| = B never reach the reinitialisation stencils.
+constexpr double kBandSnap = 1e-3;
 
 // Level-set stencil coordinate: periodic wrap, or even mirror about a wall face.
 __device__ __forceinline__ int ls_coord(int s, int n, int periodic) {

@@ -46,11 +46,17 @@ struct Driver {
       a.iface_acoef = (R)(-((double)a.eta[1] - (double)a.eta[0]) / eta_bar);
     }
     a.band = (R)P.band;
+    a.band_snap = (R)(P.band - kBandSnap);
     a.ext_dtau = (R)P.ext_dtau;
     a.reinit_dtau = (R)P.reinit_dtau;
     a.heps = (R)P.heaviside_eps;
     a.scale = ST == LSB_F16DEV ? (R)ldexp(1.0, P.fp16_scale_log2) : (R)1;
     a.inv_scale = ST == LSB_F16DEV ? (R)ldexp(1.0, -P.fp16_scale_log2) : (R)1;
+    for (int k = 0; k < 2; ++k) {
+      const bool dev16 = ST == LSB_F16DEV || ST == LSB_BF16DEV;
+      a.rho_ref[k] = dev16 ? (R)p->rho_ref[k] : (R)1;
+      a.rref_m1[k] = (R)((double)a.rho_ref[k] - 1.0);
+    }
     a.use_pb = P.use_pb;
     for (int ax = 0; ax < 3; ++ax) { a.tdim[ax] = p->tdim[ax]; a.ntile[ax] = p->ntile[ax]; }
     a.ntiles = p->ntiles;

@@ -190,7 +190,7 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
     if (L::cy(i) > 0) m1 += df; else if (L::cy(i) < 0) m1 -= df;
     if (L::cz(i) > 0) m2 += df; else if (L::cz(i) < 0) m2 -= df;
   }
-  const R rho = (R)1 + rp;
+  const R rho = sel2(a.rho_ref, k) + rp;  // deviations are carried relative to w rho_ref[k]
   const R inv = (R)1 / rho;
   const R ux = m0 * inv, uy = m1 * inv, uz = m2 * inv;
   const R uu15 = (R)1.5 * (ux * ux + uy * uy + uz * uz);
@@ -204,8 +204,14 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
   bool cum_phase = false;
   if constexpr (LAT == LSB_D3Q27 && CUM) cum_phase = sel2(a.cum, k) != 0;
   if (cum_phase) {
-    R out[Q];
-    cumulant_collide(d, om, out);
+    // the cumulant operator takes deviations from the rest state w_i
+    const R rm1 = sel2(a.rref_m1, k);
+    R da[Q], out[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) da[i] = d[i] + (R)wgt<LAT>(i) * rm1;
+    cumulant_collide(da, om, out);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out[i] = out[i] - (R)wgt<LAT>(i) * rm1;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       R v = out[i];
@@ -271,7 +277,7 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
       if (cy * cz) P5 += (R)(cy * cz) * fn2;
     }
     const R fac = -(R)1.5 * om * inv;  // -omega / (2 rho cs^2)
-    a.Mn[c] = rp;
+    a.Mn[c] = rp + sel2(a.rref_m1, k);  // rho - 1
     a.Mn[N + c] = ux;
     a.Mn[2 * N + c] = uy;
     a.Mn[3 * N + c] = uz;
@@ -826,7 +832,7 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
       m1 += (R)tab<LAT>.cy[i] * f;
       m2 += (R)tab<LAT>.cz[i] * f;
     }
-    const R rho = (R)1 + rp;
+    const R rho = sel2(a.rho_ref, k) + rp;  // deviations relative to w rho_ref[k]
     const R inv = (R)1 / rho;
     const R ux = m0 * inv, uy = m1 * inv, uz = m2 * inv;
     const R uu = ux * ux + uy * uy + uz * uz;
@@ -852,10 +858,14 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
     }
     if constexpr (LAT == LSB_D3Q27 && CUM) {
       if (cum_phase) {
+        // the cumulant operator takes deviations from the rest state w_i
+        const R rm1 = sel2(a.rref_m1, k);
         R dl[Q], out[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) dl[i] = fl[i * 256 + threadIdx.x];
+        for (int i = 0; i < Q; ++i) dl[i] = fl[i * 256 + threadIdx.x] + (R)wgt<LAT>(i) * rm1;
         cumulant_collide(dl, om, out);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) out[i] = out[i] - (R)wgt<LAT>(i) * rm1;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
           using L = typename S::L;
@@ -869,7 +879,7 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
     }
     if (active) {
       const R fac = -(R)1.5 * om * inv;
-      a.Mn[c] = rp;
+      a.Mn[c] = rp + sel2(a.rref_m1, k);  // rho - 1
       a.Mn[N + c] = ux;
       a.Mn[2 * N + c] = uy;
       a.Mn[3 * N + c] = uz;
@@ -1089,8 +1099,9 @@ __global__ __launch_bounds__(256) void k_rk3_stage(const typename Step<LAT, ST>:
     else if (stage == 2) o = (R)0.75 * a.phi[c] + (R)0.25 * v;
     else {
       o = ((R)1 / (R)3) * a.phi[c] + ((R)2 / (R)3) * v;
-      if (o > a.band) o = a.band;
-      if (o < -a.band) o = -a.band;
+      // the band edge is held at exactly +-B (values within the snap width)
+      if (o > a.band_snap) o = a.band;
+      if (o < -a.band_snap) o = -a.band;
     }
     if (act) out[c] = o;
   });
@@ -1195,8 +1206,8 @@ __global__ __launch_bounds__(256) void k_reinit_stage(const typename Step<LAT, S
     else {
       o = ((R)1 / (R)3) * a.phi[c] + ((R)2 / (R)3) * v;
       if (last) {
-        if (o > a.band) o = a.band;
-        if (o < -a.band) o = -a.band;
+        if (o > a.band_snap) o = a.band;
+        if (o < -a.band_snap) o = -a.band;
       }
     }
     out[c] = o;
@@ -1552,6 +1563,7 @@ __global__ __launch_bounds__(256) void k_refill(const typename Step<LAT, ST>::Ar
     const uint8_t t = a.tag[c];
     const int knew = t & T_GAS;
     const int kold = (t & T_OLDGAS) ? 1 : 0;
+    const R rm1_new = sel2(a.rref_m1, knew);
     const R sgn = knew == 1 ? (R)1 : (R)-1;
     const R m0 = sgn * a.G[c], m1 = sgn * a.G[N + c], m2 = sgn * a.G[2 * N + c];
     // candidate directions by alignment with the normal into the new phase
@@ -1664,7 +1676,8 @@ __global__ __launch_bounds__(256) void k_refill(const typename Step<LAT, ST>::Ar
         const R w = (R)wgt<LAT>(k);
         const R cu = (R)L::cx(k) * uG0 + (R)L::cy(k) * uG1 + (R)L::cz(k) * uG2;
         const R de = w * (rhoG + ((R)1 + rhoG) * ((R)3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu));
-        a.An[pidx<LAT>(k, c, N)] = C::enc(de, (R)(1.0 / wgt<LAT>(k)), s);
+        // stored relative to w rho_ref of the new phase
+        a.An[pidx<LAT>(k, c, N)] = C::enc(de - w * rm1_new, (R)(1.0 / wgt<LAT>(k)), s);
       }
       a.Mn[c] = rhoG;
       for (int m = 0; m < 6; ++m) a.Mn[(4 + m) * N + c] = 0;
@@ -1969,8 +1982,8 @@ __global__ __launch_bounds__(256) void k_init_phi(const typename Step<LAT, ST>::
   for (int c = c0 + blockIdx.x * 256 + threadIdx.x; c < c1; c += gridDim.x * 256) {
     double p = phi0[c - c0];
     const double B = (double)a.band;
-    if (p > B) p = B;
-    if (p < -B) p = -B;
+    if (p > B - kBandSnap) p = B;
+    if (p < -(B - kBandSnap)) p = -B;
     const R v = (R)p;
     a.phi[c] = v; a.s1[c] = v; a.s2[c] = v; a.p0[c] = v;
     a.tag[c] = 0;
@@ -2011,7 +2024,8 @@ __global__ __launch_bounds__(256) void k_init_pop(const typename Step<LAT, ST>::
       const double w = wgt<LAT>(i);
       const double cu = L::cx(i) * u[0] + L::cy(i) * u[1] + L::cz(i) * u[2];
       const double fe = w * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-      a.An[pidx<LAT>(i, c, N)] = C::enc((R)(fe - w), (R)(1.0 / w), s);
+      // stored relative to w rho_ref of the cell's phase
+      a.An[pidx<LAT>(i, c, N)] = C::enc((R)(fe - w * (double)sel2(a.rho_ref, k)), (R)(1.0 / w), s);
     }
     R* Ms[2] = {const_cast<R*>(a.M), a.Mn};
     for (int b = 0; b < 2; ++b) {
@@ -2032,15 +2046,16 @@ __global__ __launch_bounds__(256) void k_fields(const typename Step<LAT, ST>::Ar
   using C = typename S::C;
   const R s = a.scale;
   for (int c = c0 + blockIdx.x * 256 + threadIdx.x; c < c1; c += gridDim.x * 256) {
+    const int k = a.tag[c] & T_GAS;
+    const double rref = (double)sel2(a.rho_ref, k);
     double rho = 0, m[3] = {0, 0, 0};
 #pragma unroll
     for (int i = 0; i < S::Q; ++i) {
       const R w = (R)wgt<LAT>(i);
-      const double f = wgt<LAT>(i) + (double)C::dec(a.A[pidx<LAT>(i, c, a.N)], w, a.inv_scale);
+      const double f = wgt<LAT>(i) * rref + (double)C::dec(a.A[pidx<LAT>(i, c, a.N)], w, a.inv_scale);
       rho += f;
       m[0] += L::cx(i) * f; m[1] += L::cy(i) * f; m[2] += L::cz(i) * f;
     }
-    const int k = a.tag[c] & T_GAS;
     const size_t o = (size_t)(c - c0);
     if (rho_out) rho_out[o] = rho;
     if (u_out)
@@ -2058,12 +2073,14 @@ __global__ __launch_bounds__(256) void k_populations(const typename Step<LAT, ST
   using C = typename S::C;
   const R s = a.scale;
   const size_t n = (size_t)(c1 - c0);
-  for (int c = c0 + blockIdx.x * 256 + threadIdx.x; c < c1; c += gridDim.x * 256)
+  for (int c = c0 + blockIdx.x * 256 + threadIdx.x; c < c1; c += gridDim.x * 256) {
+    const double rref = (double)sel2(a.rho_ref, a.tag[c] & T_GAS);
     for (int i = i0; i < i1; ++i) {
       double w = 0;
       for (int k = 0; k < S::Q; ++k) if (k == i) w = wgt<LAT>(k);
-      out[(size_t)(i - i0) * n + (c - c0)] = w + (double)C::dec(a.A[pidx<LAT>(i, c, a.N)], (R)w, a.inv_scale);
+      out[(size_t)(i - i0) * n + (c - c0)] = w * rref + (double)C::dec(a.A[pidx<LAT>(i, c, a.N)], (R)w, a.inv_scale);
     }
+  }
 }
 
 // Integral quantities: per-block partials of mass[2], V, sum x H[3],
@@ -2075,22 +2092,24 @@ __global__ __launch_bounds__(256) void k_integrals_partial(const typename Step<L
   using L = typename S::L;
   using C = typename S::C;
   const R s = a.scale;
-  double v[11] = {0};
+  double v[13] = {0};  // ..., [11], [12]: cells of each phase
   double umax = 0;
   const double eps = (double)a.heps;
   for (int c = blockIdx.x * 256 + threadIdx.x; c < a.N; c += gridDim.x * 256) {
+    const int k = a.tag[c] & T_GAS;
+    const double rref = (double)sel2(a.rho_ref, k);
     double rho = 0, m[3] = {0, 0, 0};
 #pragma unroll
     for (int i = 0; i < S::Q; ++i) {
       const R w = (R)wgt<LAT>(i);
-      const double f = wgt<LAT>(i) + (double)C::dec(a.A[pidx<LAT>(i, c, a.N)], w, a.inv_scale);
+      const double f = wgt<LAT>(i) * rref + (double)C::dec(a.A[pidx<LAT>(i, c, a.N)], w, a.inv_scale);
       rho += f;
       m[0] += L::cx(i) * f; m[1] += L::cy(i) * f; m[2] += L::cz(i) * f;
     }
-    const int k = a.tag[c] & T_GAS;
     double u[3];
     for (int d = 0; d < 3; ++d) u[d] = m[d] / rho - 0.5 * (double)ACC(a, k, d);
     v[k] += rho;
+    v[11 + k] += 1.0;
     const double h = heaviside_d((double)a.phi[c], eps);
     const int x = c % a.nx, y = (c / a.nx) % a.ny, z = c / (a.nx * a.ny);
     v[2] += h;
@@ -2100,7 +2119,7 @@ __global__ __launch_bounds__(256) void k_integrals_partial(const typename Step<L
     if (!(rho > 0.0) || !(un <= 0.3) || !isfinite(rho)) v[10] += 1.0;
     if (un > umax) umax = un;
   }
-  block_sum<11>(v, a.partial + 16 * blockIdx.x);
+  block_sum<13>(v, a.partial + 16 * blockIdx.x);
   // max of |u|
   __shared__ double sh[256];
   sh[threadIdx.x] = umax;

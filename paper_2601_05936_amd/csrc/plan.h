@@ -86,6 +86,7 @@ struct lsb_plan {
   int ntile[3] = {1, 1, 1};
   int ntiles = 0;
   int red_blocks = 512;  // fixed reduction grid (deterministic sums)
+  double rho_ref[2] = {1.0, 1.0};  // the codec's reference density per phase (see KArgs::rho_ref)
   // workspace regions (byte offsets)
   size_t off_A[2], off_phi, off_s1, off_s2, off_p0, off_tag, off_aux, off_M[2], off_G, off_ut[2];
   size_t off_scal, off_cnt, off_tile_act, off_tile_list, off_cand_list, off_spec_list, off_flip_list, off_partial;
