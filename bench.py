@@ -32,10 +32,29 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 # HBM bytes per launch of the bulk collide-stream kernel from rocprofv3
-# FETCH_SIZE / WRITE_SIZE runs, scaled by a plain 4 GiB copy (fetch x2.000,
-# write x1.000); recorded in profiles/k_lb_bulk_wavy512_d3q27_f16dev_hbm_traffic.md.
-# Valid only for that kernel build, storage, schedule and size: null otherwise.
-MEASURED_TRAFFIC = {("f16dev", "serial", 512): 14675680100}
+# FETCH_SIZE / WRITE_SIZE runs, scaled by a plain 4 GiB copy; recorded in
+# profiles/k_lb_bulk_wavy512_d3q27_f16dev_hbm_traffic.md with the hash of the
+# kernel sources they were taken with.  Reported only while the sources hash
+# to the same value (null once any kernel source has changed).
+MEASURED_TRAFFIC = {"sources": None, ("f16dev", "serial", 512): None}
+
+
+def kernel_sources_hash() -> str:
+    """sha256 (first 16 hex digits) of the HIP sources of the library."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2601_05936_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key):
+    if MEASURED_TRAFFIC.get("sources") != kernel_sources_hash():
+        return None
+    return MEASURED_TRAFFIC.get(key)
 
 
 def log(*a):
@@ -77,6 +96,21 @@ def run_mode(size, storage, steps, warmup, schedule, cumulant_gas=False, workloa
     ms = e0.elapsed_time(e1)
     k_ms, k_n = s.kernel_timing()
     s.set_kernel_timing(False)
+    k_ms_sched = k_ms / max(k_n, 1)
+    if schedule:
+        # the bulk kernel alone: a few more steps in the serial schedule (the
+        # schedules give the same state bit for bit, so switching at a step
+        # boundary changes nothing but the timing)
+        from paper_2601_05936_amd.lsb import SCHED_OVERLAP, SCHED_SERIAL
+        s.set_schedule(SCHED_SERIAL)
+        s.step(1)
+        torch.cuda.synchronize()
+        s.set_kernel_timing(True)
+        s.step(max(3, steps // 4))
+        torch.cuda.synchronize()
+        k_ms, k_n = s.kernel_timing()
+        s.set_kernel_timing(False)
+        s.set_schedule(SCHED_OVERLAP)
     counts = s.counts()
     I = s.integrals()
     N = s.N
@@ -86,8 +120,7 @@ def run_mode(size, storage, steps, warmup, schedule, cumulant_gas=False, workloa
     # cells updated by the bulk collide-stream kernel: all but the interface
     # and wall cells (serial) and also all but the LS-active tiles (overlap);
     # in this workload the band (mid-height) and the z walls are disjoint
-    tile_cells = 512 * counts["active_tiles"] if schedule else 0
-    bulk_cells = N - counts["wall_cells"] - (tile_cells if schedule else counts["iface_cells"])
+    bulk_cells = N - counts["wall_cells"] - counts["iface_cells"]  # the serial schedule's bulk kernel
     # algorithmic bytes of one bulk launch: read Q and write Q populations of
     # every bulk cell, read one tag byte per cell
     alg_bytes = bulk_cells * 2 * Q * b + N
@@ -100,6 +133,8 @@ def run_mode(size, storage, steps, warmup, schedule, cumulant_gas=False, workloa
         k1_gbs=achieved,
         k1_frac=achieved / HBM_PEAK_GBS,
         k1_launches=k_n,
+        k1_schedule="serial",
+        k1_ms_in_step_schedule=k_ms_sched,
         alg_bytes_per_launch=alg_bytes,
         bytes_per_cell=2 * Q * b + 1,
         iface_cells=counts["iface_cells"],
@@ -334,13 +369,17 @@ def run_refine_tree(steps: int, warmup: int):
     t0 = time.time()
     for r in range(6):
         nb = g.sensor_seeded(phis[r % 2], 4.0, 6, seeds)
+        if len(nb) != len(g.boxes):
+            raise RuntimeError(f"the seeded sensor merged boxes ({len(nb)} for {len(g.boxes)}): the tree needs rebuilding")
         g.remesh_levels(nb)
+        # the first coarse step after a re-mesh captures the step graphs again
+        g.step(1)
     torch.cuda.synchronize()
-    cycle_ms = (time.time() - t0) / 6 * 1e3
+    cycle_ms = (time.time() - t0) / 6 * 1e3 - ms  # sensor + re-mesh + re-capture, beyond a plain step
     res = dict(workload="D2Q9 refinement tree, 2048^2 coarse, nine 200^2-cell boxes (401^2 nodes each)",
                steps=steps, warmup=warmup, ms_per_step=ms, node_updates_per_step=updates,
                mlups=updates / (ms * 1e-3) / 1e6, gbs=gbs, frac=gbs / HBM_PEAK_GBS, bytes_per_update=144,
-               launches_per_step=1 + 9 * 3, dtype="f64", sensor_remesh_ms=cycle_ms,
+               launches_per_step=1 + 9 * 3, dtype="f64", sensor_remesh_recapture_ms=cycle_ms,
                sensor_remesh_boxes=[list(b) for b in nb])
     log(f"[refine_tree] {res}")
     return res
@@ -458,7 +497,8 @@ def main():
                    "collision": results[head]["collision"]},
         "modes": results,
         "roofline": {"bound": "hbm", "achieved": r["k1_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r["k1_frac"], "traffic": MEASURED_TRAFFIC.get((head, sched_of(head), args.size)),
+                     "frac": r["k1_frac"], "traffic": measured_traffic((head, "serial", args.size)),
+                     "kernel_sources": kernel_sources_hash(),
                      "kernel": "k_lb_bulk (collide-stream, bulk cells)",
                      "bytes_per_cell": r["bytes_per_cell"], "alg_bytes_per_launch": r["alg_bytes_per_launch"],
                      "avg_ms": r["k1_ms"]},

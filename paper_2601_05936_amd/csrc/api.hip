@@ -299,7 +299,9 @@ int lsb_init(lsb_plan* p, const double* phi0, const double* rho0, const double* 
         cnt[k] += part[16 * (size_t)b + 11 + k];
       }
     for (int k = 0; k < 2; ++k) {
-      const double m = cnt[k] > 0 ? mass[k] / cnt[k] : 1.0;
+      // rounded to the FP32 arithmetic of the 16-bit storage modes, so that a
+      // phase at density 1 keeps the frame of the rest state exactly
+      const double m = cnt[k] > 0 ? (double)(float)(mass[k] / cnt[k]) : 1.0;
       p->rho_ref[k] = (std::isfinite(m) && m > 0) ? m : 1.0;
     }
     if (p->rho_ref[0] != 1.0 || p->rho_ref[1] != 1.0)

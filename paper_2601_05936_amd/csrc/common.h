@@ -361,4 +361,19 @@ __device__ __forceinline__ unsigned remap_xcd(unsigned b, unsigned nb) {
   return (b & 7u) * (nb >> 3) + (b >> 3);
 }
 
+// Entries of a list (0 .. n-1) that this thread takes: the list is split
+// into 8 contiguous parts, one per XCD (workgroups are dispatched round-robin
+// over the XCDs), each part strided over that XCD's blocks, so that list
+// neighbours (cells of one tile batch, a run of one wall plane) share one L2.
+struct ListSpan {
+  int e, end, stride;
+};
+__device__ __forceinline__ ListSpan xcd_list_span(int n) {
+  if ((gridDim.x & 7u) != 0u) return {(int)(blockIdx.x * 256u + threadIdx.x), n, (int)(gridDim.x * 256u)};
+  const int xcd = (int)(blockIdx.x & 7u), j = (int)(blockIdx.x >> 3);
+  const int per = (n + 7) >> 3;
+  const int lo = xcd * per;
+  return {lo + j * 256 + (int)threadIdx.x, min(n, lo + per), (int)(gridDim.x >> 3) * 256};
+}
+
 }  // namespace lsb

@@ -190,6 +190,29 @@ struct Driver {
     else k_lb_bulk<LAT, ST, SPLIT, false, false><<<g, 256, dyn, st>>>(a, xchunks);
   }
 
+  // wall-adjacent cells: the two z planes streamed (k_lb_zwall) where the
+  // only walls are no-slip z faces and rows are whole chunks, else the list
+  static void walls(lsb_plan* p, const Args& a, bool cum, bool force, hipStream_t st) {
+    if (p->n_wall_cells <= 0) return;
+    if constexpr (LAT != LSB_D2Q9) {
+      const int xchunks = a.nx / 256;
+      if (a.per[0] && a.per[1] && !a.per[2] && a.bcf[4] == LSB_NOSLIP && a.bcf[5] == LSB_NOSLIP &&
+          xchunks * 256 == a.nx) {
+        const unsigned g = (unsigned)(xchunks * 2 * a.ny);
+        if (cum) {
+          if (force) k_lb_zwall<LAT, ST, true, true><<<g, 256, 0, st>>>(a, xchunks);
+          else k_lb_zwall<LAT, ST, false, true><<<g, 256, 0, st>>>(a, xchunks);
+        } else {
+          if (force) k_lb_zwall<LAT, ST, true, false><<<g, 256, 0, st>>>(a, xchunks);
+          else k_lb_zwall<LAT, ST, false, false><<<g, 256, 0, st>>>(a, xchunks);
+        }
+        return;
+      }
+    }
+    if (cum) k_lb_wall<LAT, ST, true><<<p->grid_walls, 256, 0, st>>>(a);
+    else k_lb_wall<LAT, ST, false><<<p->grid_walls, 256, 0, st>>>(a);
+  }
+
   // copy of a step intermediate into the snapshot slot being recorded
   static void rec(lsb_plan* p, size_t off, const void* src, size_t bytes, hipStream_t st) {
     char* d = p->adj.ws + p->adj.o_snap + (size_t)p->adj.rec_slot * p->adj.stride + off;
@@ -234,13 +257,9 @@ struct Driver {
     // current LS-active tiles); their flags bound the next bulk part
     k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a, CNT_CAND, 1);
     k_dilate<LAT, ST><<<(p->ntiles + 255) / 256, 256, 0, st>>>(a, 0);
-    if (cum) {
-      k_lb_iface<LAT, ST, true><<<p->grid_cells, 256, 0, st>>>(a);
-      if (p->n_wall_cells > 0) k_lb_wall<LAT, ST, true><<<p->grid_walls, 256, 0, st>>>(a);
-    } else {
-      k_lb_iface<LAT, ST, false><<<p->grid_cells, 256, 0, st>>>(a);
-      if (p->n_wall_cells > 0) k_lb_wall<LAT, ST, false><<<p->grid_walls, 256, 0, st>>>(a);
-    }
+    if (cum) k_lb_iface<LAT, ST, true><<<p->grid_cells, 256, 0, st>>>(a);
+    else k_lb_iface<LAT, ST, false><<<p->grid_cells, 256, 0, st>>>(a);
+    walls(p, a, cum, force, st);
     (void)hipEventRecord(p->ev_pop_done, st);
     const bool recording = p->adj.rec_slot >= 0;
     const size_t rb = sizeof(R), N = (size_t)p->N;

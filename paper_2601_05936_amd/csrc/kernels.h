@@ -517,11 +517,55 @@ __global__ __launch_bounds__(256) void k_lb_band(const typename Step<LAT, ST>::A
   });
 }
 
+// The two wall planes of no-slip z faces when x and y are periodic and rows
+// are whole 256-cell chunks (3D): streamed like the bulk, one 256-cell row
+// chunk per block, with halfway bounce-back plus the moving-wall term on the
+// links through the face (the pulls of k_lb_wall's wall_pull for this case).
+// Skips interface-adjacent cells (k_lb_iface takes their wall links).
+template <int LAT, int ST, bool FORCE, bool CUM>
+__global__ __launch_bounds__(256) void k_lb_zwall(const typename Step<LAT, ST>::Args a, int xchunks) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  using T = typename S::T;
+  using L = typename S::L;
+  using C = typename S::C;
+  constexpr int Q = S::Q;
+  const unsigned b = remap_xcd(blockIdx.x, gridDim.x);
+  const int row = (int)(b / (unsigned)xchunks);  // 0 .. 2 ny - 1: bottom plane, then top
+  const int x = (int)(b - (unsigned)row * xchunks) * 256 + (int)threadIdx.x;
+  const bool top = row >= a.ny;
+  const int y = top ? row - a.ny : row;
+  const int z = top ? a.nz - 1 : 0;
+  const int c = (z * a.ny + y) * a.nx + x;
+  const uint8_t t = a.tag[c];
+  if (t & T_SPEC) return;
+  const int face = top ? 5 : 4;
+  const R uw[3] = {WALLU(a, face, 0), WALLU(a, face, 1), WALLU(a, face, 2)};
+  const int xs[3] = {x + 1 == a.nx ? 0 : x + 1, x, x == 0 ? a.nx - 1 : x - 1};
+  const int ys[3] = {y + 1 == a.ny ? 0 : y + 1, y, y == 0 ? a.ny - 1 : y - 1};
+  const int zs[3] = {z + 1, z, z - 1};  // the one beyond the face is not read
+  const R is = a.inv_scale;
+  R d[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cz = L::cz(i);
+    // through the face: the source z - cz lies outside [0, nz)
+    const bool wall = top ? (cz < 0) : (cz > 0);
+    const int src = wall ? c : (zs[cz + 1] * a.ny + ys[L::cy(i) + 1]) * a.nx + xs[L::cx(i) + 1];
+    const int dir = wall ? opp<LAT>(i) : i;
+    const T v = a.A[pop_dir<LAT>(dir, a.N) + pop_cell<LAT>(src)];
+    R di = C::dec(v, (R)wgt<LAT>(i), is);
+    if (wall) di += (R)6 * (R)wgt<LAT>(i) * ((R)L::cx(i) * uw[0] + (R)L::cy(i) * uw[1] + (R)cz * uw[2]);
+    d[i] = di;
+  }
+  collide_store<LAT, ST, FORCE, CUM>(a, c, t & T_GAS, (t & T_ACT) != 0, d);
+}
+
 // Wall-adjacent cells (static list), except interface-adjacent ones.
 template <int LAT, int ST, bool CUM>
 __global__ __launch_bounds__(256) void k_lb_wall(const typename Step<LAT, ST>::Args a) {
-  const int n = a.counters[CNT_WALL];
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+  const ListSpan sp = xcd_list_span(a.counters[CNT_WALL]);
+  for (int e = sp.e; e < sp.end; e += sp.stride) {
     const int c = a.wall_list[e];
     const uint8_t t = a.tag[c];
     if (t & T_SPEC) continue;
@@ -754,7 +798,8 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
   const R s = a.scale;
   const size_t N = a.N;
   __shared__ R fl[Q * 256];
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+  const ListSpan sp = xcd_list_span(n);
+  for (int e = sp.e; e < sp.end; e += sp.stride) {
     const int c = a.spec_list[e];
     const int x = c % a.nx;
     const int y = (c / a.nx) % a.ny;
@@ -898,9 +943,9 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
 template <int LAT, int ST>
 __global__ __launch_bounds__(256) void k_pack_iface(const typename Step<LAT, ST>::Args a) {
   using R = typename Step<LAT, ST>::R;
-  const int n = a.counters[CNT_SPEC];
   const size_t N = a.N;
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+  const ListSpan sp = xcd_list_span(a.counters[CNT_SPEC]);
+  for (int e = sp.e; e < sp.end; e += sp.stride) {
     const int c = a.spec_list[e];
     IfaceRec<R> r;
     r.v[0] = a.phi[c];
@@ -971,8 +1016,8 @@ __global__ __launch_bounds__(256) void k_ext_seed_iface(const typename Step<LAT,
   using R = typename S::R;
   using L = typename S::L;
   const size_t N = a.N;
-  const int n = a.counters[CNT_SPEC];
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+  const ListSpan sp = xcd_list_span(a.counters[CNT_SPEC]);
+  for (int e = sp.e; e < sp.end; e += sp.stride) {
     const int c = a.spec_list[e];
     const int x = c % a.nx;
     const int y = (c / a.nx) % a.ny;
@@ -1554,9 +1599,9 @@ __global__ __launch_bounds__(256) void k_refill(const typename Step<LAT, ST>::Ar
   using C = typename S::C;
   constexpr int Q = S::Q;
   const size_t N = a.N;
-  const int n = a.counters[CNT_FLIP];
   const R s = a.scale;
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+  const ListSpan sp = xcd_list_span(a.counters[CNT_FLIP]);
+  for (int e = sp.e; e < sp.end; e += sp.stride) {
     const int c = a.flip_list[e];
     const R pb = (R)baseline(a, c);
     const int x = c % a.nx, y = (c / a.nx) % a.ny, z = c / (a.nx * a.ny);
