@@ -130,22 +130,27 @@ int lsb_bind(lsb_plan* plan, void* device_workspace, size_t bytes);
 int lsb_init(lsb_plan* plan, const double* phi0, const double* rho0, const double* u0, int on_device,
              void* stream);
 
-/* Advance nsteps time steps (collide-stream with wall and interface
- * bounce-back, extension, advection, periodic reinitialisation,
- * classification, geometry, refill, centroid and pressure baseline).
+/* Advance nsteps time steps (Sec. 2: the collide-stream of each phase,
+ * Eq. 1 with the BGK or cumulant operator and the body force, with wall
+ * bounce-back, eq:bb, and interface bounce-back, eq:bb_cc with the stress
+ * jump eq:Sdecomp; Sec. 2.2: velocity extension, eq:hyperbolicExtension,
+ * transport of the level set and periodic reinitialisation; Sec. 2.4:
+ * classification and refill of cells whose phase changed; Sec. 3.2: gas
+ * centroid and pressure baseline).
  * If check_every > 0, every check_every steps the stream is synchronised and
  * LSB_EUNSTABLE returned on a non-finite or non-positive density or
  * |u| > 0.3.  LSB_ESTATE before lsb_init. */
 int lsb_step(lsb_plan* plan, int nsteps, int check_every, void* stream);
 
-/* Macroscopic fields: rho [N] (sum of populations), u [N*d] (d = 2 or 3,
+/* Macroscopic fields (Sec. 2.1, eq:macro): rho [N] (sum of populations), u [N*d] (d = 2 or 3,
  * interleaved per cell; time-centred velocity sum(c f)/rho - a/2), p [N]
  * (phase pressure rho_phys cs^2 (rho - 1), plus the baseline in the gas),
  * phase [N] (0 liquid, 1 gas).  Any pointer may be NULL. */
 int lsb_get_fields(lsb_plan* plan, double* rho, double* u, double* p, uint8_t* phase, int on_device,
                    void* stream);
 
-/* Interface description: phi [N], normal [N*d], kappa [N] (valid on
+/* Interface description (Sec. 2.2: the level set, its normal and its
+ * curvature kappa = div n): phi [N], normal [N*d], kappa [N] (valid on
  * LS-active cells), tags [N] (bit0 gas, bit1 LS-active, bit2 has a lattice
  * link to the other phase).  Any pointer may be NULL. */
 int lsb_get_interface(lsb_plan* plan, double* phi, double* normal, double* kappa, uint8_t* tags,
@@ -161,14 +166,18 @@ int lsb_get_interface(lsb_plan* plan, double* phi, double* normal, double* kappa
  * found (the baselines of the rest are missing; *count holds the number). */
 int lsb_get_bubbles(lsb_plan* plan, int max, int* count, double* out, int32_t* labels, int on_device, void* stream);
 
-/* Decoded populations A[i*N + cell] (post-collision, FP64). */
+/* Decoded populations A[i*N + cell] (post-collision, FP64; Eq. 1, the
+ * paper's direction order with the rest direction last). */
 int lsb_get_populations(lsb_plan* plan, double* out, int on_device, void* stream);
 
-/* Moments of the last collision per cell, [N][10] = (rho, u[3], S[6] with
+/* Moments of the last collision per cell (the inputs of the interface
+ * coupling, Sec. 2.3), [N][10] = (rho, u[3], S[6] with
  * S = xx, yy, zz, xy, xz, yz); valid on LS-active cells. */
 int lsb_get_moments(lsb_plan* plan, double* out, int on_device, void* stream);
 
-/* Integral quantities, FP64, synchronises the stream. */
+/* Integral quantities (Sec. 3.2: per-phase mass, gas volume, centroid and
+ * bubble velocity with the smoothed Heaviside, the gas pressure baseline,
+ * max |u|), FP64, synchronises the stream. */
 int lsb_get_integrals(lsb_plan* plan, lsb_integrals* out, void* stream);
 
 /* lsb_get_integrals without allocation, for callers that cannot allocate

@@ -3,13 +3,14 @@
 // per velocity set.
 //
 // Data layout in HBM (structure of arrays, cell index c = (z*ny + y)*nx + x):
-//   A[i][c]     populations as deviations from the rest state (codec ST)
+//   A[i][c]     populations as deviations from w_i rho_ref of the cell's
+//               phase (codec ST; 3D: chunks of 256 cells, [c/256][i][c%256])
 //   phi[c]      level set; s1/s2 Runge-Kutta stages; p0 reinit reference
 //   tag[c]      bit field (T_* in common.h)
 //   M[m][c]     rho, u[3], S[6] of the last collision (LS-active cells)
 //   G[m][c]     normal[3], curvature (LS-active cells)
 //   ut[a][c]    extension velocity
-// The level-set kernels run over a compact list of 8x8x8 (3D) or 16x16 (2D)
+// The level-set kernels run over a compact list of 32x4x4 (3D) or 16x16 (2D)
 // tiles that hold LS-active cells, with a fixed grid that strides over the
 // device-resident tile count.
 #pragma once

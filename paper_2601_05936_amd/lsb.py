@@ -306,7 +306,8 @@ class Sim:
         _check(self.lib.lsb_get_kernel_timing(self.h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
-    # -- reverse mode (D2Q9, F64/F32 storage, no reinitialisation) ---------
+    # -- reverse mode (D2Q9, F64/F32 storage; the reinitialisation is
+    # differentiated too, with its branches frozen) ----------------------
     def adjoint_bind(self, max_segment_steps: int):
         nb = C.c_size_t()
         _check(self.lib.lsb_adjoint_workspace_bytes(self.h, int(max_segment_steps), C.byref(nb)))
