@@ -5,4 +5,4 @@ of the benchmark may use it; the product path never does.
 """
 from .oracle import Oracle, TangentOracle, lattice, feq, refill_weights, heaviside, geometry, \
     advect_rate, advect, reinit, extend, build, LIB_PATH, cumulants_points, moments_from_cumulants, \
-    cumulant_collide, RefineOracle, refill  # noqa: F401
+    cumulant_collide, RefineOracle, refill, TwoPhaseRefineOracle  # noqa: F401

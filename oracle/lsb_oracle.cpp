@@ -26,7 +26,10 @@
 //             (radiation theorem).
 //   Sec. 2.4  refilling of newly activated cells (e_min, f^neq copy,
 //             quadratic extrapolation of rho and u).
-//   Sec. 3.2  Heaviside-weighted gas centroid and bubble velocity.
+//   Sec. 3.2  Heaviside-weighted gas centroid and bubble velocity; the
+//             interface kept on the finest level of a two-level grid
+//             (with the Sec. 2.1 refinement: lattice units and relaxation
+//             time rescaled, Dupuis-Chopard coupling of the levels).
 // Where the paper is silent or garbled, the reading taken is stated at the
 // place it is used; the same readings are listed in the repository's design
 // notes.
@@ -344,6 +347,10 @@ static void cumulant_collide(const Lattice& L, const T* f, double omega1, double
 // phase 1 the gas (phi >= 0).
 // --------------------------------------------------------------------------
 enum { BC_PERIODIC = 0, BC_NOSLIP = 1, BC_FREESLIP = 2 };
+// A face of a refined box: beyond it lies the coarser grid, which supplies
+// the populations that cross the face (Sim::ghost); only the refinement
+// driver below creates it.
+constexpr int BC_INJECT = 3;
 constexpr double BAND_SNAP = 1e-3;  // width of the band edge held at +-B (cells)
 
 struct Params {
@@ -402,6 +409,7 @@ struct Sim {
   std::vector<T> Mr1, Mu1, MS1;         // the ones being written this step
   std::vector<T> nrm, kap;              // interface normal and curvature (LS-active cells)
   std::vector<T> ut, ut2;               // extension velocity
+  std::vector<T> ghost;                 // [i*N + cell]: populations crossing an injected face
   T sig, Pb;
   // several bubbles (use_pb = 2): component of each cell in the support of
   // the smoothed Heaviside (-1 outside), the baseline of each cell's
@@ -674,6 +682,9 @@ struct Sim {
       cross[a] = true; face[a] = (s[a] < 0) ? 2 * a : 2 * a + 1; any = true;
     }
     if (any) {
+      // Across the face of a refined box: the coarser grid's population.
+      for (int a = 0; a < 3; ++a)
+        if (cross[a] && P.bc[face[a]] == BC_INJECT) return ghost[(size_t)i * N + c];
       // Walls lie on cell faces: halfway bounce-back (q = 1/2) with the
       // moving-wall term of Sec. 2.1 for no-slip faces, specular reflection
       // for free-slip faces.  A link crossing any no-slip face is no-slip.
@@ -1403,6 +1414,289 @@ struct Sim {
   }
 };
 
+
+// --------------------------------------------------------------------------
+// Two-level refinement of the two-phase step (Sec. 2.1, refinement
+// paragraph; Sec. 3.2, adaptive refinement with the interface on the finest
+// level, the same level on both of its sides).  Reading (the paper gives
+// the coupling of its grid levels only as Dupuis-Chopard interpolation in
+// space and time with the collision frequency adapted per level):
+//
+//   levels   a periodic coarse grid of nodes (I, J, K) in coarse lattice
+//            units, and one box [ia, ib] x [ja, jb] (x [ka, kb]) of its
+//            nodes refined at ratio 2 (fine node (i, j, k) at (ia + i/2,
+//            ...)), node-centred as the single-phase refinement.
+//   fine     the whole two-phase step (collide-stream with wall and
+//            interface bounce-back, level set, refill, baseline) on the box's
+//            nodes in fine lattice units: tau_f = 2 tau_c - 1/2 per phase
+//            (the viscosity of each phase on both levels), sigma_f = 2
+//            sigma_c, a_f = a_c / 2 (dt_f = dx_f = half the coarse ones);
+//            pressures and velocities are the same numbers on both levels.
+//            The band and the level set live on the fine level only: the box
+//            must hold the interface with its band and 3 fine cells to
+//            spare (the step refuses otherwise).
+//   coarse   every uncovered node is in one phase for good (the interface
+//            never leaves the box): pull (periodic), BGK with that phase's
+//            tau_c and body force; perimeter nodes keep their pre-collision
+//            sets G (t + 1).
+//   inject   the fine box's faces are injected faces: a fine node pulls a
+//            population from outside the box as the Dupuis-Chopard value
+//            of the single-phase refinement, the coarse sets interpolated in
+//            time ((G(t) + G(t+1))/2 for the first sub-step, G(t+1) for the
+//            second) and space (mean of the 2 or 4 coarse nodes beside an
+//            odd fine coordinate), the non-equilibrium part about the
+//            equilibrium of the interpolated moments scaled by
+//            tau_f,k / (2 tau_c,k) of the node's phase k, plus one fine
+//            step of body force.  With the first-order force a pre-collision
+//            set lags the physical time by one step of its own level, half a
+//            coarse step more on the coarse grid than on the fine level;
+//            the fine force closes that gap (the initial coarse set is the
+//            initial state less one coarse step of force).
+//   restrict after the second sub-step, only the covered coarse nodes
+//            next to the perimeter (the only ones the coarse step reads)
+//            take the fine node's state: its pre-collision populations of
+//            that sub-step (pulled again from the fine state before it; the
+//            node is a bulk node of one phase) less one fine step of force,
+//            f, e = f_eq(moments of f), the coarse post-collision
+//            populations e + 2 (tau_c,k - 1) / tau_f,k (f - e) + the coarse
+//            body force.
+// --------------------------------------------------------------------------
+struct TwoPhaseRef {
+  Params Pc;             // coarse parameters (coarse lattice units)
+  Lattice L;
+  int D = 2, Q = 9;
+  int n[3] = {1, 1, 1};  // coarse nodes per axis
+  int box[6] = {0, 0, 0, 0, 0, 0};
+  double omega_c[2], tau_c[2], tau_f[2];
+  std::vector<double> fc;            // coarse post-collision populations [q][node]
+  std::vector<unsigned char> kc;     // coarse node phase
+  std::vector<double> g0, g1;        // coarse pre-collision sets over the box nodes
+  Sim<double>* fine = nullptr;
+  long nstep = 0;
+
+  ~TwoPhaseRef() { delete fine; }
+  long nc() const { return (long)n[0] * n[1] * n[2]; }
+  long cidx(int I, int J, int K) const { return ((long)K * n[1] + J) * n[0] + I; }
+  int bext(int a) const { return box[2 * a + 1] - box[2 * a] + 1; }
+  long nbox() const { return (long)bext(0) * bext(1) * (D == 3 ? bext(2) : 1); }
+  long bidx(int I, int J, int K) const {
+    return ((long)(D == 3 ? K - box[4] : 0) * bext(1) + (J - box[2])) * bext(0) + (I - box[0]);
+  }
+  bool covered(int I, int J, int K) const {
+    return I > box[0] && I < box[1] && J > box[2] && J < box[3] && (D == 2 || (K > box[4] && K < box[5]));
+  }
+  bool in_box(int I, int J, int K) const {
+    return I >= box[0] && I <= box[1] && J >= box[2] && J <= box[3] && (D == 2 || (K >= box[4] && K <= box[5]));
+  }
+  bool perimeter(int I, int J, int K) const { return in_box(I, J, K) && !covered(I, J, K); }
+  // covered and next to the perimeter: the nodes the coarse step reads
+  bool inner_ring(int I, int J, int K) const {
+    if (!covered(I, J, K)) return false;
+    bool r = I == box[0] + 1 || I == box[1] - 1 || J == box[2] + 1 || J == box[3] - 1;
+    if (D == 3) r = r || K == box[4] + 1 || K == box[5] - 1;
+    return r;
+  }
+
+  void moments(const double* f, double& rho, double u[3]) const {
+    rho = 0.0;
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < Q; ++q) {
+      rho += f[q];
+      for (int a = 0; a < 3; ++a) m[a] += (double)L.c[q][a] * f[q];
+    }
+    for (int a = 0; a < 3; ++a) u[a] = m[a] / rho;
+  }
+  void force(int k, double rho, const double* acc, double* F) const {
+    for (int q = 0; q < Q; ++q) {
+      double ca = 0.0;
+      for (int a = 0; a < 3; ++a) ca += (double)L.c[q][a] * acc[a];
+      F[q] = L.w[q] * rho * ca / CS2;
+    }
+  }
+
+  // coarse parameters Pc (bc all periodic), box in coarse nodes
+  bool create(const Params& p, const int* b) {
+    Pc = p;
+    L = make_lattice(p.lattice);
+    D = L.D;
+    Q = L.Q;
+    n[0] = p.nx; n[1] = p.ny; n[2] = p.nz;
+    for (int a = 0; a < 6; ++a) box[a] = (a < 2 * D) ? b[a] : 0;
+    for (int a = 0; a < D; ++a)
+      if (box[2 * a] < 1 || box[2 * a + 1] > n[a] - 2 || box[2 * a + 1] - box[2 * a] < 4) return false;
+    for (int k = 0; k < 2; ++k) {
+      tau_c[k] = p.tau[k];
+      omega_c[k] = 1.0 / tau_c[k];
+      tau_f[k] = 2.0 * tau_c[k] - 0.5;
+    }
+    Params pf = p;
+    pf.nx = 2 * (box[1] - box[0]) + 1;
+    pf.ny = 2 * (box[3] - box[2]) + 1;
+    pf.nz = D == 3 ? 2 * (box[5] - box[4]) + 1 : 1;
+    for (int a = 0; a < 6; ++a) pf.bc[a] = (a < 2 * D) ? BC_INJECT : BC_PERIODIC;
+    for (int k = 0; k < 2; ++k) {
+      pf.tau[k] = tau_f[k];
+      for (int a = 0; a < 3; ++a) pf.accel[k][a] = 0.5 * p.accel[k][a];
+    }
+    pf.sigma = 2.0 * p.sigma;
+    pf.init_hydrostatic = 0;
+    fine = new Sim<double>(pf);
+    fine->ghost.assign((size_t)Q * fine->N, 0.0);
+    return true;
+  }
+
+  // equilibrium initial state on both levels from the caller's fields at
+  // the coarse nodes (phi_c, rho_c, u_c) and at the fine nodes (phi_f,
+  // rho_f, u_f); u arrays hold 3 components per node
+  void init(const double* phi_c, const double* rho_c, const double* u_c, const double* phi_f, const double* rho_f,
+            const double* u_f) {
+    const long N = nc();
+    fc.assign((size_t)Q * N, 0.0);
+    kc.assign(N, 0);
+    double e[27];
+    for (long c = 0; c < N; ++c) {
+      kc[c] = phi_c[c] >= 0.0 ? 1 : 0;
+      double u[3] = {u_c[3 * c], u_c[3 * c + 1], u_c[3 * c + 2]};
+      equilibrium(L, rho_c[c], u, e);
+      for (int q = 0; q < Q; ++q) fc[(size_t)q * N + c] = e[q];
+    }
+    fine->init(phi_f, rho_f, u_f);
+    g0.assign((size_t)Q * nbox(), 0.0);
+    g1 = g0;
+    for (int K = box[4]; K <= (D == 3 ? box[5] : 0); ++K)
+      for (int J = box[2]; J <= box[3]; ++J)
+        for (int I = box[0]; I <= box[1]; ++I)
+          if (perimeter(I, J, K)) {
+            // the pre-collision set one coarse step before the start: the
+            // initial state less one step of body force
+            const long c = cidx(I, J, K);
+            double rho = 0.0, F[27];
+            for (int q = 0; q < Q; ++q) rho += fc[(size_t)q * N + c];
+            force(kc[c], rho, Pc.accel[kc[c]], F);
+            for (int q = 0; q < Q; ++q) g0[(size_t)q * nbox() + bidx(I, J, K)] = fc[(size_t)q * N + c] - F[q];
+          }
+    nstep = 0;
+  }
+
+  // coarse step: uncovered nodes pull, keep G at the perimeter, collide
+  std::vector<double> coarse_step() {
+    const long N = nc();
+    std::vector<double> out = fc;
+    for (int K = 0; K < n[2]; ++K)
+      for (int J = 0; J < n[1]; ++J)
+        for (int I = 0; I < n[0]; ++I) {
+          if (covered(I, J, K)) continue;
+          const long c = cidx(I, J, K);
+          double f[27], e[27], F[27];
+          for (int q = 0; q < Q; ++q) {
+            const int si = (I - L.c[q][0] + n[0]) % n[0], sj = (J - L.c[q][1] + n[1]) % n[1];
+            const int sk = (K - L.c[q][2] + n[2]) % n[2];
+            f[q] = fc[(size_t)q * N + cidx(si, sj, sk)];
+          }
+          if (perimeter(I, J, K))
+            for (int q = 0; q < Q; ++q) g1[(size_t)q * nbox() + bidx(I, J, K)] = f[q];
+          const int k = kc[c];
+          double rho, u[3];
+          moments(f, rho, u);
+          equilibrium(L, rho, u, e);
+          force(k, rho, Pc.accel[k], F);
+          for (int q = 0; q < Q; ++q) out[(size_t)q * N + c] = f[q] - omega_c[k] * (f[q] - e[q]) + F[q];
+        }
+    return out;
+  }
+
+  // the populations entering the fine box across its faces, for a sub-step
+  // with time weights a (G(t)) and b (G(t+1))
+  void inject(double a, double b) {
+    Sim<double>& s = *fine;
+    const int m[3] = {s.nx - 1, s.ny - 1, s.nz - 1};
+    for (long c = 0; c < s.N; ++c) {
+      int i, j, k;
+      s.coords(c, i, j, k);
+      const bool surf = i == 0 || i == m[0] || j == 0 || j == m[1] || (D == 3 && (k == 0 || k == m[2]));
+      if (!surf) continue;
+      double H[27] = {0.0}, eh[27], rho, u[3];
+      const int o[3] = {i & 1, j & 1, D == 3 ? (k & 1) : 0};
+      const double w = (o[0] ? 0.5 : 1.0) * (o[1] ? 0.5 : 1.0) * (o[2] ? 0.5 : 1.0);
+      for (int dz = 0; dz <= o[2]; ++dz)
+        for (int dy = 0; dy <= o[1]; ++dy)
+          for (int dx = 0; dx <= o[0]; ++dx) {
+            const long bx = bidx(box[0] + (i - o[0]) / 2 + dx, box[2] + (j - o[1]) / 2 + dy,
+                                 (D == 3 ? box[4] + (k - o[2]) / 2 + dz : 0));
+            for (int q = 0; q < Q; ++q)
+              H[q] += w * (a * g0[(size_t)q * nbox() + bx] + b * g1[(size_t)q * nbox() + bx]);
+          }
+      moments(H, rho, u);
+      equilibrium(L, rho, u, eh);
+      const int ph = s.gas[c];
+      const double r = tau_f[ph] / (2.0 * tau_c[ph]);
+      double Ff[27];
+      force(ph, rho, s.P.accel[ph], Ff);
+      for (int q = 0; q < Q; ++q) {
+        const int si = i - L.c[q][0], sj = j - L.c[q][1], sk = k - L.c[q][2];
+        const bool out = si < 0 || si > m[0] || sj < 0 || sj > m[1] || (D == 3 && (sk < 0 || sk > m[2]));
+        if (out) s.ghost[(size_t)q * s.N + c] = eh[q] + r * (H[q] - eh[q]) + Ff[q];
+      }
+    }
+  }
+
+  // restriction of the inner ring from the fine state (see above); prev is
+  // the fine post-collision state before the second sub-step
+  void restrict_into(std::vector<double>& out, const std::vector<double>& prev) {
+    Sim<double>& s = *fine;
+    const long N = nc();
+    for (int K = box[4]; K <= (D == 3 ? box[5] : 0); ++K)
+      for (int J = box[2]; J <= box[3]; ++J)
+        for (int I = box[0]; I <= box[1]; ++I) {
+          if (!inner_ring(I, J, K)) continue;
+          const int fi = 2 * (I - box[0]), fj = 2 * (J - box[2]), fk = D == 3 ? 2 * (K - box[4]) : 0;
+          const long fcell = s.idx(fi, fj, fk);
+          double f[27], e[27], F[27], rho, u[3];
+          const int k = s.gas[fcell];
+          double Ff[27], rf = 0.0;
+          for (int q = 0; q < Q; ++q) {
+            f[q] = prev[(size_t)q * s.N + s.idx(fi - L.c[q][0], fj - L.c[q][1], fk - L.c[q][2])];
+            rf += f[q];
+          }
+          force(k, rf, s.P.accel[k], Ff);
+          for (int q = 0; q < Q; ++q) f[q] -= Ff[q];  // back to the coarse pre-collision time
+          moments(f, rho, u);
+          equilibrium(L, rho, u, e);
+          force(k, rho, Pc.accel[k], F);
+          const long c = cidx(I, J, K);
+          kc[c] = (unsigned char)k;
+          for (int q = 0; q < Q; ++q)
+            out[(size_t)q * N + c] = e[q] + 2.0 * (tau_c[k] - 1.0) / tau_f[k] * (f[q] - e[q]) + F[q];
+        }
+  }
+
+  // the band keeps 3 fine cells away from the box faces
+  bool band_inside() const {
+    const Sim<double>& s = *fine;
+    const int m[3] = {s.nx - 1, s.ny - 1, s.nz - 1};
+    for (long c = 0; c < s.N; ++c) {
+      if (!s.act[c]) continue;
+      int i, j, k;
+      s.coords(c, i, j, k);
+      if (i < 3 || i > m[0] - 3 || j < 3 || j > m[1] - 3 || (D == 3 && (k < 3 || k > m[2] - 3))) return false;
+    }
+    return true;
+  }
+
+  bool step() {
+    std::vector<double> out = coarse_step();
+    inject(0.5, 0.5);
+    fine->step();
+    inject(0.0, 1.0);
+    fine->step();
+    restrict_into(out, fine->An);  // after the swap, An holds the state before the second sub-step
+    fc.swap(out);
+    g0.swap(g1);
+    ++nstep;
+    return band_inside();
+  }
+};
+
 }  // namespace orc
 
 // ==========================================================================
@@ -1747,6 +2041,48 @@ int orc_refill(const orc::Params* p, const double* phi_new, const unsigned char*
   for (long c = 0; c < 6 * s.N; ++c) S[c] = s.MS1[c];
   return 0;
 }
+
+// ---- two-level refinement of the two-phase step ---------------------------
+// p: coarse parameters (all faces periodic), box: 6 ints in coarse nodes.
+void* orc_r2_create(const orc::Params* p, const int* box) {
+  if (check_params(p)) return nullptr;
+  for (int a = 0; a < 6; ++a)
+    if (p->bc[a] != orc::BC_PERIODIC) return nullptr;
+  orc::TwoPhaseRef* r = new orc::TwoPhaseRef();
+  if (!r->create(*p, box)) {
+    delete r;
+    return nullptr;
+  }
+  return r;
+}
+void orc_r2_destroy(void* h) { delete static_cast<orc::TwoPhaseRef*>(h); }
+// fine-level node counts per axis
+void orc_r2_fine_shape(void* h, int* nf) {
+  orc::TwoPhaseRef* r = static_cast<orc::TwoPhaseRef*>(h);
+  nf[0] = r->fine->nx; nf[1] = r->fine->ny; nf[2] = r->fine->nz;
+}
+int orc_r2_init(void* h, const double* phi_c, const double* rho_c, const double* u_c, const double* phi_f,
+                const double* rho_f, const double* u_f) {
+  static_cast<orc::TwoPhaseRef*>(h)->init(phi_c, rho_c, u_c, phi_f, rho_f, u_f);
+  return 0;
+}
+// -2 when the band came within 3 fine cells of the box faces
+int orc_r2_step(void* h, int nsteps) {
+  orc::TwoPhaseRef* r = static_cast<orc::TwoPhaseRef*>(h);
+  for (int s = 0; s < nsteps; ++s)
+    if (!r->step()) return -2;
+  return 0;
+}
+// coarse populations [q][node] (covered nodes: the last restriction or the
+// initial state), coarse phase [node]; either may be NULL
+int orc_r2_get_coarse(void* h, double* pop, unsigned char* phase) {
+  orc::TwoPhaseRef* r = static_cast<orc::TwoPhaseRef*>(h);
+  if (pop) std::memcpy(pop, r->fc.data(), sizeof(double) * r->fc.size());
+  if (phase) std::memcpy(phase, r->kc.data(), r->kc.size());
+  return 0;
+}
+// the fine level as an oracle simulation (populations, fields, interface, integrals)
+void* orc_r2_fine(void* h) { return static_cast<orc::TwoPhaseRef*>(h)->fine; }
 
 // ---- tangent (forward mode, frozen decisions) ---------------------------
 // Seeds: dphi0 (N values, may be null) and dsigma.  Output: the tangent of

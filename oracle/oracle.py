@@ -87,6 +87,15 @@ def _load():
     lib.orc_get_pop.argtypes = [C.c_void_p, dp]
     lib.orc_set_decisions.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
     lib.orc_replay_failed.argtypes = [C.c_void_p]
+    lib.orc_r2_create.restype = C.c_void_p
+    lib.orc_r2_create.argtypes = [P, C.POINTER(C.c_int)]
+    lib.orc_r2_destroy.argtypes = [C.c_void_p]
+    lib.orc_r2_fine_shape.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
+    lib.orc_r2_init.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, dp]
+    lib.orc_r2_step.argtypes = [C.c_void_p, C.c_int]
+    lib.orc_r2_get_coarse.argtypes = [C.c_void_p, dp, C.POINTER(C.c_ubyte)]
+    lib.orc_r2_fine.restype = C.c_void_p
+    lib.orc_r2_fine.argtypes = [C.c_void_p]
     lib.orc_decisions.restype = C.c_long
     lib.orc_decisions.argtypes = [C.c_void_p, C.POINTER(C.c_uint64), C.c_long]
     lib.orc_get_sample.argtypes = [C.c_void_p, C.POINTER(C.c_long), C.c_int, dp, dp, C.POINTER(C.c_ubyte)]
@@ -288,6 +297,59 @@ def refill(p: dict, phi_new, old_gas, pop, rho, u, S=None, pb: float = 0.0):
     return pop.reshape(-1, N), rho, u.reshape(N, 3), S.reshape(N, 6)
 
 
+class TwoPhaseRefineOracle:
+    """Two-level refinement of the two-phase step (oracle): a periodic coarse
+    grid (params in coarse lattice units) with one box (6 ints, coarse
+    nodes) refined at ratio 2 that holds the interface and its band.  The
+    fine level is an Oracle view in fine lattice units (self.fine)."""
+
+    def __init__(self, params: dict, box):
+        self.lib = _load()
+        self.p = dict(params)
+        self._cp = _params(self.p)
+        b = (tuple(int(v) for v in box) + (0, 0))[:6]
+        self.box = b
+        self.h = self.lib.orc_r2_create(C.byref(self._cp), (C.c_int * 6)(*b))
+        if not self.h:
+            raise ValueError("refinement oracle rejected the parameters or the box")
+        nf = (C.c_int * 3)()
+        self.lib.orc_r2_fine_shape(self.h, nf)
+        self.fine_shape = (nf[2], nf[1], nf[0])
+        pf = dict(self.p, nx=nf[0], ny=nf[1], nz=nf[2], tau=[2 * t - 0.5 for t in self.p["tau"]],
+                  sigma=2 * self.p["sigma"], accel=[[0.5 * a for a in ac] for ac in self.p["accel"]])
+        self.fine = Oracle._view(self.lib, self.lib.orc_r2_fine(self.h), pf, self)
+        self.Q = self.fine.Q
+        self.coarse_shape = (self.p["nz"], self.p["ny"], self.p["nx"])
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.orc_r2_destroy(self.h)
+            self.h = None
+
+    def init(self, phi_c, rho_c, u_c, phi_f, rho_f, u_f):
+        nc = int(np.prod(self.coarse_shape))
+        nf = int(np.prod(self.fine_shape))
+        self._keep = [_f64(phi_c, nc), _f64(rho_c, nc), _f64(u_c, 3 * nc), _f64(phi_f, nf), _f64(rho_f, nf),
+                      _f64(u_f, 3 * nf)]
+        assert self.lib.orc_r2_init(self.h, *[_dp(a) for a in self._keep]) == 0
+        return self
+
+    def step(self, n: int = 1):
+        rc = self.lib.orc_r2_step(self.h, int(n))
+        if rc == -2:
+            raise RuntimeError("the level-set band reached the refined box's faces")
+        assert rc == 0
+        return self
+
+    def coarse(self):
+        """(populations [Q][nz][ny][nx], phase [nz][ny][nx]) of the coarse grid."""
+        nc = int(np.prod(self.coarse_shape))
+        pop = np.zeros(self.Q * nc)
+        ph = np.zeros(nc, dtype=np.uint8)
+        self.lib.orc_r2_get_coarse(self.h, _dp(pop), ph.ctypes.data_as(C.POINTER(C.c_ubyte)))
+        return pop.reshape((self.Q,) + self.coarse_shape), ph.reshape(self.coarse_shape)
+
+
 class Oracle:
     """One oracle simulation (FP64)."""
 
@@ -320,9 +382,20 @@ class Oracle:
         return bool(self.lib.orc_replay_failed(self.h))
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and not getattr(self, "_borrowed", False):
             self.lib.orc_destroy(self.h)
-            self.h = None
+        self.h = None
+
+    @classmethod
+    def _view(cls, lib, handle, params, owner):
+        """An Oracle over a simulation owned by another object (no init)."""
+        o = cls.__new__(cls)
+        o.lib, o.h, o.p, o._borrowed, o._owner = lib, handle, dict(params), True, owner
+        o._cp = _params(o.p)
+        o.N = _ncell(o.p)
+        o.shape = (o.p["nz"], o.p["ny"], o.p["nx"])
+        o.D, o.Q = lattice(o.p["lattice"])[:2]
+        return o
 
     def step(self, n: int = 1):
         assert self.lib.orc_step(self.h, int(n)) == 0
