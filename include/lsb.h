@@ -36,7 +36,10 @@
 extern "C" {
 #endif
 
-enum { LSB_OK = 0, LSB_EINVAL = -1, LSB_ENOMEM = -2, LSB_EDEVICE = -3, LSB_ESTATE = -4, LSB_EUNSTABLE = -5 };
+/* Status codes.  LSB_EBAND: a refined box no longer holds the level-set
+ * band with its margin (lsb_refine2.h). */
+enum { LSB_OK = 0, LSB_EINVAL = -1, LSB_ENOMEM = -2, LSB_EDEVICE = -3, LSB_ESTATE = -4, LSB_EUNSTABLE = -5,
+       LSB_EBAND = -6 };
 
 /* Velocity sets (Sec. 2.1 velocity-set figure; D3Q19 is the textbook subset
  * made of the D3Q27 directions 0..17 plus rest). */

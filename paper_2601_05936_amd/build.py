@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblsb.so")
-SOURCES = ["api.hip", "lsb_d2q9.hip", "lsb_d3q19.hip", "lsb_d3q27.hip", "refine.hip"]
+SOURCES = ["api.hip", "lsb_d2q9.hip", "lsb_d3q19.hip", "lsb_d3q27.hip", "refine.hip", "refine2.hip"]
 ARCH = os.environ.get("LSB_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -78,7 +78,10 @@ extern "C" {
 
 const char* lsb_last_error(void) { return g_err.c_str(); }
 
-int lsb_create(const lsb_params* P, lsb_plan** out) {
+int lsb_create(const lsb_params* P, lsb_plan** out) { return lsb::create_plan(P, false, out); }
+}  // extern "C"
+
+int lsb::create_plan(const lsb_params* P, bool allow_inject, lsb_plan** out) {
   if (!P || !out) return fail(LSB_EINVAL, "null argument");
   *out = nullptr;
   if (P->lattice < LSB_D2Q9 || P->lattice > LSB_D3Q27) return fail(LSB_EINVAL, "unknown lattice");
@@ -89,7 +92,9 @@ int lsb_create(const lsb_params* P, lsb_plan** out) {
   if ((double)P->nx * P->ny * P->nz > 2147483647.0 / 2) return fail(LSB_EINVAL, "grid too large for 32-bit cell indices");
   for (int a = 0; a < 3; ++a) {
     for (int s = 0; s < 2; ++s)
-      if (P->bc[2 * a + s] < LSB_PERIODIC || P->bc[2 * a + s] > LSB_FREESLIP) return fail(LSB_EINVAL, "unknown face condition");
+      if ((P->bc[2 * a + s] < LSB_PERIODIC || P->bc[2 * a + s] > LSB_FREESLIP) &&
+          !(allow_inject && P->bc[2 * a + s] == lsb::kFaceInject))
+        return fail(LSB_EINVAL, "unknown face condition");
     if ((P->bc[2 * a] == LSB_PERIODIC) != (P->bc[2 * a + 1] == LSB_PERIODIC))
       return fail(LSB_EINVAL, "paired faces must both be periodic or both walls");
   }
@@ -196,10 +201,17 @@ int lsb_create(const lsb_params* P, lsb_plan** out) {
     p->grid_walls = (int)std::max<long>(1, std::min<long>((nw + 255) / 256, 4096));
     p->off_wall_list = take((size_t)(nw + 1) * sizeof(int));
   }
+  {
+    bool inject = false;
+    for (int f = 0; f < 6; ++f) inject = inject || P->bc[f] == lsb::kFaceInject;
+    p->off_ghost = take(inject ? (size_t)p->Q * N * p->bytes_real : 0);
+  }
   p->total = o;
   *out = p;
   return LSB_OK;
 }
+
+extern "C" {
 
 void lsb_destroy(lsb_plan* p) {
   if (!p) return;

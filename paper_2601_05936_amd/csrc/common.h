@@ -277,6 +277,7 @@ struct KArgs {
   int* flip_list;           // cells whose phase changed
   int* wall_list;           // cells with a link through a wall face
   double* partial;          // reduction partials
+  const R* ghost;           // populations entering across injected faces [Q][N] (kFaceInject)
 };
 
 // device scalar slots (SC_NBUB: bubbles found, may exceed kMaxBubbles)
@@ -311,6 +312,12 @@ __device__ __forceinline__ V sel6(const V (&v)[6], int i) {
 // and at initialisation, so that drifts below a reduced-precision level
 // set's resolution at |phi| = B never reach the reinitialisation stencils.
 constexpr double kBandSnap = 1e-3;
+
+// Face condition of a refined box's faces (internal; never accepted from a
+// caller's lsb_params): a population whose source lies beyond the face is
+// read from the ghost array the coarser grid fills, ghost[i N + c] (FP64 or
+// FP32 like the moments, the deviation f - w_i rho_ref of the cell's phase).
+constexpr int kFaceInject = 3;
 
 // Level-set stencil coordinate: periodic wrap, or even mirror about a wall face.
 __device__ __forceinline__ int ls_coord(int s, int n, int periodic) {

@@ -93,6 +93,7 @@ struct Driver {
     a.flip_list = reinterpret_cast<int*>(w + p->off_flip_list);
     a.wall_list = reinterpret_cast<int*>(w + p->off_wall_list);
     a.partial = reinterpret_cast<double*>(w + p->off_partial);
+    a.ghost = reinterpret_cast<const R*>(w + p->off_ghost);
     return a;
   }
 

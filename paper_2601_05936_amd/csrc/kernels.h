@@ -171,7 +171,6 @@ __device__ __forceinline__ void collide_store(const typename Step<LAT, ST>::Args
                                               typename Step<LAT, ST>::R* d) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
-  using T = typename S::T;
   using L = typename S::L;
   using C = typename S::C;
   constexpr int Q = S::Q;
@@ -324,6 +323,10 @@ __device__ __forceinline__ typename Step<LAT, ST>::R wall_pull(const typename St
   const R s = a.scale;
   const int j = opp<LAT>(i);
   const R wj = (R)wgt<LAT>(j);
+  // across the face of a refined box: the coarser grid's population
+  for (int ax = 0; ax < 3; ++ax)
+    if ((mask & (1 << ax)) && sel6(a.bcf, 2 * ax + (pos[ax] - cc[ax] < 0 ? 0 : 1)) == kFaceInject)
+      return a.ghost[(size_t)i * a.N + c];
   for (int ax = 0; ax < 3; ++ax) {
     if (!(mask & (1 << ax))) continue;
     const int face = 2 * ax + (pos[ax] - cc[ax] < 0 ? 0 : 1);
@@ -766,6 +769,9 @@ __device__ __forceinline__ typename Step<LAT, ST>::R pull_general(const typename
       src[ax] = sv3[ax] < 0 ? pos[ax] : sv3[ax];
       rc[ax] = sv3[ax] < 0 ? -cc[ax] : cc[ax];
     }
+    for (int ax = 0; ax < 3; ++ax)
+      if (sv3[ax] < 0 && sel6(a.bcf, 2 * ax + (pos[ax] - cc[ax] < 0 ? 0 : 1)) == kFaceInject)
+        return a.ghost[(size_t)i * a.N + c];
     for (int ax = 0; ax < 3; ++ax) {
       if (sv3[ax] >= 0) continue;
       const int face = 2 * ax + (pos[ax] - cc[ax] < 0 ? 0 : 1);

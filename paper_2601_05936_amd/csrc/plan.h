@@ -69,6 +69,8 @@ const Ops* ops_d3q19(int storage);
 const Ops* ops_d3q27(int storage);
 
 void set_error(const std::string& msg);
+// lsb_create, also accepting kFaceInject faces (a refined box's level)
+int create_plan(const lsb_params* P, bool allow_inject, lsb_plan** out);
 // events around the dominant kernel (no-ops unless timing is enabled)
 void timing_begin(lsb_plan* p, hipStream_t st);
 void timing_end(lsb_plan* p, hipStream_t st);
@@ -91,6 +93,7 @@ struct lsb_plan {
   size_t off_A[2], off_phi, off_s1, off_s2, off_p0, off_tag, off_aux, off_M[2], off_G, off_ut[2];
   size_t off_scal, off_cnt, off_tile_act, off_tile_list, off_cand_list, off_spec_list, off_flip_list, off_partial;
   size_t off_wall_list;
+  size_t off_ghost = 0;    // injected-face populations [Q][N] (a refined box's level only)
   size_t off_ext_k;        // extension coefficients of the current step
   size_t off_irec;         // packed interface records [N][16]
   size_t off_blab = 0, off_broots = 0, off_bpart = 0, off_bres = 0, off_pbc = 0;  // several bubbles

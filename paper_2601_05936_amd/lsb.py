@@ -1,7 +1,7 @@
 """Thin Python binding of liblsb.so (argument marshalling only).
 
 Every step of the method runs in the HIP kernels behind the C ABI of
-include/lsb.h and include/lsb_refine.h; this module only converts parameters, hands over torch device
+include/lsb.h, include/lsb_refine.h and include/lsb_refine2.h; this module only converts parameters, hands over torch device
 memory (the caller-owned workspace) and stream handles, and wraps results.
 It fails loudly when the built library is missing: there is no fallback.
 """
@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblsb.so")
 
-LSB_OK, LSB_EINVAL, LSB_ENOMEM, LSB_EDEVICE, LSB_ESTATE, LSB_EUNSTABLE = 0, -1, -2, -3, -4, -5
+LSB_OK, LSB_EINVAL, LSB_ENOMEM, LSB_EDEVICE, LSB_ESTATE, LSB_EUNSTABLE, LSB_EBAND = 0, -1, -2, -3, -4, -5, -6
 D2Q9, D3Q19, D3Q27 = 0, 1, 2
 F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
 
@@ -55,6 +55,8 @@ EXPORTS = [
     "lsb_ref_get_populations", "lsb_ref_sensor", "lsb_ref_remesh", "lsb_ref_init_levels", "lsb_ref_get_level",
     "lsb_ref_sensor_levels", "lsb_ref_remesh_levels", "lsb_ref_create_tree", "lsb_ref_set_graphs",
     "lsb_ref_sensor_seeded",
+    "lsb_ref2_create", "lsb_ref2_destroy", "lsb_ref2_workspace_bytes", "lsb_ref2_bind", "lsb_ref2_fine_shape",
+    "lsb_ref2_fine", "lsb_ref2_init", "lsb_ref2_step", "lsb_ref2_step_count", "lsb_ref2_get_coarse",
 ]
 
 
@@ -133,6 +135,18 @@ def load() -> C.CDLL:
     lib.lsb_ref_set_graphs.argtypes = [vp, C.c_int]
     lib.lsb_ref_sensor_seeded.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_int),
                                           C.POINTER(C.c_int), C.POINTER(C.c_int), vp]
+    lib.lsb_ref2_create.argtypes = [P, C.POINTER(C.c_int), C.POINTER(vp)]
+    lib.lsb_ref2_destroy.argtypes = [vp]
+    lib.lsb_ref2_destroy.restype = None
+    lib.lsb_ref2_workspace_bytes.argtypes = [vp, sz]
+    lib.lsb_ref2_bind.argtypes = [vp, vp, C.c_size_t]
+    lib.lsb_ref2_fine_shape.argtypes = [vp, C.POINTER(C.c_int)]
+    lib.lsb_ref2_fine.argtypes = [vp, C.POINTER(vp)]
+    lib.lsb_ref2_init.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.lsb_ref2_step.argtypes = [vp, C.c_int, vp]
+    lib.lsb_ref2_step_count.argtypes = [vp]
+    lib.lsb_ref2_step_count.restype = C.c_long
+    lib.lsb_ref2_get_coarse.argtypes = [vp, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -192,7 +206,27 @@ class Sim:
         self.Q = {D2Q9: 9, D3Q19: 19, D3Q27: 27}[self.p["lattice"]]
         self.shape = (self.p["nz"], self.p["ny"], self.p["nx"])
 
+    @classmethod
+    def _view(cls, handle: C.c_void_p, params: dict, owner, device):
+        """A Sim over a plan owned by another handle (owner keeps it alive;
+        the view never destroys it)."""
+        import torch
+        s = cls.__new__(cls)
+        s.torch = torch
+        s.lib = load()
+        s.p = dict(params)
+        s.device = torch.device(device)
+        s.h = handle
+        s._owner = owner
+        s.N = s.p["nx"] * s.p["ny"] * s.p["nz"]
+        s.D = 2 if s.p["lattice"] == D2Q9 else 3
+        s.Q = {D2Q9: 9, D3Q19: 19, D3Q27: 27}[s.p["lattice"]]
+        s.shape = (s.p["nz"], s.p["ny"], s.p["nx"])
+        return s
+
     def __del__(self):
+        if getattr(self, "_owner", None) is not None:
+            return
         if getattr(self, "h", None) is not None and self.h.value:
             self.lib.lsb_destroy(self.h)
             self.h = None
@@ -532,3 +566,87 @@ class Refine:
     def populations(self, as_numpy=True):
         """Every level's post-collision populations, coarse first."""
         return tuple(self.level(l, as_numpy) for l in range(self.levels))
+
+
+class TwoPhaseRefine:
+    """The two-phase step on a two-level grid (include/lsb_refine2.h): a
+    periodic coarse grid (params, coarse lattice units, each phase's BGK
+    step) and one refined box over the coarse nodes box = (ia, ib, ja, jb[,
+    ka, kb]) running the whole two-phase step at half spacing.  Device
+    memory is a torch uint8 tensor (the caller-owned workspace); calls run
+    on torch's current stream.  `fine` is a Sim view of the fine level (fine
+    lattice units) for the queries."""
+
+    def __init__(self, params: dict, box, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.p = dict(params)
+        self.device = torch.device(device)
+        self.D = 2 if self.p["lattice"] == D2Q9 else 3
+        self.Q = {D2Q9: 9, D3Q19: 19, D3Q27: 27}[self.p["lattice"]]
+        self.box = (tuple(int(v) for v in box) + (0, 0))[:6]
+        self._cp = to_params(self.p)
+        h = C.c_void_p()
+        _check(self.lib.lsb_ref2_create(C.byref(self._cp), (C.c_int * 6)(*self.box), C.byref(h)))
+        self.h = h
+        nb = C.c_size_t()
+        _check(self.lib.lsb_ref2_workspace_bytes(self.h, C.byref(nb)))
+        self.workspace_bytes = nb.value
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        _check(self.lib.lsb_ref2_bind(self.h, C.c_void_p(self.ws.data_ptr()), nb.value))
+        sh = (C.c_int * 3)()
+        _check(self.lib.lsb_ref2_fine_shape(self.h, sh))
+        fx, fy, fz = sh[0], sh[1], sh[2]
+        self.fine_shape = (fz, fy, fx)
+        self.coarse_shape = (self.p["nz"], self.p["ny"], self.p["nx"])
+        self.n_coarse = self.p["nx"] * self.p["ny"] * self.p["nz"]
+        self.n_fine = fx * fy * fz
+        fp = dict(self.p, nx=fx, ny=fy, nz=fz, sigma=2.0 * self.p["sigma"],
+                  tau=[2.0 * t - 0.5 for t in self.p["tau"]],
+                  accel=[[0.5 * v for v in a] for a in self.p["accel"]])
+        fh = C.c_void_p()
+        _check(self.lib.lsb_ref2_fine(self.h, C.byref(fh)))
+        self.fine = Sim._view(fh, fp, self, device)
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.lsb_ref2_destroy(self.h)
+            self.h = None
+
+    def stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _dev(self, a, n):
+        t = self.torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)) if isinstance(a, np.ndarray) \
+            else a.reshape(-1).to(self.torch.float64)
+        assert t.numel() == n, (t.numel(), n)
+        return t.to(self.device).contiguous()
+
+    def init(self, phi_c, rho_c, u_c, phi_f, rho_f, u_f):
+        """Coarse phi, rho [n_coarse] and u [n_coarse, 3]; fine phi (in fine
+        cells), rho [n_fine] and u [n_fine, 3] (numpy or torch)."""
+        nc, nf = self.n_coarse, self.n_fine
+        t = [self._dev(phi_c, nc), self._dev(rho_c, nc), self._dev(u_c, 3 * nc),
+             self._dev(phi_f, nf), self._dev(rho_f, nf), self._dev(u_f, 3 * nf)]
+        _check(self.lib.lsb_ref2_init(self.h, *[C.c_void_p(x.data_ptr()) for x in t], self.stream()))
+        self.torch.cuda.current_stream(self.device).synchronize()
+        return self
+
+    def step(self, n: int = 1):
+        _check(self.lib.lsb_ref2_step(self.h, int(n), self.stream()))
+        return self
+
+    @property
+    def nstep(self) -> int:
+        return self.lib.lsb_ref2_step_count(self.h)
+
+    def coarse(self, as_numpy=True):
+        """(populations [Q, nz, ny, nx], phases [nz, ny, nx]) of the coarse grid."""
+        t = self.torch
+        pop = t.empty(self.Q * self.n_coarse, dtype=t.float64, device=self.device)
+        ph = t.empty(self.n_coarse, dtype=t.uint8, device=self.device)
+        _check(self.lib.lsb_ref2_get_coarse(self.h, C.c_void_p(pop.data_ptr()), C.c_void_p(ph.data_ptr()),
+                                            self.stream()))
+        pop, ph = pop.view((self.Q,) + self.coarse_shape), ph.view(self.coarse_shape)
+        return (pop.cpu().numpy(), ph.cpu().numpy()) if as_numpy else (pop, ph)

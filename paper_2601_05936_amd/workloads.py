@@ -275,3 +275,60 @@ def seeded_bubble(seed: int, lattice=D2Q9, shape=(37, 29, 1), storage=F64, gas_i
     rho0 = 1.0 + 0.01 * rng.standard_normal((nz, ny, nx)) * 0.1
     return dict(params=p, phi0=phi, rho0=rho0, u0=u0, steps=30,
                 name=f"seeded bubble seed={seed} lattice={lattice} {nx}x{ny}x{nz}")
+
+
+# ---------------------------------------------------------------------------
+# Two-level grids (the interface on the finest level).
+# ---------------------------------------------------------------------------
+
+def two_level_bubble(lattice=D2Q9, n=(48, 48, 1), box=(10, 38, 10, 38), centre=None, radius=7.0, gas_inside=True,
+                     rho_ratio=10.0, tau=(0.8, 0.8), sigma=1e-2, g=0.0, u_amp=0.0, seed=0, storage=F64,
+                     reinit_every=10, n_reinit=3):
+    """A circle or sphere of radius R (coarse cells) in a periodic coarse
+    grid of n nodes, held on the fine level of the box (ia, ib, ja, jb[, ka,
+    kb]) of coarse nodes.  Coarse node (I, J, K) sits at (I, J, K), fine node
+    (i, j, k) at (ia + i/2, ja + j/2, ka + k/2); phi is the signed distance
+    (gas >= 0) in each level's cells.  Density 1 everywhere; the velocity is
+    zero or a seeded sum of smooth periodic modes of amplitude u_amp, the
+    same function on both levels; gravity g along -y (2D) or -z (3D) with
+    the gas pressure baseline of the bubble."""
+    nx, ny, nz = n
+    dim = 2 if lattice == D2Q9 else 3
+    b = (tuple(int(v) for v in box) + (0, 0))[:6]
+    if centre is None:
+        centre = (0.5 * (b[0] + b[1]), 0.5 * (b[2] + b[3]), 0.5 * (b[4] + b[5]) if dim == 3 else 0.0)
+    rho = [1.0, 1.0 / rho_ratio]
+    acc = [0.0, -g, 0.0] if dim == 2 else [0.0, 0.0, -g]
+    p = default_params(lattice=lattice, storage=storage, nx=nx, ny=ny, nz=nz, bc=[PERIODIC] * 6, rho_phys=rho,
+                       tau=list(tau), sigma=sigma, accel=[list(acc), list(acc)],
+                       reinit_every=reinit_every, n_reinit=n_reinit)
+    if g != 0.0:
+        p.update(use_pb=1, pb0=sigma * (1.0 if dim == 2 else 2.0) / radius)
+    rng = np.random.default_rng(seed)
+    modes = []
+    if u_amp:
+        for a in range(dim):
+            for _ in range(3):
+                kx, ky = rng.integers(1, 3, size=2)
+                kz = int(rng.integers(0, 2)) if dim == 3 else 0
+                modes.append((a, kx, ky, kz, rng.uniform(0, 2 * np.pi)))
+
+    def fields(x, y, z, scale):
+        d2 = (x - centre[0]) ** 2 + (y - centre[1]) ** 2 + ((z - centre[2]) ** 2 if dim == 3 else 0.0)
+        dist = np.sqrt(d2)
+        phi = scale * ((radius - dist) if gas_inside else (dist - radius))
+        u = np.zeros(x.shape + (3,))
+        for a, kx, ky, kz, ph in modes:
+            u[..., a] += u_amp / 3 * np.sin(2 * np.pi * (kx * x / nx + ky * y / ny + kz * z / nz) + ph)
+        return phi.reshape(-1), np.ones(x.size), u.reshape(-1, 3)
+
+    K, J, I = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    phi_c, rho_c, u_c = fields(1.0 * I, 1.0 * J, 1.0 * K, 1.0)
+    fx, fy = 2 * (b[1] - b[0]) + 1, 2 * (b[3] - b[2]) + 1
+    fz = 2 * (b[5] - b[4]) + 1 if dim == 3 else 1
+    k, j, i = np.meshgrid(np.arange(fz), np.arange(fy), np.arange(fx), indexing="ij")
+    zf = b[4] + 0.5 * k if dim == 3 else 0.0 * k
+    phi_f, rho_f, u_f = fields(b[0] + 0.5 * i, b[2] + 0.5 * j, zf, 2.0)
+    return dict(params=p, box=b, phi_c=phi_c, rho_c=rho_c, u_c=u_c, phi_f=phi_f, rho_f=rho_f, u_f=u_f,
+                fine_shape=(fz, fy, fx),
+                name=f"two-level {'bubble' if gas_inside else 'droplet'} lattice={lattice} {nx}x{ny}x{nz} box={b}")

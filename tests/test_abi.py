@@ -326,3 +326,31 @@ def test_refine_remesh_levels_checks_the_box_count_first():
     with pytest.raises(ValueError, match="rebuilding"):
         lsb.Refine.remesh_levels(g, _SIB[:2])
     lib.lsb_ref_destroy(h)
+
+
+def test_two_level_create_validates_without_a_device():
+    """lsb_ref2_create: a periodic coarse grid, BGK phases, a box keeping a
+    node to every face and spanning 4 cells per axis; host memory only."""
+    lib = lsb.load()
+    w = W.two_level_bubble(W.D2Q9)
+
+    def create(p, box):
+        h = C.c_void_p()
+        rc = lib.lsb_ref2_create(C.byref(lsb.to_params(p)), (C.c_int * 6)(*(tuple(box) + (0, 0))[:6]), C.byref(h))
+        return rc, h
+
+    for p, box in [(dict(w["params"], bc=[W.NOSLIP] * 4 + [W.PERIODIC] * 2), w["box"]),
+                   (dict(w["params"], collision=[W.BGK, W.CUMULANT], lattice=W.D3Q27, nz=48), (10, 38, 10, 38, 10, 38)),
+                   (w["params"], (10, 13, 10, 38)), (w["params"], (0, 38, 10, 38)), (w["params"], (10, 47, 10, 38)),
+                   (dict(w["params"], tau=[0.5, 0.8]), w["box"])]:
+        rc, h = create(p, box)
+        assert rc == lsb.LSB_EINVAL and not h.value, (p["bc"], box)
+    rc, h = create(w["params"], w["box"])
+    assert rc == lsb.LSB_OK and h.value
+    nb = C.c_size_t()
+    assert lib.lsb_ref2_workspace_bytes(h, C.byref(nb)) == 0
+    sh = (C.c_int * 3)()
+    assert lib.lsb_ref2_fine_shape(h, sh) == 0 and tuple(sh) == (57, 57, 1)
+    # coarse populations twice (FP64) at least, plus the fine level's workspace
+    assert nb.value > 2 * 9 * 48 * 48 * 8 + 2 * 9 * 57 * 57 * 8
+    lib.lsb_ref2_destroy(h)
