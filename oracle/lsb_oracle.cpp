@@ -1422,8 +1422,9 @@ struct Sim {
 // the coupling of its grid levels only as Dupuis-Chopard interpolation in
 // space and time with the collision frequency adapted per level):
 //
-//   levels   a periodic coarse grid of nodes (I, J, K) in coarse lattice
-//            units, and one box [ia, ib] x [ja, jb] (x [ka, kb]) of its
+//   levels   a coarse grid of nodes (I, J, K) in coarse lattice units
+//            (periodic, no-slip or free-slip faces, the walls of the
+//            one-level step), and one box [ia, ib] x [ja, jb] (x [ka, kb]) of its
 //            nodes refined at ratio 2 (fine node (i, j, k) at (ia + i/2,
 //            ...)), node-centred as the single-phase refinement.
 //   fine     the whole two-phase step (collide-stream with wall and
@@ -1436,7 +1437,7 @@ struct Sim {
 //            must hold the interface with its band and 3 fine cells to
 //            spare (the step refuses otherwise).
 //   coarse   every uncovered node is in one phase for good (the interface
-//            never leaves the box): pull (periodic), BGK with that phase's
+//            never leaves the box): pull (with the wall rules), BGK with that phase's
 //            tau_c and body force; perimeter nodes keep their pre-collision
 //            sets G (t + 1).
 //   inject   the fine box's faces are injected faces: a fine node pulls a
@@ -1578,6 +1579,42 @@ struct TwoPhaseRef {
     nstep = 0;
   }
 
+  // The coarse population entering node (I, J, K) along c_q: pull
+  // streaming with the wall rules of the one-level step (walls on cell
+  // faces; halfway bounce-back with the moving-wall term across a no-slip
+  // face, specular reflection across a free-slip face) and periodic wrap.
+  // The coarse grid holds no interface.
+  double coarse_pull(int I, int J, int K, int q) const {
+    const long N = nc();
+    const int* ci = L.c[q];
+    const int pos[3] = {I, J, K};
+    int s[3];
+    bool cross[3] = {false, false, false};
+    int face[3] = {0, 0, 0};
+    bool any = false;
+    for (int a = 0; a < 3; ++a) {
+      s[a] = pos[a] - ci[a];
+      if (s[a] >= 0 && s[a] < n[a]) continue;
+      if (Pc.bc[2 * a] == BC_PERIODIC) { s[a] = (s[a] + n[a]) % n[a]; continue; }
+      cross[a] = true;
+      face[a] = s[a] < 0 ? 2 * a : 2 * a + 1;
+      any = true;
+    }
+    if (!any) return fc[(size_t)q * N + cidx(s[0], s[1], s[2])];
+    for (int a = 0; a < 3; ++a)
+      if (cross[a] && Pc.bc[face[a]] == BC_NOSLIP) {
+        const double* uw = Pc.wall_u[face[a]];
+        const double cu = ci[0] * uw[0] + ci[1] * uw[1] + ci[2] * uw[2];
+        return fc[(size_t)L.opp[q] * N + cidx(I, J, K)] + 2.0 * L.w[q] * cu / CS2;
+      }
+    int cr[3];
+    for (int a = 0; a < 3; ++a) {
+      cr[a] = cross[a] ? -ci[a] : ci[a];
+      if (cross[a]) s[a] = pos[a];
+    }
+    return fc[(size_t)find_dir(L, cr[0], cr[1], cr[2]) * N + cidx(s[0], s[1], s[2])];
+  }
+
   // coarse step: uncovered nodes pull, keep G at the perimeter, collide
   std::vector<double> coarse_step() {
     const long N = nc();
@@ -1588,11 +1625,7 @@ struct TwoPhaseRef {
           if (covered(I, J, K)) continue;
           const long c = cidx(I, J, K);
           double f[27], e[27], F[27];
-          for (int q = 0; q < Q; ++q) {
-            const int si = (I - L.c[q][0] + n[0]) % n[0], sj = (J - L.c[q][1] + n[1]) % n[1];
-            const int sk = (K - L.c[q][2] + n[2]) % n[2];
-            f[q] = fc[(size_t)q * N + cidx(si, sj, sk)];
-          }
+          for (int q = 0; q < Q; ++q) f[q] = coarse_pull(I, J, K, q);
           if (perimeter(I, J, K))
             for (int q = 0; q < Q; ++q) g1[(size_t)q * nbox() + bidx(I, J, K)] = f[q];
           const int k = kc[c];
@@ -2043,11 +2076,14 @@ int orc_refill(const orc::Params* p, const double* phi_new, const unsigned char*
 }
 
 // ---- two-level refinement of the two-phase step ---------------------------
-// p: coarse parameters (all faces periodic), box: 6 ints in coarse nodes.
+// p: coarse parameters (periodic, no-slip or free-slip faces; z periodic in
+// 2D; BGK in both phases), box: 6 ints in coarse nodes.
 void* orc_r2_create(const orc::Params* p, const int* box) {
   if (check_params(p)) return nullptr;
   for (int a = 0; a < 6; ++a)
-    if (p->bc[a] != orc::BC_PERIODIC) return nullptr;
+    if (p->bc[a] != orc::BC_PERIODIC && p->bc[a] != orc::BC_NOSLIP && p->bc[a] != orc::BC_FREESLIP) return nullptr;
+  if (p->lattice == 0 && p->bc[4] != orc::BC_PERIODIC) return nullptr;
+  if (p->collision[0] != 0 || p->collision[1] != 0) return nullptr;
   orc::TwoPhaseRef* r = new orc::TwoPhaseRef();
   if (!r->create(*p, box)) {
     delete r;

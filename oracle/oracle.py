@@ -298,8 +298,9 @@ def refill(p: dict, phi_new, old_gas, pop, rho, u, S=None, pb: float = 0.0):
 
 
 class TwoPhaseRefineOracle:
-    """Two-level refinement of the two-phase step (oracle): a periodic coarse
-    grid (params in coarse lattice units) with one box (6 ints, coarse
+    """Two-level refinement of the two-phase step (oracle): a coarse grid
+    (params in coarse lattice units; periodic, no-slip or free-slip faces)
+    with one box (6 ints, coarse
     nodes) refined at ratio 2 that holds the interface and its band.  The
     fine level is an Oracle view in fine lattice units (self.fine)."""
 
