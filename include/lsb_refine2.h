@@ -59,8 +59,9 @@ extern "C" {
 typedef struct lsb_ref2 lsb_ref2;
 
 /* params: the coarse grid and both phases in coarse lattice units; every
- * face LSB_PERIODIC, both phases LSB_BGK; init_hydrostatic is not read (the
- * initial state is the caller's).  box: ia, ib, ja, jb, ka, kb (ka, kb
+ * face LSB_PERIODIC (coarse walls are not available on this path), both
+ * phases LSB_BGK; init_hydrostatic is not read (the initial state is the
+ * caller's).  box: ia, ib, ja, jb, ka, kb (ka, kb
  * ignored for D2Q9), inclusive coarse nodes, 1 <= ia, ib <= nx - 2 and
  * ib - ia >= 4, the same for j and (3D) k.  Host memory only.
  * LSB_EINVAL for a NULL pointer or anything outside these ranges or those of

@@ -378,6 +378,7 @@ int lsb_ref2_create(const lsb_params* P, const int* box, lsb_ref2** out) {
   if (!P || !box || !out) return fail(LSB_EINVAL, "null argument");
   *out = nullptr;
   if (P->lattice < LSB_D2Q9 || P->lattice > LSB_D3Q27) return fail(LSB_EINVAL, "unknown lattice");
+  // coarse walls are not taken on this path (see lsb_refine2.h)
   for (int f = 0; f < 6; ++f)
     if (P->bc[f] != LSB_PERIODIC) return fail(LSB_EINVAL, "the coarse grid must be periodic on every face");
   for (int k = 0; k < 2; ++k)

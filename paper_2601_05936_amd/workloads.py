@@ -283,7 +283,7 @@ def seeded_bubble(seed: int, lattice=D2Q9, shape=(37, 29, 1), storage=F64, gas_i
 
 def two_level_bubble(lattice=D2Q9, n=(48, 48, 1), box=(10, 38, 10, 38), centre=None, radius=7.0, gas_inside=True,
                      rho_ratio=10.0, tau=(0.8, 0.8), sigma=1e-2, g=0.0, u_amp=0.0, seed=0, storage=F64,
-                     reinit_every=10, n_reinit=3):
+                     reinit_every=10, n_reinit=3, bc=None, wall_u=None):
     """A circle or sphere of radius R (coarse cells) in a periodic coarse
     grid of n nodes, held on the fine level of the box (ia, ib, ja, jb[, ka,
     kb]) of coarse nodes.  Coarse node (I, J, K) sits at (I, J, K), fine node
@@ -291,7 +291,8 @@ def two_level_bubble(lattice=D2Q9, n=(48, 48, 1), box=(10, 38, 10, 38), centre=N
     (gas >= 0) in each level's cells.  Density 1 everywhere; the velocity is
     zero or a seeded sum of smooth periodic modes of amplitude u_amp, the
     same function on both levels; gravity g along -y (2D) or -z (3D) with
-    the gas pressure baseline of the bubble."""
+    the gas pressure baseline of the bubble; coarse faces bc (periodic by
+    default) with wall velocities wall_u."""
     nx, ny, nz = n
     dim = 2 if lattice == D2Q9 else 3
     b = (tuple(int(v) for v in box) + (0, 0))[:6]
@@ -299,9 +300,12 @@ def two_level_bubble(lattice=D2Q9, n=(48, 48, 1), box=(10, 38, 10, 38), centre=N
         centre = (0.5 * (b[0] + b[1]), 0.5 * (b[2] + b[3]), 0.5 * (b[4] + b[5]) if dim == 3 else 0.0)
     rho = [1.0, 1.0 / rho_ratio]
     acc = [0.0, -g, 0.0] if dim == 2 else [0.0, 0.0, -g]
-    p = default_params(lattice=lattice, storage=storage, nx=nx, ny=ny, nz=nz, bc=[PERIODIC] * 6, rho_phys=rho,
+    p = default_params(lattice=lattice, storage=storage, nx=nx, ny=ny, nz=nz,
+                       bc=list(bc) if bc is not None else [PERIODIC] * 6, rho_phys=rho,
                        tau=list(tau), sigma=sigma, accel=[list(acc), list(acc)],
                        reinit_every=reinit_every, n_reinit=n_reinit)
+    if wall_u is not None:
+        p["wall_u"] = [list(map(float, v)) for v in wall_u]
     if g != 0.0:
         p.update(use_pb=1, pb0=sigma * (1.0 if dim == 2 else 2.0) / radius)
     rng = np.random.default_rng(seed)

@@ -8,9 +8,11 @@ the uncovered nodes and of the covered ring next to the perimeter within
 1e-10 of their deviation scale max |f - w|, the coarse phases bit-exact.
 Cases: a still droplet with surface tension (density ratio 10), a bubble
 moved by a seeded flow under gravity with the gas pressure baseline and
-reinitialisation (the interface moves, cells change phase), and 3D D3Q19 /
-D3Q27 bubbles, fine levels of 57^2, 57 x 73 and 33^3 nodes (several tiles,
-ragged tails).  The radii are off the lattice: a fine node exactly on
+reinitialisation (the interface moves, cells change phase), 3D D3Q19 /
+D3Q27 bubbles, and coarse walls: free-slip x with no-slip y (one moving) in
+2D, a container (free-slip x and y, no-slip z) with a rising bubble in 3D;
+fine levels of 57^2, 57 x 73, 57 x 65, 33^3 and 39 x 39 x 41 nodes (several
+tiles, ragged tails).  The radii are off the lattice: a fine node exactly on
 phi = 0 is a tie of the phase decision that rounding breaks either way.
 """
 import numpy as np
@@ -31,6 +33,15 @@ CASES = {
                          u_amp=0.01, seed=5, steps=30),
     "bubble3d_q27": dict(lattice=W.D3Q27, n=(24, 23, 22), box=(4, 20, 3, 19, 3, 19), radius=2.55, sigma=5e-3,
                          rho_ratio=50.0, tau=(0.6, 1.0), g=1e-5, u_amp=0.01, seed=7, steps=30),
+    # coarse walls: the GPU path rejects them (LSB_EINVAL); these cases
+    # stay as skipped tests (see WALLS_OFF)
+    "walls2d": dict(lattice=W.D2Q9, n=(40, 56, 1), box=(6, 34, 8, 40), centre=(20.3, 23.0, 0.0), radius=5.1,
+                    rho_ratio=20.0, tau=(0.7, 0.9), sigma=3e-3, g=2e-5, u_amp=0.01, seed=11, steps=100,
+                    bc=[W.FREESLIP, W.FREESLIP, W.NOSLIP, W.NOSLIP, W.PERIODIC, W.PERIODIC],
+                    wall_u=[[0.0] * 3, [0.0] * 3, [0.0] * 3, [0.02, 0.0, 0.0], [0.0] * 3, [0.0] * 3]),
+    "container3d": dict(lattice=W.D3Q27, n=(24, 24, 30), box=(2, 21, 2, 21, 4, 24), centre=(11.5, 11.5, 12.0),
+                        radius=2.8, rho_ratio=100.0, tau=(0.55, 0.9), sigma=3e-3, g=1e-5, steps=30,
+                        bc=[W.FREESLIP, W.FREESLIP, W.FREESLIP, W.FREESLIP, W.NOSLIP, W.NOSLIP]),
 }
 
 
@@ -79,7 +90,15 @@ def compare_coarse(o, g, w, label):
     assert e <= TOL_F64
 
 
-@pytest.mark.parametrize("case", list(CASES))
+WALLS_OFF = pytest.mark.skip(reason=(
+    "coarse walls are switched off on the GPU path: a walled two-level run (2D, free-slip x, no-slip y, fine "
+    "level 57 x 65) returned garbage coarse populations and then a memory fault; the coarse kernels compiled "
+    "from the same source as host code run clean under AddressSanitizer on these inputs and no cause is "
+    "found yet; lsb_ref2_create rejects non-periodic coarse faces"))
+WALLED = ("walls2d", "container3d")
+
+
+@pytest.mark.parametrize("case", [pytest.param(c, marks=WALLS_OFF) if c in WALLED else c for c in CASES])
 def test_two_level_parity_f64(require_gpu, case):
     from tests.test_gpu_parity import compare
     w, steps = build(case)
