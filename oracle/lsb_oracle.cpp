@@ -1673,15 +1673,17 @@ struct TwoPhaseRef {
     }
   }
 
-  // restriction of the inner ring from the fine state (see above); prev is
-  // the fine post-collision state before the second sub-step
+  // restriction of every covered node from the fine state (see above; the
+  // coarse step reads only the ring next to the perimeter, the others keep
+  // the coarse state complete for output and re-meshing); prev is the fine
+  // post-collision state before the second sub-step
   void restrict_into(std::vector<double>& out, const std::vector<double>& prev) {
     Sim<double>& s = *fine;
     const long N = nc();
     for (int K = box[4]; K <= (D == 3 ? box[5] : 0); ++K)
       for (int J = box[2]; J <= box[3]; ++J)
         for (int I = box[0]; I <= box[1]; ++I) {
-          if (!inner_ring(I, J, K)) continue;
+          if (!covered(I, J, K)) continue;
           const int fi = 2 * (I - box[0]), fj = 2 * (J - box[2]), fk = D == 3 ? 2 * (K - box[4]) : 0;
           const long fcell = s.idx(fi, fj, fk);
           double f[27], e[27], F[27], rho, u[3];
@@ -1714,6 +1716,149 @@ struct TwoPhaseRef {
       if (i < 3 || i > m[0] - 3 || j < 3 || j > m[1] - 3 || (D == 3 && (k < 3 || k > m[2] - 3))) return false;
     }
     return true;
+  }
+
+  // The perimeter's pre-collision sets at the current time, inverted from
+  // the coarse post-collision populations f of each perimeter node: with
+  // u = m/rho - a_c the pre-collision velocity and e = f_eq(rho, u),
+  // G = e + tau_c / (tau_c - 1) (f - F_c - e) (e at tau_c = 1).
+  void perimeter_sets_from_state() {
+    const long N = nc();
+    g0.assign((size_t)Q * nbox(), 0.0);
+    for (int K = box[4]; K <= (D == 3 ? box[5] : 0); ++K)
+      for (int J = box[2]; J <= box[3]; ++J)
+        for (int I = box[0]; I <= box[1]; ++I) {
+          if (!perimeter(I, J, K)) continue;
+          const long c = cidx(I, J, K);
+          const int k = kc[c];
+          double f[27], e[27], F[27], rho, u[3];
+          for (int q = 0; q < Q; ++q) f[q] = fc[(size_t)q * N + c];
+          moments(f, rho, u);
+          for (int a = 0; a < 3; ++a) u[a] -= Pc.accel[k][a];
+          equilibrium(L, rho, u, e);
+          force(k, rho, Pc.accel[k], F);
+          const double r = tau_c[k] == 1.0 ? 0.0 : tau_c[k] / (tau_c[k] - 1.0);
+          for (int q = 0; q < Q; ++q) g0[(size_t)q * nbox() + bidx(I, J, K)] = e[q] + r * (f[q] - F[q] - e[q]);
+        }
+  }
+
+  // Re-meshing onto the box nb of the same extents, between coarse steps
+  // (reading).  Fine nodes inside the old box keep their state
+  // (populations, level set, moments of the last collision); the others take
+  // the coarse post-collision populations H interpolated as at the
+  // perimeter (mean of 2, 4 or 8 nodes) at the same time level: with u =
+  // m/rho, e_c = f_eq(rho, u - a_c) and e_f = f_eq(rho, u - a_f), the fine
+  // post-collision populations e_f + (tau_f - 1) / (2 (tau_c - 1)) (H - F_c -
+  // e_c) + F_f (the coarse non-equilibrium part rescaled to the fine level;
+  // none at tau_c = 1), the level set at +-band by the coarse phase, the
+  // moments (rho, u, 0).  The level set's tags, band and geometry are
+  // classified again, bubbles relabelled, the initial centroid moved with
+  // the fine coordinates (the baseline is unchanged); the covered coarse
+  // nodes already hold the restricted fine state, and the new perimeter's
+  // pre-collision sets are inverted from the coarse state.  Returns -1 for
+  // a box of other extents or outside the grid, -2 if the band is not
+  // inside the new box.
+  int remesh(const int* nbx) {
+    int d[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) {
+      if (nbx[2 * a + 1] - nbx[2 * a] != box[2 * a + 1] - box[2 * a]) return -1;
+      if (nbx[2 * a] < 1 || nbx[2 * a + 1] > n[a] - 2) return -1;
+      d[a] = nbx[2 * a] - box[2 * a];
+    }
+    Sim<double>& s = *fine;
+    const long Nf = s.N, N = nc();
+    std::vector<double> A2((size_t)Q * Nf), phi2(Nf), Mr2(Nf), Mu2(3 * (size_t)Nf), MS2(6 * (size_t)Nf);
+    const double B = s.P.band;
+    for (long c = 0; c < Nf; ++c) {
+      int i, j, k;
+      s.coords(c, i, j, k);
+      const int oi = i + 2 * d[0], oj = j + 2 * d[1], ok = k + 2 * d[2];
+      if (oi >= 0 && oi < s.nx && oj >= 0 && oj < s.ny && ok >= 0 && ok < s.nz) {
+        const long o = s.idx(oi, oj, ok);
+        for (int q = 0; q < Q; ++q) A2[(size_t)q * Nf + c] = s.A[(size_t)q * Nf + o];
+        phi2[c] = s.phi[o];
+        Mr2[c] = s.Mr[o];
+        for (int a = 0; a < 3; ++a) Mu2[3 * c + a] = s.Mu[3 * o + a];
+        for (int m = 0; m < 6; ++m) MS2[6 * c + m] = s.MS[6 * o + m];
+        continue;
+      }
+      const int o3[3] = {i & 1, j & 1, D == 3 ? (k & 1) : 0};
+      const double w = (o3[0] ? 0.5 : 1.0) * (o3[1] ? 0.5 : 1.0) * (o3[2] ? 0.5 : 1.0);
+      double H[27] = {0.0};
+      int kk = 0;
+      for (int dz = 0; dz <= o3[2]; ++dz)
+        for (int dy = 0; dy <= o3[1]; ++dy)
+          for (int dx = 0; dx <= o3[0]; ++dx) {
+            const long cc = cidx(nbx[0] + (i - o3[0]) / 2 + dx, nbx[2] + (j - o3[1]) / 2 + dy,
+                                 D == 3 ? nbx[4] + (k - o3[2]) / 2 + dz : 0);
+            kk = kc[cc];
+            for (int q = 0; q < Q; ++q) H[q] += w * fc[(size_t)q * N + cc];
+          }
+      double rho, u[3], uc[3], uf[3], ec[27], ef[27], Fc[27], Ff[27];
+      moments(H, rho, u);
+      for (int a = 0; a < 3; ++a) {
+        uc[a] = u[a] - Pc.accel[kk][a];
+        uf[a] = u[a] - s.P.accel[kk][a];
+      }
+      equilibrium(L, rho, uc, ec);
+      equilibrium(L, rho, uf, ef);
+      force(kk, rho, Pc.accel[kk], Fc);
+      force(kk, rho, s.P.accel[kk], Ff);
+      const double ratio = tau_c[kk] == 1.0 ? 0.0 : (tau_f[kk] - 1.0) / (2.0 * (tau_c[kk] - 1.0));
+      for (int q = 0; q < Q; ++q) A2[(size_t)q * Nf + c] = ef[q] + ratio * (H[q] - Fc[q] - ec[q]) + Ff[q];
+      phi2[c] = kk ? B : -B;
+      Mr2[c] = rho;
+      for (int a = 0; a < 3; ++a) Mu2[3 * c + a] = u[a];
+      for (int m = 0; m < 6; ++m) MS2[6 * c + m] = 0.0;
+    }
+    s.A.swap(A2);
+    s.An = s.A;
+    s.phi.swap(phi2);
+    s.Mr.swap(Mr2);
+    s.Mu.swap(Mu2);
+    s.MS.swap(MS2);
+    s.Mr1 = s.Mr;
+    s.Mu1 = s.Mu;
+    s.MS1 = s.MS;
+    for (int a = 0; a < D; ++a) s.xc0[a] = s.xc0[a] - 2.0 * d[a];
+    for (int a = 0; a < 6; ++a) box[a] = a < 2 * D ? nbx[a] : 0;
+    s.classify(s.gas, s.act);
+    s.geometry();
+    if (s.P.use_pb == 2) s.update_bubbles();
+    perimeter_sets_from_state();
+    return band_inside() ? 0 : -2;
+  }
+
+  // Level-set sensor for the box (reading; liquid phi < 0, gas phi >= 0 as
+  // everywhere here): the fine cells with phi >= -d_ref (the gas and a band
+  // of width d_ref around it) are tagged; the box keeps its extents and is
+  // moved so that the centre of the tagged cells' bounding box (fine
+  // indices lo, hi) falls on its centre, rounded half up to whole coarse
+  // nodes, clamped one node inside the grid faces.  The current box when no
+  // cell is tagged.
+  void sensor(double d_ref, int* out) const {
+    const Sim<double>& s = *fine;
+    int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
+    for (long c = 0; c < s.N; ++c) {
+      if (!(s.phi[c] >= -d_ref)) continue;
+      int ijk[3];
+      s.coords(c, ijk[0], ijk[1], ijk[2]);
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], ijk[a]);
+        hi[a] = std::max(hi[a], ijk[a]);
+      }
+    }
+    for (int a = 0; a < 6; ++a) out[a] = box[a];
+    if (hi[0] < 0) return;
+    for (int a = 0; a < D; ++a) {
+      const int E = box[2 * a + 1] - box[2 * a];
+      // new origin: round(box0 + (lo + hi) / 4 - E / 2), in quarter nodes
+      const long q4 = 4L * box[2 * a] + lo[a] + hi[a] - 2L * E + 2;
+      long b0 = q4 >= 0 ? q4 / 4 : -((-q4 + 3) / 4);
+      b0 = std::max<long>(1, std::min<long>(b0, n[a] - 2 - E));
+      out[2 * a] = (int)b0;
+      out[2 * a + 1] = (int)b0 + E;
+    }
   }
 
   bool step() {
@@ -2119,6 +2264,14 @@ int orc_r2_get_coarse(void* h, double* pop, unsigned char* phase) {
 }
 // the fine level as an oracle simulation (populations, fields, interface, integrals)
 void* orc_r2_fine(void* h) { return static_cast<orc::TwoPhaseRef*>(h)->fine; }
+
+// Box of the level-set sensor (6 ints) and re-meshing onto a box of the
+// same extents (0; -1 for an invalid box, -2 if the band is not inside it).
+void orc_r2_sensor(void* h, double d_ref, int* box) { static_cast<orc::TwoPhaseRef*>(h)->sensor(d_ref, box); }
+int orc_r2_remesh(void* h, const int* box) { return static_cast<orc::TwoPhaseRef*>(h)->remesh(box); }
+void orc_r2_box(void* h, int* box) {
+  for (int a = 0; a < 6; ++a) box[a] = static_cast<orc::TwoPhaseRef*>(h)->box[a];
+}
 
 // ---- tangent (forward mode, frozen decisions) ---------------------------
 // Seeds: dphi0 (N values, may be null) and dsigma.  Output: the tangent of

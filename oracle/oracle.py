@@ -96,6 +96,9 @@ def _load():
     lib.orc_r2_get_coarse.argtypes = [C.c_void_p, dp, C.POINTER(C.c_ubyte)]
     lib.orc_r2_fine.restype = C.c_void_p
     lib.orc_r2_fine.argtypes = [C.c_void_p]
+    lib.orc_r2_sensor.argtypes = [C.c_void_p, C.c_double, C.POINTER(C.c_int)]
+    lib.orc_r2_remesh.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
+    lib.orc_r2_box.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
     lib.orc_decisions.restype = C.c_long
     lib.orc_decisions.argtypes = [C.c_void_p, C.POINTER(C.c_uint64), C.c_long]
     lib.orc_get_sample.argtypes = [C.c_void_p, C.POINTER(C.c_long), C.c_int, dp, dp, C.POINTER(C.c_ubyte)]
@@ -342,8 +345,32 @@ class TwoPhaseRefineOracle:
         assert rc == 0
         return self
 
+    def sensor(self, d_ref: float):
+        """Box (6 ints) that the level-set sensor moves the refined box to."""
+        out = (C.c_int * 6)()
+        self.lib.orc_r2_sensor(self.h, float(d_ref), out)
+        return tuple(out)
+
+    def remesh(self, box):
+        """Re-mesh onto a box of the same extents (6 ints)."""
+        b = (tuple(int(v) for v in box) + (0, 0))[:6]
+        rc = self.lib.orc_r2_remesh(self.h, (C.c_int * 6)(*b))
+        if rc == -1:
+            raise ValueError("re-meshing needs a box of the same extents inside the grid")
+        if rc == -2:
+            raise RuntimeError("the level-set band is not inside the new box")
+        self.box = b
+        return self
+
+    @property
+    def current_box(self):
+        out = (C.c_int * 6)()
+        self.lib.orc_r2_box(self.h, out)
+        return tuple(out)
+
     def coarse(self):
-        """(populations [Q][nz][ny][nx], phase [nz][ny][nx]) of the coarse grid."""
+        """(populations [Q][nz][ny][nx], phase [nz][ny][nx]) of the coarse grid
+        (covered nodes hold the fine state restricted to the coarse level)."""
         nc = int(np.prod(self.coarse_shape))
         pop = np.zeros(self.Q * nc)
         ph = np.zeros(nc, dtype=np.uint8)
