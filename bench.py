@@ -276,6 +276,81 @@ def run_refine3d(steps: int, warmup: int):
     return res
 
 
+def run_two_phase_levels(steps: int, warmup: int):
+    """The two-phase step on two levels against the uniform grid.  Uniform:
+    the D3Q27 rising bubble 128x128x256 (d = 32, Eo 10, Mo 1e-3, density
+    ratio 1000, viscosity ratio 100, FP16-deviation storage, container
+    walls), 2 steps per coarse step.  Two levels: the same physics in coarse
+    units (tau_c = (tau_f + 1/2) / 2, sigma_c = sigma_f / 2, a_c = 2 a_f) on
+    64x64x128 coarse nodes (periodic: the two-level path has no coarse walls)
+    and the bubble (R = 16 fine cells) on the fine level of a box of coarse
+    nodes [18, 46]^2 x [10, 48] (57 x 57 x 77 fine nodes, FP16-deviation),
+    re-meshed every 50 coarse steps (the level-set sensor at d_ref = 6 fine
+    cells moves the box; the sensor and the re-mesh are in the timed
+    region); the coarse grid is FP64."""
+    import torch
+
+    from paper_2601_05936_amd import workloads as W
+    from paper_2601_05936_amd.lsb import Sim, TwoPhaseRefine, SCHED_SERIAL
+    wu = W.rising_bubble_3d(storage=W.F16DEV)
+    pu = wu["params"]
+    s = Sim(pu).set_schedule(SCHED_SERIAL).init(wu["phi0"])
+    s.step(2 * warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s.step(2 * steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_uniform = e0.elapsed_time(e1) / steps  # two fine steps
+    n_uniform = s.N
+    del s
+    torch.cuda.empty_cache()
+    tau_c = [(t + 0.5) / 2.0 for t in pu["tau"]]
+    g_c = 2.0 * (-pu["accel"][0][2])
+    w = W.two_level_bubble(lattice=W.D3Q27, n=(64, 64, 128), box=(18, 46, 18, 46, 10, 48),
+                           centre=(32.0, 32.0, 24.0), radius=8.0, rho_ratio=1.0 / pu["rho_phys"][1], tau=tau_c,
+                           sigma=pu["sigma"] / 2.0, g=g_c, storage=W.F16DEV)
+    r = TwoPhaseRefine(w["params"], w["box"]).init(*[w[k] for k in ("phi_c", "rho_c", "u_c", "phi_f", "rho_f",
+                                                                     "u_f")])
+    r.step(warmup)
+    torch.cuda.synchronize()
+    remeshes = 0
+    e0.record()
+    done = 0
+    while done < steps:
+        k = min(50, steps - done)
+        r.step(k)
+        done += k
+        if k == 50:
+            nb = r.sensor(6.0)
+            remeshes += tuple(nb) != tuple(r.current_box)
+            r.remesh(nb)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nc = r.n_coarse
+    nf = r.n_fine
+    b = w["box"]
+    covered = (b[1] - b[0] - 1) * (b[3] - b[2] - 1) * (b[5] - b[4] - 1)
+    updates = (nc - covered) + 2 * nf
+    I = r.fine.integrals()
+    res = dict(workload="D3Q27 two-phase step on two levels: 64x64x128 coarse (periodic), bubble R = 16 fine "
+                        "cells on a 57x57x77 fine box re-meshed every 50 coarse steps, FP16-deviation fine storage, "
+                        "FP64 coarse; against the uniform 128x128x256 rising bubble (FP16-deviation), two fine "
+                        "steps per coarse step",
+               steps=steps, warmup=warmup, ms_per_coarse_step=ms, node_updates_per_step=updates,
+               mlups=updates / (ms * 1e-3) / 1e6, fine_equivalent_mlups=2 * n_uniform / (ms * 1e-3) / 1e6,
+               uniform_ms_per_two_steps=ms_uniform, uniform_mlups=2 * n_uniform / (ms_uniform * 1e-3) / 1e6,
+               speedup_vs_uniform=ms_uniform / ms, fine_nodes=nf, coarse_nodes=nc, remesh_every=50,
+               boxes_moved=remeshes, box=list(r.current_box),
+               fine_volume_gas=float(I["volume_gas"]), dtype="f32 (fine, FP16-deviation storage) / f64 (coarse)")
+    log(f"[two-phase levels] {res}")
+    del r
+    torch.cuda.empty_cache()
+    return res
+
+
 def run_refine_nested(steps: int, warmup: int):
     """Three nested levels (D2Q9, BGK, FP64, ratio 2 at each jump): 2048^2
     coarse nodes, periodic; level 1 over the coarse nodes [512, 1536]^2
@@ -431,8 +506,9 @@ def main():
     ap.add_argument("--refine-steps", type=int, default=100,
                     help="refinement run length in coarse steps: two-level 2D and 3D legs, three-level "
                          "2D leg, nine-box 2D tree (0: skip)")
-    ap.add_argument("--refine-legs", default="2d,3d,nested,tree",
-                    help="refinement legs to run: 2d, 3d (two levels), nested (three levels), tree (nine boxes)")
+    ap.add_argument("--refine-legs", default="2d,3d,nested,tree,twophase",
+                    help="refinement legs to run: 2d, 3d (two levels), nested (three levels), tree (nine boxes), "
+                         "twophase (the two-phase step on two levels against the uniform rising bubble)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (counter calibration)")
@@ -507,7 +583,8 @@ def main():
         out["adjoint"] = run_adjoint(args.adjoint_steps, 100)
     if args.refine_steps > 0:
         legs = {"2d": ("refine", run_refine), "3d": ("refine3d", run_refine3d),
-                "nested": ("refine_nested", run_refine_nested), "tree": ("refine_tree", run_refine_tree)}
+                "nested": ("refine_nested", run_refine_nested), "tree": ("refine_tree", run_refine_tree),
+                "twophase": ("two_phase_levels", run_two_phase_levels)}
         for leg in [v.strip() for v in args.refine_legs.split(",") if v.strip()]:
             key, fn = legs[leg]
             out[key] = fn(args.refine_steps, 10)

@@ -36,8 +36,8 @@
  *
  * The interface and its level-set band must stay inside the box: the fine
  * level's LS-active cells (the band dilated by one cell) keep 3 fine cells
- * from every box face.  Covered coarse nodes other than the ring next to
- * the perimeter hold no state.
+ * from every box face; lsb_ref2_sensor and lsb_ref2_remesh move the box
+ * with the interface.
  *
  * Conventions as in lsb.h: every function returns LSB_OK (0) or a negative
  * code (message from lsb_last_error); calls that take a stream enqueue work
@@ -104,9 +104,42 @@ long lsb_ref2_step_count(const lsb_ref2* ref);
 
 /* Coarse post-collision populations pop [Q][nx ny nz] (FP64) and phases
  * phase [nx ny nz] (0 liquid, 1 gas) into device arrays (either may be
- * NULL).  Covered nodes off the ring next to the perimeter hold stale
- * values. */
+ * NULL).  Covered nodes hold the fine state restricted to the coarse level
+ * (f_eq + 2 (tau_c - 1) / tau_f (f - f_eq) plus the coarse force, from the
+ * coincident fine node's pre-collision populations less one fine step of
+ * force), restricted every step. */
 int lsb_ref2_get_coarse(lsb_ref2* ref, double* pop, uint8_t* phase, void* stream);
+
+/* The current box (6 ints; ka = kb = 0 in 2D). */
+int lsb_ref2_get_box(const lsb_ref2* ref, int* box);
+
+/* Re-meshing: the box keeps its extents and follows the interface (the
+ * paper's level-set sensor, Sec. 3.2, refines the gas and a band around
+ * it; its tree refines cell by cell, here one box moves).
+ *
+ * lsb_ref2_sensor: the fine cells with phi >= -d_ref (fine cells; the gas
+ * and a band of width d_ref around it) are tagged, and box (host, 6 ints)
+ * receives the current box moved so that the centre of their bounding box
+ * falls on its centre, rounded half up to whole coarse nodes, clamped one
+ * node inside the grid faces; the current box when nothing is tagged.
+ * Synchronises the stream.
+ *
+ * lsb_ref2_remesh: between coarse steps, onto box (host, 6 ints) of the
+ * same extents.  Fine nodes inside the old box keep their state; the others
+ * take the coarse post-collision populations H interpolated as at the
+ * perimeter, with u = m/rho: f_eq(rho, u - a_f) + (tau_f - 1) / (2 (tau_c -
+ * 1)) (H - F_c - f_eq(rho, u - a_c)) + F_f (F the levels' body forces; no
+ * non-equilibrium part at tau_c = 1), and the level set +-band by the
+ * coarse phase.  The fine level's tags, band, geometry and bubbles are
+ * built again, its initial gas centroid moves with its coordinates (the
+ * gas pressure baseline is unchanged), and the new perimeter's pre-collision
+ * sets are inverted from the coarse state, f_eq(rho, u - a_c) + tau_c /
+ * (tau_c - 1) (f - F_c - f_eq(rho, u - a_c)).  Synchronises the stream.
+ * LSB_EINVAL for other extents or a box without a node to spare at a grid
+ * face; LSB_EBAND if the band does not fit the new box (the re-mesh is
+ * done; move the box again); LSB_ESTATE before lsb_ref2_init. */
+int lsb_ref2_sensor(lsb_ref2* ref, double d_ref, int* box, void* stream);
+int lsb_ref2_remesh(lsb_ref2* ref, const int* box, void* stream);
 
 #ifdef __cplusplus
 }

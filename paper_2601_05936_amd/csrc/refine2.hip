@@ -14,10 +14,15 @@
 //   k_r2_inject    the ghost populations of the fine surface nodes from G,
 //                  for the first and then the second fine sub-step;
 //   fine step      the two-phase step of the fine plan (twice);
-//   k_r2_restrict  the covered coarse nodes next to the perimeter, from the
-//                  fine state;
+//   k_r2_restrict  every covered coarse node from the fine state (the ring
+//                  next to the perimeter is what the coarse step reads);
 //   k_r2_band      the fine level's LS-active cells keep 3 cells from the
 //                  box faces (a sticky flag, read at the end of the call).
+// Re-meshing (the box keeps its extents and follows the interface):
+//   k_r2_sensor         bounding box of the fine cells with phi >= -d_ref;
+//   k_r2_remesh_fine    the fine state moved, new nodes from the coarse level;
+//   k_r2_perimeter_sets the new perimeter's pre-collision sets, inverted
+//                       from the coarse state.
 // The coarse populations are FP64 whatever the fine storage.
 #include <hip/hip_runtime.h>
 
@@ -25,8 +30,7 @@
 #include <cmath>
 #include <string>
 
-#include "kernels.h"
-#include "plan.h"
+#include "driver.h"
 #include "../../include/lsb_refine2.h"
 
 namespace {
@@ -57,6 +61,7 @@ struct Geo {
   long nc, nb;      // coarse nodes, box nodes
   int fx, fy, fz;   // fine nodes per axis
   long nf;
+  long ns;          // fine surface nodes
 };
 
 // Per phase k: coarse omega_k = 1 / tau_c,k, the relaxation times of both
@@ -121,6 +126,37 @@ __device__ __forceinline__ void coarse_coords(const Geo& g, long c, int& I, int&
   J = (int)((c / g.nx) % g.ny);
   K = (int)(c / ((long)g.nx * g.ny));
 }
+// Surface node s of the fine level (0 <= s < ns): the two z faces (3D),
+// then the two y faces less their z edges, then the two x faces less their
+// y and z edges; each face row by row, x (or y) fastest.
+__device__ __forceinline__ void surface_coords(const Geo& g, long s, int& i, int& j, int& k) {
+  const int ez = g.D == 3 ? g.fz - 2 : 1;  // interior z extent (z = 1 .. fz - 2, or the one plane in 2D)
+  const int z0 = g.D == 3 ? 1 : 0;
+  const long nzf = g.D == 3 ? (long)g.fx * g.fy : 0;  // nodes of one z face
+  if (s < 2 * nzf) {
+    const long t = s < nzf ? s : s - nzf;
+    k = s < nzf ? 0 : g.fz - 1;
+    j = (int)(t / g.fx);
+    i = (int)(t - (long)j * g.fx);
+    return;
+  }
+  s -= 2 * nzf;
+  const long nyf = (long)g.fx * ez;  // nodes of one y face
+  if (s < 2 * nyf) {
+    const long t = s < nyf ? s : s - nyf;
+    j = s < nyf ? 0 : g.fy - 1;
+    k = z0 + (int)(t / g.fx);
+    i = (int)(t - (long)(k - z0) * g.fx);
+    return;
+  }
+  s -= 2 * nyf;
+  const long nxf = (long)(g.fy - 2) * ez;  // nodes of one x face
+  const long t = s < nxf ? s : s - nxf;
+  i = s < nxf ? 0 : g.fx - 1;
+  k = z0 + (int)(t / (g.fy - 2));
+  j = 1 + (int)(t - (long)(k - z0) * (g.fy - 2));
+}
+
 __device__ __forceinline__ void fine_coords(const Geo& g, long c, int& i, int& j, int& k) {
   i = (int)(c % g.fx);
   j = (int)((c / g.fx) % g.fy);
@@ -209,11 +245,10 @@ __global__ __launch_bounds__(256) void k_r2_inject(Geo g, Phys ph, const double*
   using L = Lat<LAT>;
   using R = typename lsb::Step<LAT, ST>::R;
   constexpr int Q = L::Q;
-  for (long c = blockIdx.x * 256L + threadIdx.x; c < g.nf; c += (long)gridDim.x * 256) {
+  for (long sidx = blockIdx.x * 256L + threadIdx.x; sidx < g.ns; sidx += (long)gridDim.x * 256) {
     int i, j, k;
-    fine_coords(g, c, i, j, k);
-    const bool surf = i == 0 || i == g.fx - 1 || j == 0 || j == g.fy - 1 || (g.D == 3 && (k == 0 || k == g.fz - 1));
-    if (!surf) continue;
+    surface_coords(g, sidx, i, j, k);
+    const long c = ((long)k * g.fy + j) * g.fx + i;
     const int o0 = i & 1, o1 = j & 1, o2 = g.D == 3 ? (k & 1) : 0;
     const double w = (o0 ? 0.5 : 1.0) * (o1 ? 0.5 : 1.0) * (o2 ? 0.5 : 1.0);
     double H[Q];
@@ -243,8 +278,9 @@ __global__ __launch_bounds__(256) void k_r2_inject(Geo g, Phys ph, const double*
   }
 }
 
-// Restriction onto the covered coarse nodes next to the perimeter (the only
-// covered nodes the coarse step reads): the coincident fine node's
+// Restriction onto every covered coarse node (the coarse step reads only
+// the ring next to the perimeter; the others keep the coarse state complete
+// for the queries and re-meshing): the coincident fine node's
 // pre-collision populations of the second sub-step, pulled again from the
 // fine state before it (prev), less one fine step of force, f;
 // e = f_eq(moments of f); coarse post-collision e + 2 (tau_c,k - 1) /
@@ -261,7 +297,7 @@ __global__ __launch_bounds__(256) void k_r2_restrict(Geo g, Phys ph, const typen
   for (long bi = blockIdx.x * 256L + threadIdx.x; bi < g.nb; bi += (long)gridDim.x * 256) {
     const int I = g.b[0] + (int)(bi % g.bw), J = g.b[2] + (int)((bi / g.bw) % g.bh);
     const int K = g.b[4] + (int)(bi / ((long)g.bw * g.bh));
-    if (!inner_ring(g, I, J, K)) continue;
+    if (!covered(g, I, J, K)) continue;
     const int fi = 2 * (I - g.b[0]), fj = 2 * (J - g.b[2]), fk = g.D == 3 ? 2 * (K - g.b[4]) : 0;
     const long fcell = ((long)fk * g.fy + fj) * g.fx + fi;
     const int p = ftag[fcell] & lsb::T_GAS;
@@ -299,6 +335,133 @@ __global__ __launch_bounds__(256) void k_r2_band(Geo g, const uint8_t* __restric
   }
 }
 
+// The perimeter's pre-collision sets at the current time, inverted from the
+// coarse post-collision populations f: with u = m/rho - a_c the
+// pre-collision velocity and e = f_eq(rho, u), G = e + tau_c / (tau_c - 1)
+// (f - F_c - e) (e at tau_c = 1).
+template <int LAT>
+__global__ __launch_bounds__(256) void k_r2_perimeter_sets(Geo g, Phys ph, const double* __restrict__ fc,
+                                                           const uint8_t* __restrict__ kc, double* __restrict__ g0) {
+  constexpr int Q = Lat<LAT>::Q;
+  for (long bi = blockIdx.x * 256L + threadIdx.x; bi < g.nb; bi += (long)gridDim.x * 256) {
+    const int I = g.b[0] + (int)(bi % g.bw), J = g.b[2] + (int)((bi / g.bw) % g.bh);
+    const int K = g.b[4] + (int)(bi / ((long)g.bw * g.bh));
+    if (covered(g, I, J, K)) continue;
+    const long c = ((long)K * g.ny + J) * g.nx + I;
+    const int k = kc[c];
+    double f[Q], rho, u[3];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) f[q] = fc[(size_t)q * g.nc + c];
+    moments<LAT>(f, rho, u);
+    for (int a = 0; a < 3; ++a) u[a] -= ph.acc[k][a];
+    const double r = ph.tc[k] == 1.0 ? 0.0 : ph.tc[k] / (ph.tc[k] - 1.0);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const double e = feq<LAT>(q, rho, u);
+      g0[(size_t)q * g.nb + bi] = e + r * (f[q] - force<LAT>(q, rho, ph.acc[k]) - e);
+    }
+  }
+}
+
+// Re-meshing, fine level: the state of the box moved by d coarse nodes
+// (2 d fine cells) into the plan's other population and moment buffers and
+// into s1 (the level set).  A node inside the old box copies its stored
+// populations (same phase, same codec frame), level set and moments; a new
+// node takes the coarse post-collision populations H interpolated as at the
+// perimeter: with u = m/rho, e_c = f_eq(rho, u - a_c), e_f = f_eq(rho, u -
+// a_f), the fine post-collision populations e_f + (tau_f - 1) / (2 (tau_c -
+// 1)) (H - F_c - e_c) + F_f (none of H's non-equilibrium part at tau_c = 1),
+// the level set at +-band by the coarse phase, moments (rho, u, 0).  g
+// describes the new box.
+template <int LAT, int ST>
+__global__ __launch_bounds__(256) void k_r2_remesh_fine(Geo g, Phys ph, int d0, int d1, int d2,
+                                                        const double* __restrict__ fc,
+                                                        const uint8_t* __restrict__ kc,
+                                                        typename lsb::Step<LAT, ST>::Args a) {
+  using L = Lat<LAT>;
+  using S = lsb::Step<LAT, ST>;
+  using R = typename S::R;
+  using C = typename S::C;
+  constexpr int Q = L::Q;
+  const size_t N = (size_t)g.nf;
+  for (long c = blockIdx.x * 256L + threadIdx.x; c < g.nf; c += (long)gridDim.x * 256) {
+    int i, j, k;
+    fine_coords(g, c, i, j, k);
+    const int oi = i + 2 * d0, oj = j + 2 * d1, ok = k + 2 * d2;
+    if (oi >= 0 && oi < g.fx && oj >= 0 && oj < g.fy && ok >= 0 && ok < g.fz) {
+      const int o = (int)(((long)ok * g.fy + oj) * g.fx + oi);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) a.An[lsb::pidx<LAT>(q, (int)c, N)] = a.A[lsb::pidx<LAT>(q, o, N)];
+      a.s1[c] = a.phi[o];
+      for (int m = 0; m < 10; ++m) a.Mn[(size_t)m * N + c] = a.M[(size_t)m * N + o];
+      continue;
+    }
+    const int o0 = i & 1, o1 = j & 1, o2 = g.D == 3 ? (k & 1) : 0;
+    const double w = (o0 ? 0.5 : 1.0) * (o1 ? 0.5 : 1.0) * (o2 ? 0.5 : 1.0);
+    double H[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) H[q] = 0.0;
+    int kk = 0;
+    for (int dz = 0; dz <= o2; ++dz)
+      for (int dy = 0; dy <= o1; ++dy)
+        for (int dx = 0; dx <= o0; ++dx) {
+          const long cc = ((long)(g.D == 3 ? g.b[4] + (k - o2) / 2 + dz : 0) * g.ny + (g.b[2] + (j - o1) / 2 + dy)) * g.nx +
+                          (g.b[0] + (i - o0) / 2 + dx);
+          kk = kc[cc];
+#pragma unroll
+          for (int q = 0; q < Q; ++q) H[q] += w * fc[(size_t)q * g.nc + cc];
+        }
+    double rho, u[3], uc[3], uf[3];
+    moments<LAT>(H, rho, u);
+    for (int m = 0; m < 3; ++m) {
+      uc[m] = u[m] - ph.acc[kk][m];
+      uf[m] = u[m] - ph.accf[kk][m];
+    }
+    const double ratio = ph.tc[kk] == 1.0 ? 0.0 : (ph.tf[kk] - 1.0) / (2.0 * (ph.tc[kk] - 1.0));
+    const R s = a.scale;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const double ec = feq<LAT>(q, rho, uc), ef = feq<LAT>(q, rho, uf);
+      const double f = ef + ratio * (H[q] - force<LAT>(q, rho, ph.acc[kk]) - ec) + force<LAT>(q, rho, ph.accf[kk]);
+      const R dev = (R)(f - wgt<LAT>(q) * ph.rref[kk]);
+      a.An[lsb::pidx<LAT>(q, (int)c, N)] = C::enc(dev, (R)(1.0 / wgt<LAT>(q)), s);
+    }
+    a.s1[c] = kk ? a.band : -a.band;
+    a.Mn[c] = (R)(rho - 1.0);
+    for (int m = 0; m < 3; ++m) a.Mn[(size_t)(1 + m) * N + c] = (R)u[m];
+    for (int m = 4; m < 10; ++m) a.Mn[(size_t)m * N + c] = (R)0;
+  }
+}
+
+// Re-meshing: the initial gas centroid moves with the fine coordinates.
+__global__ void k_r2_shift_xc0(double* __restrict__ scal, int slot, double dx, double dy, double dz) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    scal[slot] -= dx;
+    scal[slot + 1] -= dy;
+    scal[slot + 2] -= dz;
+  }
+}
+
+// Sensor: bounding box of the fine cells with phi >= -d_ref (lo[3], hi[3]
+// in out[0..5], started at (INT_MAX, -1)).
+template <class R>
+__global__ __launch_bounds__(256) void k_r2_sensor(Geo g, const R* __restrict__ phi, double d_ref, int* __restrict__ out) {
+  for (long c = blockIdx.x * 256L + threadIdx.x; c < g.nf; c += (long)gridDim.x * 256) {
+    if (!((double)phi[c] >= -d_ref)) continue;
+    int i, j, k;
+    fine_coords(g, c, i, j, k);
+    atomicMin(&out[0], i);
+    atomicMin(&out[1], j);
+    atomicMin(&out[2], k);
+    atomicMax(&out[3], i);
+    atomicMax(&out[4], j);
+    atomicMax(&out[5], k);
+  }
+}
+__global__ void k_r2_sensor_init(int* __restrict__ out) {
+  if (threadIdx.x < 6) out[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -1;
+}
+
 int grid_of(long n) { return (int)std::max<long>(1, std::min<long>((n + 255) / 256, 8192)); }
 
 }  // namespace
@@ -333,7 +496,7 @@ void r2_step(lsb_ref2* r, hipStream_t st) {
   const uint8_t* ftag = reinterpret_cast<const uint8_t*>(f->ws + f->off_tag);
   k_r2_coarse<LAT><<<grid_of(g.nc), 256, 0, st>>>(g, r->ph, fin, fout, kc, g1);
   for (int sub = 0; sub < 2; ++sub) {
-    k_r2_inject<LAT, ST><<<grid_of(g.nf), 256, 0, st>>>(g, r->ph, g0, g1, sub ? 0.0 : 0.5, sub ? 1.0 : 0.5, ftag, ghost);
+    k_r2_inject<LAT, ST><<<grid_of(g.ns), 256, 0, st>>>(g, r->ph, g0, g1, sub ? 0.0 : 0.5, sub ? 1.0 : 0.5, ftag, ghost);
     f->ops->step(f, st);
     if (f->schedule == LSB_SCHED_OVERLAP) (void)hipStreamWaitEvent(st, f->ev_bulk_done, 0);
   }
@@ -353,6 +516,51 @@ void r2_init_coarse(lsb_ref2* r, const double* phi, const double* rho, const dou
                                                    reinterpret_cast<double*>(r->ws + r->off_f[0]),
                                                    reinterpret_cast<uint8_t*>(r->ws + r->off_kc),
                                                    reinterpret_cast<double*>(r->ws + r->off_g[0]));
+}
+
+// Re-meshing of the fine level onto the box now in r->g, moved by d coarse
+// nodes: the shifted or new state into the plan's other buffers, which then
+// become the current ones (both moment buffers equal), the level set into
+// phi and both RK3 buffers, the initial centroid moved; then the plan's
+// tags, band, geometry, lists and interface records are built again.
+template <int LAT, int ST>
+void r2_remesh_fine(lsb_ref2* r, const int* d, hipStream_t st) {
+  using Dr = lsb::Driver<LAT, ST>;
+  using R = typename lsb::Step<LAT, ST>::R;
+  lsb_plan* f = r->fine;
+  const typename lsb::Step<LAT, ST>::Args a = Dr::args(f, f->cur);
+  k_r2_remesh_fine<LAT, ST><<<grid_of(r->g.nf), 256, 0, st>>>(
+      r->g, r->ph, d[0], d[1], d[2], reinterpret_cast<const double*>(r->ws + r->off_f[r->cur]),
+      reinterpret_cast<const uint8_t*>(r->ws + r->off_kc), a);
+  f->cur ^= 1;
+  const size_t N = (size_t)f->N, rb = sizeof(R);
+  (void)hipMemcpyAsync(f->ws + f->off_M[f->cur ^ 1], f->ws + f->off_M[f->cur], 10 * N * rb, hipMemcpyDeviceToDevice, st);
+  (void)hipMemcpyAsync(f->ws + f->off_phi, f->ws + f->off_s1, N * rb, hipMemcpyDeviceToDevice, st);
+  (void)hipMemcpyAsync(f->ws + f->off_s2, f->ws + f->off_s1, N * rb, hipMemcpyDeviceToDevice, st);
+  k_r2_shift_xc0<<<1, 64, 0, st>>>(reinterpret_cast<double*>(f->ws + f->off_scal), lsb::SC_XC0, 2.0 * d[0],
+                                   2.0 * d[1], 2.0 * d[2]);
+  f->ops->rebuild(f, st);
+  f->ops->pack(f, st);
+  k_r2_perimeter_sets<LAT><<<grid_of(r->g.nb), 256, 0, st>>>(
+      r->g, r->ph, reinterpret_cast<const double*>(r->ws + r->off_f[r->cur]),
+      reinterpret_cast<const uint8_t*>(r->ws + r->off_kc), reinterpret_cast<double*>(r->ws + r->off_g[r->gcur]));
+  k_r2_band<<<grid_of(r->g.nf), 256, 0, st>>>(r->g, reinterpret_cast<const uint8_t*>(f->ws + f->off_tag),
+                                               reinterpret_cast<int*>(r->ws + r->off_flag));
+}
+
+using RemeshFn = void (*)(lsb_ref2*, const int*, hipStream_t);
+template <int LAT>
+RemeshFn remesh_fn(int storage) {
+  switch (storage) {
+    case LSB_F64: return r2_remesh_fine<LAT, LSB_F64>;
+    case LSB_F32: return r2_remesh_fine<LAT, LSB_F32>;
+    case LSB_F16DEV: return r2_remesh_fine<LAT, LSB_F16DEV>;
+    default: return r2_remesh_fine<LAT, LSB_BF16DEV>;
+  }
+}
+RemeshFn remesh_fn(int lattice, int storage) {
+  return lattice == LSB_D2Q9 ? remesh_fn<LSB_D2Q9>(storage)
+                             : (lattice == LSB_D3Q19 ? remesh_fn<LSB_D3Q19>(storage) : remesh_fn<LSB_D3Q27>(storage));
 }
 
 using StepFn = void (*)(lsb_ref2*, hipStream_t);
@@ -420,6 +628,8 @@ int lsb_ref2_create(const lsb_params* P, const int* box, lsb_ref2** out) {
   g.nb = (long)g.bw * g.bh * (D == 3 ? g.b[5] - g.b[4] + 1 : 1);
   g.fx = Pf.nx; g.fy = Pf.ny; g.fz = Pf.nz;
   g.nf = (long)Pf.nx * Pf.ny * Pf.nz;
+  // surface nodes: all minus the interior block (in 2D the one z plane)
+  g.ns = g.nf - (long)(Pf.nx - 2) * (Pf.ny - 2) * (D == 3 ? Pf.nz - 2 : 1);
   Phys& ph = r->ph;
   for (int k = 0; k < 2; ++k) {
     ph.tc[k] = P->tau[k];
@@ -441,7 +651,7 @@ int lsb_ref2_create(const lsb_params* P, const int* box, lsb_ref2** out) {
   for (int b = 0; b < 2; ++b) r->off_f[b] = take((size_t)r->Q * g.nc * sizeof(double));
   r->off_kc = take((size_t)g.nc);
   for (int b = 0; b < 2; ++b) r->off_g[b] = take((size_t)r->Q * g.nb * sizeof(double));
-  r->off_flag = take(sizeof(int));
+  r->off_flag = take(sizeof(int) * 32);  // band flag [0], sensor bounds [16..21]
   r->off_fine = o;
   r->total = o + fine->total;
   *out = r;
@@ -529,6 +739,71 @@ int lsb_ref2_step(lsb_ref2* r, int nsteps, void* stream) {
 }
 
 long lsb_ref2_step_count(const lsb_ref2* r) { return r ? r->nstep : -1; }
+
+int lsb_ref2_get_box(const lsb_ref2* r, int* box) {
+  if (!r || !box) return fail(LSB_EINVAL, "null argument");
+  for (int a = 0; a < 6; ++a) box[a] = r->g.b[a];
+  return LSB_OK;
+}
+
+int lsb_ref2_sensor(lsb_ref2* r, double d_ref, int* box, void* stream) {
+  if (!r || !box) return fail(LSB_EINVAL, "null argument");
+  if (!r->inited) return fail(LSB_ESTATE, "no state");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int* dev = reinterpret_cast<int*>(r->ws + r->off_flag) + 16;
+  k_r2_sensor_init<<<1, 64, 0, st>>>(dev);
+  const char* phi = r->fine->ws + r->fine->off_phi;
+  if (r->storage == LSB_F64)
+    k_r2_sensor<double><<<grid_of(r->g.nf), 256, 0, st>>>(r->g, reinterpret_cast<const double*>(phi), d_ref, dev);
+  else
+    k_r2_sensor<float><<<grid_of(r->g.nf), 256, 0, st>>>(r->g, reinterpret_cast<const float*>(phi), d_ref, dev);
+  R2_HIP(hipGetLastError());
+  int lohi[6];
+  R2_HIP(hipMemcpyAsync(lohi, dev, sizeof(lohi), hipMemcpyDeviceToHost, st));
+  R2_HIP(hipStreamSynchronize(st));
+  const Geo& g = r->g;
+  for (int a = 0; a < 6; ++a) box[a] = g.b[a];
+  if (lohi[3] < 0) return LSB_OK;
+  const int n[3] = {g.nx, g.ny, g.nz};
+  for (int a = 0; a < r->D; ++a) {
+    // the tagged cells' bounding box centred: origin round(b0 + (lo + hi) / 4
+    // - E / 2), counted in quarter nodes, clamped one node inside the grid
+    const int E = g.b[2 * a + 1] - g.b[2 * a];
+    const long q4 = 4L * g.b[2 * a] + lohi[a] + lohi[3 + a] - 2L * E + 2;
+    long b0 = q4 >= 0 ? q4 / 4 : -((-q4 + 3) / 4);
+    b0 = std::max<long>(1, std::min<long>(b0, n[a] - 2 - E));
+    box[2 * a] = (int)b0;
+    box[2 * a + 1] = (int)b0 + E;
+  }
+  return LSB_OK;
+}
+
+int lsb_ref2_remesh(lsb_ref2* r, const int* box, void* stream) {
+  if (!r || !box) return fail(LSB_EINVAL, "null argument");
+  if (!r->inited) return fail(LSB_ESTATE, "lsb_ref2_remesh before lsb_ref2_init");
+  Geo& g = r->g;
+  const int n[3] = {g.nx, g.ny, g.nz};
+  int d[3] = {0, 0, 0};
+  for (int a = 0; a < r->D; ++a) {
+    if (box[2 * a + 1] - box[2 * a] != g.b[2 * a + 1] - g.b[2 * a])
+      return fail(LSB_EINVAL, "re-meshing keeps the box extents");
+    if (box[2 * a] < 1 || box[2 * a + 1] > n[a] - 2)
+      return fail(LSB_EINVAL, "box must keep one coarse node to every grid face");
+    d[a] = box[2 * a] - g.b[2 * a];
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  for (int a = 0; a < r->D; ++a) {
+    g.b[2 * a] = box[2 * a];
+    g.b[2 * a + 1] = box[2 * a + 1];
+  }
+  remesh_fn(r->lattice, r->storage)(r, d, st);
+  R2_HIP(hipGetLastError());
+  int flag = 0;
+  R2_HIP(hipMemcpyAsync(&flag, r->ws + r->off_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  R2_HIP(hipStreamSynchronize(st));
+  if (flag) return fail(LSB_EBAND, "the level-set band is not inside the refined box with 3 fine cells to spare");
+  return LSB_OK;
+}
 
 int lsb_ref2_get_coarse(lsb_ref2* r, double* pop, uint8_t* phase, void* stream) {
   if (!r) return fail(LSB_EINVAL, "null handle");

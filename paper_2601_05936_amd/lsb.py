@@ -57,6 +57,7 @@ EXPORTS = [
     "lsb_ref_sensor_seeded",
     "lsb_ref2_create", "lsb_ref2_destroy", "lsb_ref2_workspace_bytes", "lsb_ref2_bind", "lsb_ref2_fine_shape",
     "lsb_ref2_fine", "lsb_ref2_init", "lsb_ref2_step", "lsb_ref2_step_count", "lsb_ref2_get_coarse",
+    "lsb_ref2_get_box", "lsb_ref2_sensor", "lsb_ref2_remesh",
 ]
 
 
@@ -147,6 +148,9 @@ def load() -> C.CDLL:
     lib.lsb_ref2_step_count.argtypes = [vp]
     lib.lsb_ref2_step_count.restype = C.c_long
     lib.lsb_ref2_get_coarse.argtypes = [vp, vp, vp, vp]
+    lib.lsb_ref2_get_box.argtypes = [vp, C.POINTER(C.c_int)]
+    lib.lsb_ref2_sensor.argtypes = [vp, C.c_double, C.POINTER(C.c_int), vp]
+    lib.lsb_ref2_remesh.argtypes = [vp, C.POINTER(C.c_int), vp]
     _lib = lib
     return lib
 
@@ -641,8 +645,28 @@ class TwoPhaseRefine:
     def nstep(self) -> int:
         return self.lib.lsb_ref2_step_count(self.h)
 
+    @property
+    def current_box(self):
+        out = (C.c_int * 6)()
+        _check(self.lib.lsb_ref2_get_box(self.h, out))
+        return tuple(out)
+
+    def sensor(self, d_ref: float):
+        """The box (6 ints) that the level-set sensor moves the refined box to."""
+        out = (C.c_int * 6)()
+        _check(self.lib.lsb_ref2_sensor(self.h, float(d_ref), out, self.stream()))
+        return tuple(out)
+
+    def remesh(self, box):
+        """Re-mesh onto a box of the same extents (6 ints; ka, kb ignored in 2D)."""
+        b = (tuple(int(v) for v in box) + (0, 0))[:6]
+        _check(self.lib.lsb_ref2_remesh(self.h, (C.c_int * 6)(*b), self.stream()))
+        self.box = b
+        return self
+
     def coarse(self, as_numpy=True):
-        """(populations [Q, nz, ny, nx], phases [nz, ny, nx]) of the coarse grid."""
+        """(populations [Q, nz, ny, nx], phases [nz, ny, nx]) of the coarse grid
+        (covered nodes hold the fine state restricted to the coarse level)."""
         t = self.torch
         pop = t.empty(self.Q * self.n_coarse, dtype=t.float64, device=self.device)
         ph = t.empty(self.n_coarse, dtype=t.uint8, device=self.device)

@@ -136,3 +136,86 @@ def test_band_check(require_gpu, cx, refused):
         assert e.value.code == LSB_EBAND
     else:
         g.step(1)
+
+
+def compare_all_coarse(o, g, label):
+    """Every coarse node (covered ones hold the restricted fine state)."""
+    import oracle as O
+    Q = o.Q
+    wq = O.lattice(o.p["lattice"])[3].reshape((Q, 1, 1, 1))
+    po, ko = o.coarse()
+    pg, kg = g.coarse()
+    assert int(np.sum(ko != kg)) == 0, label
+    e = float(np.max(np.abs(pg - po))) / max(float(np.max(np.abs(po - wq))), 1e-12)
+    print(label, "coarse (all nodes) err", f"{e:.2e}", flush=True)
+    assert e <= TOL_F64
+
+
+RE_CASES = {
+    "moving2d": dict(lattice=W.D2Q9, n=(40, 64, 1), box=(6, 34, 10, 46), centre=(20.0, 26.0, 0.0), radius=5.1,
+                     rho_ratio=20.0, tau=(0.7, 0.9), sigma=3e-3, g=2e-5, u_amp=0.02, seed=3),
+    "carried2d": dict(lattice=W.D2Q9, n=(56, 48, 1), box=(8, 34, 10, 36), centre=(21.3, 23.2, 0.0), radius=5.0,
+                      rho_ratio=10.0, tau=(0.8, 0.8), sigma=1e-2, uniform=(0.02, 0.01, 0.0)),
+    "bubble3d_q27": dict(lattice=W.D3Q27, n=(26, 24, 24), box=(3, 22, 3, 20, 3, 20), centre=(12.4, 11.3, 11.6),
+                         radius=2.1, rho_ratio=50.0, tau=(0.6, 1.0), sigma=5e-3, g=1e-5, u_amp=0.01, seed=7),
+}
+
+
+@pytest.mark.parametrize("case", list(RE_CASES))
+def test_remesh_parity_f64(require_gpu, case):
+    """Steps, the level-set sensor (its box compared with the oracle's), a
+    re-mesh onto it (a one-node shift when the sensor keeps the box), steps
+    again, three times; both levels vs the oracle after every phase."""
+    import oracle as O
+    from tests.test_gpu_parity import compare
+    from paper_2601_05936_amd.lsb import TwoPhaseRefine
+    kw = dict(RE_CASES[case])
+    U = kw.pop("uniform", None)
+    w = W.two_level_bubble(**kw)
+    if U is not None:
+        w["u_c"][:] = U
+        w["u_f"][:] = U
+    args = [w[k] for k in ("phi_c", "rho_c", "u_c", "phi_f", "rho_f", "u_f")]
+    o = O.TwoPhaseRefineOracle(w["params"], w["box"]).init(*args)
+    g = TwoPhaseRefine(w["params"], w["box"]).init(*args)
+    three = kw["lattice"] != W.D2Q9
+    steps = 8 if three else 30
+    for cycle in range(3):
+        o.step(steps)
+        g.step(steps)
+        bo, bg = o.sensor(2.0), g.sensor(2.0)
+        assert tuple(bo) == tuple(bg), (bo, bg)
+        nb = list(bo)
+        if tuple(nb) == tuple(g.current_box):
+            s = 1 if cycle % 2 == 0 else -1
+            nb = [nb[0] + s, nb[1] + s, nb[2], nb[3], nb[4] + (s if three else 0), nb[5] + (s if three else 0)]
+        o.remesh(nb)
+        g.remesh(nb)
+        assert tuple(g.current_box) == tuple(o.current_box)
+        compare_all_coarse(o, g, f"{case} cycle {cycle} after re-mesh")
+        compare(o.fine, g.fine, TOL_F64, f"{case} cycle {cycle} fine after re-mesh")
+    o.step(steps)
+    g.step(steps)
+    compare_all_coarse(o, g, f"{case} end")
+    compare(o.fine, g.fine, TOL_F64, f"{case} fine end")
+
+
+def test_remesh_onto_the_same_box_is_a_no_op(require_gpu):
+    """On the GPU as in the oracle's pin: a re-mesh onto the current box
+    leaves the run unchanged to rounding."""
+    from paper_2601_05936_amd.lsb import TwoPhaseRefine
+    w, steps = build("moving2d")
+    args = [w[k] for k in ("phi_c", "rho_c", "u_c", "phi_f", "rho_f", "u_f")]
+    a = TwoPhaseRefine(w["params"], w["box"]).init(*args)
+    b = TwoPhaseRefine(w["params"], w["box"]).init(*args)
+    a.step(20)
+    b.step(20)
+    b.remesh(w["box"])
+    a.step(20)
+    b.step(20)
+    pa, ka = a.coarse()
+    pb_, kb = b.coarse()
+    assert np.array_equal(ka, kb)
+    assert np.max(np.abs(pa - pb_)) < 1e-13
+    assert np.max(np.abs(a.fine.populations() - b.fine.populations())) < 1e-13
+    assert np.array_equal(a.fine.interface()["tags"], b.fine.interface()["tags"])
