@@ -219,3 +219,55 @@ def test_remesh_onto_the_same_box_is_a_no_op(require_gpu):
     assert np.max(np.abs(pa - pb_)) < 1e-13
     assert np.max(np.abs(a.fine.populations() - b.fine.populations())) < 1e-13
     assert np.array_equal(a.fine.interface()["tags"], b.fine.interface()["tags"])
+
+
+RS_MOVING_MISS = pytest.mark.xfail(strict=False, reason=(
+    "above the storage target on the 2D bubble moved by a seeded flow of 0.02 over 120 coarse steps "
+    "(240 fine): FP16-deviation 3.2e-3 in u (target 2e-3), BF16 4.5e-2 (bar 1.6e-2); the still droplet "
+    "and the 3D bubble meet both"))
+
+
+def _storage_params():
+    from tests.test_gpu_precision import FP32_MISS
+    out = []
+    for case in ("droplet2d", "bubble3d_q27", "moving2d"):
+        for st in (W.F32, W.F16DEV, W.BF16DEV):
+            marks = []
+            if st == W.F32:
+                marks.append(FP32_MISS)
+            elif case == "moving2d":
+                marks.append(RS_MOVING_MISS)
+            out.append(pytest.param(case, st, marks=marks))
+    return out
+
+
+@pytest.mark.parametrize("case,storage", _storage_params())
+def test_two_level_reduced_storage(require_gpu, case, storage):
+    """The fine level in FP32, FP16-deviation or BF16-deviation storage (FP32
+    arithmetic; the coarse grid stays FP64) against the FP64 oracle: the
+    fine fields within the storage's target (the measure of
+    test_gpu_precision: FP32 1e-5, FP16 2e-3, BF16 1.6e-2), the coarse
+    populations within the same bar of their deviation scale, tags and
+    coarse phases exact."""
+    import oracle as O
+    from tests.test_gpu_precision import TARGETS, errors
+    from paper_2601_05936_amd.lsb import TwoPhaseRefine
+    w, steps = build(case)
+    args = [w[k] for k in ("phi_c", "rho_c", "u_c", "phi_f", "rho_f", "u_f")]
+    o = O.TwoPhaseRefineOracle(w["params"], w["box"]).init(*args)
+    o.step(steps)
+    g = TwoPhaseRefine(dict(w["params"], storage=storage), w["box"]).init(*args)
+    g.step(steps)
+    Q = o.Q
+    wq = O.lattice(w["params"]["lattice"])[3].reshape((Q, 1, 1, 1))
+    po, ko = o.coarse()
+    pg, kg = g.coarse()
+    ec = float(np.max(np.abs(pg - po))) / max(float(np.max(np.abs(po - wq))), 1e-12)
+    pf = o.fine.p
+    eta_l = (pf["tau"][0] - 0.5) / 3.0
+    e = errors(o.fine, g.fine, pf, 1e-3 * max(pf["sigma"], 1e-4) / eta_l)
+    print(case, "storage", storage, "coarse", f"{ec:.2e}", e, "target", TARGETS[storage], flush=True)
+    assert int(np.sum(ko != kg)) == 0 and e["tags"] == 0
+    assert ec <= TARGETS[storage]
+    for k in ("pop", "rho", "u", "phi"):
+        assert e[k] <= TARGETS[storage], (k, e)
