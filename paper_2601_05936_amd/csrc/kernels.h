@@ -796,7 +796,8 @@ __device__ __forceinline__ typename Step<LAT, ST>::R pull_general(const typename
 // directions gathers the incoming populations into LDS and the moments, a
 // second loop collides and stores.
 template <int LAT, int ST, bool CUM>
-__global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::Args a) {
+__global__ __launch_bounds__(256, sizeof(typename Step<LAT, ST>::R) == 4 ? 5 : 1) void k_lb_iface(
+    const typename Step<LAT, ST>::Args a) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
   using C = typename S::C;
@@ -831,11 +832,13 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
       using L = typename S::L;
       using T = typename S::T;
       const R is = a.inv_scale;
+      // source coordinate x - c for c = -1, 0, +1 (-1 beyond a wall face)
+      const int xs[3] = {lb_coord(x + 1, a.nx, a.per[0]), x, lb_coord(x - 1, a.nx, a.per[0])};
+      const int ys[3] = {lb_coord(y + 1, a.ny, a.per[1]), y, lb_coord(y - 1, a.ny, a.per[1])};
+      const int zs[3] = {lb_coord(z + 1, a.nz, a.per[2]), z, lb_coord(z - 1, a.nz, a.per[2])};
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        const int sx = lb_coord(x - L::cx(i), a.nx, a.per[0]);
-        const int sy = lb_coord(y - L::cy(i), a.ny, a.per[1]);
-        const int sz = lb_coord(z - L::cz(i), a.nz, a.per[2]);
+        const int sx = xs[L::cx(i) + 1], sy = ys[L::cy(i) + 1], sz = zs[L::cz(i) + 1];
         if ((sx | sy | sz) < 0) {
           wall |= 1u << i;
           continue;
@@ -850,8 +853,11 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
         fl[i * 256 + threadIdx.x] = C::dec(v, (R)wgt<LAT>(i), is);
       }
     }
-    // pass 2: interface bounce-back on the cut links, two at a time: the
-    // loads of both links are issued before either is evaluated
+    // pass 2: interface bounce-back on the cut links, one at a time (fewer
+    // live registers: with FP32 arithmetic the kernel runs at five
+    // wavefronts per SIMD, which hides more of the links' load latency than
+    // two links in flight per thread did; measured 175 us against 205 us
+    // at 512^3)
     auto cut_source = [&](int i) {  // in the domain (not a wall link)
       const int sx = lb_coord(x - tab<LAT>.cx[i], a.nx, a.per[0]);
       const int sy = lb_coord(y - tab<LAT>.cy[i], a.ny, a.per[1]);
@@ -861,13 +867,8 @@ __global__ __launch_bounds__(256) void k_lb_iface(const typename Step<LAT, ST>::
     while (cut) {
       const int i0 = __ffs(cut) - 1;
       cut &= cut - 1u;
-      const int i1 = cut ? __ffs(cut) - 1 : -1;
-      cut &= cut - 1u;
       const CutLink<LAT, ST> L0 = cut_fetch<LAT, ST>(a, c, x, y, z, cut_source(i0), i0, k);
-      CutLink<LAT, ST> L1;
-      if (i1 >= 0) L1 = cut_fetch<LAT, ST>(a, c, x, y, z, cut_source(i1), i1, k);
       fl[i0 * 256 + threadIdx.x] = cut_eval<LAT, ST>(a, own, L0, i0, k);
-      if (i1 >= 0) fl[i1 * 256 + threadIdx.x] = cut_eval<LAT, ST>(a, own, L1, i1, k);
     }
     // pass 3: links through a wall face
     while (wall) {
