@@ -19,6 +19,7 @@ enum : uint8_t {
   T_SPEC = 4,     // has a lattice link to a cell of the other phase
   T_WALL = 8,     // has a lattice link through a wall face (static)
   T_OLDGAS = 16,  // phase before the last classification (refill)
+  T_XWALL = 32,   // 3D: lattice links through x faces only (the bulk kernel takes them, static)
 };
 
 // ---------------------------------------------------------------------------

@@ -172,23 +172,38 @@ struct Driver {
   // bulk collide-stream launch (with or without the body-force terms).  The
   // FP32-storage kernel reserves 32 KB of LDS per block it does not use: that
   // holds it at five blocks per CU, where its 54 streams run at 5.4 TB/s
-  // against 4.7 TB/s at the full eight (measured); FP16 is fastest at eight,
-  // FP64 is held at four by its registers.
+  // against 4.7 TB/s at the full eight (measured); FP16 runs at seven (its
+  // 66 registers; forcing eight spills and is 2.7% slower, holding it at six
+  // or five is slower too), FP64 is held at four by its registers.
+  // With wall faces in x (3D) the kernel also takes the x-face cells
+  // (XW, T_XWALL).
+  template <bool SPLIT, bool CUM, bool XW>
+  static void bulk_launch(const Args& a, bool force, unsigned g, size_t dyn, int xchunks, hipStream_t st) {
+    if (force) k_lb_bulk<LAT, ST, SPLIT, true, CUM, XW><<<g, 256, dyn, st>>>(a, xchunks);
+    else k_lb_bulk<LAT, ST, SPLIT, false, CUM, XW><<<g, 256, dyn, st>>>(a, xchunks);
+  }
+  static bool xwall(const Args& a) { return LAT != LSB_D2Q9 && !a.per[0] && a.bcf[0] != kFaceInject; }
   template <bool SPLIT>
   static void bulk(const Args& a, bool force, int xchunks, int rows, hipStream_t st) {
     // whole 256-cell row chunks when nx allows, else consecutive cells
     if (xchunks * 256 != a.nx) xchunks = 0;
     const unsigned g = xchunks ? (unsigned)(xchunks * rows) : (unsigned)(((long)a.N + 255) / 256);
     const size_t dyn = ST == LSB_F32 ? 32768 : 0;
+    const bool xw = xwall(a);
     if constexpr (LAT == LSB_D3Q27) {
       if (a.cum[0] || a.cum[1]) {
-        if (force) k_lb_bulk<LAT, ST, SPLIT, true, true><<<g, 256, dyn, st>>>(a, xchunks);
-        else k_lb_bulk<LAT, ST, SPLIT, false, true><<<g, 256, dyn, st>>>(a, xchunks);
+        if (xw) bulk_launch<SPLIT, true, true>(a, force, g, dyn, xchunks, st);
+        else bulk_launch<SPLIT, true, false>(a, force, g, dyn, xchunks, st);
         return;
       }
     }
-    if (force) k_lb_bulk<LAT, ST, SPLIT, true, false><<<g, 256, dyn, st>>>(a, xchunks);
-    else k_lb_bulk<LAT, ST, SPLIT, false, false><<<g, 256, dyn, st>>>(a, xchunks);
+    if constexpr (LAT != LSB_D2Q9) {
+      if (xw) {
+        bulk_launch<SPLIT, false, true>(a, force, g, dyn, xchunks, st);
+        return;
+      }
+    }
+    bulk_launch<SPLIT, false, false>(a, force, g, dyn, xchunks, st);
   }
 
   // wall-adjacent cells: the two z planes streamed (k_lb_zwall) where the
@@ -247,8 +262,14 @@ struct Driver {
       bulk<true>(a, force, xchunks, rows, p->side);
       timing_end(p, p->side);
       (void)hipEventRecord(p->ev_bulk_done, p->side);
-      if (cum) k_lb_band<LAT, ST, true><<<p->grid_tiles, 256, 0, st>>>(a);
-      else k_lb_band<LAT, ST, false><<<p->grid_tiles, 256, 0, st>>>(a);
+      const bool xw = xwall(a);
+      if (cum) {
+        if (xw) k_lb_band<LAT, ST, true, true><<<p->grid_tiles, 256, 0, st>>>(a);
+        else k_lb_band<LAT, ST, true, false><<<p->grid_tiles, 256, 0, st>>>(a);
+      } else {
+        if (xw) k_lb_band<LAT, ST, false, true><<<p->grid_tiles, 256, 0, st>>>(a);
+        else k_lb_band<LAT, ST, false, false><<<p->grid_tiles, 256, 0, st>>>(a);
+      }
     } else {
       timing_begin(p, st);
       bulk<false>(a, force, xchunks, rows, st);

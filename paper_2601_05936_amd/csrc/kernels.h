@@ -379,11 +379,45 @@ __device__ __forceinline__ void for_tile_cells(const Args& a, const int* list, i
   }
 }
 
+// The wall rule's source of link i at a cell on the x face that the link
+// crosses (face 0 for c_x = +1, face 1 for c_x = -1), as an element offset
+// into the populations: the own cell's opposite population at a no-slip
+// face, the mirrored direction (-c_x, c_y, c_z) at the cell's own x in the
+// source row (mirror_cell: element offset of (x, y - c_y, z - c_z)) at a
+// free-slip face.
+template <int LAT, class Args>
+__device__ __forceinline__ size_t xwall_source(const Args& a, int i, int c, size_t mirror_cell) {
+  using L = Lat<LAT>;
+  const int face = L::cx(i) > 0 ? 0 : 1;
+  if (sel6(a.bcf, face) == LSB_NOSLIP) return pop_dir<LAT>(opp<LAT>(i), a.N) + pop_cell<LAT>(c);
+  return pop_dir<LAT>(dir_of<LAT>(-L::cx(i), L::cy(i), L::cz(i)), a.N) + mirror_cell;
+}
+// ... and the moving-wall term added at a no-slip face (zero at a free-slip
+// one), 6 w_i (c_i . u_wall) as in wall_pull.
+template <int LAT, class R, class Args>
+__device__ __forceinline__ R xwall_term(const Args& a, int i) {
+  using L = Lat<LAT>;
+  const int face = L::cx(i) > 0 ? 0 : 1;
+  if (sel6(a.bcf, face) != LSB_NOSLIP) return (R)0;
+  const R cu = (R)L::cx(i) * WALLU(a, face, 0) + (R)L::cy(i) * WALLU(a, face, 1) + (R)L::cz(i) * WALLU(a, face, 2);
+  return (R)6 * (R)wgt<LAT>(i) * cu;
+}
+
 // ---------------------------------------------------------------------------
 // a2 for one cell with no lattice link to the other phase or through a wall:
 // branch-free gather (per-direction base pointer plus a 32-bit cell offset).
+// XW (3D grids with wall faces in x): cells tagged T_XWALL, whose only
+// links through a wall cross an x face, are taken here too (every cell on
+// an x face that reaches this point is one: the others are on the wall or
+// interface lists).  On a link crossing the face the lane loads the wall
+// rule's source instead (halfway bounce-back: the own cell's opposite
+// population, plus the moving-wall term; free slip: the mirrored direction
+// at (x, y - c_y, z - c_z)), so the gather stays one load per direction
+// without divergence, and the rows stay coalesced, which the wall list
+// cannot do for x faces (stride of a row).  The expressions are those of
+// wall_pull.
 // ---------------------------------------------------------------------------
-template <int LAT, int ST, bool FORCE = true, bool CUM = true>
+template <int LAT, int ST, bool FORCE = true, bool CUM = true, bool XW = false>
 __device__ __forceinline__ void fast_cell(const typename Step<LAT, ST>::Args& a, int c, int x, int y, int z, uint8_t t) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
@@ -424,6 +458,15 @@ __device__ __forceinline__ void fast_cell(const typename Step<LAT, ST>::Args& a,
     for (int k = 0; k < 3; ++k) xo[k] = pop_cell<LAT>(xs[k]);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
+      if constexpr (XW) {
+        if (L::cx(i) != 0) {
+          const size_t off = pop_dir<LAT>(i, a.N) + rb[L::cz(i) + 1][L::cy(i) + 1] + xo[L::cx(i) + 1];
+          const size_t woff = xwall_source<LAT>(a, i, c, rb[L::cz(i) + 1][L::cy(i) + 1] + xo[1]);
+          const bool cross = L::cx(i) > 0 ? x == 0 : x == a.nx - 1;
+          d[i] = C::dec(a.A[cross ? woff : off], (R)wgt<LAT>(i), is) + (cross ? xwall_term<LAT, R>(a, i) : (R)0);
+          continue;
+        }
+      }
       const T* __restrict__ Ai = a.A + pop_dir<LAT>(i, a.N);
       d[i] = C::dec(Ai[rb[L::cz(i) + 1][L::cy(i) + 1] + xo[L::cx(i) + 1]], (R)wgt<LAT>(i), is);
     }
@@ -431,6 +474,15 @@ __device__ __forceinline__ void fast_cell(const typename Step<LAT, ST>::Args& a,
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int sc = rowoff[L::cz(i) + 1][L::cy(i) + 1] + xs[L::cx(i) + 1];
+      if constexpr (XW && LAT != LSB_D2Q9) {
+        if (L::cx(i) != 0) {
+          const size_t off = pop_dir<LAT>(i, a.N) + pop_cell<LAT>(sc);
+          const size_t woff = xwall_source<LAT>(a, i, c, pop_cell<LAT>(rowoff[L::cz(i) + 1][L::cy(i) + 1] + x));
+          const bool cross = L::cx(i) > 0 ? x == 0 : x == a.nx - 1;
+          d[i] = C::dec(a.A[cross ? woff : off], (R)wgt<LAT>(i), is) + (cross ? xwall_term<LAT, R>(a, i) : (R)0);
+          continue;
+        }
+      }
       const T* __restrict__ Ai = a.A + pop_dir<LAT>(i, a.N);
       d[i] = C::dec(Ai[pop_cell<LAT>(sc)], (R)wgt<LAT>(i), is);
     }
@@ -483,8 +535,9 @@ __device__ __forceinline__ int tile_of(const Args& a, int x, int y, int z) {
 // xchunks > 0: blocks of 256 cells of one x-row (nx a multiple of 256);
 // xchunks == 0: blocks of 256 consecutive cells across rows (any nx, no idle
 // threads at the row ends).
-template <int LAT, int ST, bool SPLIT, bool FORCE, bool CUM>
-__global__ __launch_bounds__(256) void k_lb_bulk(const typename Step<LAT, ST>::Args a, int xchunks) {
+template <int LAT, int ST, bool SPLIT, bool FORCE, bool CUM, bool XW = false>
+__global__ __launch_bounds__(256, (XW && sizeof(typename Step<LAT, ST>::R) == 4) ? 7 : 1) void k_lb_bulk(
+    const typename Step<LAT, ST>::Args a, int xchunks) {
   const unsigned b = remap_xcd(blockIdx.x, gridDim.x);
   int c, x, y, z;
   if (xchunks > 0) {
@@ -505,19 +558,19 @@ __global__ __launch_bounds__(256) void k_lb_bulk(const typename Step<LAT, ST>::A
   if (SPLIT && a.cand_prev[tile_of<Step<LAT, ST>::D>(a, x, y, z)]) return;
   const uint8_t t = a.tag[c];
   if (t & (T_SPEC | T_WALL)) return;
-  fast_cell<LAT, ST, FORCE, CUM>(a, c, x, y, z, SPLIT ? (uint8_t)(t & ~T_ACT) : t);
+  fast_cell<LAT, ST, FORCE, CUM, XW>(a, c, x, y, z, SPLIT ? (uint8_t)(t & ~T_ACT) : t);
 }
 
 // Band part of the collide-stream: the non-interface, non-wall cells of the
 // candidate tiles of the previous step's classification (a superset of the
 // LS-active tiles; the moments of LS-active cells feed the level-set kernels
 // of the same step).
-template <int LAT, int ST, bool CUM>
+template <int LAT, int ST, bool CUM, bool XW = false>
 __global__ __launch_bounds__(256) void k_lb_band(const typename Step<LAT, ST>::Args a) {
   for_tile_cells<Step<LAT, ST>::D>(a, a.cand_list, a.counters[CNT_CAND], [&](int c, int x, int y, int z) {
     const uint8_t t = a.tag[c];
     if (t & (T_SPEC | T_WALL)) return;
-    fast_cell<LAT, ST, true, CUM>(a, c, x, y, z, t);
+    fast_cell<LAT, ST, true, CUM, XW>(a, c, x, y, z, t);
   });
 }
 
@@ -589,8 +642,12 @@ __global__ __launch_bounds__(256) void k_mark_walls(const typename Step<LAT, ST>
     const bool wx = !a.per[0] && (x == 0 || x == a.nx - 1);
     const bool wy = !a.per[1] && (y == 0 || y == a.ny - 1);
     const bool wz = !a.per[2] && (z == 0 || z == a.nz - 1);
-    const bool wall = wx || wy || wz;
-    a.tag[c] = (uint8_t)((a.tag[c] & ~T_WALL) | (wall ? T_WALL : 0));
+    // 3D cells with wall links through x faces only are left to the bulk
+    // kernel (T_XWALL; see fast_cell), the others are listed; the x faces of
+    // a refined box's level read its ghost array and stay on the list
+    const bool xonly = LAT != LSB_D2Q9 && wx && !wy && !wz && sel6(a.bcf, x == 0 ? 0 : 1) != kFaceInject;
+    const bool wall = (wx || wy || wz) && !xonly;
+    a.tag[c] = (uint8_t)((a.tag[c] & ~(T_WALL | T_XWALL)) | (wall ? T_WALL : 0) | (xonly ? T_XWALL : 0));
     // one append per wavefront, lanes in cell order: the list comes in runs
     // of consecutive cells, which the wall kernel reads coalesced
     const int slot = wave_append(&a.counters[CNT_WALL], wall);
@@ -1466,7 +1523,7 @@ __global__ __launch_bounds__(256) void k_classify(const typename Step<LAT, ST>::
           // bit is set afterwards by k_mark_walls
           const uint8_t told = record_flips ? tprev[it] : (uint8_t)ph;
           const int old = told & T_GAS;
-          tag0[(unsigned)((iz * a.ny + iy) * a.nx + ix)] = (uint8_t)(ph | (act ? T_ACT : 0) | (sp ? T_SPEC : 0) | (told & T_WALL) | (old ? T_OLDGAS : 0));
+          tag0[(unsigned)((iz * a.ny + iy) * a.nx + ix)] = (uint8_t)(ph | (act ? T_ACT : 0) | (sp ? T_SPEC : 0) | (told & (T_WALL | T_XWALL)) | (old ? T_OLDGAS : 0));
           act_any = act_any || act;
           fl = record_flips && ph != old;
         }

@@ -259,3 +259,35 @@ def test_streamed_z_wall_planes_against_oracle(require_gpu, lat, storage):
         bad = int(np.sum(((o.interface()["tags"] ^ s.interface()["tags"]) & 5) != 0))
         print("z walls", lat, storage, "pop", e, "tag mismatches", bad, flush=True)
         assert bad == 0 and e < 2e-3
+
+
+@pytest.mark.parametrize("lat", [W.D3Q19, W.D3Q27])
+@pytest.mark.parametrize("xwall", [W.NOSLIP, W.FREESLIP])
+@pytest.mark.parametrize("nx", [23, 256])
+def test_x_wall_faces_in_the_bulk_kernel(require_gpu, lat, xwall, nx):
+    """Wall faces in x (3D): the cells whose only wall links cross an x face
+    are collided by the bulk kernel (the gather wraps x, the face lanes
+    then apply the wall rule) instead of the wall list; the cells on the x
+    edges with y and z walls stay on the list.  No-slip x faces moving (with
+    free-slip y and no-slip z), or free-slip x faces; a bubble with gravity
+    and a seeded flow, rows of 23 cells (consecutive-cell blocks) and of 256
+    (row-chunk blocks); FP64 within 1e-10 of the oracle, tags exact."""
+    w = W.seeded_bubble(11, lattice=lat, shape=(nx, 13, 15), g=1e-4, u_amp=0.02)
+    p = dict(w["params"])
+    p["bc"] = [xwall, xwall, W.FREESLIP, W.FREESLIP, W.NOSLIP, W.NOSLIP]
+    wu = [[0.0] * 3 for _ in range(6)]
+    if xwall == W.NOSLIP:
+        wu[0] = [0.0, 0.01, -0.004]
+        wu[1] = [0.0, -0.006, 0.008]
+    wu[5] = [0.01, 0.0, 0.0]
+    p["wall_u"] = wu
+    O = _oracle()
+    o = O.Oracle(p, w["phi0"], rho0=w["rho0"], u0=w["u0"])
+    s = _sim()(p).init(w["phi0"], w["rho0"], w["u0"])
+    o.step(20)
+    s.step(20)
+    compare(o, s, TOL_F64, f"x walls lat={lat} bc={xwall} nx={nx}")
+    c = s.counts()
+    # the list holds only the y and z faces (x edges included)
+    ny, nz = 13, 15
+    assert c["wall_cells"] == 2 * nx * nz + 2 * nx * (ny - 2)
