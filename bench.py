@@ -34,20 +34,37 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # HBM bytes per launch of the bulk collide-stream kernel from rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs, scaled by a plain 4 GiB copy; recorded in
 # profiles/k_lb_bulk_wavy512_d3q27_f16dev_hbm_traffic.md with the hash of the
-# kernel sources they were taken with.  Reported only while the sources hash
-# to the same value (null once any kernel source has changed).
+# sources that kernel is built from.  Reported only while those sources hash
+# to the same value (null once any of them has changed).
 MEASURED_TRAFFIC = {"sources": None, ("f16dev", "serial", 512): None}
 
 
-def kernel_sources_hash() -> str:
-    """sha256 (first 16 hex digits) of the HIP sources of the library."""
-    import hashlib
+def kernel_sources() -> list:
+    """What the D3Q27 kernels and their launches are built from: the D3Q27
+    translation unit and the plan set-up with every header they include,
+    and the build flags (paths relative to the repository root)."""
+    import re
     d = os.path.join(ROOT, "paper_2601_05936_amd", "csrc")
+    todo = [os.path.join(d, "lsb_d3q27.hip"), os.path.join(d, "api.hip")]
+    seen = []
+    while todo:
+        f = os.path.normpath(todo.pop())
+        if f in seen:
+            continue
+        seen.append(f)
+        for inc in re.findall(r'^#include "([^"]+)"', open(f).read(), flags=re.M):
+            todo.append(os.path.join(os.path.dirname(f), inc))
+    seen.append(os.path.join(ROOT, "paper_2601_05936_amd", "build.py"))
+    return sorted(os.path.relpath(f, ROOT) for f in seen)
+
+
+def kernel_sources_hash() -> str:
+    """sha256 (first 16 hex digits) of kernel_sources()."""
+    import hashlib
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".h", ".hip")):
-            h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
+    for f in kernel_sources():
+        h.update(f.encode())
+        h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
 
 

@@ -354,3 +354,25 @@ def test_two_level_create_validates_without_a_device():
     # coarse populations twice (FP64) at least, plus the fine level's workspace
     assert nb.value > 2 * 9 * 48 * 48 * 8 + 2 * 9 * 57 * 57 * 8
     lib.lsb_ref2_destroy(h)
+
+
+def test_traffic_record_is_tied_to_the_bulk_kernel_sources():
+    """The benchmark reports counter traffic only for the sources it was
+    measured on: the hash covers the D3Q27 unit, every header it includes,
+    the plan set-up and the build flags, and nothing the kernel is not built
+    from."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    files = bench.kernel_sources()
+    for f in ("paper_2601_05936_amd/csrc/kernels.h", "paper_2601_05936_amd/csrc/common.h",
+              "paper_2601_05936_amd/csrc/driver.h", "paper_2601_05936_amd/csrc/plan.h",
+              "paper_2601_05936_amd/csrc/api.hip", "paper_2601_05936_amd/csrc/lsb_d3q27.hip",
+              "include/lsb.h", "paper_2601_05936_amd/build.py"):
+        assert f in files, f
+    assert not any(f.endswith(("refine.hip", "refine2.hip", "adjoint.h")) for f in files)
+    h = bench.kernel_sources_hash()
+    assert len(h) == 16 and h == bench.kernel_sources_hash()
+    if bench.MEASURED_TRAFFIC["sources"] != h:
+        assert bench.measured_traffic(("f16dev", "serial", 512)) is None

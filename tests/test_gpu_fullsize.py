@@ -4,10 +4,10 @@ stratified layer) in the launch configuration the benchmark times.
 The oracle cannot be copied out whole at this size, so populations, phi and
 tags are compared on sampled cells: every cell of four z-columns (through
 both phases and the interface) and 20000 seeded random cells.  FP64 path:
-1e-10 and identical tags as in the small parity tests; FP16-deviation path
-(the benchmark's headline storage, FP32 level set): within the precision
-pattern's 2e-3 target, identical phase and interface bits, LS-active bit
-differences only at the band edge.  The serial
+1e-10 and identical tags as in the small parity tests; FP32 and
+FP16-deviation paths (FP32 level set; FP16 is the benchmark's headline
+storage): within the precision pattern's targets (1e-5, 2e-3), identical
+phase and interface bits, LS-active bit differences only at the band edge.  The serial
 and overlap schedules are compared bit for bit over 12 steps (one
 reinitialisation included).  The 3D rising bubble (128x128x256 D3Q27,
 FP16-deviation) is compared with the FP64 oracle through its integrals.
@@ -58,7 +58,7 @@ def test_wavy_512_sampled_against_oracle(require_gpu):
     del o
     scale = np.max(np.abs(op))  # deviations f - w: reference state w
     res = {}
-    for st in (W.F64, W.F16DEV):
+    for st in (W.F64, W.F32, W.F16DEV):
         s = Sim(dict(p, storage=st)).init(torch.as_tensor(phi0.reshape(-1)).to("cuda:0"))
         s.step(steps)
         gp, gphi, gtag = _gpu_sample(s, cells)
@@ -76,10 +76,11 @@ def test_wavy_512_sampled_against_oracle(require_gpu):
         print("storage", st, res[st], flush=True)
     assert res[W.F64]["tags"] == 0
     assert res[W.F64]["pop"] < 1e-10 and res[W.F64]["phi"] < 1e-10
-    r16 = res[W.F16DEV]
-    assert r16["phase_iface"] == 0
-    assert r16["act_flips"] == 0 or r16["act_flip_min_abs_phi"] > p["band"] - 2.0
-    assert r16["pop"] < 2e-3 and r16["phi"] < 2e-3
+    for st, target in ((W.F32, 1e-5), (W.F16DEV, 2e-3)):
+        r = res[st]
+        assert r["phase_iface"] == 0, (st, r)
+        assert r["act_flips"] == 0 or r["act_flip_min_abs_phi"] > p["band"] - 2.0, (st, r)
+        assert r["pop"] < target and r["phi"] < target, (st, r)
 
 
 def test_wavy_512_overlap_schedule_bitwise(require_gpu):
