@@ -343,7 +343,7 @@ struct TileShape {
 };
 // largest tile plus one-cell halo, in cells, that the tile kernels accept
 constexpr int kClassifyLds = 1280;
-// candidate tiles per block batch of the classification kernel
+// most candidate tiles per block batch of the classification kernel
 constexpr int kClassifyBatch = 8;
 
 // Append for the lanes of a wavefront with pred set: one atomic per

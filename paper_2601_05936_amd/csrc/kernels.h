@@ -1384,8 +1384,8 @@ __global__ __launch_bounds__(256) void k_dilate(const typename Step<LAT, ST>::Ar
   }
 }
 
-// Candidate tiles are classified kClassifyBatch at a time per block, and the
-// block reserves the list slots of the whole batch with one atomic per list:
+// Candidate tiles are classified up to kClassifyBatch at a time per block, and
+// the block reserves the list slots of the whole batch with one atomic per list:
 // atomics on one counter from every block serialise on the device (about
 // 12 ns each on MI355X), so one per tile would cost more than the
 // classification itself.
@@ -1433,8 +1433,11 @@ __global__ __launch_bounds__(256) void k_classify(const typename Step<LAT, ST>::
   const int lane = threadIdx.x & 63;
   const R B = a.band;
   const R INVALID = (R)1e30;
-  for (int e0 = blockIdx.x * KT; e0 < count; e0 += gridDim.x * KT) {
-    const int nk = min(KT, count - e0);
+  // tiles per block: up to KT, fewer where the candidates would otherwise
+  // leave the GPU idle (small grids: about 1024 blocks, four per CU)
+  const int kb = min(KT, max(1, (count + 1023) / 1024));
+  for (int e0 = blockIdx.x * kb; e0 < count; e0 += gridDim.x * kb) {
+    const int nk = min(kb, count - e0);
     if ((int)threadIdx.x < nk) tiles[threadIdx.x] = a.cand_list[e0 + threadIdx.x];
     __syncthreads();
     unsigned sbits = 0u, fbits = 0u;  // bit k * ITER + it: spec / flipped cell
