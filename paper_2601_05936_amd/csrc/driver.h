@@ -279,8 +279,16 @@ struct Driver {
     // current LS-active tiles); their flags bound the next bulk part
     k_reset_counters<LAT, ST><<<1, 256, 0, st>>>(a, CNT_CAND, 1);
     k_dilate<LAT, ST><<<(p->ntiles + 255) / 256, 256, 0, st>>>(a, 0);
-    if (cum) k_lb_iface<LAT, ST, true><<<p->grid_cells, 256, 0, st>>>(a);
-    else k_lb_iface<LAT, ST, false><<<p->grid_cells, 256, 0, st>>>(a);
+    // grids below 2^25 cells: the interface kernel with lane groups for
+    // short lists (bit-identical results)
+    const bool lg = p->N < (1 << 25);
+    if (cum) {
+      if (lg) k_lb_iface<LAT, ST, true, true><<<p->grid_cells, 256, 0, st>>>(a);
+      else k_lb_iface<LAT, ST, true, false><<<p->grid_cells, 256, 0, st>>>(a);
+    } else {
+      if (lg) k_lb_iface<LAT, ST, false, true><<<p->grid_cells, 256, 0, st>>>(a);
+      else k_lb_iface<LAT, ST, false, false><<<p->grid_cells, 256, 0, st>>>(a);
+    }
     walls(p, a, cum, force, st);
     (void)hipEventRecord(p->ev_pop_done, st);
     const bool recording = p->adj.rec_slot >= 0;

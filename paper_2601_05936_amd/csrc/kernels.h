@@ -849,157 +849,235 @@ __device__ __forceinline__ typename Step<LAT, ST>::R pull_general(const typename
   return iface_pull<LAT, ST>(a, own, c, x, y, z, sc, i, k);
 }
 
-// a2-a4 for the listed interface-adjacent cells: a runtime loop over the
-// directions gathers the incoming populations into LDS and the moments, a
-// second loop collides and stores.
-template <int LAT, int ST, bool CUM>
-__global__ __launch_bounds__(256, sizeof(typename Step<LAT, ST>::R) == 4 ? 5 : 1) void k_lb_iface(
-    const typename Step<LAT, ST>::Args a) {
+// a2-a4 for the listed interface-adjacent cells, in two parts: the gather
+// of the incoming populations into LDS (column col of fl) and the collision.
+// G lanes share a cell (G = 1 or 4): lane sub gathers the directions
+// i = sub (mod G) and stores their post-collision populations; every lane
+// sums the moments over all directions from LDS in the same order, so the
+// result does not depend on G.
+template <int LAT, int ST, int G>
+__device__ __forceinline__ void iface_gather(const typename Step<LAT, ST>::Args& a,
+                                             const OwnCell<typename Step<LAT, ST>::R>& own, int c, int x, int y,
+                                             int z, int k, int sub, typename Step<LAT, ST>::R* fl, int col) {
+  using S = Step<LAT, ST>;
+  using R = typename S::R;
+  using C = typename S::C;
+  using L = typename S::L;
+  using T = typename S::T;
+  constexpr int Q = S::Q;
+  const size_t N = a.N;
+  // pass 1 (directions unrolled, all loads issued together): plain
+  // streaming from own-phase sources; cut links and links through a wall
+  // face are marked
+  unsigned cut = 0u, wall = 0u;
+  {
+    const R is = a.inv_scale;
+    // source coordinate x - c for c = -1, 0, +1 (-1 beyond a wall face)
+    const int xs[3] = {lb_coord(x + 1, a.nx, a.per[0]), x, lb_coord(x - 1, a.nx, a.per[0])};
+    const int ys[3] = {lb_coord(y + 1, a.ny, a.per[1]), y, lb_coord(y - 1, a.ny, a.per[1])};
+    const int zs[3] = {lb_coord(z + 1, a.nz, a.per[2]), z, lb_coord(z - 1, a.nz, a.per[2])};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (G > 1 && (i & (G - 1)) != sub) continue;
+      const int sx = xs[L::cx(i) + 1], sy = ys[L::cy(i) + 1], sz = zs[L::cz(i) + 1];
+      if ((sx | sy | sz) < 0) {
+        wall |= 1u << i;
+        continue;
+      }
+      const int sc = (sz * a.ny + sy) * a.nx + sx;
+      const uint8_t ts = a.tag[sc];
+      const T v = a.A[pidx<LAT>(i, sc, N)];
+      if ((ts & T_GAS) != k) {
+        cut |= 1u << i;
+        continue;
+      }
+      fl[i * 256 + col] = C::dec(v, (R)wgt<LAT>(i), is);
+    }
+  }
+  // pass 2: interface bounce-back on the cut links, one at a time (fewer
+  // live registers: with FP32 arithmetic the kernel runs at five
+  // wavefronts per SIMD, which hides more of the links' load latency than
+  // two links in flight per thread did; measured 175 us against 205 us
+  // at 512^3)
+  while (cut) {
+    const int i0 = __ffs(cut) - 1;
+    cut &= cut - 1u;
+    const int sx = lb_coord(x - tab<LAT>.cx[i0], a.nx, a.per[0]);
+    const int sy = lb_coord(y - tab<LAT>.cy[i0], a.ny, a.per[1]);
+    const int sz = lb_coord(z - tab<LAT>.cz[i0], a.nz, a.per[2]);
+    const CutLink<LAT, ST> L0 = cut_fetch<LAT, ST>(a, c, x, y, z, (sz * a.ny + sy) * a.nx + sx, i0, k);
+    fl[i0 * 256 + col] = cut_eval<LAT, ST>(a, own, L0, i0, k);
+  }
+  // pass 3: links through a wall face
+  while (wall) {
+    const int i = __ffs(wall) - 1;
+    wall &= wall - 1u;
+    fl[i * 256 + col] = pull_general<LAT, ST>(a, own, c, x, y, z, i, k);
+  }
+}
+
+template <int LAT, int ST, bool CUM, int G>
+__device__ __forceinline__ void iface_collide(const typename Step<LAT, ST>::Args& a, int c, int k, bool active,
+                                              int sub, const typename Step<LAT, ST>::R* fl, int col) {
   using S = Step<LAT, ST>;
   using R = typename S::R;
   using C = typename S::C;
   constexpr int Q = S::Q;
-  const int n = a.counters[CNT_SPEC];
-  const R s = a.scale;
   const size_t N = a.N;
+  const R s = a.scale;
+  R rp = 0, m0 = 0, m1 = 0, m2 = 0;
+#pragma unroll 1
+  for (int i = 0; i < Q; ++i) {
+    const R f = fl[i * 256 + col];
+    rp += f;
+    m0 += (R)tab<LAT>.cx[i] * f;
+    m1 += (R)tab<LAT>.cy[i] * f;
+    m2 += (R)tab<LAT>.cz[i] * f;
+  }
+  const R rho = sel2(a.rho_ref, k) + rp;  // deviations relative to w rho_ref[k]
+  const R inv = (R)1 / rho;
+  const R ux = m0 * inv, uy = m1 * inv, uz = m2 * inv;
+  const R uu = ux * ux + uy * uy + uz * uz;
+  const R om = sel2(a.omega, k);
+  const R fx = (R)3 * ACC(a, k, 0), fy = (R)3 * ACC(a, k, 1), fz = (R)3 * ACC(a, k, 2);
+  bool cum_phase = false;
+  if constexpr (LAT == LSB_D3Q27 && CUM) cum_phase = sel2(a.cum, k) != 0;
+  // strain-rate moments of the incoming populations (lane 0 of the cell's
+  // group); BGK stores here
+  const bool lead = sub == 0;
+  R P0 = 0, P1 = 0, P2 = 0, P3 = 0, P4 = 0, P5 = 0;
+#pragma unroll 1
+  for (int i = 0; i < Q; ++i) {
+    const bool mine = G == 1 || (i & (G - 1)) == sub;
+    if (!lead && !mine) continue;
+    const R f = fl[i * 256 + col];
+    const R w = tw<LAT, R>(i);
+    const R cx = (R)tab<LAT>.cx[i], cy = (R)tab<LAT>.cy[i], cz = (R)tab<LAT>.cz[i];
+    const R cu = cx * ux + cy * uy + cz * uz;
+    const R deq = w * (rp + rho * ((R)3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu));
+    const R fn = f - deq;
+    P0 += cx * cx * fn; P1 += cy * cy * fn; P2 += cz * cz * fn;
+    P3 += cx * cy * fn; P4 += cx * cz * fn; P5 += cy * cz * fn;
+    if (cum_phase || !mine) continue;
+    const R ca = cx * fx + cy * fy + cz * fz;
+    store_pop(&a.An[pidx<LAT>(i, c, N)], C::enc(f - om * fn + w * rho * ca, twinv<LAT, R>(i), s));
+  }
+  if constexpr (LAT == LSB_D3Q27 && CUM) {
+    if (cum_phase && lead) {
+      // the cumulant operator takes deviations from the rest state w_i
+      const R rm1 = sel2(a.rref_m1, k);
+      R dl[Q], out[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) dl[i] = fl[i * 256 + col] + (R)wgt<LAT>(i) * rm1;
+      cumulant_collide(dl, om, out);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) out[i] = out[i] - (R)wgt<LAT>(i) * rm1;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        using L = typename S::L;
+        R ca = 0;
+        if (L::cx(i)) ca += (R)L::cx(i) * fx;
+        if (L::cy(i)) ca += (R)L::cy(i) * fy;
+        if (L::cz(i)) ca += (R)L::cz(i) * fz;
+        store_pop(&a.An[pidx<LAT>(i, c, N)], C::enc(out[i] + (R)wgt<LAT>(i) * rho * ca, (R)(1.0 / wgt<LAT>(i)), s));
+      }
+    }
+  }
+  if (active && lead) {
+    const R fac = -(R)1.5 * om * inv;
+    a.Mn[c] = rp + sel2(a.rref_m1, k);  // rho - 1
+    a.Mn[N + c] = ux;
+    a.Mn[2 * N + c] = uy;
+    a.Mn[3 * N + c] = uz;
+    a.Mn[4 * N + c] = fac * P0;
+    a.Mn[5 * N + c] = fac * P1;
+    a.Mn[6 * N + c] = fac * P2;
+    a.Mn[7 * N + c] = fac * P3;
+    a.Mn[8 * N + c] = fac * P4;
+    a.Mn[9 * N + c] = fac * P5;
+  }
+}
+
+template <int LAT, int ST>
+__device__ __forceinline__ void iface_cell(const typename Step<LAT, ST>::Args& a, int c, int& x, int& y, int& z,
+                                           int& k, bool& active, OwnCell<typename Step<LAT, ST>::R>& own) {
+  x = c % a.nx;
+  y = (c / a.nx) % a.ny;
+  z = c / (a.nx * a.ny);
+  const uint8_t t = a.tag[c];
+  k = t & T_GAS;
+  active = (t & T_ACT) != 0;
+  const IfaceRec<typename Step<LAT, ST>::R> ro = load_rec(a, c);
+  own.phi = ro.v[0];
+#pragma unroll
+  for (int m = 0; m < 10; ++m) own.M[m] = ro.v[1 + m];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) own.G[m] = ro.v[11 + m];
+}
+
+// G lanes per cell, 256 / G cells per block and pass, the list split over
+// the XCDs as in xcd_list_span; every lane of a block runs the same passes
+// (the gather and the collision meet at a block barrier).
+template <int LAT, int ST, bool CUM, int G>
+__device__ __forceinline__ void iface_grouped(const typename Step<LAT, ST>::Args& a, int n,
+                                              typename Step<LAT, ST>::R* fl) {
+  constexpr int CPB = 256 / G;
+  const int col = (int)threadIdx.x / G, sub = (int)threadIdx.x & (G - 1);
+  int lo = 0, end = n, first = (int)blockIdx.x * CPB, stride = (int)gridDim.x * CPB;
+  if ((gridDim.x & 7u) == 0u) {
+    const int per = (n + 7) >> 3;
+    lo = (int)(blockIdx.x & 7u) * per;
+    end = min(n, lo + per);
+    first = lo + (int)(blockIdx.x >> 3) * CPB;
+    stride = (int)(gridDim.x >> 3) * CPB;
+  }
+  for (int base = first; base < end; base += stride) {
+    const int e = base + col;
+    const bool valid = e < end;
+    int c = 0, x = 0, y = 0, z = 0, k = 0;
+    bool active = false;
+    OwnCell<typename Step<LAT, ST>::R> own;
+    if (valid) {
+      c = a.spec_list[e];
+      iface_cell<LAT, ST>(a, c, x, y, z, k, active, own);
+      iface_gather<LAT, ST, G>(a, own, c, x, y, z, k, sub, fl, col);
+    }
+    __syncthreads();
+    if (valid) iface_collide<LAT, ST, CUM, G>(a, c, k, active, sub, fl, col);
+    __syncthreads();  // the next pass rewrites fl
+  }
+}
+
+// One lane per cell, or (LG, for grids whose interface lists do not fill
+// the GPU) four lanes per cell while the list has at most kIfaceLanes4 cells,
+// which splits the chain of dependent loads of a cell's cut links: 55 -> 46 us
+// per step for the bubble of radius 16 in 128x128x256.  LG is a separate
+// kernel because the group path costs the one-lane path registers (512^3:
+// 175 -> 181 us with both in one kernel).
+constexpr int kIfaceLanes4 = 65536;
+
+template <int LAT, int ST, bool CUM, bool LG>
+__global__ __launch_bounds__(256, sizeof(typename Step<LAT, ST>::R) == 4 ? 5 : 1) void k_lb_iface(
+    const typename Step<LAT, ST>::Args a) {
+  using R = typename Step<LAT, ST>::R;
+  constexpr int Q = Step<LAT, ST>::Q;
+  const int n = a.counters[CNT_SPEC];
   __shared__ R fl[Q * 256];
+  if constexpr (LG) {
+    if (n <= kIfaceLanes4) {
+      iface_grouped<LAT, ST, CUM, 4>(a, n, fl);
+      return;
+    }
+  }
   const ListSpan sp = xcd_list_span(n);
   for (int e = sp.e; e < sp.end; e += sp.stride) {
     const int c = a.spec_list[e];
-    const int x = c % a.nx;
-    const int y = (c / a.nx) % a.ny;
-    const int z = c / (a.nx * a.ny);
-    const uint8_t t = a.tag[c];
-    const int k = t & T_GAS;
-    const bool active = (t & T_ACT) != 0;
+    int x, y, z, k;
+    bool active;
     OwnCell<R> own;
-    {
-      const IfaceRec<R> ro = load_rec(a, c);
-      own.phi = ro.v[0];
-#pragma unroll
-      for (int m = 0; m < 10; ++m) own.M[m] = ro.v[1 + m];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) own.G[m] = ro.v[11 + m];
-    }
-    // pass 1 (directions unrolled, all loads issued together): plain
-    // streaming from own-phase sources; cut links and links through a wall
-    // face are marked
-    unsigned cut = 0u, wall = 0u;
-    {
-      using L = typename S::L;
-      using T = typename S::T;
-      const R is = a.inv_scale;
-      // source coordinate x - c for c = -1, 0, +1 (-1 beyond a wall face)
-      const int xs[3] = {lb_coord(x + 1, a.nx, a.per[0]), x, lb_coord(x - 1, a.nx, a.per[0])};
-      const int ys[3] = {lb_coord(y + 1, a.ny, a.per[1]), y, lb_coord(y - 1, a.ny, a.per[1])};
-      const int zs[3] = {lb_coord(z + 1, a.nz, a.per[2]), z, lb_coord(z - 1, a.nz, a.per[2])};
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const int sx = xs[L::cx(i) + 1], sy = ys[L::cy(i) + 1], sz = zs[L::cz(i) + 1];
-        if ((sx | sy | sz) < 0) {
-          wall |= 1u << i;
-          continue;
-        }
-        const int sc = (sz * a.ny + sy) * a.nx + sx;
-        const uint8_t ts = a.tag[sc];
-        const T v = a.A[pidx<LAT>(i, sc, N)];
-        if ((ts & T_GAS) != k) {
-          cut |= 1u << i;
-          continue;
-        }
-        fl[i * 256 + threadIdx.x] = C::dec(v, (R)wgt<LAT>(i), is);
-      }
-    }
-    // pass 2: interface bounce-back on the cut links, one at a time (fewer
-    // live registers: with FP32 arithmetic the kernel runs at five
-    // wavefronts per SIMD, which hides more of the links' load latency than
-    // two links in flight per thread did; measured 175 us against 205 us
-    // at 512^3)
-    auto cut_source = [&](int i) {  // in the domain (not a wall link)
-      const int sx = lb_coord(x - tab<LAT>.cx[i], a.nx, a.per[0]);
-      const int sy = lb_coord(y - tab<LAT>.cy[i], a.ny, a.per[1]);
-      const int sz = lb_coord(z - tab<LAT>.cz[i], a.nz, a.per[2]);
-      return (sz * a.ny + sy) * a.nx + sx;
-    };
-    while (cut) {
-      const int i0 = __ffs(cut) - 1;
-      cut &= cut - 1u;
-      const CutLink<LAT, ST> L0 = cut_fetch<LAT, ST>(a, c, x, y, z, cut_source(i0), i0, k);
-      fl[i0 * 256 + threadIdx.x] = cut_eval<LAT, ST>(a, own, L0, i0, k);
-    }
-    // pass 3: links through a wall face
-    while (wall) {
-      const int i = __ffs(wall) - 1;
-      wall &= wall - 1u;
-      fl[i * 256 + threadIdx.x] = pull_general<LAT, ST>(a, own, c, x, y, z, i, k);
-    }
-    R rp = 0, m0 = 0, m1 = 0, m2 = 0;
-#pragma unroll 1
-    for (int i = 0; i < Q; ++i) {
-      const R f = fl[i * 256 + threadIdx.x];
-      rp += f;
-      m0 += (R)tab<LAT>.cx[i] * f;
-      m1 += (R)tab<LAT>.cy[i] * f;
-      m2 += (R)tab<LAT>.cz[i] * f;
-    }
-    const R rho = sel2(a.rho_ref, k) + rp;  // deviations relative to w rho_ref[k]
-    const R inv = (R)1 / rho;
-    const R ux = m0 * inv, uy = m1 * inv, uz = m2 * inv;
-    const R uu = ux * ux + uy * uy + uz * uz;
-    const R om = sel2(a.omega, k);
-    const R fx = (R)3 * ACC(a, k, 0), fy = (R)3 * ACC(a, k, 1), fz = (R)3 * ACC(a, k, 2);
-    bool cum_phase = false;
-    if constexpr (LAT == LSB_D3Q27 && CUM) cum_phase = sel2(a.cum, k) != 0;
-    // strain-rate moments of the incoming populations; BGK stores here
-    R P0 = 0, P1 = 0, P2 = 0, P3 = 0, P4 = 0, P5 = 0;
-#pragma unroll 1
-    for (int i = 0; i < Q; ++i) {
-      const R f = fl[i * 256 + threadIdx.x];
-      const R w = tw<LAT, R>(i);
-      const R cx = (R)tab<LAT>.cx[i], cy = (R)tab<LAT>.cy[i], cz = (R)tab<LAT>.cz[i];
-      const R cu = cx * ux + cy * uy + cz * uz;
-      const R deq = w * (rp + rho * ((R)3 * cu + (R)4.5 * cu * cu - (R)1.5 * uu));
-      const R fn = f - deq;
-      P0 += cx * cx * fn; P1 += cy * cy * fn; P2 += cz * cz * fn;
-      P3 += cx * cy * fn; P4 += cx * cz * fn; P5 += cy * cz * fn;
-      if (cum_phase) continue;
-      const R ca = cx * fx + cy * fy + cz * fz;
-      store_pop(&a.An[pidx<LAT>(i, c, N)], C::enc(f - om * fn + w * rho * ca, twinv<LAT, R>(i), s));
-    }
-    if constexpr (LAT == LSB_D3Q27 && CUM) {
-      if (cum_phase) {
-        // the cumulant operator takes deviations from the rest state w_i
-        const R rm1 = sel2(a.rref_m1, k);
-        R dl[Q], out[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) dl[i] = fl[i * 256 + threadIdx.x] + (R)wgt<LAT>(i) * rm1;
-        cumulant_collide(dl, om, out);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) out[i] = out[i] - (R)wgt<LAT>(i) * rm1;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          using L = typename S::L;
-          R ca = 0;
-          if (L::cx(i)) ca += (R)L::cx(i) * fx;
-          if (L::cy(i)) ca += (R)L::cy(i) * fy;
-          if (L::cz(i)) ca += (R)L::cz(i) * fz;
-          store_pop(&a.An[pidx<LAT>(i, c, N)], C::enc(out[i] + (R)wgt<LAT>(i) * rho * ca, (R)(1.0 / wgt<LAT>(i)), s));
-        }
-      }
-    }
-    if (active) {
-      const R fac = -(R)1.5 * om * inv;
-      a.Mn[c] = rp + sel2(a.rref_m1, k);  // rho - 1
-      a.Mn[N + c] = ux;
-      a.Mn[2 * N + c] = uy;
-      a.Mn[3 * N + c] = uz;
-      a.Mn[4 * N + c] = fac * P0;
-      a.Mn[5 * N + c] = fac * P1;
-      a.Mn[6 * N + c] = fac * P2;
-      a.Mn[7 * N + c] = fac * P3;
-      a.Mn[8 * N + c] = fac * P4;
-      a.Mn[9 * N + c] = fac * P5;
-    }
+    iface_cell<LAT, ST>(a, c, x, y, z, k, active, own);
+    iface_gather<LAT, ST, 1>(a, own, c, x, y, z, k, 0, fl, (int)threadIdx.x);
+    iface_collide<LAT, ST, CUM, 1>(a, c, k, active, 0, fl, (int)threadIdx.x);
   }
 }
 
