@@ -845,7 +845,10 @@ __global__ __launch_bounds__(256) void k_reinit_finish(const uint8_t* tag0, cons
 
 // extension sweep: adjoint of the sweep's output (AR_UTOUT) into the
 // previous sweep's velocity (AR_UT), phi_n and G_n; seeded cells hold
-// their velocity
+// their velocity.  The output's adjoint is consumed: every cell's is read
+// once (by its own lane, or by the wavefront running its unit) and then
+// cleared, so the buffer is zero for its next use as an accumulator (the
+// sweep reads no AR_UTOUT value through its inputs).
 template <class R>
 __global__ __launch_bounds__(256) void k_sweep_adj(View<R> v, int* overflow) {
   const long N = v.N;
@@ -853,20 +856,26 @@ __global__ __launch_bounds__(256) void k_sweep_adj(View<R> v, int* overflow) {
       N,
       [&](int c) {
         const uint8_t t = v.tag0[c];
+        const bool unit = (t & T_ACT) && !(t & T_SPEC);
         if ((t & T_ACT) && (t & T_SPEC))
           for (int m = 0; m < 3; ++m) atomicAdd(&v.bar[AR_UT][m * N + c], v.bar[AR_UTOUT][m * N + c]);
-        return (t & T_ACT) && !(t & T_SPEC);
+        if (!unit)
+          for (int m = 0; m < 3; ++m) v.bar[AR_UTOUT][m * N + c] = 0.0;
+        return unit;
       },
       [&](int c) {
         double yb[3];
         for (int m = 0; m < 3; ++m) yb[m] = v.bar[AR_UTOUT][m * N + c];
         reverse_unit<R, 3>(v, yb, [&](Acc<R>& A, Dual* out) { ext_sweep(A, c, out); }, overflow);
+        if ((threadIdx.x & 63u) == 0u)
+          for (int m = 0; m < 3; ++m) v.bar[AR_UTOUT][m * N + c] = 0.0;
       });
 }
 
 // extension seed: adjoint of the seeded velocity (AR_UTOUT) into the
 // collide-stream moments and phi_n; away from the interface the seed is the
 // cell's own velocity moment
+// (the output's adjoint is consumed and cleared as in k_sweep_adj)
 template <class R>
 __global__ __launch_bounds__(256) void k_seed_adj(View<R> v, int* overflow) {
   const long N = v.N;
@@ -874,14 +883,19 @@ __global__ __launch_bounds__(256) void k_seed_adj(View<R> v, int* overflow) {
       N,
       [&](int c) {
         const uint8_t t = v.tag0[c];
+        const bool unit = (t & T_ACT) && (t & T_SPEC);
         if ((t & T_ACT) && !(t & T_SPEC))
           for (int m = 0; m < 3; ++m) atomicAdd(&v.bar[AR_MNEW][(1 + m) * N + c], v.bar[AR_UTOUT][m * N + c]);
-        return (t & T_ACT) && (t & T_SPEC);
+        if (!unit)
+          for (int m = 0; m < 3; ++m) v.bar[AR_UTOUT][m * N + c] = 0.0;
+        return unit;
       },
       [&](int c) {
         double yb[3];
         for (int m = 0; m < 3; ++m) yb[m] = v.bar[AR_UTOUT][m * N + c];
         reverse_unit<R, 3>(v, yb, [&](Acc<R>& A, Dual* out) { seed_iface(A, c, out); }, overflow);
+        if ((threadIdx.x & 63u) == 0u)
+          for (int m = 0; m < 3; ++m) v.bar[AR_UTOUT][m * N + c] = 0.0;
       });
 }
 
@@ -1056,6 +1070,44 @@ __global__ void k_set_unit(double* w, int axis) {
 
 __global__ __launch_bounds__(256) void k_zero(double* p, long n) {
   for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) p[i] = 0.0;
+}
+
+// several device-to-device copies in one launch: 16-byte words where both
+// ends are 16-byte aligned, then the remaining bytes
+struct CopySet {
+  static constexpr int kMax = 8;
+  const char* src[kMax];
+  char* dst[kMax];
+  long bytes[kMax];
+  int count;
+};
+__global__ __launch_bounds__(256) void k_copy_set(const CopySet z) {
+  const long t0 = blockIdx.x * 256L + threadIdx.x, step = (long)gridDim.x * 256;
+  for (int j = 0; j < z.count; ++j) {
+    const char* const s = z.src[j];
+    char* const d = z.dst[j];
+    const long n = z.bytes[j];
+    const bool aligned = ((reinterpret_cast<uintptr_t>(s) | reinterpret_cast<uintptr_t>(d)) & 15u) == 0u;
+    const long n16 = aligned ? n / 16 : 0;
+    for (long i = t0; i < n16; i += step)
+      reinterpret_cast<uint4*>(d)[i] = reinterpret_cast<const uint4*>(s)[i];
+    for (long i = n16 * 16 + t0; i < n; i += step) d[i] = s[i];
+  }
+}
+
+// several arrays cleared by one launch
+struct ZeroSet {
+  static constexpr int kMax = 8;
+  double* p[kMax];
+  long n[kMax];
+  int count;
+};
+__global__ __launch_bounds__(256) void k_zero_set(const ZeroSet z) {
+  for (int j = 0; j < z.count; ++j) {
+    double* const p = z.p[j];
+    const long n = z.n[j];
+    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) p[i] = 0.0;
+  }
 }
 
 // sum of the block partials of k_init_pop_adj into the xc0 adjoint

@@ -31,12 +31,19 @@ struct AdjDriver {
     const AdjState& s = p->adj;
     char* d = slot(p, k);
     const size_t N = (size_t)p->N, rb = p->bytes_real;
-    (void)hipMemcpyAsync(d + s.s_A, p->ws + p->off_A[p->cur], p->pop_bytes, hipMemcpyDeviceToDevice, st);
-    (void)hipMemcpyAsync(d + s.s_M, p->ws + p->off_M[p->cur], 10 * N * rb, hipMemcpyDeviceToDevice, st);
-    (void)hipMemcpyAsync(d + s.s_phi, p->ws + p->off_phi, N * rb, hipMemcpyDeviceToDevice, st);
-    (void)hipMemcpyAsync(d + s.s_G, p->ws + p->off_G, 4 * N * rb, hipMemcpyDeviceToDevice, st);
-    (void)hipMemcpyAsync(d + s.s_tag, p->ws + p->off_tag, N, hipMemcpyDeviceToDevice, st);
-    (void)hipMemcpyAsync(d + s.s_scal, p->ws + p->off_scal, SC_COUNT * sizeof(double), hipMemcpyDeviceToDevice, st);
+    // one launch for the six arrays (six copies cost six launches)
+    adj::CopySet z{};
+    const std::pair<size_t, size_t> from[6] = {{p->off_A[p->cur], s.s_A}, {p->off_M[p->cur], s.s_M},
+                                               {p->off_phi, s.s_phi},     {p->off_G, s.s_G},
+                                               {p->off_tag, s.s_tag},     {p->off_scal, s.s_scal}};
+    const size_t bytes[6] = {p->pop_bytes, 10 * N * rb, N * rb, 4 * N * rb, N, SC_COUNT * sizeof(double)};
+    for (int j = 0; j < 6; ++j) {
+      z.src[j] = p->ws + from[j].first;
+      z.dst[j] = d + from[j].second;
+      z.bytes[j] = (long)bytes[j];
+    }
+    z.count = 6;
+    adj::k_copy_set<<<grid(p), 256, 0, st>>>(z);
   }
 
   static void record(lsb_plan* p, int nsteps, hipStream_t st) {
@@ -117,6 +124,17 @@ struct AdjDriver {
     adj::k_zero<<<grid(p), 256, 0, st>>>(dbl(p, off), n);
   }
 
+  // up to ZeroSet::kMax workspace arrays (offset, length) cleared in one launch
+  static void zero_set(lsb_plan* p, std::initializer_list<std::pair<size_t, long>> arrays, hipStream_t st) {
+    adj::ZeroSet z{};
+    for (const auto& a : arrays) {
+      z.p[z.count] = dbl(p, a.first);
+      z.n[z.count] = a.second;
+      ++z.count;
+    }
+    adj::k_zero_set<<<grid(p), 256, 0, st>>>(z);
+  }
+
   static void zero_all(lsb_plan* p, hipStream_t st) {
     const AdjState& s = p->adj;
     const long N = p->N;
@@ -186,25 +204,19 @@ struct AdjDriver {
       v.bar[adj::AR_UTOUT] = dbl(p, s.o_utbar[u]);
       v.val[adj::AR_UT] = reinterpret_cast<const R*>(s0 + s.s_ut + (size_t)(k - 1) * lvl);
       v.bar[adj::AR_UT] = dbl(p, s.o_utbar[u ^ 1]);
-      adj::k_sweep_adj<R><<<gu, 256, 0, st>>>(v, flag);
-      zero(p, s.o_utbar[u], 3 * N, st);
+      adj::k_sweep_adj<R><<<gu, 256, 0, st>>>(v, flag);  // clears utbar[u]
       u ^= 1;
     }
     // extension seed
     v.val[adj::AR_UTOUT] = reinterpret_cast<const R*>(s0 + s.s_ut);
     v.bar[adj::AR_UTOUT] = dbl(p, s.o_utbar[u]);
-    adj::k_seed_adj<R><<<gu, 256, 0, st>>>(v, flag);
-    zero(p, s.o_utbar[u], 3 * N, st);
+    adj::k_seed_adj<R><<<gu, 256, 0, st>>>(v, flag);  // clears utbar[u]
     // collide-stream with wall and interface bounce-back
     adj::k_collide_adj_plain<R><<<g, 256, 0, st>>>(v);
     adj::k_collide_adj<R><<<gu, 256, 0, st>>>(v, flag);
     // the adjoint of step n + 1's state is consumed
-    zero(p, s.o_Abar[r], 9 * N, st);
-    zero(p, s.o_Mbar[r], 10 * N, st);
-    zero(p, s.o_phibar[r], N, st);
-    zero(p, s.o_Gbar[r], 4 * N, st);
-    zero(p, s.o_s1bar, N, st);
-    zero(p, s.o_s2bar, N, st);
+    zero_set(p, {{s.o_Abar[r], 9 * N}, {s.o_Mbar[r], 10 * N}, {s.o_phibar[r], N}, {s.o_Gbar[r], 4 * N},
+                 {s.o_s1bar, N}, {s.o_s2bar, N}}, st);
     s.role = r ^ 1;
   }
 
@@ -234,9 +246,7 @@ struct AdjDriver {
       v.val[adj::AR_RS1] = reinterpret_cast<const R*>(base + lvl);
       v.val[adj::AR_RS2] = reinterpret_cast<const R*>(base + 2 * lvl);
       v.bar[adj::AR_RPHI] = dbl(p, s.o_rphibar[cur]);
-      zero(p, s.o_rphibar[cur], N, st);
-      zero(p, s.o_rs1bar, N, st);
-      zero(p, s.o_rs2bar, N, st);
+      zero_set(p, {{s.o_rphibar[cur], N}, {s.o_rs1bar, N}, {s.o_rs2bar, N}}, st);
       adj::k_reinit_adj<R><<<gu, 256, 0, st>>>(v, 3, k == nr - 1 ? 1 : 0, ob, flag);
       adj::k_reinit_adj<R><<<gu, 256, 0, st>>>(v, 2, 0, dbl(p, s.o_rs2bar), flag);
       adj::k_reinit_adj<R><<<gu, 256, 0, st>>>(v, 1, 0, dbl(p, s.o_rs1bar), flag);
