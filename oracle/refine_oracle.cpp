@@ -11,7 +11,7 @@
 // viscosity is the same on both (Sec. 2, lattice Boltzmann method).  With
 // dt = dx on each level and a ratio of 2 that gives tau_f = 2 tau_c - 1/2 in
 // each level's lattice units.  The paper gives no further detail; the steps
-// below are the reading this build takes (node layout, interpolation order,
+// below are the reading taken here (node layout, interpolation order,
 // rescaling of the non-equilibrium part, order of the sub-steps):
 //
 //   nodes      coarse (I, J, K), periodic on every axis; the fine patch
@@ -255,7 +255,7 @@ struct Ref {
 
   // Level-set refinement sensor (Sec. 3, adaptive mesh refinement): a coarse
   // node is tagged for refinement where it lies in the gas or within d_ref
-  // of it.  This build's level set is negative in the liquid and >= 0 in the
+  // of it.  The level set here is negative in the liquid and >= 0 in the
   // gas, the opposite of the sign the sensor is written with, so the test is
   // phi >= -d_ref.  The patch is the tagged nodes' bounding box grown by
   // margin nodes, clamped to keep one node to spare at each grid face and

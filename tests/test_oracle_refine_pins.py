@@ -240,7 +240,7 @@ def test_remesh_keeps_a_uniform_state(lattice):
 
 
 def test_sensor_box_is_the_bounding_box_of_the_gas_and_its_margin():
-    """Gas where phi >= 0 (the level set's sign in this build); a node is
+    """Gas where phi >= 0 (the sign convention of this level set); a node is
     tagged where phi >= -d_ref; the box is grown by the margin and clamped
     to keep one node at each face.  Checked by brute force on a disk."""
     n = 64
