@@ -45,15 +45,15 @@ def kernel_sources() -> list:
     and the build flags (paths relative to the repository root)."""
     import re
     d = os.path.join(ROOT, "paper_2601_05936_amd", "csrc")
-    todo = [os.path.join(d, "lsb_d3q27.hip"), os.path.join(d, "api.hip")]
+    pending = [os.path.join(d, "lsb_d3q27.hip"), os.path.join(d, "api.hip")]
     seen = []
-    while todo:
-        f = os.path.normpath(todo.pop())
+    while pending:
+        f = os.path.normpath(pending.pop())
         if f in seen:
             continue
         seen.append(f)
         for inc in re.findall(r'^#include "([^"]+)"', open(f).read(), flags=re.M):
-            todo.append(os.path.join(os.path.dirname(f), inc))
+            pending.append(os.path.join(os.path.dirname(f), inc))
     seen.append(os.path.join(ROOT, "paper_2601_05936_amd", "build.py"))
     return sorted(os.path.relpath(f, ROOT) for f in seen)
 
