@@ -234,7 +234,10 @@ def _storage_params():
         for st in (W.F32, W.F16DEV, W.BF16DEV):
             marks = []
             if st == W.F32:
-                marks.append(FP32_MISS)
+                # the still droplet (sigma 1e-2) carries the FP32 level set's
+                # curvature error; the moving and 3D bubbles meet 1e-5
+                if case == "droplet2d":
+                    marks.append(FP32_MISS)
             elif case == "moving2d":
                 marks.append(RS_MOVING_MISS)
             out.append(pytest.param(case, st, marks=marks))
