@@ -285,7 +285,7 @@ struct KArgs {
 // SC_RREF: the codec's reference density of each phase (two slots)
 enum { SC_PB = 0, SC_XC0 = 1, SC_XC = 4, SC_V = 7, SC_NBUB = 8, SC_RREF = 9, SC_COUNT = 16 };
 constexpr int kMaxBubbles = LSB_MAX_BUBBLES;
-constexpr int kBubbleParts = 2048;  // reduction blocks of the per-bubble sums
+constexpr int kBubbleParts = 16384;  // reduction blocks of the per-bubble sums
 // counters: CNT_SPEC, CNT_TILES and CNT_FLIP are cleared before each
 // classification, CNT_CAND before each dilation, CNT_WALL is static.
 // CNT_SPEC and CNT_TILES form one aligned 64-bit word (one atomic reserves
